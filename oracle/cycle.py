@@ -1,0 +1,219 @@
+"""Level hierarchy, coarsest-level direct solve, V-cycle, solve to tolerance
+and mixed-precision iterative refinement.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The V-cycle is the textbook recursion (Trottenberg et al., *Multigrid*,
+Sec. 2.4, gamma = 1): on level l, smooth nu1 times, restrict the residual to
+the right-hand side of level l+1, start level l+1 from zero, recurse, add the
+interpolated correction, smooth nu2 times; on the coarsest level solve
+exactly.  Coarse operators are rediscretised (the same stencil with the
+coarse mesh width), matching ExaSlang's per-level ``Stencil`` declarations.
+The coarsest solve is always FP64: a dense Cholesky factorisation of the
+coarsest matrix followed by two triangular solves, with float32 right-hand
+sides upcast and the result downcast.
+
+``solve`` repeats cycles until ||r_k|| / ||r_0|| <= tol (the ExaSlang
+``repeat ... until`` form), with the unweighted 2-norm over the unknowns.
+
+``mixed_solve`` is FP64 iterative refinement around single-precision
+V-cycles: r = f - A u in FP64, sigma = 2^floor(log2 max|r|), c = V32(0,
+fl32(r / sigma)), u <- u + sigma * fl64(c).  The power-of-two scale adds no
+rounding.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+
+from . import cell, node
+
+
+@dataclass
+class Params:
+    centering: str = "node"          # "node" or "cell"
+    dim: int = 2
+    n: int = 129                     # nodes per axis (node) or cells per axis (cell), finest
+    coarsest: int = 5                # 5 nodes (3^d unknowns) or 4 cells
+    smoother: str = "jacobi"         # "jacobi" or "rbgs"
+    omega: float = 0.8
+    nu1: int = 2
+    nu2: int = 2
+    post_order: tuple = (0, 1)       # colour order of post-smoothing sweeps
+    k: np.ndarray | None = None      # cell coefficients (cell grids); None = 1
+
+
+@dataclass
+class Hierarchy:
+    p: Params
+    sizes: list
+    beta: list = field(default_factory=list)       # per level, FP64 face lists (cell only)
+    chol: np.ndarray | None = None                  # FP64 lower Cholesky factor, coarsest
+    _beta_cache: dict = field(default_factory=dict)
+
+    @property
+    def levels(self) -> int:
+        return len(self.sizes)
+
+    def beta_as(self, lvl: int, dtype):
+        key = (lvl, np.dtype(dtype).str)
+        if key not in self._beta_cache:
+            self._beta_cache[key] = [b.astype(dtype) for b in self.beta[lvl]]
+        return self._beta_cache[key]
+
+
+def ladder(p: Params) -> list:
+    sizes = [p.n]
+    n = p.n
+    while n > p.coarsest:
+        if p.centering == "node":
+            if (n - 1) % 2:
+                raise ValueError(f"node size {n} cannot be coarsened 2:1")
+            n = (n - 1) // 2 + 1
+        else:
+            if n % 2:
+                raise ValueError(f"cell count {n} cannot be coarsened 2:1")
+            n //= 2
+        sizes.append(n)
+    if n != p.coarsest:
+        raise ValueError(f"ladder from {p.n} misses the coarsest size {p.coarsest}")
+    return sizes
+
+
+def build_hierarchy(p: Params) -> Hierarchy:
+    h = Hierarchy(p, ladder(p))
+    if p.centering == "cell":
+        k = p.k if p.k is not None else np.ones((p.n,) * p.dim)
+        h.beta.append(cell.harmonic_faces(np.asarray(k, dtype=np.float64)))
+        for _ in h.sizes[1:]:
+            h.beta.append(cell.coarsen_faces(h.beta[-1]))
+        A = cell.dense_matrix(h.beta[-1], h.sizes[-1], p.dim)
+    else:
+        A = node.dense_matrix(h.sizes[-1], p.dim)
+    h.chol = np.linalg.cholesky(A)
+    return h
+
+
+# ---------------------------------------------------------------- level ops
+def residual(h: Hierarchy, lvl: int, u, f):
+    if h.p.centering == "node":
+        return node.residual(u, f)
+    return cell.residual(u, f, h.beta_as(lvl, u.dtype))
+
+
+def unknowns(h: Hierarchy, a):
+    """The entries of a level array that are unknowns (flattened view)."""
+    if h.p.centering == "node":
+        return a[node.interior(a.ndim)]
+    return a
+
+
+def smooth(h: Hierarchy, lvl: int, u, f, sweeps: int, order=(0, 1)):
+    p = h.p
+    for _ in range(sweeps):
+        if p.centering == "node":
+            u = node.jacobi(u, f, p.omega) if p.smoother == "jacobi" else node.rbgs(u, f, order)
+        else:
+            b = h.beta_as(lvl, u.dtype)
+            u = cell.jacobi(u, f, b, p.omega) if p.smoother == "jacobi" else cell.rbgs(u, f, b, order)
+    return u
+
+
+def restrict(h: Hierarchy, r):
+    return node.restrict_fw(r) if h.p.centering == "node" else cell.restrict_mean(r)
+
+
+def prolong_correct(h: Hierarchy, u, ec):
+    return node.correct(u, ec) if h.p.centering == "node" else cell.correct(u, ec)
+
+
+def coarse_solve(h: Hierarchy, fc):
+    """Exact coarsest solve in FP64 via the stored Cholesky factor L:
+    L y = b, L^T x = y; float32 inputs are upcast and the result downcast."""
+    b = np.asarray(unknowns(h, fc), dtype=np.float64).reshape(-1)
+    y = scipy.linalg.solve_triangular(h.chol, b, lower=True)
+    x = scipy.linalg.solve_triangular(h.chol.T, y, lower=False)
+    out = np.zeros(fc.shape, dtype=fc.dtype)
+    if h.p.centering == "node":
+        out[node.interior(fc.ndim)] = x.reshape((fc.shape[0] - 2,) * fc.ndim).astype(fc.dtype)
+    else:
+        out[...] = x.reshape(fc.shape).astype(fc.dtype)
+    return out
+
+
+def vcycle(h: Hierarchy, u, f, lvl: int = 0):
+    """One V(nu1, nu2)-cycle on level lvl; returns the new iterate."""
+    p = h.p
+    if lvl == h.levels - 1:
+        return coarse_solve(h, f)
+    u = smooth(h, lvl, u, f, p.nu1, (0, 1))
+    r = residual(h, lvl, u, f)
+    fc = restrict(h, r)
+    uc = np.zeros_like(fc)
+    uc = vcycle(h, uc, fc, lvl + 1)
+    u = prolong_correct(h, u, uc)
+    u = smooth(h, lvl, u, f, p.nu2, p.post_order)
+    return u
+
+
+def residual_norm(h: Hierarchy, u, f) -> float:
+    r = residual(h, 0, u, f)
+    ru = np.asarray(unknowns(h, r), dtype=np.float64)
+    return float(np.sqrt(np.sum(ru * ru)))
+
+
+def solve(h: Hierarchy, f, u0=None, tol=1e-10, max_cycles=100, record_iterates=False):
+    """V-cycles from u0 until ||r|| / ||r0|| <= tol.  Returns
+    (u, relres history including the initial 1.0, iterates or None)."""
+    u = np.zeros_like(f) if u0 is None else u0.copy()
+    r0 = residual_norm(h, u, f)
+    hist = [1.0]
+    its = [] if record_iterates else None
+    for _ in range(max_cycles):
+        if r0 == 0.0 or hist[-1] <= tol:
+            break
+        u = vcycle(h, u, f)
+        if its is not None:
+            its.append(u.copy())
+        hist.append(residual_norm(h, u, f) / r0)
+    return u, hist, its
+
+
+def cycles(h: Hierarchy, f, u0, k: int):
+    """Exactly k V-cycles from u0; returns the list of iterates u^1..u^k."""
+    u = u0.copy()
+    out = []
+    for _ in range(k):
+        u = vcycle(h, u, f)
+        out.append(u.copy())
+    return out
+
+
+def pow2_scale(maxabs: float) -> float:
+    """2^floor(log2 maxabs) for maxabs > 0 (frexp gives maxabs = m 2^e, m in [0.5, 1))."""
+    _, e = np.frexp(maxabs)
+    return float(np.ldexp(1.0, int(e) - 1))
+
+
+def mixed_solve(h: Hierarchy, f, tol=1e-10, max_outer=100, inner=np.float32):
+    """FP64 iterative refinement with single-precision V-cycles, from u = 0.
+    Returns (u, relres history ||r_k|| / ||f||)."""
+    u = np.zeros_like(f, dtype=np.float64)
+    hist = []
+    r0 = None
+    for _ in range(max_outer + 1):
+        r = residual(h, 0, u, f)
+        ru = np.asarray(unknowns(h, r))
+        nrm = float(np.sqrt(np.sum(ru * ru)))
+        if r0 is None:
+            r0 = nrm
+        hist.append(nrm / r0 if r0 else 0.0)
+        if r0 == 0.0 or hist[-1] <= tol or len(hist) > max_outer:
+            break
+        sigma = pow2_scale(float(np.max(np.abs(ru))))
+        r32 = (r / sigma).astype(inner)
+        c = vcycle(h, np.zeros_like(r32), r32)
+        u = u + sigma * c.astype(np.float64)
+    return u, hist

@@ -1,0 +1,34 @@
+"""Readings taken where the paper is silent, ambiguous or garbled.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper describes no multigrid algorithm (its method is a quadrature-free
+DG discretisation of the shallow water equations, Sec. 2); the V-cycle
+vocabulary comes from the ExaSlang keyword lists that accompany its
+listings (``coarsest``, ``restriction``, ``prolongation``, ``jacobi``,
+``color``, ``relax``, ``solve``, ``repeat ... until``, ``StencilField``).
+Each reading below fixes one constant of the textbook method; the GPU
+library is configured with the same values in its tests.
+"""
+
+READINGS = {
+    "R0": "V-cycle, smoothers and transfers follow the textbook definitions (gamma = 1).",
+    "R1": "'coarsest 3x3' / '3^3 coarse solve' = 3^d interior unknowns, i.e. 5^d nodes "
+          "(513 -> ... -> 5 is 8 grids, matching the stated 8 levels).",
+    "R2": "Full weighting sums to 1 and linear interpolation is P = 2^d R^T.",
+    "R3": "Coarse operators are rediscretised (same stencil, coarse 1/H^2), not Galerkin RAP.",
+    "R4": "Boundary nodes are not unknowns and hold 0 on every level for u, r and e.",
+    "R5": "Red = even index sum (boundary index 0), updated first in pre- and post-smoothing.",
+    "R6": "Initial guess 0 where unstated; the 2-D case uses U[-1,1] on interior nodes.",
+    "R7": "The variable-coefficient case uses red-black GS V(3,3) and zero Dirichlet walls.",
+    "R8": "'257^3 cells' is read as 256^3 cells (257 vertices per axis).",
+    "R9": "Coarse face coefficient = mean of the fine faces that tile the coarse face.",
+    "R10": "Mixed precision: one single-precision V-cycle per FP64 refinement step, "
+           "scale 2^floor(log2 max|r|).",
+    "R11": "Norm = unweighted 2-norm over the unknowns; relative to the initial residual.",
+    "R12": "Stopping counts may differ by one cycle when ||r|| crosses tol within rounding; "
+           "parity is judged on iterates at equal cycle counts.",
+    "R13": "Seeds: NumPy PCG64, 0 (2-D u0), 1 (3-D f), 2 (variable-coefficient f), "
+           "3/4 (arrivals/sizes), 1000+id (request f).",
+    "R14": "Served 2-D requests use damped Jacobi V(2,2); 3-D requests use red-black GS V(3,3).",
+}

@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs for the multigrid workloads.
+
+This module only draws and samples inputs: right-hand sides, initial guesses,
+coefficient fields and request arrival traces.  It holds none of the solver's
+arithmetic (no operator, smoother, transfer or norm) so that both the GPU
+library's tests and the CPU oracle can be fed the very same arrays.
+
+Everything is NumPy float64 on the host, C order, x fastest
+(``a[z, y, x]`` in 3-D, ``a[y, x]`` in 2-D).  Node grids hold the boundary
+nodes (always zero); cell grids hold only cells.
+
+Seeds follow one fixed scheme: 0 for the 2-D initial guess, 1 for the 3-D
+Poisson right-hand side, 2 for the variable-coefficient right-hand side,
+3 and 4 for the request stream's arrivals and size classes, 1000 + id for
+request right-hand sides.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_U0_2D = 0
+SEED_F_3D = 1
+SEED_F_VARCOEF = 2
+SEED_ARRIVALS = 3
+SEED_SIZES = 4
+SEED_REQUEST_BASE = 1000
+
+
+def node_coords(n: int) -> np.ndarray:
+    """Node positions x_i = i*h, h = 1/(n-1), on [0, 1]."""
+    return np.arange(n, dtype=np.float64) / (n - 1)
+
+
+def cell_coords(N: int) -> np.ndarray:
+    """Cell-centre positions (i + 1/2)*h, h = 1/N, on [0, 1]."""
+    return (np.arange(N, dtype=np.float64) + 0.5) / N
+
+
+def interior_uniform(n: int, dim: int, seed: int, lo=-1.0, hi=1.0) -> np.ndarray:
+    """Node array of shape (n,)*dim: U[lo, hi] on interior nodes, 0 on the boundary."""
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n,) * dim, dtype=np.float64)
+    a[(slice(1, -1),) * dim] = rng.uniform(lo, hi, size=(n - 2,) * dim)
+    return a
+
+
+def sine_rhs_2d(n: int) -> np.ndarray:
+    """f = 2 pi^2 sin(pi x) sin(pi y) sampled at the nodes of an n x n grid
+    (boundary samples are zero up to rounding; they are set to exactly 0)."""
+    x = node_coords(n)
+    s = np.sin(np.pi * x)
+    f = 2.0 * np.pi ** 2 * np.outer(s, s)
+    f[0, :] = f[-1, :] = f[:, 0] = f[:, -1] = 0.0
+    return f
+
+
+def sine_mode(n: int, dim: int, ks=None) -> np.ndarray:
+    """Product over array axes a of sin(ks[a] * pi * x_a) at the nodes; the
+    boundary samples are set to exactly 0."""
+    ks = ks or (1,) * dim
+    x = node_coords(n)
+    out = np.ones((n,) * dim)
+    for ax in range(dim):
+        shape = [1] * dim
+        shape[ax] = n
+        out = out * np.sin(ks[ax] * np.pi * x).reshape(shape)
+    for ax in range(dim):
+        idx = [slice(None)] * dim
+        idx[ax] = 0
+        out[tuple(idx)] = 0.0
+        idx[ax] = -1
+        out[tuple(idx)] = 0.0
+    return out
+
+
+def varcoef_k(N: int, dim: int = 3) -> np.ndarray:
+    """k = exp(0.5 * prod_a sin(2 pi x_a)) at the N^dim cell centres."""
+    x = cell_coords(N)
+    s = np.sin(2.0 * np.pi * x)
+    prod = np.ones((1,) * dim)
+    for ax in range(dim):
+        shape = [1] * dim
+        shape[ax] = N
+        prod = prod * s.reshape(shape)
+    return np.exp(0.5 * np.broadcast_to(prod, (N,) * dim))
+
+
+def normal_zero_mean(N: int, dim: int, seed: int) -> np.ndarray:
+    """N(0, 1) samples on N^dim cells, shifted to zero mean."""
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal(size=(N,) * dim)
+    return f - f.mean()
+
+
+# --------------------------------------------------------------------------
+# Request stream for the served workload
+# --------------------------------------------------------------------------
+SERVE_CLASSES = (
+    (2, 65), (2, 129), (2, 257), (2, 513), (2, 1025),
+    (3, 33), (3, 65), (3, 129),
+)
+
+
+@dataclass(frozen=True)
+class Request:
+    rid: int
+    dim: int
+    n: int
+    t_arrive: float   # seconds from the start of the stream
+
+    def rhs(self) -> np.ndarray:
+        return interior_uniform(self.n, self.dim, SEED_REQUEST_BASE + self.rid)
+
+
+def request_stream(count: int, rate_per_s: float, classes=SERVE_CLASSES,
+                   seed_arrivals: int = SEED_ARRIVALS,
+                   seed_sizes: int = SEED_SIZES) -> list[Request]:
+    """Poisson arrivals (exponential gaps at ``rate_per_s``) with size classes
+    drawn uniformly from ``classes``."""
+    ra = np.random.default_rng(seed_arrivals)
+    rs = np.random.default_rng(seed_sizes)
+    gaps = ra.exponential(1.0 / rate_per_s, size=count) if rate_per_s > 0 else np.zeros(count)
+    t = np.cumsum(gaps) - gaps[0] if count else gaps
+    cls = rs.integers(0, len(classes), size=count)
+    out = []
+    for i in range(count):
+        d, n = classes[int(cls[i])]
+        out.append(Request(i, d, n, float(t[i])))
+    return out

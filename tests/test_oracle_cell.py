@@ -1,0 +1,236 @@
+"""Pins for the cell-centred variable-coefficient oracle: closed forms with
+mirror ghosts, exact scalings, SPD structure, brute-force loops, and the
+experimental order of convergence of a manufactured solution (the paper's
+own verification method, Sec. 3.1 and Table tab:convergence)."""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse
+import scipy.sparse.linalg
+
+from oracle import cell, cycle
+from paper_1904_08684_amd import workloads as W
+
+
+def ones_beta(N, d):
+    return cell.harmonic_faces(np.ones((N,) * d))
+
+
+def cell_sine(N, d, ks):
+    x = W.cell_coords(N)
+    out = np.ones((N,) * d)
+    for ax in range(d):
+        shape = [1] * d
+        shape[ax] = N
+        out = out * np.sin(ks[ax] * np.pi * x).reshape(shape)
+    return out
+
+
+@pytest.mark.parametrize("d,N,ks", [(2, 16, (1, 1)), (2, 16, (3, 8)), (3, 8, (1, 2, 3)), (3, 16, (5, 1, 2))])
+def test_unit_coefficient_sine_eigenvector(d, N, ks):
+    """With k = 1 and mirror ghosts, sin(k pi x)... sampled at cell centres is an
+    exact eigenvector with eigenvalue (4/h^2) sum sin^2(k pi h / 2)."""
+    h = 1.0 / N
+    u = cell_sine(N, d, ks)
+    lam = 4 / h ** 2 * sum(np.sin(k * np.pi * h / 2) ** 2 for k in ks)
+    Au = cell.apply_A(u, ones_beta(N, d))
+    assert np.max(np.abs(Au - lam * u)) <= 1e-12 * lam
+
+
+def test_harmonic_mean_and_walls():
+    k = np.array([[1.0, 3.0], [2.0, 2.0]])
+    bx, by = cell.harmonic_faces(k)[1], cell.harmonic_faces(k)[0]
+    # along x (array axis 1): row 0 faces: wall=1, 2*1*3/4=1.5, wall=3
+    assert np.allclose(bx[0], [1.0, 1.5, 3.0]) and np.allclose(bx[1], [2.0, 2.0, 2.0])
+    # along y (array axis 0): column 0 faces: wall=1, 2*1*2/3, wall=2
+    assert np.allclose(by[:, 0], [1.0, 4.0 / 3.0, 2.0])
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])
+def test_operator_brute_force(d, N):
+    rng = np.random.default_rng(1)
+    k = np.exp(rng.uniform(-1, 1, size=(N,) * d))
+    beta = cell.harmonic_faces(k)
+    u = rng.uniform(-1, 1, size=(N,) * d)
+    Au = cell.apply_A(u, beta)
+    s = N * N
+    for p in itertools.product(range(N), repeat=d):
+        acc = 0.0
+        for ax in range(d):
+            for side in (-1, 1):
+                q = list(p)
+                q[ax] += side
+                if 0 <= q[ax] < N:
+                    kb = 2 * k[p] * k[tuple(q)] / (k[p] + k[tuple(q)])
+                    acc += kb * (u[p] - u[tuple(q)])
+                else:
+                    acc += k[p] * (u[p] + u[p])     # mirror ghost -u[p]
+        assert abs(Au[p] - s * acc) <= 1e-12 * s * 10
+
+
+def test_spd_and_constant_coefficient_scaling():
+    N, d = 8, 3
+    k = W.varcoef_k(N, d)
+    A = cell.dense_matrix(cell.harmonic_faces(k), N, d)
+    assert np.allclose(A, A.T, rtol=0, atol=1e-9)
+    assert np.min(np.linalg.eigvalsh(A)) > 0
+    # k = c scales the operator (and so the solution) exactly for c a power of two
+    f = W.normal_zero_mean(N, d, 3)
+    b1 = ones_beta(N, d)
+    b4 = cell.harmonic_faces(4.0 * np.ones((N,) * d))
+    u = np.random.default_rng(0).uniform(-1, 1, (N,) * d)
+    assert np.array_equal(cell.apply_A(u, b4), 4.0 * cell.apply_A(u, b1))
+    del f
+
+
+def test_coarse_faces_of_unit_coefficient_are_one():
+    beta = ones_beta(16, 3)
+    for lvl in range(3):
+        beta = cell.coarsen_faces(beta)
+        for b in beta:
+            assert np.all(b == 1.0)
+    assert beta[0].shape == (3, 2, 2)
+
+
+def test_coarse_face_brute_force():
+    rng = np.random.default_rng(2)
+    N, d = 8, 3
+    beta = cell.harmonic_faces(np.exp(rng.uniform(-1, 1, (N,) * d)))
+    bc = cell.coarsen_faces(beta)
+    bx = beta[2]   # faces along x: shape (N, N, N+1)
+    for K, J, I in itertools.product(range(N // 2), range(N // 2), range(N // 2 + 1)):
+        want = (bx[2 * K, 2 * J, 2 * I] + bx[2 * K, 2 * J + 1, 2 * I]
+                + bx[2 * K + 1, 2 * J, 2 * I] + bx[2 * K + 1, 2 * J + 1, 2 * I]) / 4
+        assert abs(bc[2][K, J, I] - want) < 1e-15
+
+
+def test_rbgs_colour_invariant_and_brute_force():
+    N, d = 8, 3
+    k = W.varcoef_k(N, d)
+    beta = cell.harmonic_faces(k)
+    f = W.normal_zero_mean(N, d, 4)
+    u = np.random.default_rng(6).uniform(-1, 1, (N,) * d)
+    got = cell.rbgs(u, f, beta)
+    # brute force: lexicographic loop per colour with the explicit face formula
+    ref = u.copy()
+    s = N * N
+    for colour in (0, 1):
+        for p in itertools.product(range(N), repeat=d):
+            if sum(p) % 2 != colour:
+                continue
+            num, den = f[p] / s, 0.0
+            for ax in reversed(range(d)):
+                for side in (-1, 1):
+                    q = list(p)
+                    q[ax] += side
+                    fi = p[ax] if side < 0 else p[ax] + 1
+                    idx = list(p)
+                    idx[ax] = fi
+                    b = beta[ax][tuple(idx)]
+                    if 0 <= q[ax] < N:
+                        num += b * ref[tuple(q)]
+                        den += b
+                    else:
+                        den += 2 * b
+            ref[p] = num / den
+    assert np.max(np.abs(got - ref)) < 1e-13
+    r = cell.residual(got, f, beta)
+    black = cell.colour_mask(N, d, 1)
+    assert np.max(np.abs(r[black])) < 1e-10 * np.max(np.abs(r[~black]))
+
+
+def test_restriction_of_constants_and_prolongation_of_linears():
+    N = 8
+    c = np.full((N,) * 3, 2.5)
+    assert np.all(cell.restrict_mean(c) == 2.5)
+    # 1-D check of the interpolation weights including the mirror ghost at walls
+    ec = np.array([[[1.0, 2.0, 4.0, 8.0]]])
+    ef = cell.prolong_trilinear(ec)
+    # interior cells along x: 3/4 parent + 1/4 neighbour
+    assert ef.shape == (2, 2, 8)
+    row = ef[0, 0]
+    want = [0.75 * 1 - 0.25 * 1, 0.75 * 1 + 0.25 * 2, 0.75 * 2 + 0.25 * 1, 0.75 * 2 + 0.25 * 4,
+            0.75 * 4 + 0.25 * 2, 0.75 * 4 + 0.25 * 8, 0.75 * 8 + 0.25 * 4, 0.75 * 8 - 0.25 * 8]
+    # y and z directions see mirror ghosts too: single coarse cell -> factor 1/2 per axis
+    assert np.allclose(row, np.array(want) * 0.5 * 0.5)
+    # linear functions are reproduced away from the walls
+    Nc = 8
+    xc = W.cell_coords(Nc)
+    xf = W.cell_coords(2 * Nc)
+    g = lambda z, y, x: 1 + 2 * x - 3 * y + 0.5 * z
+    ecl = g(*np.meshgrid(xc, xc, xc, indexing="ij"))
+    efl = g(*np.meshgrid(xf, xf, xf, indexing="ij"))
+    inner = (slice(1, -1),) * 3
+    assert np.max(np.abs(cell.prolong_trilinear(ecl)[inner] - efl[inner])) < 1e-14
+
+
+def _manufactured(N):
+    """u* = sin(pi x) sin(pi y) sin(pi z), f = -div(k grad u*) with
+    k = exp(0.5 sin 2pi x sin 2pi y sin 2pi z), at cell centres."""
+    x = W.cell_coords(N)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    sx, sy, sz = np.sin(np.pi * X), np.sin(np.pi * Y), np.sin(np.pi * Z)
+    cx, cy, cz = np.cos(np.pi * X), np.cos(np.pi * Y), np.cos(np.pi * Z)
+    S2x, S2y, S2z = np.sin(2 * np.pi * X), np.sin(2 * np.pi * Y), np.sin(2 * np.pi * Z)
+    C2x, C2y, C2z = np.cos(2 * np.pi * X), np.cos(2 * np.pi * Y), np.cos(2 * np.pi * Z)
+    k = np.exp(0.5 * S2x * S2y * S2z)
+    kx = k * 0.5 * 2 * np.pi * C2x * S2y * S2z
+    ky = k * 0.5 * 2 * np.pi * S2x * C2y * S2z
+    kz = k * 0.5 * 2 * np.pi * S2x * S2y * C2z
+    u = sx * sy * sz
+    ux, uy, uz = np.pi * cx * sy * sz, np.pi * sx * cy * sz, np.pi * sx * sy * cz
+    lap = -3 * np.pi ** 2 * u
+    f = -(kx * ux + ky * uy + kz * uz + k * lap)
+    return u, f, k
+
+
+def test_manufactured_solution_eoc_two():
+    """Experimental order of convergence ~ 2 under refinement, the verification
+    method of the paper's numerical section."""
+    errs = []
+    for N in (8, 16, 32):
+        u_star, f, k = _manufactured(N)
+        p = cycle.Params(centering="cell", dim=3, n=N, coarsest=4, smoother="rbgs", nu1=3, nu2=3, k=k)
+        h = cycle.build_hierarchy(p)
+        u, hist, _ = cycle.solve(h, f, tol=1e-12, max_cycles=40)
+        assert hist[-1] <= 1e-12
+        errs.append(np.sqrt(np.mean((u - u_star) ** 2)))
+    eoc = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 < e < 2.2 for e in eoc), (errs, eoc)
+
+
+def test_varcoef_vcycle_converges_to_sparse_direct_solve():
+    N = 16
+    k = W.varcoef_k(N)
+    p = cycle.Params(centering="cell", dim=3, n=N, coarsest=4, smoother="rbgs", nu1=3, nu2=3, k=k)
+    h = cycle.build_hierarchy(p)
+    f = W.normal_zero_mean(N, 3, 2)
+    u, hist, _ = cycle.solve(h, f, tol=1e-13, max_cycles=40)
+    # assemble the sparse operator independently from the face formula
+    idx = np.arange(N ** 3).reshape((N,) * 3)
+    beta = cell.harmonic_faces(k)
+    rows, cols, vals = [], [], []
+    s = N * N
+    for ax in range(3):
+        b = beta[ax]
+        for side in (-1, 1):
+            for p_ in itertools.product(range(N), repeat=3):
+                q = list(p_)
+                q[ax] += side
+                fi = list(p_)
+                fi[ax] = p_[ax] if side < 0 else p_[ax] + 1
+                bf = b[tuple(fi)]
+                if 0 <= q[ax] < N:
+                    rows += [idx[p_], idx[p_]]
+                    cols += [idx[p_], idx[tuple(q)]]
+                    vals += [s * bf, -s * bf]
+                else:
+                    rows.append(idx[p_])
+                    cols.append(idx[p_])
+                    vals.append(2 * s * bf)
+    A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(N ** 3, N ** 3))
+    ud = scipy.sparse.linalg.spsolve(A.tocsc(), f.reshape(-1)).reshape((N,) * 3)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-11
+    rates = [hist[i + 1] / hist[i] for i in range(1, len(hist) - 1)]
+    assert max(rates) < 0.12, rates

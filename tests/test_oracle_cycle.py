@@ -1,0 +1,179 @@
+"""Pins for the oracle's V-cycle, solve and mixed-precision refinement:
+textbook two-grid factors, direct solves and closed forms."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cycle, node
+from paper_1904_08684_amd import workloads as W
+from tests.test_oracle_node import dst_solve
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lfa_2d_rbgs.json")))
+
+
+def two_grid_matrix(p: cycle.Params):
+    """Dense two-grid iteration matrix (f = 0) of the oracle's cycle with an
+    exact coarse solve, built by applying one cycle to unit vectors."""
+    q = cycle.Params(**{**p.__dict__, "coarsest": (p.n + 1) // 2})
+    h = cycle.build_hierarchy(q)
+    assert h.levels == 2
+    n, d = p.n, p.dim
+    m = (n - 2) ** d
+    M = np.zeros((m, m))
+    f = np.zeros((n,) * d)
+    c = node.interior(d)
+    for j in range(m):
+        e = np.zeros(m)
+        e[j] = 1
+        u = np.zeros((n,) * d)
+        u[c] = e.reshape((n - 2,) * d)
+        M[:, j] = cycle.vcycle(h, u, f)[c].reshape(-1)
+    return M
+
+
+def spectral_radius(M):
+    return float(np.max(np.abs(np.linalg.eigvals(M))))
+
+
+@pytest.mark.parametrize("nu", [1, 2])
+def test_two_grid_rbgs_matches_lfa(nu):
+    p = cycle.Params(centering="node", dim=2, n=33, smoother="rbgs", nu1=nu, nu2=nu)
+    rho = spectral_radius(two_grid_matrix(p))
+    ref = GOLD["rho_two_grid"][str(2 * nu)]
+    assert abs(rho - ref) / ref < 0.05, (rho, ref)
+
+
+def test_two_grid_jacobi_near_smoothing_bound():
+    """omega-Jacobi V(2,2): the two-grid factor is close to mu^4 = 0.1296."""
+    p = cycle.Params(centering="node", dim=2, n=33, smoother="jacobi", omega=0.8, nu1=2, nu2=2)
+    rho = spectral_radius(two_grid_matrix(p))
+    mu = GOLD["smoothing_factor_omega_jacobi"]["mu"]
+    assert mu ** 4 * 0.95 < rho < mu ** 4 * 1.15, rho
+
+
+def _vcycle_factor(p, cycles_=10):
+    """Asymptotic V-cycle factor by power iteration with f = 0."""
+    h = cycle.build_hierarchy(p)
+    e = W.interior_uniform(p.n, p.dim, 77)
+    f = np.zeros_like(e)
+    c = node.interior(p.dim)
+    nrm = [np.linalg.norm(e[c])]
+    for _ in range(cycles_):
+        e = cycle.vcycle(h, e, f)
+        nrm.append(np.linalg.norm(e[c]))
+    return (nrm[-1] / nrm[-4]) ** (1 / 3)
+
+
+def test_vcycle_factor_2d_rbgs_h_independent():
+    """The V(2,2) factor stays within 1.5x the two-grid LFA value and does not
+    grow under refinement."""
+    rates = []
+    for n in (33, 65, 129):
+        p = cycle.Params(centering="node", dim=2, n=n, smoother="rbgs", nu1=2, nu2=2)
+        rates.append(_vcycle_factor(p, 12))
+    assert max(rates) <= 1.5 * GOLD["rho_two_grid"]["4"], rates
+    assert max(rates) - min(rates) < 0.01, rates
+
+
+def test_vcycle_factor_3d_rbgs():
+    p = cycle.Params(centering="node", dim=3, n=33, smoother="rbgs", nu1=3, nu2=3)
+    rate = _vcycle_factor(p, 10)
+    assert rate < 0.09, rate
+
+
+def test_two_grid_3d_rbgs_power_iteration():
+    """3-D RB-GS V(3,3) two-grid factor at n = 17, by power iteration."""
+    p = cycle.Params(centering="node", dim=3, n=17, smoother="rbgs", nu1=3, nu2=3, coarsest=9)
+    h = cycle.build_hierarchy(p)
+    assert h.levels == 2
+    e = W.interior_uniform(17, 3, 5)
+    f = np.zeros_like(e)
+    norms = [np.linalg.norm(e)]
+    for _ in range(25):
+        e = cycle.vcycle(h, e, f)
+        norms.append(np.linalg.norm(e))
+    rho = (norms[-1] / norms[-6]) ** 0.2
+    assert 0.03 < rho < 0.08, rho
+
+
+@pytest.mark.parametrize("d,n,smoother", [(2, 17, "jacobi"), (2, 33, "rbgs"), (3, 9, "rbgs"), (3, 17, "jacobi")])
+def test_vcycles_converge_to_dense_solution(d, n, smoother):
+    p = cycle.Params(centering="node", dim=d, n=n, smoother=smoother, nu1=2, nu2=2)
+    h = cycle.build_hierarchy(p)
+    f = W.interior_uniform(n, d, 40)
+    A = node.dense_matrix(n, d)
+    c = node.interior(d)
+    ud = np.linalg.solve(A, f[c].reshape(-1))
+    u = np.zeros_like(f)
+    for _ in range(50):
+        u = cycle.vcycle(h, u, f)
+    assert np.linalg.norm(u[c].reshape(-1) - ud) <= 1e-13 * np.linalg.norm(ud) * 10
+
+
+def test_coarse_solve_is_exact():
+    for d in (2, 3):
+        p = cycle.Params(centering="node", dim=d, n=5, smoother="rbgs")
+        h = cycle.build_hierarchy(p)
+        assert h.levels == 1
+        f = W.interior_uniform(5, d, 9)
+        e = cycle.coarse_solve(h, f)
+        assert np.max(np.abs(node.residual(e, f))) < 1e-13 * np.max(np.abs(f)) * 16
+        assert np.max(np.abs(e - dst_solve(f))) < 1e-16 * 100
+
+
+def test_c0_solution_closed_form():
+    """The oracle's C0 solve reaches c_h sin(pi x) sin(pi y)."""
+    n = 129
+    p = cycle.Params(centering="node", dim=2, n=n, smoother="jacobi", omega=0.8, nu1=2, nu2=2)
+    h = cycle.build_hierarchy(p)
+    ch = (np.pi / 256) ** 2 / np.sin(np.pi / 256) ** 2
+    u, hist, _ = cycle.solve(h, W.sine_rhs_2d(n), W.interior_uniform(n, 2, 0), tol=1e-13, max_cycles=40)
+    assert hist[-1] <= 1e-13
+    assert np.max(np.abs(u - ch * W.sine_mode(n, 2))) < 5e-12
+
+
+def test_3d_solve_matches_dst():
+    n = 33
+    p = cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3)
+    h = cycle.build_hierarchy(p)
+    f = W.interior_uniform(n, 3, 1)
+    u, hist, _ = cycle.solve(h, f, tol=1e-10)
+    assert hist[-1] <= 1e-10 and len(hist) - 1 <= 12
+    ud = dst_solve(f)
+    kappa = 4 * (n - 1) ** 2 / (3 * np.pi ** 2) * 3
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= kappa * 1e-10
+
+
+def test_mixed_precision_reaches_fp64_tolerance():
+    n = 33
+    p = cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3)
+    h = cycle.build_hierarchy(p)
+    f = W.interior_uniform(n, 3, 1)
+    u, hist = cycle.mixed_solve(h, f, tol=1e-10)
+    # recompute the final residual independently of the solver's own bookkeeping
+    rel = np.linalg.norm(node.residual(u, f)) / np.linalg.norm(f)
+    assert rel <= 1e-10 and abs(rel - hist[-1]) <= 1e-3 * rel
+    ud = dst_solve(f)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-8
+    # the refinement contracts like the FP64 cycle (single precision is not the bottleneck)
+    rates = [hist[i + 1] / hist[i] for i in range(1, len(hist) - 1)]
+    assert max(rates) < 0.15
+
+
+def test_float32_cycle_stays_in_float32_and_tracks_fp64():
+    n = 17
+    p = cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3)
+    h = cycle.build_hierarchy(p)
+    f = W.interior_uniform(n, 3, 2)
+    c32 = cycle.vcycle(h, np.zeros(f.shape, np.float32), f.astype(np.float32))
+    c64 = cycle.vcycle(h, np.zeros_like(f), f)
+    assert c32.dtype == np.float32
+    assert np.max(np.abs(c32 - c64)) <= 1e-5 * np.max(np.abs(c64))
+
+
+def test_pow2_scale():
+    for v in (1.0, 0.75, 3.0, 1e-300, 5e300, 2.0 ** -20):
+        s = cycle.pow2_scale(v)
+        assert s <= v < 2 * s and np.log2(s) == np.floor(np.log2(s))
