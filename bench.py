@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark: 3-D Poisson, 7-point stencil, 513^3 nodes (8 levels, 3^3
+coarsest unknowns), red-black Gauss-Seidel V(3,3), full weighting,
+trilinear interpolation, solved to relative residual 1e-10 in FP64 on one
+MI355X.  One step = one complete solve from u = 0 on a resident seeded
+right-hand side.  The same solve in mixed precision (single-precision
+V-cycles inside FP64 iterative refinement) is timed beside it.
+
+Prints one JSON line.  ``value`` is V-cycle MLUpS of the FP64 solve
+(finest interior unknowns x V-cycles / time).  ``roofline`` covers the
+dominant kernel (the finest-level red-black half-sweep), timed live with HIP
+events on the library's stream over the timed solves.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "V-cycle MLUpS & HBM GB/s to 1e-10 residual, FP64 vs mixed; solves/s + p99"
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1904_08684_amd", "csrc", "mg_kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_record(n: int):
+    """HBM bytes of the dominant kernel from committed rocprofv3 counter runs,
+    valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", f"gs_sweep_{n}cubed_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec
+
+
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(n_sample: int = 257):
+    """The oracle (plain NumPy FP64, one core) timed on one V(3,3)-cycle of the
+    same problem at a bounded size."""
+    import numpy as np
+    from oracle import cycle
+    from paper_1904_08684_amd import workloads as W
+    f = W.interior_uniform(n_sample, 3, W.SEED_F_3D)
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n_sample, smoother="rbgs", nu1=3, nu2=3))
+    t = time.perf_counter()
+    cycle.vcycle(h, np.zeros_like(f), f)
+    dt = time.perf_counter() - t
+    return {"value": (n_sample - 2) ** 3 / dt / 1e6, "unit": "MLUpS", "cores": 1, "kind": "oracle",
+            "sample": f"one V(3,3) RB-GS cycle of the 3-D Poisson problem at {n_sample}^3 nodes "
+                      f"({dt:.1f} s, NumPy single thread on {cpu_model()}, {os.cpu_count()} host CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=513)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1904_08684_amd import mg
+    from paper_1904_08684_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    n = args.n
+    unknowns = (n - 2) ** 3
+    print(f"# bench: {n}^3 FP64 setup", file=sys.stderr, flush=True)
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    f_dev = torch.from_numpy(f).cuda()
+    del f
+
+    def run(precision):
+        s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, precision=precision)
+        s.set_rhs(f_dev)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            s.set_initial(None)
+            code, cyc, rel = s.solve(args.tol)
+            assert code == mg.MG_OK, (code, rel)
+        s.profile(True)
+        times, cycles, rels = [], [], []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            s.set_initial(None)
+            code, cyc, rel = s.solve(args.tol)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            assert code == mg.MG_OK, (code, rel)
+            cycles.append(cyc)
+            rels.append(rel)
+        total = time.perf_counter() - t_all
+        prof = {}
+        for name, kc in (("smooth", mg.MG_K_SMOOTH), ("residual", mg.MG_K_RESIDUAL),
+                         ("restrict", mg.MG_K_RESTRICT), ("prolong", mg.MG_K_PROLONG),
+                         ("coarse", mg.MG_K_COARSE), ("reduce", mg.MG_K_REDUCE), ("cast", mg.MG_K_CAST),
+                         ("update", mg.MG_K_UPDATE), ("copy", mg.MG_K_COPY)):
+            cnt, ms = s.profile_read(kc, -1)
+            if cnt:
+                prof[name] = {"launches": cnt, "ms": round(ms, 3)}
+        c0, ms0 = s.profile_read(mg.MG_K_SMOOTH, 0)
+        s.profile(False)
+        s.close()
+        return {"total": total, "times": times, "cycles": cycles, "rels": rels, "prof": prof,
+                "fine_smooth": (c0, ms0)}
+
+    r64 = run(mg.MG_FP64)
+    ms_step = 1e3 * r64["total"] / args.steps
+    cyc_total = sum(r64["cycles"])
+    mlups = unknowns * cyc_total / r64["total"] / 1e6
+    c0, ms0 = r64["fine_smooth"]
+    avg_ms = ms0 / c0
+    # one red-black half-sweep on the finest level reads the other colour and
+    # f of its own colour and writes its own colour: 24 B per updated point
+    bytes_per_launch = 24.0 * unknowns / 2
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traf = traffic_record(n)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (traf["hbm_bytes_per_launch"] if traf else None),
+                "kernel": "finest-level red-black Gauss-Seidel half-sweep (k_node_gs<double,3>)",
+                "avg_launch_ms": round(avg_ms, 4), "launches": c0,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUpS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded U[-1,1] right-hand side, u0 = 0)",
+           "config": {"workload": f"3-D Poisson 7-point, {n}^3 nodes, 8 levels, RB-GS V(3,3), full weighting, "
+                                  f"trilinear, 3^3 coarsest Cholesky, to relres {args.tol:g}",
+                      "n": n, "unknowns": unknowns, "tol": args.tol,
+                      "cycles_per_solve": r64["cycles"][0], "final_relres": r64["rels"][-1]},
+           "roofline": roofline,
+           "kernel_ms_total": r64["prof"]}
+    if not args.no_mixed:
+        print("# bench: mixed precision", file=sys.stderr, flush=True)
+        rmx = run(mg.MG_MIXED)
+        ms_mx = 1e3 * rmx["total"] / args.steps
+        out["mixed"] = {"ms_per_solve": round(ms_mx, 3), "refinement_steps": rmx["cycles"][0],
+                        "final_relres": rmx["rels"][-1],
+                        "mlups": round(unknowns * sum(rmx["cycles"]) / rmx["total"] / 1e6, 1),
+                        "speedup_vs_fp64_time_to_tol": round(ms_step / ms_mx, 3),
+                        "kernel_ms_total": rmx["prof"]}
+    out["solves_per_s_fp64"] = round(args.steps / r64["total"], 3)
+    if not args.no_cpu_baseline:
+        print("# bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

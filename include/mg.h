@@ -1,0 +1,186 @@
+/*
+ * mg.h - C ABI of the MI355X geometric-multigrid V-cycle library (libmg.so).
+ *
+ * The library solves the elliptic problems that ExaStencils-style generated
+ * programs solve iteratively on regular grids with stencil operators (paper,
+ * Sec. 1): -Laplace(u) = f with the 5-point (2-D) or 7-point (3-D) stencil on
+ * a node grid, and -div(k grad u) = f with harmonic-mean face coefficients on
+ * a cell-centred grid (a per-point stencil field, ExaSlang's StencilField),
+ * both on the unit square/cube with zero Dirichlet data (the paper assumes
+ * Dirichlet boundaries, Sec. 2.1).  The solver is the textbook geometric
+ * multigrid V-cycle named by the ExaSlang vocabulary that accompanies the
+ * paper's listings: per-level stencils on coarser/coarsest levels, restriction
+ * and prolongation, jacobi or color-ed relax-ation, a coarsest-level solve,
+ * repeat ... until a residual criterion.
+ *
+ * Conventions shared by every call:
+ *  - Arrays crossing the ABI are dense FP64 in C order with x fastest:
+ *    a[z][y][x] (3-D) or a[y][x] (2-D).  Node grids pass n^d values including
+ *    the boundary nodes (ignored on input, returned as 0); cell grids pass
+ *    N^d cell values.
+ *  - `on_device` = 1: the pointer is HIP device memory on the context's
+ *    device; 0: ordinary host memory.  Host transfers are synchronous.
+ *  - The caller owns every buffer, including the device workspace passed to
+ *    mg_setup; the library never frees caller memory and allocates only small
+ *    host-side metadata.  A context is bound to one HIP stream and is not
+ *    thread-safe; distinct contexts may be used from distinct threads.
+ *  - Every int-returning call returns MG_OK (0) or a negative MG_E* code;
+ *    no C++ exception or abort crosses the ABI.  mg_last_error() returns the
+ *    message of the last failure on a context.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+    MG_OK = 0,
+    MG_EINVAL = -1,      /* bad argument: sizes, kinds, null pointers      */
+    MG_ENOMEM = -2,      /* workspace too small / admission budget exceeded */
+    MG_EDEVICE = -3,     /* a HIP call failed or no device is present       */
+    MG_ENOTCONV = -4,    /* max_cycles reached before the tolerance         */
+    MG_ENONFINITE = -5,  /* residual norm is NaN or Inf                     */
+    MG_EDIVERGED = -6,   /* residual grew in 3 consecutive cycles           */
+    MG_EBUSY = -7        /* server queue full                               */
+};
+
+enum { MG_NODE = 0, MG_CELL = 1 };              /* field location           */
+enum { MG_LAPLACE = 0, MG_VARCOEF = 1 };        /* operator kind            */
+enum { MG_DIRICHLET0 = 0 };                     /* boundary kind            */
+enum { MG_JACOBI = 0, MG_RBGS = 1 };            /* smoother                 */
+enum { MG_FP64 = 0, MG_MIXED = 1 };             /* arithmetic               */
+enum { MG_PREC_FP64 = 0, MG_PREC_FP32 = 1 };    /* which level hierarchy    */
+enum { MG_FIELD_U = 0, MG_FIELD_F = 1, MG_FIELD_R = 2 };
+
+/* Grid: the domain is [0,1]^dim.
+ *  MG_NODE: n[a] = nodes per axis, (coarsest_n - 1) * 2^L + 1, boundary included;
+ *           coarsest_n = 5 means 3^dim unknowns on the coarsest level.
+ *  MG_CELL: n[a] = cells per axis, coarsest_n * 2^L; coarsest_n = 4 typical.
+ *  All axes must have the same size.  dim is 2 or 3. */
+typedef struct mg_grid {
+    int dim;
+    int n[3];
+    int centering;
+    int coarsest_n;
+} mg_grid;
+
+/* Operator.  MG_LAPLACE: -Laplace.  MG_VARCOEF (cell grids only): k holds N^dim
+ * positive cell coefficients (host or device per k_on_device); face
+ * coefficients are their harmonic means, wall faces take the inner cell's k,
+ * coarse faces are the mean of the fine faces that tile them.  k is read
+ * during mg_setup only. */
+typedef struct mg_stencil {
+    int kind;
+    const double* k;
+    int k_on_device;
+} mg_stencil;
+
+typedef struct mg_bc {
+    int kind;                  /* MG_DIRICHLET0 */
+} mg_bc;
+
+/* Cycle options.  omega is the Jacobi damping; nu1/nu2 pre/post sweeps;
+ * post_order 0 = red (even index sum) first, 1 = black first; max_cycles caps
+ * mg_solve (cycles in MG_FP64, refinement steps in MG_MIXED, each one
+ * single-precision V-cycle). */
+typedef struct mg_opts {
+    int smoother;
+    double omega;
+    int nu1, nu2;
+    int precision;
+    int max_cycles;
+    int post_order;
+} mg_opts;
+
+typedef struct mg_ctx mg_ctx;
+
+/* ---------------------------------------------------------------- setup */
+const char* mg_version(void);
+
+/* Fill *o with the defaults: RB-GS, omega 0.8, V(2,2), FP64, 100 cycles, red first. */
+void mg_default_opts(mg_opts* o);
+
+/* Device workspace bytes mg_setup needs for this problem (host-only call). */
+int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes);
+
+/* Build the level hierarchy inside the caller's device workspace (256-byte
+ * aligned, >= mg_workspace_bytes), upload per-level constants, face
+ * coefficients and the FP64 Cholesky factor of the coarsest matrix, and zero
+ * all fields.  hip_stream is a hipStream_t (NULL = default stream); every
+ * later call on the context is ordered on it.  On success *out owns host
+ * metadata only; release it with mg_destroy. */
+int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_opts* o,
+             void* d_workspace, size_t bytes, void* hip_stream, mg_ctx** out);
+
+void mg_destroy(mg_ctx* c);                     /* NULL-safe */
+
+/* ---------------------------------------------------------- data in/out */
+int mg_set_rhs(mg_ctx* c, const double* f, int on_device);
+int mg_set_initial(mg_ctx* c, const double* u0, int on_device);   /* u0 NULL = zero */
+int mg_get_solution(mg_ctx* c, double* u, int on_device);
+
+/* -------------------------------------------------------------- compute */
+/* Enqueue ncycles V(nu1,nu2)-cycles on the stream (MG_MIXED: ncycles FP64
+ * refinement steps, each with one single-precision V-cycle); asynchronous. */
+int mg_vcycle(mg_ctx* c, int ncycles);
+
+/* Cycle until ||f - A u||_2 / ||f - A u0||_2 <= tol over the unknowns;
+ * synchronous.  Returns MG_OK, MG_ENOTCONV, MG_ENONFINITE or MG_EDIVERGED;
+ * cycles_out / relres_out may be NULL. */
+int mg_solve(mg_ctx* c, double tol, int* cycles_out, double* relres_out);
+
+/* ||f - A u||_2 over the unknowns of the finest level (FP64); synchronous. */
+int mg_residual_norm(mg_ctx* c, double* out);
+
+/* Relative residual history of the last mg_solve, starting with 1.0. */
+int mg_history(const mg_ctx* c, double* buf, int cap, int* n);
+
+/* --------------------------------------------- level access and single ops
+ * For kernel-level verification and custom cycles.  Level 0 is the finest.
+ * prec selects the FP64 or the single-precision hierarchy (the latter exists
+ * only with MG_MIXED, where the FP64 hierarchy has level 0 only).  Values
+ * cross the ABI as FP64 and are rounded to FP32 on the way in. */
+int mg_levels(const mg_ctx* c, int* nlevels);
+int mg_level_size(const mg_ctx* c, int level, int* n);
+int mg_level_set(mg_ctx* c, int level, int field, int prec, const double* a, int on_device);
+int mg_level_get(mg_ctx* c, int level, int field, int prec, double* a, int on_device);
+
+enum {
+    MG_OP_GS_RED = 0,     /* u <- GS update of red unknowns                       */
+    MG_OP_GS_BLACK = 1,   /* u <- GS update of black unknowns                     */
+    MG_OP_JACOBI = 2,     /* u <- u + omega D^-1 (f - A u)                        */
+    MG_OP_RESIDUAL = 3,   /* r <- f - A u                                         */
+    MG_OP_RESTRICT = 4,   /* f(level+1) <- R r(level)                             */
+    MG_OP_PROLONG = 5,    /* u(level) <- u(level) + P u(level+1)                  */
+    MG_OP_COARSE = 6,     /* u <- A^-1 f on the coarsest level (FP64 Cholesky)    */
+    MG_OP_VCYCLE = 7      /* one V-cycle starting at `level` (u, f of that level) */
+};
+int mg_apply(mg_ctx* c, int op, int level, int prec);
+
+/* -------------------------------------------------------------- profiling
+ * When enabled, every kernel launch is bracketed by HIP events on the
+ * context's stream.  mg_profile_read synchronises the stream and returns the
+ * launch count and summed milliseconds of one kernel class on one level
+ * (level -1 = all levels). */
+enum {
+    MG_K_SMOOTH = 0, MG_K_RESIDUAL = 1, MG_K_RESTRICT = 2, MG_K_PROLONG = 3,
+    MG_K_COARSE = 4, MG_K_REDUCE = 5, MG_K_CAST = 6, MG_K_UPDATE = 7, MG_K_COPY = 8,
+    MG_K_COUNT = 9
+};
+int mg_profile(mg_ctx* c, int enable);          /* enabling clears the record */
+int mg_profile_read(mg_ctx* c, int kclass, int level, int* count, double* ms);
+
+/* ------------------------------------------------------------------ errors */
+const char* mg_strerror(int code);
+const char* mg_last_error(const mg_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H */

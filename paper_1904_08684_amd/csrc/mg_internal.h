@@ -1,0 +1,73 @@
+// Internal layout and launch descriptors shared by the kernels and the runtime.
+//
+// Colour-split storage.  Every level field keeps its two colours (red = even
+// index sum, black = odd) in separate half arrays: the entry at grid index
+// (x, y, z) lives in colour plane c = (x + y + z) & 1 at (z, y, x >> 1).
+// A red-black Gauss-Seidel half-sweep then reads one whole colour, writes the
+// other, and touches no byte it does not need (8 B read of the other colour,
+// 8 B read of f, 8 B write per updated point, FP64), where an interleaved
+// layout drags both colours through HBM on every half-sweep.  All six axis
+// neighbours of a point sit in the other colour plane: the y and z
+// neighbours at the same x >> 1, the x neighbours at x >> 1 - 1 + p and
+// x >> 1 + p where p = x & 1.
+//
+// Node grids keep their boundary nodes (always zero); cell grids have no
+// boundary entries and handle walls with mirror ghosts inside the kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace mg {
+
+// Geometry of one level in colour-split storage (element strides).
+struct Geom {
+    int dim;          // 2 or 3
+    int n;            // nodes (node grid) or cells (cell grid) per axis
+    int cell;         // 1 for a cell grid
+    int nz, ny;       // array extents in z (1 in 2-D) and y
+    int half;         // entries per colour row actually used
+    int pitch;        // row pitch in elements (>= half)
+    long long plane;  // ny * pitch
+    long long cs;     // colour stride: nz * plane
+    // face-coefficient arrays (cell grids): natural layout, [z][y][x]
+    int fpitch;       // row pitch, >= n + 1
+    long long fplane; // (n + 1) * fpitch
+    long long fsize;  // elements per face array (nz_f * fplane)
+};
+
+// Iteration space of one launch over colour-split points and its tiling into
+// blocks of (1<<lx) x (1<<ly) x (1<<lz) threads.
+struct Space {
+    int xr, y0, yr, z0, zr;  // xs in [0, xr), y in [y0, y0+yr), z in [z0, z0+zr)
+    int ncol, col0;          // colours col0 .. col0+ncol-1
+    int lx, ly, lz;          // log2 tile extents
+    int ntx, nty, ntz;       // tiles per axis
+    long long blocks() const { return (long long)ntx * ncol * nty * ntz; }
+    int threads() const { return 1 << (lx + ly + lz); }
+};
+
+static inline int ilog2ceil(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Tile a space: x extent up to 64 lanes (one wavefront per row), the rest of
+// a 256-thread block over y, then z, each clipped to the space.
+static inline Space make_space(int xr, int y0, int yr, int z0, int zr, int ncol, int col0) {
+    Space s;
+    s.xr = xr; s.y0 = y0; s.yr = yr; s.z0 = z0; s.zr = zr; s.ncol = ncol; s.col0 = col0;
+    s.lx = ilog2ceil(xr) < 6 ? ilog2ceil(xr) : 6;
+    int rem = 8 - s.lx;
+    int ly = ilog2ceil(yr);
+    s.ly = ly < rem ? ly : rem;
+    rem -= s.ly;
+    int lz = ilog2ceil(zr);
+    s.lz = lz < rem ? lz : rem;
+    s.ntx = (xr + (1 << s.lx) - 1) >> s.lx;
+    s.nty = (yr + (1 << s.ly) - 1) >> s.ly;
+    s.ntz = (zr + (1 << s.lz) - 1) >> s.lz;
+    return s;
+}
+
+}  // namespace mg

@@ -1,0 +1,68 @@
+// Host-side launchers of the HIP kernels.  Each returns hipSuccess or the
+// error of the launch.  `prec` is 0 for FP64 fields, 1 for FP32 fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+// Faces of a cell level: x-, y- and z-face coefficient arrays (null for node grids).
+struct Faces {
+    const void* b[3];
+};
+
+// One Gauss-Seidel half-sweep over colour `colour` (0 red, 1 black):
+// u_i <- (f_i / s + sum of neighbours) / (2d) on a node grid,
+// u_i <- (f_i / s + off_i) / diag_i on a cell grid.
+// zero: every neighbour is known to be zero (first sweep from a zero guess).
+hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, const void* f,
+                     const Faces& fc, double s, hipStream_t st);
+
+// Damped Jacobi: out = u + (omega r) / (diag s), out of place.
+hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, const void* f, void* out,
+                         const Faces& fc, double s, double omega, hipStream_t st);
+
+// r = f - A u on the unknowns; with `norm`, per-block (sum r^2, max |r|)
+// pairs are written to partials[2 * block] and *nblocks is set.
+hipError_t launch_residual(const Geom& g, int prec, const void* u, const void* f, void* r,
+                           const Faces& fc, double s, bool norm, bool store, double* partials,
+                           long long* nblocks, hipStream_t st);
+
+// Upper bound of the partials pairs launch_residual may produce on level g.
+long long residual_blocks(const Geom& g);
+
+// f_coarse = R r_fine (full weighting on node grids, 2^d mean on cell grids).
+hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void* r, void* fcoarse,
+                           hipStream_t st);
+
+// u_fine += P e_coarse on the colours in `colour_mask` (bit 0 red, bit 1 black).
+hipError_t launch_prolong(const Geom& gf, const Geom& gc, int prec, void* u, const void* ec,
+                          int colour_mask, hipStream_t st);
+
+// Coarsest solve u = A^-1 f with the FP64 lower Cholesky factor L (m x m, row major).
+hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const double* L, int m,
+                         hipStream_t st);
+
+// Deterministic reduction of `count` (sum, max) pairs to out[0..1];
+// scratch holds at least 2 * ceil(count / 4096) doubles.
+hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
+                         hipStream_t st);
+long long reduce_scratch_pairs(long long count);
+
+// natural FP64 array <-> colour-split level field (node grids: interior only).
+hipError_t launch_pack(const Geom& g, int prec, const double* nat, void* split, hipStream_t st);
+hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat, hipStream_t st);
+
+// Mixed precision: sigma = 2^floor(log2 red[1]) (red[1] = max|r|), stored to
+// *sigma; f32 = fl32(r64 / sigma).  And u64 += sigma * c32.
+hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* red, double* sigma,
+                       hipStream_t st);
+hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
+                         hipStream_t st);
+
+// Zero `bytes` bytes (a kernel, not a memset, so the call is graph-capturable).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace mg

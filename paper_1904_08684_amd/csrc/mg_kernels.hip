@@ -1,0 +1,748 @@
+// HIP kernels of the V-cycle for gfx950 (MI355X).
+//
+// Every level operation is a streaming stencil sweep over colour-split
+// storage (see mg_internal.h).  The operations are HBM-bandwidth bound
+// (~0.4 flop/byte against a machine balance near 10), so the kernels are
+// written for coalesced 64-lane row accesses, neighbour reuse in L1/L2,
+// and XCD-aware block ordering; none of them is a dense contraction, so
+// none uses MFMA.
+//
+// Floating-point evaluation order follows the textbook formulas term by
+// term (neighbours x-, x+, y-, y+, z-, z+; transfer terms in tensor-product
+// order) and the library is compiled with -ffp-contract=off, so each
+// operation rounds exactly as the written formula does.
+
+#include <hip/hip_runtime.h>
+
+#include "mg_kernels.h"
+
+namespace mg {
+namespace {
+
+constexpr int kReduceChunk = 4096;
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b to XCD
+// b % 8).  Renumber so that each XCD walks a contiguous run of logical
+// tiles: consecutive rows and planes then meet in the same XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int per = nb >> 3, rem = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+struct Pt {
+    int xs, y, z, c;
+};
+
+__device__ __forceinline__ bool map_point(const Space& sp, Pt& p) {
+    int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    int t = (int)threadIdx.x;
+    const int lx = t & ((1 << sp.lx) - 1);
+    t >>= sp.lx;
+    const int ly = t & ((1 << sp.ly) - 1);
+    t >>= sp.ly;
+    const int lz = t;
+    const int tx = b % sp.ntx;
+    b /= sp.ntx;
+    const int tc = b % sp.ncol;
+    b /= sp.ncol;
+    const int ty = b % sp.nty;
+    const int tz = b / sp.nty;
+    p.xs = (tx << sp.lx) + lx;
+    p.y = sp.y0 + (ty << sp.ly) + ly;
+    p.z = sp.z0 + (tz << sp.lz) + lz;
+    p.c = sp.col0 + tc;
+    return p.xs < sp.xr && p.y < sp.y0 + sp.yr && p.z < sp.z0 + sp.zr;
+}
+
+__device__ __forceinline__ long long row_off(const Geom& g, int y, int z) {
+    return (long long)z * g.plane + (long long)y * g.pitch;
+}
+
+// Fixed-order block reduction of (sum, max); blockDim.x is a power of two.
+__device__ void block_sum_max(double sq, double mx, double* out2) {
+    __shared__ double s_sq[256];
+    __shared__ double s_mx[256];
+    const int t = (int)threadIdx.x;
+    s_sq[t] = sq;
+    s_mx[t] = mx;
+    __syncthreads();
+    for (int w = (int)blockDim.x >> 1; w > 0; w >>= 1) {
+        if (t < w) {
+            s_sq[t] = s_sq[t] + s_sq[t + w];
+            s_mx[t] = fmax(s_mx[t], s_mx[t + w]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out2[0] = s_sq[0];
+        out2[1] = s_mx[0];
+    }
+}
+
+// ------------------------------------------------------------ node grids
+// Sum of the 2d neighbours of the point at row offset ro (+ xs) in the
+// other colour plane o; par = x & 1.
+template <typename T, int D>
+__device__ __forceinline__ T node_nb(const T* __restrict__ o, long long ro, int par, const Geom& g) {
+    T nb = o[ro - 1 + par];
+    nb = nb + o[ro + par];
+    nb = nb + o[ro - g.pitch];
+    nb = nb + o[ro + g.pitch];
+    if (D == 3) {
+        nb = nb + o[ro - g.plane];
+        nb = nb + o[ro + g.plane];
+    }
+    return nb;
+}
+
+template <typename T, int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 T s) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (x < 1 || x > g.n - 2) return;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    const T nb = ZERO ? T(0) : node_nb<T, D>(other, ro, par, g);
+    me[ro] = (f[ro] / s + nb) / T(2 * D);
+}
+
+template <typename T, int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_node_jacobi(Geom g, Space sp, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out,
+                                                     T s, T omega) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (x < 1 || x > g.n - 2) return;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    const long long me = (long long)p.c * g.cs + ro;
+    const T uc = ZERO ? T(0) : u[me];
+    const T nb = ZERO ? T(0) : node_nb<T, D>(u + (long long)(1 - p.c) * g.cs, ro, par, g);
+    const T r = f[me] - (T(2 * D) * uc - nb) * s;
+    out[me] = uc + (omega * r) / (T(2 * D) * s);
+}
+
+template <typename T, int D, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_node_residual(Geom g, Space sp, const T* __restrict__ u,
+                                                       const T* __restrict__ f, T* __restrict__ r,
+                                                       T s, double* __restrict__ part) {
+    double sq = 0.0, mx = 0.0;
+    Pt p;
+    if (map_point(sp, p)) {
+        const int par = (p.y + p.z + p.c) & 1;
+        const int x = 2 * p.xs + par;
+        if (x >= 1 && x <= g.n - 2) {
+            const long long ro = row_off(g, p.y, p.z) + p.xs;
+            const long long me = (long long)p.c * g.cs + ro;
+            const T nb = node_nb<T, D>(u + (long long)(1 - p.c) * g.cs, ro, par, g);
+            const T rv = f[me] - (T(2 * D) * u[me] - nb) * s;
+            if (STORE) r[me] = rv;
+            const double dv = (double)rv;
+            sq = dv * dv;
+            mx = fabs(dv);
+        }
+    }
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)blockIdx.x);
+}
+
+// Full weighting: f_c[X] = sum_{o in {-1,0,1}^d} prod_a (2 - |o_a|) / 4^d r[2X + o],
+// summed with the z offset slowest and the x offset fastest.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_node_restrict(Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int X = 2 * p.xs + par;
+    if (X < 1 || X > gc.n - 2) return;
+    const int Y = p.y, Z = p.z;
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz) {
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int fx = 2 * X + ox, fy = 2 * Y + oy, fz = (D == 3) ? 2 * Z + oz : 0;
+                const int wgt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) *
+                                (D == 3 ? (2 - (oz < 0 ? -oz : oz)) : 1);
+                const T w = T(wgt) / T(D == 3 ? 64 : 16);
+                const int cf = (fx + fy + fz) & 1;
+                const T term = w * r[(long long)cf * gf.cs + row_off(gf, fy, fz) + (fx >> 1)];
+                acc = first ? term : acc + term;
+                first = false;
+            }
+        }
+    }
+    fcoarse[(long long)p.c * gc.cs + row_off(gc, Y, Z) + p.xs] = acc;
+}
+
+// Linear interpolation as the tensor product of the 1-D rule (even fine
+// node: coarse value; odd: half the sum of the two coarse neighbours),
+// along x first, then y, then z; then u += P e.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_node_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
+                                                      const T* __restrict__ ec) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (x < 1 || x > gf.n - 2) return;
+    const int y = p.y, z = p.z;
+    const T half = T(0.5);
+    const int X0 = x >> 1, X1 = (x + 1) >> 1, Y0 = y >> 1, Y1 = (y + 1) >> 1;
+    const int Z0 = z >> 1, Z1 = (z + 1) >> 1;
+    auto E = [&](int X, int Y, int Z) -> T {
+        return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
+    };
+    auto ex = [&](int Y, int Z) -> T {
+        return (x & 1) ? half * (E(X0, Y, Z) + E(X1, Y, Z)) : E(X0, Y, Z);
+    };
+    auto ey = [&](int Z) -> T { return (y & 1) ? half * (ex(Y0, Z) + ex(Y1, Z)) : ex(Y0, Z); };
+    T e;
+    if (D == 3)
+        e = (z & 1) ? half * (ey(Z0) + ey(Z1)) : ey(Z0);
+    else
+        e = ey(0);
+    const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
+    u[me] = u[me] + e;
+}
+
+// ------------------------------------------------------------ cell grids
+// Face-coefficient sums of one cell: diag = sum of w_f beta_f (w_f = 2 on
+// walls) and, unless ZERO, off = sum of beta_f u_neighbour over interior
+// faces, both in the order x-, x+, y-, y+, z-, z+.
+template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void cell_sums(const Geom& g, const T* __restrict__ o, long long ro,
+                                          int par, int x, int y, int z,
+                                          const T* __restrict__ bx, const T* __restrict__ by,
+                                          const T* __restrict__ bz, T& dg, T& off) {
+    const int N = g.n;
+    const long long fb = (long long)z * g.fplane + (long long)y * g.fpitch + x;
+    const T bxm = bx[fb], bxp = bx[fb + 1], bym = by[fb], byp = by[fb + g.fpitch];
+    const bool wxm = x == 0, wxp = x == N - 1, wym = y == 0, wyp = y == N - 1;
+    dg = wxm ? T(2) * bxm : bxm;
+    dg = dg + (wxp ? T(2) * bxp : bxp);
+    dg = dg + (wym ? T(2) * bym : bym);
+    dg = dg + (wyp ? T(2) * byp : byp);
+    T bzm = T(0), bzp = T(0);
+    bool wzm = true, wzp = true;
+    if (D == 3) {
+        bzm = bz[fb];
+        bzp = bz[fb + g.fplane];
+        wzm = z == 0;
+        wzp = z == N - 1;
+        dg = dg + (wzm ? T(2) * bzm : bzm);
+        dg = dg + (wzp ? T(2) * bzp : bzp);
+    }
+    if (ZERO) {
+        off = T(0);
+        return;
+    }
+    // neighbour indices are clamped to the cell itself where the face is a wall
+    const T vxm = o[wxm ? ro : ro - 1 + par];
+    const T vxp = o[wxp ? ro : ro + par];
+    const T vym = o[wym ? ro : ro - g.pitch];
+    const T vyp = o[wyp ? ro : ro + g.pitch];
+    off = wxm ? T(0) : bxm * vxm;
+    off = off + (wxp ? T(0) : bxp * vxp);
+    off = off + (wym ? T(0) : bym * vym);
+    off = off + (wyp ? T(0) : byp * vyp);
+    if (D == 3) {
+        const T vzm = o[wzm ? ro : ro - g.plane];
+        const T vzp = o[wzp ? ro : ro + g.plane];
+        off = off + (wzm ? T(0) : bzm * vzm);
+        off = off + (wzp ? T(0) : bzp * vzp);
+    }
+}
+
+template <typename T, int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_cell_gs(Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 const T* __restrict__ bx, const T* __restrict__ by,
+                                                 const T* __restrict__ bz, T s) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    T dg, off;
+    cell_sums<T, D, ZERO>(g, other, ro, par, x, p.y, p.z, bx, by, bz, dg, off);
+    me[ro] = (f[ro] / s + off) / dg;
+}
+
+template <typename T, int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_cell_jacobi(Geom g, Space sp, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out,
+                                                     const T* __restrict__ bx, const T* __restrict__ by,
+                                                     const T* __restrict__ bz, T s, T omega) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    const long long me = (long long)p.c * g.cs + ro;
+    T dg, off;
+    cell_sums<T, D, ZERO>(g, u + (long long)(1 - p.c) * g.cs, ro, par, x, p.y, p.z, bx, by, bz, dg, off);
+    const T uc = ZERO ? T(0) : u[me];
+    const T r = f[me] - (dg * uc - off) * s;
+    out[me] = uc + (omega * r) / (dg * s);
+}
+
+template <typename T, int D, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_cell_residual(Geom g, Space sp, const T* __restrict__ u,
+                                                       const T* __restrict__ f, T* __restrict__ r,
+                                                       const T* __restrict__ bx, const T* __restrict__ by,
+                                                       const T* __restrict__ bz, T s,
+                                                       double* __restrict__ part) {
+    double sq = 0.0, mx = 0.0;
+    Pt p;
+    if (map_point(sp, p)) {
+        const int par = (p.y + p.z + p.c) & 1;
+        const int x = 2 * p.xs + par;
+        const long long ro = row_off(g, p.y, p.z) + p.xs;
+        const long long me = (long long)p.c * g.cs + ro;
+        T dg, off;
+        cell_sums<T, D, false>(g, u + (long long)(1 - p.c) * g.cs, ro, par, x, p.y, p.z, bx, by, bz, dg,
+                               off);
+        const T rv = f[me] - (dg * u[me] - off) * s;
+        if (STORE) r[me] = rv;
+        const double dv = (double)rv;
+        sq = dv * dv;
+        mx = fabs(dv);
+    }
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)blockIdx.x);
+}
+
+// Mean of the 2^d children, summed with the z offset slowest, then scaled.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int X = 2 * p.xs + par, Y = p.y, Z = p.z;
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int oz = 0; oz <= (D == 3 ? 1 : 0); ++oz) {
+#pragma unroll
+        for (int oy = 0; oy <= 1; ++oy) {
+#pragma unroll
+            for (int ox = 0; ox <= 1; ++ox) {
+                const int fx = 2 * X + ox, fy = 2 * Y + oy, fz = (D == 3) ? 2 * Z + oz : 0;
+                const T v = r[(long long)((fx + fy + fz) & 1) * gf.cs + row_off(gf, fy, fz) + (fx >> 1)];
+                acc = first ? v : acc + v;
+                first = false;
+            }
+        }
+    }
+    fcoarse[(long long)p.c * gc.cs + row_off(gc, Y, Z) + p.xs] = acc * T(D == 3 ? 0.125 : 0.25);
+}
+
+// Cell-centred linear interpolation: per axis fine(2I) = 3/4 e[I] + 1/4 e[I-1],
+// fine(2I+1) = 3/4 e[I] + 1/4 e[I+1], mirror ghost -e[I] beyond a wall;
+// x first, then y, then z; then u += P e.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cell_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
+                                                      const T* __restrict__ ec) {
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par, y = p.y, z = p.z;
+    const int Nc = gc.n;
+    const T a = T(0.75), b = T(0.25);
+    const int I = x >> 1, In = (x & 1) ? I + 1 : I - 1;
+    const int J = y >> 1, Jn = (y & 1) ? J + 1 : J - 1;
+    const int K = z >> 1, Kn = (z & 1) ? K + 1 : K - 1;
+    const bool wI = In < 0 || In >= Nc, wJ = Jn < 0 || Jn >= Nc, wK = Kn < 0 || Kn >= Nc;
+    auto E = [&](int X, int Y, int Z) -> T {
+        return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
+    };
+    auto ex = [&](int Y, int Z) -> T {
+        const T c0 = E(I, Y, Z);
+        const T c1 = wI ? -c0 : E(In, Y, Z);
+        return a * c0 + b * c1;
+    };
+    auto ey = [&](int Z) -> T {
+        const T c0 = ex(J, Z);
+        const T c1 = wJ ? -c0 : ex(Jn, Z);
+        return a * c0 + b * c1;
+    };
+    T e;
+    if (D == 3) {
+        const T c0 = ey(K);
+        const T c1 = wK ? -c0 : ey(Kn);
+        e = a * c0 + b * c1;
+    } else {
+        e = ey(0);
+    }
+    const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
+    u[me] = u[me] + e;
+}
+
+// ------------------------------------------------------ coarsest, reductions
+// Exact coarsest solve: gather the m unknowns (C order), L y = b and
+// L^T x = y column by column in FP64, scatter x.  One block of 64 threads.
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, T* __restrict__ u,
+                                               const double* __restrict__ L, int m) {
+    __shared__ double b[64];
+    const int t = (int)threadIdx.x;
+    const int side = g.cell ? g.n : g.n - 2, off = g.cell ? 0 : 1;
+    long long idx = 0;
+    if (t < m) {
+        const int x = t % side + off, y = (t / side) % side + off;
+        const int z = (g.dim == 3) ? t / (side * side) + off : 0;
+        idx = (long long)((x + y + z) & 1) * g.cs + row_off(g, y, z) + (x >> 1);
+        b[t] = (double)f[idx];
+    }
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        if (t == j) b[j] = b[j] / L[j * m + j];
+        __syncthreads();
+        if (t > j && t < m) b[t] = b[t] - L[t * m + j] * b[j];
+        __syncthreads();
+    }
+    for (int j = m - 1; j >= 0; --j) {
+        if (t == j) b[j] = b[j] / L[j * m + j];
+        __syncthreads();
+        if (t < j) b[t] = b[t] - L[j * m + t] * b[j];
+        __syncthreads();
+    }
+    if (t < m) u[idx] = (T)b[t];
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, long long count,
+                                                double* __restrict__ out) {
+    const long long i0 = (long long)blockIdx.x * kReduceChunk;
+    const long long i1 = i0 + kReduceChunk < count ? i0 + kReduceChunk : count;
+    double sq = 0.0, mx = 0.0;
+    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        sq = sq + in[2 * i];
+        mx = fmax(mx, in[2 * i + 1]);
+    }
+    block_sum_max(sq, mx, out + 2 * (long long)blockIdx.x);
+}
+
+// ------------------------------------------------------ layout conversion
+__device__ __forceinline__ bool nat_to_split(const Geom& g, long long i, long long& s) {
+    const int n = g.n;
+    const int x = (int)(i % n);
+    const int y = (int)((i / n) % n);
+    const int z = g.dim == 3 ? (int)(i / ((long long)n * n)) : 0;
+    s = (long long)((x + y + z) & 1) * g.cs + row_off(g, y, z) + (x >> 1);
+    if (g.cell) return true;
+    const bool bx = x == 0 || x == n - 1, by = y == 0 || y == n - 1;
+    const bool bz = g.dim == 3 && (z == 0 || z == n - 1);
+    return !(bx || by || bz);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack(Geom g, long long total, const double* __restrict__ nat,
+                                              T* __restrict__ split) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    long long s;
+    if (nat_to_split(g, i, s)) split[s] = (T)nat[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack(Geom g, long long total, const T* __restrict__ split,
+                                                double* __restrict__ nat) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    long long s;
+    nat[i] = nat_to_split(g, i, s) ? (double)split[s] : 0.0;
+}
+
+// ------------------------------------------------------ mixed precision
+__device__ __forceinline__ double pow2_floor(double v) {
+    if (!(v > 0.0)) return 1.0;
+    int e;
+    frexp(v, &e);              // v = m 2^e, m in [0.5, 1)
+    return ldexp(1.0, e - 1);
+}
+
+__global__ __launch_bounds__(256) void k_cast(Geom g, Space sp, const double* __restrict__ r,
+                                              float* __restrict__ f32, const double* __restrict__ red,
+                                              double* __restrict__ sigma_out) {
+    const double sigma = pow2_floor(red[1]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sigma_out = sigma;
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (!g.cell && (x < 1 || x > g.n - 2)) return;
+    const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
+    f32[me] = (float)(r[me] / sigma);
+}
+
+__global__ __launch_bounds__(256) void k_update(Geom g, Space sp, double* __restrict__ u,
+                                                const float* __restrict__ c32,
+                                                const double* __restrict__ sigma_p) {
+    const double sigma = *sigma_p;
+    Pt p;
+    if (!map_point(sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (!g.cell && (x < 1 || x > g.n - 2)) return;
+    const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
+    u[me] = u[me] + sigma * (double)c32[me];
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, long long n16) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ------------------------------------------------------------- spaces
+// Points of one or both colours over the unknowns of a level.
+Space level_space(const Geom& g, int ncol, int col0) {
+    if (g.cell)
+        return make_space(g.n / 2, 0, g.n, 0, g.dim == 3 ? g.n : 1, ncol, col0);
+    // node grid: interior rows/planes; xs in [0, (n-1)/2) covers interior x
+    return make_space((g.n - 1) / 2, 1, g.n - 2, g.dim == 3 ? 1 : 0, g.dim == 3 ? g.n - 2 : 1, ncol, col0);
+}
+
+dim3 grid_of(const Space& sp) { return dim3((unsigned)sp.blocks()); }
+dim3 block_of(const Space& sp) { return dim3((unsigned)sp.threads()); }
+
+template <typename T>
+const T* cp(const void* p) { return static_cast<const T*>(p); }
+template <typename T>
+T* mp(void* p) { return static_cast<T*>(p); }
+
+}  // namespace
+
+// =================================================================== launchers
+#define MG_DISPATCH_DIM(g, ...)      \
+    if ((g).dim == 3) {              \
+        constexpr int D = 3;         \
+        __VA_ARGS__;                 \
+    } else {                         \
+        constexpr int D = 2;         \
+        __VA_ARGS__;                 \
+    }
+
+template <typename T>
+static hipError_t gs_t(const Geom& g, int colour, bool zero, void* u, const void* f, const Faces& fc,
+                       double s, hipStream_t st) {
+    const Space sp = level_space(g, 1, colour);
+    T* me = mp<T>(u) + (long long)colour * g.cs;
+    const T* other = cp<T>(u) + (long long)(1 - colour) * g.cs;
+    const T* fm = cp<T>(f) + (long long)colour * g.cs;
+    if (g.cell) {
+        MG_DISPATCH_DIM(g, if (zero) k_cell_gs<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, me, other, fm, cp<T>(fc.b[0]), cp<T>(fc.b[1]), cp<T>(fc.b[2]), (T)s);
+                           else k_cell_gs<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, me, other, fm, cp<T>(fc.b[0]), cp<T>(fc.b[1]), cp<T>(fc.b[2]), (T)s));
+    } else {
+        MG_DISPATCH_DIM(g, if (zero) k_node_gs<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, me, other, fm, (T)s);
+                           else k_node_gs<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, me, other, fm, (T)s));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, const void* f,
+                     const Faces& fc, double s, hipStream_t st) {
+    return prec ? gs_t<float>(g, colour, zero, u, f, fc, s, st)
+                : gs_t<double>(g, colour, zero, u, f, fc, s, st);
+}
+
+template <typename T>
+static hipError_t jacobi_t(const Geom& g, bool zero, const void* u, const void* f, void* out,
+                           const Faces& fc, double s, double omega, hipStream_t st) {
+    const Space sp = level_space(g, 2, 0);
+    if (g.cell) {
+        MG_DISPATCH_DIM(g, if (zero) k_cell_jacobi<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<T>(u), cp<T>(f), mp<T>(out), cp<T>(fc.b[0]), cp<T>(fc.b[1]),
+                               cp<T>(fc.b[2]), (T)s, (T)omega);
+                           else k_cell_jacobi<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<T>(u), cp<T>(f), mp<T>(out), cp<T>(fc.b[0]), cp<T>(fc.b[1]),
+                               cp<T>(fc.b[2]), (T)s, (T)omega));
+    } else {
+        MG_DISPATCH_DIM(g, if (zero) k_node_jacobi<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, (T)omega);
+                           else k_node_jacobi<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, (T)omega));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, const void* f, void* out,
+                         const Faces& fc, double s, double omega, hipStream_t st) {
+    return prec ? jacobi_t<float>(g, zero, u, f, out, fc, s, omega, st)
+                : jacobi_t<double>(g, zero, u, f, out, fc, s, omega, st);
+}
+
+long long residual_blocks(const Geom& g) { return level_space(g, 2, 0).blocks(); }
+
+template <typename T, bool NORM, bool STORE>
+static void residual_tt(const Geom& g, const Space& sp, const void* u, const void* f, void* r,
+                        const Faces& fc, double s, double* part, hipStream_t st) {
+    if (g.cell) {
+        MG_DISPATCH_DIM(g, k_cell_residual<T, D, NORM, STORE><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<T>(u), cp<T>(f), mp<T>(r), cp<T>(fc.b[0]), cp<T>(fc.b[1]),
+                               cp<T>(fc.b[2]), (T)s, part));
+    } else {
+        MG_DISPATCH_DIM(g, k_node_residual<T, D, NORM, STORE><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part));
+    }
+}
+
+template <typename T>
+static hipError_t residual_t(const Geom& g, const void* u, const void* f, void* r, const Faces& fc,
+                             double s, bool norm, bool store, double* part, long long* nb,
+                             hipStream_t st) {
+    const Space sp = level_space(g, 2, 0);
+    if (nb) *nb = sp.blocks();
+    if (norm && store) residual_tt<T, true, true>(g, sp, u, f, r, fc, s, part, st);
+    else if (norm) residual_tt<T, true, false>(g, sp, u, f, r, fc, s, part, st);
+    else residual_tt<T, false, true>(g, sp, u, f, r, fc, s, part, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const Geom& g, int prec, const void* u, const void* f, void* r,
+                           const Faces& fc, double s, bool norm, bool store, double* partials,
+                           long long* nblocks, hipStream_t st) {
+    return prec ? residual_t<float>(g, u, f, r, fc, s, norm, store, partials, nblocks, st)
+                : residual_t<double>(g, u, f, r, fc, s, norm, store, partials, nblocks, st);
+}
+
+template <typename T>
+static hipError_t restrict_t(const Geom& gf, const Geom& gc, const void* r, void* fco, hipStream_t st) {
+    const Space sp = level_space(gc, 2, 0);
+    if (gf.cell) {
+        MG_DISPATCH_DIM(gf, k_cell_restrict<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, cp<T>(r),
+                                                                                         mp<T>(fco)));
+    } else {
+        MG_DISPATCH_DIM(gf, k_node_restrict<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, cp<T>(r),
+                                                                                         mp<T>(fco)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void* r, void* fcoarse,
+                           hipStream_t st) {
+    return prec ? restrict_t<float>(gf, gc, r, fcoarse, st) : restrict_t<double>(gf, gc, r, fcoarse, st);
+}
+
+template <typename T>
+static hipError_t prolong_t(const Geom& gf, const Geom& gc, void* u, const void* ec, int mask,
+                            hipStream_t st) {
+    const int ncol = (mask == 3) ? 2 : 1;
+    const int col0 = (mask == 2) ? 1 : 0;
+    const Space sp = level_space(gf, ncol, col0);
+    if (gf.cell) {
+        MG_DISPATCH_DIM(gf, k_cell_prolong<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, mp<T>(u),
+                                                                                        cp<T>(ec)));
+    } else {
+        MG_DISPATCH_DIM(gf, k_node_prolong<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, mp<T>(u),
+                                                                                        cp<T>(ec)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Geom& gf, const Geom& gc, int prec, void* u, const void* ec,
+                          int colour_mask, hipStream_t st) {
+    if (colour_mask < 1 || colour_mask > 3) return hipErrorInvalidValue;
+    return prec ? prolong_t<float>(gf, gc, u, ec, colour_mask, st)
+                : prolong_t<double>(gf, gc, u, ec, colour_mask, st);
+}
+
+hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const double* L, int m,
+                         hipStream_t st) {
+    if (m < 1 || m > 64) return hipErrorInvalidValue;
+    if (prec)
+        k_coarse<float><<<1, 64, 0, st>>>(g, cp<float>(f), mp<float>(u), L, m);
+    else
+        k_coarse<double><<<1, 64, 0, st>>>(g, cp<double>(f), mp<double>(u), L, m);
+    return hipGetLastError();
+}
+
+long long reduce_scratch_pairs(long long count) {
+    long long total = 0;
+    while (count > 1) {
+        count = (count + kReduceChunk - 1) / kReduceChunk;
+        total += count;
+    }
+    return total + 1;
+}
+
+hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
+                         hipStream_t st) {
+    const double* in = partials;
+    double* buf = scratch;
+    if (count < 1) return hipErrorInvalidValue;
+    while (count > 1) {
+        const long long nb = (count + kReduceChunk - 1) / kReduceChunk;
+        double* dst = (nb == 1) ? out : buf;
+        k_reduce<<<(unsigned)nb, 256, 0, st>>>(in, count, dst);
+        in = dst;
+        buf += 2 * nb;
+        count = nb;
+    }
+    if (in != out) {   // a single partial pair: copy it through the reduce kernel
+        k_reduce<<<1, 256, 0, st>>>(in, 1, out);
+    }
+    return hipGetLastError();
+}
+
+static long long nat_total(const Geom& g) {
+    return (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
+}
+
+hipError_t launch_pack(const Geom& g, int prec, const double* nat, void* split, hipStream_t st) {
+    const long long tot = nat_total(g);
+    const unsigned nb = (unsigned)((tot + 255) / 256);
+    if (prec)
+        k_pack<float><<<nb, 256, 0, st>>>(g, tot, nat, mp<float>(split));
+    else
+        k_pack<double><<<nb, 256, 0, st>>>(g, tot, nat, mp<double>(split));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat, hipStream_t st) {
+    const long long tot = nat_total(g);
+    const unsigned nb = (unsigned)((tot + 255) / 256);
+    if (prec)
+        k_unpack<float><<<nb, 256, 0, st>>>(g, tot, cp<float>(split), nat);
+    else
+        k_unpack<double><<<nb, 256, 0, st>>>(g, tot, cp<double>(split), nat);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* red, double* sigma,
+                       hipStream_t st) {
+    const Space sp = level_space(g, 2, 0);
+    k_cast<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, r64, f32, red, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
+                         hipStream_t st) {
+    const Space sp = level_space(g, 2, 0);
+    k_update<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, u64, c32, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const long long n16 = (long long)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    k_zero<<<(unsigned)((n16 + 255) / 256), 256, 0, st>>>(static_cast<uint4*>(p), n16);
+    return hipGetLastError();
+}
+
+}  // namespace mg

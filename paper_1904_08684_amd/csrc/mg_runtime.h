@@ -1,0 +1,105 @@
+// Host-side state of a multigrid context (internal to libmg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_internal.h"
+#include "mg_kernels.h"
+
+namespace mg {
+
+constexpr int kMaxLevels = 16;
+
+// Byte offsets of one level's fields inside the workspace, per precision
+// (0 = FP64, 1 = FP32); SIZE_MAX = absent.
+struct LevelPlan {
+    Geom g;
+    bool has[2] = {false, false};
+    size_t u[2] = {SIZE_MAX, SIZE_MAX}, f[2] = {SIZE_MAX, SIZE_MAX}, r[2] = {SIZE_MAX, SIZE_MAX};
+    size_t utmp[2] = {SIZE_MAX, SIZE_MAX};
+    size_t beta[2][3] = {{SIZE_MAX, SIZE_MAX, SIZE_MAX}, {SIZE_MAX, SIZE_MAX, SIZE_MAX}};
+};
+
+struct Plan {
+    int L = 0, m = 0;
+    std::vector<LevelPlan> lv;
+    long long partial_pairs = 0;
+    size_t partials = 0, reduce_scratch = 0, red = 0, chol = 0, staging = 0, total = 0;
+};
+
+// Workspace layout for a problem; returns the total byte count.
+size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, Plan* out);
+
+struct Level {
+    Geom g;
+    bool has[2] = {false, false};
+    void* u[2] = {nullptr, nullptr};
+    void* f[2] = {nullptr, nullptr};
+    void* r[2] = {nullptr, nullptr};
+    void* utmp[2] = {nullptr, nullptr};
+    void* beta[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    size_t field_bytes[2] = {0, 0};
+};
+
+struct Rec {
+    int kclass, level;
+    hipEvent_t e0, e1;
+};
+
+struct Ctx {
+    mg_grid grid{};
+    mg_opts opts{};
+    int kind = MG_LAPLACE;
+    void* base = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    int L = 0, m = 0;
+    std::vector<Level> lv;
+    long long partial_pairs = 0;
+    double* partials = nullptr;
+    double* reduce_scratch = nullptr;
+    double* red = nullptr;        // [sum r^2, max |r|, sigma]
+    double* chol = nullptr;
+    double* staging = nullptr;
+    std::vector<double> hist;
+    std::string err;
+    std::vector<std::vector<double>> coarse_beta_host;
+    // profiling
+    bool prof = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double agg_ms[MG_K_COUNT][kMaxLevels] = {};
+    int agg_n[MG_K_COUNT][kMaxLevels] = {};
+
+    int fail(int code, const std::string& msg);
+    int dev(hipError_t e, const char* what);
+    void* at(size_t off) const;
+    Faces faces(int l, int pr) const;
+    double scale(int l) const;
+    hipEvent_t begin();
+    hipEvent_t event();
+    int record(int kclass, int level, hipError_t e, hipEvent_t e0, const char* what);
+
+    int gs(int l, int pr, int colour, bool zero);
+    int jacobi(int l, int pr, bool zero);
+    int smooth(int l, int pr, int sweeps, bool from_zero, int first_colour);
+    int residual(int l, int pr, bool norm, bool store);
+    int restrict_to(int l, int pr);
+    int prolong(int l, int pr, int mask);
+    int coarse(int pr);
+    int vcycle(int l, int pr, bool from_zero);
+    int refine_step();
+    int read_red(double* sq, double* mx);
+    int norm(double* out);
+    int step(int k);
+    int solve(double tol, int* cycles_out, double* relres_out);
+};
+
+}  // namespace mg

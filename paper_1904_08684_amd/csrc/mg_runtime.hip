@@ -1,0 +1,932 @@
+// Runtime of the multigrid library: workspace plan, level hierarchy, the
+// V-cycle driver, solve-to-tolerance, FP64 iterative refinement around
+// single-precision cycles, level access and profiling, behind the C ABI of
+// include/mg.h.
+//
+// The V-cycle is the textbook recursion (gamma = 1) over rediscretised
+// per-level stencils, the structure that ExaSlang's coarser/coarsest levels,
+// restriction/prolongation, relax and solve keywords describe (paper's
+// listing vocabulary; the algorithm itself is not stated in the paper).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg.h"
+#include "mg_internal.h"
+#include "mg_kernels.h"
+#include "mg_runtime.h"
+
+using namespace mg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+Geom make_geom(int dim, int n, int cell) {
+    Geom g;
+    g.dim = dim;
+    g.n = n;
+    g.cell = cell;
+    g.nz = dim == 3 ? n : 1;
+    g.ny = n;
+    g.half = cell ? n / 2 : (n + 1) / 2;
+    g.pitch = round_up(g.half, 8);
+    g.plane = (long long)g.ny * g.pitch;
+    g.cs = (long long)g.nz * g.plane;
+    g.fpitch = round_up(n + 1, 8);
+    g.fplane = (long long)(n + 1) * g.fpitch;
+    g.fsize = (dim == 3 ? (long long)(n + 1) : 1LL) * g.fplane;
+    return g;
+}
+
+// ----------------------------------------------------------- validation
+int validate(const mg_grid* g, const mg_stencil* st, const mg_opts* o, std::string* why) {
+    auto bad = [&](const char* m) {
+        if (why) *why = m;
+        return MG_EINVAL;
+    };
+    if (!g || !o) return bad("null grid or options");
+    if (g->dim != 2 && g->dim != 3) return bad("dim must be 2 or 3");
+    if (g->centering != MG_NODE && g->centering != MG_CELL) return bad("unknown centering");
+    for (int a = 1; a < g->dim; ++a)
+        if (g->n[a] != g->n[0]) return bad("all axes must have the same size");
+    const int n = g->n[0], c = g->coarsest_n;
+    if (g->centering == MG_NODE) {
+        if (c < 3) return bad("node coarsest_n must be >= 3");
+        if (n < c || (n - 1) % (c - 1)) return bad("node n must be (coarsest_n - 1) * 2^L + 1");
+        const int q = (n - 1) / (c - 1);
+        if (q & (q - 1)) return bad("node n must be (coarsest_n - 1) * 2^L + 1");
+    } else {
+        if (c < 2) return bad("cell coarsest_n must be >= 2");
+        if (n < c || n % c) return bad("cell n must be coarsest_n * 2^L");
+        const int q = n / c;
+        if (q & (q - 1)) return bad("cell n must be coarsest_n * 2^L");
+        if (c % 2) return bad("cell coarsest_n must be even");
+    }
+    long long m = 1;
+    const int side = g->centering == MG_NODE ? c - 2 : c;
+    for (int a = 0; a < g->dim; ++a) m *= side;
+    if (m > 64) return bad("coarsest level has more than 64 unknowns");
+    if (st) {
+        if (st->kind != MG_LAPLACE && st->kind != MG_VARCOEF) return bad("unknown stencil kind");
+        if (st->kind == MG_VARCOEF && g->centering != MG_CELL)
+            return bad("variable coefficients need a cell-centred grid");
+        if (st->kind == MG_VARCOEF && !st->k) return bad("variable coefficients need k");
+    }
+    if (o->smoother != MG_JACOBI && o->smoother != MG_RBGS) return bad("unknown smoother");
+    if (o->precision != MG_FP64 && o->precision != MG_MIXED) return bad("unknown precision");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1) return bad("need nu1, nu2 >= 0 and nu1 + nu2 >= 1");
+    if (!(o->omega > 0.0) || !(o->omega < 2.0)) return bad("omega must be in (0, 2)");
+    if (o->max_cycles < 1) return bad("max_cycles must be >= 1");
+    if (o->post_order != 0 && o->post_order != 1) return bad("post_order must be 0 or 1");
+    return MG_OK;
+}
+
+std::vector<int> ladder(const mg_grid* g) {
+    std::vector<int> s{g->n[0]};
+    int n = g->n[0];
+    while (n > g->coarsest_n) {
+        n = g->centering == MG_NODE ? (n - 1) / 2 + 1 : n / 2;
+        s.push_back(n);
+    }
+    return s;
+}
+
+}  // namespace
+
+// =================================================================== plan
+namespace mg {
+
+size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, Plan* out) {
+    Plan p;
+    const int cell = g->centering == MG_CELL;
+    const bool varcoef = cell;   // cell grids always carry face coefficients
+    const bool mixed = o->precision == MG_MIXED;
+    const bool jac = o->smoother == MG_JACOBI;
+    (void)st;
+    std::vector<int> sizes = ladder(g);
+    p.L = (int)sizes.size();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
+    for (int l = 0; l < p.L; ++l) {
+        LevelPlan lp;
+        lp.g = make_geom(g->dim, sizes[l], cell);
+        for (int pr = 0; pr < 2; ++pr) {
+            const bool has = pr == 0 ? (!mixed || l == 0) : mixed;
+            lp.has[pr] = has;
+            if (!has) continue;
+            const size_t es = pr == 0 ? 8 : 4;
+            const size_t fb = (size_t)(2 * lp.g.cs) * es;
+            lp.u[pr] = take(fb);
+            lp.f[pr] = take(fb);
+            lp.r[pr] = take(fb);
+            const bool need_tmp = jac && !(mixed && pr == 0);
+            lp.utmp[pr] = need_tmp ? take(fb) : SIZE_MAX;
+            for (int a = 0; a < 3; ++a)
+                lp.beta[pr][a] = (varcoef && a < g->dim) ? take((size_t)lp.g.fsize * es) : SIZE_MAX;
+        }
+        p.lv.push_back(lp);
+    }
+    const Geom& g0 = p.lv[0].g;
+    p.partial_pairs = residual_blocks(g0);
+    p.partials = take((size_t)p.partial_pairs * 16);
+    p.reduce_scratch = take((size_t)reduce_scratch_pairs(p.partial_pairs) * 16);
+    p.red = take(64);   // [sum r^2, max |r|, sigma, spare...]
+    const Geom& gc = p.lv.back().g;
+    const int side = cell ? gc.n : gc.n - 2;
+    p.m = side * side * (g->dim == 3 ? side : 1);
+    p.chol = take((size_t)p.m * p.m * 8);
+    const long long nat = (long long)g0.n * g0.n * (g->dim == 3 ? g0.n : 1);
+    p.staging = take((size_t)nat * 8);
+    p.total = off;
+    if (out) *out = p;
+    return off;
+}
+
+}  // namespace mg
+
+// ============================================================ host numerics
+namespace {
+
+// Face coefficients of the finest cell level from cell values k (FP64):
+// interior face 2 ka kb / (ka + kb) evaluated as ((2 ka) kb) / (ka + kb) with
+// ka the lower cell, wall face the adjacent cell's k.  Stored in the device
+// face layout [z][y][x] with row pitch fpitch and plane fplane.
+void harmonic_faces(const Geom& g, const double* k, std::vector<double> beta[3]) {
+    const int N = g.n, d = g.dim;
+    const int nz = d == 3 ? N : 1;
+    for (int a = 0; a < d; ++a) beta[a].assign((size_t)g.fsize, 0.0);
+    auto K = [&](int x, int y, int z) { return k[((size_t)z * N + y) * N + x]; };
+    auto at = [&](std::vector<double>& b, int x, int y, int z) -> double& {
+        return b[(size_t)z * g.fplane + (size_t)y * g.fpitch + x];
+    };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x <= N; ++x) {
+                double v;
+                if (x == 0) v = K(0, y, z);
+                else if (x == N) v = K(N - 1, y, z);
+                else {
+                    const double ka = K(x - 1, y, z), kb = K(x, y, z);
+                    v = ((2.0 * ka) * kb) / (ka + kb);
+                }
+                at(beta[0], x, y, z) = v;
+            }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y <= N; ++y)
+            for (int x = 0; x < N; ++x) {
+                double v;
+                if (y == 0) v = K(x, 0, z);
+                else if (y == N) v = K(x, N - 1, z);
+                else {
+                    const double ka = K(x, y - 1, z), kb = K(x, y, z);
+                    v = ((2.0 * ka) * kb) / (ka + kb);
+                }
+                at(beta[1], x, y, z) = v;
+            }
+    if (d == 3)
+        for (int z = 0; z <= N; ++z)
+            for (int y = 0; y < N; ++y)
+                for (int x = 0; x < N; ++x) {
+                    double v;
+                    if (z == 0) v = K(x, y, 0);
+                    else if (z == N) v = K(x, y, N - 1);
+                    else {
+                        const double ka = K(x, y, z - 1), kb = K(x, y, z);
+                        v = ((2.0 * ka) * kb) / (ka + kb);
+                    }
+                    at(beta[2], x, y, z) = v;
+                }
+}
+
+// Coarse face = mean of the 2^(d-1) fine faces that tile it: fine face 2I
+// along the face's axis, index pairs (2J, 2J+1) along the others, summed
+// with the lower array axis slowest, then scaled by 1 / 2^(d-1).
+void coarsen_faces(const Geom& gf, const std::vector<double> bf[3], const Geom& gc, std::vector<double> bc[3]) {
+    const int d = gf.dim, Nc = gc.n;
+    const double sc = d == 3 ? 0.25 : 0.5;
+    auto F = [&](const std::vector<double>& b, int x, int y, int z) {
+        return b[(size_t)z * gf.fplane + (size_t)y * gf.fpitch + x];
+    };
+    for (int a = 0; a < d; ++a) bc[a].assign((size_t)gc.fsize, 0.0);
+    const int ncz = d == 3 ? Nc : 1;
+    // x faces: others are (z, y) in 3-D, (y) in 2-D
+    for (int z = 0; z < ncz; ++z)
+        for (int y = 0; y < Nc; ++y)
+            for (int x = 0; x <= Nc; ++x) {
+                double acc;
+                if (d == 3)
+                    acc = ((F(bf[0], 2 * x, 2 * y, 2 * z) + F(bf[0], 2 * x, 2 * y + 1, 2 * z)) +
+                           F(bf[0], 2 * x, 2 * y, 2 * z + 1)) + F(bf[0], 2 * x, 2 * y + 1, 2 * z + 1);
+                else
+                    acc = F(bf[0], 2 * x, 2 * y, 0) + F(bf[0], 2 * x, 2 * y + 1, 0);
+                bc[0][(size_t)z * gc.fplane + (size_t)y * gc.fpitch + x] = acc * sc;
+            }
+    // y faces: others are (z, x) in 3-D, (x) in 2-D
+    for (int z = 0; z < ncz; ++z)
+        for (int y = 0; y <= Nc; ++y)
+            for (int x = 0; x < Nc; ++x) {
+                double acc;
+                if (d == 3)
+                    acc = ((F(bf[1], 2 * x, 2 * y, 2 * z) + F(bf[1], 2 * x + 1, 2 * y, 2 * z)) +
+                           F(bf[1], 2 * x, 2 * y, 2 * z + 1)) + F(bf[1], 2 * x + 1, 2 * y, 2 * z + 1);
+                else
+                    acc = F(bf[1], 2 * x, 2 * y, 0) + F(bf[1], 2 * x + 1, 2 * y, 0);
+                bc[1][(size_t)z * gc.fplane + (size_t)y * gc.fpitch + x] = acc * sc;
+            }
+    // z faces: others are (y, x)
+    if (d == 3)
+        for (int z = 0; z <= Nc; ++z)
+            for (int y = 0; y < Nc; ++y)
+                for (int x = 0; x < Nc; ++x) {
+                    const double acc = ((F(bf[2], 2 * x, 2 * y, 2 * z) + F(bf[2], 2 * x + 1, 2 * y, 2 * z)) +
+                                        F(bf[2], 2 * x, 2 * y + 1, 2 * z)) + F(bf[2], 2 * x + 1, 2 * y + 1, 2 * z);
+                    bc[2][(size_t)z * gc.fplane + (size_t)y * gc.fpitch + x] = acc * sc;
+                }
+}
+
+// Dense FP64 matrix of the coarsest level over its unknowns in C order.
+std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta) {
+    const int d = g.dim;
+    const int side = g.cell ? g.n : g.n - 2, off = g.cell ? 0 : 1;
+    const int m = side * side * (d == 3 ? side : 1);
+    std::vector<double> A((size_t)m * m, 0.0);
+    auto idx = [&](int x, int y, int z) { return ((z - (d == 3 ? off : 0)) * side + (y - off)) * side + (x - off); };
+    const double s = g.cell ? (double)g.n * g.n : (double)(g.n - 1) * (g.n - 1);
+    const int zlo = d == 3 ? off : 0, zhi = d == 3 ? off + side : 1;
+    for (int z = zlo; z < zhi; ++z)
+        for (int y = off; y < off + side; ++y)
+            for (int x = off; x < off + side; ++x) {
+                const int i = idx(x, y, z);
+                if (!g.cell) {
+                    A[(size_t)i * m + i] = (double)(2 * d) * s;
+                    const int nbx[6] = {x - 1, x + 1, x, x, x, x}, nby[6] = {y, y, y - 1, y + 1, y, y},
+                              nbz[6] = {z, z, z, z, z - 1, z + 1};
+                    for (int q = 0; q < 2 * d; ++q) {
+                        const int X = nbx[q], Y = nby[q], Z = nbz[q];
+                        if (X < 1 || X > g.n - 2 || Y < 1 || Y > g.n - 2) continue;
+                        if (d == 3 && (Z < 1 || Z > g.n - 2)) continue;
+                        A[(size_t)idx(X, Y, Z) * m + i] = (0.0 - 1.0) * s;
+                    }
+                } else {
+                    const int N = g.n;
+                    auto B = [&](int a, int X, int Y, int Z) {
+                        return beta[a][(size_t)Z * g.fplane + (size_t)Y * g.fpitch + X];
+                    };
+                    // faces in the order x-, x+, y-, y+, z-, z+
+                    const double bf[6] = {B(0, x, y, z), B(0, x + 1, y, z), B(1, x, y, z), B(1, x, y + 1, z),
+                                          d == 3 ? B(2, x, y, z) : 0.0, d == 3 ? B(2, x, y, z + 1) : 0.0};
+                    const bool wall[6] = {x == 0, x == N - 1, y == 0, y == N - 1, z == 0, z == N - 1};
+                    const int nbx[6] = {x - 1, x + 1, x, x, x, x}, nby[6] = {y, y, y - 1, y + 1, y, y},
+                              nbz[6] = {z, z, z, z, z - 1, z + 1};
+                    double dg = 0.0;
+                    for (int q = 0; q < 2 * d; ++q) {
+                        const double t = wall[q] ? 2.0 * bf[q] : bf[q];
+                        dg = q == 0 ? t : dg + t;
+                    }
+                    A[(size_t)i * m + i] = (dg * 1.0 - 0.0) * s;
+                    for (int q = 0; q < 2 * d; ++q) {
+                        if (wall[q]) continue;
+                        A[(size_t)idx(nbx[q], nby[q], nbz[q]) * m + i] = (0.0 - bf[q]) * s;
+                    }
+                }
+            }
+    return A;
+}
+
+// Textbook Cholesky A = L L^T (row-oriented); false if A is not SPD.
+bool cholesky(std::vector<double>& A, int m) {
+    std::vector<double> L((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double dsum = A[(size_t)j * m + j];
+        for (int k = 0; k < j; ++k) dsum -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+        if (!(dsum > 0.0)) return false;
+        const double ljj = std::sqrt(dsum);
+        L[(size_t)j * m + j] = ljj;
+        for (int i = j + 1; i < m; ++i) {
+            double v = A[(size_t)i * m + j];
+            for (int k = 0; k < j; ++k) v -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+            L[(size_t)i * m + j] = v / ljj;
+        }
+    }
+    A.swap(L);
+    return true;
+}
+
+}  // namespace
+
+// ============================================================ the context
+namespace mg {
+
+int Ctx::fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+}
+
+int Ctx::dev(hipError_t e, const char* what) {
+    if (e == hipSuccess) return MG_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return MG_EDEVICE;
+}
+
+void* Ctx::at(size_t off) const { return off == SIZE_MAX ? nullptr : static_cast<char*>(base) + off; }
+
+Faces Ctx::faces(int l, int pr) const {
+    Faces f;
+    for (int a = 0; a < 3; ++a) f.b[a] = lv[l].beta[pr][a];
+    return f;
+}
+
+double Ctx::scale(int l) const {
+    const Geom& g = lv[l].g;
+    return g.cell ? (double)g.n * g.n : (double)(g.n - 1) * (g.n - 1);
+}
+
+int Ctx::record(int kclass, int level, hipError_t e, hipEvent_t e0, const char* what) {
+    if (prof) {
+        hipEvent_t e1 = event();
+        (void)hipEventRecord(e1, stream);
+        recs.push_back({kclass, level, e0, e1});
+    }
+    return dev(e, what);
+}
+
+hipEvent_t Ctx::begin() {
+    if (!prof) return nullptr;
+    hipEvent_t e0 = event();
+    (void)hipEventRecord(e0, stream);
+    return e0;
+}
+
+hipEvent_t Ctx::event() {
+    if (ev_used == ev_pool.size()) {
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+}
+
+// ------------------------------------------------------------- level ops
+int Ctx::gs(int l, int pr, int colour, bool zero) {
+    Level& L = lv[l];
+    hipEvent_t e0 = begin();
+    return record(MG_K_SMOOTH, l, launch_gs(L.g, pr, colour, zero, L.u[pr], L.f[pr], faces(l, pr), scale(l), stream),
+                  e0, "gs");
+}
+
+int Ctx::jacobi(int l, int pr, bool zero) {
+    Level& L = lv[l];
+    hipEvent_t e0 = begin();
+    int rc = record(MG_K_SMOOTH, l,
+                    launch_jacobi(L.g, pr, zero, L.u[pr], L.f[pr], L.utmp[pr], faces(l, pr), scale(l), opts.omega,
+                                  stream),
+                    e0, "jacobi");
+    if (rc) return rc;
+    std::swap(L.u[pr], L.utmp[pr]);
+    return MG_OK;
+}
+
+int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
+    Level& L = lv[l];
+    if (sweeps == 0 && from_zero) {
+        hipEvent_t e0 = begin();
+        int rc = record(MG_K_COPY, l, launch_zero(L.u[pr], L.field_bytes[pr], stream), e0, "zero");
+        if (rc) return rc;
+    }
+    for (int k = 0; k < sweeps; ++k) {
+        const bool z = from_zero && k == 0;
+        int rc;
+        if (opts.smoother == MG_RBGS) {
+            rc = gs(l, pr, first_colour, z);
+            if (!rc) rc = gs(l, pr, 1 - first_colour, false);
+        } else {
+            rc = jacobi(l, pr, z);
+        }
+        if (rc) return rc;
+    }
+    return MG_OK;
+}
+
+int Ctx::residual(int l, int pr, bool norm, bool store) {
+    Level& L = lv[l];
+    long long nb = 0;
+    hipEvent_t e0 = begin();
+    int rc = record(MG_K_RESIDUAL, l,
+                    launch_residual(L.g, pr, L.u[pr], L.f[pr], L.r[pr], faces(l, pr), scale(l), norm, store,
+                                    partials, &nb, stream),
+                    e0, "residual");
+    if (rc || !norm) return rc;
+    e0 = begin();
+    return record(MG_K_REDUCE, l, launch_reduce(partials, nb, reduce_scratch, red, stream), e0, "reduce");
+}
+
+int Ctx::restrict_to(int l, int pr) {
+    hipEvent_t e0 = begin();
+    return record(MG_K_RESTRICT, l, launch_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].r[pr], lv[l + 1].f[pr], stream),
+                  e0, "restrict");
+}
+
+int Ctx::prolong(int l, int pr, int mask) {
+    hipEvent_t e0 = begin();
+    return record(MG_K_PROLONG, l,
+                  launch_prolong(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l + 1].u[pr], mask, stream), e0,
+                  "prolong");
+}
+
+int Ctx::coarse(int pr) {
+    const int l = L - 1;
+    hipEvent_t e0 = begin();
+    return record(MG_K_COARSE, l, launch_coarse(lv[l].g, pr, lv[l].f[pr], lv[l].u[pr], chol, m, stream), e0,
+                  "coarse");
+}
+
+// One V(nu1, nu2)-cycle on level l of hierarchy pr.  from_zero: the level's
+// current iterate is zero (coarse levels, and the single-precision finest
+// level inside refinement), so the first sweep reads no neighbour values and
+// no zero fill is needed.
+int Ctx::vcycle(int l, int pr, bool from_zero) {
+    if (l == L - 1) return coarse(pr);
+    int rc = smooth(l, pr, opts.nu1, from_zero, 0);
+    if (!rc) rc = residual(l, pr, false, true);
+    if (!rc) rc = restrict_to(l, pr);
+    if (!rc) rc = vcycle(l + 1, pr, true);
+    if (rc) return rc;
+    // With red-black smoothing that starts with colour c, the corrections of
+    // colour c are overwritten before anything reads them: prolong onto the
+    // other colour only.
+    int mask = 3;
+    if (opts.smoother == MG_RBGS && opts.nu2 > 0) mask = opts.post_order == 0 ? 2 : 1;
+    rc = prolong(l, pr, mask);
+    if (!rc) rc = smooth(l, pr, opts.nu2, false, opts.post_order);
+    return rc;
+}
+
+// One FP64 refinement step around a single-precision V-cycle.  Expects
+// r64 and (sum r^2, max |r|) of the current iterate in place (residual()
+// with norm and store); leaves u64 updated.
+int Ctx::refine_step() {
+    Level& L0 = lv[0];
+    hipEvent_t e0 = begin();
+    int rc = record(MG_K_CAST, 0,
+                    launch_cast(L0.g, static_cast<const double*>(L0.r[0]), static_cast<float*>(L0.f[1]), red,
+                                red + 2, stream),
+                    e0, "cast");
+    if (!rc) rc = vcycle(0, 1, true);
+    if (rc) return rc;
+    e0 = begin();
+    return record(MG_K_UPDATE, 0,
+                  launch_update(L0.g, static_cast<double*>(L0.u[0]), static_cast<const float*>(L0.u[1]), red + 2,
+                                stream),
+                  e0, "update");
+}
+
+int Ctx::read_red(double* sq, double* mx) {
+    double h[2];
+    int rc = dev(hipMemcpyAsync(h, red, 16, hipMemcpyDeviceToHost, stream), "read norm");
+    if (!rc) rc = dev(hipStreamSynchronize(stream), "sync");
+    if (rc) return rc;
+    *sq = h[0];
+    *mx = h[1];
+    return MG_OK;
+}
+
+int Ctx::norm(double* out) {
+    int rc = residual(0, 0, true, opts.precision == MG_MIXED);
+    double sq, mx;
+    if (!rc) rc = read_red(&sq, &mx);
+    if (rc) return rc;
+    *out = std::sqrt(sq);
+    return MG_OK;
+}
+
+int Ctx::step(int k) {
+    for (int i = 0; i < k; ++i) {
+        int rc;
+        if (opts.precision == MG_MIXED) {
+            rc = residual(0, 0, true, true);
+            if (!rc) rc = refine_step();
+        } else {
+            rc = vcycle(0, 0, false);
+        }
+        if (rc) return rc;
+    }
+    return MG_OK;
+}
+
+int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
+    hist.clear();
+    double r0;
+    int rc = norm(&r0);   // in mixed mode this also leaves r64 and max|r| for the first step
+    if (rc) return rc;
+    if (!std::isfinite(r0)) return fail(MG_ENONFINITE, "initial residual is not finite");
+    hist.push_back(1.0);
+    int cycles = 0, grow = 0;
+    double rel = 1.0;
+    int status = MG_OK;
+    while (r0 > 0.0 && rel > tol) {
+        if (cycles == opts.max_cycles) {
+            status = MG_ENOTCONV;
+            err = "max_cycles reached";
+            break;
+        }
+        rc = opts.precision == MG_MIXED ? refine_step() : vcycle(0, 0, false);
+        if (rc) return rc;
+        ++cycles;
+        double nr;
+        rc = norm(&nr);
+        if (rc) return rc;
+        const double prev = rel;
+        rel = nr / r0;
+        hist.push_back(rel);
+        if (!std::isfinite(rel)) {
+            status = fail(MG_ENONFINITE, "residual norm is not finite");
+            break;
+        }
+        grow = rel > prev ? grow + 1 : 0;
+        if (grow >= 3 && rel > 1.0) {
+            status = fail(MG_EDIVERGED, "residual grew in 3 consecutive cycles");
+            break;
+        }
+    }
+    if (r0 == 0.0) rel = 0.0;
+    if (cycles_out) *cycles_out = cycles;
+    if (relres_out) *relres_out = rel;
+    return status;
+}
+
+}  // namespace mg
+
+// =================================================================== C ABI
+using mg::Ctx;
+
+extern "C" {
+
+const char* mg_version(void) { return "mg 0.1.0 (gfx950, colour-split storage)"; }
+
+void mg_default_opts(mg_opts* o) {
+    if (!o) return;
+    o->smoother = MG_RBGS;
+    o->omega = 0.8;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->precision = MG_FP64;
+    o->max_cycles = 100;
+    o->post_order = 0;
+}
+
+int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes) {
+    if (!bytes) return MG_EINVAL;
+    int rc = validate(g, st, o, nullptr);
+    if (rc) return rc;
+    *bytes = mg::plan_workspace(g, st, o, nullptr);
+    return MG_OK;
+}
+
+static thread_local std::string g_setup_error;
+
+int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_opts* o, void* d_workspace,
+             size_t bytes, void* hip_stream, mg_ctx** out) {
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(g, st, o, &why);
+    if (rc) {
+        g_setup_error = why;
+        return rc;
+    }
+    if (bc && bc->kind != MG_DIRICHLET0) {
+        g_setup_error = "only zero Dirichlet boundaries are supported";
+        return MG_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        g_setup_error = "no HIP device";
+        return MG_EDEVICE;
+    }
+    mg::Plan plan;
+    const size_t need = mg::plan_workspace(g, st, o, &plan);
+    if (!d_workspace || bytes < need) {
+        g_setup_error = "workspace too small: need " + std::to_string(need) + " bytes";
+        return MG_ENOMEM;
+    }
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256) {
+        g_setup_error = "workspace must be 256-byte aligned";
+        return MG_EINVAL;
+    }
+    Ctx* c = new (std::nothrow) Ctx();
+    if (!c) return MG_ENOMEM;
+    c->grid = *g;
+    c->opts = *o;
+    c->kind = st ? st->kind : MG_LAPLACE;
+    c->base = d_workspace;
+    c->bytes = bytes;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->L = plan.L;
+    c->m = plan.m;
+    c->partial_pairs = plan.partial_pairs;
+    c->partials = static_cast<double*>(c->at(plan.partials));
+    c->reduce_scratch = static_cast<double*>(c->at(plan.reduce_scratch));
+    c->red = static_cast<double*>(c->at(plan.red));
+    c->chol = static_cast<double*>(c->at(plan.chol));
+    c->staging = static_cast<double*>(c->at(plan.staging));
+    for (int l = 0; l < plan.L; ++l) {
+        const mg::LevelPlan& lp = plan.lv[l];
+        mg::Level lvv;
+        lvv.g = lp.g;
+        for (int pr = 0; pr < 2; ++pr) {
+            lvv.has[pr] = lp.has[pr];
+            lvv.u[pr] = c->at(lp.u[pr]);
+            lvv.f[pr] = c->at(lp.f[pr]);
+            lvv.r[pr] = c->at(lp.r[pr]);
+            lvv.utmp[pr] = c->at(lp.utmp[pr]);
+            lvv.field_bytes[pr] = (size_t)(2 * lp.g.cs) * (pr == 0 ? 8 : 4);
+            for (int a = 0; a < 3; ++a) lvv.beta[pr][a] = c->at(lp.beta[pr][a]);
+        }
+        c->lv.push_back(lvv);
+    }
+    // zero every field (boundary nodes and padding stay zero for good)
+    rc = c->dev(mg::launch_zero(d_workspace, plan.total, c->stream), "zero workspace");
+    // face coefficients
+    if (!rc && g->centering == MG_CELL) {
+        const mg::Geom& g0 = c->lv[0].g;
+        const long long ncell = (long long)g0.n * g0.n * (g0.dim == 3 ? g0.n : 1);
+        std::vector<double> k((size_t)ncell, 1.0);
+        if (c->kind == MG_VARCOEF) {
+            if (st->k_on_device)
+                rc = c->dev(hipMemcpy(k.data(), st->k, (size_t)ncell * 8, hipMemcpyDeviceToHost), "read k");
+            else
+                std::memcpy(k.data(), st->k, (size_t)ncell * 8);
+            for (long long i = 0; !rc && i < ncell; ++i)
+                if (!(k[(size_t)i] > 0.0) || !std::isfinite(k[(size_t)i])) {
+                    rc = c->fail(MG_EINVAL, "k must be positive and finite");
+                }
+        }
+        std::vector<double> bf[3], bc2[3];
+        if (!rc) harmonic_faces(g0, k.data(), bf);
+        std::vector<float> tmp32;
+        for (int l = 0; !rc && l < c->L; ++l) {
+            const mg::Geom& gl = c->lv[l].g;
+            if (l > 0) {
+                coarsen_faces(c->lv[l - 1].g, bf, gl, bc2);
+                for (int a = 0; a < 3; ++a) bf[a].swap(bc2[a]);
+            }
+            for (int a = 0; !rc && a < gl.dim; ++a) {
+                if (c->lv[l].has[0])
+                    rc = c->dev(hipMemcpyAsync(c->lv[l].beta[0][a], bf[a].data(), (size_t)gl.fsize * 8,
+                                               hipMemcpyHostToDevice, c->stream),
+                                "upload faces");
+                if (!rc && c->lv[l].has[1]) {
+                    tmp32.assign(bf[a].begin(), bf[a].end());
+                    rc = c->dev(hipMemcpyAsync(c->lv[l].beta[1][a], tmp32.data(), (size_t)gl.fsize * 4,
+                                               hipMemcpyHostToDevice, c->stream),
+                                "upload faces");
+                    if (!rc) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+                }
+            }
+            if (!rc) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+        }
+        if (!rc) c->coarse_beta_host.assign(bf, bf + 3);
+    }
+    // coarsest matrix, Cholesky factor
+    if (!rc) {
+        std::vector<double> A = coarse_matrix(c->lv.back().g, c->coarse_beta_host.empty() ? nullptr
+                                                                                         : c->coarse_beta_host.data());
+        if (!cholesky(A, c->m)) rc = c->fail(MG_EINVAL, "coarsest matrix is not SPD");
+        if (!rc)
+            rc = c->dev(hipMemcpyAsync(c->chol, A.data(), A.size() * 8, hipMemcpyHostToDevice, c->stream),
+                        "upload factor");
+        if (!rc) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+    }
+    c->coarse_beta_host.clear();
+    if (rc) {
+        g_setup_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = reinterpret_cast<mg_ctx*>(c);
+    return MG_OK;
+}
+
+void mg_destroy(mg_ctx* h) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c) return;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+static int copy_in(Ctx* c, const mg::Geom& g, int pr, void* field, const double* a, int on_device) {
+    const long long tot = (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
+    const double* src = a;
+    if (!on_device) {
+        int rc = c->dev(hipMemcpyAsync(c->staging, a, (size_t)tot * 8, hipMemcpyHostToDevice, c->stream), "upload");
+        if (rc) return rc;
+        src = c->staging;
+    }
+    hipEvent_t e0 = c->begin();
+    int rc = c->record(MG_K_COPY, -1, mg::launch_pack(g, pr, src, field, c->stream), e0, "pack");
+    if (!rc && !on_device) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+    return rc;
+}
+
+static int copy_out(Ctx* c, const mg::Geom& g, int pr, const void* field, double* a, int on_device) {
+    const long long tot = (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
+    double* dst = on_device ? a : c->staging;
+    hipEvent_t e0 = c->begin();
+    int rc = c->record(MG_K_COPY, -1, mg::launch_unpack(g, pr, field, dst, c->stream), e0, "unpack");
+    if (!rc && !on_device)
+        rc = c->dev(hipMemcpyAsync(a, c->staging, (size_t)tot * 8, hipMemcpyDeviceToHost, c->stream), "download");
+    if (!rc && !on_device) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+    return rc;
+}
+
+int mg_set_rhs(mg_ctx* h, const double* f, int on_device) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !f) return MG_EINVAL;
+    return copy_in(c, c->lv[0].g, 0, c->lv[0].f[0], f, on_device);
+}
+
+int mg_set_initial(mg_ctx* h, const double* u0, int on_device) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c) return MG_EINVAL;
+    if (!u0) {
+        hipEvent_t e0 = c->begin();
+        return c->record(MG_K_COPY, 0, mg::launch_zero(c->lv[0].u[0], c->lv[0].field_bytes[0], c->stream), e0,
+                         "zero");
+    }
+    return copy_in(c, c->lv[0].g, 0, c->lv[0].u[0], u0, on_device);
+}
+
+int mg_get_solution(mg_ctx* h, double* u, int on_device) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !u) return MG_EINVAL;
+    return copy_out(c, c->lv[0].g, 0, c->lv[0].u[0], u, on_device);
+}
+
+int mg_vcycle(mg_ctx* h, int ncycles) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || ncycles < 0) return MG_EINVAL;
+    return c->step(ncycles);
+}
+
+int mg_solve(mg_ctx* h, double tol, int* cycles_out, double* relres_out) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !(tol >= 0.0)) return MG_EINVAL;
+    return c->solve(tol, cycles_out, relres_out);
+}
+
+int mg_residual_norm(mg_ctx* h, double* out) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !out) return MG_EINVAL;
+    return c->norm(out);
+}
+
+int mg_history(const mg_ctx* h, double* buf, int cap, int* n) {
+    const Ctx* c = reinterpret_cast<const Ctx*>(h);
+    if (!c || !n || (cap > 0 && !buf)) return MG_EINVAL;
+    *n = (int)c->hist.size();
+    for (int i = 0; i < cap && i < *n; ++i) buf[i] = c->hist[(size_t)i];
+    return MG_OK;
+}
+
+int mg_levels(const mg_ctx* h, int* nlevels) {
+    const Ctx* c = reinterpret_cast<const Ctx*>(h);
+    if (!c || !nlevels) return MG_EINVAL;
+    *nlevels = c->L;
+    return MG_OK;
+}
+
+int mg_level_size(const mg_ctx* h, int level, int* n) {
+    const Ctx* c = reinterpret_cast<const Ctx*>(h);
+    if (!c || !n || level < 0 || level >= c->L) return MG_EINVAL;
+    *n = c->lv[level].g.n;
+    return MG_OK;
+}
+
+static void* field_ptr(Ctx* c, int level, int field, int pr) {
+    if (level < 0 || level >= c->L || pr < 0 || pr > 1 || !c->lv[level].has[pr]) return nullptr;
+    mg::Level& L = c->lv[level];
+    switch (field) {
+        case MG_FIELD_U: return L.u[pr];
+        case MG_FIELD_F: return L.f[pr];
+        case MG_FIELD_R: return L.r[pr];
+        default: return nullptr;
+    }
+}
+
+int mg_level_set(mg_ctx* h, int level, int field, int prec, const double* a, int on_device) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !a) return MG_EINVAL;
+    void* p = field_ptr(c, level, field, prec);
+    if (!p) return c->fail(MG_EINVAL, "no such level field");
+    return copy_in(c, c->lv[level].g, prec, p, a, on_device);
+}
+
+int mg_level_get(mg_ctx* h, int level, int field, int prec, double* a, int on_device) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !a) return MG_EINVAL;
+    void* p = field_ptr(c, level, field, prec);
+    if (!p) return c->fail(MG_EINVAL, "no such level field");
+    return copy_out(c, c->lv[level].g, prec, p, a, on_device);
+}
+
+int mg_apply(mg_ctx* h, int op, int level, int prec) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c) return MG_EINVAL;
+    if (level < 0 || level >= c->L || prec < 0 || prec > 1 || !c->lv[level].has[prec])
+        return c->fail(MG_EINVAL, "no such level in this precision");
+    const bool has_next = level + 1 < c->L && c->lv[level + 1].has[prec];
+    switch (op) {
+        case MG_OP_GS_RED: return c->gs(level, prec, 0, false);
+        case MG_OP_GS_BLACK: return c->gs(level, prec, 1, false);
+        case MG_OP_JACOBI:
+            if (!c->lv[level].utmp[prec]) return c->fail(MG_EINVAL, "Jacobi needs a Jacobi context");
+            return c->jacobi(level, prec, false);
+        case MG_OP_RESIDUAL: return c->residual(level, prec, false, true);
+        case MG_OP_RESTRICT:
+            if (!has_next) return c->fail(MG_EINVAL, "no coarser level");
+            return c->restrict_to(level, prec);
+        case MG_OP_PROLONG:
+            if (!has_next) return c->fail(MG_EINVAL, "no coarser level");
+            return c->prolong(level, prec, 3);
+        case MG_OP_COARSE:
+            if (level != c->L - 1) return c->fail(MG_EINVAL, "not the coarsest level");
+            return c->coarse(prec);
+        case MG_OP_VCYCLE:
+            if (level < c->L - 1 && !has_next) return c->fail(MG_EINVAL, "no coarser level");
+            return c->vcycle(level, prec, false);
+        default: return c->fail(MG_EINVAL, "unknown op");
+    }
+}
+
+int mg_profile(mg_ctx* h, int enable) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c) return MG_EINVAL;
+    int rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+    c->prof = enable != 0;
+    c->recs.clear();
+    c->ev_used = 0;
+    std::memset(c->agg_ms, 0, sizeof(c->agg_ms));
+    std::memset(c->agg_n, 0, sizeof(c->agg_n));
+    return rc;
+}
+
+int mg_profile_read(mg_ctx* h, int kclass, int level, int* count, double* ms) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || kclass < 0 || kclass >= MG_K_COUNT || level < -1 || level >= mg::kMaxLevels) return MG_EINVAL;
+    int rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+    if (rc) return rc;
+    for (const mg::Rec& r : c->recs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) continue;
+        const int lvl = r.level < 0 ? mg::kMaxLevels - 1 : r.level;
+        c->agg_ms[r.kclass][lvl] += t;
+        c->agg_n[r.kclass][lvl] += 1;
+    }
+    c->recs.clear();
+    c->ev_used = 0;
+    double s = 0.0;
+    int n = 0;
+    for (int l = 0; l < mg::kMaxLevels; ++l)
+        if (level < 0 || l == level) {
+            s += c->agg_ms[kclass][l];
+            n += c->agg_n[kclass][l];
+        }
+    if (count) *count = n;
+    if (ms) *ms = s;
+    return MG_OK;
+}
+
+const char* mg_strerror(int code) {
+    switch (code) {
+        case MG_OK: return "ok";
+        case MG_EINVAL: return "invalid argument";
+        case MG_ENOMEM: return "out of memory (workspace or budget)";
+        case MG_EDEVICE: return "HIP device error";
+        case MG_ENOTCONV: return "not converged within max_cycles";
+        case MG_ENONFINITE: return "non-finite residual";
+        case MG_EDIVERGED: return "diverged";
+        case MG_EBUSY: return "busy";
+        default: return "unknown error";
+    }
+}
+
+const char* mg_last_error(const mg_ctx* h) {
+    const Ctx* c = reinterpret_cast<const Ctx*>(h);
+    if (!c) return g_setup_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""Python binding of libmg.so (ctypes; argument marshalling only).
+
+Every numerical step runs inside the HIP library.  The module-level
+functions carry the C names of include/mg.h; ``Solver`` bundles a context
+with the PyTorch device workspace it lives in.  PyTorch provides device
+memory and the stream only.
+
+Importing this module loads the built library and raises ImportError when it
+is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmg.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_1904_08684_amd.build` "
+                      "or __graft_entry__.build()")
+lib = C.CDLL(_LIB_PATH)
+
+# ------------------------------------------------------------------ constants
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE = 0, -1, -2, -3
+MG_ENOTCONV, MG_ENONFINITE, MG_EDIVERGED, MG_EBUSY = -4, -5, -6, -7
+MG_NODE, MG_CELL = 0, 1
+MG_LAPLACE, MG_VARCOEF = 0, 1
+MG_DIRICHLET0 = 0
+MG_JACOBI, MG_RBGS = 0, 1
+MG_FP64, MG_MIXED = 0, 1
+MG_PREC_FP64, MG_PREC_FP32 = 0, 1
+MG_FIELD_U, MG_FIELD_F, MG_FIELD_R = 0, 1, 2
+(MG_OP_GS_RED, MG_OP_GS_BLACK, MG_OP_JACOBI, MG_OP_RESIDUAL, MG_OP_RESTRICT,
+ MG_OP_PROLONG, MG_OP_COARSE, MG_OP_VCYCLE) = range(8)
+(MG_K_SMOOTH, MG_K_RESIDUAL, MG_K_RESTRICT, MG_K_PROLONG, MG_K_COARSE, MG_K_REDUCE,
+ MG_K_CAST, MG_K_UPDATE, MG_K_COPY, MG_K_COUNT) = range(10)
+
+
+class mg_grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("centering", C.c_int), ("coarsest_n", C.c_int)]
+
+
+class mg_stencil(C.Structure):
+    _fields_ = [("kind", C.c_int), ("k", C.POINTER(C.c_double)), ("k_on_device", C.c_int)]
+
+
+class mg_bc(C.Structure):
+    _fields_ = [("kind", C.c_int)]
+
+
+class mg_opts(C.Structure):
+    _fields_ = [("smoother", C.c_int), ("omega", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("precision", C.c_int), ("max_cycles", C.c_int), ("post_order", C.c_int)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_sigs = {
+    "mg_version": (C.c_char_p, []),
+    "mg_default_opts": (None, [C.POINTER(mg_opts)]),
+    "mg_workspace_bytes": (C.c_int, [C.POINTER(mg_grid), C.POINTER(mg_stencil), C.POINTER(mg_opts),
+                                     C.POINTER(C.c_size_t)]),
+    "mg_setup": (C.c_int, [C.POINTER(mg_grid), C.POINTER(mg_stencil), C.POINTER(mg_bc), C.POINTER(mg_opts),
+                           _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "mg_destroy": (None, [_P]),
+    "mg_set_rhs": (C.c_int, [_P, _P, C.c_int]),
+    "mg_set_initial": (C.c_int, [_P, _P, C.c_int]),
+    "mg_get_solution": (C.c_int, [_P, _P, C.c_int]),
+    "mg_vcycle": (C.c_int, [_P, C.c_int]),
+    "mg_solve": (C.c_int, [_P, C.c_double, C.POINTER(C.c_int), _D]),
+    "mg_residual_norm": (C.c_int, [_P, _D]),
+    "mg_history": (C.c_int, [_P, _D, C.c_int, C.POINTER(C.c_int)]),
+    "mg_levels": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    "mg_level_size": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
+    "mg_level_set": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, C.c_int]),
+    "mg_level_get": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, C.c_int]),
+    "mg_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
+    "mg_profile": (C.c_int, [_P, C.c_int]),
+    "mg_profile_read": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int), _D]),
+    "mg_strerror": (C.c_char_p, [C.c_int]),
+    "mg_last_error": (C.c_char_p, [_P]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+class MGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{mg_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(code: int, ctx=None):
+    if code != MG_OK:
+        raise MGError(code, mg_last_error(ctx).decode())
+    return code
+
+
+def make_grid(dim: int, n: int, centering: int = MG_NODE, coarsest: int | None = None) -> mg_grid:
+    if coarsest is None:
+        coarsest = 5 if centering == MG_NODE else 4
+    g = mg_grid()
+    g.dim = dim
+    g.n[0] = g.n[1] = n
+    g.n[2] = n if dim == 3 else 1
+    g.centering = centering
+    g.coarsest_n = coarsest
+    return g
+
+
+def make_opts(smoother=MG_RBGS, omega=0.8, nu1=2, nu2=2, precision=MG_FP64, max_cycles=100,
+              post_order=0) -> mg_opts:
+    o = mg_opts()
+    o.smoother, o.omega, o.nu1, o.nu2 = smoother, omega, nu1, nu2
+    o.precision, o.max_cycles, o.post_order = precision, max_cycles, post_order
+    return o
+
+
+def workspace_bytes(grid: mg_grid, opts: mg_opts, stencil: mg_stencil | None = None) -> int:
+    b = C.c_size_t()
+    _check(mg_workspace_bytes(C.byref(grid), C.byref(stencil) if stencil else None, C.byref(opts),
+                              C.byref(b)))
+    return b.value
+
+
+def _ptr(a):
+    """(pointer, on_device, keepalive) for a NumPy array or a torch tensor of float64."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            if a.dtype != torch.float64 or not a.is_contiguous():
+                raise ValueError("tensors crossing the ABI must be contiguous float64")
+            return C.c_void_p(a.data_ptr()), int(a.is_cuda), a
+    except ImportError:
+        pass
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    return C.c_void_p(arr.ctypes.data), 0, arr
+
+
+class Solver:
+    """One multigrid context and the device workspace it lives in."""
+
+    def __init__(self, dim: int, n: int, centering: int = MG_NODE, coarsest: int | None = None,
+                 smoother: int = MG_RBGS, omega: float = 0.8, nu1: int = 2, nu2: int = 2,
+                 precision: int = MG_FP64, max_cycles: int = 100, post_order: int = 0,
+                 k=None, stream=None, device: str = "cuda"):
+        import torch
+        self.dim, self.n, self.centering = dim, n, centering
+        self.grid = make_grid(dim, n, centering, coarsest)
+        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order)
+        self.stencil = mg_stencil()
+        self._k = None
+        if k is not None:
+            kp, kd, self._k = _ptr(k)
+            self.stencil.kind = MG_VARCOEF
+            self.stencil.k = C.cast(kp, _D)
+            self.stencil.k_on_device = kd
+        else:
+            self.stencil.kind = MG_LAPLACE
+        self.bytes = workspace_bytes(self.grid, self.opts, self.stencil)
+        self.workspace = torch.empty(max(self.bytes, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        bc = mg_bc(MG_DIRICHLET0)
+        h = C.c_void_p()
+        _check(mg_setup(C.byref(self.grid), C.byref(self.stencil), C.byref(bc), C.byref(self.opts),
+                        C.c_void_p(self.workspace.data_ptr()), self.bytes,
+                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.ctx = h
+        self._k = None
+
+    # -------------------------------------------------------------- sizes
+    @property
+    def shape(self):
+        return (self.n,) * self.dim
+
+    def levels(self) -> int:
+        v = C.c_int()
+        _check(mg_levels(self.ctx, C.byref(v)), self.ctx)
+        return v.value
+
+    def level_size(self, level: int) -> int:
+        v = C.c_int()
+        _check(mg_level_size(self.ctx, level, C.byref(v)), self.ctx)
+        return v.value
+
+    # ------------------------------------------------------------ data
+    def set_rhs(self, f):
+        p, dev, keep = _ptr(f)
+        _check(mg_set_rhs(self.ctx, p, dev), self.ctx)
+        del keep
+
+    def set_initial(self, u0=None):
+        if u0 is None:
+            _check(mg_set_initial(self.ctx, None, 0), self.ctx)
+            return
+        p, dev, keep = _ptr(u0)
+        _check(mg_set_initial(self.ctx, p, dev), self.ctx)
+        del keep
+
+    def solution(self, out=None):
+        if out is None:
+            out = np.empty(self.shape, dtype=np.float64)
+        p, dev, keep = _ptr(out)
+        _check(mg_get_solution(self.ctx, p, dev), self.ctx)
+        return out
+
+    def level_set(self, level: int, field: int, a, prec: int = MG_PREC_FP64):
+        p, dev, keep = _ptr(a)
+        _check(mg_level_set(self.ctx, level, field, prec, p, dev), self.ctx)
+        del keep
+
+    def level_get(self, level: int, field: int, prec: int = MG_PREC_FP64):
+        n = self.level_size(level)
+        out = np.empty((n,) * self.dim, dtype=np.float64)
+        _check(mg_level_get(self.ctx, level, field, prec, C.c_void_p(out.ctypes.data), 0), self.ctx)
+        return out
+
+    # --------------------------------------------------------- compute
+    def apply(self, op: int, level: int = 0, prec: int = MG_PREC_FP64):
+        _check(mg_apply(self.ctx, op, level, prec), self.ctx)
+
+    def vcycle(self, k: int = 1):
+        _check(mg_vcycle(self.ctx, k), self.ctx)
+
+    def solve(self, tol: float):
+        """Returns (status, cycles, relres); status is MG_OK or a convergence code."""
+        cyc = C.c_int()
+        rel = C.c_double()
+        code = mg_solve(self.ctx, tol, C.byref(cyc), C.byref(rel))
+        if code not in (MG_OK, MG_ENOTCONV, MG_ENONFINITE, MG_EDIVERGED):
+            _check(code, self.ctx)
+        return code, cyc.value, rel.value
+
+    def residual_norm(self) -> float:
+        v = C.c_double()
+        _check(mg_residual_norm(self.ctx, C.byref(v)), self.ctx)
+        return v.value
+
+    def history(self) -> list:
+        n = C.c_int()
+        _check(mg_history(self.ctx, None, 0, C.byref(n)), self.ctx)
+        buf = (C.c_double * max(n.value, 1))()
+        _check(mg_history(self.ctx, buf, n.value, C.byref(n)), self.ctx)
+        return list(buf[: n.value])
+
+    # -------------------------------------------------------- profiling
+    def profile(self, enable: bool = True):
+        _check(mg_profile(self.ctx, int(enable)), self.ctx)
+
+    def profile_read(self, kclass: int, level: int = -1):
+        n = C.c_int()
+        ms = C.c_double()
+        _check(mg_profile_read(self.ctx, kclass, level, C.byref(n), C.byref(ms)), self.ctx)
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

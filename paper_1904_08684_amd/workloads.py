@@ -129,3 +129,9 @@ def request_stream(count: int, rate_per_s: float, classes=SERVE_CLASSES,
         d, n = classes[int(cls[i])]
         out.append(Request(i, d, n, float(t[i])))
     return out
+
+
+def cell_uniform(N: int, dim: int, seed: int, lo=-1.0, hi=1.0) -> np.ndarray:
+    """U[lo, hi] samples on N^dim cells."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(N,) * dim)

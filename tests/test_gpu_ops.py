@@ -1,0 +1,157 @@
+"""Kernel-level parity: every level operation of the HIP library against the
+oracle routine it implements, one application on seeded random fields, at
+sizes spanning one to many tiles with ragged tails, node and cell grids,
+FP64 and the single-precision hierarchy.  The library is compiled without
+FMA contraction and evaluates the oracle's formulas in the same order, so
+the expected agreement is to the last bit; the test bar is 1e-14 relative
+(FP64) and 1e-6 relative (FP32)."""
+import numpy as np
+import pytest
+
+from oracle import cell, cycle, node
+from paper_1904_08684_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NODE_CASES = [(2, 9), (2, 17), (2, 129), (2, 257), (3, 9), (3, 17), (3, 33), (3, 65)]
+CELL_CASES = [(2, 8), (2, 16), (2, 128), (3, 8), (3, 16), (3, 32)]
+
+
+def tol(prec):
+    return 1e-14 if prec == 0 else 1e-6
+
+
+def close(got, ref, prec, what):
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    err = np.max(np.abs(got - ref)) / scale
+    exact = np.array_equal(got, ref)
+    print(f"{what}: max rel diff {err:.3e} bit-exact {exact}", flush=True)
+    assert err <= tol(prec), (what, err)
+
+
+def make(mg, dim, n, cent, prec, smoother=None):
+    k = W.varcoef_k(n, dim) if cent == mg.MG_CELL else None
+    s = mg.Solver(dim, n, centering=cent, smoother=mg.MG_JACOBI if smoother is None else smoother,
+                  omega=0.8, nu1=1, nu2=1, precision=mg.MG_MIXED if prec else mg.MG_FP64, k=k)
+    p = cycle.Params(centering="cell" if cent else "node", dim=dim, n=n,
+                     coarsest=4 if cent else 5, smoother="jacobi", omega=0.8, k=k)
+    return s, cycle.build_hierarchy(p)
+
+
+def rand(n, dim, cent, seed, dtype):
+    a = W.cell_uniform(n, dim, seed) if cent else W.interior_uniform(n, dim, seed)
+    return a.astype(dtype)
+
+
+def cases():
+    out = []
+    for d, n in NODE_CASES:
+        out.append((d, n, 0))
+    for d, n in CELL_CASES:
+        out.append((d, n, 1))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("dim,n,cent", cases())
+def test_smoothers_and_residual(mg, dim, n, cent, prec):
+    s, h = make(mg, dim, n, cent, prec)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, dim, cent, 100 + n, dt)
+    f = rand(n, dim, cent, 200 + n, dt) * dt(n * n)
+    beta = h.beta_as(0, dt) if cent else None
+    tag = f"{dim}d n={n} {'cell' if cent else 'node'} prec={prec}"
+
+    for colour, op in ((0, mg.MG_OP_GS_RED), (1, mg.MG_OP_GS_BLACK)):
+        s.level_set(0, mg.MG_FIELD_U, u, prec)
+        s.level_set(0, mg.MG_FIELD_F, f, prec)
+        s.apply(op, 0, prec)
+        got = s.level_get(0, mg.MG_FIELD_U, prec)
+        ref = u.copy()
+        if cent:
+            cell.gs_colour(ref, f, beta, colour)
+        else:
+            node.gs_colour(ref, f, colour)
+        close(got, ref.astype(np.float64), prec, f"gs colour {colour} {tag}")
+
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.apply(mg.MG_OP_JACOBI, 0, prec)
+    got = s.level_get(0, mg.MG_FIELD_U, prec)
+    ref = cell.jacobi(u, f, beta, 0.8) if cent else node.jacobi(u, f, 0.8)
+    close(got, ref.astype(np.float64), prec, f"jacobi {tag}")
+
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.apply(mg.MG_OP_RESIDUAL, 0, prec)
+    got = s.level_get(0, mg.MG_FIELD_R, prec)
+    ref = cell.residual(u, f, beta) if cent else node.residual(u, f)
+    close(got, ref.astype(np.float64), prec, f"residual {tag}")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("dim,n,cent", [c for c in cases() if c[1] > (4 if c[2] else 5)])
+def test_transfers(mg, dim, n, cent, prec):
+    s, h = make(mg, dim, n, cent, prec)
+    dt = np.float64 if prec == 0 else np.float32
+    nc = s.level_size(1)
+    tag = f"{dim}d n={n} {'cell' if cent else 'node'} prec={prec}"
+    r = rand(n, dim, cent, 300 + n, dt)
+    s.level_set(0, mg.MG_FIELD_R, r, prec)
+    s.apply(mg.MG_OP_RESTRICT, 0, prec)
+    got = s.level_get(1, mg.MG_FIELD_F, prec)
+    ref = cell.restrict_mean(r) if cent else node.restrict_fw(r)
+    close(got, ref.astype(np.float64), prec, f"restrict {tag}")
+
+    u = rand(n, dim, cent, 400 + n, dt)
+    e = rand(nc, dim, cent, 500 + n, dt)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(1, mg.MG_FIELD_U, e, prec)
+    s.apply(mg.MG_OP_PROLONG, 0, prec)
+    got = s.level_get(0, mg.MG_FIELD_U, prec)
+    ref = cell.correct(u, e) if cent else node.correct(u, e)
+    close(got, ref.astype(np.float64), prec, f"prolong {tag}")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("dim,cent", [(2, 0), (3, 0), (2, 1), (3, 1)])
+def test_coarsest_solve(mg, dim, cent, prec):
+    n = 17 if not cent else 16
+    s, h = make(mg, dim, n, cent, prec)
+    dt = np.float64 if prec == 0 else np.float32
+    L = s.levels() - 1
+    nc = s.level_size(L)
+    fc = rand(nc, dim, cent, 600, dt)
+    s.level_set(L, mg.MG_FIELD_F, fc, prec)
+    s.apply(mg.MG_OP_COARSE, L, prec)
+    got = s.level_get(L, mg.MG_FIELD_U, prec)
+    ref = cycle.coarse_solve(h, fc)
+    # the oracle factors with LAPACK, the library with its own Cholesky: agreement to rounding
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref)) / scale
+    print(f"coarse {dim}d cent={cent} prec={prec}: max rel diff {err:.3e}", flush=True)
+    assert err <= (1e-13 if prec == 0 else 1e-6)
+    s.close()
+
+
+def test_mixed_hierarchy_rejects_missing_fp64_levels(mg):
+    s = mg.Solver(3, 17, smoother=mg.MG_RBGS, precision=mg.MG_MIXED)
+    with pytest.raises(mg.MGError):
+        s.apply(mg.MG_OP_RESTRICT, 0, mg.MG_PREC_FP64)
+    s.close()
+
+
+def test_repeat_is_bitwise_deterministic(mg):
+    """Same inputs, same launches: bitwise identical outputs (catches races in
+    the in-place colour sweeps)."""
+    n = 65
+    f = W.interior_uniform(n, 3, 1)
+    outs = []
+    for _ in range(2):
+        s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
+        s.set_rhs(f)
+        s.set_initial(None)
+        s.vcycle(3)
+        outs.append(s.solution())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
