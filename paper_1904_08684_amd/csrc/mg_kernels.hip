@@ -34,9 +34,25 @@ struct Pt {
     int xs, y, z, c;
 };
 
-__device__ __forceinline__ bool map_point(const Space& sp, Pt& p) {
-    int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    int t = (int)threadIdx.x;
+// Logical block id, thread id and thread count of the block running an
+// operation: a plain launch (block ids XCD-renumbered) or one tile of a
+// batched launch.
+struct Ex {
+    int b, t, nt;
+};
+
+__device__ __forceinline__ Ex solo_ex() {
+    Ex e;
+    e.b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    e.t = (int)(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z));
+    e.nt = (int)(blockDim.x * blockDim.y * blockDim.z);
+    return e;
+}
+
+__device__ __forceinline__ bool map_point(const Ex& ex, const Space& sp, Pt& p) {
+    if (ex.t >= (1 << (sp.lx + sp.ly + sp.lz))) return false;
+    int b = ex.b;
+    int t = ex.t;
     const int lx = t & ((1 << sp.lx) - 1);
     t >>= sp.lx;
     const int ly = t & ((1 << sp.ly) - 1);
@@ -59,15 +75,17 @@ __device__ __forceinline__ long long row_off(const Geom& g, int y, int z) {
     return (long long)z * g.plane + (long long)y * g.pitch;
 }
 
-// Fixed-order block reduction of (sum, max); blockDim.x is a power of two.
+// Fixed-order block reduction of (sum, max) over all threads of the block
+// (up to 1024; the thread count is a power of two).
 __device__ void block_sum_max(double sq, double mx, double* out2) {
-    __shared__ double s_sq[256];
-    __shared__ double s_mx[256];
-    const int t = (int)threadIdx.x;
+    __shared__ double s_sq[1024];
+    __shared__ double s_mx[1024];
+    const int nt = (int)(blockDim.x * blockDim.y * blockDim.z);
+    const int t = (int)(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z));
     s_sq[t] = sq;
     s_mx[t] = mx;
     __syncthreads();
-    for (int w = (int)blockDim.x >> 1; w > 0; w >>= 1) {
+    for (int w = nt >> 1; w > 0; w >>= 1) {
         if (t < w) {
             s_sq[t] = s_sq[t] + s_sq[t + w];
             s_mx[t] = fmax(s_mx[t], s_mx[t + w]);
@@ -97,11 +115,11 @@ __device__ __forceinline__ T node_nb(const T* __restrict__ o, long long ro, int 
 }
 
 template <typename T, int D, bool ZERO>
-__global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict__ me,
+__device__ __forceinline__ void d_node_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
                                                  const T* __restrict__ other, const T* __restrict__ f,
                                                  T s) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > g.n - 2) return;
@@ -111,11 +129,18 @@ __global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict
 }
 
 template <typename T, int D, bool ZERO>
-__global__ __launch_bounds__(256) void k_node_jacobi(Geom g, Space sp, const T* __restrict__ u,
+__global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 T s) {
+    d_node_gs<T, D, ZERO>(solo_ex(), g, sp, me, other, f, s);
+}
+
+template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void d_node_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
                                                      T s, T omega) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > g.n - 2) return;
@@ -127,13 +152,20 @@ __global__ __launch_bounds__(256) void k_node_jacobi(Geom g, Space sp, const T* 
     out[me] = uc + (omega * r) / (T(2 * D) * s);
 }
 
+template <typename T, int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_node_jacobi(Geom g, Space sp, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out,
+                                                     T s, T omega) {
+    d_node_jacobi<T, D, ZERO>(solo_ex(), g, sp, u, f, out, s, omega);
+}
+
 template <typename T, int D, bool NORM, bool STORE>
-__global__ __launch_bounds__(256) void k_node_residual(Geom g, Space sp, const T* __restrict__ u,
+__device__ __forceinline__ void d_node_residual(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
                                                        const T* __restrict__ f, T* __restrict__ r,
                                                        T s, double* __restrict__ part) {
     double sq = 0.0, mx = 0.0;
     Pt p;
-    if (map_point(sp, p)) {
+    if (map_point(ex, sp, p)) {
         const int par = (p.y + p.z + p.c) & 1;
         const int x = 2 * p.xs + par;
         if (x >= 1 && x <= g.n - 2) {
@@ -147,17 +179,212 @@ __global__ __launch_bounds__(256) void k_node_residual(Geom g, Space sp, const T
             mx = fabs(dv);
         }
     }
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
+template <typename T, int D, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_node_residual(Geom g, Space sp, const T* __restrict__ u,
+                                                       const T* __restrict__ f, T* __restrict__ r,
+                                                       T s, double* __restrict__ part) {
+    d_node_residual<T, D, NORM, STORE>(solo_ex(), g, sp, u, f, r, s, part);
+}
+
+// ---------------------------------------------- 3-D node grids, column marching
+__device__ __forceinline__ int zm_block(const ZSpace& zs, int& tx, int& ty, int& tz) {
+    int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    tx = b % zs.ntx;
+    b /= zs.ntx;
+    ty = b % zs.nty;
+    tz = b / zs.nty;
+    return 0;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Half-sweep of one colour; the thread's column of the other colour at
+// z-1, z, z+1 stays in registers while it walks its planes, U planes at a
+// time so that U planes of loads are in flight per thread.  f and the
+// updated colour are pure streams (NT: non-temporal).
+template <typename T, int U, bool NT>
+__global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __restrict__ me,
+                                                     const T* __restrict__ other,
+                                                     const T* __restrict__ f, T s, int colour) {
+    int tx, ty, tz;
+    zm_block(zs, tx, ty, tz);
+    const int xs = tx * 64 + (int)threadIdx.x;
+    const int y = 1 + ty * zs.rows + (int)threadIdx.y;
+    if (xs >= zs.xr || y > g.n - 2) return;
+    const int z0 = 1 + tz * zs.zc;
+    const int z1 = min(z0 + zs.zc, g.n - 1);
+    const long long pl = g.plane;
+    long long ro = row_off(g, y, z0) + xs;
+    const long long xl = xs > 0 ? -1 : 0;     // offset of x >> 1 - 1, clamped at the row start
+    T zv[U + 2];
+    zv[U] = other[ro - pl];
+    zv[U + 1] = other[ro];
+    int z = z0;
+    for (; z + U <= z1; z += U, ro += U * pl) {
+        zv[0] = zv[U];
+        zv[1] = zv[U + 1];
+        T xo[U], ym[U], yp[U], fv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const long long rk = ro + k * pl;
+            const int par = (y + z + k + colour) & 1;
+            zv[k + 2] = other[rk + pl];
+            xo[k] = other[rk + (par ? 1 : xl)];
+            ym[k] = other[rk - g.pitch];
+            yp[k] = other[rk + g.pitch];
+            fv[k] = ld_stream<NT>(f + rk);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int par = (y + z + k + colour) & 1;
+            if (par | xs) {   // x = 2 xs + par >= 1
+                T nb = par ? zv[k + 1] : xo[k];
+                nb = nb + (par ? xo[k] : zv[k + 1]);
+                nb = nb + ym[k];
+                nb = nb + yp[k];
+                nb = nb + zv[k];
+                nb = nb + zv[k + 2];
+                st_stream<NT>(me + ro + k * pl, (fv[k] / s + nb) / T(6));
+            }
+        }
+    }
+    T om = zv[U], oc = zv[U + 1];
+    for (; z < z1; ++z, ro += pl) {
+        const T op = other[ro + pl];
+        const int par = (y + z + colour) & 1;
+        const T xo = other[ro + (par ? 1 : xl)];
+        const T ym = other[ro - g.pitch];
+        const T yp = other[ro + g.pitch];
+        if (par | xs) {
+            T nb = par ? oc : xo;
+            nb = nb + (par ? xo : oc);
+            nb = nb + ym;
+            nb = nb + yp;
+            nb = nb + om;
+            nb = nb + op;
+            st_stream<NT>(me + ro, (ld_stream<NT>(f + ro) / s + nb) / T(6));
+        }
+        om = oc;
+        oc = op;
+    }
+}
+
+// r = f - A u at both colours of the thread's column; both colours' z-1, z,
+// z+1 values stay in registers, U planes per step.
+template <typename T, int U, bool NORM, bool STORE>
+__global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T* __restrict__ u,
+                                                      const T* __restrict__ f, T* __restrict__ r, T s,
+                                                      double* __restrict__ part) {
+    double sq = 0.0, mx = 0.0;
+    int tx, ty, tz;
+    zm_block(zs, tx, ty, tz);
+    const int xs = tx * 64 + (int)threadIdx.x;
+    const int y = 1 + ty * zs.rows + (int)threadIdx.y;
+    if (xs < zs.xr && y <= g.n - 2) {
+        const T* __restrict__ R = u;           // red plane
+        const T* __restrict__ B = u + g.cs;    // black plane
+        const long long pl = g.plane, cs = g.cs;
+        const int z0 = 1 + tz * zs.zc;
+        const int z1 = min(z0 + zs.zc, g.n - 1);
+        const long long xl = xs > 0 ? -1 : 0;
+        long long ro = row_off(g, y, z0) + xs;
+        T rv[U + 2], bv[U + 2];
+        rv[U] = R[ro - pl];
+        rv[U + 1] = R[ro];
+        bv[U] = B[ro - pl];
+        bv[U + 1] = B[ro];
+        auto point = [&](T xm, T xp, T ym, T yp, T zm, T zp, T uc, T fv, long long at) {
+            T nb = xm;
+            nb = nb + xp;
+            nb = nb + ym;
+            nb = nb + yp;
+            nb = nb + zm;
+            nb = nb + zp;
+            const T v = fv - (T(6) * uc - nb) * s;
+            if (STORE) st_stream<true>(r + at, v);
+            const double dv = (double)v;
+            sq = sq + dv * dv;
+            mx = fmax(mx, fabs(dv));
+        };
+        int z = z0;
+        for (; z + U <= z1; z += U, ro += U * pl) {
+            rv[0] = rv[U];
+            rv[1] = rv[U + 1];
+            bv[0] = bv[U];
+            bv[1] = bv[U + 1];
+            T bx[U], rx[U], bym[U], byp[U], rym[U], ryp[U], fr[U], fb[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const long long rk = ro + k * pl;
+                const int pr = (y + z + k) & 1;   // x parity of the red point; the black one has 1 - pr
+                rv[k + 2] = R[rk + pl];
+                bv[k + 2] = B[rk + pl];
+                bx[k] = B[rk + (pr ? 1 : xl)];
+                rx[k] = R[rk + (pr ? xl : 1)];
+                bym[k] = B[rk - g.pitch];
+                byp[k] = B[rk + g.pitch];
+                rym[k] = R[rk - g.pitch];
+                ryp[k] = R[rk + g.pitch];
+                fr[k] = ld_stream<true>(f + rk);
+                fb[k] = ld_stream<true>(f + cs + rk);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const long long rk = ro + k * pl;
+                const int pr = (y + z + k) & 1;
+                if (pr | xs)
+                    point(pr ? bv[k + 1] : bx[k], pr ? bx[k] : bv[k + 1], bym[k], byp[k], bv[k], bv[k + 2],
+                          rv[k + 1], fr[k], rk);
+                if ((1 - pr) | xs)
+                    point(pr ? rx[k] : rv[k + 1], pr ? rv[k + 1] : rx[k], rym[k], ryp[k], rv[k], rv[k + 2],
+                          bv[k + 1], fb[k], cs + rk);
+            }
+        }
+        T rm = rv[U], rc = rv[U + 1], bm = bv[U], bc = bv[U + 1];
+        for (; z < z1; ++z, ro += pl) {
+            const T rp = R[ro + pl];
+            const T bp = B[ro + pl];
+            const int pr = (y + z) & 1;
+            const T bx = B[ro + (pr ? 1 : xl)];
+            const T rx = R[ro + (pr ? xl : 1)];
+            if (pr | xs)
+                point(pr ? bc : bx, pr ? bx : bc, B[ro - g.pitch], B[ro + g.pitch], bm, bp, rc,
+                      ld_stream<true>(f + ro), ro);
+            if ((1 - pr) | xs)
+                point(pr ? rx : rc, pr ? rc : rx, R[ro - g.pitch], R[ro + g.pitch], rm, rp, bc,
+                      ld_stream<true>(f + cs + ro), cs + ro);
+            rm = rc;
+            rc = rp;
+            bm = bc;
+            bc = bp;
+        }
+    }
     if (NORM) block_sum_max(sq, mx, part + 2 * (long long)blockIdx.x);
 }
 
 // Full weighting: f_c[X] = sum_{o in {-1,0,1}^d} prod_a (2 - |o_a|) / 4^d r[2X + o],
 // summed with the z offset slowest and the x offset fastest.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_node_restrict(Geom gf, Geom gc, Space sp,
+__device__ __forceinline__ void d_node_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ fcoarse) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int X = 2 * p.xs + par;
     if (X < 1 || X > gc.n - 2) return;
@@ -184,14 +411,21 @@ __global__ __launch_bounds__(256) void k_node_restrict(Geom gf, Geom gc, Space s
     fcoarse[(long long)p.c * gc.cs + row_off(gc, Y, Z) + p.xs] = acc;
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_node_restrict(Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    d_node_restrict<T, D>(solo_ex(), gf, gc, sp, r, fcoarse);
+}
+
 // Linear interpolation as the tensor product of the 1-D rule (even fine
 // node: coarse value; odd: half the sum of the two coarse neighbours),
 // along x first, then y, then z; then u += P e.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_node_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
+__device__ __forceinline__ void d_node_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > gf.n - 2) return;
@@ -202,17 +436,23 @@ __global__ __launch_bounds__(256) void k_node_prolong(Geom gf, Geom gc, Space sp
     auto E = [&](int X, int Y, int Z) -> T {
         return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
     };
-    auto ex = [&](int Y, int Z) -> T {
+    auto ix = [&](int Y, int Z) -> T {
         return (x & 1) ? half * (E(X0, Y, Z) + E(X1, Y, Z)) : E(X0, Y, Z);
     };
-    auto ey = [&](int Z) -> T { return (y & 1) ? half * (ex(Y0, Z) + ex(Y1, Z)) : ex(Y0, Z); };
+    auto iy = [&](int Z) -> T { return (y & 1) ? half * (ix(Y0, Z) + ix(Y1, Z)) : ix(Y0, Z); };
     T e;
     if (D == 3)
-        e = (z & 1) ? half * (ey(Z0) + ey(Z1)) : ey(Z0);
+        e = (z & 1) ? half * (iy(Z0) + iy(Z1)) : iy(Z0);
     else
-        e = ey(0);
+        e = iy(0);
     const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
     u[me] = u[me] + e;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_node_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
+                                                      const T* __restrict__ ec) {
+    d_node_prolong<T, D>(solo_ex(), gf, gc, sp, u, ec);
 }
 
 // ------------------------------------------------------------ cell grids
@@ -264,12 +504,12 @@ __device__ __forceinline__ void cell_sums(const Geom& g, const T* __restrict__ o
 }
 
 template <typename T, int D, bool ZERO>
-__global__ __launch_bounds__(256) void k_cell_gs(Geom g, Space sp, T* __restrict__ me,
+__device__ __forceinline__ void d_cell_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
                                                  const T* __restrict__ other, const T* __restrict__ f,
                                                  const T* __restrict__ bx, const T* __restrict__ by,
                                                  const T* __restrict__ bz, T s) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     const long long ro = row_off(g, p.y, p.z) + p.xs;
@@ -279,12 +519,20 @@ __global__ __launch_bounds__(256) void k_cell_gs(Geom g, Space sp, T* __restrict
 }
 
 template <typename T, int D, bool ZERO>
-__global__ __launch_bounds__(256) void k_cell_jacobi(Geom g, Space sp, const T* __restrict__ u,
+__global__ __launch_bounds__(256) void k_cell_gs(Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 const T* __restrict__ bx, const T* __restrict__ by,
+                                                 const T* __restrict__ bz, T s) {
+    d_cell_gs<T, D, ZERO>(solo_ex(), g, sp, me, other, f, bx, by, bz, s);
+}
+
+template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void d_cell_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
                                                      const T* __restrict__ bx, const T* __restrict__ by,
                                                      const T* __restrict__ bz, T s, T omega) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     const long long ro = row_off(g, p.y, p.z) + p.xs;
@@ -296,15 +544,23 @@ __global__ __launch_bounds__(256) void k_cell_jacobi(Geom g, Space sp, const T* 
     out[me] = uc + (omega * r) / (dg * s);
 }
 
+template <typename T, int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_cell_jacobi(Geom g, Space sp, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out,
+                                                     const T* __restrict__ bx, const T* __restrict__ by,
+                                                     const T* __restrict__ bz, T s, T omega) {
+    d_cell_jacobi<T, D, ZERO>(solo_ex(), g, sp, u, f, out, bx, by, bz, s, omega);
+}
+
 template <typename T, int D, bool NORM, bool STORE>
-__global__ __launch_bounds__(256) void k_cell_residual(Geom g, Space sp, const T* __restrict__ u,
+__device__ __forceinline__ void d_cell_residual(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
                                                        const T* __restrict__ f, T* __restrict__ r,
                                                        const T* __restrict__ bx, const T* __restrict__ by,
                                                        const T* __restrict__ bz, T s,
                                                        double* __restrict__ part) {
     double sq = 0.0, mx = 0.0;
     Pt p;
-    if (map_point(sp, p)) {
+    if (map_point(ex, sp, p)) {
         const int par = (p.y + p.z + p.c) & 1;
         const int x = 2 * p.xs + par;
         const long long ro = row_off(g, p.y, p.z) + p.xs;
@@ -318,16 +574,25 @@ __global__ __launch_bounds__(256) void k_cell_residual(Geom g, Space sp, const T
         sq = dv * dv;
         mx = fabs(dv);
     }
-    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)blockIdx.x);
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
+template <typename T, int D, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_cell_residual(Geom g, Space sp, const T* __restrict__ u,
+                                                       const T* __restrict__ f, T* __restrict__ r,
+                                                       const T* __restrict__ bx, const T* __restrict__ by,
+                                                       const T* __restrict__ bz, T s,
+                                                       double* __restrict__ part) {
+    d_cell_residual<T, D, NORM, STORE>(solo_ex(), g, sp, u, f, r, bx, by, bz, s, part);
 }
 
 // Mean of the 2^d children, summed with the z offset slowest, then scaled.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space sp,
+__device__ __forceinline__ void d_cell_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ fcoarse) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int X = 2 * p.xs + par, Y = p.y, Z = p.z;
     T acc = T(0);
@@ -348,14 +613,21 @@ __global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space s
     fcoarse[(long long)p.c * gc.cs + row_off(gc, Y, Z) + p.xs] = acc * T(D == 3 ? 0.125 : 0.25);
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    d_cell_restrict<T, D>(solo_ex(), gf, gc, sp, r, fcoarse);
+}
+
 // Cell-centred linear interpolation: per axis fine(2I) = 3/4 e[I] + 1/4 e[I-1],
 // fine(2I+1) = 3/4 e[I] + 1/4 e[I+1], mirror ghost -e[I] beyond a wall;
 // x first, then y, then z; then u += P e.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_cell_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
+__device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par, y = p.y, z = p.z;
     const int Nc = gc.n;
@@ -367,36 +639,42 @@ __global__ __launch_bounds__(256) void k_cell_prolong(Geom gf, Geom gc, Space sp
     auto E = [&](int X, int Y, int Z) -> T {
         return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
     };
-    auto ex = [&](int Y, int Z) -> T {
+    auto ix = [&](int Y, int Z) -> T {
         const T c0 = E(I, Y, Z);
         const T c1 = wI ? -c0 : E(In, Y, Z);
         return a * c0 + b * c1;
     };
-    auto ey = [&](int Z) -> T {
-        const T c0 = ex(J, Z);
-        const T c1 = wJ ? -c0 : ex(Jn, Z);
+    auto iy = [&](int Z) -> T {
+        const T c0 = ix(J, Z);
+        const T c1 = wJ ? -c0 : ix(Jn, Z);
         return a * c0 + b * c1;
     };
     T e;
     if (D == 3) {
-        const T c0 = ey(K);
-        const T c1 = wK ? -c0 : ey(Kn);
+        const T c0 = iy(K);
+        const T c1 = wK ? -c0 : iy(Kn);
         e = a * c0 + b * c1;
     } else {
-        e = ey(0);
+        e = iy(0);
     }
     const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
     u[me] = u[me] + e;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cell_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
+                                                      const T* __restrict__ ec) {
+    d_cell_prolong<T, D>(solo_ex(), gf, gc, sp, u, ec);
 }
 
 // ------------------------------------------------------ coarsest, reductions
 // Exact coarsest solve: gather the m unknowns (C order), L y = b and
 // L^T x = y column by column in FP64, scatter x.  One block of 64 threads.
 template <typename T>
-__global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, T* __restrict__ u,
+__device__ __forceinline__ void d_coarse(const Ex& ex, Geom g, const T* __restrict__ f, T* __restrict__ u,
                                                const double* __restrict__ L, int m) {
     __shared__ double b[64];
-    const int t = (int)threadIdx.x;
+    const int t = ex.t;
     const int side = g.cell ? g.n : g.n - 2, off = g.cell ? 0 : 1;
     long long idx = 0;
     if (t < m) {
@@ -421,16 +699,27 @@ __global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, 
     if (t < m) u[idx] = (T)b[t];
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, long long count,
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, T* __restrict__ u,
+                                               const double* __restrict__ L, int m) {
+    d_coarse<T>(solo_ex(), g, f, u, L, m);
+}
+
+__device__ __forceinline__ void d_reduce(const Ex& ex, const double* __restrict__ in, long long count,
                                                 double* __restrict__ out) {
-    const long long i0 = (long long)blockIdx.x * kReduceChunk;
+    const long long i0 = (long long)ex.b * kReduceChunk;
     const long long i1 = i0 + kReduceChunk < count ? i0 + kReduceChunk : count;
     double sq = 0.0, mx = 0.0;
-    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    for (long long i = i0 + ex.t; i < i1; i += ex.nt) {
         sq = sq + in[2 * i];
         mx = fmax(mx, in[2 * i + 1]);
     }
-    block_sum_max(sq, mx, out + 2 * (long long)blockIdx.x);
+    block_sum_max(sq, mx, out + 2 * (long long)ex.b);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, long long count,
+                                                double* __restrict__ out) {
+    d_reduce(solo_ex(), in, count, out);
 }
 
 // ------------------------------------------------------ layout conversion
@@ -447,21 +736,33 @@ __device__ __forceinline__ bool nat_to_split(const Geom& g, long long i, long lo
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pack(Geom g, long long total, const double* __restrict__ nat,
+__device__ __forceinline__ void d_pack(const Ex& ex, Geom g, long long total, const double* __restrict__ nat,
                                               T* __restrict__ split) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = (long long)ex.b * ex.nt + ex.t;
     if (i >= total) return;
     long long s;
     if (nat_to_split(g, i, s)) split[s] = (T)nat[i];
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_unpack(Geom g, long long total, const T* __restrict__ split,
+__global__ __launch_bounds__(256) void k_pack(Geom g, long long total, const double* __restrict__ nat,
+                                              T* __restrict__ split) {
+    d_pack<T>(solo_ex(), g, total, nat, split);
+}
+
+template <typename T>
+__device__ __forceinline__ void d_unpack(const Ex& ex, Geom g, long long total, const T* __restrict__ split,
                                                 double* __restrict__ nat) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = (long long)ex.b * ex.nt + ex.t;
     if (i >= total) return;
     long long s;
     nat[i] = nat_to_split(g, i, s) ? (double)split[s] : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack(Geom g, long long total, const T* __restrict__ split,
+                                                double* __restrict__ nat) {
+    d_unpack<T>(solo_ex(), g, total, split, nat);
 }
 
 // ------------------------------------------------------ mixed precision
@@ -472,13 +773,13 @@ __device__ __forceinline__ double pow2_floor(double v) {
     return ldexp(1.0, e - 1);
 }
 
-__global__ __launch_bounds__(256) void k_cast(Geom g, Space sp, const double* __restrict__ r,
+__device__ __forceinline__ void d_cast(const Ex& ex, Geom g, Space sp, const double* __restrict__ r,
                                               float* __restrict__ f32, const double* __restrict__ red,
                                               double* __restrict__ sigma_out) {
     const double sigma = pow2_floor(red[1]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *sigma_out = sigma;
+    if (ex.b == 0 && ex.t == 0) *sigma_out = sigma;
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (!g.cell && (x < 1 || x > g.n - 2)) return;
@@ -486,17 +787,29 @@ __global__ __launch_bounds__(256) void k_cast(Geom g, Space sp, const double* __
     f32[me] = (float)(r[me] / sigma);
 }
 
-__global__ __launch_bounds__(256) void k_update(Geom g, Space sp, double* __restrict__ u,
+__global__ __launch_bounds__(256) void k_cast(Geom g, Space sp, const double* __restrict__ r,
+                                              float* __restrict__ f32, const double* __restrict__ red,
+                                              double* __restrict__ sigma_out) {
+    d_cast(solo_ex(), g, sp, r, f32, red, sigma_out);
+}
+
+__device__ __forceinline__ void d_update(const Ex& ex, Geom g, Space sp, double* __restrict__ u,
                                                 const float* __restrict__ c32,
                                                 const double* __restrict__ sigma_p) {
     const double sigma = *sigma_p;
     Pt p;
-    if (!map_point(sp, p)) return;
+    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (!g.cell && (x < 1 || x > g.n - 2)) return;
     const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
     u[me] = u[me] + sigma * (double)c32[me];
+}
+
+__global__ __launch_bounds__(256) void k_update(Geom g, Space sp, double* __restrict__ u,
+                                                const float* __restrict__ c32,
+                                                const double* __restrict__ sigma_p) {
+    d_update(solo_ex(), g, sp, u, c32, sigma_p);
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, long long n16) {
@@ -545,6 +858,12 @@ static hipError_t gs_t(const Geom& g, int colour, bool zero, void* u, const void
                                g, sp, me, other, fm, cp<T>(fc.b[0]), cp<T>(fc.b[1]), cp<T>(fc.b[2]), (T)s);
                            else k_cell_gs<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
                                g, sp, me, other, fm, cp<T>(fc.b[0]), cp<T>(fc.b[1]), cp<T>(fc.b[2]), (T)s));
+    } else if (!zero && use_zmarch(g)) {
+        const ZSpace zs = make_zspace(g);
+        const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+        // planes in flight per thread: 2 x 8 B (FP64) or 4 x 4 B (FP32) columns
+        constexpr int U = sizeof(T) == 8 ? 2 : 4;
+        k_node_gs_zm<T, U, true><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour);
     } else {
         MG_DISPATCH_DIM(g, if (zero) k_node_gs<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
                                g, sp, me, other, fm, (T)s);
@@ -586,7 +905,9 @@ hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, cons
                 : jacobi_t<double>(g, zero, u, f, out, fc, s, omega, st);
 }
 
-long long residual_blocks(const Geom& g) { return level_space(g, 2, 0).blocks(); }
+long long residual_blocks(const Geom& g) {
+    return use_zmarch(g) ? make_zspace(g).blocks() : level_space(g, 2, 0).blocks();
+}
 
 template <typename T, bool NORM, bool STORE>
 static void residual_tt(const Geom& g, const Space& sp, const void* u, const void* f, void* r,
@@ -605,6 +926,19 @@ template <typename T>
 static hipError_t residual_t(const Geom& g, const void* u, const void* f, void* r, const Faces& fc,
                              double s, bool norm, bool store, double* part, long long* nb,
                              hipStream_t st) {
+    if (use_zmarch(g)) {
+        const ZSpace zs = make_zspace(g);
+        if (nb) *nb = zs.blocks();
+        const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+        constexpr int U = sizeof(T) == 8 ? 2 : 4;
+        if (norm && store)
+            k_node_res_zm<T, U, true, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        else if (norm)
+            k_node_res_zm<T, U, true, false><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        else
+            k_node_res_zm<T, U, false, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        return hipGetLastError();
+    }
     const Space sp = level_space(g, 2, 0);
     if (nb) *nb = sp.blocks();
     if (norm && store) residual_tt<T, true, true>(g, sp, u, f, r, fc, s, part, st);

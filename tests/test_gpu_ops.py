@@ -13,7 +13,7 @@ from paper_1904_08684_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-NODE_CASES = [(2, 9), (2, 17), (2, 129), (2, 257), (3, 9), (3, 17), (3, 33), (3, 65)]
+NODE_CASES = [(2, 9), (2, 17), (2, 129), (2, 257), (3, 9), (3, 17), (3, 33), (3, 65), (3, 129), (3, 257)]
 CELL_CASES = [(2, 8), (2, 16), (2, 128), (3, 8), (3, 16), (3, 32)]
 
 
