@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -149,7 +151,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": (traf["hbm_bytes_per_launch"] if traf else None),
-                "kernel": "finest-level red-black Gauss-Seidel half-sweep (k_node_gs<double,3>)",
+                "kernel": "finest-level red-black Gauss-Seidel half-sweep (k_node_gs_zm<double, 2, true>)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": c0,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
 
@@ -173,6 +175,18 @@ def main():
                         "speedup_vs_fp64_time_to_tol": round(ms_step / ms_mx, 3),
                         "kernel_ms_total": rmx["prof"]}
     out["solves_per_s_fp64"] = round(args.steps / r64["total"], 3)
+    if not args.no_serve:
+        print("# bench: served stream", file=sys.stderr, flush=True)
+        from paper_1904_08684_amd import serve_bench
+        f_dev = None
+        torch.cuda.empty_cache()
+        sv = serve_bench.main(["--count", str(args.serve_count)], emit=False)
+        out["serve"] = {"workload": sv["workload"], "solves_per_s": round(sv["open_loop"]["solves_per_s"], 1),
+                        "p50_ms": round(sv["open_loop"]["p50_ms"], 3), "p99_ms": round(sv["open_loop"]["p99_ms"], 3),
+                        "rate_per_s": round(sv["rate_per_s"], 1),
+                        "saturation_solves_per_s": round(sv["saturation"]["solves_per_s"], 1),
+                        "fifo_fp64_one_at_a_time": {k: round(v, 3) for k, v in sv["fifo_fp64_one_at_a_time"].items()},
+                        "speedup_solves_per_s": round(sv["speedup_solves_per_s"], 2), "server": sv["server"]}
     if not args.no_cpu_baseline:
         print("# bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

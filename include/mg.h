@@ -176,6 +176,79 @@ enum {
 int mg_profile(mg_ctx* c, int enable);          /* enabling clears the record */
 int mg_profile_read(mg_ctx* c, int kclass, int level, int* count, double* ms);
 
+/* ---------------------------------------------------------------- serving
+ * A solve server keeps level hierarchies resident in one caller-owned device
+ * arena and runs many mixed-precision solves at once.  Work advances in
+ * rounds: in each round every in-flight request performs one FP64
+ * refinement step (a newly admitted request also loads its right-hand side
+ * and computes its initial residual), and launch k of the round runs op k
+ * of every in-flight request in one persistent batched kernel.  One host
+ * synchronisation per round reads all residual norms; converged requests
+ * write their solution and retire, and queued requests are admitted in FIFO
+ * order as slots and arena bytes free up (their footprint is checked against
+ * the arena before admission).  Idle hierarchies stay resident for reuse by
+ * later requests of the same shape and are evicted, least recently used
+ * first, when a different shape needs the memory.
+ *
+ * A request's arithmetic does not depend on what else is in flight: it runs
+ * the same kernels on its own hierarchy with per-request reductions, so its
+ * result is bitwise the same alone and in any mix. */
+typedef struct mg_server mg_server;
+
+typedef struct mg_server_opts {
+    void* d_arena;          /* caller-owned device buffer, 256-byte aligned   */
+    size_t arena_bytes;     /* HBM budget of the server                       */
+    int max_slots;          /* requests in flight at most (1 .. 4096)         */
+    int max_queue;          /* queued requests at most; submit beyond: MG_EBUSY */
+    void* hip_stream;       /* hipStream_t for all server work (NULL default)  */
+} mg_server_opts;
+
+/* A solve request.  grid: MG_NODE, dim 2 or 3; opts: smoother, omega, nu1,
+ * nu2, max_cycles (refinement steps); precision is always MG_MIXED.  f and
+ * u_out are device arrays of n^dim doubles (C order, boundary included);
+ * the caller keeps them valid until the request's result is polled.
+ * t_arrive is the arrival time on the server clock (mg_server_clock). */
+typedef struct mg_request {
+    uint64_t id;
+    mg_grid grid;
+    mg_opts opts;
+    double tol;
+    const double* f;
+    double* u_out;
+    double t_arrive;
+} mg_request;
+
+typedef struct mg_result {
+    uint64_t id;
+    int status;             /* MG_OK, MG_ENOTCONV, MG_ENONFINITE              */
+    int steps;              /* refinement steps (single-precision V-cycles)   */
+    double relres;          /* ||f - A u|| / ||f|| of the returned solution   */
+    double t_arrive, t_admit, t_done;   /* server clock, seconds               */
+} mg_result;
+
+typedef struct mg_server_stats {
+    long long rounds, launches, admitted, completed, hierarchies_built, evictions;
+    size_t arena_peak_bytes, arena_used_bytes;
+    int in_flight, queued, resident;
+} mg_server_stats;
+
+/* Device bytes one resident hierarchy of this grid and options occupies. */
+int mg_server_footprint(const mg_grid* g, const mg_opts* o, size_t* bytes);
+int mg_server_create(const mg_server_opts* o, mg_server** out);
+void mg_server_destroy(mg_server* s);                  /* NULL-safe */
+double mg_server_clock(const mg_server* s);           /* seconds since create */
+/* Queue a request (copies the descriptor, not the arrays).  MG_EBUSY when the
+ * queue is full, MG_EINVAL for unsupported grids/options, MG_ENOMEM when the
+ * request alone cannot fit the arena. */
+int mg_server_submit(mg_server* s, const mg_request* r);
+/* Run one round; *in_flight receives the requests still in flight and
+ * *queued those waiting.  Synchronous. */
+int mg_server_step(mg_server* s, int* in_flight, int* queued);
+/* Move up to cap finished results to out; *n receives the count. */
+int mg_server_poll(mg_server* s, mg_result* out, int cap, int* n);
+int mg_server_get_stats(const mg_server* s, mg_server_stats* st);
+const char* mg_server_last_error(const mg_server* s);
+
 /* ------------------------------------------------------------------ errors */
 const char* mg_strerror(int code);
 const char* mg_last_error(const mg_ctx* c);

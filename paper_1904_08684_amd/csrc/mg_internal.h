@@ -89,6 +89,13 @@ struct ZSpace {
 constexpr int kZChunk = 8;
 constexpr int kZRows = 4;
 
+// A field larger than the 256 MB Infinity Cache streams from HBM: such
+// levels read f and write the updated colour with non-temporal accesses;
+// smaller levels keep default caching so that consecutive sweeps hit in cache.
+static inline bool streams_from_hbm(const Geom& g, size_t elem_bytes) {
+    return (size_t)(2 * g.cs) * elem_bytes > (size_t(256) << 20);
+}
+
 static inline bool use_zmarch(const Geom& g) {
     return g.dim == 3 && !g.cell && (g.n - 1) / 2 >= 64;
 }

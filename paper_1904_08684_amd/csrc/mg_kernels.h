@@ -65,4 +65,58 @@ hipError_t launch_update(const Geom& g, double* u64, const float* c32, const dou
 // Zero `bytes` bytes (a kernel, not a memset, so the call is graph-capturable).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
+// Iteration space of the point-per-thread kernels over one or both colours.
+Space level_space(const Geom& g, int ncol, int col0);
+
+// ------------------------------------------------------------ batched ops
+// One level operation of one request, resident in device memory, executed
+// tile by tile by the batched kernel with the same device code as the
+// stand-alone launches.  Serving runs node grids with FP64 outer and FP32
+// inner arithmetic, so each op has a fixed precision.
+enum BOp : int {
+    BOP_PACK = 0,      // f64 (split) <- natural FP64 array at *io[0]
+    BOP_ZERO,          // n 16-byte words at a
+    BOP_RES64,         // r64 = f64 - A u64, per-tile (sum r^2, max |r|) to part
+    BOP_REDUCE,        // part[0..n) -> red[0..1] and res[0..1]
+    BOP_CAST,          // f32 = fl32(r64 / sigma), sigma = 2^floor(log2 red[1]) -> red[2]
+    BOP_GS,            // FP32 GS half-sweep (colour-offset pointers)
+    BOP_GS_ZERO,       // FP32 GS half-sweep from a zero iterate
+    BOP_JAC,           // FP32 damped Jacobi, out of place
+    BOP_JAC_ZERO,      // FP32 damped Jacobi from a zero iterate
+    BOP_RES32,         // FP32 residual
+    BOP_RESTRICT,      // FP32 full weighting
+    BOP_PROLONG,       // FP32 interpolation + correction
+    BOP_COARSE,        // FP32 in, FP64 Cholesky solve, FP32 out
+    BOP_UPDATE,        // u64 += sigma * u32
+    BOP_UNPACK,        // natural FP64 array at *io[1] <- u64 (split)
+    BOP_COUNT
+};
+
+struct BItem {
+    int op, dim;
+    Geom g, gc;
+    Space sp;
+    long long tiles;       // blocks of 256 threads the op needs
+    long long n;           // elements (pack/unpack), 16-byte words (zero), pairs (reduce)
+    void* a;
+    void* b;
+    void* c;
+    const double* L;
+    int m;
+    double* part;
+    double* red;
+    double* res;
+    void* const* io;
+    double s, omega;
+};
+
+// A batched launch: entries sorted by `prefix`, the first global tile of each.
+struct BEntry {
+    const BItem* item;
+    long long prefix;
+};
+
+// Persistent batched kernel over n entries with `total` tiles in all.
+hipError_t launch_batch(const BEntry* d_entries, int n, long long total, hipStream_t st);
+
 }  // namespace mg

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __res
 
 // r = f - A u at both colours of the thread's column; both colours' z-1, z,
 // z+1 values stay in registers, U planes per step.
-template <typename T, int U, bool NORM, bool STORE>
+template <typename T, int U, bool NT, bool NORM, bool STORE>
 __global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T* __restrict__ u,
                                                       const T* __restrict__ f, T* __restrict__ r, T s,
                                                       double* __restrict__ part) {
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T
             nb = nb + zm;
             nb = nb + zp;
             const T v = fv - (T(6) * uc - nb) * s;
-            if (STORE) st_stream<true>(r + at, v);
+            if (STORE) st_stream<NT>(r + at, v);
             const double dv = (double)v;
             sq = sq + dv * dv;
             mx = fmax(mx, fabs(dv));
@@ -340,8 +340,8 @@ __global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T
                 byp[k] = B[rk + g.pitch];
                 rym[k] = R[rk - g.pitch];
                 ryp[k] = R[rk + g.pitch];
-                fr[k] = ld_stream<true>(f + rk);
-                fb[k] = ld_stream<true>(f + cs + rk);
+                fr[k] = ld_stream<NT>(f + rk);
+                fb[k] = ld_stream<NT>(f + cs + rk);
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) {
@@ -364,10 +364,10 @@ __global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T
             const T rx = R[ro + (pr ? xl : 1)];
             if (pr | xs)
                 point(pr ? bc : bx, pr ? bx : bc, B[ro - g.pitch], B[ro + g.pitch], bm, bp, rc,
-                      ld_stream<true>(f + ro), ro);
+                      ld_stream<NT>(f + ro), ro);
             if ((1 - pr) | xs)
                 point(pr ? rx : rc, pr ? rc : rx, R[ro - g.pitch], R[ro + g.pitch], rm, rp, bc,
-                      ld_stream<true>(f + cs + ro), cs + ro);
+                      ld_stream<NT>(f + cs + ro), cs + ro);
             rm = rc;
             rc = rp;
             bm = bc;
@@ -819,11 +819,138 @@ __global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, long long n
 
 // ------------------------------------------------------------- spaces
 // Points of one or both colours over the unknowns of a level.
-Space level_space(const Geom& g, int ncol, int col0) {
+Space space_of(const Geom& g, int ncol, int col0) {
     if (g.cell)
         return make_space(g.n / 2, 0, g.n, 0, g.dim == 3 ? g.n : 1, ncol, col0);
     // node grid: interior rows/planes; xs in [0, (n-1)/2) covers interior x
     return make_space((g.n - 1) / 2, 1, g.n - 2, g.dim == 3 ? 1 : 0, g.dim == 3 ? g.n - 2 : 1, ncol, col0);
+}
+
+// ------------------------------------------------------------ batched ops
+__device__ void run_item(const BItem& it, const Ex& ex) {
+    switch (it.op) {
+        case BOP_PACK:
+            d_pack<double>(ex, it.g, it.n, static_cast<const double*>(it.io[0]), static_cast<double*>(it.a));
+            break;
+        case BOP_ZERO: {
+            const long long i = (long long)ex.b * ex.nt + ex.t;
+            if (i < it.n) static_cast<uint4*>(it.a)[i] = make_uint4(0u, 0u, 0u, 0u);
+            break;
+        }
+        case BOP_RES64:
+            if (it.dim == 3)
+                d_node_residual<double, 3, true, true>(ex, it.g, it.sp, static_cast<const double*>(it.a),
+                                                       static_cast<const double*>(it.b),
+                                                       static_cast<double*>(it.c), it.s, it.part);
+            else
+                d_node_residual<double, 2, true, true>(ex, it.g, it.sp, static_cast<const double*>(it.a),
+                                                       static_cast<const double*>(it.b),
+                                                       static_cast<double*>(it.c), it.s, it.part);
+            break;
+        case BOP_REDUCE: {
+            double sq = 0.0, mx = 0.0;
+            for (long long i = ex.t; i < it.n; i += ex.nt) {
+                sq = sq + it.part[2 * i];
+                mx = fmax(mx, it.part[2 * i + 1]);
+            }
+            block_sum_max(sq, mx, it.red);
+            if (ex.t == 0 && it.res) {
+                it.res[0] = it.red[0];
+                it.res[1] = it.red[1];
+            }
+            break;
+        }
+        case BOP_CAST:
+            d_cast(ex, it.g, it.sp, static_cast<const double*>(it.a), static_cast<float*>(it.b), it.red,
+                   it.red + 2);
+            break;
+        case BOP_GS:
+        case BOP_GS_ZERO: {
+            float* me = static_cast<float*>(it.a);
+            const float* ot = static_cast<const float*>(it.b);
+            const float* f = static_cast<const float*>(it.c);
+            const float s = (float)it.s;
+            if (it.op == BOP_GS_ZERO) {
+                if (it.dim == 3) d_node_gs<float, 3, true>(ex, it.g, it.sp, me, ot, f, s);
+                else d_node_gs<float, 2, true>(ex, it.g, it.sp, me, ot, f, s);
+            } else {
+                if (it.dim == 3) d_node_gs<float, 3, false>(ex, it.g, it.sp, me, ot, f, s);
+                else d_node_gs<float, 2, false>(ex, it.g, it.sp, me, ot, f, s);
+            }
+            break;
+        }
+        case BOP_JAC:
+        case BOP_JAC_ZERO: {
+            const float* u = static_cast<const float*>(it.a);
+            const float* f = static_cast<const float*>(it.b);
+            float* out = static_cast<float*>(it.c);
+            const float s = (float)it.s, om = (float)it.omega;
+            if (it.op == BOP_JAC_ZERO) {
+                if (it.dim == 3) d_node_jacobi<float, 3, true>(ex, it.g, it.sp, u, f, out, s, om);
+                else d_node_jacobi<float, 2, true>(ex, it.g, it.sp, u, f, out, s, om);
+            } else {
+                if (it.dim == 3) d_node_jacobi<float, 3, false>(ex, it.g, it.sp, u, f, out, s, om);
+                else d_node_jacobi<float, 2, false>(ex, it.g, it.sp, u, f, out, s, om);
+            }
+            break;
+        }
+        case BOP_RES32:
+            if (it.dim == 3)
+                d_node_residual<float, 3, false, true>(ex, it.g, it.sp, static_cast<const float*>(it.a),
+                                                       static_cast<const float*>(it.b), static_cast<float*>(it.c),
+                                                       (float)it.s, nullptr);
+            else
+                d_node_residual<float, 2, false, true>(ex, it.g, it.sp, static_cast<const float*>(it.a),
+                                                       static_cast<const float*>(it.b), static_cast<float*>(it.c),
+                                                       (float)it.s, nullptr);
+            break;
+        case BOP_RESTRICT:
+            if (it.dim == 3)
+                d_node_restrict<float, 3>(ex, it.g, it.gc, it.sp, static_cast<const float*>(it.a),
+                                          static_cast<float*>(it.b));
+            else
+                d_node_restrict<float, 2>(ex, it.g, it.gc, it.sp, static_cast<const float*>(it.a),
+                                          static_cast<float*>(it.b));
+            break;
+        case BOP_PROLONG:
+            if (it.dim == 3)
+                d_node_prolong<float, 3>(ex, it.g, it.gc, it.sp, static_cast<float*>(it.a),
+                                         static_cast<const float*>(it.b));
+            else
+                d_node_prolong<float, 2>(ex, it.g, it.gc, it.sp, static_cast<float*>(it.a),
+                                         static_cast<const float*>(it.b));
+            break;
+        case BOP_COARSE:
+            d_coarse<float>(ex, it.g, static_cast<const float*>(it.a), static_cast<float*>(it.b), it.L, it.m);
+            break;
+        case BOP_UPDATE:
+            d_update(ex, it.g, it.sp, static_cast<double*>(it.a), static_cast<const float*>(it.b), it.red + 2);
+            break;
+        case BOP_UNPACK:
+            d_unpack<double>(ex, it.g, it.n, static_cast<const double*>(it.a), static_cast<double*>(it.io[1]));
+            break;
+        default:
+            break;
+    }
+}
+
+// Persistent: each block walks global tiles with stride gridDim.x, finds the
+// entry owning the tile and runs that tile of the entry's op.
+__global__ __launch_bounds__(256) void k_batch(const BEntry* __restrict__ ent, int n, long long total) {
+    for (long long gt = blockIdx.x; gt < total; gt += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ent[mid].prefix <= gt) lo = mid;
+            else hi = mid - 1;
+        }
+        Ex ex;
+        ex.b = (int)(gt - ent[lo].prefix);
+        ex.t = (int)threadIdx.x;
+        ex.nt = (int)blockDim.x;
+        run_item(*ent[lo].item, ex);
+        __syncthreads();
+    }
 }
 
 dim3 grid_of(const Space& sp) { return dim3((unsigned)sp.blocks()); }
@@ -849,7 +976,7 @@ T* mp(void* p) { return static_cast<T*>(p); }
 template <typename T>
 static hipError_t gs_t(const Geom& g, int colour, bool zero, void* u, const void* f, const Faces& fc,
                        double s, hipStream_t st) {
-    const Space sp = level_space(g, 1, colour);
+    const Space sp = space_of(g, 1, colour);
     T* me = mp<T>(u) + (long long)colour * g.cs;
     const T* other = cp<T>(u) + (long long)(1 - colour) * g.cs;
     const T* fm = cp<T>(f) + (long long)colour * g.cs;
@@ -863,7 +990,10 @@ static hipError_t gs_t(const Geom& g, int colour, bool zero, void* u, const void
         const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
         // planes in flight per thread: 2 x 8 B (FP64) or 4 x 4 B (FP32) columns
         constexpr int U = sizeof(T) == 8 ? 2 : 4;
-        k_node_gs_zm<T, U, true><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour);
+        if (streams_from_hbm(g, sizeof(T)))
+            k_node_gs_zm<T, U, true><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour);
+        else
+            k_node_gs_zm<T, U, false><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour);
     } else {
         MG_DISPATCH_DIM(g, if (zero) k_node_gs<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
                                g, sp, me, other, fm, (T)s);
@@ -882,7 +1012,7 @@ hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, co
 template <typename T>
 static hipError_t jacobi_t(const Geom& g, bool zero, const void* u, const void* f, void* out,
                            const Faces& fc, double s, double omega, hipStream_t st) {
-    const Space sp = level_space(g, 2, 0);
+    const Space sp = space_of(g, 2, 0);
     if (g.cell) {
         MG_DISPATCH_DIM(g, if (zero) k_cell_jacobi<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
                                g, sp, cp<T>(u), cp<T>(f), mp<T>(out), cp<T>(fc.b[0]), cp<T>(fc.b[1]),
@@ -906,7 +1036,10 @@ hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, cons
 }
 
 long long residual_blocks(const Geom& g) {
-    return use_zmarch(g) ? make_zspace(g).blocks() : level_space(g, 2, 0).blocks();
+    // the stand-alone path may march columns; the batched path uses one point per thread
+    const long long a = use_zmarch(g) ? make_zspace(g).blocks() : 0;
+    const long long b = space_of(g, 2, 0).blocks();
+    return a > b ? a : b;
 }
 
 template <typename T, bool NORM, bool STORE>
@@ -931,15 +1064,30 @@ static hipError_t residual_t(const Geom& g, const void* u, const void* f, void* 
         if (nb) *nb = zs.blocks();
         const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
         constexpr int U = sizeof(T) == 8 ? 2 : 4;
-        if (norm && store)
-            k_node_res_zm<T, U, true, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
-        else if (norm)
-            k_node_res_zm<T, U, true, false><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
-        else
-            k_node_res_zm<T, U, false, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        if (streams_from_hbm(g, sizeof(T))) {
+            if (norm && store)
+                k_node_res_zm<T, U, true, true, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r),
+                                                                             (T)s, part);
+            else if (norm)
+                k_node_res_zm<T, U, true, true, false><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r),
+                                                                              (T)s, part);
+            else
+                k_node_res_zm<T, U, true, false, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r),
+                                                                              (T)s, part);
+        } else {
+            if (norm && store)
+                k_node_res_zm<T, U, false, true, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(r),
+                                                                              (T)s, part);
+            else if (norm)
+                k_node_res_zm<T, U, false, true, false><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f),
+                                                                               mp<T>(r), (T)s, part);
+            else
+                k_node_res_zm<T, U, false, false, true><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f),
+                                                                               mp<T>(r), (T)s, part);
+        }
         return hipGetLastError();
     }
-    const Space sp = level_space(g, 2, 0);
+    const Space sp = space_of(g, 2, 0);
     if (nb) *nb = sp.blocks();
     if (norm && store) residual_tt<T, true, true>(g, sp, u, f, r, fc, s, part, st);
     else if (norm) residual_tt<T, true, false>(g, sp, u, f, r, fc, s, part, st);
@@ -956,7 +1104,7 @@ hipError_t launch_residual(const Geom& g, int prec, const void* u, const void* f
 
 template <typename T>
 static hipError_t restrict_t(const Geom& gf, const Geom& gc, const void* r, void* fco, hipStream_t st) {
-    const Space sp = level_space(gc, 2, 0);
+    const Space sp = space_of(gc, 2, 0);
     if (gf.cell) {
         MG_DISPATCH_DIM(gf, k_cell_restrict<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, cp<T>(r),
                                                                                          mp<T>(fco)));
@@ -977,7 +1125,7 @@ static hipError_t prolong_t(const Geom& gf, const Geom& gc, void* u, const void*
                             hipStream_t st) {
     const int ncol = (mask == 3) ? 2 : 1;
     const int col0 = (mask == 2) ? 1 : 0;
-    const Space sp = level_space(gf, ncol, col0);
+    const Space sp = space_of(gf, ncol, col0);
     if (gf.cell) {
         MG_DISPATCH_DIM(gf, k_cell_prolong<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, mp<T>(u),
                                                                                         cp<T>(ec)));
@@ -1059,15 +1207,25 @@ hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat
 
 hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* red, double* sigma,
                        hipStream_t st) {
-    const Space sp = level_space(g, 2, 0);
+    const Space sp = space_of(g, 2, 0);
     k_cast<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, r64, f32, red, sigma);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
                          hipStream_t st) {
-    const Space sp = level_space(g, 2, 0);
+    const Space sp = space_of(g, 2, 0);
     k_update<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, u64, c32, sigma);
+    return hipGetLastError();
+}
+
+Space level_space(const Geom& g, int ncol, int col0) { return space_of(g, ncol, col0); }
+
+hipError_t launch_batch(const BEntry* d_entries, int n, long long total, hipStream_t st) {
+    if (n < 1 || total < 1) return hipSuccess;
+    // ~8 resident blocks per CU on 256 CUs; smaller batches get one block per tile
+    const long long grid = total < 2048 ? total : 2048;
+    k_batch<<<(unsigned)grid, 256, 0, st>>>(d_entries, n, total);
     return hipGetLastError();
 }
 

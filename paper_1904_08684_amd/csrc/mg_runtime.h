@@ -34,7 +34,13 @@ struct Plan {
 };
 
 // Workspace layout for a problem; returns the total byte count.
-size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, Plan* out);
+size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, Plan* out, bool staging);
+
+struct Ctx;
+// Validate, lay out and initialise a context inside d_workspace (staging:
+// reserve a host-transfer buffer for host-pointer I/O).
+int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_workspace, size_t bytes,
+              hipStream_t stream, bool staging, Ctx** out, std::string* errmsg);
 
 struct Level {
     Geom g;
@@ -77,6 +83,12 @@ struct Ctx {
     size_t ev_used = 0;
     double agg_ms[MG_K_COUNT][kMaxLevels] = {};
     int agg_n[MG_K_COUNT][kMaxLevels] = {};
+    // recording mode (batched execution): ops append descriptors here
+    std::vector<BItem>* rec = nullptr;
+    double* rec_res = nullptr;    // extra destination of recorded norm reductions
+    BItem item(int op, int l) const;
+    int push(BItem it);
+    int rec_check(int pr, bool want_fp32);
 
     int fail(int code, const std::string& msg);
     int dev(hipError_t e, const char* what);

@@ -105,7 +105,7 @@ std::vector<int> ladder(const mg_grid* g) {
 // =================================================================== plan
 namespace mg {
 
-size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, Plan* out) {
+size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, Plan* out, bool staging) {
     Plan p;
     const int cell = g->centering == MG_CELL;
     const bool varcoef = cell;   // cell grids always carry face coefficients
@@ -149,7 +149,7 @@ size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, 
     p.m = side * side * (g->dim == 3 ? side : 1);
     p.chol = take((size_t)p.m * p.m * 8);
     const long long nat = (long long)g0.n * g0.n * (g->dim == 3 ? g0.n : 1);
-    p.staging = take((size_t)nat * 8);
+    p.staging = staging ? take((size_t)nat * 8) : SIZE_MAX;
     p.total = off;
     if (out) *out = p;
     return off;
@@ -379,9 +379,47 @@ hipEvent_t Ctx::event() {
     return ev_pool[ev_used++];
 }
 
+// ------------------------------------------------------------- recording
+// In recording mode (rec != null) the level ops below append batched-op
+// descriptors instead of launching; the serving path records one refinement
+// step of a request this way, so a served request runs exactly the op
+// sequence and operands of a stand-alone mixed-precision solve.
+BItem Ctx::item(int op, int l) const {
+    BItem it;
+    std::memset(&it, 0, sizeof(it));
+    it.op = op;
+    it.dim = grid.dim;
+    it.g = lv[l].g;
+    it.s = scale(l);
+    it.omega = opts.omega;
+    it.red = red;
+    return it;
+}
+
+int Ctx::push(BItem it) {
+    if (!(it.tiles > 0)) it.tiles = it.sp.blocks();
+    rec->push_back(it);
+    return MG_OK;
+}
+
+int Ctx::rec_check(int pr, bool want_fp32) {
+    if (grid.centering != MG_NODE) return fail(MG_EINVAL, "batched execution supports node grids");
+    if (want_fp32 != (pr == 1)) return fail(MG_EINVAL, "batched execution runs FP32 cycles only");
+    return MG_OK;
+}
+
 // ------------------------------------------------------------- level ops
 int Ctx::gs(int l, int pr, int colour, bool zero) {
     Level& L = lv[l];
+    if (rec) {
+        if (int rc = rec_check(pr, true)) return rc;
+        BItem it = item(zero ? BOP_GS_ZERO : BOP_GS, l);
+        it.sp = level_space(L.g, 1, colour);
+        it.a = static_cast<float*>(L.u[pr]) + (long long)colour * L.g.cs;
+        it.b = static_cast<float*>(L.u[pr]) + (long long)(1 - colour) * L.g.cs;
+        it.c = static_cast<float*>(L.f[pr]) + (long long)colour * L.g.cs;
+        return push(it);
+    }
     hipEvent_t e0 = begin();
     return record(MG_K_SMOOTH, l, launch_gs(L.g, pr, colour, zero, L.u[pr], L.f[pr], faces(l, pr), scale(l), stream),
                   e0, "gs");
@@ -389,6 +427,17 @@ int Ctx::gs(int l, int pr, int colour, bool zero) {
 
 int Ctx::jacobi(int l, int pr, bool zero) {
     Level& L = lv[l];
+    if (rec) {
+        if (int rc = rec_check(pr, true)) return rc;
+        BItem it = item(zero ? BOP_JAC_ZERO : BOP_JAC, l);
+        it.sp = level_space(L.g, 2, 0);
+        it.a = L.u[pr];
+        it.b = L.f[pr];
+        it.c = L.utmp[pr];
+        push(it);
+        std::swap(L.u[pr], L.utmp[pr]);
+        return MG_OK;
+    }
     hipEvent_t e0 = begin();
     int rc = record(MG_K_SMOOTH, l,
                     launch_jacobi(L.g, pr, zero, L.u[pr], L.f[pr], L.utmp[pr], faces(l, pr), scale(l), opts.omega,
@@ -401,7 +450,13 @@ int Ctx::jacobi(int l, int pr, bool zero) {
 
 int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
     Level& L = lv[l];
-    if (sweeps == 0 && from_zero) {
+    if (sweeps == 0 && from_zero && rec) {
+        BItem it = item(BOP_ZERO, l);
+        it.a = L.u[pr];
+        it.n = (long long)(L.field_bytes[pr] / 16);
+        it.tiles = (it.n + 255) / 256;
+        push(it);
+    } else if (sweeps == 0 && from_zero) {
         hipEvent_t e0 = begin();
         int rc = record(MG_K_COPY, l, launch_zero(L.u[pr], L.field_bytes[pr], stream), e0, "zero");
         if (rc) return rc;
@@ -422,6 +477,27 @@ int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
 
 int Ctx::residual(int l, int pr, bool norm, bool store) {
     Level& L = lv[l];
+    if (rec) {
+        if (pr == 0 && !(norm && store)) return fail(MG_EINVAL, "batched FP64 residual carries its norm");
+        if (pr == 1 && norm) return fail(MG_EINVAL, "batched FP32 residual has no norm");
+        if (grid.centering != MG_NODE) return fail(MG_EINVAL, "batched execution supports node grids");
+        BItem it = item(pr == 0 ? BOP_RES64 : BOP_RES32, l);
+        it.sp = level_space(L.g, 2, 0);
+        it.a = L.u[pr];
+        it.b = L.f[pr];
+        it.c = L.r[pr];
+        it.part = partials;
+        push(it);
+        if (pr == 0) {
+            BItem rd = item(BOP_REDUCE, l);
+            rd.part = partials;
+            rd.n = it.sp.blocks();
+            rd.res = rec_res;
+            rd.tiles = 1;
+            push(rd);
+        }
+        return MG_OK;
+    }
     long long nb = 0;
     hipEvent_t e0 = begin();
     int rc = record(MG_K_RESIDUAL, l,
@@ -434,12 +510,30 @@ int Ctx::residual(int l, int pr, bool norm, bool store) {
 }
 
 int Ctx::restrict_to(int l, int pr) {
+    if (rec) {
+        if (int rc = rec_check(pr, true)) return rc;
+        BItem it = item(BOP_RESTRICT, l);
+        it.gc = lv[l + 1].g;
+        it.sp = level_space(lv[l + 1].g, 2, 0);
+        it.a = lv[l].r[pr];
+        it.b = lv[l + 1].f[pr];
+        return push(it);
+    }
     hipEvent_t e0 = begin();
     return record(MG_K_RESTRICT, l, launch_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].r[pr], lv[l + 1].f[pr], stream),
                   e0, "restrict");
 }
 
 int Ctx::prolong(int l, int pr, int mask) {
+    if (rec) {
+        if (int rc = rec_check(pr, true)) return rc;
+        BItem it = item(BOP_PROLONG, l);
+        it.gc = lv[l + 1].g;
+        it.sp = level_space(lv[l].g, mask == 3 ? 2 : 1, mask == 2 ? 1 : 0);
+        it.a = lv[l].u[pr];
+        it.b = lv[l + 1].u[pr];
+        return push(it);
+    }
     hipEvent_t e0 = begin();
     return record(MG_K_PROLONG, l,
                   launch_prolong(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l + 1].u[pr], mask, stream), e0,
@@ -448,6 +542,16 @@ int Ctx::prolong(int l, int pr, int mask) {
 
 int Ctx::coarse(int pr) {
     const int l = L - 1;
+    if (rec) {
+        if (int rc = rec_check(pr, true)) return rc;
+        BItem it = item(BOP_COARSE, l);
+        it.a = lv[l].f[pr];
+        it.b = lv[l].u[pr];
+        it.L = chol;
+        it.m = m;
+        it.tiles = 1;
+        return push(it);
+    }
     hipEvent_t e0 = begin();
     return record(MG_K_COARSE, l, launch_coarse(lv[l].g, pr, lv[l].f[pr], lv[l].u[pr], chol, m, stream), e0,
                   "coarse");
@@ -479,6 +583,19 @@ int Ctx::vcycle(int l, int pr, bool from_zero) {
 // with norm and store); leaves u64 updated.
 int Ctx::refine_step() {
     Level& L0 = lv[0];
+    if (rec) {
+        BItem ca = item(BOP_CAST, 0);
+        ca.sp = level_space(L0.g, 2, 0);
+        ca.a = L0.r[0];
+        ca.b = L0.f[1];
+        push(ca);
+        if (int rc = vcycle(0, 1, true)) return rc;
+        BItem up = item(BOP_UPDATE, 0);
+        up.sp = level_space(L0.g, 2, 0);
+        up.a = L0.u[0];
+        up.b = L0.u[1];
+        return push(up);
+    }
     hipEvent_t e0 = begin();
     int rc = record(MG_K_CAST, 0,
                     launch_cast(L0.g, static_cast<const double*>(L0.r[0]), static_cast<float*>(L0.f[1]), red,
@@ -569,61 +686,30 @@ int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
 
 }  // namespace mg
 
-// =================================================================== C ABI
-using mg::Ctx;
+namespace mg {
 
-extern "C" {
-
-const char* mg_version(void) { return "mg 0.1.0 (gfx950, colour-split storage)"; }
-
-void mg_default_opts(mg_opts* o) {
-    if (!o) return;
-    o->smoother = MG_RBGS;
-    o->omega = 0.8;
-    o->nu1 = 2;
-    o->nu2 = 2;
-    o->precision = MG_FP64;
-    o->max_cycles = 100;
-    o->post_order = 0;
-}
-
-int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes) {
-    if (!bytes) return MG_EINVAL;
-    int rc = validate(g, st, o, nullptr);
-    if (rc) return rc;
-    *bytes = mg::plan_workspace(g, st, o, nullptr);
-    return MG_OK;
-}
-
-static thread_local std::string g_setup_error;
-
-int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_opts* o, void* d_workspace,
-             size_t bytes, void* hip_stream, mg_ctx** out) {
-    if (!out) return MG_EINVAL;
+int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_workspace, size_t bytes,
+              hipStream_t stream, bool staging, Ctx** out, std::string* errmsg) {
     *out = nullptr;
     std::string why;
     int rc = validate(g, st, o, &why);
     if (rc) {
-        g_setup_error = why;
+        *errmsg = why;
         return rc;
-    }
-    if (bc && bc->kind != MG_DIRICHLET0) {
-        g_setup_error = "only zero Dirichlet boundaries are supported";
-        return MG_EINVAL;
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-        g_setup_error = "no HIP device";
+        *errmsg = "no HIP device";
         return MG_EDEVICE;
     }
-    mg::Plan plan;
-    const size_t need = mg::plan_workspace(g, st, o, &plan);
+    Plan plan;
+    const size_t need = plan_workspace(g, st, o, &plan, staging);
     if (!d_workspace || bytes < need) {
-        g_setup_error = "workspace too small: need " + std::to_string(need) + " bytes";
+        *errmsg = "workspace too small: need " + std::to_string(need) + " bytes";
         return MG_ENOMEM;
     }
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256) {
-        g_setup_error = "workspace must be 256-byte aligned";
+        *errmsg = "workspace must be 256-byte aligned";
         return MG_EINVAL;
     }
     Ctx* c = new (std::nothrow) Ctx();
@@ -633,7 +719,7 @@ int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_o
     c->kind = st ? st->kind : MG_LAPLACE;
     c->base = d_workspace;
     c->bytes = bytes;
-    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->stream = stream;
     c->L = plan.L;
     c->m = plan.m;
     c->partial_pairs = plan.partial_pairs;
@@ -643,8 +729,8 @@ int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_o
     c->chol = static_cast<double*>(c->at(plan.chol));
     c->staging = static_cast<double*>(c->at(plan.staging));
     for (int l = 0; l < plan.L; ++l) {
-        const mg::LevelPlan& lp = plan.lv[l];
-        mg::Level lvv;
+        const LevelPlan& lp = plan.lv[l];
+        Level lvv;
         lvv.g = lp.g;
         for (int pr = 0; pr < 2; ++pr) {
             lvv.has[pr] = lp.has[pr];
@@ -658,10 +744,10 @@ int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_o
         c->lv.push_back(lvv);
     }
     // zero every field (boundary nodes and padding stay zero for good)
-    rc = c->dev(mg::launch_zero(d_workspace, plan.total, c->stream), "zero workspace");
+    rc = c->dev(launch_zero(d_workspace, plan.total, c->stream), "zero workspace");
     // face coefficients
     if (!rc && g->centering == MG_CELL) {
-        const mg::Geom& g0 = c->lv[0].g;
+        const Geom& g0 = c->lv[0].g;
         const long long ncell = (long long)g0.n * g0.n * (g0.dim == 3 ? g0.n : 1);
         std::vector<double> k((size_t)ncell, 1.0);
         if (c->kind == MG_VARCOEF) {
@@ -678,7 +764,7 @@ int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_o
         if (!rc) harmonic_faces(g0, k.data(), bf);
         std::vector<float> tmp32;
         for (int l = 0; !rc && l < c->L; ++l) {
-            const mg::Geom& gl = c->lv[l].g;
+            const Geom& gl = c->lv[l].g;
             if (l > 0) {
                 coarsen_faces(c->lv[l - 1].g, bf, gl, bc2);
                 for (int a = 0; a < 3; ++a) bf[a].swap(bc2[a]);
@@ -712,10 +798,56 @@ int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_o
     }
     c->coarse_beta_host.clear();
     if (rc) {
-        g_setup_error = c->err;
+        *errmsg = c->err;
         delete c;
         return rc;
     }
+    *out = c;
+    return MG_OK;
+}
+
+}  // namespace mg
+
+// =================================================================== C ABI
+using mg::Ctx;
+
+extern "C" {
+
+const char* mg_version(void) { return "mg 0.1.0 (gfx950, colour-split storage)"; }
+
+void mg_default_opts(mg_opts* o) {
+    if (!o) return;
+    o->smoother = MG_RBGS;
+    o->omega = 0.8;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->precision = MG_FP64;
+    o->max_cycles = 100;
+    o->post_order = 0;
+}
+
+int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes) {
+    if (!bytes) return MG_EINVAL;
+    int rc = validate(g, st, o, nullptr);
+    if (rc) return rc;
+    *bytes = mg::plan_workspace(g, st, o, nullptr, true);
+    return MG_OK;
+}
+
+static thread_local std::string g_setup_error;
+
+int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_opts* o, void* d_workspace,
+             size_t bytes, void* hip_stream, mg_ctx** out) {
+    if (!out) return MG_EINVAL;
+    *out = nullptr;
+    if (bc && bc->kind != MG_DIRICHLET0) {
+        g_setup_error = "only zero Dirichlet boundaries are supported";
+        return MG_EINVAL;
+    }
+    Ctx* c = nullptr;
+    const int rc = mg::setup_ctx(g, st, o, d_workspace, bytes, static_cast<hipStream_t>(hip_stream), true, &c,
+                                 &g_setup_error);
+    if (rc) return rc;
     *out = reinterpret_cast<mg_ctx*>(c);
     return MG_OK;
 }
@@ -730,6 +862,7 @@ void mg_destroy(mg_ctx* h) {
 static int copy_in(Ctx* c, const mg::Geom& g, int pr, void* field, const double* a, int on_device) {
     const long long tot = (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
     const double* src = a;
+    if (!on_device && !c->staging) return c->fail(MG_EINVAL, "this context takes device arrays only");
     if (!on_device) {
         int rc = c->dev(hipMemcpyAsync(c->staging, a, (size_t)tot * 8, hipMemcpyHostToDevice, c->stream), "upload");
         if (rc) return rc;
@@ -743,6 +876,7 @@ static int copy_in(Ctx* c, const mg::Geom& g, int pr, void* field, const double*
 
 static int copy_out(Ctx* c, const mg::Geom& g, int pr, const void* field, double* a, int on_device) {
     const long long tot = (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
+    if (!on_device && !c->staging) return c->fail(MG_EINVAL, "this context takes device arrays only");
     double* dst = on_device ? a : c->staging;
     hipEvent_t e0 = c->begin();
     int rc = c->record(MG_K_COPY, -1, mg::launch_unpack(g, pr, field, dst, c->stream), e0, "unpack");

@@ -267,3 +267,133 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ===================================================================== serving
+class mg_server_opts(C.Structure):
+    _fields_ = [("d_arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int),
+                ("max_queue", C.c_int), ("hip_stream", C.c_void_p)]
+
+
+class mg_request(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("grid", mg_grid), ("opts", mg_opts), ("tol", C.c_double),
+                ("f", C.c_void_p), ("u_out", C.c_void_p), ("t_arrive", C.c_double)]
+
+
+class mg_result(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int), ("steps", C.c_int), ("relres", C.c_double),
+                ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class mg_server_stats(C.Structure):
+    _fields_ = [("rounds", C.c_longlong), ("launches", C.c_longlong), ("admitted", C.c_longlong),
+                ("completed", C.c_longlong), ("hierarchies_built", C.c_longlong), ("evictions", C.c_longlong),
+                ("arena_peak_bytes", C.c_size_t), ("arena_used_bytes", C.c_size_t),
+                ("in_flight", C.c_int), ("queued", C.c_int), ("resident", C.c_int)]
+
+
+_ssigs = {
+    "mg_server_footprint": (C.c_int, [C.POINTER(mg_grid), C.POINTER(mg_opts), C.POINTER(C.c_size_t)]),
+    "mg_server_create": (C.c_int, [C.POINTER(mg_server_opts), C.POINTER(_P)]),
+    "mg_server_destroy": (None, [_P]),
+    "mg_server_clock": (C.c_double, [_P]),
+    "mg_server_submit": (C.c_int, [_P, C.POINTER(mg_request)]),
+    "mg_server_step": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "mg_server_poll": (C.c_int, [_P, C.POINTER(mg_result), C.c_int, C.POINTER(C.c_int)]),
+    "mg_server_get_stats": (C.c_int, [_P, C.POINTER(mg_server_stats)]),
+    "mg_server_last_error": (C.c_char_p, [_P]),
+}
+for _name, (_res, _args) in _ssigs.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+def server_footprint(dim: int, n: int, smoother: int, nu1: int, nu2: int, omega: float = 0.8) -> int:
+    b = C.c_size_t()
+    g = make_grid(dim, n)
+    o = make_opts(smoother, omega, nu1, nu2, MG_MIXED)
+    _check(mg_server_footprint(C.byref(g), C.byref(o), C.byref(b)))
+    return b.value
+
+
+class Server:
+    """A solve server on a PyTorch-allocated device arena."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 256, max_queue: int = 1 << 20, stream=None,
+                 device: str = "cuda"):
+        import torch
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        o = mg_server_opts()
+        o.d_arena = self.arena.data_ptr()
+        o.arena_bytes = arena_bytes
+        o.max_slots = max_slots
+        o.max_queue = max_queue
+        o.hip_stream = self.stream.cuda_stream
+        h = C.c_void_p()
+        code = mg_server_create(C.byref(o), C.byref(h))
+        if code != MG_OK:
+            raise MGError(code, "server create")
+        self.h = h
+        self._keep = {}
+
+    def _err(self, code):
+        raise MGError(code, mg_server_last_error(self.h).decode())
+
+    def clock(self) -> float:
+        return mg_server_clock(self.h)
+
+    def submit(self, rid: int, dim: int, n: int, f, u_out, tol: float, smoother: int = MG_RBGS,
+               nu1: int = 2, nu2: int = 2, omega: float = 0.8, max_steps: int = 50, t_arrive=None) -> int:
+        """f and u_out: contiguous float64 CUDA tensors of shape (n,)*dim, kept
+        alive here until the result is polled.  Returns the status code."""
+        r = mg_request()
+        r.id = rid
+        r.grid = make_grid(dim, n)
+        r.opts = make_opts(smoother, omega, nu1, nu2, MG_MIXED, max_steps)
+        r.tol = tol
+        r.f = f.data_ptr()
+        r.u_out = u_out.data_ptr()
+        r.t_arrive = self.clock() if t_arrive is None else t_arrive
+        code = mg_server_submit(self.h, C.byref(r))
+        if code == MG_OK:
+            self._keep[rid] = (f, u_out)
+        return code
+
+    def step(self):
+        a = C.c_int()
+        q = C.c_int()
+        code = mg_server_step(self.h, C.byref(a), C.byref(q))
+        if code != MG_OK:
+            self._err(code)
+        return a.value, q.value
+
+    def poll(self, cap: int = 4096) -> list:
+        buf = (mg_result * cap)()
+        n = C.c_int()
+        _check(mg_server_poll(self.h, buf, cap, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            out.append({"id": r.id, "status": r.status, "steps": r.steps, "relres": r.relres,
+                        "t_arrive": r.t_arrive, "t_admit": r.t_admit, "t_done": r.t_done})
+            self._keep.pop(r.id, None)
+        return out
+
+    def stats(self) -> dict:
+        st = mg_server_stats()
+        _check(mg_server_get_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in mg_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            mg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,135 @@
+"""The continuously batched solve server: each result is bitwise the same
+alone and in a mix (with arrivals while others are in flight), meets its
+tolerance by the oracle's own residual, matches the oracle's mixed-precision
+solve, and admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+from oracle import cycle
+from paper_1904_08684_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# (dim, n): 2-D requests use damped Jacobi V(2,2), 3-D requests red-black GS V(3,3)
+MIX = [(2, 65), (3, 33), (2, 129), (3, 65), (2, 257), (3, 17), (2, 33), (3, 33)]
+
+
+def method(dim):
+    from paper_1904_08684_amd import mg
+    return (mg.MG_JACOBI, 2, 2) if dim == 2 else (mg.MG_RBGS, 3, 3)
+
+
+def make_inputs(torch, reqs):
+    fs, us = [], []
+    for rid, (d, n) in enumerate(reqs):
+        fs.append(torch.from_numpy(W.interior_uniform(n, d, W.SEED_REQUEST_BASE + rid)).cuda())
+        us.append(torch.zeros((n,) * d, dtype=torch.float64, device="cuda"))
+    return fs, us
+
+
+def run(mg, torch, reqs, order, arena=1 << 30, slots=64, stagger=False, tol=1e-8):
+    srv = mg.Server(arena, max_slots=slots)
+    fs, us = make_inputs(torch, reqs)
+    pending = list(order)
+    results = {}
+    # with stagger, requests arrive two at a time while earlier ones are in flight
+    while pending or len(results) < len(order):
+        batch = pending[:2] if stagger else pending
+        for rid in batch:
+            d, n = reqs[rid]
+            sm, nu1, nu2 = method(d)
+            assert srv.submit(rid, d, n, fs[rid], us[rid], tol, sm, nu1, nu2) == mg.MG_OK
+        pending = pending[len(batch):]
+        srv.step()
+        for r in srv.poll():
+            results[r["id"]] = r
+    torch.cuda.synchronize()
+    st = srv.stats()
+    sols = {rid: us[rid].cpu().numpy() for rid in order}
+    srv.close()
+    return results, sols, st
+
+
+def test_alone_equals_in_mix_bitwise(mg):
+    import torch
+    reqs = MIX
+    alone_res, alone_sol = {}, {}
+    for rid in range(len(reqs)):
+        r, s, _ = run(mg, torch, reqs, [rid])
+        alone_res.update(r)
+        alone_sol.update(s)
+    mix_res, mix_sol, st = run(mg, torch, reqs, list(range(len(reqs)))[::-1], stagger=True)
+    for rid in range(len(reqs)):
+        assert alone_res[rid]["status"] == mg.MG_OK
+        assert mix_res[rid]["steps"] == alone_res[rid]["steps"]
+        assert np.array_equal(mix_sol[rid], alone_sol[rid]), rid
+        assert mix_res[rid]["relres"] == alone_res[rid]["relres"]
+    print("mix stats", st, flush=True)
+    assert st["completed"] == len(reqs) and st["rounds"] > 0
+
+
+def test_results_meet_tolerance_and_match_oracle(mg):
+    import torch
+    reqs = MIX[:6]
+    res, sols, _ = run(mg, torch, reqs, list(range(len(reqs))))
+    for rid, (d, n) in enumerate(reqs):
+        f = W.interior_uniform(n, d, W.SEED_REQUEST_BASE + rid)
+        sm = "jacobi" if d == 2 else "rbgs"
+        nu = 2 if d == 2 else 3
+        h = cycle.build_hierarchy(cycle.Params(centering="node", dim=d, n=n, smoother=sm, nu1=nu, nu2=nu))
+        u = sols[rid]
+        rel = cycle.residual_norm(h, u, f) / cycle.residual_norm(h, np.zeros_like(f), f)
+        u_ref, hist = cycle.mixed_solve(h, f, tol=1e-8)
+        diff = np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))
+        print(f"request {rid} {d}d n={n}: steps {res[rid]['steps']} (oracle {len(hist) - 1}) "
+              f"relres {res[rid]['relres']:.3e} cpu {rel:.3e} vs oracle {diff:.2e}", flush=True)
+        assert res[rid]["status"] == mg.MG_OK and rel <= 1e-8
+        assert abs(rel - res[rid]["relres"]) <= 1e-6 * rel
+        assert res[rid]["steps"] == len(hist) - 1
+        assert diff <= 1e-9
+
+
+def test_small_budget_admits_within_footprint(mg):
+    """An arena that holds about two hierarchies: requests queue, the arena is
+    never overcommitted, hierarchies are evicted and rebuilt, all finish."""
+    import torch
+    reqs = [(3, 65), (2, 257), (3, 65), (3, 33), (2, 257), (3, 65)]
+    fp = max(mg.server_footprint(d, n, *method(d)) for d, n in reqs)
+    arena = 2 * fp + (1 << 20)
+    res, sols, st = run(mg, torch, reqs, list(range(len(reqs))), arena=arena, slots=8)
+    assert all(r["status"] == mg.MG_OK for r in res.values())
+    assert st["arena_peak_bytes"] <= arena
+    assert st["evictions"] >= 1
+    # same answers as with a roomy arena
+    res2, sols2, _ = run(mg, torch, reqs, list(range(len(reqs))))
+    for rid in range(len(reqs)):
+        assert np.array_equal(sols[rid], sols2[rid])
+
+
+def test_queue_limit_and_invalid_requests(mg):
+    import torch
+    srv = mg.Server(256 << 20, max_slots=2, max_queue=3)
+    f = torch.zeros((17,) * 3, dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(f)
+    codes = [srv.submit(i, 3, 17, f, u, 1e-8, mg.MG_RBGS, 3, 3) for i in range(4)]
+    assert codes[:3] == [mg.MG_OK] * 3 and codes[3] == mg.MG_EBUSY
+    assert srv.submit(9, 3, 18, f, u, 1e-8) == mg.MG_EINVAL
+    big = mg.server_footprint(3, 257, mg.MG_RBGS, 3, 3)
+    assert big > (256 << 20)
+    fb = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
+    assert srv.submit(10, 3, 257, fb, fb, 1e-8, mg.MG_RBGS, 3, 3) == mg.MG_ENOMEM
+    done = []
+    while len(done) < 3:
+        srv.step()
+        done += srv.poll()
+    assert all(r["status"] == mg.MG_OK for r in done)
+    # zero right-hand side: converged at once with a zero solution
+    u.fill_(1.0)
+    assert srv.submit(20, 3, 17, f, u, 1e-8, mg.MG_RBGS, 3, 3) == mg.MG_OK
+    out = []
+    while not out:
+        srv.step()
+        out = srv.poll()
+    torch.cuda.synchronize()
+    assert out[0]["status"] == mg.MG_OK and float(u.abs().max()) == 0.0
+    srv.close()
