@@ -71,6 +71,51 @@ def cpu_baseline(n_sample: int = 257):
                       f"({dt:.1f} s, NumPy single thread on {cpu_model()}, {os.cpu_count()} host CPUs)"}
 
 
+def other_configs(mg, W, torch, np):
+    """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound) and the
+    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10)."""
+    res = {}
+    n = 129
+    s = mg.Solver(2, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2)
+    s.set_rhs(W.sine_rhs_2d(n))
+    u0 = W.interior_uniform(n, 2, W.SEED_U0_2D)
+    s.set_initial(u0)
+    s.vcycle(10)
+    torch.cuda.synchronize()
+    reps = 20
+    t = time.perf_counter()
+    for _ in range(reps):
+        s.set_initial(u0)
+        s.vcycle(10)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    res["poisson2d_129_jacobi_10cycles"] = {"ms_per_10_cycles": round(1e3 * dt, 3),
+                                            "us_per_cycle": round(1e5 * dt, 2),
+                                            "mlups": round(127 ** 2 * 10 / dt / 1e6, 1)}
+    s.close()
+    N = 256
+    k = torch.from_numpy(W.varcoef_k(N, 3)).cuda()
+    f = torch.from_numpy(W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)).cuda()
+    for prec, name in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
+        s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, precision=prec)
+        s.set_rhs(f)
+        s.set_initial(None)
+        s.solve(1e-10)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            s.set_initial(None)
+            t = time.perf_counter()
+            code, cyc, rel = s.solve(1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        dt = min(times)
+        res[f"varcoef_cell_256_{name}"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
+                                           "status": code, "mlups": round(N ** 3 * cyc / dt / 1e6, 1)}
+        s.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +126,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--serve-count", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -175,6 +221,8 @@ def main():
                         "speedup_vs_fp64_time_to_tol": round(ms_step / ms_mx, 3),
                         "kernel_ms_total": rmx["prof"]}
     out["solves_per_s_fp64"] = round(args.steps / r64["total"], 3)
+    if not args.no_configs:
+        out["other_configs"] = other_configs(mg, W, torch, np)
     if not args.no_serve:
         print("# bench: served stream", file=sys.stderr, flush=True)
         from paper_1904_08684_amd import serve_bench

@@ -61,6 +61,8 @@ hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const doubl
                        hipStream_t st);
 hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
                          hipStream_t st);
+// Groups of four elements in one level field (both colours, padding included).
+long long field_quads(const Geom& g);
 
 // Zero `bytes` bytes (a kernel, not a memset, so the call is graph-capturable).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

@@ -76,25 +76,31 @@ __device__ __forceinline__ long long row_off(const Geom& g, int y, int z) {
 }
 
 // Fixed-order block reduction of (sum, max) over all threads of the block
-// (up to 1024; the thread count is a power of two).
+// (a power of two, at most 1024): a shuffle tree inside each wavefront, then
+// thread 0 adds the wavefront results in order.  Deterministic.
 __device__ void block_sum_max(double sq, double mx, double* out2) {
-    __shared__ double s_sq[1024];
-    __shared__ double s_mx[1024];
+    __shared__ double s_sq[16];
+    __shared__ double s_mx[16];
     const int nt = (int)(blockDim.x * blockDim.y * blockDim.z);
     const int t = (int)(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z));
-    s_sq[t] = sq;
-    s_mx[t] = mx;
-    __syncthreads();
-    for (int w = nt >> 1; w > 0; w >>= 1) {
-        if (t < w) {
-            s_sq[t] = s_sq[t] + s_sq[t + w];
-            s_mx[t] = fmax(s_mx[t], s_mx[t + w]);
-        }
-        __syncthreads();
+    const int w = nt < 64 ? nt : 64;
+    for (int o = w >> 1; o > 0; o >>= 1) {
+        sq = sq + __shfl_down(sq, o, w);
+        mx = fmax(mx, __shfl_down(mx, o, w));
     }
+    if ((t & 63) == 0) {
+        s_sq[t >> 6] = sq;
+        s_mx[t >> 6] = mx;
+    }
+    __syncthreads();
     if (t == 0) {
-        out2[0] = s_sq[0];
-        out2[1] = s_mx[0];
+        double a = s_sq[0], b = s_mx[0];
+        for (int i = 1; i < (nt + 63) / 64; ++i) {
+            a = a + s_sq[i];
+            b = fmax(b, s_mx[i]);
+        }
+        out2[0] = a;
+        out2[1] = b;
     }
 }
 
@@ -773,43 +779,59 @@ __device__ __forceinline__ double pow2_floor(double v) {
     return ldexp(1.0, e - 1);
 }
 
-__device__ __forceinline__ void d_cast(const Ex& ex, Geom g, Space sp, const double* __restrict__ r,
-                                              float* __restrict__ f32, const double* __restrict__ red,
-                                              double* __restrict__ sigma_out) {
+// The cast and the update run over whole level fields as flat streams, four
+// elements per thread: boundary nodes and row padding of r64 and of the
+// single-precision iterate are zero and stay zero, so a flat pass computes
+// the same values at every unknown as a pass over the unknowns.
+__device__ __forceinline__ void d_cast(const Ex& ex, long long n4, const double* __restrict__ r,
+                                       float* __restrict__ f32, const double* __restrict__ red,
+                                       double* __restrict__ sigma_out) {
     const double sigma = pow2_floor(red[1]);
     if (ex.b == 0 && ex.t == 0) *sigma_out = sigma;
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
-    const int par = (p.y + p.z + p.c) & 1;
-    const int x = 2 * p.xs + par;
-    if (!g.cell && (x < 1 || x > g.n - 2)) return;
-    const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
-    f32[me] = (float)(r[me] / sigma);
+    const long long i = (long long)ex.b * ex.nt + ex.t;
+    if (i >= n4) return;
+    const double2 a = reinterpret_cast<const double2*>(r)[2 * i];
+    const double2 b = reinterpret_cast<const double2*>(r)[2 * i + 1];
+    float4 o;
+    o.x = (float)(a.x / sigma);
+    o.y = (float)(a.y / sigma);
+    o.z = (float)(b.x / sigma);
+    o.w = (float)(b.y / sigma);
+    reinterpret_cast<float4*>(f32)[i] = o;
 }
 
-__global__ __launch_bounds__(256) void k_cast(Geom g, Space sp, const double* __restrict__ r,
-                                              float* __restrict__ f32, const double* __restrict__ red,
-                                              double* __restrict__ sigma_out) {
-    d_cast(solo_ex(), g, sp, r, f32, red, sigma_out);
+__global__ __launch_bounds__(256) void k_cast(long long n4, const double* __restrict__ r, float* __restrict__ f32,
+                                              const double* __restrict__ red, double* __restrict__ sigma_out) {
+    Ex ex;
+    ex.b = (int)blockIdx.x;
+    ex.t = (int)threadIdx.x;
+    ex.nt = (int)blockDim.x;
+    d_cast(ex, n4, r, f32, red, sigma_out);
 }
 
-__device__ __forceinline__ void d_update(const Ex& ex, Geom g, Space sp, double* __restrict__ u,
-                                                const float* __restrict__ c32,
-                                                const double* __restrict__ sigma_p) {
+__device__ __forceinline__ void d_update(const Ex& ex, long long n4, double* __restrict__ u,
+                                         const float* __restrict__ c32, const double* __restrict__ sigma_p) {
+    const long long i = (long long)ex.b * ex.nt + ex.t;
+    if (i >= n4) return;
     const double sigma = *sigma_p;
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
-    const int par = (p.y + p.z + p.c) & 1;
-    const int x = 2 * p.xs + par;
-    if (!g.cell && (x < 1 || x > g.n - 2)) return;
-    const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
-    u[me] = u[me] + sigma * (double)c32[me];
+    const float4 c = reinterpret_cast<const float4*>(c32)[i];
+    double2 a = reinterpret_cast<double2*>(u)[2 * i];
+    double2 b = reinterpret_cast<double2*>(u)[2 * i + 1];
+    a.x = a.x + sigma * (double)c.x;
+    a.y = a.y + sigma * (double)c.y;
+    b.x = b.x + sigma * (double)c.z;
+    b.y = b.y + sigma * (double)c.w;
+    reinterpret_cast<double2*>(u)[2 * i] = a;
+    reinterpret_cast<double2*>(u)[2 * i + 1] = b;
 }
 
-__global__ __launch_bounds__(256) void k_update(Geom g, Space sp, double* __restrict__ u,
-                                                const float* __restrict__ c32,
+__global__ __launch_bounds__(256) void k_update(long long n4, double* __restrict__ u, const float* __restrict__ c32,
                                                 const double* __restrict__ sigma_p) {
-    d_update(solo_ex(), g, sp, u, c32, sigma_p);
+    Ex ex;
+    ex.b = (int)blockIdx.x;
+    ex.t = (int)threadIdx.x;
+    ex.nt = (int)blockDim.x;
+    d_update(ex, n4, u, c32, sigma_p);
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, long long n16) {
@@ -861,8 +883,7 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
             break;
         }
         case BOP_CAST:
-            d_cast(ex, it.g, it.sp, static_cast<const double*>(it.a), static_cast<float*>(it.b), it.red,
-                   it.red + 2);
+            d_cast(ex, it.n, static_cast<const double*>(it.a), static_cast<float*>(it.b), it.red, it.red + 2);
             break;
         case BOP_GS:
         case BOP_GS_ZERO: {
@@ -924,7 +945,7 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
             d_coarse<float>(ex, it.g, static_cast<const float*>(it.a), static_cast<float*>(it.b), it.L, it.m);
             break;
         case BOP_UPDATE:
-            d_update(ex, it.g, it.sp, static_cast<double*>(it.a), static_cast<const float*>(it.b), it.red + 2);
+            d_update(ex, it.n, static_cast<double*>(it.a), static_cast<const float*>(it.b), it.red + 2);
             break;
         case BOP_UNPACK:
             d_unpack<double>(ex, it.g, it.n, static_cast<const double*>(it.a), static_cast<double*>(it.io[1]));
@@ -934,21 +955,44 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
     }
 }
 
-// Persistent: each block walks global tiles with stride gridDim.x, finds the
-// entry owning the tile and runs that tile of the entry's op.
+// Persistent: block b runs the contiguous tile range [b c, (b + 1) c) of the
+// launch, c = ceil(total / gridDim.x).  Entry prefixes sit in LDS; the
+// descriptor of the current entry is copied to LDS once and reused for all
+// consecutive tiles of that entry.
+constexpr int kBatchLds = 1024;
+
 __global__ __launch_bounds__(256) void k_batch(const BEntry* __restrict__ ent, int n, long long total) {
-    for (long long gt = blockIdx.x; gt < total; gt += gridDim.x) {
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (ent[mid].prefix <= gt) lo = mid;
-            else hi = mid - 1;
+    __shared__ long long s_pre[kBatchLds];
+    __shared__ BItem s_item;
+    const bool in_lds = n <= kBatchLds;
+    if (in_lds)
+        for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) s_pre[i] = ent[i].prefix;
+    __syncthreads();
+    const long long chunk = (total + gridDim.x - 1) / gridDim.x;
+    const long long g0 = (long long)blockIdx.x * chunk;
+    const long long g1 = g0 + chunk < total ? g0 + chunk : total;
+    long long cur_lo = 0, cur_hi = -1;
+    for (long long gt = g0; gt < g1; ++gt) {
+        if (gt >= cur_hi) {
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                const long long pm = in_lds ? s_pre[mid] : ent[mid].prefix;
+                if (pm <= gt) lo = mid;
+                else hi = mid - 1;
+            }
+            cur_lo = in_lds ? s_pre[lo] : ent[lo].prefix;
+            cur_hi = lo + 1 < n ? (in_lds ? s_pre[lo + 1] : ent[lo + 1].prefix) : total;
+            const unsigned* src = reinterpret_cast<const unsigned*>(ent[lo].item);
+            unsigned* dst = reinterpret_cast<unsigned*>(&s_item);
+            for (int i = (int)threadIdx.x; i < (int)(sizeof(BItem) / 4); i += (int)blockDim.x) dst[i] = src[i];
+            __syncthreads();
         }
         Ex ex;
-        ex.b = (int)(gt - ent[lo].prefix);
+        ex.b = (int)(gt - cur_lo);
         ex.t = (int)threadIdx.x;
         ex.nt = (int)blockDim.x;
-        run_item(*ent[lo].item, ex);
+        run_item(s_item, ex);
         __syncthreads();
     }
 }
@@ -1205,17 +1249,27 @@ hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat
     return hipGetLastError();
 }
 
+long long field_quads(const Geom& g) { return g.cs / 2; }   // 2 cs elements, 4 per thread
+
 hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* red, double* sigma,
                        hipStream_t st) {
-    const Space sp = space_of(g, 2, 0);
-    k_cast<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, r64, f32, red, sigma);
+    const long long n4 = field_quads(g);
+    k_cast<<<(unsigned)((n4 + 255) / 256), 256, 0, st>>>(n4, r64, f32, red, sigma);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
                          hipStream_t st) {
-    const Space sp = space_of(g, 2, 0);
-    k_update<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, u64, c32, sigma);
+    const long long n4 = field_quads(g);
+    k_update<<<(unsigned)((n4 + 255) / 256), 256, 0, st>>>(n4, u64, c32, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const long long n16 = (long long)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    k_zero<<<(unsigned)((n16 + 255) / 256), 256, 0, st>>>(static_cast<uint4*>(p), n16);
     return hipGetLastError();
 }
 
@@ -1226,14 +1280,6 @@ hipError_t launch_batch(const BEntry* d_entries, int n, long long total, hipStre
     // ~8 resident blocks per CU on 256 CUs; smaller batches get one block per tile
     const long long grid = total < 2048 ? total : 2048;
     k_batch<<<(unsigned)grid, 256, 0, st>>>(d_entries, n, total);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
-    if (bytes % 16) return hipErrorInvalidValue;
-    const long long n16 = (long long)(bytes / 16);
-    if (n16 == 0) return hipSuccess;
-    k_zero<<<(unsigned)((n16 + 255) / 256), 256, 0, st>>>(static_cast<uint4*>(p), n16);
     return hipGetLastError();
 }
 

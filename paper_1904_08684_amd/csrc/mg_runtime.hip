@@ -585,13 +585,15 @@ int Ctx::refine_step() {
     Level& L0 = lv[0];
     if (rec) {
         BItem ca = item(BOP_CAST, 0);
-        ca.sp = level_space(L0.g, 2, 0);
+        ca.n = field_quads(L0.g);
+        ca.tiles = (ca.n + 255) / 256;
         ca.a = L0.r[0];
         ca.b = L0.f[1];
         push(ca);
         if (int rc = vcycle(0, 1, true)) return rc;
         BItem up = item(BOP_UPDATE, 0);
-        up.sp = level_space(L0.g, 2, 0);
+        up.n = field_quads(L0.g);
+        up.tiles = (up.n + 255) / 256;
         up.a = L0.u[0];
         up.b = L0.u[1];
         return push(up);
