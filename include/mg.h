@@ -159,7 +159,9 @@ enum {
     MG_OP_RESTRICT = 4,   /* f(level+1) <- R r(level)                             */
     MG_OP_PROLONG = 5,    /* u(level) <- u(level) + P u(level+1)                  */
     MG_OP_COARSE = 6,     /* u <- A^-1 f on the coarsest level (FP64 Cholesky)    */
-    MG_OP_VCYCLE = 7      /* one V-cycle starting at `level` (u, f of that level) */
+    MG_OP_VCYCLE = 7,     /* one V-cycle starting at `level` (u, f of that level) */
+    MG_OP_RESIDUAL_RESTRICT = 8  /* f(level+1) <- R (f - A u); r is not written where a
+                                    fused kernel exists (3-D node levels with n >= 129) */
 };
 int mg_apply(mg_ctx* c, int op, int level, int prec);
 

@@ -37,6 +37,12 @@ long long residual_blocks(const Geom& g);
 hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void* r, void* fcoarse,
                            hipStream_t st);
 
+// Residual and restriction in one pass (3-D node levels with fused_transfers):
+// f_coarse = R (f - A u) without writing the fine residual.
+bool fused_transfers(const Geom& gf);
+hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, int prec, const void* u, const void* f,
+                                    void* fcoarse, double s, hipStream_t st);
+
 // u_fine += P e_coarse on the colours in `colour_mask` (bit 0 red, bit 1 black).
 hipError_t launch_prolong(const Geom& gf, const Geom& gc, int prec, void* u, const void* ec,
                           int colour_mask, hipStream_t st);

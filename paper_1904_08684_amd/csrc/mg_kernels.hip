@@ -383,6 +383,176 @@ __global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T
     if (NORM) block_sum_max(sq, mx, part + 2 * (long long)blockIdx.x);
 }
 
+// ------------------------------------ 3-D node grids, fused transfer kernels
+// Residual and full weighting in one pass.  A block owns a 32 x 8 tile of
+// coarse points (natural coordinates) and walks kFuseZ coarse planes.  For
+// each coarse plane Z it computes the fine residual on fine planes 2Z and
+// 2Z + 1 over the 65 x 17 fine tile that the coarse tile's stencils cover
+// into a three-plane LDS ring (plane 2Z - 1 is kept from the previous step)
+// and then restricts from LDS.  The fine residual is never written to HBM:
+// the pass reads u and f and writes f_coarse, 16 + 8 / 8 B per fine point.
+// Residual terms and restriction terms are evaluated in the same order as
+// the separate kernels.
+constexpr int kFuseCX = 32, kFuseCY = 8, kFuseZ = 8;
+constexpr int kFuseFX = 2 * kFuseCX + 1, kFuseFY = 2 * kFuseCY + 1;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_node_res_restrict(Geom gf, Geom gc, int ntx, int nty,
+                                                          const T* __restrict__ u, const T* __restrict__ f,
+                                                          T* __restrict__ fcoarse, T s) {
+    __shared__ T rs[3][kFuseFY][kFuseFX + 1];
+    int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int tz = b / nty;
+    const int X0 = 1 + tx * kFuseCX, Y0 = 1 + ty * kFuseCY, Z0 = 1 + tz * kFuseZ;
+    const int Z1 = min(Z0 + kFuseZ, gc.n - 1);
+    const int t = (int)threadIdx.x;
+    const T* __restrict__ R = u;
+    const T* __restrict__ B = u + gf.cs;
+    // each thread computes up to kPer points of a fine plane; all their loads
+    // are issued before any arithmetic (points outside load a safe address)
+    constexpr int kPer = (kFuseFX * kFuseFY + NT - 1) / NT;
+    auto fine_plane = [&](int z, int slot) {
+        T v[kPer][8];
+        bool ok[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = t + NT * k;
+            const int lx = i % kFuseFX, ly = i / kFuseFX;
+            const int x = 2 * X0 - 1 + lx, y = 2 * Y0 - 1 + ly;
+            ok[k] = i < kFuseFX * kFuseFY && x <= gf.n - 2 && y <= gf.n - 2;
+            const int xx = ok[k] ? x : 1, yy = ok[k] ? y : 1;
+            const int c = (xx + yy + z) & 1;
+            const long long ro = row_off(gf, yy, z) + (xx >> 1);
+            const T* __restrict__ me = c ? B : R;
+            const T* __restrict__ ot = c ? R : B;
+            const int par = xx & 1;
+            v[k][0] = ot[ro - 1 + par];
+            v[k][1] = ot[ro + par];
+            v[k][2] = ot[ro - gf.pitch];
+            v[k][3] = ot[ro + gf.pitch];
+            v[k][4] = ot[ro - gf.plane];
+            v[k][5] = ot[ro + gf.plane];
+            v[k][6] = me[ro];
+            v[k][7] = f[(long long)c * gf.cs + ro];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = t + NT * k;
+            if (i >= kFuseFX * kFuseFY) continue;
+            T r = T(0);
+            if (ok[k]) {
+                T nb = v[k][0];
+                nb = nb + v[k][1];
+                nb = nb + v[k][2];
+                nb = nb + v[k][3];
+                nb = nb + v[k][4];
+                nb = nb + v[k][5];
+                r = v[k][7] - (T(6) * v[k][6] - nb) * s;
+            }
+            rs[slot][i / kFuseFX][i % kFuseFX] = r;
+        }
+    };
+    int sa = 0, sb = 1, sc = 2;
+    fine_plane(2 * Z0 - 1, sa);
+    const int cx = t % kFuseCX, cy = t / kFuseCX;
+    const int X = X0 + cx, Y = Y0 + cy;
+    for (int Z = Z0; Z < Z1; ++Z) {
+        fine_plane(2 * Z, sb);
+        fine_plane(2 * Z + 1, sc);
+        __syncthreads();
+        if (t < kFuseCX * kFuseCY && X <= gc.n - 2 && Y <= gc.n - 2) {
+            T acc = T(0);
+            bool first = true;
+#pragma unroll
+            for (int oz = -1; oz <= 1; ++oz) {
+                const int sl = oz < 0 ? sa : (oz == 0 ? sb : sc);
+#pragma unroll
+                for (int oy = -1; oy <= 1; ++oy) {
+#pragma unroll
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int wgt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) * (2 - (oz < 0 ? -oz : oz));
+                        const T w = T(wgt) / T(64);
+                        const T term = w * rs[sl][2 * cy + 1 + oy][2 * cx + 1 + ox];
+                        acc = first ? term : acc + term;
+                        first = false;
+                    }
+                }
+            }
+            fcoarse[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)] = acc;
+        }
+        __syncthreads();
+        const int tmp = sa;   // fine plane 2Z + 1 is plane 2(Z + 1) - 1 of the next step
+        sa = sc;
+        sc = tmp;
+    }
+}
+
+// Interpolation + correction walking fine columns.  A thread owns one
+// (x >> 1, y) column of one colour; for every coarse plane Z it forms once
+// the y-interpolated values for an even and an odd fine x (the column's x
+// parity flips with z) and reuses them for the fine planes 2Z - 1 .. 2Z + 1.
+// Same evaluation order as the point kernel: x, then y, then z.
+template <typename T>
+__global__ __launch_bounds__(256) void k_node_prolong_zm(Geom gf, Geom gc, ZSpace zs, int colour,
+                                                         T* __restrict__ u, const T* __restrict__ ec) {
+    int tx, ty, tz;
+    {
+        int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+        tx = b % zs.ntx;
+        b /= zs.ntx;
+        ty = b % zs.nty;
+        tz = b / zs.nty;
+    }
+    const int xs = tx * 64 + (int)threadIdx.x;
+    const int y = 1 + ty * zs.rows + (int)threadIdx.y;
+    if (xs >= zs.xr || y > gf.n - 2) return;
+    const int z0 = 1 + tz * zs.zc;
+    const int z1 = min(z0 + zs.zc, gf.n - 1);
+    const T half = T(0.5);
+    const int Y0 = y >> 1, Y1 = (y + 1) >> 1;
+    const bool yodd = y & 1;
+    // coarse value at (X, Yc, Z), X in {xs, xs + 1}
+    auto E = [&](int X, int Yc, int Z) -> T {
+        return ec[(long long)((X + Yc + Z) & 1) * gc.cs + row_off(gc, Yc, Z) + (X >> 1)];
+    };
+    // y-interpolated values of plane Z for an even fine x (X = xs) and an odd one (X = xs, xs + 1)
+    auto plane = [&](int Z, T& ev, T& od) {
+        const T a0 = E(xs, Y0, Z), b0 = E(xs + 1, Y0, Z);
+        const T ix_e0 = a0, ix_o0 = half * (a0 + b0);
+        if (yodd) {
+            const T a1 = E(xs, Y1, Z), b1 = E(xs + 1, Y1, Z);
+            ev = half * (ix_e0 + a1);
+            od = half * (ix_o0 + half * (a1 + b1));
+        } else {
+            ev = ix_e0;
+            od = ix_o0;
+        }
+    };
+    int Zlo = z0 >> 1;
+    T lo_e, lo_o, hi_e, hi_o;
+    plane(Zlo, lo_e, lo_o);
+    plane(Zlo + 1, hi_e, hi_o);
+    long long ro = row_off(gf, y, z0) + xs + (long long)colour * gf.cs;
+    for (int z = z0; z < z1; ++z, ro += gf.plane) {
+        const int Zc = z >> 1;
+        if (Zc != Zlo) {   // advance the two-plane window by one coarse plane
+            lo_e = hi_e;
+            lo_o = hi_o;
+            Zlo = Zc;
+            plane(Zlo + 1, hi_e, hi_o);
+        }
+        const int par = (y + z + colour) & 1;
+        if (par | xs) {
+            const T v0 = par ? lo_o : lo_e;
+            const T e = (z & 1) ? half * (v0 + (par ? hi_o : hi_e)) : v0;
+            u[ro] = u[ro] + e;
+        }
+    }
+}
+
 // Full weighting: f_c[X] = sum_{o in {-1,0,1}^d} prod_a (2 - |o_a|) / 4^d r[2X + o],
 // summed with the z offset slowest and the x offset fastest.
 template <typename T, int D>
@@ -1159,6 +1329,26 @@ static hipError_t restrict_t(const Geom& gf, const Geom& gc, const void* r, void
     return hipGetLastError();
 }
 
+bool fused_transfers(const Geom& gf) { return use_zmarch(gf); }
+
+template <typename T>
+static hipError_t res_restrict_t(const Geom& gf, const Geom& gc, const void* u, const void* f, void* fco,
+                                 double s, hipStream_t st) {
+    const int ntx = (gc.n - 2 + kFuseCX - 1) / kFuseCX, nty = (gc.n - 2 + kFuseCY - 1) / kFuseCY;
+    const int ntz = (gc.n - 2 + kFuseZ - 1) / kFuseZ;
+    const unsigned nb = (unsigned)((long long)ntx * nty * ntz);
+    // 256 threads (5 fine points each) measured faster than 512 or 1024 on MI355X
+    k_node_res_restrict<T, 256><<<nb, 256, 0, st>>>(gf, gc, ntx, nty, cp<T>(u), cp<T>(f), mp<T>(fco), (T)s);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, int prec, const void* u, const void* f,
+                                    void* fcoarse, double s, hipStream_t st) {
+    if (!fused_transfers(gf)) return hipErrorInvalidValue;
+    return prec ? res_restrict_t<float>(gf, gc, u, f, fcoarse, s, st)
+                : res_restrict_t<double>(gf, gc, u, f, fcoarse, s, st);
+}
+
 hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void* r, void* fcoarse,
                            hipStream_t st) {
     return prec ? restrict_t<float>(gf, gc, r, fcoarse, st) : restrict_t<double>(gf, gc, r, fcoarse, st);
@@ -1167,6 +1357,14 @@ hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void*
 template <typename T>
 static hipError_t prolong_t(const Geom& gf, const Geom& gc, void* u, const void* ec, int mask,
                             hipStream_t st) {
+    if (use_zmarch(gf)) {
+        const ZSpace zs = make_zspace(gf);
+        for (int c = 0; c < 2; ++c)
+            if (mask & (1 << c))
+                k_node_prolong_zm<T><<<dim3((unsigned)zs.blocks()), dim3(64, zs.rows), 0, st>>>(
+                    gf, gc, zs, c, mp<T>(u), cp<T>(ec));
+        return hipGetLastError();
+    }
     const int ncol = (mask == 3) ? 2 : 1;
     const int col0 = (mask == 2) ? 1 : 0;
     const Space sp = space_of(gf, ncol, col0);

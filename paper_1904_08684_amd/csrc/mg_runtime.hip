@@ -564,8 +564,17 @@ int Ctx::coarse(int pr) {
 int Ctx::vcycle(int l, int pr, bool from_zero) {
     if (l == L - 1) return coarse(pr);
     int rc = smooth(l, pr, opts.nu1, from_zero, 0);
-    if (!rc) rc = residual(l, pr, false, true);
-    if (!rc) rc = restrict_to(l, pr);
+    if (!rc && !rec && grid.centering == MG_NODE && fused_transfers(lv[l].g)) {
+        // fine residual and full weighting in one pass; r is not written
+        hipEvent_t e0 = begin();
+        rc = record(MG_K_RESTRICT, l,
+                    launch_residual_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr], lv[l + 1].f[pr],
+                                             scale(l), stream),
+                    e0, "residual+restrict");
+    } else {
+        if (!rc) rc = residual(l, pr, false, true);
+        if (!rc) rc = restrict_to(l, pr);
+    }
     if (!rc) rc = vcycle(l + 1, pr, true);
     if (rc) return rc;
     // With red-black smoothing that starts with colour c, the corrections of
@@ -1000,6 +1009,19 @@ int mg_apply(mg_ctx* h, int op, int level, int prec) {
         case MG_OP_COARSE:
             if (level != c->L - 1) return c->fail(MG_EINVAL, "not the coarsest level");
             return c->coarse(prec);
+        case MG_OP_RESIDUAL_RESTRICT: {
+            if (!has_next) return c->fail(MG_EINVAL, "no coarser level");
+            if (c->grid.centering == MG_NODE && mg::fused_transfers(c->lv[level].g)) {
+                hipEvent_t e0 = c->begin();
+                return c->record(MG_K_RESTRICT, level,
+                                 mg::launch_residual_restrict(c->lv[level].g, c->lv[level + 1].g, prec,
+                                                              c->lv[level].u[prec], c->lv[level].f[prec],
+                                                              c->lv[level + 1].f[prec], c->scale(level), c->stream),
+                                 e0, "residual+restrict");
+            }
+            int rc = c->residual(level, prec, false, true);
+            return rc ? rc : c->restrict_to(level, prec);
+        }
         case MG_OP_VCYCLE:
             if (level < c->L - 1 && !has_next) return c->fail(MG_EINVAL, "no coarser level");
             return c->vcycle(level, prec, false);

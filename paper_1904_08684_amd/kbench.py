@@ -22,8 +22,8 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--prec", type=int, default=0, help="0 FP64 hierarchy, 1 FP32 hierarchy")
     ap.add_argument("--copy-mib", type=int, default=2048)
-    ap.add_argument("--ops", default="gs,residual,restrict,prolong,copy",
-                    help="comma list of gs, residual, restrict, prolong, copy")
+    ap.add_argument("--ops", default="gs,residual,restrict,resrestrict,prolong,copy",
+                    help="comma list of gs, residual, restrict, resrestrict, prolong, copy")
     a = ap.parse_args(argv)
 
     import torch
@@ -37,7 +37,7 @@ def main(argv=None):
     n = a.n
     unknowns = (n - 2) ** 3
     es = 8 if a.prec == 0 else 4
-    if ops & {"gs", "residual", "restrict", "prolong"}:
+    if ops & {"gs", "residual", "restrict", "resrestrict", "prolong"}:
         s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3,
                       precision=mg.MG_MIXED if a.prec else mg.MG_FP64)
         u = W.interior_uniform(n, 3, 11)
@@ -72,6 +72,10 @@ def main(argv=None):
             t = timed(mg.MG_K_RESTRICT, lambda: s.apply(mg.MG_OP_RESTRICT, 0, a.prec))
             out["restrict_ms"] = t
             out["restrict_GBps"] = es * unknowns * (1 + 1 / 8) / (t * 1e-3) / 1e9
+        if "resrestrict" in ops:
+            t = timed(mg.MG_K_RESTRICT, lambda: s.apply(mg.MG_OP_RESIDUAL_RESTRICT, 0, a.prec))
+            out["residual_restrict_ms"] = t
+            out["residual_restrict_GBps"] = es * unknowns * (2 + 1 / 8) / (t * 1e-3) / 1e9
         if "prolong" in ops:
             t = timed(mg.MG_K_PROLONG, lambda: s.apply(mg.MG_OP_PROLONG, 0, a.prec))
             out["prolong_ms"] = t

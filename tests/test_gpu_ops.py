@@ -155,3 +155,21 @@ def test_repeat_is_bitwise_deterministic(mg):
         outs.append(s.solution())
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [33, 129, 257])
+def test_fused_residual_restriction(mg, n, prec):
+    """f_coarse = R (f - A u) in one pass (fused on 3-D levels with n >= 129)
+    equals restriction of the oracle's residual."""
+    s, h = make(mg, 3, n, 0, prec, smoother=mg.MG_RBGS)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 3, 0, 700 + n, dt)
+    f = rand(n, 3, 0, 800 + n, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_RESIDUAL_RESTRICT, 0, prec)
+    got = s.level_get(1, mg.MG_FIELD_F, prec)
+    ref = node.restrict_fw(node.residual(u, f))
+    close(got, ref.astype(np.float64), prec, f"residual+restrict 3d n={n} prec={prec}")
+    s.close()
