@@ -114,4 +114,32 @@ static inline ZSpace make_zspace(const Geom& g) {
     return z;
 }
 
+// Row-marching tiling of a 2-D node level: 256-thread blocks of 64 lanes
+// over x >> 1 times `rows` row chunks; each thread walks `yc` consecutive rows
+// of its column and keeps rows y-1, y, y+1 of both colours in registers.
+struct YSpace {
+    int xr;          // xs in [0, xr)
+    int yc;          // rows per thread
+    int rows;        // row chunks per block
+    int ntx, nty;
+    long long blocks() const { return (long long)ntx * nty; }
+};
+
+constexpr int kYChunk = 16;
+constexpr int kYRows = 4;
+
+static inline bool use_ymarch(const Geom& g) {
+    return g.dim == 2 && !g.cell && (g.n - 1) / 2 >= 64;
+}
+
+static inline YSpace make_yspace(const Geom& g) {
+    YSpace y;
+    y.xr = (g.n - 1) / 2;
+    y.yc = kYChunk;
+    y.rows = kYRows;
+    y.ntx = (y.xr + 63) / 64;
+    y.nty = (g.n - 2 + y.yc * y.rows - 1) / (y.yc * y.rows);
+    return y;
+}
+
 }  // namespace mg

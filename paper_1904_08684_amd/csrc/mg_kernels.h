@@ -97,6 +97,11 @@ enum BOp : int {
     BOP_COARSE,        // FP32 in, FP64 Cholesky solve, FP32 out
     BOP_UPDATE,        // u64 += sigma * u32
     BOP_UNPACK,        // natural FP64 array at *io[1] <- u64 (split)
+    BOP_GS_M,          // FP32 GS half-sweep, 3-D column marching (zs)
+    BOP_JAC_M,         // FP32 damped Jacobi, 2-D row marching (ys)
+    BOP_JAC_ZERO_M,    // the same from a zero iterate
+    BOP_RES32_M,       // FP32 residual, marching (3-D: zs, 2-D: ys)
+    BOP_RES64_M,       // FP64 residual with per-tile partials, marching
     BOP_COUNT
 };
 
@@ -104,7 +109,10 @@ struct BItem {
     int op, dim;
     Geom g, gc;
     Space sp;
+    ZSpace zs;             // tiling of the marching forms
+    YSpace ys;
     long long tiles;       // blocks of 256 threads the op needs
+    int w;                 // work units per tile (a unit ~ 256 points) for batched scheduling
     long long n;           // elements (pack/unpack), 16-byte words (zero), pairs (reduce)
     void* a;
     void* b;
@@ -118,13 +126,14 @@ struct BItem {
     double s, omega;
 };
 
-// A batched launch: entries sorted by `prefix`, the first global tile of each.
+// A batched launch: entries sorted by `prefix`, the first global work unit of
+// each; an entry spans tiles x w units.
 struct BEntry {
     const BItem* item;
     long long prefix;
 };
 
-// Persistent batched kernel over n entries with `total` tiles in all.
+// Persistent batched kernel over n entries with `total` work units in all.
 hipError_t launch_batch(const BEntry* d_entries, int n, long long total, hipStream_t st);
 
 }  // namespace mg

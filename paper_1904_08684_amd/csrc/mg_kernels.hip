@@ -196,13 +196,11 @@ __global__ __launch_bounds__(256) void k_node_residual(Geom g, Space sp, const T
 }
 
 // ---------------------------------------------- 3-D node grids, column marching
-__device__ __forceinline__ int zm_block(const ZSpace& zs, int& tx, int& ty, int& tz) {
-    int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+__device__ __forceinline__ void zm_tile(const ZSpace& zs, int b, int& tx, int& ty, int& tz) {
     tx = b % zs.ntx;
     b /= zs.ntx;
     ty = b % zs.nty;
     tz = b / zs.nty;
-    return 0;
 }
 
 template <bool NT, typename T>
@@ -224,13 +222,13 @@ __device__ __forceinline__ void st_stream(T* p, T v) {
 // time so that U planes of loads are in flight per thread.  f and the
 // updated colour are pure streams (NT: non-temporal).
 template <typename T, int U, bool NT>
-__global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __restrict__ me,
+__device__ __forceinline__ void d_node_gs_zm(const Ex& ex, Geom g, ZSpace zs, T* __restrict__ me,
                                                      const T* __restrict__ other,
                                                      const T* __restrict__ f, T s, int colour) {
     int tx, ty, tz;
-    zm_block(zs, tx, ty, tz);
-    const int xs = tx * 64 + (int)threadIdx.x;
-    const int y = 1 + ty * zs.rows + (int)threadIdx.y;
+    zm_tile(zs, ex.b, tx, ty, tz);
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y = 1 + ty * zs.rows + (ex.t >> 6);
     if (xs >= zs.xr || y > g.n - 2) return;
     const int z0 = 1 + tz * zs.zc;
     const int z1 = min(z0 + zs.zc, g.n - 1);
@@ -290,17 +288,24 @@ __global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __res
     }
 }
 
+template <typename T, int U, bool NT>
+__global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __restrict__ me,
+                                                     const T* __restrict__ other,
+                                                     const T* __restrict__ f, T s, int colour) {
+    d_node_gs_zm<T, U, NT>(solo_ex(), g, zs, me, other, f, s, colour);
+}
+
 // r = f - A u at both colours of the thread's column; both colours' z-1, z,
 // z+1 values stay in registers, U planes per step.
 template <typename T, int U, bool NT, bool NORM, bool STORE>
-__global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T* __restrict__ u,
+__device__ __forceinline__ void d_node_res_zm(const Ex& ex, Geom g, ZSpace zs, const T* __restrict__ u,
                                                       const T* __restrict__ f, T* __restrict__ r, T s,
                                                       double* __restrict__ part) {
     double sq = 0.0, mx = 0.0;
     int tx, ty, tz;
-    zm_block(zs, tx, ty, tz);
-    const int xs = tx * 64 + (int)threadIdx.x;
-    const int y = 1 + ty * zs.rows + (int)threadIdx.y;
+    zm_tile(zs, ex.b, tx, ty, tz);
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y = 1 + ty * zs.rows + (ex.t >> 6);
     if (xs < zs.xr && y <= g.n - 2) {
         const T* __restrict__ R = u;           // red plane
         const T* __restrict__ B = u + g.cs;    // black plane
@@ -380,7 +385,143 @@ __global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T
             bc = bp;
         }
     }
-    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)blockIdx.x);
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
+template <typename T, int U, bool NT, bool NORM, bool STORE>
+__global__ __launch_bounds__(1024) void k_node_res_zm(Geom g, ZSpace zs, const T* __restrict__ u,
+                                                      const T* __restrict__ f, T* __restrict__ r, T s,
+                                                      double* __restrict__ part) {
+    d_node_res_zm<T, U, NT, NORM, STORE>(solo_ex(), g, zs, u, f, r, s, part);
+}
+
+// ------------------------------------------------ 2-D node grids, row marching
+// Damped Jacobi (both colours, out of place) and residual walking rows: lane
+// x >> 1 keeps rows y-1, y, y+1 of both colours in registers, so a row of
+// each colour is loaded once instead of three times.  Same formulas and
+// evaluation order as the point kernels (x-, x+, y-, y+).
+template <typename T, bool ZERO>
+__device__ __forceinline__ void d_node_jac_ym(const Ex& ex, Geom g, YSpace ys, const T* __restrict__ u,
+                                              const T* __restrict__ f, T* __restrict__ out, T s, T omega) {
+    const int tx = ex.b % ys.ntx, ty = ex.b / ys.ntx;
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y0 = 1 + (ty * ys.rows + (ex.t >> 6)) * ys.yc, y1 = min(y0 + ys.yc, g.n - 1);
+    if (xs >= ys.xr || y0 >= y1) return;
+    const T* __restrict__ R = u;
+    const T* __restrict__ B = u + g.cs;
+    const long long cs = g.cs, pt = g.pitch;
+    const long long xl = xs > 0 ? -1 : 0;
+    const T D = T(4) * s;
+    long long ro = (long long)y0 * pt + xs;
+    T rm = T(0), rc = T(0), bm = T(0), bc = T(0);
+    if (!ZERO) {
+        rm = R[ro - pt];
+        rc = R[ro];
+        bm = B[ro - pt];
+        bc = B[ro];
+    }
+    for (int y = y0; y < y1; ++y, ro += pt) {
+        const int pr = y & 1;   // x parity of the red point; the black one has 1 - pr
+        T rp = T(0), bp = T(0), bx = T(0), rx = T(0);
+        if (!ZERO) {
+            rp = R[ro + pt];
+            bp = B[ro + pt];
+            bx = B[ro + (pr ? 1 : xl)];
+            rx = R[ro + (pr ? xl : 1)];
+        }
+        const T fr = f[ro], fb = f[cs + ro];
+        if (pr | xs) {
+            T nb = T(0);
+            if (!ZERO) {
+                nb = pr ? bc : bx;
+                nb = nb + (pr ? bx : bc);
+                nb = nb + bm;
+                nb = nb + bp;
+            }
+            const T r = fr - (T(4) * rc - nb) * s;
+            out[ro] = rc + (omega * r) / D;
+        }
+        if ((1 - pr) | xs) {
+            T nb = T(0);
+            if (!ZERO) {
+                nb = pr ? rx : rc;
+                nb = nb + (pr ? rc : rx);
+                nb = nb + rm;
+                nb = nb + rp;
+            }
+            const T r = fb - (T(4) * bc - nb) * s;
+            out[cs + ro] = bc + (omega * r) / D;
+        }
+        rm = rc;
+        rc = rp;
+        bm = bc;
+        bc = bp;
+    }
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(256) void k_node_jac_ym(Geom g, YSpace ys, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out, T s, T omega) {
+    d_node_jac_ym<T, ZERO>(solo_ex(), g, ys, u, f, out, s, omega);
+}
+
+template <typename T, bool NORM, bool STORE>
+__device__ __forceinline__ void d_node_res_ym(const Ex& ex, Geom g, YSpace ys, const T* __restrict__ u,
+                                              const T* __restrict__ f, T* __restrict__ r, T s,
+                                              double* __restrict__ part) {
+    double sq = 0.0, mx = 0.0;
+    const int tx = ex.b % ys.ntx, ty = ex.b / ys.ntx;
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y0 = 1 + (ty * ys.rows + (ex.t >> 6)) * ys.yc, y1 = min(y0 + ys.yc, g.n - 1);
+    if (xs < ys.xr && y0 < y1) {
+        const T* __restrict__ R = u;
+        const T* __restrict__ B = u + g.cs;
+        const long long cs = g.cs, pt = g.pitch;
+        const long long xl = xs > 0 ? -1 : 0;
+        long long ro = (long long)y0 * pt + xs;
+        T rm = R[ro - pt], rc = R[ro], bm = B[ro - pt], bc = B[ro];
+        for (int y = y0; y < y1; ++y, ro += pt) {
+            const int pr = y & 1;
+            const T rp = R[ro + pt], bp = B[ro + pt];
+            const T bx = B[ro + (pr ? 1 : xl)];
+            const T rx = R[ro + (pr ? xl : 1)];
+            const T fr = f[ro], fb = f[cs + ro];
+            if (pr | xs) {
+                T nb = pr ? bc : bx;
+                nb = nb + (pr ? bx : bc);
+                nb = nb + bm;
+                nb = nb + bp;
+                const T v = fr - (T(4) * rc - nb) * s;
+                if (STORE) r[ro] = v;
+                const double dv = (double)v;
+                sq = sq + dv * dv;
+                mx = fmax(mx, fabs(dv));
+            }
+            if ((1 - pr) | xs) {
+                T nb = pr ? rx : rc;
+                nb = nb + (pr ? rc : rx);
+                nb = nb + rm;
+                nb = nb + rp;
+                const T v = fb - (T(4) * bc - nb) * s;
+                if (STORE) r[cs + ro] = v;
+                const double dv = (double)v;
+                sq = sq + dv * dv;
+                mx = fmax(mx, fabs(dv));
+            }
+            rm = rc;
+            rc = rp;
+            bm = bc;
+            bc = bp;
+        }
+    }
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
+template <typename T, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_node_res_ym(Geom g, YSpace ys, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ r, T s,
+                                                     double* __restrict__ part) {
+    d_node_res_ym<T, NORM, STORE>(solo_ex(), g, ys, u, f, r, s, part);
 }
 
 // ------------------------------------ 3-D node grids, fused transfer kernels
@@ -1120,18 +1261,55 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
         case BOP_UNPACK:
             d_unpack<double>(ex, it.g, it.n, static_cast<const double*>(it.a), static_cast<double*>(it.io[1]));
             break;
+        case BOP_GS_M:
+            d_node_gs_zm<float, 2, false>(ex, it.g, it.zs, static_cast<float*>(it.a), static_cast<const float*>(it.b),
+                                          static_cast<const float*>(it.c), (float)it.s, it.m);
+            break;
+        case BOP_JAC_M:
+            d_node_jac_ym<float, false>(ex, it.g, it.ys, static_cast<const float*>(it.a),
+                                        static_cast<const float*>(it.b), static_cast<float*>(it.c), (float)it.s,
+                                        (float)it.omega);
+            break;
+        case BOP_JAC_ZERO_M:
+            d_node_jac_ym<float, true>(ex, it.g, it.ys, static_cast<const float*>(it.a),
+                                       static_cast<const float*>(it.b), static_cast<float*>(it.c), (float)it.s,
+                                       (float)it.omega);
+            break;
+        case BOP_RES32_M:
+            if (it.dim == 3)
+                d_node_res_zm<float, 2, false, false, true>(ex, it.g, it.zs, static_cast<const float*>(it.a),
+                                                            static_cast<const float*>(it.b),
+                                                            static_cast<float*>(it.c), (float)it.s, nullptr);
+            else
+                d_node_res_ym<float, false, true>(ex, it.g, it.ys, static_cast<const float*>(it.a),
+                                                  static_cast<const float*>(it.b), static_cast<float*>(it.c),
+                                                  (float)it.s, nullptr);
+            break;
+        case BOP_RES64_M:
+            if (it.dim == 3)
+                d_node_res_zm<double, 1, false, true, true>(ex, it.g, it.zs, static_cast<const double*>(it.a),
+                                                            static_cast<const double*>(it.b),
+                                                            static_cast<double*>(it.c), it.s, it.part);
+            else
+                d_node_res_ym<double, true, true>(ex, it.g, it.ys, static_cast<const double*>(it.a),
+                                                  static_cast<const double*>(it.b), static_cast<double*>(it.c), it.s,
+                                                  it.part);
+            break;
         default:
             break;
     }
 }
 
-// Persistent: block b runs the contiguous tile range [b c, (b + 1) c) of the
-// launch, c = ceil(total / gridDim.x).  Entry prefixes sit in LDS; the
-// descriptor of the current entry is copied to LDS once and reused for all
-// consecutive tiles of that entry.
+// Persistent: block b owns the work-unit range [b c, (b + 1) c) of the launch,
+// c = ceil(total / gridDim.x), and runs every tile that starts in it.  A tile
+// of entry e covers w units, so blocks get equal work whatever mix of light
+// (one point per thread) and heavy (marching) tiles the launch holds.  Entry
+// prefixes sit in LDS; the descriptor of the current entry is copied to LDS
+// once and reused for all its tiles in the range.
 constexpr int kBatchLds = 1024;
 
-__global__ __launch_bounds__(256) void k_batch(const BEntry* __restrict__ ent, int n, long long total) {
+// at most 128 VGPRs: four waves per SIMD whatever op the launch holds
+__global__ __launch_bounds__(256, 4) void k_batch(const BEntry* __restrict__ ent, int n, long long total) {
     __shared__ long long s_pre[kBatchLds];
     __shared__ BItem s_item;
     const bool in_lds = n <= kBatchLds;
@@ -1141,29 +1319,42 @@ __global__ __launch_bounds__(256) void k_batch(const BEntry* __restrict__ ent, i
     const long long chunk = (total + gridDim.x - 1) / gridDim.x;
     const long long g0 = (long long)blockIdx.x * chunk;
     const long long g1 = g0 + chunk < total ? g0 + chunk : total;
-    long long cur_lo = 0, cur_hi = -1;
-    for (long long gt = g0; gt < g1; ++gt) {
-        if (gt >= cur_hi) {
+    long long lo_u = 0, hi_u = -1;
+    unsigned w = 1;
+    long long u = g0;
+    while (u < g1) {
+        if (u >= hi_u) {
             int lo = 0, hi = n - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 const long long pm = in_lds ? s_pre[mid] : ent[mid].prefix;
-                if (pm <= gt) lo = mid;
+                if (pm <= u) lo = mid;
                 else hi = mid - 1;
             }
-            cur_lo = in_lds ? s_pre[lo] : ent[lo].prefix;
-            cur_hi = lo + 1 < n ? (in_lds ? s_pre[lo + 1] : ent[lo + 1].prefix) : total;
+            lo_u = in_lds ? s_pre[lo] : ent[lo].prefix;
+            hi_u = lo + 1 < n ? (in_lds ? s_pre[lo + 1] : ent[lo + 1].prefix) : total;
             const unsigned* src = reinterpret_cast<const unsigned*>(ent[lo].item);
             unsigned* dst = reinterpret_cast<unsigned*>(&s_item);
+            __syncthreads();   // every thread is done with the previous descriptor
             for (int i = (int)threadIdx.x; i < (int)(sizeof(BItem) / 4); i += (int)blockDim.x) dst[i] = src[i];
             __syncthreads();
+            w = s_item.w > 1 ? (unsigned)s_item.w : 1u;
         }
+        // first tile of the entry that starts at or after u (an entry spans < 2^32 units)
+        const unsigned t = ((unsigned)(u - lo_u) + w - 1) / w;
+        const long long start = lo_u + (long long)t * w;
+        if (start >= hi_u) {
+            u = hi_u;
+            continue;
+        }
+        if (start >= g1) break;
         Ex ex;
-        ex.b = (int)(gt - cur_lo);
+        ex.b = (int)t;
         ex.t = (int)threadIdx.x;
         ex.nt = (int)blockDim.x;
         run_item(s_item, ex);
         __syncthreads();
+        u = start + w;
     }
 }
 
@@ -1226,6 +1417,16 @@ hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, co
 template <typename T>
 static hipError_t jacobi_t(const Geom& g, bool zero, const void* u, const void* f, void* out,
                            const Faces& fc, double s, double omega, hipStream_t st) {
+    if (use_ymarch(g)) {
+        const YSpace ys = make_yspace(g);
+        if (zero)
+            k_node_jac_ym<T, true><<<(unsigned)ys.blocks(), 256, 0, st>>>(g, ys, cp<T>(u), cp<T>(f), mp<T>(out),
+                                                                         (T)s, (T)omega);
+        else
+            k_node_jac_ym<T, false><<<(unsigned)ys.blocks(), 256, 0, st>>>(g, ys, cp<T>(u), cp<T>(f), mp<T>(out),
+                                                                          (T)s, (T)omega);
+        return hipGetLastError();
+    }
     const Space sp = space_of(g, 2, 0);
     if (g.cell) {
         MG_DISPATCH_DIM(g, if (zero) k_cell_jacobi<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
@@ -1250,8 +1451,8 @@ hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, cons
 }
 
 long long residual_blocks(const Geom& g) {
-    // the stand-alone path may march columns; the batched path uses one point per thread
-    const long long a = use_zmarch(g) ? make_zspace(g).blocks() : 0;
+    // the stand-alone path may march columns or rows; the batched path may use one point per thread
+    const long long a = use_zmarch(g) ? make_zspace(g).blocks() : (use_ymarch(g) ? make_yspace(g).blocks() : 0);
     const long long b = space_of(g, 2, 0).blocks();
     return a > b ? a : b;
 }
@@ -1273,6 +1474,18 @@ template <typename T>
 static hipError_t residual_t(const Geom& g, const void* u, const void* f, void* r, const Faces& fc,
                              double s, bool norm, bool store, double* part, long long* nb,
                              hipStream_t st) {
+    if (use_ymarch(g)) {
+        const YSpace ys = make_yspace(g);
+        if (nb) *nb = ys.blocks();
+        const unsigned grid = (unsigned)ys.blocks();
+        if (norm && store)
+            k_node_res_ym<T, true, true><<<grid, 256, 0, st>>>(g, ys, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        else if (norm)
+            k_node_res_ym<T, true, false><<<grid, 256, 0, st>>>(g, ys, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        else
+            k_node_res_ym<T, false, true><<<grid, 256, 0, st>>>(g, ys, cp<T>(u), cp<T>(f), mp<T>(r), (T)s, part);
+        return hipGetLastError();
+    }
     if (use_zmarch(g)) {
         const ZSpace zs = make_zspace(g);
         if (nb) *nb = zs.blocks();
@@ -1475,7 +1688,7 @@ Space level_space(const Geom& g, int ncol, int col0) { return space_of(g, ncol, 
 
 hipError_t launch_batch(const BEntry* d_entries, int n, long long total, hipStream_t st) {
     if (n < 1 || total < 1) return hipSuccess;
-    // ~8 resident blocks per CU on 256 CUs; smaller batches get one block per tile
+    // ~8 resident blocks per CU on 256 CUs; smaller batches get one block per work unit
     const long long grid = total < 2048 ? total : 2048;
     k_batch<<<(unsigned)grid, 256, 0, st>>>(d_entries, n, total);
     return hipGetLastError();

@@ -398,6 +398,7 @@ BItem Ctx::item(int op, int l) const {
 
 int Ctx::push(BItem it) {
     if (!(it.tiles > 0)) it.tiles = it.sp.blocks();
+    if (it.w < 1) it.w = 1;
     rec->push_back(it);
     return MG_OK;
 }
@@ -413,8 +414,15 @@ int Ctx::gs(int l, int pr, int colour, bool zero) {
     Level& L = lv[l];
     if (rec) {
         if (int rc = rec_check(pr, true)) return rc;
-        BItem it = item(zero ? BOP_GS_ZERO : BOP_GS, l);
+        const bool march = !zero && use_zmarch(L.g) && 64 * kZRows == 256;
+        BItem it = item(march ? BOP_GS_M : (zero ? BOP_GS_ZERO : BOP_GS), l);
         it.sp = level_space(L.g, 1, colour);
+        if (march) {
+            it.zs = make_zspace(L.g);
+            it.tiles = it.zs.blocks();
+            it.w = it.zs.zc;
+            it.m = colour;
+        }
         it.a = static_cast<float*>(L.u[pr]) + (long long)colour * L.g.cs;
         it.b = static_cast<float*>(L.u[pr]) + (long long)(1 - colour) * L.g.cs;
         it.c = static_cast<float*>(L.f[pr]) + (long long)colour * L.g.cs;
@@ -429,8 +437,14 @@ int Ctx::jacobi(int l, int pr, bool zero) {
     Level& L = lv[l];
     if (rec) {
         if (int rc = rec_check(pr, true)) return rc;
-        BItem it = item(zero ? BOP_JAC_ZERO : BOP_JAC, l);
+        const bool march = use_ymarch(L.g);
+        BItem it = item(march ? (zero ? BOP_JAC_ZERO_M : BOP_JAC_M) : (zero ? BOP_JAC_ZERO : BOP_JAC), l);
         it.sp = level_space(L.g, 2, 0);
+        if (march) {
+            it.ys = make_yspace(L.g);
+            it.tiles = it.ys.blocks();
+            it.w = 2 * it.ys.yc;
+        }
         it.a = L.u[pr];
         it.b = L.f[pr];
         it.c = L.utmp[pr];
@@ -481,8 +495,20 @@ int Ctx::residual(int l, int pr, bool norm, bool store) {
         if (pr == 0 && !(norm && store)) return fail(MG_EINVAL, "batched FP64 residual carries its norm");
         if (pr == 1 && norm) return fail(MG_EINVAL, "batched FP32 residual has no norm");
         if (grid.centering != MG_NODE) return fail(MG_EINVAL, "batched execution supports node grids");
-        BItem it = item(pr == 0 ? BOP_RES64 : BOP_RES32, l);
+        const bool zm = use_zmarch(L.g) && 64 * kZRows == 256, ym = use_ymarch(L.g);
+        BItem it = item(zm || ym ? (pr == 0 ? BOP_RES64_M : BOP_RES32_M) : (pr == 0 ? BOP_RES64 : BOP_RES32), l);
         it.sp = level_space(L.g, 2, 0);
+        if (zm) {
+            it.zs = make_zspace(L.g);
+            it.tiles = it.zs.blocks();
+            it.w = 2 * it.zs.zc;
+        } else if (ym) {
+            it.ys = make_yspace(L.g);
+            it.tiles = it.ys.blocks();
+            it.w = 2 * it.ys.yc;
+        } else {
+            it.tiles = it.sp.blocks();
+        }
         it.a = L.u[pr];
         it.b = L.f[pr];
         it.c = L.r[pr];
@@ -491,7 +517,7 @@ int Ctx::residual(int l, int pr, bool norm, bool store) {
         if (pr == 0) {
             BItem rd = item(BOP_REDUCE, l);
             rd.part = partials;
-            rd.n = it.sp.blocks();
+            rd.n = it.tiles;
             rd.res = rec_res;
             rd.tiles = 1;
             push(rd);

@@ -107,7 +107,7 @@ struct Hier {
     Ctx* ctx = nullptr;
     int slot = -1;                    // row of the I/O and result tables
     BItem* d_items = nullptr;
-    std::vector<long long> tiles;     // per item
+    std::vector<long long> units;     // per item: tiles x work units per tile
     std::vector<int> first[2];        // a new request's first round, by step parity
     std::vector<int> step[2];         // one refinement step, by parity (Jacobi buffer swaps)
     int unpack = -1;
@@ -321,8 +321,11 @@ struct Server {
         }
         if (items.size() > items_bound(&c->grid, &c->opts) || h->first[0].size() > (size_t)kMaxProgram)
             return fail(MG_EINVAL, "program larger than its bound");
-        h->tiles.clear();
-        for (const BItem& it : items) h->tiles.push_back(it.tiles);
+        h->units.clear();
+        for (BItem& it : items) {
+            if (it.w < 1) it.w = 1;
+            h->units.push_back(it.tiles * it.w);
+        }
         h->d_items = reinterpret_cast<BItem*>(base + head_bytes + h->off + h->ctx_bytes);
         rc = dev(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, st),
                  "upload program");
@@ -381,7 +384,7 @@ struct Server {
                 const int idx = (*progs[j])[k];
                 h_entries[ne].item = hs[j]->d_items + idx;
                 h_entries[ne].prefix = l.total;
-                l.total += hs[j]->tiles[(size_t)idx];
+                l.total += hs[j]->units[(size_t)idx];
                 ++l.count;
                 ++ne;
             }
