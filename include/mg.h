@@ -160,8 +160,13 @@ enum {
     MG_OP_PROLONG = 5,    /* u(level) <- u(level) + P u(level+1)                  */
     MG_OP_COARSE = 6,     /* u <- A^-1 f on the coarsest level (FP64 Cholesky)    */
     MG_OP_VCYCLE = 7,     /* one V-cycle starting at `level` (u, f of that level) */
-    MG_OP_RESIDUAL_RESTRICT = 8  /* f(level+1) <- R (f - A u); r is not written where a
+    MG_OP_RESIDUAL_RESTRICT = 8, /* f(level+1) <- R (f - A u); r is not written where a
                                     fused kernel exists (3-D node levels with n >= 129) */
+    MG_OP_PRESMOOTH = 9,  /* u <- nu1 smoothing sweeps, as the V-cycle's pre-smoothing
+                             (red-black: red first); on 3-D node levels with
+                             n >= 257 up to three red-black sweeps run as one fused
+                             pass, bitwise equal to the separate half-sweeps     */
+    MG_OP_POSTSMOOTH = 10 /* u <- nu2 sweeps, as the post-smoothing (post_order)     */
 };
 int mg_apply(mg_ctx* c, int op, int level, int prec);
 

@@ -142,4 +142,49 @@ static inline YSpace make_yspace(const Geom& g) {
     return y;
 }
 
+// Temporally blocked red-black GS on a 3-D node level: a block owns a region
+// of 64 x (16 R) positions (x >> 1, y) with a halo of ceil(S/2) positions in
+// x >> 1 and S rows in y, and marches z over a chunk of `zc` output planes
+// plus S planes of wavefront lead-in and lead-out on either side.
+struct TbSpace {
+    int S, R;
+    int ntx, nty, ntz, zc;
+    long long blocks() const { return (long long)ntx * nty * ntz; }
+};
+
+constexpr int kTbLanes = 64;
+constexpr int kTbWaves = 16;
+
+static inline bool use_tb(const Geom& g) {
+    return g.dim == 3 && !g.cell && g.n >= 257;
+}
+
+static inline TbSpace make_tbspace(const Geom& g, int S, int R) {
+    TbSpace t;
+    t.S = S;
+    t.R = R;
+    const int H = (S + 1) / 2;
+    t.ntx = (g.half + kTbLanes - 2 * H - 1) / (kTbLanes - 2 * H);
+    const int ry = kTbWaves * R - 2 * S;
+    t.nty = (g.n + ry - 1) / ry;
+    // one resident block per CU: pick the chunk length that minimises
+    // (rounds of 256 blocks) x (wavefront steps per block)
+    const int planes = g.n - 2;
+    long long best = -1;
+    t.zc = planes;
+    t.ntz = 1;
+    for (int c = 1; c <= 64; ++c) {
+        const int zc = (planes + c - 1) / c;
+        const int nz = (planes + zc - 1) / zc;
+        const long long nb = (long long)t.ntx * t.nty * nz;
+        const long long cost = ((nb + 255) / 256) * (zc + 2 * S);
+        if (best < 0 || cost < best) {
+            best = cost;
+            t.zc = zc;
+            t.ntz = nz;
+        }
+    }
+    return t;
+}
+
 }  // namespace mg

@@ -19,6 +19,11 @@ struct Faces {
 // zero: every neighbour is known to be zero (first sweep from a zero guess).
 hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, const void* f,
                      const Faces& fc, double s, hipStream_t st);
+// 1 to 3 fused red-black sweeps (2 sweeps half-sweeps, colours first_colour,
+// 1 - first_colour, ...) on a level where use_tb holds, from u (zero: from a
+// zero iterate, u not read) into out; out's boundary and padding must be zero.
+hipError_t launch_gs_tb(const Geom& g, int prec, int sweeps, int first_colour, bool zero, const void* u,
+                        const void* f, void* out, double s, hipStream_t st);
 
 // Damped Jacobi: out = u + (omega r) / (diag s), out of place.
 hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, const void* f, void* out,

@@ -12,6 +12,7 @@
 // order) and the library is compiled with -ffp-contract=off, so each
 // operation rounds exactly as the written formula does.
 
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include "mg_kernels.h"
@@ -522,6 +523,123 @@ __global__ __launch_bounds__(256) void k_node_res_ym(Geom g, YSpace ys, const T*
                                                      const T* __restrict__ f, T* __restrict__ r, T s,
                                                      double* __restrict__ part) {
     d_node_res_ym<T, NORM, STORE>(solo_ex(), g, ys, u, f, r, s, part);
+}
+
+// ------------------------------------------ 3-D node grids, temporal blocking
+// S red-black half-sweeps (colours c1, 1 - c1, c1, ...) fused into one pass.
+// Half-sweep k updates its colour from half-sweep k - 1's values of the other
+// colour (k = 0: the iterate), so the pass runs as a wavefront in z: at step
+// t, stage 0 loads plane t of the other colour and stage k updates plane t - k.
+// Each block owns a region of 64 positions (x >> 1) by 16 R rows; stage k's
+// current plane sits in LDS for the x and y neighbours of stage k + 1, the
+// z neighbours stay in registers (planes p - 1, p, p + 1 of each stage at the
+// thread's own position).  Values near the region edge go stale one point
+// per stage, so only positions at least ceil(S/2) columns and S rows inside
+// are written; neighbouring regions overlap by that halo.  Every point takes
+// the same operands in the same order as the one-colour kernels, so the
+// result is bitwise that of S separate half-sweeps.  The output goes to a
+// second buffer (a neighbouring block may still read the iterate); both
+// colours of every interior node are written, boundary nodes stay zero.
+template <typename T, int S, int R, bool P2>
+__global__ __launch_bounds__(1024) void k_node_gs_tb(Geom g, TbSpace ts, const T* __restrict__ uin,
+                                                     const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
+                                                     int c1, int zero) {
+    constexpr int W = kTbLanes, RY = kTbWaves * R, LP = W + 2, LR = RY + 2, H = (S + 1) / 2;
+    __shared__ T lds[S][LR][LP];
+    {
+        T* lf = &lds[0][0][0];
+        for (int i = (int)threadIdx.x; i < S * LR * LP; i += (int)blockDim.x) lf[i] = T(0);
+    }
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tx = b % ts.ntx, ty = (b / ts.ntx) % ts.nty, tz = b / (ts.ntx * ts.nty);
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    const int n = g.n;
+    const int xg = tx * (W - 2 * H) - H + lane;
+    const int Z0 = 1 + tz * ts.zc, Z1 = min(Z0 + ts.zc, n - 1);
+    const int c0 = 1 - c1;
+    const long long cs = g.cs, pl = g.plane;
+    int yg[R];
+    bool yin[R], outp[R];
+    long long ro[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int ly = wv * R + r;
+        yg[r] = ty * (RY - 2 * S) - S + ly;
+        const bool inreg = xg >= 0 && xg < g.half && yg[r] >= 0 && yg[r] < n;
+        yin[r] = inreg && yg[r] >= 1 && yg[r] <= n - 2;
+        outp[r] = inreg && lane >= H && lane < W - H && ly >= S && ly < RY - S;
+        ro[r] = yin[r] ? (long long)yg[r] * g.pitch + xg : 0;
+    }
+    // is the colour-c point of row r on plane p an unknown?
+    auto inside = [&](int r, int p, int c) -> bool {
+        const int x = 2 * xg + ((yg[r] + p + c) & 1);
+        return yin[r] && x >= 1 && x <= n - 2 && p >= 1 && p <= n - 2;
+    };
+    // element offset of that point, or 0 (a harmless address) when it is none
+    auto at = [&](int r, int p, int c) -> long long { return inside(r, p, c) ? c * cs + p * pl + ro[r] : 0; };
+    // Operands of the coming step are loaded one step ahead: qu = iterate on
+    // plane t (stage 0), qf[k - 1] = right-hand side of stage k on plane t - k.
+    T qu[R], qf[S][R];
+    T old[S][R], cur[S][R];
+    const int t0 = Z0 - S;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        qu[r] = zero ? T(0) : uin[at(r, t0, c0)];
+#pragma unroll
+        for (int k = 1; k <= S; ++k) qf[k - 1][r] = f[at(r, t0 - k, (c1 + k - 1) & 1)];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            old[k][r] = T(0);
+            cur[k][r] = T(0);
+        }
+    }
+    __syncthreads();
+    for (int t = t0; t < Z1 + S; ++t) {
+        // stage k's plane t - 1 - k becomes visible to stage k + 1
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[k][1 + wv * R + r][1 + lane] = cur[k][r];
+        __syncthreads();
+        T nw[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            nw[r] = inside(r, t, c0) ? qu[r] : T(0);
+            if (!zero) qu[r] = uin[at(r, t + 1, c0)];
+        }
+#pragma unroll
+        for (int k = 1; k <= S; ++k) {
+            const int p = t - k, ck = (c1 + k - 1) & 1;
+            const bool zout = k >= S - 1 && p >= Z0 && p < Z1;
+            T nk[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int ly = wv * R + r;
+                const int par = (yg[r] + p + ck) & 1;
+                const T xn = lds[k - 1][1 + ly][lane + 2 * par];   // x >> 1 - 1 + 2 par
+                const T own = cur[k - 1][r];
+                T nb = par ? own : xn;
+                nb = nb + (par ? xn : own);
+                nb = nb + lds[k - 1][ly][1 + lane];
+                nb = nb + lds[k - 1][2 + ly][1 + lane];
+                nb = nb + old[k - 1][r];
+                nb = nb + nw[r];
+                const T fv = qf[k - 1][r];
+                qf[k - 1][r] = f[at(r, p + 1, ck)];
+                // s is a power of two when P2: f * (1 / s) rounds exactly as f / s
+                const T v = inside(r, p, ck) ? ((P2 ? fv * rs : fv / s) + nb) / T(6) : T(0);
+                if (zout && outp[r] && inside(r, p, ck)) uout[ck * cs + p * pl + ro[r]] = v;
+                nk[r] = v;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                old[k - 1][r] = cur[k - 1][r];
+                cur[k - 1][r] = nw[r];
+                nw[r] = nk[r];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------ 3-D node grids, fused transfer kernels
@@ -1412,6 +1530,44 @@ hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, co
                      const Faces& fc, double s, hipStream_t st) {
     return prec ? gs_t<float>(g, colour, zero, u, f, fc, s, st)
                 : gs_t<double>(g, colour, zero, u, f, fc, s, st);
+}
+
+template <typename T, int S, int R>
+static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void* f, void* out, double s,
+                         hipStream_t st) {
+    const TbSpace ts = make_tbspace(g, S, R);
+    const dim3 grid((unsigned)ts.blocks()), block(1024);
+    int e;
+    const bool p2 = s > 0.0 && std::frexp(s, &e) == 0.5;   // s = 2^(e - 1)
+    if (p2)
+        k_node_gs_tb<T, S, R, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
+                                                             (T)(1.0 / s), c1, z);
+    else
+        k_node_gs_tb<T, S, R, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
+                                                              (T)(1.0 / s), c1, z);
+}
+
+template <typename T>
+static hipError_t gs_tb_t(const Geom& g, int sweeps, int c1, bool zero, const void* u, const void* f, void* out,
+                          double s, hipStream_t st) {
+    // rows per thread: registers (two planes of every stage per row) and LDS
+    // (one plane of every stage) both grow with S x R
+    constexpr int R46 = sizeof(T) == 8 ? 2 : 3;
+    const int z = zero ? 1 : 0;
+    switch (sweeps) {
+        case 1: gs_tb_launch<T, 2, 3>(g, c1, z, u, f, out, s, st); break;
+        case 2: gs_tb_launch<T, 4, R46>(g, c1, z, u, f, out, s, st); break;
+        case 3: gs_tb_launch<T, 6, R46>(g, c1, z, u, f, out, s, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_tb(const Geom& g, int prec, int sweeps, int first_colour, bool zero, const void* u,
+                        const void* f, void* out, double s, hipStream_t st) {
+    if (!use_tb(g) || sweeps < 1 || sweeps > 3 || (first_colour & ~1)) return hipErrorInvalidValue;
+    return prec ? gs_tb_t<float>(g, sweeps, first_colour, zero, u, f, out, s, st)
+                : gs_tb_t<double>(g, sweeps, first_colour, zero, u, f, out, s, st);
 }
 
 template <typename T>

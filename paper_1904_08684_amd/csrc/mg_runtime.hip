@@ -132,7 +132,10 @@ size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, 
             lp.u[pr] = take(fb);
             lp.f[pr] = take(fb);
             lp.r[pr] = take(fb);
-            const bool need_tmp = jac && !(mixed && pr == 0);
+            // a second iterate: Jacobi's output, or the out-of-place target of
+            // fused red-black sweeps on large 3-D node levels
+            const bool smoothed = !(mixed && pr == 0);
+            const bool need_tmp = smoothed && (jac || (!cell && use_tb(lp.g)));
             lp.utmp[pr] = need_tmp ? take(fb) : SIZE_MAX;
             for (int a = 0; a < 3; ++a)
                 lp.beta[pr][a] = (varcoef && a < g->dim) ? take((size_t)lp.g.fsize * es) : SIZE_MAX;
@@ -474,6 +477,23 @@ int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
         hipEvent_t e0 = begin();
         int rc = record(MG_K_COPY, l, launch_zero(L.u[pr], L.field_bytes[pr], stream), e0, "zero");
         if (rc) return rc;
+    }
+    if (opts.smoother == MG_RBGS && !rec && sweeps > 0 && L.utmp[pr] && use_tb(L.g)) {
+        // up to three sweeps per pass, out of place
+        bool z = from_zero;
+        for (int left = sweeps; left > 0;) {
+            const int k = left < 3 ? left : 3;
+            hipEvent_t e0 = begin();
+            int rc = record(MG_K_SMOOTH, l,
+                            launch_gs_tb(L.g, pr, k, first_colour, z, L.u[pr], L.f[pr], L.utmp[pr], scale(l),
+                                         stream),
+                            e0, "gs_tb");
+            if (rc) return rc;
+            std::swap(L.u[pr], L.utmp[pr]);
+            left -= k;
+            z = false;
+        }
+        return MG_OK;
     }
     for (int k = 0; k < sweeps; ++k) {
         const bool z = from_zero && k == 0;
@@ -1051,6 +1071,8 @@ int mg_apply(mg_ctx* h, int op, int level, int prec) {
         case MG_OP_VCYCLE:
             if (level < c->L - 1 && !has_next) return c->fail(MG_EINVAL, "no coarser level");
             return c->vcycle(level, prec, false);
+        case MG_OP_PRESMOOTH: return c->smooth(level, prec, c->opts.nu1, false, 0);
+        case MG_OP_POSTSMOOTH: return c->smooth(level, prec, c->opts.nu2, false, c->opts.post_order);
         default: return c->fail(MG_EINVAL, "unknown op");
     }
 }

@@ -67,7 +67,7 @@ def test_c0_ten_jacobi_cycles_per_iterate(mg):
     s.close()
 
 
-@pytest.mark.parametrize("n,cycles", [(33, 4), (65, 3), (129, 2)])
+@pytest.mark.parametrize("n,cycles", [(33, 4), (65, 3), (129, 2), (257, 1)])
 def test_3d_rbgs_per_iterate(mg, n, cycles):
     f = W.interior_uniform(n, 3, W.SEED_F_3D)
     s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
@@ -168,6 +168,25 @@ def test_mixed_precision_matches_oracle(mg, dim, n, cent):
     assert abs(steps - (len(hist_ref) - 1)) <= 1
     assert rel_max(u, u_ref) <= 1e-9
     s.close()
+
+
+def test_mixed_step_257_matches_oracle(mg):
+    """One refinement step at 257^3 (the single-precision V-cycle smooths the
+    finest level with fused passes, the first from a zero iterate) against
+    the oracle's first step."""
+    n = 257
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, precision=mg.MG_MIXED)
+    s.set_rhs(f)
+    s.set_initial(None)
+    s.vcycle(1)
+    u = s.solution()
+    s.close()
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3))
+    u_ref, hist = cycle.mixed_solve(h, f, tol=0.0, max_outer=1)
+    err = rel_max(u, u_ref)
+    print(f"mixed step n={n}: max rel diff {err:.3e} (oracle relres after step {hist[-1]:.3e})", flush=True)
+    assert len(hist) == 2 and err <= 1e-6
 
 
 def test_solver_reports_nonconvergence_and_resume(mg):

@@ -173,3 +173,34 @@ def test_fused_residual_restriction(mg, n, prec):
     ref = node.restrict_fw(node.residual(u, f))
     close(got, ref.astype(np.float64), prec, f"residual+restrict 3d n={n} prec={prec}")
     s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nu,post", [(1, 0), (2, 0), (3, 0), (3, 1)])
+def test_fused_sweeps_equal_half_sweeps(mg, prec, nu, post):
+    """On 3-D node levels with n >= 257 the smoother runs up to three red-black
+    sweeps as one temporally blocked pass: bitwise equal to the separate
+    half-sweeps on the same level, and to the oracle's sweeps to the op bar."""
+    n = 257
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=nu, nu2=nu, post_order=post,
+                  precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 3, 0, 900 + 10 * nu + post, dt)
+    f = rand(n, 3, 0, 950 + 10 * nu + post, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_POSTSMOOTH if post else mg.MG_OP_PRESMOOTH, 0, prec)
+    fused = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    first, second = (mg.MG_OP_GS_BLACK, mg.MG_OP_GS_RED) if post else (mg.MG_OP_GS_RED, mg.MG_OP_GS_BLACK)
+    for _ in range(nu):
+        s.apply(first, 0, prec)
+        s.apply(second, 0, prec)
+    halves = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.close()
+    assert np.array_equal(fused, halves), f"nu={nu} post={post} prec={prec}"
+    ref = u.copy()
+    for _ in range(nu):
+        node.gs_colour(ref, f, post)
+        node.gs_colour(ref, f, 1 - post)
+    close(fused, ref.astype(np.float64), prec, f"fused {nu} sweeps 3d n={n} post={post} prec={prec}")
