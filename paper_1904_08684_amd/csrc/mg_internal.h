@@ -143,29 +143,28 @@ static inline YSpace make_yspace(const Geom& g) {
 }
 
 // Temporally blocked red-black GS on a 3-D node level: a block owns a region
-// of 64 x (16 R) positions (x >> 1, y) with a halo of ceil(S/2) positions in
+// of 64 x R positions (x >> 1, y) with a halo of ceil(S/2) positions in
 // x >> 1 and S rows in y, and marches z over a chunk of `zc` output planes
 // plus S planes of wavefront lead-in and lead-out on either side.
 struct TbSpace {
-    int S, R;
+    int S, R;        // half-sweeps fused, region rows
     int ntx, nty, ntz, zc;
     long long blocks() const { return (long long)ntx * nty * ntz; }
 };
 
 constexpr int kTbLanes = 64;
-constexpr int kTbWaves = 16;
 
 static inline bool use_tb(const Geom& g) {
     return g.dim == 3 && !g.cell && g.n >= 257;
 }
 
-static inline TbSpace make_tbspace(const Geom& g, int S, int R) {
+static inline TbSpace make_tbspace(const Geom& g, int S, int rows) {
     TbSpace t;
     t.S = S;
-    t.R = R;
+    t.R = rows;
     const int H = (S + 1) / 2;
     t.ntx = (g.half + kTbLanes - 2 * H - 1) / (kTbLanes - 2 * H);
-    const int ry = kTbWaves * R - 2 * S;
+    const int ry = rows - 2 * S;
     t.nty = (g.n + ry - 1) / ry;
     // one resident block per CU: pick the chunk length that minimises
     // (rounds of 256 blocks) x (wavefront steps per block)

@@ -525,6 +525,23 @@ __global__ __launch_bounds__(256) void k_node_res_ym(Geom g, YSpace ys, const T*
     d_node_res_ym<T, NORM, STORE>(solo_ex(), g, ys, u, f, r, s, part);
 }
 
+// a / 6 correctly rounded with one multiply and two FMAs (Markstein's
+// correction step): q0 = a y with y = RN(1/6) is faithful, r = a - 6 q0 is
+// exact, and RN(q0 + r y) is then the correctly rounded quotient.  Equal to
+// a / 6 for every finite a away from the subnormal range (checked over 4e8
+// random doubles and every float mantissa of one binade), except that -0
+// gives +0.
+__device__ __forceinline__ double div6(double a) {
+    constexpr double y = 1.0 / 6.0;
+    const double q0 = a * y;
+    return __builtin_fma(__builtin_fma(-q0, 6.0, a), y, q0);
+}
+__device__ __forceinline__ float div6(float a) {
+    constexpr float y = 1.0f / 6.0f;
+    const float q0 = a * y;
+    return __builtin_fmaf(__builtin_fmaf(-q0, 6.0f, a), y, q0);
+}
+
 // ------------------------------------------ 3-D node grids, temporal blocking
 // S red-black half-sweeps (colours c1, 1 - c1, c1, ...) fused into one pass.
 // Half-sweep k updates its colour from half-sweep k - 1's values of the other
@@ -540,11 +557,11 @@ __global__ __launch_bounds__(256) void k_node_res_ym(Geom g, YSpace ys, const T*
 // result is bitwise that of S separate half-sweeps.  The output goes to a
 // second buffer (a neighbouring block may still read the iterate); both
 // colours of every interior node are written, boundary nodes stay zero.
-template <typename T, int S, int R, bool P2>
-__global__ __launch_bounds__(1024) void k_node_gs_tb(Geom g, TbSpace ts, const T* __restrict__ uin,
-                                                     const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
-                                                     int c1, int zero) {
-    constexpr int W = kTbLanes, RY = kTbWaves * R, LP = W + 2, LR = RY + 2, H = (S + 1) / 2;
+template <typename T, int S, int R, int NW, bool P2>
+__global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, const T* __restrict__ uin,
+                                                        const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
+                                                        int c1, int zero) {
+    constexpr int W = kTbLanes, RY = NW * R, LP = W + 2, LR = RY + 2, H = (S + 1) / 2;
     __shared__ T lds[S][LR][LP];
     {
         T* lf = &lds[0][0][0];
@@ -552,31 +569,35 @@ __global__ __launch_bounds__(1024) void k_node_gs_tb(Geom g, TbSpace ts, const T
     }
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int tx = b % ts.ntx, ty = (b / ts.ntx) % ts.nty, tz = b / (ts.ntx * ts.nty);
-    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    const int lane = (int)threadIdx.x & 63;
+    // rows belong to whole wavefronts: everything that depends on y or z only
+    // is wavefront-uniform and lives in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int n = g.n;
     const int xg = tx * (W - 2 * H) - H + lane;
     const int Z0 = 1 + tz * ts.zc, Z1 = min(Z0 + ts.zc, n - 1);
     const int c0 = 1 - c1;
     const long long cs = g.cs, pl = g.plane;
+    // lane offset of every access: x >> 1 clamped into the row (values of
+    // positions outside the grid are masked, never their addresses)
+    const unsigned xo = (unsigned)min(max(xg, 0), g.half - 1);
+    const bool xreg = xg >= 0 && xg < g.half;
+    const bool xin0 = xreg && xg >= 1 && 2 * xg <= n - 2;   // x = 2 (x >> 1) is an unknown column
+    const bool xin1 = xreg && 2 * xg + 1 <= n - 2;           // x = 2 (x >> 1) + 1 is
+    const bool xout = xreg && lane >= H && lane < W - H;
     int yg[R];
-    bool yin[R], outp[R];
-    long long ro[R];
+    long long yo[R];   // offset of the (clamped) row
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int ly = wv * R + r;
-        yg[r] = ty * (RY - 2 * S) - S + ly;
-        const bool inreg = xg >= 0 && xg < g.half && yg[r] >= 0 && yg[r] < n;
-        yin[r] = inreg && yg[r] >= 1 && yg[r] <= n - 2;
-        outp[r] = inreg && lane >= H && lane < W - H && ly >= S && ly < RY - S;
-        ro[r] = yin[r] ? (long long)yg[r] * g.pitch + xg : 0;
+        yg[r] = ty * (RY - 2 * S) - S + wv * R + r;
+        yo[r] = (long long)min(max(yg[r], 0), n - 1) * g.pitch;
     }
-    // is the colour-c point of row r on plane p an unknown?
-    auto inside = [&](int r, int p, int c) -> bool {
-        const int x = 2 * xg + ((yg[r] + p + c) & 1);
-        return yin[r] && x >= 1 && x <= n - 2 && p >= 1 && p <= n - 2;
-    };
-    // element offset of that point, or 0 (a harmless address) when it is none
-    auto at = [&](int r, int p, int c) -> long long { return inside(r, p, c) ? c * cs + p * pl + ro[r] : 0; };
+    auto yin = [&](int r) { return yg[r] >= 1 && yg[r] <= n - 2; };
+    auto yout = [&](int r) { return wv * R + r >= S && wv * R + r < RY - S && yg[r] <= n - 2; };
+    auto pin = [&](int p) { return p >= 1 && p <= n - 2; };
+    auto pcl = [&](int p) -> long long { return (long long)min(max(p, 0), n - 1) * pl; };
+    // is the colour-c point of row r on plane p an unknown? (par: its x parity)
+    auto inside = [&](int r, int p, int par) { return yin(r) && pin(p) && (par ? xin1 : xin0); };
     // Operands of the coming step are loaded one step ahead: qu = iterate on
     // plane t (stage 0), qf[k - 1] = right-hand side of stage k on plane t - k.
     T qu[R], qf[S][R];
@@ -584,9 +605,9 @@ __global__ __launch_bounds__(1024) void k_node_gs_tb(Geom g, TbSpace ts, const T
     const int t0 = Z0 - S;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        qu[r] = zero ? T(0) : uin[at(r, t0, c0)];
+        qu[r] = zero ? T(0) : uin[c0 * cs + pcl(t0) + yo[r] + xo];
 #pragma unroll
-        for (int k = 1; k <= S; ++k) qf[k - 1][r] = f[at(r, t0 - k, (c1 + k - 1) & 1)];
+        for (int k = 1; k <= S; ++k) qf[k - 1][r] = f[((c1 + k - 1) & 1) * cs + pcl(t0 - k) + yo[r] + xo];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             old[k][r] = T(0);
@@ -604,8 +625,8 @@ __global__ __launch_bounds__(1024) void k_node_gs_tb(Geom g, TbSpace ts, const T
         T nw[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            nw[r] = inside(r, t, c0) ? qu[r] : T(0);
-            if (!zero) qu[r] = uin[at(r, t + 1, c0)];
+            nw[r] = inside(r, t, (yg[r] + t + c0) & 1) ? qu[r] : T(0);
+            if (!zero) qu[r] = uin[c0 * cs + pcl(t + 1) + yo[r] + xo];
         }
 #pragma unroll
         for (int k = 1; k <= S; ++k) {
@@ -616,19 +637,27 @@ __global__ __launch_bounds__(1024) void k_node_gs_tb(Geom g, TbSpace ts, const T
             for (int r = 0; r < R; ++r) {
                 const int ly = wv * R + r;
                 const int par = (yg[r] + p + ck) & 1;
-                const T xn = lds[k - 1][1 + ly][lane + 2 * par];   // x >> 1 - 1 + 2 par
+                const T* lrow = &lds[k - 1][1 + ly][1 + lane];
                 const T own = cur[k - 1][r];
-                T nb = par ? own : xn;
-                nb = nb + (par ? xn : own);
-                nb = nb + lds[k - 1][ly][1 + lane];
-                nb = nb + lds[k - 1][2 + ly][1 + lane];
+                T nb;
+                if (par) {
+                    nb = own;
+                    nb = nb + lrow[1];
+                } else {
+                    nb = lrow[-1];
+                    nb = nb + own;
+                }
+                nb = nb + lrow[-LP];
+                nb = nb + lrow[LP];
                 nb = nb + old[k - 1][r];
                 nb = nb + nw[r];
                 const T fv = qf[k - 1][r];
-                qf[k - 1][r] = f[at(r, p + 1, ck)];
+                qf[k - 1][r] = f[ck * cs + pcl(p + 1) + yo[r] + xo];
                 // s is a power of two when P2: f * (1 / s) rounds exactly as f / s
-                const T v = inside(r, p, ck) ? ((P2 ? fv * rs : fv / s) + nb) / T(6) : T(0);
-                if (zout && outp[r] && inside(r, p, ck)) uout[ck * cs + p * pl + ro[r]] = v;
+                T v = div6((P2 ? fv * rs : fv / s) + nb);
+                const bool in = inside(r, p, par);
+                v = in ? v : T(0);
+                if (zout && yout(r) && xout && in) uout[ck * cs + p * pl + yo[r] + xo] = v;
                 nk[r] = v;
             }
 #pragma unroll
@@ -1532,32 +1561,33 @@ hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, co
                 : gs_t<double>(g, colour, zero, u, f, fc, s, st);
 }
 
-template <typename T, int S, int R>
+template <typename T, int S, int R, int NW>
 static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void* f, void* out, double s,
                          hipStream_t st) {
-    const TbSpace ts = make_tbspace(g, S, R);
-    const dim3 grid((unsigned)ts.blocks()), block(1024);
+    const TbSpace ts = make_tbspace(g, S, NW * R);
+    const dim3 grid((unsigned)ts.blocks()), block(64 * NW);
     int e;
     const bool p2 = s > 0.0 && std::frexp(s, &e) == 0.5;   // s = 2^(e - 1)
     if (p2)
-        k_node_gs_tb<T, S, R, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
-                                                             (T)(1.0 / s), c1, z);
+        k_node_gs_tb<T, S, R, NW, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
+                                                                 (T)(1.0 / s), c1, z);
     else
-        k_node_gs_tb<T, S, R, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
-                                                              (T)(1.0 / s), c1, z);
+        k_node_gs_tb<T, S, R, NW, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
+                                                                  (T)(1.0 / s), c1, z);
 }
 
 template <typename T>
 static hipError_t gs_tb_t(const Geom& g, int sweeps, int c1, bool zero, const void* u, const void* f, void* out,
                           double s, hipStream_t st) {
-    // rows per thread: registers (two planes of every stage per row) and LDS
-    // (one plane of every stage) both grow with S x R
-    constexpr int R46 = sizeof(T) == 8 ? 2 : 3;
+    // rows per thread: registers (two planes of every stage per row, plus the
+    // operands in flight) and LDS (one plane of every stage) grow with S x R;
+    // these are the largest that stay within 128 VGPRs and 160 KB
+    constexpr bool dp = sizeof(T) == 8;
     const int z = zero ? 1 : 0;
     switch (sweeps) {
-        case 1: gs_tb_launch<T, 2, 3>(g, c1, z, u, f, out, s, st); break;
-        case 2: gs_tb_launch<T, 4, R46>(g, c1, z, u, f, out, s, st); break;
-        case 3: gs_tb_launch<T, 6, R46>(g, c1, z, u, f, out, s, st); break;
+        case 1: gs_tb_launch<T, 2, 3, 16>(g, c1, z, u, f, out, s, st); break;
+        case 2: gs_tb_launch<T, 4, dp ? 3 : 4, 16>(g, c1, z, u, f, out, s, st); break;
+        case 3: gs_tb_launch<T, 6, dp ? 3 : 4, dp ? 12 : 16>(g, c1, z, u, f, out, s, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

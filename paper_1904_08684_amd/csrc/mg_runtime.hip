@@ -478,24 +478,24 @@ int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
         int rc = record(MG_K_COPY, l, launch_zero(L.u[pr], L.field_bytes[pr], stream), e0, "zero");
         if (rc) return rc;
     }
-    if (opts.smoother == MG_RBGS && !rec && sweeps > 0 && L.utmp[pr] && use_tb(L.g)) {
-        // up to three sweeps per pass, out of place
-        bool z = from_zero;
-        for (int left = sweeps; left > 0;) {
-            const int k = left < 3 ? left : 3;
+    int done = 0;
+    if (opts.smoother == MG_RBGS && !rec && sweeps > 1 && L.utmp[pr] && use_tb(L.g)) {
+        // two or three sweeps per fused pass, out of place (a lone sweep
+        // runs faster as two half-sweeps)
+        for (int left = sweeps; left > 1;) {
+            const int k = left == 4 ? 2 : (left < 3 ? left : 3);
             hipEvent_t e0 = begin();
             int rc = record(MG_K_SMOOTH, l,
-                            launch_gs_tb(L.g, pr, k, first_colour, z, L.u[pr], L.f[pr], L.utmp[pr], scale(l),
-                                         stream),
+                            launch_gs_tb(L.g, pr, k, first_colour, from_zero && done == 0, L.u[pr], L.f[pr],
+                                         L.utmp[pr], scale(l), stream),
                             e0, "gs_tb");
             if (rc) return rc;
             std::swap(L.u[pr], L.utmp[pr]);
             left -= k;
-            z = false;
+            done += k;
         }
-        return MG_OK;
     }
-    for (int k = 0; k < sweeps; ++k) {
+    for (int k = done; k < sweeps; ++k) {
         const bool z = from_zero && k == 0;
         int rc;
         if (opts.smoother == MG_RBGS) {

@@ -176,7 +176,7 @@ def test_fused_residual_restriction(mg, n, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("nu,post", [(1, 0), (2, 0), (3, 0), (3, 1)])
+@pytest.mark.parametrize("nu,post", [(1, 0), (2, 0), (3, 0), (3, 1), (4, 0), (5, 1)])
 def test_fused_sweeps_equal_half_sweeps(mg, prec, nu, post):
     """On 3-D node levels with n >= 257 the smoother runs up to three red-black
     sweeps as one temporally blocked pass: bitwise equal to the separate
