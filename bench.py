@@ -8,8 +8,10 @@ V-cycles inside FP64 iterative refinement) is timed beside it.
 
 Prints one JSON line.  ``value`` is V-cycle MLUpS of the FP64 solve
 (finest interior unknowns x V-cycles / time).  ``roofline`` covers the
-dominant kernel (the finest-level red-black half-sweep), timed live with HIP
-events on the library's stream over the timed solves.
+dominant kernel (the finest-level fused pass of three red-black sweeps),
+timed live with HIP events on the library's stream over the timed solves.
+``vcycle_roofline`` relates a whole V-cycle to the compulsory HBM bytes of
+the plain (unfused) operation sequence: 222 B per finest unknown in FP64.
 """
 from __future__ import annotations
 
@@ -36,7 +38,7 @@ def kernel_source_hash() -> str:
 def traffic_record(n: int):
     """HBM bytes of the dominant kernel from committed rocprofv3 counter runs,
     valid only while the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", f"gs_sweep_{n}cubed_counters.json")
+    path = os.path.join(ROOT, "profiles", f"gs_fused_{n}cubed_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -189,17 +191,28 @@ def main():
     mlups = unknowns * cyc_total / r64["total"] / 1e6
     c0, ms0 = r64["fine_smooth"]
     avg_ms = ms0 / c0
-    # one red-black half-sweep on the finest level reads the other colour and
-    # f of its own colour and writes its own colour: 24 B per updated point
-    bytes_per_launch = 24.0 * unknowns / 2
+    # one fused pass of three red-black sweeps on the finest level reads one
+    # colour of the iterate and both colours of f and writes both colours of
+    # the new iterate: (4 + 8 + 8) B per unknown in FP64
+    bytes_per_launch = 20.0 * unknowns
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traf = traffic_record(n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": (traf["hbm_bytes_per_launch"] if traf else None),
-                "kernel": "finest-level red-black Gauss-Seidel half-sweep (k_node_gs_zm<double, 2, true>)",
+                "kernel": "finest-level fused pass of three red-black GS sweeps (k_node_gs_tb<double, 6, 3, 12, true>)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": c0,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "halfsweep_equivalent_GBps": round(6 * 12.0 * unknowns / (avg_ms * 1e-3) / 1e9, 1)}
+    # whole V-cycle against the plain operation sequence: per level 2 (nu1 + nu2)
+    # half-sweeps x 12 B, residual 24 B, restriction 9 B, interpolation and
+    # correction 17 B per unknown (194 B), summed over levels (x 8/7)
+    vc_bytes = 194.0 * 8.0 / 7.0 * unknowns
+    vc_ms = 1e3 * r64["total"] / cyc_total
+    vcycle_roofline = {"bound": "hbm", "unfused_compulsory_bytes_per_cycle": round(vc_bytes),
+                       "ms_per_cycle": round(vc_ms, 4),
+                       "achieved": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUpS", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -210,6 +223,7 @@ def main():
                       "n": n, "unknowns": unknowns, "tol": args.tol,
                       "cycles_per_solve": r64["cycles"][0], "final_relres": r64["rels"][-1]},
            "roofline": roofline,
+           "vcycle_roofline": vcycle_roofline,
            "kernel_ms_total": r64["prof"]}
     if not args.no_mixed:
         print("# bench: mixed precision", file=sys.stderr, flush=True)
