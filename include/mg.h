@@ -127,13 +127,21 @@ int mg_get_solution(mg_ctx* c, double* u, int on_device);
 
 /* -------------------------------------------------------------- compute */
 /* Enqueue ncycles V(nu1,nu2)-cycles on the stream (MG_MIXED: ncycles FP64
- * refinement steps, each with one single-precision V-cycle); asynchronous. */
+ * refinement steps, each with one single-precision V-cycle); asynchronous.
+ * Each cycle is replayed from a captured HIP graph unless profiling is on. */
 int mg_vcycle(mg_ctx* c, int ncycles);
 
 /* Cycle until ||f - A u||_2 / ||f - A u0||_2 <= tol over the unknowns;
  * synchronous.  Returns MG_OK, MG_ENOTCONV, MG_ENONFINITE or MG_EDIVERGED;
- * cycles_out / relres_out may be NULL. */
+ * cycles_out / relres_out may be NULL.  Each iteration (cycle or refinement
+ * step, then the residual norm) is captured once as a HIP graph on a private
+ * stream and replayed on the context's stream; the results are those of the
+ * same launches issued one by one.  While profiling is enabled, or if
+ * capture is unavailable, the launches are issued one by one. */
 int mg_solve(mg_ctx* c, double tol, int* cycles_out, double* relres_out);
+
+/* Number of graph replays mg_solve and mg_vcycle have made on this context. */
+int mg_graph_launches(const mg_ctx* c, long long* n);
 
 /* ||f - A u||_2 over the unknowns of the finest level (FP64); synchronous. */
 int mg_residual_norm(mg_ctx* c, double* out);

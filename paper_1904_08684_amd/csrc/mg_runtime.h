@@ -112,6 +112,34 @@ struct Ctx {
     int norm(double* out);
     int step(int k);
     int solve(double tol, int* cycles_out, double* relres_out);
+
+    // One solve iteration (a V-cycle, or a refinement step in mixed mode)
+    // followed by the residual norm, replayed from a captured HIP graph when
+    // profiling is off: the ~100 launches of a cycle cost one graph launch.
+    // Operations swap level buffers on the host (Jacobi and fused sweeps run
+    // out of place), so a graph is keyed by the buffer assignment it was
+    // captured from and restores the assignment it leaves.
+    // With profiling on the launches are issued one by one, bracketed by
+    // events (elapsed times of events recorded by graph nodes are not
+    // available from the runtime).
+    struct Graph {
+        int kind = 0;   // 0: iteration + norm copied to h_red (mg_solve); 1: one step (mg_vcycle)
+        std::vector<void*> pre, post;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap_stream = nullptr;
+    double* h_red = nullptr;    // pinned copy of red[0..1] written by the graph
+    bool graphs_off = false;
+    long long graph_launches = 0;
+    void add_times(const std::vector<Rec>& rs);
+    std::vector<void*> buffers() const;
+    void set_buffers(const std::vector<void*>& b);
+    const Graph* capture(int kind);
+    const Graph* replayable(int kind);
+    int iterate(double* nr);
+    int step_once();
+    ~Ctx();
 };
 
 }  // namespace mg

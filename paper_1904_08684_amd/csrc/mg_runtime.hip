@@ -687,17 +687,138 @@ int Ctx::norm(double* out) {
 }
 
 int Ctx::step(int k) {
-    for (int i = 0; i < k; ++i) {
-        int rc;
-        if (opts.precision == MG_MIXED) {
-            rc = residual(0, 0, true, true);
-            if (!rc) rc = refine_step();
-        } else {
-            rc = vcycle(0, 0, false);
-        }
-        if (rc) return rc;
-    }
+    for (int i = 0; i < k; ++i)
+        if (int rc = step_once()) return rc;
     return MG_OK;
+}
+
+std::vector<void*> Ctx::buffers() const {
+    std::vector<void*> b;
+    for (const Level& v : lv)
+        for (int pr = 0; pr < 2; ++pr) {
+            b.push_back(v.u[pr]);
+            b.push_back(v.utmp[pr]);
+        }
+    return b;
+}
+
+void Ctx::set_buffers(const std::vector<void*>& b) {
+    size_t i = 0;
+    for (Level& v : lv)
+        for (int pr = 0; pr < 2; ++pr) {
+            v.u[pr] = b[i++];
+            v.utmp[pr] = b[i++];
+        }
+}
+
+const Ctx::Graph* Ctx::capture(int kind) {
+    if (graphs.size() >= 8) return nullptr;
+    if (!cap_stream) {
+        if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            cap_stream = nullptr;
+            return nullptr;
+        }
+        if (hipHostMalloc(reinterpret_cast<void**>(&h_red), 16, hipHostMallocDefault) != hipSuccess) {
+            h_red = nullptr;
+            return nullptr;
+        }
+    }
+    const bool mixed = opts.precision == MG_MIXED;
+    const std::vector<void*> pre = buffers();
+    if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    hipStream_t user = stream;
+    stream = cap_stream;
+    int rc;
+    if (kind == 0) {
+        rc = mixed ? refine_step() : vcycle(0, 0, false);
+        if (!rc) rc = residual(0, 0, true, mixed);
+        if (!rc) rc = dev(hipMemcpyAsync(h_red, red, 16, hipMemcpyDeviceToHost, stream), "norm copy");
+    } else {
+        rc = mixed ? residual(0, 0, true, true) : MG_OK;
+        if (!rc) rc = mixed ? refine_step() : vcycle(0, 0, false);
+    }
+    stream = user;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cap_stream, &g);
+    Graph gr;
+    gr.kind = kind;
+    gr.pre = pre;
+    gr.post = buffers();
+    // nothing ran yet: the host-side buffer assignment goes back to `pre`
+    set_buffers(pre);
+    bool ok = rc == MG_OK && ec == hipSuccess && g != nullptr &&
+              hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ok) {
+        if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+        err.clear();
+        return nullptr;
+    }
+    graphs.push_back(std::move(gr));
+    return &graphs.back();
+}
+
+void Ctx::add_times(const std::vector<Rec>& rs) {
+    for (const Rec& r : rs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) continue;
+        const int lvl = r.level < 0 ? kMaxLevels - 1 : r.level;
+        agg_ms[r.kclass][lvl] += t;
+        agg_n[r.kclass][lvl] += 1;
+    }
+}
+
+// the graph of `kind` for the current buffer assignment (captured on first
+// use), or null when launches are to be issued one by one
+const Ctx::Graph* Ctx::replayable(int kind) {
+    if (prof || graphs_off) return nullptr;
+    const std::vector<void*> cur = buffers();
+    for (const Graph& x : graphs)
+        if (x.kind == kind && x.pre == cur) return &x;
+    const Graph* gr = capture(kind);
+    if (!gr) graphs_off = true;   // capture unavailable: issue launches from now on
+    return gr;
+}
+
+int Ctx::step_once() {
+    if (const Graph* gr = replayable(1)) {
+        int rc = dev(hipGraphLaunch(gr->exec, stream), "graph launch");
+        if (rc) return rc;
+        ++graph_launches;
+        set_buffers(gr->post);
+        return MG_OK;
+    }
+    if (opts.precision == MG_MIXED) {
+        int rc = residual(0, 0, true, true);
+        return rc ? rc : refine_step();
+    }
+    return vcycle(0, 0, false);
+}
+
+int Ctx::iterate(double* nr) {
+    {
+        const Graph* gr = replayable(0);
+        if (gr) {
+            int rc = dev(hipGraphLaunch(gr->exec, stream), "graph launch");
+            if (!rc) rc = dev(hipStreamSynchronize(stream), "sync");
+            if (rc) return rc;
+            ++graph_launches;
+            set_buffers(gr->post);
+            *nr = std::sqrt(h_red[0]);
+            return MG_OK;
+        }
+    }
+    int rc = opts.precision == MG_MIXED ? refine_step() : vcycle(0, 0, false);
+    if (!rc) rc = norm(nr);
+    return rc;
+}
+
+Ctx::~Ctx() {
+    for (Graph& g : graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (h_red) (void)hipHostFree(h_red);
 }
 
 int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
@@ -716,12 +837,10 @@ int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
             err = "max_cycles reached";
             break;
         }
-        rc = opts.precision == MG_MIXED ? refine_step() : vcycle(0, 0, false);
+        double nr;
+        rc = iterate(&nr);
         if (rc) return rc;
         ++cycles;
-        double nr;
-        rc = norm(&nr);
-        if (rc) return rc;
         const double prev = rel;
         rel = nr / r0;
         hist.push_back(rel);
@@ -1094,13 +1213,7 @@ int mg_profile_read(mg_ctx* h, int kclass, int level, int* count, double* ms) {
     if (!c || kclass < 0 || kclass >= MG_K_COUNT || level < -1 || level >= mg::kMaxLevels) return MG_EINVAL;
     int rc = c->dev(hipStreamSynchronize(c->stream), "sync");
     if (rc) return rc;
-    for (const mg::Rec& r : c->recs) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) continue;
-        const int lvl = r.level < 0 ? mg::kMaxLevels - 1 : r.level;
-        c->agg_ms[r.kclass][lvl] += t;
-        c->agg_n[r.kclass][lvl] += 1;
-    }
+    c->add_times(c->recs);
     c->recs.clear();
     c->ev_used = 0;
     double s = 0.0;
@@ -1112,6 +1225,13 @@ int mg_profile_read(mg_ctx* h, int kclass, int level, int* count, double* ms) {
         }
     if (count) *count = n;
     if (ms) *ms = s;
+    return MG_OK;
+}
+
+int mg_graph_launches(const mg_ctx* h, long long* n) {
+    const Ctx* c = reinterpret_cast<const Ctx*>(h);
+    if (!c || !n) return MG_EINVAL;
+    *n = c->graph_launches;
     return MG_OK;
 }
 

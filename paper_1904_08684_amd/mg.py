@@ -79,6 +79,7 @@ _sigs = {
     "mg_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
     "mg_profile": (C.c_int, [_P, C.c_int]),
     "mg_profile_read": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_int), _D]),
+    "mg_graph_launches": (C.c_int, [_P, C.POINTER(C.c_longlong)]),
     "mg_strerror": (C.c_char_p, [C.c_int]),
     "mg_last_error": (C.c_char_p, [_P]),
 }
@@ -257,6 +258,11 @@ class Solver:
         ms = C.c_double()
         _check(mg_profile_read(self.ctx, kclass, level, C.byref(n), C.byref(ms)), self.ctx)
         return n.value, ms.value
+
+    def graph_launches(self) -> int:
+        n = C.c_longlong()
+        _check(mg_graph_launches(self.ctx, C.byref(n)), self.ctx)
+        return n.value
 
     def close(self):
         if getattr(self, "ctx", None):

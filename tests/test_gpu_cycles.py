@@ -268,3 +268,61 @@ def test_full_size_513_properties(mg, precision):
     rates = [hist[i + 1] / hist[i] for i in range(1, len(hist) - 1)]
     assert max(rates) < 0.12, rates
     s.close()
+
+
+@pytest.mark.parametrize("dim,n,sm,nu1,nu2,precision", [
+    (3, 65, "rbgs", 3, 3, "fp64"),
+    (3, 65, "rbgs", 3, 3, "mixed"),
+    (2, 129, "jacobi", 1, 2, "fp64"),     # three buffer swaps per level: two graphs alternate
+    (3, 257, "rbgs", 3, 3, "fp64"),      # fused sweeps run out of place
+])
+def test_graph_replay_equals_eager(mg, dim, n, sm, nu1, nu2, precision):
+    """mg_solve and mg_vcycle replay each iteration from a captured HIP graph;
+    after k iterations the iterate and the residual history equal k cycles
+    issued launch by launch (profiling on) bitwise."""
+    k = 4
+    f = W.interior_uniform(n, dim, W.SEED_F_3D)
+    smoother = mg.MG_RBGS if sm == "rbgs" else mg.MG_JACOBI
+    prec = mg.MG_MIXED if precision == "mixed" else mg.MG_FP64
+
+    def make():
+        s = mg.Solver(dim, n, smoother=smoother, omega=0.8, nu1=nu1, nu2=nu2, precision=prec, max_cycles=k)
+        s.set_rhs(f)
+        s.set_initial(None)
+        return s
+
+    eager = make()
+    eager.profile(True)   # launches issued one by one
+    r0 = eager.residual_norm()
+    hist_e = [1.0]
+    for _ in range(k):
+        eager.vcycle(1)
+        hist_e.append(eager.residual_norm() / r0)
+    u_e = eager.solution()
+    assert eager.graph_launches() == 0
+    eager.close()
+    for mode in ("solve", "solve-profiled", "vcycle"):
+        s = make()
+        if mode == "solve-profiled":
+            s.profile(True)
+        if mode == "vcycle":
+            s.vcycle(k)
+            hist = None
+        else:
+            code, cyc, rel = s.solve(0.0)
+            assert code == mg.MG_ENOTCONV and cyc == k
+            hist = s.history()
+        assert s.graph_launches() == (0 if mode == "solve-profiled" else k)
+        if mode == "solve-profiled":
+            cnt, ms = s.profile_read(mg.MG_K_SMOOTH, -1)
+            assert cnt > 0 and ms > 0.0
+        u = s.solution()
+        # the context keeps working after graph replays (no stale error state)
+        s.set_initial(None)
+        assert s.residual_norm() > 0.0
+        s.close()
+        print(f"graph {dim}d n={n} {sm} V({nu1},{nu2}) {precision} {mode}: bitwise {np.array_equal(u, u_e)}",
+              flush=True)
+        assert np.array_equal(u, u_e)
+        if hist is not None:
+            assert hist == hist_e
