@@ -557,7 +557,7 @@ __device__ __forceinline__ float div6(float a) {
 // result is bitwise that of S separate half-sweeps.  The output goes to a
 // second buffer (a neighbouring block may still read the iterate); both
 // colours of every interior node are written, boundary nodes stay zero.
-template <typename T, int S, int R, int NW, bool P2>
+template <typename T, int S, int R, int NW, int PF, bool P2>
 __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, const T* __restrict__ uin,
                                                         const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
                                                         int c1, int zero) {
@@ -598,16 +598,18 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
     auto pcl = [&](int p) -> long long { return (long long)min(max(p, 0), n - 1) * pl; };
     // is the colour-c point of row r on plane p an unknown? (par: its x parity)
     auto inside = [&](int r, int p, int par) { return yin(r) && pin(p) && (par ? xin1 : xin0); };
-    // Operands of the coming step are loaded one step ahead: qu = iterate on
-    // plane t (stage 0), qf[k - 1] = right-hand side of stage k on plane t - k.
-    T qu[R], qf[S][R];
+    // Operands that come from HBM are loaded one step ahead: qu = iterate on
+    // plane t (stage 0), qf[k - 1] = right-hand side of stage k <= PF on plane
+    // t - k (stages 1 and 2 touch a plane of f first; later stages re-read
+    // it from L2 where it is used).
+    T qu[R], qf[PF][R];
     T old[S][R], cur[S][R];
     const int t0 = Z0 - S;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         qu[r] = zero ? T(0) : uin[c0 * cs + pcl(t0) + yo[r] + xo];
 #pragma unroll
-        for (int k = 1; k <= S; ++k) qf[k - 1][r] = f[((c1 + k - 1) & 1) * cs + pcl(t0 - k) + yo[r] + xo];
+        for (int k = 1; k <= PF; ++k) qf[k - 1][r] = f[((c1 + k - 1) & 1) * cs + pcl(t0 - k) + yo[r] + xo];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             old[k][r] = T(0);
@@ -651,8 +653,13 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
                 nb = nb + lrow[LP];
                 nb = nb + old[k - 1][r];
                 nb = nb + nw[r];
-                const T fv = qf[k - 1][r];
-                qf[k - 1][r] = f[ck * cs + pcl(p + 1) + yo[r] + xo];
+                T fv;
+                if (k <= PF) {
+                    fv = qf[k - 1][r];
+                    qf[k - 1][r] = f[ck * cs + pcl(p + 1) + yo[r] + xo];
+                } else {
+                    fv = f[ck * cs + pcl(p) + yo[r] + xo];
+                }
                 // s is a power of two when P2: f * (1 / s) rounds exactly as f / s
                 T v = div6((P2 ? fv * rs : fv / s) + nb);
                 const bool in = inside(r, p, par);
@@ -1561,7 +1568,7 @@ hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, co
                 : gs_t<double>(g, colour, zero, u, f, fc, s, st);
 }
 
-template <typename T, int S, int R, int NW>
+template <typename T, int S, int R, int NW, int PF>
 static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void* f, void* out, double s,
                          hipStream_t st) {
     const TbSpace ts = make_tbspace(g, S, NW * R);
@@ -1569,10 +1576,10 @@ static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void
     int e;
     const bool p2 = s > 0.0 && std::frexp(s, &e) == 0.5;   // s = 2^(e - 1)
     if (p2)
-        k_node_gs_tb<T, S, R, NW, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
+        k_node_gs_tb<T, S, R, NW, PF, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
                                                                  (T)(1.0 / s), c1, z);
     else
-        k_node_gs_tb<T, S, R, NW, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
+        k_node_gs_tb<T, S, R, NW, PF, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
                                                                   (T)(1.0 / s), c1, z);
 }
 
@@ -1585,9 +1592,9 @@ static hipError_t gs_tb_t(const Geom& g, int sweeps, int c1, bool zero, const vo
     constexpr bool dp = sizeof(T) == 8;
     const int z = zero ? 1 : 0;
     switch (sweeps) {
-        case 1: gs_tb_launch<T, 2, 3, 16>(g, c1, z, u, f, out, s, st); break;
-        case 2: gs_tb_launch<T, 4, dp ? 3 : 4, 16>(g, c1, z, u, f, out, s, st); break;
-        case 3: gs_tb_launch<T, 6, dp ? 3 : 4, dp ? 12 : 16>(g, c1, z, u, f, out, s, st); break;
+        case 1: gs_tb_launch<T, 2, 3, 16, 2>(g, c1, z, u, f, out, s, st); break;
+        case 2: gs_tb_launch<T, 4, dp ? 3 : 4, 16, 4>(g, c1, z, u, f, out, s, st); break;
+        case 3: gs_tb_launch<T, 6, dp ? 3 : 4, dp ? 12 : 16, 6>(g, c1, z, u, f, out, s, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
