@@ -679,109 +679,161 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
 }
 
 // ------------------------------------ 3-D node grids, fused transfer kernels
-// Residual and full weighting in one pass.  A block owns a 32 x 8 tile of
-// coarse points (natural coordinates) and walks kFuseZ coarse planes.  For
-// each coarse plane Z it computes the fine residual on fine planes 2Z and
-// 2Z + 1 over the 65 x 17 fine tile that the coarse tile's stencils cover
-// into a three-plane LDS ring (plane 2Z - 1 is kept from the previous step)
-// and then restricts from LDS.  The fine residual is never written to HBM:
-// the pass reads u and f and writes f_coarse, 16 + 8 / 8 B per fine point.
-// Residual terms and restriction terms are evaluated in the same order as
-// the separate kernels.
-constexpr int kFuseCX = 32, kFuseCY = 8, kFuseZ = 8;
-constexpr int kFuseFX = 2 * kFuseCX + 1, kFuseFY = 2 * kFuseCY + 1;
-
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_node_res_restrict(Geom gf, Geom gc, int ntx, int nty,
-                                                          const T* __restrict__ u, const T* __restrict__ f,
-                                                          T* __restrict__ fcoarse, T s) {
-    __shared__ T rs[3][kFuseFY][kFuseFX + 1];
-    int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tx = b % ntx;
-    b /= ntx;
-    const int ty = b % nty;
-    const int tz = b / nty;
-    const int X0 = 1 + tx * kFuseCX, Y0 = 1 + ty * kFuseCY, Z0 = 1 + tz * kFuseZ;
-    const int Z1 = min(Z0 + kFuseZ, gc.n - 1);
-    const int t = (int)threadIdx.x;
-    const T* __restrict__ R = u;
-    const T* __restrict__ B = u + gf.cs;
-    // each thread computes up to kPer points of a fine plane; all their loads
-    // are issued before any arithmetic (points outside load a safe address)
-    constexpr int kPer = (kFuseFX * kFuseFY + NT - 1) / NT;
-    auto fine_plane = [&](int z, int slot) {
-        T v[kPer][8];
-        bool ok[kPer];
+// Residual and full weighting in one pass, marching fine planes.  A block of
+// NW wavefronts owns 64 positions of x >> 1 (fine x 126 tx .. 126 tx + 127)
+// by 32 fine rows and the coarse points I0 .. I0 + 62, J0 .. J0 + 14 whose
+// 3 x 3 fine footprints lie inside.  Each thread owns an (x >> 1, y) column of
+// both colours for R rows and keeps the iterate on planes z - 1, z, z + 1 in
+// registers; the fine residual of plane z goes to one LDS plane, from which
+// every coarse point adds its nine terms of that plane: planes arrive in the
+// order z offset -1, 0, +1, so the 27 terms are accumulated in the same order
+// as by the separate kernels and only one residual plane is ever held.  The
+// fine residual is never written: the pass reads u and f and writes
+// f_coarse, 16 + 8 / 8 B per fine point.
+constexpr int kRrCX = 63;                  // coarse points per region in x
+template <typename T, int R, int NW>
+__global__ __launch_bounds__(64 * NW, 4) void k_node_res_restrict_zm(Geom gf, Geom gc, int ntx, int nty, int kc,
+                                                                  const T* __restrict__ u, const T* __restrict__ f,
+                                                                  T* __restrict__ fcoarse, T s) {
+    constexpr int RY = NW * R, CY = (RY - 1) / 2, NQ = kRrCX * CY;
+    constexpr int NT = 64 * NW, QP = (NQ + NT - 1) / NT;
+    // two residual planes: plane z is restricted from one while plane z + 1
+    // is written to the other, so one barrier per plane suffices
+    __shared__ T rpl[2][RY][2 * 64 + 2];
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int n = gf.n;
+    const int xs = kRrCX * tx + lane;
+    const int yb = 2 * CY * ty + 1;
+    const int K0 = 1 + tz * kc, K1 = min(K0 + kc, gc.n - 1);
+    const int I0 = 1 + kRrCX * tx, J0 = 1 + CY * ty;
+    const T* __restrict__ RD = u;            // red (even x + y + z) points
+    const T* __restrict__ BK = u + gf.cs;    // black points
+    const bool xreg = xs < gf.half;
+    int yg[R];
+    bool rowin[R];
+    long long ro[R];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int i = t + NT * k;
-            const int lx = i % kFuseFX, ly = i / kFuseFX;
-            const int x = 2 * X0 - 1 + lx, y = 2 * Y0 - 1 + ly;
-            ok[k] = i < kFuseFX * kFuseFY && x <= gf.n - 2 && y <= gf.n - 2;
-            const int xx = ok[k] ? x : 1, yy = ok[k] ? y : 1;
-            const int c = (xx + yy + z) & 1;
-            const long long ro = row_off(gf, yy, z) + (xx >> 1);
-            const T* __restrict__ me = c ? B : R;
-            const T* __restrict__ ot = c ? R : B;
-            const int par = xx & 1;
-            v[k][0] = ot[ro - 1 + par];
-            v[k][1] = ot[ro + par];
-            v[k][2] = ot[ro - gf.pitch];
-            v[k][3] = ot[ro + gf.pitch];
-            v[k][4] = ot[ro - gf.plane];
-            v[k][5] = ot[ro + gf.plane];
-            v[k][6] = me[ro];
-            v[k][7] = f[(long long)c * gf.cs + ro];
+    for (int r = 0; r < R; ++r) {
+        yg[r] = yb + wv * R + r;
+        rowin[r] = xreg && yg[r] <= n - 1;
+        ro[r] = rowin[r] ? (long long)yg[r] * gf.pitch + xs : 0;
+    }
+    // iterate of both colours on planes z - 1, z, z + 1 of the thread's rows,
+    // and the right-hand side of plane z, loaded one plane ahead
+    T rm[R], rc[R], rn[R], bm[R], bc[R], bn[R], fr[R], fb[R];
+    const int zf0 = 2 * K0 - 1, zf1 = 2 * K1 - 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long a = ro[r] + (long long)(zf0 - 1) * gf.plane, c = a + gf.plane;
+        rm[r] = rowin[r] ? RD[a] : T(0);
+        bm[r] = rowin[r] ? BK[a] : T(0);
+        rc[r] = rowin[r] ? RD[c] : T(0);
+        bc[r] = rowin[r] ? BK[c] : T(0);
+        fr[r] = rowin[r] ? f[c] : T(0);
+        fb[r] = rowin[r] ? f[gf.cs + c] : T(0);
+    }
+    // coarse points of this thread and their open accumulations
+    T acc[QP];
+#pragma unroll
+    for (int q = 0; q < QP; ++q) acc[q] = T(0);
+    for (int z = zf0; z <= zf1; ++z) {
+        T(*rp)[2 * 64 + 2] = rpl[z & 1];
+        const bool zin = z >= 1 && z <= n - 2;
+        const long long zo = (long long)z * gf.plane;
+        T frn[R], fbn[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const long long a = ro[r] + zo + gf.plane;
+            const bool ld = rowin[r] && z + 1 <= n - 1;
+            rn[r] = ld ? RD[a] : T(0);
+            bn[r] = ld ? BK[a] : T(0);
+            frn[r] = ld ? f[a] : T(0);
+            fbn[r] = ld ? f[gf.cs + a] : T(0);
         }
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int i = t + NT * k;
-            if (i >= kFuseFX * kFuseFY) continue;
-            T r = T(0);
-            if (ok[k]) {
-                T nb = v[k][0];
-                nb = nb + v[k][1];
-                nb = nb + v[k][2];
-                nb = nb + v[k][3];
-                nb = nb + v[k][4];
-                nb = nb + v[k][5];
-                r = v[k][7] - (T(6) * v[k][6] - nb) * s;
+        for (int r = 0; r < R; ++r) {
+            const int y = yg[r];
+            const int pr = (y + z) & 1;   // x parity of the red point
+            const bool yin = rowin[r] && y >= 1 && y <= n - 2 && zin;
+            const int xr = 2 * xs + pr, xb = 2 * xs + 1 - pr;
+            const bool rin = yin && xr >= 1 && xr <= n - 2, bin = yin && xb >= 1 && xb <= n - 2;
+            const long long a = ro[r] + zo;
+            T vr = T(0), vb = T(0);
+            if (rin) {
+                // black neighbours of the red point: x - 1, x + 1 at x >> 1 - 1 + pr, x >> 1 + pr
+                const T bx = BK[a + (pr ? 1 : -1)];
+                T nb = pr ? bc[r] : bx;
+                nb = nb + (pr ? bx : bc[r]);
+                nb = nb + (r > 0 ? bc[r - 1] : BK[a - gf.pitch]);
+                nb = nb + (r < R - 1 ? bc[r + 1] : BK[a + gf.pitch]);
+                nb = nb + bm[r];
+                nb = nb + bn[r];
+                vr = fr[r] - (T(6) * rc[r] - nb) * s;
             }
-            rs[slot][i / kFuseFX][i % kFuseFX] = r;
+            if (bin) {
+                const T rx = RD[a + (pr ? -1 : 1)];
+                T nb = pr ? rx : rc[r];
+                nb = nb + (pr ? rc[r] : rx);
+                nb = nb + (r > 0 ? rc[r - 1] : RD[a - gf.pitch]);
+                nb = nb + (r < R - 1 ? rc[r + 1] : RD[a + gf.pitch]);
+                nb = nb + rm[r];
+                nb = nb + rn[r];
+                vb = fb[r] - (T(6) * bc[r] - nb) * s;
+            }
+            rp[wv * R + r][2 * lane + pr] = vr;
+            rp[wv * R + r][2 * lane + 1 - pr] = vb;
         }
-    };
-    int sa = 0, sb = 1, sc = 2;
-    fine_plane(2 * Z0 - 1, sa);
-    const int cx = t % kFuseCX, cy = t / kFuseCX;
-    const int X = X0 + cx, Y = Y0 + cy;
-    for (int Z = Z0; Z < Z1; ++Z) {
-        fine_plane(2 * Z, sb);
-        fine_plane(2 * Z + 1, sc);
         __syncthreads();
-        if (t < kFuseCX * kFuseCY && X <= gc.n - 2 && Y <= gc.n - 2) {
-            T acc = T(0);
-            bool first = true;
+        // fine plane z is offset -1 of coarse plane (z + 1) / 2 and +1 of
+        // (z - 1) / 2 when odd, offset 0 of z / 2 when even
+        const bool odd = z & 1;
 #pragma unroll
-            for (int oz = -1; oz <= 1; ++oz) {
-                const int sl = oz < 0 ? sa : (oz == 0 ? sb : sc);
+        for (int q = 0; q < QP; ++q) {
+            const int qi = (int)threadIdx.x + NT * q;
+            if (qi < NQ) {
+                const int ci = qi % kRrCX, cj = qi / kRrCX;
+                const int I = I0 + ci, J = J0 + cj;
+                if (I <= gc.n - 2 && J <= gc.n - 2) {
+                    const int lx = 2 * ci + 2, ly = 2 * cj + 1;
+                    auto plane_terms = [&](int wz, bool first, T a0) -> T {
+                        T a = a0;
+                        bool fst = first;
 #pragma unroll
-                for (int oy = -1; oy <= 1; ++oy) {
+                        for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        const int wgt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) * (2 - (oz < 0 ? -oz : oz));
-                        const T w = T(wgt) / T(64);
-                        const T term = w * rs[sl][2 * cy + 1 + oy][2 * cx + 1 + ox];
-                        acc = first ? term : acc + term;
-                        first = false;
+                            for (int ox = -1; ox <= 1; ++ox) {
+                                const int wgt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) * wz;
+                                const T term = (T(wgt) / T(64)) * rp[ly + oy][lx + ox];
+                                a = fst ? term : a + term;
+                                fst = false;
+                            }
+                        return a;
+                    };
+                    if (odd) {
+                        const int Ke = (z - 1) >> 1, Ks = (z + 1) >> 1;
+                        if (Ke >= K0) {
+                            const T done = plane_terms(1, false, acc[q]);
+                            fcoarse[(long long)((I + J + Ke) & 1) * gc.cs + row_off(gc, J, Ke) + (I >> 1)] = done;
+                        }
+                        if (Ks < K1) acc[q] = plane_terms(1, true, T(0));
+                    } else {
+                        acc[q] = plane_terms(2, false, acc[q]);
                     }
                 }
             }
-            fcoarse[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)] = acc;
         }
-        __syncthreads();
-        const int tmp = sa;   // fine plane 2Z + 1 is plane 2(Z + 1) - 1 of the next step
-        sa = sc;
-        sc = tmp;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            rm[r] = rc[r];
+            rc[r] = rn[r];
+            bm[r] = bc[r];
+            bc[r] = bn[r];
+            fr[r] = frn[r];
+            fb[r] = fbn[r];
+        }
     }
 }
 
@@ -1740,11 +1792,14 @@ bool fused_transfers(const Geom& gf) { return use_zmarch(gf); }
 template <typename T>
 static hipError_t res_restrict_t(const Geom& gf, const Geom& gc, const void* u, const void* f, void* fco,
                                  double s, hipStream_t st) {
-    const int ntx = (gc.n - 2 + kFuseCX - 1) / kFuseCX, nty = (gc.n - 2 + kFuseCY - 1) / kFuseCY;
-    const int ntz = (gc.n - 2 + kFuseZ - 1) / kFuseZ;
+    // 256-thread blocks of 3 (FP64) or 4 (FP32) rows per thread measured
+    // fastest among 2-4 rows and 4 or 8 wavefronts
+    constexpr int R = sizeof(T) == 8 ? 3 : 4, NW = 4, CY = (R * NW - 1) / 2, KC = 8;
+    const int ntx = (gc.n - 2 + kRrCX - 1) / kRrCX, nty = (gc.n - 2 + CY - 1) / CY;
+    const int ntz = (gc.n - 2 + KC - 1) / KC;
     const unsigned nb = (unsigned)((long long)ntx * nty * ntz);
-    // 256 threads (5 fine points each) measured faster than 512 or 1024 on MI355X
-    k_node_res_restrict<T, 256><<<nb, 256, 0, st>>>(gf, gc, ntx, nty, cp<T>(u), cp<T>(f), mp<T>(fco), (T)s);
+    k_node_res_restrict_zm<T, R, NW><<<nb, 64 * NW, 0, st>>>(gf, gc, ntx, nty, KC, cp<T>(u), cp<T>(f), mp<T>(fco),
+                                                             (T)s);
     return hipGetLastError();
 }
 
