@@ -122,6 +122,7 @@ def main(argv=None, emit=True):
     ap.add_argument("--slots", type=int, default=512)
     ap.add_argument("--arena-gb", type=float, default=48.0)
     ap.add_argument("--fifo-count", type=int, default=256)
+    ap.add_argument("--sweep", default="", help="comma list of further loads (x saturation) to run open loop")
     a = ap.parse_args(argv)
 
     import torch
@@ -145,6 +146,13 @@ def main(argv=None, emit=True):
     arrivals = [t / rate for t in unit]
     print(f"# serve: open loop at {rate:.0f} req/s", file=sys.stderr, flush=True)
     opn = run_server(mg, srv, reqs, fs, us, a.tol, arrivals)
+    sweep = []
+    for ld in [float(x) for x in a.sweep.split(",") if x]:
+        r = ld * sat["solves_per_s"]
+        print(f"# serve: open loop at {ld:g} x saturation ({r:.0f} req/s)", file=sys.stderr, flush=True)
+        res = run_server(mg, srv, reqs, fs, us, a.tol, [t / r for t in unit])
+        sweep.append({"load": ld, "rate_per_s": r, "solves_per_s": res["solves_per_s"], "p50_ms": res["p50_ms"],
+                      "p99_ms": res["p99_ms"], "failed": res["failed"]})
     st = srv.stats()
     srv.close()
     print("# serve: FIFO FP64 baseline", file=sys.stderr, flush=True)
@@ -154,6 +162,7 @@ def main(argv=None, emit=True):
            "cold_start": warm, "saturation": sat, "rate_per_s": rate, "load": a.load, "open_loop": opn,
            "fifo_fp64_one_at_a_time": fifo,
            "speedup_solves_per_s": opn["solves_per_s"] / fifo["solves_per_s"],
+           "load_sweep": sweep,
            "server": {"max_slots": a.slots, "arena_gb": a.arena_gb, "rounds": st["rounds"],
                       "launches": st["launches"], "hierarchies_built": st["hierarchies_built"],
                       "arena_peak_gb": st["arena_peak_bytes"] / (1 << 30)}}
