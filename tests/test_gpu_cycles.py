@@ -138,7 +138,7 @@ def test_varcoef_cell_per_iterate(mg, N, smoother):
     s.close()
 
 
-@pytest.mark.parametrize("dim,n,cent", [(3, 33, 0), (3, 65, 0), (2, 129, 0), (3, 32, 1)])
+@pytest.mark.parametrize("dim,n,cent", [(3, 33, 0), (3, 65, 0), (3, 129, 0), (2, 129, 0), (3, 32, 1)])
 def test_mixed_precision_matches_oracle(mg, dim, n, cent):
     if cent:
         k = W.varcoef_k(n, 3)
@@ -275,6 +275,7 @@ def test_full_size_513_properties(mg, precision):
     (3, 65, "rbgs", 3, 3, "mixed"),
     (2, 129, "jacobi", 1, 2, "fp64"),     # three buffer swaps per level: two graphs alternate
     (3, 257, "rbgs", 3, 3, "fp64"),      # fused sweeps run out of place
+    (3, 129, "rbgs", 3, 3, "mixed"),     # mg_solve fuses the update with the next residual; mg_vcycle does not
 ])
 def test_graph_replay_equals_eager(mg, dim, n, sm, nu1, nu2, precision):
     """mg_solve and mg_vcycle replay each iteration from a captured HIP graph;
