@@ -1,5 +1,5 @@
-"""Level hierarchy, coarsest-level direct solve, V-cycle, solve to tolerance
-and mixed-precision iterative refinement.
+"""Level hierarchy, coarsest-level direct solve, multigrid cycles (V, W, F),
+solve to tolerance and mixed-precision iterative refinement.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -7,7 +7,11 @@ The V-cycle is the textbook recursion (Trottenberg et al., *Multigrid*,
 Sec. 2.4, gamma = 1): on level l, smooth nu1 times, restrict the residual to
 the right-hand side of level l+1, start level l+1 from zero, recurse, add the
 interpolated correction, smooth nu2 times; on the coarsest level solve
-exactly.  Coarse operators are rediscretised (the same stencil with the
+exactly.  The W-cycle (gamma = 2) visits level l+1 twice, the second visit
+continuing from the first one's result; the F-cycle visits it with an
+F-cycle from zero followed by a V-cycle (Trottenberg et al., Sec. 2.4.2).
+A level directly above the coarsest is visited once in every type, since
+the coarsest solve is exact.  Coarse operators are rediscretised (the same stencil with the
 coarse mesh width), matching ExaSlang's per-level ``Stencil`` declarations.
 The coarsest solve is always FP64: a dense Cholesky factorisation of the
 coarsest matrix followed by two triangular solves, with float32 right-hand
@@ -43,6 +47,7 @@ class Params:
     nu2: int = 2
     post_order: tuple = (0, 1)       # colour order of post-smoothing sweeps
     k: np.ndarray | None = None      # cell coefficients (cell grids); None = 1
+    cycle: str = "V"                 # "V", "W" or "F"
 
 
 @dataclass
@@ -52,6 +57,7 @@ class Hierarchy:
     beta: list = field(default_factory=list)       # per level, FP64 face lists (cell only)
     chol: np.ndarray | None = None                  # FP64 lower Cholesky factor, coarsest
     _beta_cache: dict = field(default_factory=dict)
+    coarse_solves: int = 0                          # coarsest solves performed (instrumentation)
 
     @property
     def levels(self) -> int:
@@ -132,6 +138,7 @@ def prolong_correct(h: Hierarchy, u, ec):
 def coarse_solve(h: Hierarchy, fc):
     """Exact coarsest solve in FP64 via the stored Cholesky factor L:
     L y = b, L^T x = y; float32 inputs are upcast and the result downcast."""
+    h.coarse_solves += 1
     b = np.asarray(unknowns(h, fc), dtype=np.float64).reshape(-1)
     y = scipy.linalg.solve_triangular(h.chol, b, lower=True)
     x = scipy.linalg.solve_triangular(h.chol.T, y, lower=False)
@@ -144,7 +151,12 @@ def coarse_solve(h: Hierarchy, fc):
 
 
 def vcycle(h: Hierarchy, u, f, lvl: int = 0):
-    """One V(nu1, nu2)-cycle on level lvl; returns the new iterate."""
+    """One (nu1, nu2)-cycle of type h.p.cycle on level lvl; returns the new
+    iterate (the name is kept for the default V-cycle)."""
+    return mg_cycle(h, u, f, lvl, h.p.cycle)
+
+
+def mg_cycle(h: Hierarchy, u, f, lvl: int, kind: str):
     p = h.p
     if lvl == h.levels - 1:
         return coarse_solve(h, f)
@@ -152,7 +164,12 @@ def vcycle(h: Hierarchy, u, f, lvl: int = 0):
     r = residual(h, lvl, u, f)
     fc = restrict(h, r)
     uc = np.zeros_like(fc)
-    uc = vcycle(h, uc, fc, lvl + 1)
+    uc = mg_cycle(h, uc, fc, lvl + 1, kind)
+    if lvl + 1 < h.levels - 1:
+        if kind == "W":
+            uc = mg_cycle(h, uc, fc, lvl + 1, "W")
+        elif kind == "F":
+            uc = mg_cycle(h, uc, fc, lvl + 1, "V")
     u = prolong_correct(h, u, uc)
     u = smooth(h, lvl, u, f, p.nu2, p.post_order)
     return u

@@ -177,3 +177,61 @@ def test_pow2_scale():
     for v in (1.0, 0.75, 3.0, 1e-300, 5e300, 2.0 ** -20):
         s = cycle.pow2_scale(v)
         assert s <= v < 2 * s and np.log2(s) == np.floor(np.log2(s))
+
+
+# ------------------------------------------------------------ W- and F-cycles
+
+@pytest.mark.parametrize("n", [33, 65, 129])
+def test_cycle_types_visit_the_coarsest_level_as_defined(n):
+    """gamma = 2 doubles the visits of every level below the second-coarsest,
+    and the F-cycle adds one visit per level: per cycle the coarsest solve runs
+    1 (V), 2^(L-2) (W) and L-1 (F) times for L levels."""
+    for kind, count in (("V", lambda L: 1), ("W", lambda L: 2 ** (L - 2)), ("F", lambda L: L - 1)):
+        h = cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=n, smoother="rbgs", nu1=1, nu2=1,
+                                               cycle=kind))
+        u = W.interior_uniform(n, 2, 5)
+        cycle.vcycle(h, u, np.zeros_like(u))
+        assert h.coarse_solves == count(h.levels), (kind, h.levels, h.coarse_solves)
+
+
+def test_cycle_types_agree_on_two_levels():
+    """With one level above the exact coarsest solve, V, W and F are the same
+    two-grid cycle, bit for bit."""
+    n = 9
+    f = W.interior_uniform(n, 2, 3)
+    u0 = W.interior_uniform(n, 2, 4)
+    out = []
+    for kind in ("V", "W", "F"):
+        h = cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=n, smoother="rbgs", nu1=2, nu2=2,
+                                               cycle=kind))
+        assert h.levels == 2
+        out.append(cycle.vcycle(h, u0, f))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+@pytest.mark.parametrize("nu", [1, 2])
+def test_w_and_f_cycles_reach_the_two_grid_factor(nu):
+    """A W-cycle (and an F-cycle) recovers the two-grid convergence factor
+    within the LFA's accuracy on a 5-level hierarchy, where the V-cycle is
+    slower."""
+    ref = GOLD["rho_two_grid"][str(2 * nu)]
+    fac = {}
+    for kind in ("V", "W", "F"):
+        fac[kind] = _vcycle_factor(cycle.Params(centering="node", dim=2, n=65, smoother="rbgs", nu1=nu, nu2=nu,
+                                                cycle=kind), cycles_=12)
+    for kind in ("W", "F"):
+        assert ref / 1.35 < fac[kind] < ref * 1.35, (kind, fac, ref)
+    assert fac["V"] > 1.2 * fac["W"], fac
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+def test_w_and_f_cycles_converge_to_dense_solution(kind):
+    n = 17
+    f = W.interior_uniform(n, 2, 9)
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=n, smoother="rbgs", nu1=2, nu2=2,
+                                           cycle=kind))
+    u, hist, _ = cycle.solve(h, f, tol=1e-14, max_cycles=40)
+    A = node.dense_matrix(n, 2)
+    c = node.interior(2)
+    ud = np.linalg.solve(A, f[c].reshape(-1))
+    assert np.max(np.abs(u[c].reshape(-1) - ud)) <= 1e-12 * np.max(np.abs(ud))
