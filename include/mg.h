@@ -55,6 +55,7 @@ enum { MG_LAPLACE = 0, MG_VARCOEF = 1 };        /* operator kind            */
 enum { MG_DIRICHLET0 = 0 };                     /* boundary kind            */
 enum { MG_JACOBI = 0, MG_RBGS = 1 };            /* smoother                 */
 enum { MG_FP64 = 0, MG_MIXED = 1 };             /* arithmetic               */
+enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 };   /* cycle type      */
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32 = 1 };    /* which level hierarchy    */
 enum { MG_FIELD_U = 0, MG_FIELD_F = 1, MG_FIELD_R = 2 };
 
@@ -88,7 +89,12 @@ typedef struct mg_bc {
 /* Cycle options.  omega is the Jacobi damping; nu1/nu2 pre/post sweeps;
  * post_order 0 = red (even index sum) first, 1 = black first; max_cycles caps
  * mg_solve (cycles in MG_FP64, refinement steps in MG_MIXED, each one
- * single-precision V-cycle). */
+ * single-precision cycle).  cycle: MG_CYCLE_V (cycle index 1), MG_CYCLE_W
+ * (cycle index 2: each coarser level is visited twice, the second visit
+ * continuing from the first) or MG_CYCLE_F (an F-cycle from zero, then a
+ * V-cycle, on each coarser level); a level directly above the coarsest is
+ * visited once (Trottenberg, Oosterlee, Schueller, Multigrid, Sec. 2.4).
+ * The solve server runs V-cycles only. */
 typedef struct mg_opts {
     int smoother;
     double omega;
@@ -96,6 +102,7 @@ typedef struct mg_opts {
     int precision;
     int max_cycles;
     int post_order;
+    int cycle;
 } mg_opts;
 
 typedef struct mg_ctx mg_ctx;
@@ -103,7 +110,7 @@ typedef struct mg_ctx mg_ctx;
 /* ---------------------------------------------------------------- setup */
 const char* mg_version(void);
 
-/* Fill *o with the defaults: RB-GS, omega 0.8, V(2,2), FP64, 100 cycles, red first. */
+/* Fill *o with the defaults: RB-GS, omega 0.8, V(2,2), FP64, 100 cycles, red first, V-cycle. */
 void mg_default_opts(mg_opts* o);
 
 /* Device workspace bytes mg_setup needs for this problem (host-only call). */

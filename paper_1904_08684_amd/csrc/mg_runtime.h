@@ -107,6 +107,7 @@ struct Ctx {
     int prolong(int l, int pr, int mask);
     int coarse(int pr);
     int vcycle(int l, int pr, bool from_zero);
+    int cycle(int l, int pr, bool from_zero, int kind);
     int refine_step();
     int read_red(double* sq, double* mx);
     int norm(double* out);

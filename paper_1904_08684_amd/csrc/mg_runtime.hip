@@ -87,6 +87,7 @@ int validate(const mg_grid* g, const mg_stencil* st, const mg_opts* o, std::stri
     if (!(o->omega > 0.0) || !(o->omega < 2.0)) return bad("omega must be in (0, 2)");
     if (o->max_cycles < 1) return bad("max_cycles must be >= 1");
     if (o->post_order != 0 && o->post_order != 1) return bad("post_order must be 0 or 1");
+    if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) return bad("unknown cycle type");
     return MG_OK;
 }
 
@@ -607,7 +608,10 @@ int Ctx::coarse(int pr) {
 // current iterate is zero (coarse levels, and the single-precision finest
 // level inside refinement), so the first sweep reads no neighbour values and
 // no zero fill is needed.
-int Ctx::vcycle(int l, int pr, bool from_zero) {
+int Ctx::vcycle(int l, int pr, bool from_zero) { return cycle(l, pr, from_zero, opts.cycle); }
+
+// One cycle of the given type on level l (see mg_opts).
+int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
     int rc = smooth(l, pr, opts.nu1, from_zero, 0);
     if (!rc && !rec && grid.centering == MG_NODE && fused_transfers(lv[l].g)) {
@@ -621,7 +625,9 @@ int Ctx::vcycle(int l, int pr, bool from_zero) {
         if (!rc) rc = residual(l, pr, false, true);
         if (!rc) rc = restrict_to(l, pr);
     }
-    if (!rc) rc = vcycle(l + 1, pr, true);
+    if (!rc) rc = cycle(l + 1, pr, true, kind);
+    if (!rc && l + 2 < L && kind != MG_CYCLE_V)
+        rc = cycle(l + 1, pr, false, kind == MG_CYCLE_W ? MG_CYCLE_W : MG_CYCLE_V);
     if (rc) return rc;
     // With red-black smoothing that starts with colour c, the corrections of
     // colour c are overwritten before anything reads them: prolong onto the
@@ -1000,6 +1006,7 @@ void mg_default_opts(mg_opts* o) {
     o->precision = MG_FP64;
     o->max_cycles = 100;
     o->post_order = 0;
+    o->cycle = MG_CYCLE_V;
 }
 
 int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes) {

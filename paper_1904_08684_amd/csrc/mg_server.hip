@@ -561,6 +561,7 @@ int mg_server_submit(mg_server* h, const mg_request* r) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (r->grid.centering != MG_NODE || !r->f || !r->u_out || !(r->tol > 0.0))
         return s->fail(MG_EINVAL, "requests need a node grid, device f and u_out, and tol > 0");
+    if (r->opts.cycle != MG_CYCLE_V) return s->fail(MG_EINVAL, "the server runs V-cycles");
     size_t ws = 0;
     mg_opts m = r->opts;
     m.precision = MG_MIXED;

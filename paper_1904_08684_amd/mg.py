@@ -29,6 +29,7 @@ MG_LAPLACE, MG_VARCOEF = 0, 1
 MG_DIRICHLET0 = 0
 MG_JACOBI, MG_RBGS = 0, 1
 MG_FP64, MG_MIXED = 0, 1
+MG_CYCLE_V, MG_CYCLE_W, MG_CYCLE_F = 0, 1, 2
 MG_PREC_FP64, MG_PREC_FP32 = 0, 1
 MG_FIELD_U, MG_FIELD_F, MG_FIELD_R = 0, 1, 2
 (MG_OP_GS_RED, MG_OP_GS_BLACK, MG_OP_JACOBI, MG_OP_RESIDUAL, MG_OP_RESTRICT,
@@ -52,7 +53,7 @@ class mg_bc(C.Structure):
 
 class mg_opts(C.Structure):
     _fields_ = [("smoother", C.c_int), ("omega", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("precision", C.c_int), ("max_cycles", C.c_int), ("post_order", C.c_int)]
+                ("precision", C.c_int), ("max_cycles", C.c_int), ("post_order", C.c_int), ("cycle", C.c_int)]
 
 
 _P = C.c_void_p
@@ -115,10 +116,10 @@ def make_grid(dim: int, n: int, centering: int = MG_NODE, coarsest: int | None =
 
 
 def make_opts(smoother=MG_RBGS, omega=0.8, nu1=2, nu2=2, precision=MG_FP64, max_cycles=100,
-              post_order=0) -> mg_opts:
+              post_order=0, cycle=0) -> mg_opts:
     o = mg_opts()
     o.smoother, o.omega, o.nu1, o.nu2 = smoother, omega, nu1, nu2
-    o.precision, o.max_cycles, o.post_order = precision, max_cycles, post_order
+    o.precision, o.max_cycles, o.post_order, o.cycle = precision, max_cycles, post_order, cycle
     return o
 
 
@@ -148,12 +149,12 @@ class Solver:
 
     def __init__(self, dim: int, n: int, centering: int = MG_NODE, coarsest: int | None = None,
                  smoother: int = MG_RBGS, omega: float = 0.8, nu1: int = 2, nu2: int = 2,
-                 precision: int = MG_FP64, max_cycles: int = 100, post_order: int = 0,
+                 precision: int = MG_FP64, max_cycles: int = 100, post_order: int = 0, cycle: int = 0,
                  k=None, stream=None, device: str = "cuda"):
         import torch
         self.dim, self.n, self.centering = dim, n, centering
         self.grid = make_grid(dim, n, centering, coarsest)
-        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order)
+        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order, cycle)
         self.stencil = mg_stencil()
         self._k = None
         if k is not None:

@@ -327,3 +327,43 @@ def test_graph_replay_equals_eager(mg, dim, n, sm, nu1, nu2, precision):
         assert np.array_equal(u, u_e)
         if hist is not None:
             assert hist == hist_e
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("dim,n,sm,nu,cycles", [(2, 129, "jacobi", 2, 3), (3, 33, "rbgs", 3, 3),
+                                                (3, 65, "rbgs", 3, 2), (3, 257, "rbgs", 3, 1)])
+def test_w_and_f_cycles_per_iterate(mg, kind, dim, n, sm, nu, cycles):
+    """W- and F-cycles against the oracle's, iterate by iterate (at 257^3 the
+    second visit of level 1 runs the fused sweeps from a non-zero iterate)."""
+    f = W.interior_uniform(n, dim, W.SEED_F_3D)
+    u0 = W.interior_uniform(n, dim, W.SEED_U0_2D)
+    code = mg.MG_CYCLE_W if kind == "W" else mg.MG_CYCLE_F
+    s = mg.Solver(dim, n, smoother=mg.MG_RBGS if sm == "rbgs" else mg.MG_JACOBI, omega=0.8, nu1=nu, nu2=nu,
+                  cycle=code)
+    s.set_rhs(f)
+    s.set_initial(u0)
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=dim, n=n, smoother=sm, omega=0.8, nu1=nu,
+                                           nu2=nu, cycle=kind))
+    ref = cycle.cycles(h, f, u0, cycles)
+    for k in range(cycles):
+        s.vcycle(1)
+        err = rel_max(s.solution(), ref[k])
+        print(f"{kind}-cycle {dim}d n={n} {sm} cycle {k + 1}: max rel diff {err:.3e}", flush=True)
+        assert err <= TOL_ITERATE
+    s.close()
+
+
+def test_w_cycle_mixed_solve_matches_oracle(mg):
+    n = 65
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, precision=mg.MG_MIXED, cycle=mg.MG_CYCLE_W)
+    s.set_rhs(f)
+    s.set_initial(None)
+    code, steps, rel = s.solve(1e-10)
+    u = s.solution()
+    s.close()
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3, cycle="W"))
+    u_ref, hist = cycle.mixed_solve(h, f, tol=1e-10)
+    print(f"W mixed: steps {steps} (oracle {len(hist) - 1}) relres {rel:.3e} vs oracle {rel_max(u, u_ref):.2e}",
+          flush=True)
+    assert code == mg.MG_OK and abs(steps - (len(hist) - 1)) <= 1 and rel_max(u, u_ref) <= 1e-9

@@ -114,6 +114,12 @@ def test_queue_limit_and_invalid_requests(mg):
     codes = [srv.submit(i, 3, 17, f, u, 1e-8, mg.MG_RBGS, 3, 3) for i in range(4)]
     assert codes[:3] == [mg.MG_OK] * 3 and codes[3] == mg.MG_EBUSY
     assert srv.submit(9, 3, 18, f, u, 1e-8) == mg.MG_EINVAL
+    # served requests are V-cycles
+    r = mg.mg_request()
+    r.id, r.grid, r.tol = 11, mg.make_grid(3, 17), 1e-8
+    r.opts = mg.make_opts(mg.MG_RBGS, 0.8, 3, 3, mg.MG_MIXED, 50, 0, mg.MG_CYCLE_W)
+    r.f, r.u_out = f.data_ptr(), u.data_ptr()
+    assert mg.mg_server_submit(srv.h, mg.C.byref(r)) == mg.MG_EINVAL
     big = mg.server_footprint(3, 257, mg.MG_RBGS, 3, 3)
     assert big > (256 << 20)
     fb = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
