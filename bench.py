@@ -50,6 +50,19 @@ def traffic_record(n: int):
     return rec
 
 
+def vcycle_traffic_record(n: int):
+    """Measured HBM bytes per V-cycle (all kernels of a solve) from the
+    committed rocprofv3 counter runs, valid only while the kernel source is
+    unchanged."""
+    path = os.path.join(ROOT, "profiles", f"vcycle_{n}cubed_fp64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec
+
+
 def cpu_model() -> str:
     try:
         for ln in open("/proc/cpuinfo"):
@@ -77,8 +90,9 @@ def cpu_baseline(n_sample: int = 257):
 
 
 def other_configs(mg, W, torch, np):
-    """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound) and the
-    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10)."""
+    """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound), the
+    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10), and W-
+    and F-cycle solves of the 513^3 Poisson problem."""
     res = {}
     n = 129
     s = mg.Solver(2, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2)
@@ -123,6 +137,27 @@ def other_configs(mg, W, torch, np):
         s.close()
     res["varcoef_cell_256_mixed"]["max_rel_diff_vs_fp64_solution"] = float(
         (sols["mixed"] - sols["fp64"]).abs().max() / sols["fp64"].abs().max())
+    sols = None
+    # W- and F-cycles on the 513^3 problem (same kernels, cycle index 2 / F-recursion)
+    n = 513
+    f3 = torch.from_numpy(W.interior_uniform(n, 3, W.SEED_F_3D)).cuda()
+    for code, name in ((mg.MG_CYCLE_W, "W"), (mg.MG_CYCLE_F, "F")):
+        s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, cycle=code)
+        s.set_rhs(f3)
+        s.set_initial(None)
+        s.solve(1e-10)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            s.set_initial(None)
+            t = time.perf_counter()
+            code_, cyc, rel = s.solve(1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        dt = min(times)
+        res[f"poisson3d_513_{name}cycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
+                                                 "status": code_, "ms_per_cycle": round(1e3 * dt / cyc, 3)}
+        s.close()
     return res
 
 
@@ -229,8 +264,10 @@ def main():
     # correction 17 B per unknown (194 B), summed over levels (x 8/7)
     vc_bytes = 194.0 * 8.0 / 7.0 * unknowns
     vc_ms = 1e3 * r64["total"] / cyc_total
+    vtr = vcycle_traffic_record(n)
     vcycle_roofline = {"bound": "hbm", "unfused_compulsory_bytes_per_cycle": round(vc_bytes),
                        "ms_per_cycle": round(vc_ms, 4),
+                       "traffic_per_cycle": (round(vtr["hbm_bytes_per_cycle"]) if vtr else None),
                        "achieved": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
