@@ -557,7 +557,20 @@ __device__ __forceinline__ float div6(float a) {
 // result is bitwise that of S separate half-sweeps.  The output goes to a
 // second buffer (a neighbouring block may still read the iterate); both
 // colours of every interior node are written, boundary nodes stay zero.
-template <typename T, int S, int R, int NW, int PF, bool P2>
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t rsc, unsigned voff, int soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsc, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsc, voff, soff, 0));
+}
+
+// BUF: fields below 2 GiB are read through buffer resources, the lane's byte
+// offset in a vector register and the row's in a scalar one (no per-load
+// 64-bit address arithmetic).  Offsets stay inside the field (planes are
+// clamped as in the plain path), so the range check never clips a value
+// that is used.
+template <typename T, int S, int R, int NW, int PF, bool P2, bool BUF>
 __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, const T* __restrict__ uin,
                                                         const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
                                                         int c1, int zero) {
@@ -596,6 +609,17 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
     auto yout = [&](int r) { return wv * R + r >= S && wv * R + r < RY - S && yg[r] <= n - 2; };
     auto pin = [&](int p) { return p >= 1 && p <= n - 2; };
     auto pcl = [&](int p) -> long long { return (long long)min(max(p, 0), n - 1) * pl; };
+    // (unused without BUF; the byte count is only meaningful below 2 GiB)
+    const int fbytes = BUF ? (int)(2 * cs * (long long)sizeof(T)) : 0;
+    const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(uin), 0, fbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f), 0, fbytes, 0x00020000);
+    const unsigned xb = xo * (unsigned)sizeof(T);
+    // element (colour c, plane p clamped, row r) at the thread's lane
+    auto ld = [&](const T* base, __amdgpu_buffer_rsrc_t rsc, int c, int p, int r) -> T {
+        const long long e = c * cs + pcl(p) + yo[r];
+        if constexpr (BUF) return buf_load<T>(rsc, xb, (int)(e * (long long)sizeof(T)));
+        else return base[e + xo];
+    };
     // is the colour-c point of row r on plane p an unknown? (par: its x parity)
     auto inside = [&](int r, int p, int par) { return yin(r) && pin(p) && (par ? xin1 : xin0); };
     // Operands that come from HBM are loaded one step ahead: qu = iterate on
@@ -607,9 +631,9 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
     const int t0 = Z0 - S;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        qu[r] = zero ? T(0) : uin[c0 * cs + pcl(t0) + yo[r] + xo];
+        qu[r] = zero ? T(0) : ld(uin, ru, c0, t0, r);
 #pragma unroll
-        for (int k = 1; k <= PF; ++k) qf[k - 1][r] = f[((c1 + k - 1) & 1) * cs + pcl(t0 - k) + yo[r] + xo];
+        for (int k = 1; k <= PF; ++k) qf[k - 1][r] = ld(f, rf, (c1 + k - 1) & 1, t0 - k, r);
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             old[k][r] = T(0);
@@ -628,7 +652,7 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             nw[r] = inside(r, t, (yg[r] + t + c0) & 1) ? qu[r] : T(0);
-            if (!zero) qu[r] = uin[c0 * cs + pcl(t + 1) + yo[r] + xo];
+            if (!zero) qu[r] = ld(uin, ru, c0, t + 1, r);
         }
 #pragma unroll
         for (int k = 1; k <= S; ++k) {
@@ -656,15 +680,21 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
                 T fv;
                 if (k <= PF) {
                     fv = qf[k - 1][r];
-                    qf[k - 1][r] = f[ck * cs + pcl(p + 1) + yo[r] + xo];
+                    qf[k - 1][r] = ld(f, rf, ck, p + 1, r);
                 } else {
-                    fv = f[ck * cs + pcl(p) + yo[r] + xo];
+                    fv = ld(f, rf, ck, p, r);
                 }
                 // s is a power of two when P2: f * (1 / s) rounds exactly as f / s
                 T v = div6((P2 ? fv * rs : fv / s) + nb);
                 const bool in = inside(r, p, par);
                 v = in ? v : T(0);
-                if (zout && yout(r) && xout && in) uout[ck * cs + p * pl + yo[r] + xo] = v;
+                if (zout && yout(r) && xout && in) {
+                    // FP64 output streams past the L2 (less eviction of the halo
+                    // and right-hand-side planes later stages re-read)
+                    T* dst = uout + (ck * cs + p * pl + yo[r] + xo);
+                    if (sizeof(T) == 8) __builtin_nontemporal_store(v, dst);
+                    else *dst = v;
+                }
                 nk[r] = v;
             }
 #pragma unroll
@@ -1627,12 +1657,21 @@ static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void
     const dim3 grid((unsigned)ts.blocks()), block(64 * NW);
     int e;
     const bool p2 = s > 0.0 && std::frexp(s, &e) == 0.5;   // s = 2^(e - 1)
-    if (p2)
-        k_node_gs_tb<T, S, R, NW, PF, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
-                                                                 (T)(1.0 / s), c1, z);
+    // buffer loads measured 2.6 % faster for FP64 and 19 % slower for FP32
+    const bool buf = sizeof(T) == 8 && 2 * g.cs * (long long)sizeof(T) < (1LL << 31);
+    const T rs = (T)(1.0 / s);
+    if (p2 && buf)
+        k_node_gs_tb<T, S, R, NW, PF, true, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
+                                                                          (T)s, rs, c1, z);
+    else if (p2)
+        k_node_gs_tb<T, S, R, NW, PF, true, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
+                                                                           (T)s, rs, c1, z);
+    else if (buf)
+        k_node_gs_tb<T, S, R, NW, PF, false, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
+                                                                           (T)s, rs, c1, z);
     else
-        k_node_gs_tb<T, S, R, NW, PF, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s,
-                                                                  (T)(1.0 / s), c1, z);
+        k_node_gs_tb<T, S, R, NW, PF, false, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
+                                                                            (T)s, rs, c1, z);
 }
 
 template <typename T>
