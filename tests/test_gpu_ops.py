@@ -204,3 +204,37 @@ def test_fused_sweeps_equal_half_sweeps(mg, prec, nu, post):
         node.gs_colour(ref, f, post)
         node.gs_colour(ref, f, 1 - post)
     close(fused, ref.astype(np.float64), prec, f"fused {nu} sweeps 3d n={n} post={post} prec={prec}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_paths_with_non_power_of_two_scale(mg, prec):
+    """385^3 nodes with a 4-node coarsest level: s = 384^2 is not a power of
+    two, so the fused sweeps divide by s instead of multiplying by 1/s; the
+    fused pass still equals the half-sweeps bitwise and the oracle's sweeps,
+    and the fused residual + restriction equals the oracle's."""
+    n = 385
+    s = mg.Solver(3, n, coarsest=4, smoother=mg.MG_RBGS, nu1=3, nu2=3,
+                  precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 3, 0, 1200, dt)
+    f = rand(n, 3, 0, 1201, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_PRESMOOTH, 0, prec)
+    fused = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    for _ in range(3):
+        s.apply(mg.MG_OP_GS_RED, 0, prec)
+        s.apply(mg.MG_OP_GS_BLACK, 0, prec)
+    halves = s.level_get(0, mg.MG_FIELD_U, prec)
+    assert np.array_equal(fused, halves)
+    ref = u.copy()
+    for _ in range(3):
+        node.gs_colour(ref, f, 0)
+        node.gs_colour(ref, f, 1)
+    close(fused, ref.astype(np.float64), prec, f"fused 3 sweeps n={n} prec={prec}")
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.apply(mg.MG_OP_RESIDUAL_RESTRICT, 0, prec)
+    got = s.level_get(1, mg.MG_FIELD_F, prec)
+    s.close()
+    close(got, node.restrict_fw(node.residual(u, f)).astype(np.float64), prec, f"residual+restrict n={n} prec={prec}")
