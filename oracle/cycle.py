@@ -175,6 +175,24 @@ def mg_cycle(h: Hierarchy, u, f, lvl: int, kind: str):
     return u
 
 
+def fmg(h: Hierarchy, f, cycles_per_level: int = 1):
+    """Full multigrid (Trottenberg et al., Sec. 2.6): the right-hand side is
+    restricted to every level by the transfer operator of the cycle, the
+    coarsest level is solved exactly, and each finer level starts from the
+    interpolated coarser solution (multilinear interpolation, the cycle's
+    own) and applies cycles_per_level cycles of type h.p.cycle.  Returns the
+    finest iterate."""
+    fs = [f]
+    for _ in range(1, h.levels):
+        fs.append(restrict(h, fs[-1]))
+    u = coarse_solve(h, fs[-1])
+    for lvl in range(h.levels - 2, -1, -1):
+        u = prolong_correct(h, np.zeros_like(fs[lvl]), u)
+        for _ in range(cycles_per_level):
+            u = mg_cycle(h, u, fs[lvl], lvl, h.p.cycle)
+    return u
+
+
 def residual_norm(h: Hierarchy, u, f) -> float:
     r = residual(h, 0, u, f)
     ru = np.asarray(unknowns(h, r), dtype=np.float64)

@@ -235,3 +235,38 @@ def test_w_and_f_cycles_converge_to_dense_solution(kind):
     c = node.interior(2)
     ud = np.linalg.solve(A, f[c].reshape(-1))
     assert np.max(np.abs(u[c].reshape(-1) - ud)) <= 1e-12 * np.max(np.abs(ud))
+
+
+# ------------------------------------------------------------------ full multigrid
+
+def _fmg_errors(dim, n, sm, nu, cpl):
+    """FMG on -Lap u = dim pi^2 prod sin(pi x): returns the algebraic error
+    max |u_fmg - u_h| over the discretisation error max |u_h - u|, where the
+    discrete solution is u_h = c_h u with c_h = (pi h / 2)^2 / sin^2(pi h / 2)
+    in closed form."""
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=dim, n=n, smoother=sm, nu1=nu, nu2=nu))
+    ue = W.sine_mode(n, dim)
+    f = dim * np.pi ** 2 * ue
+    hh = 1.0 / (n - 1)
+    ch = (np.pi * hh / 2) ** 2 / np.sin(np.pi * hh / 2) ** 2
+    u = cycle.fmg(h, f, cpl)
+    return np.max(np.abs(u - ch * ue)) / abs(ch - 1.0)
+
+
+def test_fmg_reaches_discretisation_accuracy_2d():
+    """One FMG pass with one RB-GS V(2,2)-cycle per level leaves an algebraic
+    error below the discretisation error, independently of h."""
+    r = [_fmg_errors(2, n, "rbgs", 2, 1) for n in (33, 65, 129, 257)]
+    assert max(r) < 1.0 and max(r) / min(r) < 1.1, r
+
+
+def test_fmg_reaches_discretisation_accuracy_3d():
+    """3-D, RB-GS V(3,3), two cycles per level: algebraic error at most 0.15 of
+    the discretisation error on every grid."""
+    r = [_fmg_errors(3, n, "rbgs", 3, 2) for n in (17, 33, 65)]
+    assert max(r) < 0.15, r
+
+
+def test_fmg_more_cycles_approach_the_discrete_solution():
+    r = [_fmg_errors(2, 65, "jacobi", 2, c) for c in (1, 2, 3)]
+    assert r[0] > r[1] > r[2], r
