@@ -138,6 +138,15 @@ int mg_get_solution(mg_ctx* c, double* u, int on_device);
  * Each cycle is replayed from a captured HIP graph unless profiling is on. */
 int mg_vcycle(mg_ctx* c, int ncycles);
 
+/* Full multigrid (Trottenberg, Oosterlee, Schueller, Multigrid, Sec. 2.6):
+ * the right-hand side is restricted to every level, the coarsest level is
+ * solved exactly, and each finer level starts from the interpolated coarser
+ * solution and receives cycles_per_level cycles of the context's type; the
+ * finest result becomes the iterate (a following mg_solve continues from it).
+ * Overwrites the coarse levels' fields.  FP64 contexts only (MG_EINVAL
+ * otherwise); asynchronous. */
+int mg_fmg(mg_ctx* c, int cycles_per_level);
+
 /* Cycle until ||f - A u||_2 / ||f - A u0||_2 <= tol over the unknowns;
  * synchronous.  Returns MG_OK, MG_ENOTCONV, MG_ENONFINITE or MG_EDIVERGED;
  * cycles_out / relres_out may be NULL.  Each iteration (cycle or refinement

@@ -108,6 +108,7 @@ struct Ctx {
     int coarse(int pr);
     int vcycle(int l, int pr, bool from_zero);
     int cycle(int l, int pr, bool from_zero, int kind);
+    int fmg(int cpl);
     int refine_step();
     int read_red(double* sq, double* mx);
     int norm(double* out);

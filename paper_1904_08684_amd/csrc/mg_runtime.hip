@@ -610,6 +610,28 @@ int Ctx::coarse(int pr) {
 // no zero fill is needed.
 int Ctx::vcycle(int l, int pr, bool from_zero) { return cycle(l, pr, from_zero, opts.cycle); }
 
+// Full multigrid: f restricted to every level, the coarsest solved exactly,
+// each finer level started from the interpolated coarser solution and given
+// cpl cycles of the context's type.  FP64 contexts.
+int Ctx::fmg(int cpl) {
+    const int pr = 0;
+    for (int l = 0; l + 1 < L; ++l) {
+        hipEvent_t e0 = begin();
+        int rc = record(MG_K_RESTRICT, l,
+                        launch_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].f[pr], lv[l + 1].f[pr], stream), e0,
+                        "restrict f");
+        if (rc) return rc;
+    }
+    int rc = coarse(pr);
+    for (int l = L - 2; l >= 0 && !rc; --l) {
+        hipEvent_t e0 = begin();
+        rc = record(MG_K_COPY, l, launch_zero(lv[l].u[pr], lv[l].field_bytes[pr], stream), e0, "zero");
+        if (!rc) rc = prolong(l, pr, 3);
+        for (int k = 0; k < cpl && !rc; ++k) rc = cycle(l, pr, false, opts.cycle);
+    }
+    return rc;
+}
+
 // One cycle of the given type on level l (see mg_opts).
 int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
@@ -1096,6 +1118,13 @@ int mg_vcycle(mg_ctx* h, int ncycles) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     if (!c || ncycles < 0) return MG_EINVAL;
     return c->step(ncycles);
+}
+
+int mg_fmg(mg_ctx* h, int cycles_per_level) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || cycles_per_level < 1) return MG_EINVAL;
+    if (c->opts.precision != MG_FP64) return c->fail(MG_EINVAL, "full multigrid runs in FP64 contexts");
+    return c->fmg(cycles_per_level);
 }
 
 int mg_solve(mg_ctx* h, double tol, int* cycles_out, double* relres_out) {

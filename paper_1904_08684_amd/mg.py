@@ -71,6 +71,7 @@ _sigs = {
     "mg_get_solution": (C.c_int, [_P, _P, C.c_int]),
     "mg_vcycle": (C.c_int, [_P, C.c_int]),
     "mg_solve": (C.c_int, [_P, C.c_double, C.POINTER(C.c_int), _D]),
+    "mg_fmg": (C.c_int, [_P, C.c_int]),
     "mg_residual_norm": (C.c_int, [_P, _D]),
     "mg_history": (C.c_int, [_P, _D, C.c_int, C.POINTER(C.c_int)]),
     "mg_levels": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -259,6 +260,10 @@ class Solver:
         ms = C.c_double()
         _check(mg_profile_read(self.ctx, kclass, level, C.byref(n), C.byref(ms)), self.ctx)
         return n.value, ms.value
+
+    def fmg(self, cycles_per_level: int = 1):
+        """Full multigrid from the right-hand side; the result becomes the iterate."""
+        _check(mg_fmg(self.ctx, cycles_per_level), self.ctx)
 
     def graph_launches(self) -> int:
         n = C.c_longlong()

@@ -367,3 +367,47 @@ def test_w_cycle_mixed_solve_matches_oracle(mg):
     print(f"W mixed: steps {steps} (oracle {len(hist) - 1}) relres {rel:.3e} vs oracle {rel_max(u, u_ref):.2e}",
           flush=True)
     assert code == mg.MG_OK and abs(steps - (len(hist) - 1)) <= 1 and rel_max(u, u_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("dim,n,cent,sm,nu,cpl", [(2, 129, 0, "rbgs", 2, 1), (2, 129, 0, "jacobi", 2, 2),
+                                                 (3, 65, 0, "rbgs", 3, 2), (3, 32, 1, "rbgs", 3, 1)])
+def test_fmg_matches_oracle(mg, dim, n, cent, sm, nu, cpl):
+    if cent:
+        k = W.varcoef_k(n, 3)
+        f = W.normal_zero_mean(n, 3, W.SEED_F_VARCOEF)
+        p = cycle.Params(centering="cell", dim=3, n=n, coarsest=4, smoother=sm, nu1=nu, nu2=nu, k=k)
+        s = mg.Solver(3, n, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=nu, nu2=nu, k=k)
+    else:
+        f = W.interior_uniform(n, dim, W.SEED_F_3D)
+        p = cycle.Params(centering="node", dim=dim, n=n, smoother=sm, omega=0.8, nu1=nu, nu2=nu)
+        s = mg.Solver(dim, n, smoother=mg.MG_RBGS if sm == "rbgs" else mg.MG_JACOBI, omega=0.8, nu1=nu, nu2=nu)
+    s.set_rhs(f)
+    s.fmg(cpl)
+    u = s.solution()
+    s.close()
+    ref = cycle.fmg(cycle.build_hierarchy(p), f, cpl)
+    err = rel_max(u, ref)
+    print(f"FMG {dim}d n={n} cell={cent} {sm} nu={nu} x{cpl}: max rel diff {err:.3e}", flush=True)
+    assert err <= TOL_ITERATE
+
+
+def test_fmg_513_reaches_discretisation_accuracy(mg):
+    """513^3 sine problem: one FMG pass with two V(3,3)-cycles per level is
+    within 0.15 of the discretisation error of the closed-form discrete
+    solution c_h u (the property the oracle pins at 17^3 .. 65^3)."""
+    import torch
+    n = 513
+    ue = torch.from_numpy(W.sine_mode(n, 3)).cuda()
+    f = 3 * np.pi ** 2 * ue
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
+    s.set_rhs(f)
+    s.fmg(2)
+    u = torch.empty_like(f)
+    s.solution(u)
+    rel = s.residual_norm() / float(torch.linalg.vector_norm(f[1:-1, 1:-1, 1:-1]))
+    s.close()
+    hh = 1.0 / (n - 1)
+    ch = (np.pi * hh / 2) ** 2 / np.sin(np.pi * hh / 2) ** 2
+    alg = float((u - ch * ue).abs().max()) / abs(ch - 1.0)
+    print(f"FMG 513^3: algebraic / discretisation error {alg:.3f}, relres {rel:.3e}", flush=True)
+    assert alg < 0.15
