@@ -193,6 +193,50 @@ def fmg(h: Hierarchy, f, cycles_per_level: int = 1):
     return u
 
 
+def apply_operator(h: Hierarchy, u):
+    """A u on the finest level (0 on node boundaries)."""
+    return -residual(h, 0, u, np.zeros_like(u))
+
+
+def dot(h: Hierarchy, a, b) -> float:
+    """Euclidean inner product over the finest level's unknowns."""
+    ua = np.asarray(unknowns(h, a), dtype=np.float64)
+    ub = np.asarray(unknowns(h, b), dtype=np.float64)
+    return float(np.sum(ua * ub))
+
+
+def pcg(h: Hierarchy, f, u0=None, tol=1e-10, max_it=100, precondition=True):
+    """Conjugate gradients for A u = f preconditioned by one cycle from zero
+    (Trottenberg et al., Sec. 7.8; Saad, Iterative Methods for Sparse Linear
+    Systems, Alg. 9.1).  The cycle is a symmetric positive definite
+    preconditioner when nu1 = nu2 and post-smoothing is the adjoint of
+    pre-smoothing (red-black GS: the reverse colour order).  With
+    precondition=False it is plain CG.  Returns (u, relres history)."""
+    u = np.zeros_like(f) if u0 is None else u0.copy()
+    r = residual(h, 0, u, f)
+    prec = (lambda v: vcycle(h, np.zeros_like(v), v)) if precondition else (lambda v: v.copy())
+    z = prec(r)
+    p = z.copy()
+    rho = dot(h, r, z)
+    r0 = np.sqrt(dot(h, r, r))
+    hist = [1.0]
+    for _ in range(max_it):
+        if r0 == 0.0 or hist[-1] <= tol:
+            break
+        q = apply_operator(h, p)
+        alpha = rho / dot(h, p, q)
+        u = u + alpha * p
+        r = r - alpha * q
+        hist.append(np.sqrt(dot(h, r, r)) / r0)
+        if hist[-1] <= tol:
+            break
+        z = prec(r)
+        rho_new = dot(h, r, z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return u, hist
+
+
 def residual_norm(h: Hierarchy, u, f) -> float:
     r = residual(h, 0, u, f)
     ru = np.asarray(unknowns(h, r), dtype=np.float64)

@@ -6,7 +6,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import cycle, node
+from oracle import cell, cycle, node
 from paper_1904_08684_amd import workloads as W
 from tests.test_oracle_node import dst_solve
 
@@ -270,3 +270,63 @@ def test_fmg_reaches_discretisation_accuracy_3d():
 def test_fmg_more_cycles_approach_the_discrete_solution():
     r = [_fmg_errors(2, 65, "jacobi", 2, c) for c in (1, 2, 3)]
     assert r[0] > r[1] > r[2], r
+
+
+# ----------------------------------------------- multigrid-preconditioned CG
+
+def test_vcycle_preconditioner_symmetric_with_reversed_post_order():
+    """b . M a = a . M b for the V(2,2) cycle from zero when post-smoothing runs
+    the colours in reverse (black, red); with red-first post-smoothing it is
+    not symmetric."""
+    gaps = {}
+    for post in ((1, 0), (0, 1)):
+        h = cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=17, smoother="rbgs", nu1=2, nu2=2,
+                                               post_order=post))
+        a = W.interior_uniform(17, 2, 1)
+        b = W.interior_uniform(17, 2, 2)
+        ma = cycle.vcycle(h, np.zeros_like(a), a)
+        mb = cycle.vcycle(h, np.zeros_like(b), b)
+        gaps[post] = abs(cycle.dot(h, b, ma) - cycle.dot(h, a, mb)) / abs(cycle.dot(h, b, ma))
+    assert gaps[(1, 0)] < 1e-14 and gaps[(0, 1)] > 1e-6, gaps
+
+
+def test_plain_cg_terminates_within_m_steps():
+    n = 9
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=n, smoother="rbgs", nu1=1, nu2=1,
+                                           post_order=(1, 0)))
+    f = W.interior_uniform(n, 2, 3)
+    u, hist = cycle.pcg(h, f, tol=1e-13, max_it=200, precondition=False)
+    assert len(hist) - 1 <= (n - 2) ** 2 and hist[-1] <= 1e-13
+
+
+@pytest.mark.parametrize("centering", ["node", "cell"])
+def test_pcg_reaches_dense_solution(centering):
+    if centering == "node":
+        n = 17
+        p = cycle.Params(centering="node", dim=2, n=n, smoother="rbgs", nu1=2, nu2=2, post_order=(1, 0))
+        f = W.interior_uniform(n, 2, 9)
+        A = node.dense_matrix(n, 2)
+        c = node.interior(2)
+    else:
+        n = 8
+        k = W.varcoef_k(n, 3)
+        p = cycle.Params(centering="cell", dim=3, n=n, coarsest=4, smoother="rbgs", nu1=2, nu2=2,
+                         post_order=(1, 0), k=k)
+        f = W.normal_zero_mean(n, 3, 9)
+        h0 = cycle.build_hierarchy(p)
+        A = cell.dense_matrix(h0.beta[0], n, 3)
+        c = (slice(None),) * 3
+    h = cycle.build_hierarchy(p)
+    u, hist = cycle.pcg(h, f, tol=1e-14, max_it=60)
+    ud = np.linalg.solve(A, f[c].reshape(-1))
+    assert np.max(np.abs(u[c].reshape(-1) - ud)) <= 1e-12 * np.max(np.abs(ud))
+
+
+def test_pcg_needs_fewer_iterations_than_stationary_cycles():
+    n = 33
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=2, nu2=2,
+                                           post_order=(1, 0)))
+    f = W.interior_uniform(n, 3, 1)
+    _, hp = cycle.pcg(h, f, tol=1e-10)
+    _, hm, _ = cycle.solve(h, f, tol=1e-10)
+    assert len(hp) < len(hm), (len(hp), len(hm))
