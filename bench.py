@@ -91,8 +91,10 @@ def cpu_baseline(n_sample: int = 257):
 
 def other_configs(mg, W, torch, np):
     """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound), the
-    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10), and W-
-    and F-cycle solves of the 513^3 Poisson problem."""
+    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10), W- and
+    F-cycle solves of the 513^3 Poisson problem, conjugate gradients with the
+    V-cycle as preconditioner on it, and full multigrid on a 513^3 problem
+    with a closed-form discrete solution."""
     res = {}
     n = 129
     s = mg.Solver(2, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2)
@@ -137,7 +139,27 @@ def other_configs(mg, W, torch, np):
         s.close()
     res["varcoef_cell_256_mixed"]["max_rel_diff_vs_fp64_solution"] = float(
         (sols["mixed"] - sols["fp64"]).abs().max() / sols["fp64"].abs().max())
-    sols = None
+    # the same problem by CG preconditioned with the symmetric V(3,3)-cycle
+    s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, k=k, krylov=1)
+    s.set_rhs(f)
+    s.set_initial(None)
+    s.pcg(1e-10, 40)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        s.set_initial(None)
+        t = time.perf_counter()
+        code, its, rel = s.pcg(1e-10, 40)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    u = torch.empty((N, N, N), dtype=torch.float64, device="cuda")
+    s.solution(u)
+    res["varcoef_cell_256_pcg_fp64"] = {"ms_to_1e-10": round(1e3 * min(times), 3), "iterations": its,
+                                        "relres": rel, "status": code,
+                                        "max_rel_diff_vs_fp64_solution": float(
+                                            (u - sols["fp64"]).abs().max() / sols["fp64"].abs().max())}
+    s.close()
+    sols = u = None
     # W- and F-cycles on the 513^3 problem (same kernels, cycle index 2 / F-recursion)
     n = 513
     f3 = torch.from_numpy(W.interior_uniform(n, 3, W.SEED_F_3D)).cuda()
@@ -158,6 +180,45 @@ def other_configs(mg, W, torch, np):
         res[f"poisson3d_513_{name}cycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
                                                  "status": code_, "ms_per_cycle": round(1e3 * dt / cyc, 3)}
         s.close()
+    # conjugate gradients preconditioned by the symmetric V(3,3)-cycle
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, krylov=1)
+    s.set_rhs(f3)
+    s.set_initial(None)
+    s.pcg(1e-10, 40)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        s.set_initial(None)
+        t = time.perf_counter()
+        code_, its, rel = s.pcg(1e-10, 40)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    dt = min(times)
+    res["poisson3d_513_pcg_vcycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "iterations": its, "relres": rel,
+                                            "status": code_, "ms_per_iteration": round(1e3 * dt / its, 3)}
+    s.close()
+    # full multigrid on the sine problem, whose discrete solution is known in
+    # closed form: one pass with two V(3,3)-cycles per level
+    ue = torch.from_numpy(W.sine_mode(n, 3)).cuda()
+    fs = 3 * np.pi ** 2 * ue
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
+    s.set_rhs(fs)
+    s.fmg(2)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t = time.perf_counter()
+        s.fmg(2)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    u = torch.empty_like(fs)
+    s.solution(u)
+    hh = 1.0 / (n - 1)
+    ch = (np.pi * hh / 2) ** 2 / np.sin(np.pi * hh / 2) ** 2
+    res["fmg_513_sine_fp64"] = {"ms": round(1e3 * min(times), 3), "cycles_per_level": 2,
+                                "algebraic_over_discretisation_error": float((u - ch * ue).abs().max()) / abs(ch - 1.0),
+                                "relres": s.residual_norm() / float(torch.linalg.vector_norm(fs[1:-1, 1:-1, 1:-1]))}
+    s.close()
     return res
 
 

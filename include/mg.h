@@ -94,7 +94,8 @@ typedef struct mg_bc {
  * continuing from the first) or MG_CYCLE_F (an F-cycle from zero, then a
  * V-cycle, on each coarser level); a level directly above the coarsest is
  * visited once (Trottenberg, Oosterlee, Schueller, Multigrid, Sec. 2.4).
- * The solve server runs V-cycles only. */
+ * The solve server runs V-cycles only.  krylov = 1 reserves the vectors of
+ * mg_pcg (five FP64 fields of the finest level; FP64 contexts). */
 typedef struct mg_opts {
     int smoother;
     double omega;
@@ -103,6 +104,7 @@ typedef struct mg_opts {
     int max_cycles;
     int post_order;
     int cycle;
+    int krylov;
 } mg_opts;
 
 typedef struct mg_ctx mg_ctx;
@@ -146,6 +148,16 @@ int mg_vcycle(mg_ctx* c, int ncycles);
  * Overwrites the coarse levels' fields.  FP64 contexts only (MG_EINVAL
  * otherwise); asynchronous. */
 int mg_fmg(mg_ctx* c, int cycles_per_level);
+
+/* Conjugate gradients preconditioned by one cycle from zero (Saad, Iterative
+ * Methods for Sparse Linear Systems, Alg. 9.1; Trottenberg et al. Sec. 7.8),
+ * from the current iterate until ||f - A u||_2 / ||f - A u0||_2 <= tol or
+ * max_it iterations; the result becomes the iterate and f is kept.  The
+ * cycle must be symmetric: nu1 = nu2 and, with red-black GS, post_order = 1
+ * (MG_EINVAL otherwise, and without krylov = 1 in the options).  FP64
+ * contexts; synchronous (one 16-byte read-back per iteration).  Returns
+ * MG_OK, MG_ENOTCONV or MG_ENONFINITE; the history is kept for mg_history. */
+int mg_pcg(mg_ctx* c, double tol, int max_it, int* its_out, double* relres_out);
 
 /* Cycle until ||f - A u||_2 / ||f - A u0||_2 <= tol over the unknowns;
  * synchronous.  Returns MG_OK, MG_ENOTCONV, MG_ENONFINITE or MG_EDIVERGED;

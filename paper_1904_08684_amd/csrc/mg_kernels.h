@@ -77,6 +77,18 @@ long long field_quads(const Geom& g);
 
 // Zero `bytes` bytes (a kernel, not a memset, so the call is graph-capturable).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+// Preconditioned-CG vector operations over whole FP64 level fields (bytes a
+// multiple of 16).  launch_dot writes dot_blocks(bytes) partial pairs (sum, 0)
+// for launch_reduce; sc points to device scalars: sc[0] = rho, sc[2] = p . q,
+// sc[4] = rho_new.
+long long dot_blocks(size_t bytes);
+hipError_t launch_dot(const double* a, const double* b, size_t bytes, double* partials, hipStream_t st);
+hipError_t launch_pcg_step(double* x, const double* p, double* r, const double* q, const double* sc, size_t bytes,
+                           hipStream_t st);
+hipError_t launch_pcg_dir(double* p, const double* z, const double* sc, size_t bytes, hipStream_t st);
+hipError_t launch_scalar_copy(double* dst, const double* src, hipStream_t st);
 
 // Iteration space of the point-per-thread kernels over one or both colours.
 Space level_space(const Geom& g, int ncol, int col0);

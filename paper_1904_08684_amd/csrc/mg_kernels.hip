@@ -1381,6 +1381,67 @@ __global__ __launch_bounds__(256) void k_update(long long n4, double* __restrict
     d_update(ex, n4, u, c32, sigma_p);
 }
 
+// ------------------------------------------------ preconditioned CG vectors
+// Flat FP64 kernels over whole level fields (boundary nodes and padding are
+// zero in every vector involved, so they add nothing).  The dot product uses
+// a fixed grid of at most kDotBlocks blocks striding over the field: a fixed
+// assignment of elements to threads, hence a deterministic sum.
+constexpr int kDotBlocks = 2048;
+
+__global__ __launch_bounds__(256) void k_dot(long long n2, const double* __restrict__ a,
+                                             const double* __restrict__ b, double* __restrict__ part) {
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long long)gridDim.x * 256) {
+        const double2 x = reinterpret_cast<const double2*>(a)[i];
+        const double2 y = reinterpret_cast<const double2*>(b)[i];
+        acc = acc + x.x * y.x;
+        acc = acc + x.y * y.y;
+    }
+    block_sum_max(acc, 0.0, part + 2 * (long long)blockIdx.x);
+}
+
+// x += alpha p, r += alpha q with q = -A p and alpha = rho / (p . A p):
+// sc[0] = rho, sc[2] = p . q
+__global__ __launch_bounds__(256) void k_pcg_step(long long n2, double* __restrict__ x, const double* __restrict__ p,
+                                                  double* __restrict__ r, const double* __restrict__ q,
+                                                  const double* __restrict__ sc) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n2) return;
+    const double alpha = -(sc[0] / sc[2]);
+    const double2 pv = reinterpret_cast<const double2*>(p)[i];
+    const double2 qv = reinterpret_cast<const double2*>(q)[i];
+    double2 xv = reinterpret_cast<double2*>(x)[i];
+    double2 rv = reinterpret_cast<double2*>(r)[i];
+    xv.x = xv.x + alpha * pv.x;
+    xv.y = xv.y + alpha * pv.y;
+    rv.x = rv.x + alpha * qv.x;
+    rv.y = rv.y + alpha * qv.y;
+    reinterpret_cast<double2*>(x)[i] = xv;
+    reinterpret_cast<double2*>(r)[i] = rv;
+}
+
+// p = z + beta p with beta = rho_new / rho: sc[4] = rho_new, sc[0] = rho
+__global__ __launch_bounds__(256) void k_pcg_dir(long long n2, double* __restrict__ p, const double* __restrict__ z,
+                                                 const double* __restrict__ sc) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n2) return;
+    const double beta = sc[4] / sc[0];
+    const double2 zv = reinterpret_cast<const double2*>(z)[i];
+    double2 pv = reinterpret_cast<double2*>(p)[i];
+    pv.x = zv.x + beta * pv.x;
+    pv.y = zv.y + beta * pv.y;
+    reinterpret_cast<double2*>(p)[i] = pv;
+}
+
+__global__ void k_scalar_copy(double* __restrict__ dst, const double* __restrict__ src) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+__global__ __launch_bounds__(256) void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, long long n16) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, long long n16) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -1960,6 +2021,47 @@ hipError_t launch_update(const Geom& g, double* u64, const float* c32, const dou
                          hipStream_t st) {
     const long long n4 = field_quads(g);
     k_update<<<(unsigned)((n4 + 255) / 256), 256, 0, st>>>(n4, u64, c32, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const long long n16 = (long long)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    k_copy<<<(unsigned)((n16 + 255) / 256), 256, 0, st>>>(static_cast<uint4*>(dst), static_cast<const uint4*>(src),
+                                                          n16);
+    return hipGetLastError();
+}
+
+long long dot_blocks(size_t bytes) {
+    const long long n2 = (long long)(bytes / 16);
+    const long long nb = (n2 + 255) / 256;
+    return nb < kDotBlocks ? (nb > 0 ? nb : 1) : kDotBlocks;
+}
+
+hipError_t launch_dot(const double* a, const double* b, size_t bytes, double* partials, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    k_dot<<<(unsigned)dot_blocks(bytes), 256, 0, st>>>((long long)(bytes / 16), a, b, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_step(double* x, const double* p, double* r, const double* q, const double* sc, size_t bytes,
+                           hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const long long n2 = (long long)(bytes / 16);
+    k_pcg_step<<<(unsigned)((n2 + 255) / 256), 256, 0, st>>>(n2, x, p, r, q, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir(double* p, const double* z, const double* sc, size_t bytes, hipStream_t st) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const long long n2 = (long long)(bytes / 16);
+    k_pcg_dir<<<(unsigned)((n2 + 255) / 256), 256, 0, st>>>(n2, p, z, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scalar_copy(double* dst, const double* src, hipStream_t st) {
+    k_scalar_copy<<<1, 64, 0, st>>>(dst, src);
     return hipGetLastError();
 }
 

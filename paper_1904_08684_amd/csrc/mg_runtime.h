@@ -31,6 +31,7 @@ struct Plan {
     std::vector<LevelPlan> lv;
     long long partial_pairs = 0;
     size_t partials = 0, reduce_scratch = 0, red = 0, chol = 0, staging = 0, total = 0;
+    size_t pcg = SIZE_MAX;        // x, p, q, saved f, zero (finest FP64 fields), partials, scratch, scalars
 };
 
 // Workspace layout for a problem; returns the total byte count.
@@ -73,6 +74,11 @@ struct Ctx {
     double* red = nullptr;        // [sum r^2, max |r|, sigma]
     double* chol = nullptr;
     double* staging = nullptr;
+    // preconditioned CG (krylov = 1): finest-level FP64 vectors and scalars
+    void* pcg_v[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // x, p, q = -A p, saved f, zero
+    double* pcg_part = nullptr;
+    double* pcg_scratch = nullptr;
+    double* pcg_s = nullptr;      // [rho, -, p.q, -, rho_new, -, r.r, -]
     std::vector<double> hist;
     std::string err;
     std::vector<std::vector<double>> coarse_beta_host;
@@ -109,6 +115,7 @@ struct Ctx {
     int vcycle(int l, int pr, bool from_zero);
     int cycle(int l, int pr, bool from_zero, int kind);
     int fmg(int cpl);
+    int pcg(double tol, int max_it, int* its_out, double* relres_out);
     int refine_step();
     int read_red(double* sq, double* mx);
     int norm(double* out);

@@ -88,6 +88,8 @@ int validate(const mg_grid* g, const mg_stencil* st, const mg_opts* o, std::stri
     if (o->max_cycles < 1) return bad("max_cycles must be >= 1");
     if (o->post_order != 0 && o->post_order != 1) return bad("post_order must be 0 or 1");
     if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) return bad("unknown cycle type");
+    if (o->krylov != 0 && o->krylov != 1) return bad("krylov must be 0 or 1");
+    if (o->krylov && o->precision != MG_FP64) return bad("krylov vectors need an FP64 context");
     return MG_OK;
 }
 
@@ -154,6 +156,10 @@ size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, 
     p.chol = take((size_t)p.m * p.m * 8);
     const long long nat = (long long)g0.n * g0.n * (g->dim == 3 ? g0.n : 1);
     p.staging = staging ? take((size_t)nat * 8) : SIZE_MAX;
+    if (o->krylov) {
+        const size_t fb = (size_t)(2 * g0.cs) * 8;
+        p.pcg = take(5 * align_up(fb) + (size_t)(dot_blocks(fb) + reduce_scratch_pairs(dot_blocks(fb))) * 16 + 64);
+    }
     p.total = off;
     if (out) *out = p;
     return off;
@@ -849,6 +855,88 @@ Ctx::~Ctx() {
     if (h_red) (void)hipHostFree(h_red);
 }
 
+// Preconditioned conjugate gradients; r lives in the finest f (so the
+// preconditioner is a cycle from zero on that level, z in the finest u).
+int Ctx::pcg(double tol, int max_it, int* its_out, double* relres_out) {
+    Level& L0 = lv[0];
+    const size_t fb = L0.field_bytes[0];
+    double* x = static_cast<double*>(pcg_v[0]);
+    double* p = static_cast<double*>(pcg_v[1]);
+    double* q = static_cast<double*>(pcg_v[2]);
+    double* fs = static_cast<double*>(pcg_v[3]);
+    const double* zero = static_cast<const double*>(pcg_v[4]);
+    const long long nd = dot_blocks(fb);
+    auto dotp = [&](const void* a, const void* b, double* out) -> int {
+        hipEvent_t e0 = begin();
+        int rc = record(MG_K_REDUCE, 0, launch_dot(static_cast<const double*>(a), static_cast<const double*>(b), fb,
+                                                   pcg_part, stream), e0, "dot");
+        return rc ? rc : dev(launch_reduce(pcg_part, nd, pcg_scratch, out, stream), "dot reduce");
+    };
+    auto residual_into = [&](const void* u, const void* f, void* r) -> int {
+        long long nb = 0;
+        hipEvent_t e0 = begin();
+        return record(MG_K_RESIDUAL, 0,
+                      launch_residual(L0.g, 0, u, f, r, faces(0, 0), scale(0), false, true, partials, &nb, stream),
+                      e0, "residual");
+    };
+    auto host = [&](const double* d, double* h) -> int {
+        int rc = dev(hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, stream), "read scalar");
+        return rc ? rc : dev(hipStreamSynchronize(stream), "sync");
+    };
+    hist.clear();
+    int rc = dev(launch_copy(fs, L0.f[0], fb, stream), "save f");
+    if (!rc) rc = dev(launch_copy(x, L0.u[0], fb, stream), "iterate");
+    if (!rc) rc = residual_into(x, fs, L0.f[0]);                  // r = f - A x
+    double rr0 = 0.0;
+    if (!rc) rc = dotp(L0.f[0], L0.f[0], pcg_s + 6);
+    if (!rc) rc = host(pcg_s + 6, &rr0);
+    if (rc) return rc;
+    const double r0 = std::sqrt(rr0);
+    if (!std::isfinite(r0)) return fail(MG_ENONFINITE, "initial residual is not finite");
+    hist.push_back(1.0);
+    int its = 0, status = MG_OK;
+    double rel = 1.0;
+    if (r0 > 0.0 && rel > tol) {
+        rc = vcycle(0, 0, true);                                    // z = M r
+        if (!rc) rc = dev(launch_copy(p, L0.u[0], fb, stream), "p = z");
+        if (!rc) rc = dotp(L0.f[0], L0.u[0], pcg_s + 0);            // rho = r . z
+        while (!rc) {
+            if (its == max_it) {
+                status = MG_ENOTCONV;
+                err = "max_it reached";
+                break;
+            }
+            rc = residual_into(p, zero, q);                          // q = -A p
+            if (!rc) rc = dotp(p, q, pcg_s + 2);
+            if (!rc) rc = dev(launch_pcg_step(x, p, static_cast<double*>(L0.f[0]), q, pcg_s, fb, stream), "x, r");
+            double rr = 0.0;
+            if (!rc) rc = dotp(L0.f[0], L0.f[0], pcg_s + 6);
+            if (!rc) rc = host(pcg_s + 6, &rr);
+            if (rc) break;
+            ++its;
+            rel = std::sqrt(rr) / r0;
+            hist.push_back(rel);
+            if (!std::isfinite(rel)) {
+                status = fail(MG_ENONFINITE, "residual norm is not finite");
+                break;
+            }
+            if (rel <= tol) break;
+            rc = vcycle(0, 0, true);                                 // z = M r
+            if (!rc) rc = dotp(L0.f[0], L0.u[0], pcg_s + 4);         // rho_new = r . z
+            if (!rc) rc = dev(launch_pcg_dir(p, static_cast<const double*>(L0.u[0]), pcg_s, fb, stream), "p");
+            if (!rc) rc = dev(launch_scalar_copy(pcg_s + 0, pcg_s + 4, stream), "rho");
+        }
+    }
+    // the solution becomes the iterate, f is restored
+    if (!rc) rc = dev(launch_copy(L0.u[0], x, fb, stream), "solution");
+    if (!rc) rc = dev(launch_copy(L0.f[0], fs, fb, stream), "restore f");
+    if (!rc) rc = dev(hipStreamSynchronize(stream), "sync");
+    if (rc) return rc;
+    if (its_out) *its_out = its;
+    if (relres_out) *relres_out = r0 == 0.0 ? 0.0 : rel;
+    return status;
+}
+
 int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
     hist.clear();
     double r0;
@@ -931,6 +1019,14 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
     c->reduce_scratch = static_cast<double*>(c->at(plan.reduce_scratch));
     c->red = static_cast<double*>(c->at(plan.red));
     c->chol = static_cast<double*>(c->at(plan.chol));
+    if (plan.pcg != SIZE_MAX) {
+        const size_t fb = align_up((size_t)(2 * plan.lv[0].g.cs) * 8);
+        char* b = static_cast<char*>(c->at(plan.pcg));
+        for (int i = 0; i < 5; ++i) c->pcg_v[i] = b + i * fb;
+        c->pcg_part = reinterpret_cast<double*>(b + 5 * fb);
+        c->pcg_scratch = c->pcg_part + 2 * dot_blocks((size_t)(2 * plan.lv[0].g.cs) * 8);
+        c->pcg_s = c->pcg_scratch + 2 * reduce_scratch_pairs(dot_blocks((size_t)(2 * plan.lv[0].g.cs) * 8));
+    }
     c->staging = static_cast<double*>(c->at(plan.staging));
     for (int l = 0; l < plan.L; ++l) {
         const LevelPlan& lp = plan.lv[l];
@@ -1029,6 +1125,7 @@ void mg_default_opts(mg_opts* o) {
     o->max_cycles = 100;
     o->post_order = 0;
     o->cycle = MG_CYCLE_V;
+    o->krylov = 0;
 }
 
 int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes) {
@@ -1125,6 +1222,16 @@ int mg_fmg(mg_ctx* h, int cycles_per_level) {
     if (!c || cycles_per_level < 1) return MG_EINVAL;
     if (c->opts.precision != MG_FP64) return c->fail(MG_EINVAL, "full multigrid runs in FP64 contexts");
     return c->fmg(cycles_per_level);
+}
+
+int mg_pcg(mg_ctx* h, double tol, int max_it, int* its_out, double* relres_out) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c || !(tol >= 0.0) || max_it < 1) return MG_EINVAL;
+    if (!c->pcg_s) return c->fail(MG_EINVAL, "mg_pcg needs a context set up with krylov = 1");
+    const mg_opts& o = c->opts;
+    if (o.nu1 != o.nu2 || (o.smoother == MG_RBGS && o.post_order != 1))
+        return c->fail(MG_EINVAL, "the preconditioner must be symmetric: nu1 = nu2, and post_order = 1 with RB-GS");
+    return c->pcg(tol, max_it, its_out, relres_out);
 }
 
 int mg_solve(mg_ctx* h, double tol, int* cycles_out, double* relres_out) {

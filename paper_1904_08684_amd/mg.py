@@ -53,7 +53,8 @@ class mg_bc(C.Structure):
 
 class mg_opts(C.Structure):
     _fields_ = [("smoother", C.c_int), ("omega", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("precision", C.c_int), ("max_cycles", C.c_int), ("post_order", C.c_int), ("cycle", C.c_int)]
+                ("precision", C.c_int), ("max_cycles", C.c_int), ("post_order", C.c_int), ("cycle", C.c_int),
+                ("krylov", C.c_int)]
 
 
 _P = C.c_void_p
@@ -72,6 +73,7 @@ _sigs = {
     "mg_vcycle": (C.c_int, [_P, C.c_int]),
     "mg_solve": (C.c_int, [_P, C.c_double, C.POINTER(C.c_int), _D]),
     "mg_fmg": (C.c_int, [_P, C.c_int]),
+    "mg_pcg": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int), _D]),
     "mg_residual_norm": (C.c_int, [_P, _D]),
     "mg_history": (C.c_int, [_P, _D, C.c_int, C.POINTER(C.c_int)]),
     "mg_levels": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -117,10 +119,10 @@ def make_grid(dim: int, n: int, centering: int = MG_NODE, coarsest: int | None =
 
 
 def make_opts(smoother=MG_RBGS, omega=0.8, nu1=2, nu2=2, precision=MG_FP64, max_cycles=100,
-              post_order=0, cycle=0) -> mg_opts:
+              post_order=0, cycle=0, krylov=0) -> mg_opts:
     o = mg_opts()
     o.smoother, o.omega, o.nu1, o.nu2 = smoother, omega, nu1, nu2
-    o.precision, o.max_cycles, o.post_order, o.cycle = precision, max_cycles, post_order, cycle
+    o.precision, o.max_cycles, o.post_order, o.cycle, o.krylov = precision, max_cycles, post_order, cycle, krylov
     return o
 
 
@@ -151,11 +153,12 @@ class Solver:
     def __init__(self, dim: int, n: int, centering: int = MG_NODE, coarsest: int | None = None,
                  smoother: int = MG_RBGS, omega: float = 0.8, nu1: int = 2, nu2: int = 2,
                  precision: int = MG_FP64, max_cycles: int = 100, post_order: int = 0, cycle: int = 0,
+                 krylov: int = 0,
                  k=None, stream=None, device: str = "cuda"):
         import torch
         self.dim, self.n, self.centering = dim, n, centering
         self.grid = make_grid(dim, n, centering, coarsest)
-        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order, cycle)
+        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order, cycle, krylov)
         self.stencil = mg_stencil()
         self._k = None
         if k is not None:
@@ -264,6 +267,15 @@ class Solver:
     def fmg(self, cycles_per_level: int = 1):
         """Full multigrid from the right-hand side; the result becomes the iterate."""
         _check(mg_fmg(self.ctx, cycles_per_level), self.ctx)
+
+    def pcg(self, tol: float, max_it: int = 100):
+        """Multigrid-preconditioned CG from the current iterate; returns (code, iterations, relres)."""
+        its = C.c_int()
+        rel = C.c_double()
+        code = mg_pcg(self.ctx, tol, max_it, C.byref(its), C.byref(rel))
+        if code not in (MG_OK, MG_ENOTCONV, MG_ENONFINITE):
+            _check(code, self.ctx)
+        return code, its.value, rel.value
 
     def graph_launches(self) -> int:
         n = C.c_longlong()

@@ -88,7 +88,8 @@ def test_bad_options_rejected(mg):
     g = mg.make_grid(2, 129)
     b = C.c_size_t()
     for kw in ({"nu1": 0, "nu2": 0}, {"omega": 0.0}, {"omega": 2.5}, {"max_cycles": 0},
-               {"smoother": 7}, {"precision": 3}, {"post_order": 2}):
+               {"smoother": 7}, {"precision": 3}, {"post_order": 2}, {"cycle": 3}, {"krylov": 2},
+               {"krylov": 1, "precision": 1}):
         o = mg.make_opts(**kw)
         assert mg.mg_workspace_bytes(C.byref(g), None, C.byref(o), C.byref(b)) == mg.MG_EINVAL, kw
 
@@ -102,6 +103,9 @@ def test_workspace_scales_with_problem(mg):
     # FP64: u, f, r on ~8/7 of the finest size + staging; mixed adds FP32 fields
     assert 4 * 8 * n < b64 < 6 * 8 * n
     assert b64 < bmx < b64 + 3 * 4 * n * 1.3
+    # the Krylov vectors add five finest-level FP64 fields
+    bk = mg.workspace_bytes(mg.make_grid(3, 513), mg.make_opts(precision=mg.MG_FP64, krylov=1))
+    assert 5 * 8 * n < bk - b64 < 5 * 8 * n * 1.1
     # Jacobi adds a double buffer
     bj = mg.workspace_bytes(mg.make_grid(2, 129), mg.make_opts(smoother=mg.MG_JACOBI))
     br = mg.workspace_bytes(mg.make_grid(2, 129), mg.make_opts(smoother=mg.MG_RBGS))
@@ -127,4 +131,5 @@ def test_null_safety(mg):
     mg.mg_destroy(None)
     assert mg.mg_vcycle(None, 1) == mg.MG_EINVAL
     assert mg.mg_solve(None, 1e-10, None, None) == mg.MG_EINVAL
+    assert mg.mg_pcg(None, 1e-10, 10, None, None) == mg.MG_EINVAL
     assert mg.mg_set_rhs(None, None, 0) == mg.MG_EINVAL

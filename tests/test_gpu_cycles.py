@@ -411,3 +411,111 @@ def test_fmg_513_reaches_discretisation_accuracy(mg):
     alg = float((u - ch * ue).abs().max()) / abs(ch - 1.0)
     print(f"FMG 513^3: algebraic / discretisation error {alg:.3f}, relres {rel:.3e}", flush=True)
     assert alg < 0.15
+
+
+# CG's step lengths come from dot products summed in another order, so each
+# update alpha p carries a relative rounding difference; measured against
+# the size of the total correction u - u0 (of order |u0| = 1 here, while the
+# solution is of order 1e-3), the bar is the per-iterate one of the cycles.
+TOL_PCG = 1e-12
+
+
+@pytest.mark.parametrize("dim,n,cent,sm,nu,its", [(2, 129, 0, "jacobi", 2, 5), (3, 65, 0, "rbgs", 2, 4),
+                                                 (3, 257, 0, "rbgs", 3, 3), (3, 32, 1, "rbgs", 2, 4)])
+def test_pcg_iterates_match_oracle(mg, dim, n, cent, sm, nu, its):
+    """Multigrid-preconditioned CG against the oracle's after a fixed number
+    of iterations (tol 0: stops at max_it), with the residual history.  The
+    257^3 case runs the fused sweeps inside the preconditioner."""
+    if cent:
+        k = W.varcoef_k(n, 3)
+        f = W.normal_zero_mean(n, 3, W.SEED_F_VARCOEF)
+        u0 = np.zeros_like(f)
+        p = cycle.Params(centering="cell", dim=3, n=n, coarsest=4, smoother=sm, nu1=nu, nu2=nu,
+                         post_order=(1, 0), k=k)
+        s = mg.Solver(3, n, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=nu, nu2=nu, post_order=1, k=k,
+                      krylov=1)
+    else:
+        f = W.interior_uniform(n, dim, W.SEED_F_3D)
+        u0 = W.interior_uniform(n, dim, W.SEED_U0_2D)
+        p = cycle.Params(centering="node", dim=dim, n=n, smoother=sm, omega=0.8, nu1=nu, nu2=nu,
+                         post_order=(1, 0))
+        s = mg.Solver(dim, n, smoother=mg.MG_RBGS if sm == "rbgs" else mg.MG_JACOBI, omega=0.8, nu1=nu, nu2=nu,
+                      post_order=1, krylov=1)
+    s.set_rhs(f)
+    s.set_initial(u0)
+    code, done, rel = s.pcg(0.0, its)
+    u = s.solution()
+    hist = s.history()
+    f_back = s.level_get(0, mg.MG_FIELD_F)
+    s.close()
+    u_ref, hist_ref = cycle.pcg(cycle.build_hierarchy(p), f, u0, tol=0.0, max_it=its)
+    err = float(np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref - u0)))
+    print(f"PCG {dim}d n={n} cell={cent} {sm} nu={nu} x{its}: max diff / max correction {err:.3e} "
+          f"(/ max solution {rel_max(u, u_ref):.3e}), relres {rel:.3e} (oracle {hist_ref[-1]:.3e})", flush=True)
+    assert code == mg.MG_ENOTCONV and done == its and len(hist) == its + 1
+    for a, b in zip(hist, hist_ref):
+        assert abs(a - b) <= 1e-9 * b
+    assert err <= TOL_PCG
+    assert np.array_equal(f_back, f)       # the right-hand side is restored
+
+
+def test_pcg_converges_and_resumes(mg):
+    """To a tolerance: the count matches the oracle's, the returned relres is
+    the recomputed one, and a second call from the result stops at once."""
+    n = 65
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=2, nu2=2, post_order=1, krylov=1)
+    s.set_rhs(f)
+    s.set_initial(None)
+    r0 = s.residual_norm()
+    code, its, rel = s.pcg(1e-10, 50)
+    rel_check = s.residual_norm() / r0
+    code2, its2, _ = s.pcg(1.0, 50)
+    s.close()
+    _, hist_ref = cycle.pcg(cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="rbgs",
+                                                               nu1=2, nu2=2, post_order=(1, 0))), f, tol=1e-10)
+    print(f"PCG 65^3: {its} iterations (oracle {len(hist_ref) - 1}), relres {rel:.3e} recomputed {rel_check:.3e}",
+          flush=True)
+    assert code == mg.MG_OK and its == len(hist_ref) - 1 and rel <= 1e-10
+    assert abs(rel_check - rel) <= 1e-3 * rel
+    assert code2 == mg.MG_OK and its2 == 0
+
+
+def test_pcg_rejects_nonsymmetric_cycles_and_missing_vectors(mg):
+    f = W.interior_uniform(33, 3, 5)
+    for kw in ({"nu1": 2, "nu2": 1, "post_order": 1, "krylov": 1}, {"nu1": 2, "nu2": 2, "post_order": 0, "krylov": 1},
+               {"nu1": 2, "nu2": 2, "post_order": 1, "krylov": 0}):
+        s = mg.Solver(3, 33, smoother=mg.MG_RBGS, **kw)
+        s.set_rhs(f)
+        s.set_initial(None)
+        with pytest.raises(RuntimeError):
+            s.pcg(1e-8, 10)
+        s.close()
+
+
+def test_pcg_513_converges_faster_than_cycles(mg):
+    """513^3 Poisson, V(3,3) symmetric preconditioner: converges to 1e-10 in
+    fewer iterations than stationary V-cycles need, the residual recomputed
+    independently on the CPU from the returned solution."""
+    import torch
+    n = 513
+    f = torch.from_numpy(W.interior_uniform(n, 3, W.SEED_F_3D)).cuda()
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, krylov=1)
+    s.set_rhs(f)
+    s.set_initial(None)
+    code, its, rel = s.pcg(1e-10, 40)
+    u = torch.empty_like(f)
+    s.solution(u)
+    s.set_initial(None)
+    code_v, cycles, _ = s.solve(1e-10)
+    s.close()
+    hh = 1.0 / (n - 1)
+    uc, fc = u.cpu().numpy(), f.cpu().numpy()
+    c = (slice(1, -1),) * 3
+    au = (6 * uc[c] - uc[2:, 1:-1, 1:-1] - uc[:-2, 1:-1, 1:-1] - uc[1:-1, 2:, 1:-1] - uc[1:-1, :-2, 1:-1]
+          - uc[1:-1, 1:-1, 2:] - uc[1:-1, 1:-1, :-2]) / hh ** 2
+    rel_cpu = float(np.linalg.norm(fc[c] - au) / np.linalg.norm(fc[c]))
+    print(f"PCG 513^3: {its} iterations (V-cycles {cycles}), relres {rel:.3e}, CPU recomputed {rel_cpu:.3e}",
+          flush=True)
+    assert code == mg.MG_OK and code_v == mg.MG_OK and its < cycles
+    assert rel_cpu <= 1.5e-10
