@@ -206,6 +206,30 @@ def test_fused_sweeps_equal_half_sweeps(mg, prec, nu, post):
     close(fused, ref.astype(np.float64), prec, f"fused {nu} sweeps 3d n={n} post={post} prec={prec}")
 
 
+@pytest.mark.parametrize("prec,nu", [(0, 3), (0, 2), (1, 1)])
+def test_fused_sweeps_513(mg, prec, nu):
+    """The fused passes at the full 513^3 size (five regions across x, the
+    last one partly outside the grid; two z chunks): bitwise equal to the
+    separate half-sweeps."""
+    n = 513
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=nu, nu2=nu, precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 3, 0, 700 + nu, dt)
+    f = rand(n, 3, 0, 750 + nu, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_PRESMOOTH, 0, prec)
+    fused = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    for _ in range(nu):
+        s.apply(mg.MG_OP_GS_RED, 0, prec)
+        s.apply(mg.MG_OP_GS_BLACK, 0, prec)
+    halves = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.close()
+    print(f"513^3 fused nu={nu} prec={prec}: bitwise {np.array_equal(fused, halves)}", flush=True)
+    assert np.array_equal(fused, halves)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_fused_paths_with_non_power_of_two_scale(mg, prec):
     """385^3 nodes with a 4-node coarsest level: s = 384^2 is not a power of
