@@ -1,5 +1,5 @@
 """Cell-centred variable-coefficient diffusion -div(k grad u) = f on [0, 1]^d
-with zero Dirichlet walls.
+with zero Dirichlet walls or homogeneous Neumann walls (zero flux).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -14,9 +14,14 @@ Operator (finite volumes, two-point fluxes):
     (A u)_i = s * (diag_i * u_i - off_i),   s = 1/h^2 = N^2,
     diag_i  = sum over the 2d faces of w_f * beta_f   (w_f = 2 on a wall),
     off_i   = sum over interior faces of beta_f * u_neighbour.
-A wall face uses the mirror ghost u_g = -u_i (zero value on the wall), which
-is what the weight 2 and the missing off-diagonal term express.  Face sums
-run in the order x-, x+, y-, y+, z-, z+.
+A Dirichlet wall face uses the mirror ghost u_g = -u_i (zero value on the
+wall), which is what the weight 2 and the missing off-diagonal term express.
+A Neumann wall face uses the even ghost u_g = u_i: its flux vanishes, so it
+has weight 0 and again no off-diagonal term; the operator then annihilates
+constants and the problem is solvable for right-hand sides of zero mean
+(Trottenberg et al., Sec. 5.6.4; the solution is fixed by zero mean).  Face
+sums run in the order x-, x+, y-, y+, z-, z+.  Functions taking ``bc`` accept
+"dirichlet" (default) or "neumann".
 """
 from __future__ import annotations
 
@@ -104,13 +109,18 @@ def _face_terms(u: np.ndarray, beta: list[np.ndarray]):
             yield bf, wall, nb
 
 
-def diagonal(beta: list[np.ndarray], shape, dtype) -> np.ndarray:
-    """diag_i = sum over faces of w_f beta_f, w_f = 2 on walls, 1 inside."""
+WALL_WEIGHT = {"dirichlet": 2, "neumann": 0}
+
+
+def diagonal(beta: list[np.ndarray], shape, dtype, bc: str = "dirichlet") -> np.ndarray:
+    """diag_i = sum over faces of w_f beta_f, w_f = 1 inside and on walls 2
+    (Dirichlet) or 0 (Neumann)."""
     t = np.dtype(dtype).type
+    w = t(WALL_WEIGHT[bc])
     dummy = np.zeros(shape, dtype=dtype)
     acc = None
     for bf, wall, _ in _face_terms(dummy, beta):
-        term = np.where(wall, t(2) * bf, bf).astype(dtype)
+        term = np.where(wall, w * bf, bf).astype(dtype)
         acc = term if acc is None else acc + term
     return acc
 
@@ -124,42 +134,48 @@ def off_sum(u: np.ndarray, beta: list[np.ndarray]) -> np.ndarray:
     return acc
 
 
-def apply_A(u: np.ndarray, beta: list[np.ndarray]) -> np.ndarray:
+def apply_A(u: np.ndarray, beta: list[np.ndarray], bc: str = "dirichlet") -> np.ndarray:
     s = scale(u.shape[0], u.dtype)
-    return (diagonal(beta, u.shape, u.dtype) * u - off_sum(u, beta)) * s
+    return (diagonal(beta, u.shape, u.dtype, bc) * u - off_sum(u, beta)) * s
 
 
-def residual(u: np.ndarray, f: np.ndarray, beta: list[np.ndarray]) -> np.ndarray:
+def residual(u: np.ndarray, f: np.ndarray, beta: list[np.ndarray], bc: str = "dirichlet") -> np.ndarray:
     """r = f - (diag u - off) s."""
     s = scale(u.shape[0], u.dtype)
-    return f - (diagonal(beta, u.shape, u.dtype) * u - off_sum(u, beta)) * s
+    return f - (diagonal(beta, u.shape, u.dtype, bc) * u - off_sum(u, beta)) * s
 
 
-def jacobi(u, f, beta, omega):
+def jacobi(u, f, beta, omega, bc: str = "dirichlet"):
     """u' = u + (omega r) / (diag s)."""
     t = u.dtype.type
     s = scale(u.shape[0], u.dtype)
-    r = residual(u, f, beta)
-    return u + (t(omega) * r) / (diagonal(beta, u.shape, u.dtype) * s)
+    r = residual(u, f, beta, bc)
+    return u + (t(omega) * r) / (diagonal(beta, u.shape, u.dtype, bc) * s)
 
 
 def colour_mask(N: int, d: int, colour: int) -> np.ndarray:
     return (np.indices((N,) * d).sum(axis=0) % 2) == colour
 
 
-def gs_colour(u, f, beta, colour) -> None:
+def gs_colour(u, f, beta, colour, bc: str = "dirichlet") -> None:
     """In place: u_i <- (f_i / s + off_i) / diag_i on cells of one colour."""
     s = scale(u.shape[0], u.dtype)
-    new = (f / s + off_sum(u, beta)) / diagonal(beta, u.shape, u.dtype)
+    new = (f / s + off_sum(u, beta)) / diagonal(beta, u.shape, u.dtype, bc)
     m = colour_mask(u.shape[0], u.ndim, colour)
     u[m] = new[m]
 
 
-def rbgs(u, f, beta, order=(0, 1)):
+def rbgs(u, f, beta, order=(0, 1), bc: str = "dirichlet"):
     out = u.copy()
     for c in order:
-        gs_colour(out, f, beta, c)
+        gs_colour(out, f, beta, c, bc)
     return out
+
+
+def project_mean(a: np.ndarray) -> np.ndarray:
+    """a minus its arithmetic mean over all cells: the component of a
+    orthogonal to the constants, the null space of the Neumann operator."""
+    return a - a.dtype.type(np.sum(a, dtype=np.float64) / a.size)
 
 
 def restrict_mean(r: np.ndarray) -> np.ndarray:
@@ -174,19 +190,22 @@ def restrict_mean(r: np.ndarray) -> np.ndarray:
     return acc * r.dtype.type(1.0 / 2 ** d)
 
 
-def prolong_trilinear(ec: np.ndarray) -> np.ndarray:
+def prolong_trilinear(ec: np.ndarray, bc: str = "dirichlet") -> np.ndarray:
     """Cell-centred (bi/tri)linear interpolation, the tensor product of the 1-D
     rule fine(2I) = 3/4 e[I] + 1/4 e[I-1], fine(2I+1) = 3/4 e[I] + 1/4 e[I+1]
-    with mirror ghosts e[-1] = -e[0], e[Nc] = -e[Nc-1]; applied along x first,
-    then y, then z.  In 3-D the weights are 27, 9, 3, 1 over 64."""
+    with ghosts beyond the walls: e[-1] = -e[0], e[Nc] = -e[Nc-1] (Dirichlet,
+    odd mirror) or e[-1] = e[0], e[Nc] = e[Nc-1] (Neumann, even mirror);
+    applied along x first, then y, then z.  In 3-D the weights are 27, 9, 3, 1
+    over 64."""
     d = ec.ndim
     t = ec.dtype.type
     a, b = t(0.75), t(0.25)
+    sg = t(-1) if bc == "dirichlet" else t(1)
     e = ec
     for ax in reversed(range(d)):
         Nc = e.shape[ax]
-        lo = np.concatenate([-e[_sl(d, ax, slice(0, 1))], e[_sl(d, ax, slice(0, Nc - 1))]], axis=ax)
-        hi = np.concatenate([e[_sl(d, ax, slice(1, Nc))], -e[_sl(d, ax, slice(Nc - 1, Nc))]], axis=ax)
+        lo = np.concatenate([sg * e[_sl(d, ax, slice(0, 1))], e[_sl(d, ax, slice(0, Nc - 1))]], axis=ax)
+        hi = np.concatenate([e[_sl(d, ax, slice(1, Nc))], sg * e[_sl(d, ax, slice(Nc - 1, Nc))]], axis=ax)
         shape = list(e.shape)
         shape[ax] = 2 * Nc
         out = np.empty(shape, dtype=e.dtype)
@@ -196,16 +215,16 @@ def prolong_trilinear(ec: np.ndarray) -> np.ndarray:
     return e
 
 
-def correct(u, ec):
-    return u + prolong_trilinear(ec)
+def correct(u, ec, bc: str = "dirichlet"):
+    return u + prolong_trilinear(ec, bc)
 
 
-def dense_matrix(beta: list[np.ndarray], N: int, d: int) -> np.ndarray:
+def dense_matrix(beta: list[np.ndarray], N: int, d: int, bc: str = "dirichlet") -> np.ndarray:
     """Dense FP64 A over the N^d cells (C order), column by column from unit vectors."""
     m = N ** d
     A = np.zeros((m, m))
     for j in range(m):
         e = np.zeros(m)
         e[j] = 1.0
-        A[:, j] = apply_A(e.reshape((N,) * d), beta).reshape(-1)
+        A[:, j] = apply_A(e.reshape((N,) * d), beta, bc).reshape(-1)
     return A

@@ -20,6 +20,13 @@ sides upcast and the result downcast.
 ``solve`` repeats cycles until ||r_k|| / ||r_0|| <= tol (the ExaSlang
 ``repeat ... until`` form), with the unweighted 2-norm over the unknowns.
 
+Cell grids with Neumann walls (``bc="neumann"``): the right-hand side is
+projected to zero mean when a solve starts and after every restriction, the
+coarsest level is solved by the minimum-norm least-squares solution (the
+zero-mean solution of the singular consistent system), interpolation uses
+even ghosts, and the finest iterate is projected to zero mean after every
+cycle, which fixes the constant the operator cannot see.
+
 ``mixed_solve`` is FP64 iterative refinement around single-precision
 V-cycles: r = f - A u in FP64, sigma = 2^floor(log2 max|r|), c = V32(0,
 fl32(r / sigma)), u <- u + sigma * fl64(c).  The power-of-two scale adds no
@@ -48,6 +55,7 @@ class Params:
     post_order: tuple = (0, 1)       # colour order of post-smoothing sweeps
     k: np.ndarray | None = None      # cell coefficients (cell grids); None = 1
     cycle: str = "V"                 # "V", "W" or "F"
+    bc: str = "dirichlet"            # "dirichlet", or "neumann" (cell grids)
 
 
 @dataclass
@@ -56,6 +64,7 @@ class Hierarchy:
     sizes: list
     beta: list = field(default_factory=list)       # per level, FP64 face lists (cell only)
     chol: np.ndarray | None = None                  # FP64 lower Cholesky factor, coarsest
+    dense: np.ndarray | None = None                 # FP64 coarsest matrix (Neumann: singular)
     _beta_cache: dict = field(default_factory=dict)
     coarse_solves: int = 0                          # coarsest solves performed (instrumentation)
 
@@ -88,17 +97,25 @@ def ladder(p: Params) -> list:
     return sizes
 
 
+def neumann(h: Hierarchy) -> bool:
+    return h.p.bc == "neumann"
+
+
 def build_hierarchy(p: Params) -> Hierarchy:
+    if p.bc not in ("dirichlet", "neumann") or (p.bc == "neumann" and p.centering != "cell"):
+        raise ValueError(f"boundary {p.bc!r} with {p.centering} centring")
     h = Hierarchy(p, ladder(p))
     if p.centering == "cell":
         k = p.k if p.k is not None else np.ones((p.n,) * p.dim)
         h.beta.append(cell.harmonic_faces(np.asarray(k, dtype=np.float64)))
         for _ in h.sizes[1:]:
             h.beta.append(cell.coarsen_faces(h.beta[-1]))
-        A = cell.dense_matrix(h.beta[-1], h.sizes[-1], p.dim)
+        A = cell.dense_matrix(h.beta[-1], h.sizes[-1], p.dim, p.bc)
     else:
         A = node.dense_matrix(h.sizes[-1], p.dim)
-    h.chol = np.linalg.cholesky(A)
+    h.dense = A
+    if p.bc == "dirichlet":
+        h.chol = np.linalg.cholesky(A)
     return h
 
 
@@ -106,7 +123,7 @@ def build_hierarchy(p: Params) -> Hierarchy:
 def residual(h: Hierarchy, lvl: int, u, f):
     if h.p.centering == "node":
         return node.residual(u, f)
-    return cell.residual(u, f, h.beta_as(lvl, u.dtype))
+    return cell.residual(u, f, h.beta_as(lvl, u.dtype), h.p.bc)
 
 
 def unknowns(h: Hierarchy, a):
@@ -123,16 +140,22 @@ def smooth(h: Hierarchy, lvl: int, u, f, sweeps: int, order=(0, 1)):
             u = node.jacobi(u, f, p.omega) if p.smoother == "jacobi" else node.rbgs(u, f, order)
         else:
             b = h.beta_as(lvl, u.dtype)
-            u = cell.jacobi(u, f, b, p.omega) if p.smoother == "jacobi" else cell.rbgs(u, f, b, order)
+            u = (cell.jacobi(u, f, b, p.omega, p.bc) if p.smoother == "jacobi"
+                 else cell.rbgs(u, f, b, order, p.bc))
     return u
 
 
 def restrict(h: Hierarchy, r):
-    return node.restrict_fw(r) if h.p.centering == "node" else cell.restrict_mean(r)
+    """Transfer of a residual to the next coarser right-hand side (zero mean
+    with Neumann walls)."""
+    if h.p.centering == "node":
+        return node.restrict_fw(r)
+    fc = cell.restrict_mean(r)
+    return cell.project_mean(fc) if neumann(h) else fc
 
 
 def prolong_correct(h: Hierarchy, u, ec):
-    return node.correct(u, ec) if h.p.centering == "node" else cell.correct(u, ec)
+    return node.correct(u, ec) if h.p.centering == "node" else cell.correct(u, ec, h.p.bc)
 
 
 def coarse_solve(h: Hierarchy, fc):
@@ -140,8 +163,12 @@ def coarse_solve(h: Hierarchy, fc):
     L y = b, L^T x = y; float32 inputs are upcast and the result downcast."""
     h.coarse_solves += 1
     b = np.asarray(unknowns(h, fc), dtype=np.float64).reshape(-1)
-    y = scipy.linalg.solve_triangular(h.chol, b, lower=True)
-    x = scipy.linalg.solve_triangular(h.chol.T, y, lower=False)
+    if neumann(h):
+        # minimum-norm least-squares solution of the singular system
+        x = np.linalg.lstsq(h.dense, b, rcond=None)[0]
+    else:
+        y = scipy.linalg.solve_triangular(h.chol, b, lower=True)
+        x = scipy.linalg.solve_triangular(h.chol.T, y, lower=False)
     out = np.zeros(fc.shape, dtype=fc.dtype)
     if h.p.centering == "node":
         out[node.interior(fc.ndim)] = x.reshape((fc.shape[0] - 2,) * fc.ndim).astype(fc.dtype)
@@ -172,7 +199,14 @@ def mg_cycle(h: Hierarchy, u, f, lvl: int, kind: str):
             uc = mg_cycle(h, uc, fc, lvl + 1, "V")
     u = prolong_correct(h, u, uc)
     u = smooth(h, lvl, u, f, p.nu2, p.post_order)
+    if lvl == 0 and neumann(h):
+        u = cell.project_mean(u)
     return u
+
+
+def start_rhs(h: Hierarchy, f):
+    """The right-hand side a solve starts from: zero mean with Neumann walls."""
+    return cell.project_mean(f) if neumann(h) else f
 
 
 def fmg(h: Hierarchy, f, cycles_per_level: int = 1):
@@ -182,7 +216,7 @@ def fmg(h: Hierarchy, f, cycles_per_level: int = 1):
     interpolated coarser solution (multilinear interpolation, the cycle's
     own) and applies cycles_per_level cycles of type h.p.cycle.  Returns the
     finest iterate."""
-    fs = [f]
+    fs = [start_rhs(h, f)]
     for _ in range(1, h.levels):
         fs.append(restrict(h, fs[-1]))
     u = coarse_solve(h, fs[-1])
@@ -212,6 +246,8 @@ def pcg(h: Hierarchy, f, u0=None, tol=1e-10, max_it=100, precondition=True):
     preconditioner when nu1 = nu2 and post-smoothing is the adjoint of
     pre-smoothing (red-black GS: the reverse colour order).  With
     precondition=False it is plain CG.  Returns (u, relres history)."""
+    if neumann(h):
+        raise ValueError("the Krylov solver is for Dirichlet problems")
     u = np.zeros_like(f) if u0 is None else u0.copy()
     r = residual(h, 0, u, f)
     prec = (lambda v: vcycle(h, np.zeros_like(v), v)) if precondition else (lambda v: v.copy())
@@ -246,6 +282,7 @@ def residual_norm(h: Hierarchy, u, f) -> float:
 def solve(h: Hierarchy, f, u0=None, tol=1e-10, max_cycles=100, record_iterates=False):
     """V-cycles from u0 until ||r|| / ||r0|| <= tol.  Returns
     (u, relres history including the initial 1.0, iterates or None)."""
+    f = start_rhs(h, f)
     u = np.zeros_like(f) if u0 is None else u0.copy()
     r0 = residual_norm(h, u, f)
     hist = [1.0]
@@ -262,6 +299,7 @@ def solve(h: Hierarchy, f, u0=None, tol=1e-10, max_cycles=100, record_iterates=F
 
 def cycles(h: Hierarchy, f, u0, k: int):
     """Exactly k V-cycles from u0; returns the list of iterates u^1..u^k."""
+    f = start_rhs(h, f)
     u = u0.copy()
     out = []
     for _ in range(k):
@@ -279,6 +317,8 @@ def pow2_scale(maxabs: float) -> float:
 def mixed_solve(h: Hierarchy, f, tol=1e-10, max_outer=100, inner=np.float32):
     """FP64 iterative refinement with single-precision V-cycles, from u = 0.
     Returns (u, relres history ||r_k|| / ||f||)."""
+    if neumann(h):
+        raise ValueError("mixed-precision refinement is for Dirichlet problems")
     u = np.zeros_like(f, dtype=np.float64)
     hist = []
     r0 = None

@@ -234,3 +234,137 @@ def test_varcoef_vcycle_converges_to_sparse_direct_solve():
     assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-11
     rates = [hist[i + 1] / hist[i] for i in range(1, len(hist) - 1)]
     assert max(rates) < 0.12, rates
+
+
+# ------------------------------------------------------------ Neumann walls
+def cell_cosine(N, d, ks):
+    x = W.cell_coords(N)
+    out = np.ones((N,) * d)
+    for ax in range(d):
+        shape = [1] * d
+        shape[ax] = N
+        out = out * np.cos(ks[ax] * np.pi * x).reshape(shape)
+    return out
+
+
+@pytest.mark.parametrize("d,N,ks", [(2, 16, (0, 0)), (2, 16, (1, 3)), (3, 8, (0, 2, 5)), (3, 16, (4, 1, 0))])
+def test_neumann_cosine_eigenvector(d, N, ks):
+    """With k = 1 and zero-flux walls, cos(k pi x)... at cell centres is an
+    exact eigenvector with eigenvalue (4/h^2) sum sin^2(k pi h / 2); k = 0 in
+    every direction is the constant null vector."""
+    h = 1.0 / N
+    u = cell_cosine(N, d, ks)
+    lam = 4 / h ** 2 * sum(np.sin(k * np.pi * h / 2) ** 2 for k in ks)
+    Au = cell.apply_A(u, ones_beta(N, d), "neumann")
+    assert np.max(np.abs(Au - lam * u)) <= 1e-12 * max(lam, 4 / h ** 2)
+    if not any(ks):
+        assert np.array_equal(Au, np.zeros_like(Au))
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])
+def test_neumann_operator_brute_force(d, N):
+    """Flux form with the wall fluxes left out, point by point."""
+    rng = np.random.default_rng(4)
+    k = np.exp(rng.uniform(-1, 1, size=(N,) * d))
+    beta = cell.harmonic_faces(k)
+    u = rng.uniform(-1, 1, size=(N,) * d)
+    Au = cell.apply_A(u, beta, "neumann")
+    s = N * N
+    for p in itertools.product(range(N), repeat=d):
+        acc = 0.0
+        for ax in range(d):
+            for side in (-1, 1):
+                q = list(p)
+                q[ax] += side
+                if 0 <= q[ax] < N:
+                    kb = 2 * k[p] * k[tuple(q)] / (k[p] + k[tuple(q)])
+                    acc += kb * (u[p] - u[tuple(q)])
+        assert abs(Au[p] - s * acc) <= 1e-12 * s * 10
+    # symmetric, positive semidefinite, constants in the null space
+    A = cell.dense_matrix(beta, N, d, "neumann")
+    assert np.allclose(A, A.T, rtol=0, atol=1e-12 * s)
+    ev = np.linalg.eigvalsh(A)
+    assert abs(ev[0]) <= 1e-10 * ev[-1] and ev[1] > 1e-6 * ev[-1]
+
+
+def test_neumann_prolongation_reproduces_constants():
+    """Even ghosts make cell-centred interpolation exact for constants up to
+    the walls (the odd Dirichlet ghosts pull wall cells to 1/2)."""
+    for d in (2, 3):
+        e = np.full((4,) * d, 3.0)
+        assert np.array_equal(cell.prolong_trilinear(e, "neumann"), np.full((8,) * d, 3.0))
+        assert cell.prolong_trilinear(e)[(0,) * d] != 3.0
+
+
+def test_neumann_coarse_solve_is_the_zero_mean_solution():
+    """The minimum-norm coarsest solve against the regularised system
+    (A + 1 1^T) x = f, which for zero-mean f has the zero-mean solution."""
+    N = 4
+    k = W.varcoef_k(N)
+    h = cycle.build_hierarchy(cycle.Params(centering="cell", dim=3, n=N, coarsest=4, smoother="rbgs",
+                                           k=k, bc="neumann"))
+    f = cell.project_mean(W.normal_zero_mean(N, 3, 6))
+    x = cycle.coarse_solve(h, f)
+    A = cell.dense_matrix(h.beta[0], N, 3, "neumann")
+    xr = np.linalg.solve(A + np.ones_like(A), f.reshape(-1))
+    assert np.max(np.abs(x.reshape(-1) - xr)) <= 1e-12 * np.max(np.abs(xr))
+    assert abs(np.sum(x)) <= 1e-12 * np.sum(np.abs(x))
+
+
+@pytest.mark.parametrize("smoother", ["rbgs", "jacobi"])
+def test_neumann_vcycle_converges_to_bordered_solution(smoother):
+    """V-cycles with projections reach the zero-mean solution of the singular
+    system, obtained independently from the bordered system
+    [A 1; 1^T 0] [u; l] = [f; 0] assembled from the face formula; the
+    convergence factor stays small at 16^3 and 32^3 cells."""
+    N = 16
+    k = W.varcoef_k(N)
+    f = W.normal_zero_mean(N, 3, 2)
+    p = cycle.Params(centering="cell", dim=3, n=N, coarsest=4, smoother=smoother, omega=0.8, nu1=3, nu2=3,
+                     k=k, bc="neumann")
+    u, hist, _ = cycle.solve(cycle.build_hierarchy(p), f, tol=1e-13, max_cycles=80)
+    assert hist[-1] <= 1e-13 and abs(np.mean(u)) <= 1e-14 * np.max(np.abs(u))
+    idx = np.arange(N ** 3).reshape((N,) * 3)
+    beta = cell.harmonic_faces(k)
+    rows, cols, vals = [], [], []
+    s = N * N
+    for ax in range(3):
+        b = beta[ax]
+        for side in (-1, 1):
+            for p_ in itertools.product(range(N), repeat=3):
+                q = list(p_)
+                q[ax] += side
+                if 0 <= q[ax] < N:
+                    fi = list(p_)
+                    fi[ax] = p_[ax] if side < 0 else p_[ax] + 1
+                    bf = b[tuple(fi)]
+                    rows += [idx[p_], idx[p_]]
+                    cols += [idx[p_], idx[tuple(q)]]
+                    vals += [s * bf, -s * bf]
+    m = N ** 3
+    rows += list(range(m)) + [m] * m
+    cols += [m] * m + list(range(m))
+    vals += [1.0] * (2 * m)
+    K = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(m + 1, m + 1))
+    rhs = np.append(f.reshape(-1) - np.mean(f), 0.0)
+    ud = scipy.sparse.linalg.spsolve(K.tocsc(), rhs)[:m].reshape((N,) * 3)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-11
+    for n_ in (16, 32):
+        p.n = n_
+        p.k = W.varcoef_k(n_)
+        _, hh, _ = cycle.solve(cycle.build_hierarchy(p), W.normal_zero_mean(n_, 3, 3), tol=1e-10, max_cycles=80)
+        rates = [hh[i + 1] / hh[i] for i in range(1, len(hh) - 1)]
+        assert max(rates) < (0.15 if smoother == "rbgs" else 0.45), (n_, rates)
+
+
+def test_neumann_rhs_is_projected():
+    """A right-hand side with a nonzero mean is solved as its zero-mean part."""
+    N = 8
+    p = cycle.Params(centering="cell", dim=3, n=N, coarsest=4, smoother="rbgs", nu1=2, nu2=2, bc="neumann")
+    h = cycle.build_hierarchy(p)
+    f = W.normal_zero_mean(N, 3, 8)
+    u1, _, _ = cycle.solve(h, f, tol=1e-12)
+    u2, _, _ = cycle.solve(h, f + 5.0, tol=1e-12)
+    assert np.max(np.abs(u1 - u2)) <= 1e-10 * np.max(np.abs(u1))
+    with pytest.raises(ValueError):
+        cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=17, bc="neumann"))
