@@ -91,7 +91,8 @@ def cpu_baseline(n_sample: int = 257):
 
 def other_configs(mg, W, torch, np):
     """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound), the
-    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10), W- and
+    256^3-cell variable-coefficient case (FP64 and mixed to 1e-10, and FP64
+    with zero-flux walls), W- and
     F-cycle solves of the 513^3 Poisson problem, conjugate gradients with the
     V-cycle as preconditioner on it, and full multigrid on a 513^3 problem
     with a closed-form discrete solution."""
@@ -139,6 +140,23 @@ def other_configs(mg, W, torch, np):
         s.close()
     res["varcoef_cell_256_mixed"]["max_rel_diff_vs_fp64_solution"] = float(
         (sols["mixed"] - sols["fp64"]).abs().max() / sols["fp64"].abs().max())
+    # the same problem with zero-flux walls (projected right-hand side, zero-mean solution)
+    s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, bc=mg.MG_NEUMANN0)
+    s.set_rhs(f)
+    s.set_initial(None)
+    s.solve(1e-10)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        s.set_initial(None)
+        t = time.perf_counter()
+        code, cyc, rel = s.solve(1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    dt = min(times)
+    res["varcoef_cell_256_neumann_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
+                                            "status": code, "mlups": round(N ** 3 * cyc / dt / 1e6, 1)}
+    s.close()
     # the same problem by CG preconditioned with the symmetric V(3,3)-cycle
     s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, k=k, krylov=1)
     s.set_rhs(f)

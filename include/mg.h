@@ -52,7 +52,7 @@ enum {
 
 enum { MG_NODE = 0, MG_CELL = 1 };              /* field location           */
 enum { MG_LAPLACE = 0, MG_VARCOEF = 1 };        /* operator kind            */
-enum { MG_DIRICHLET0 = 0 };                     /* boundary kind            */
+enum { MG_DIRICHLET0 = 0, MG_NEUMANN0 = 1 };   /* boundary kind            */
 enum { MG_JACOBI = 0, MG_RBGS = 1 };            /* smoother                 */
 enum { MG_FP64 = 0, MG_MIXED = 1 };             /* arithmetic               */
 enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 };   /* cycle type      */
@@ -82,8 +82,18 @@ typedef struct mg_stencil {
     int k_on_device;
 } mg_stencil;
 
+/* Boundary condition.  MG_DIRICHLET0: u = 0 on the boundary (node grids:
+ * the boundary nodes; cell grids: on the walls, odd ghosts).  MG_NEUMANN0:
+ * zero normal flux on the walls of a cell grid (Trottenberg et al. Sec.
+ * 5.6.4): wall faces drop out of the stencil, interpolation uses even
+ * ghosts; the operator annihilates constants, so mg_set_rhs projects f to
+ * zero mean, every restricted right-hand side is projected likewise, the
+ * coarsest solve returns the zero-mean solution (Cholesky of A + a 1 1^T)
+ * and the finest iterate is projected to zero mean after every cycle.
+ * Neumann needs cell centring and FP64 precision, and no krylov vectors.
+ * NULL means MG_DIRICHLET0. */
 typedef struct mg_bc {
-    int kind;                  /* MG_DIRICHLET0 */
+    int kind;                  /* MG_DIRICHLET0 or MG_NEUMANN0 */
 } mg_bc;
 
 /* Cycle options.  omega is the Jacobi damping; nu1/nu2 pre/post sweeps;

@@ -31,4 +31,13 @@ READINGS = {
     "R13": "Seeds: NumPy PCG64, 0 (2-D u0), 1 (3-D f), 2 (variable-coefficient f), "
            "3/4 (arrivals/sizes), 1000+id (request f).",
     "R14": "Served 2-D requests use damped Jacobi V(2,2); 3-D requests use red-black GS V(3,3).",
+    "R15": "FMG: the right-hand side goes to every level by the cycle's restriction, each finer "
+           "level starts from the interpolated coarser result, a level directly above the "
+           "coarsest gets its cycles too.",
+    "R16": "Preconditioned CG: the preconditioner is one cycle from zero with nu1 = nu2 and the "
+           "adjoint post-smoother (red-black GS: reversed colours); the stopping test uses CG's "
+           "recurrence residual.",
+    "R17": "Neumann walls (cell grids): f is projected to zero mean at the start and after every "
+           "restriction, the finest iterate after every cycle; the coarsest solve returns the "
+           "zero-mean (minimum-norm) solution.",
 }

@@ -33,6 +33,7 @@ struct Geom {
     int fpitch;       // row pitch, >= n + 1
     long long fplane; // (n + 1) * fpitch
     long long fsize;  // elements per face array (nz_f * fplane)
+    int neu;          // cell grid with zero-flux (Neumann) walls
 };
 
 // Iteration space of one launch over colour-split points and its tiling into

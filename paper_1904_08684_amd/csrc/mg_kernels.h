@@ -58,6 +58,11 @@ hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const 
 
 // Deterministic reduction of `count` (sum, max) pairs to out[0..1];
 // scratch holds at least 2 * ceil(count / 4096) doubles.
+// Cell grids: a -= (sum of a over all cells) / (number of cells), the sum
+// through per-block partials and launch_reduce into out[0].
+hipError_t launch_project(const Geom& g, double* a, double* partials, double* scratch, double* out,
+                          hipStream_t st);
+
 hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
                          hipStream_t st);
 long long reduce_scratch_pairs(long long count);

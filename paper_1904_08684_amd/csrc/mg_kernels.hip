@@ -1021,10 +1021,12 @@ __device__ __forceinline__ void cell_sums(const Geom& g, const T* __restrict__ o
     const long long fb = (long long)z * g.fplane + (long long)y * g.fpitch + x;
     const T bxm = bx[fb], bxp = bx[fb + 1], bym = by[fb], byp = by[fb + g.fpitch];
     const bool wxm = x == 0, wxp = x == N - 1, wym = y == 0, wyp = y == N - 1;
-    dg = wxm ? T(2) * bxm : bxm;
-    dg = dg + (wxp ? T(2) * bxp : bxp);
-    dg = dg + (wym ? T(2) * bym : bym);
-    dg = dg + (wyp ? T(2) * byp : byp);
+    // wall faces weigh 2 (Dirichlet, odd ghost) or 0 (Neumann, no flux)
+    const T ww = g.neu ? T(0) : T(2);
+    dg = wxm ? ww * bxm : bxm;
+    dg = dg + (wxp ? ww * bxp : bxp);
+    dg = dg + (wym ? ww * bym : bym);
+    dg = dg + (wyp ? ww * byp : byp);
     T bzm = T(0), bzp = T(0);
     bool wzm = true, wzp = true;
     if (D == 3) {
@@ -1032,8 +1034,8 @@ __device__ __forceinline__ void cell_sums(const Geom& g, const T* __restrict__ o
         bzp = bz[fb + g.fplane];
         wzm = z == 0;
         wzp = z == N - 1;
-        dg = dg + (wzm ? T(2) * bzm : bzm);
-        dg = dg + (wzp ? T(2) * bzp : bzp);
+        dg = dg + (wzm ? ww * bzm : bzm);
+        dg = dg + (wzp ? ww * bzp : bzp);
     }
     if (ZERO) {
         off = T(0);
@@ -1174,8 +1176,8 @@ __global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space s
 }
 
 // Cell-centred linear interpolation: per axis fine(2I) = 3/4 e[I] + 1/4 e[I-1],
-// fine(2I+1) = 3/4 e[I] + 1/4 e[I+1], mirror ghost -e[I] beyond a wall;
-// x first, then y, then z; then u += P e.
+// fine(2I+1) = 3/4 e[I] + 1/4 e[I+1], ghost -e[I] (Dirichlet) or e[I]
+// (Neumann) beyond a wall; x first, then y, then z; then u += P e.
 template <typename T, int D>
 __device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
@@ -1189,23 +1191,24 @@ __device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, S
     const int J = y >> 1, Jn = (y & 1) ? J + 1 : J - 1;
     const int K = z >> 1, Kn = (z & 1) ? K + 1 : K - 1;
     const bool wI = In < 0 || In >= Nc, wJ = Jn < 0 || Jn >= Nc, wK = Kn < 0 || Kn >= Nc;
+    const T sg = gc.neu ? T(1) : T(-1);
     auto E = [&](int X, int Y, int Z) -> T {
         return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
     };
     auto ix = [&](int Y, int Z) -> T {
         const T c0 = E(I, Y, Z);
-        const T c1 = wI ? -c0 : E(In, Y, Z);
+        const T c1 = wI ? sg * c0 : E(In, Y, Z);
         return a * c0 + b * c1;
     };
     auto iy = [&](int Z) -> T {
         const T c0 = ix(J, Z);
-        const T c1 = wJ ? -c0 : ix(Jn, Z);
+        const T c1 = wJ ? sg * c0 : ix(Jn, Z);
         return a * c0 + b * c1;
     };
     T e;
     if (D == 3) {
         const T c0 = iy(K);
-        const T c1 = wK ? -c0 : iy(Kn);
+        const T c1 = wK ? sg * c0 : iy(Kn);
         e = a * c0 + b * c1;
     } else {
         e = iy(0);
@@ -1433,6 +1436,27 @@ __global__ __launch_bounds__(256) void k_pcg_dir(long long n2, double* __restric
     reinterpret_cast<double2*>(p)[i] = pv;
 }
 
+// ------------------------------------------- zero-mean projection (Neumann)
+// Sum over all cells of a cell-grid FP64 field into per-block partials
+// (fixed assignment of cells to threads: deterministic), then a -= sum / count.
+__global__ __launch_bounds__(256) void k_cell_sum(Geom g, Space sp, const double* __restrict__ a,
+                                                  double* __restrict__ part) {
+    const Ex ex = solo_ex();
+    Pt p;
+    double v = 0.0;
+    if (map_point(ex, sp, p)) v = a[(long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs];
+    block_sum_max(v, 0.0, part + 2 * (long long)ex.b);
+}
+
+__global__ __launch_bounds__(256) void k_cell_shift(Geom g, Space sp, double* __restrict__ a,
+                                                    const double* __restrict__ sum, double count) {
+    Pt p;
+    if (!map_point(solo_ex(), sp, p)) return;
+    const double mean = sum[0] / count;
+    const long long i = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
+    a[i] = a[i] - mean;
+}
+
 __global__ void k_scalar_copy(double* __restrict__ dst, const double* __restrict__ src) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
 }
@@ -1448,6 +1472,10 @@ __global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, long long n
 }
 
 // ------------------------------------------------------------- spaces
+static long long nat_count(const Geom& g) {
+    return (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
+}
+
 // Points of one or both colours over the unknowns of a level.
 Space space_of(const Geom& g, int ncol, int col0) {
     if (g.cell)
@@ -1965,6 +1993,17 @@ long long reduce_scratch_pairs(long long count) {
     return total + 1;
 }
 
+hipError_t launch_project(const Geom& g, double* a, double* partials, double* scratch, double* out,
+                          hipStream_t st) {
+    if (!g.cell) return hipErrorInvalidValue;
+    const Space sp = space_of(g, 2, 0);
+    k_cell_sum<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, a, partials);
+    hipError_t e = launch_reduce(partials, sp.blocks(), scratch, out, st);
+    if (e != hipSuccess) return e;
+    k_cell_shift<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, a, out, (double)nat_count(g));
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
                          hipStream_t st) {
     const double* in = partials;
@@ -1984,12 +2023,8 @@ hipError_t launch_reduce(const double* partials, long long count, double* scratc
     return hipGetLastError();
 }
 
-static long long nat_total(const Geom& g) {
-    return (long long)g.n * g.n * (g.dim == 3 ? g.n : 1);
-}
-
 hipError_t launch_pack(const Geom& g, int prec, const double* nat, void* split, hipStream_t st) {
-    const long long tot = nat_total(g);
+    const long long tot = nat_count(g);
     const unsigned nb = (unsigned)((tot + 255) / 256);
     if (prec)
         k_pack<float><<<nb, 256, 0, st>>>(g, tot, nat, mp<float>(split));
@@ -1999,7 +2034,7 @@ hipError_t launch_pack(const Geom& g, int prec, const double* nat, void* split, 
 }
 
 hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat, hipStream_t st) {
-    const long long tot = nat_total(g);
+    const long long tot = nat_count(g);
     const unsigned nb = (unsigned)((tot + 255) / 256);
     if (prec)
         k_unpack<float><<<nb, 256, 0, st>>>(g, tot, cp<float>(split), nat);

@@ -41,7 +41,7 @@ struct Ctx;
 // Validate, lay out and initialise a context inside d_workspace (staging:
 // reserve a host-transfer buffer for host-pointer I/O).
 int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_workspace, size_t bytes,
-              hipStream_t stream, bool staging, Ctx** out, std::string* errmsg);
+              hipStream_t stream, bool staging, Ctx** out, std::string* errmsg, int bc_kind = MG_DIRICHLET0);
 
 struct Level {
     Geom g;
@@ -63,6 +63,7 @@ struct Ctx {
     mg_grid grid{};
     mg_opts opts{};
     int kind = MG_LAPLACE;
+    bool neu = false;             // Neumann walls (cell grids, FP64)
     void* base = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
@@ -71,7 +72,7 @@ struct Ctx {
     long long partial_pairs = 0;
     double* partials = nullptr;
     double* reduce_scratch = nullptr;
-    double* red = nullptr;        // [sum r^2, max |r|, sigma]
+    double* red = nullptr;        // [sum r^2, max |r|, sigma, -, projection sum, -]
     double* chol = nullptr;
     double* staging = nullptr;
     // preconditioned CG (krylov = 1): finest-level FP64 vectors and scalars
@@ -115,6 +116,7 @@ struct Ctx {
     int vcycle(int l, int pr, bool from_zero);
     int cycle(int l, int pr, bool from_zero, int kind);
     int fmg(int cpl);
+    int project(int l, void* a);
     int pcg(double tol, int max_it, int* its_out, double* relres_out);
     int refine_step();
     int read_red(double* sq, double* mx);

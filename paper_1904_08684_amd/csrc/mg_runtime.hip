@@ -44,6 +44,7 @@ Geom make_geom(int dim, int n, int cell) {
     g.fpitch = round_up(n + 1, 8);
     g.fplane = (long long)(n + 1) * g.fpitch;
     g.fsize = (dim == 3 ? (long long)(n + 1) : 1LL) * g.fplane;
+    g.neu = 0;
     return g;
 }
 
@@ -268,6 +269,9 @@ void coarsen_faces(const Geom& gf, const std::vector<double> bf[3], const Geom& 
 }
 
 // Dense FP64 matrix of the coarsest level over its unknowns in C order.
+// With Neumann walls the matrix is singular (constants); a 1 1^T with a the
+// mean diagonal over m is added, which makes it SPD and leaves the solution
+// for a zero-mean right-hand side that of A itself with zero mean.
 std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta) {
     const int d = g.dim;
     const int side = g.cell ? g.n : g.n - 2, off = g.cell ? 0 : 1;
@@ -302,8 +306,9 @@ std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta
                     const int nbx[6] = {x - 1, x + 1, x, x, x, x}, nby[6] = {y, y, y - 1, y + 1, y, y},
                               nbz[6] = {z, z, z, z, z - 1, z + 1};
                     double dg = 0.0;
+                    const double ww = g.neu ? 0.0 : 2.0;
                     for (int q = 0; q < 2 * d; ++q) {
-                        const double t = wall[q] ? 2.0 * bf[q] : bf[q];
+                        const double t = wall[q] ? ww * bf[q] : bf[q];
                         dg = q == 0 ? t : dg + t;
                     }
                     A[(size_t)i * m + i] = (dg * 1.0 - 0.0) * s;
@@ -313,6 +318,12 @@ std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta
                     }
                 }
             }
+    if (g.neu) {
+        double tr = 0.0;
+        for (int i = 0; i < m; ++i) tr += A[(size_t)i * m + i];
+        const double a = tr / m / m;
+        for (double& v : A) v += a;
+    }
     return A;
 }
 
@@ -626,6 +637,7 @@ int Ctx::fmg(int cpl) {
         int rc = record(MG_K_RESTRICT, l,
                         launch_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].f[pr], lv[l + 1].f[pr], stream), e0,
                         "restrict f");
+        if (!rc && neu) rc = project(l + 1, lv[l + 1].f[pr]);
         if (rc) return rc;
     }
     int rc = coarse(pr);
@@ -653,6 +665,7 @@ int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
         if (!rc) rc = residual(l, pr, false, true);
         if (!rc) rc = restrict_to(l, pr);
     }
+    if (!rc && neu) rc = project(l + 1, lv[l + 1].f[pr]);
     if (!rc) rc = cycle(l + 1, pr, true, kind);
     if (!rc && l + 2 < L && kind != MG_CYCLE_V)
         rc = cycle(l + 1, pr, false, kind == MG_CYCLE_W ? MG_CYCLE_W : MG_CYCLE_V);
@@ -664,7 +677,16 @@ int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (opts.smoother == MG_RBGS && opts.nu2 > 0) mask = opts.post_order == 0 ? 2 : 1;
     rc = prolong(l, pr, mask);
     if (!rc) rc = smooth(l, pr, opts.nu2, false, opts.post_order);
+    if (!rc && neu && l == 0) rc = project(0, lv[0].u[pr]);
     return rc;
+}
+
+// Zero-mean projection of a cell-grid FP64 field of level l (Neumann walls).
+int Ctx::project(int l, void* a) {
+    hipEvent_t e0 = begin();
+    return record(MG_K_REDUCE, l,
+                  launch_project(lv[l].g, static_cast<double*>(a), partials, reduce_scratch, red + 4, stream), e0,
+                  "project");
 }
 
 // One FP64 refinement step around a single-precision V-cycle.  Expects
@@ -981,7 +1003,7 @@ int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
 namespace mg {
 
 int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_workspace, size_t bytes,
-              hipStream_t stream, bool staging, Ctx** out, std::string* errmsg) {
+              hipStream_t stream, bool staging, Ctx** out, std::string* errmsg, int bc_kind) {
     *out = nullptr;
     std::string why;
     int rc = validate(g, st, o, &why);
@@ -1009,6 +1031,7 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
     c->grid = *g;
     c->opts = *o;
     c->kind = st ? st->kind : MG_LAPLACE;
+    c->neu = bc_kind == MG_NEUMANN0;
     c->base = d_workspace;
     c->bytes = bytes;
     c->stream = stream;
@@ -1032,6 +1055,7 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
         const LevelPlan& lp = plan.lv[l];
         Level lvv;
         lvv.g = lp.g;
+        lvv.g.neu = bc_kind == MG_NEUMANN0 ? 1 : 0;
         for (int pr = 0; pr < 2; ++pr) {
             lvv.has[pr] = lp.has[pr];
             lvv.u[pr] = c->at(lp.u[pr]);
@@ -1142,13 +1166,19 @@ int mg_setup(const mg_grid* g, const mg_stencil* st, const mg_bc* bc, const mg_o
              size_t bytes, void* hip_stream, mg_ctx** out) {
     if (!out) return MG_EINVAL;
     *out = nullptr;
-    if (bc && bc->kind != MG_DIRICHLET0) {
-        g_setup_error = "only zero Dirichlet boundaries are supported";
+    const int kind = bc ? bc->kind : MG_DIRICHLET0;
+    if (kind != MG_DIRICHLET0 && kind != MG_NEUMANN0) {
+        g_setup_error = "unknown boundary kind";
+        return MG_EINVAL;
+    }
+    if (kind == MG_NEUMANN0 && g && o &&
+        (g->centering != MG_CELL || o->precision != MG_FP64 || o->krylov != 0)) {
+        g_setup_error = "Neumann walls need a cell grid, FP64 precision and no Krylov vectors";
         return MG_EINVAL;
     }
     Ctx* c = nullptr;
     const int rc = mg::setup_ctx(g, st, o, d_workspace, bytes, static_cast<hipStream_t>(hip_stream), true, &c,
-                                 &g_setup_error);
+                                 &g_setup_error, kind);
     if (rc) return rc;
     *out = reinterpret_cast<mg_ctx*>(c);
     return MG_OK;
@@ -1191,7 +1221,9 @@ static int copy_out(Ctx* c, const mg::Geom& g, int pr, const void* field, double
 int mg_set_rhs(mg_ctx* h, const double* f, int on_device) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     if (!c || !f) return MG_EINVAL;
-    return copy_in(c, c->lv[0].g, 0, c->lv[0].f[0], f, on_device);
+    int rc = copy_in(c, c->lv[0].g, 0, c->lv[0].f[0], f, on_device);
+    if (!rc && c->neu) rc = c->project(0, c->lv[0].f[0]);
+    return rc;
 }
 
 int mg_set_initial(mg_ctx* h, const double* u0, int on_device) {

@@ -26,7 +26,7 @@ MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE = 0, -1, -2, -3
 MG_ENOTCONV, MG_ENONFINITE, MG_EDIVERGED, MG_EBUSY = -4, -5, -6, -7
 MG_NODE, MG_CELL = 0, 1
 MG_LAPLACE, MG_VARCOEF = 0, 1
-MG_DIRICHLET0 = 0
+MG_DIRICHLET0, MG_NEUMANN0 = 0, 1
 MG_JACOBI, MG_RBGS = 0, 1
 MG_FP64, MG_MIXED = 0, 1
 MG_CYCLE_V, MG_CYCLE_W, MG_CYCLE_F = 0, 1, 2
@@ -153,7 +153,7 @@ class Solver:
     def __init__(self, dim: int, n: int, centering: int = MG_NODE, coarsest: int | None = None,
                  smoother: int = MG_RBGS, omega: float = 0.8, nu1: int = 2, nu2: int = 2,
                  precision: int = MG_FP64, max_cycles: int = 100, post_order: int = 0, cycle: int = 0,
-                 krylov: int = 0,
+                 krylov: int = 0, bc: int = 0,
                  k=None, stream=None, device: str = "cuda"):
         import torch
         self.dim, self.n, self.centering = dim, n, centering
@@ -171,7 +171,7 @@ class Solver:
         self.bytes = workspace_bytes(self.grid, self.opts, self.stencil)
         self.workspace = torch.empty(max(self.bytes, 256), dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
-        bc = mg_bc(MG_DIRICHLET0)
+        bc = mg_bc(bc)
         h = C.c_void_p()
         _check(mg_setup(C.byref(self.grid), C.byref(self.stencil), C.byref(bc), C.byref(self.opts),
                         C.c_void_p(self.workspace.data_ptr()), self.bytes,

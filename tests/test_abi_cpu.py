@@ -133,3 +133,18 @@ def test_null_safety(mg):
     assert mg.mg_solve(None, 1e-10, None, None) == mg.MG_EINVAL
     assert mg.mg_pcg(None, 1e-10, 10, None, None) == mg.MG_EINVAL
     assert mg.mg_set_rhs(None, None, 0) == mg.MG_EINVAL
+
+
+def test_neumann_combinations_rejected_before_any_device_work(mg):
+    """Zero-flux walls need a cell grid, FP64 and no Krylov vectors; unknown
+    boundary kinds are refused (all checked before the device is touched)."""
+    h = C.c_void_p()
+    cases = [(mg.make_grid(3, 33, mg.MG_NODE), mg.make_opts(), mg.MG_NEUMANN0),
+             (mg.make_grid(3, 32, mg.MG_CELL), mg.make_opts(precision=mg.MG_MIXED), mg.MG_NEUMANN0),
+             (mg.make_grid(3, 32, mg.MG_CELL), mg.make_opts(krylov=1), mg.MG_NEUMANN0),
+             (mg.make_grid(3, 32, mg.MG_CELL), mg.make_opts(), 7)]
+    for g, o, kind in cases:
+        bc = mg.mg_bc(kind)
+        rc = mg.mg_setup(C.byref(g), None, C.byref(bc), C.byref(o), C.c_void_p(256), 1 << 30, None, C.byref(h))
+        assert rc == mg.MG_EINVAL
+        assert mg.mg_last_error(None)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import scipy.fft
 
-from oracle import cycle, node
+from oracle import cell, cycle, node
 from paper_1904_08684_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -519,3 +519,80 @@ def test_pcg_513_converges_faster_than_cycles(mg):
           flush=True)
     assert code == mg.MG_OK and code_v == mg.MG_OK and its < cycles
     assert rel_cpu <= 1.5e-10
+
+
+# ------------------------------------------------------ Neumann walls (cells)
+@pytest.mark.parametrize("dim,N,sm,nu,cycles", [(3, 32, "rbgs", 2, 3), (3, 64, "rbgs", 3, 2), (3, 32, "jacobi", 2, 3),
+                                                (2, 64, "rbgs", 2, 3)])
+def test_neumann_per_iterate(mg, dim, N, sm, nu, cycles):
+    """Zero-flux walls: f projected at set-up, coarse right-hand sides
+    projected, zero-mean coarsest solve, even-ghost interpolation, finest
+    iterate projected after each cycle; every iterate against the oracle's."""
+    k = W.varcoef_k(N, dim)
+    f = W.normal_zero_mean(N, dim, W.SEED_F_VARCOEF) + 0.25      # a nonzero mean, removed by the projection
+    u0 = W.cell_uniform(N, dim, 31)
+    s = mg.Solver(dim, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS if sm == "rbgs" else mg.MG_JACOBI, omega=0.8,
+                  nu1=nu, nu2=nu, k=k, bc=mg.MG_NEUMANN0)
+    s.set_rhs(f)
+    s.set_initial(u0)
+    h = cycle.build_hierarchy(cycle.Params(centering="cell", dim=dim, n=N, coarsest=4, smoother=sm, omega=0.8,
+                                           nu1=nu, nu2=nu, k=k, bc="neumann"))
+    ref = cycle.cycles(h, f, u0, cycles)
+    for j in range(cycles):
+        s.vcycle(1)
+        u = s.solution()
+        err = rel_max(u, ref[j])
+        print(f"Neumann {dim}d N={N} {sm} nu={nu} cycle {j + 1}: max rel diff {err:.3e}, mean {np.mean(u):.1e}",
+              flush=True)
+        assert err <= TOL_ITERATE
+    s.close()
+
+
+def test_neumann_solve_and_fmg_match_oracle(mg):
+    N = 64
+    k = W.varcoef_k(N, 3)
+    f = W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)
+    p = cycle.Params(centering="cell", dim=3, n=N, coarsest=4, smoother="rbgs", nu1=3, nu2=3, k=k, bc="neumann")
+    s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, bc=mg.MG_NEUMANN0)
+    s.set_rhs(f)
+    s.set_initial(None)
+    code, cyc, rel = s.solve(1e-10)
+    u = s.solution()
+    hist = s.history()
+    s.set_rhs(f + 3.0)
+    s.fmg(1)
+    u_f = s.solution()
+    s.close()
+    u_ref, hist_ref, _ = cycle.solve(cycle.build_hierarchy(p), f, tol=1e-10)
+    u_fref = cycle.fmg(cycle.build_hierarchy(p), f + 3.0, 1)
+    print(f"Neumann 64^3 solve: {cyc} cycles (oracle {len(hist_ref) - 1}), relres {rel:.3e}, "
+          f"vs oracle {rel_max(u, u_ref):.2e}; FMG vs oracle {rel_max(u_f, u_fref):.2e}", flush=True)
+    assert code == mg.MG_OK and cyc == len(hist_ref) - 1
+    for a, b in zip(hist, hist_ref):
+        assert abs(a - b) <= 1e-9 * b + 1e-15    # the bar of the Dirichlet histories
+    assert rel_max(u, u_ref) <= 1e-9
+    assert rel_max(u_f, u_fref) <= TOL_ITERATE
+
+
+def test_neumann_256_converges_with_zero_mean(mg):
+    """The 256^3-cell variable-coefficient problem with zero-flux walls: to
+    1e-10 in a cycle count like the Dirichlet one's, zero-mean solution, and
+    the residual recomputed on the CPU from the returned solution."""
+    import torch
+    N = 256
+    k = W.varcoef_k(N, 3)
+    f = W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)
+    s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=torch.from_numpy(k).cuda(),
+                  bc=mg.MG_NEUMANN0)
+    s.set_rhs(torch.from_numpy(f).cuda())
+    s.set_initial(None)
+    code, cyc, rel = s.solve(1e-10)
+    u = s.solution()
+    s.close()
+    beta = cell.harmonic_faces(k)
+    r = cell.residual(u, cell.project_mean(f), beta, "neumann")
+    rel_cpu = float(np.linalg.norm(r) / np.linalg.norm(cell.project_mean(f)))
+    print(f"Neumann 256^3: {cyc} cycles, relres {rel:.3e}, CPU recomputed {rel_cpu:.3e}, mean {np.mean(u):.1e}",
+          flush=True)
+    assert code == mg.MG_OK and cyc <= 12 and rel_cpu <= 1.5e-10
+    assert abs(np.mean(u)) <= 1e-13 * np.max(np.abs(u))
