@@ -84,8 +84,8 @@ typedef struct mg_stencil {
 
 /* Boundary condition.  MG_DIRICHLET0: u = 0 on the boundary (node grids:
  * the boundary nodes; cell grids: on the walls, odd ghosts).  MG_NEUMANN0:
- * zero normal flux on the walls of a cell grid (Trottenberg et al. Sec.
- * 5.6.4): wall faces drop out of the stencil, interpolation uses even
+ * zero normal flux on the walls of a cell grid (the ExaSlang `Neumann`
+ * boundary): wall faces drop out of the stencil, interpolation uses even
  * ghosts; the operator annihilates constants, so mg_set_rhs projects f to
  * zero mean, every restricted right-hand side is projected likewise, the
  * coarsest solve returns the zero-mean solution (Cholesky of A + a 1 1^T)

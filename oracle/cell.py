@@ -19,7 +19,7 @@ wall), which is what the weight 2 and the missing off-diagonal term express.
 A Neumann wall face uses the even ghost u_g = u_i: its flux vanishes, so it
 has weight 0 and again no off-diagonal term; the operator then annihilates
 constants and the problem is solvable for right-hand sides of zero mean
-(Trottenberg et al., Sec. 5.6.4; the solution is fixed by zero mean).  Face
+(a singular compatible system; the solution is fixed by zero mean).  Face
 sums run in the order x-, x+, y-, y+, z-, z+.  Functions taking ``bc`` accept
 "dirichlet" (default) or "neumann".
 """

@@ -20,6 +20,11 @@ sides upcast and the result downcast.
 ``solve`` repeats cycles until ||r_k|| / ||r_0|| <= tol (the ExaSlang
 ``repeat ... until`` form), with the unweighted 2-norm over the unknowns.
 
+Galerkin coarse operators (``coarse_op="galerkin"``, node grids with damped
+Jacobi smoothing): every coarser level uses A_{l+1} = R A_l P (``galerkin``)
+for its smoothing, residual and coarsest solve, the finest level keeps the
+5/7-point stencil.
+
 Cell grids with Neumann walls (``bc="neumann"``): the right-hand side is
 projected to zero mean when a solve starts and after every restriction, the
 coarsest level is solved by the minimum-norm least-squares solution (the
@@ -39,7 +44,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg
 
-from . import cell, node
+from . import cell, galerkin, node
 
 
 @dataclass
@@ -56,6 +61,7 @@ class Params:
     k: np.ndarray | None = None      # cell coefficients (cell grids); None = 1
     cycle: str = "V"                 # "V", "W" or "F"
     bc: str = "dirichlet"            # "dirichlet", or "neumann" (cell grids)
+    coarse_op: str = "rediscretise"  # or "galerkin" (node grids, Jacobi): A_{l+1} = R A_l P
 
 
 @dataclass
@@ -65,6 +71,7 @@ class Hierarchy:
     beta: list = field(default_factory=list)       # per level, FP64 face lists (cell only)
     chol: np.ndarray | None = None                  # FP64 lower Cholesky factor, coarsest
     dense: np.ndarray | None = None                 # FP64 coarsest matrix (Neumann: singular)
+    W: list = field(default_factory=list)           # Galerkin: 3^d stencil per level
     _beta_cache: dict = field(default_factory=dict)
     coarse_solves: int = 0                          # coarsest solves performed (instrumentation)
 
@@ -104,6 +111,9 @@ def neumann(h: Hierarchy) -> bool:
 def build_hierarchy(p: Params) -> Hierarchy:
     if p.bc not in ("dirichlet", "neumann") or (p.bc == "neumann" and p.centering != "cell"):
         raise ValueError(f"boundary {p.bc!r} with {p.centering} centring")
+    if p.coarse_op not in ("rediscretise", "galerkin") or (
+            p.coarse_op == "galerkin" and (p.centering != "node" or p.smoother != "jacobi")):
+        raise ValueError(f"coarse operator {p.coarse_op!r} with {p.centering} centring and {p.smoother}")
     h = Hierarchy(p, ladder(p))
     if p.centering == "cell":
         k = p.k if p.k is not None else np.ones((p.n,) * p.dim)
@@ -111,6 +121,11 @@ def build_hierarchy(p: Params) -> Hierarchy:
         for _ in h.sizes[1:]:
             h.beta.append(cell.coarsen_faces(h.beta[-1]))
         A = cell.dense_matrix(h.beta[-1], h.sizes[-1], p.dim, p.bc)
+    elif p.coarse_op == "galerkin":
+        h.W.append(galerkin.laplacian_stencil(p.n, p.dim))
+        for _ in h.sizes[1:]:
+            h.W.append(galerkin.coarse_stencil(h.W[-1]))
+        A = galerkin.dense_matrix(h.W[-1], h.sizes[-1])
     else:
         A = node.dense_matrix(h.sizes[-1], p.dim)
     h.dense = A
@@ -120,7 +135,15 @@ def build_hierarchy(p: Params) -> Hierarchy:
 
 
 # ---------------------------------------------------------------- level ops
+def galerkin_level(h: Hierarchy, lvl: int) -> bool:
+    """Coarse levels of a Galerkin hierarchy carry R A P stencils; the finest
+    keeps the 5/7-point operator."""
+    return h.p.coarse_op == "galerkin" and lvl > 0
+
+
 def residual(h: Hierarchy, lvl: int, u, f):
+    if galerkin_level(h, lvl):
+        return galerkin.residual(u, f, h.W[lvl])
     if h.p.centering == "node":
         return node.residual(u, f)
     return cell.residual(u, f, h.beta_as(lvl, u.dtype), h.p.bc)
@@ -136,7 +159,9 @@ def unknowns(h: Hierarchy, a):
 def smooth(h: Hierarchy, lvl: int, u, f, sweeps: int, order=(0, 1)):
     p = h.p
     for _ in range(sweeps):
-        if p.centering == "node":
+        if galerkin_level(h, lvl):
+            u = galerkin.jacobi(u, f, h.W[lvl], p.omega)
+        elif p.centering == "node":
             u = node.jacobi(u, f, p.omega) if p.smoother == "jacobi" else node.rbgs(u, f, order)
         else:
             b = h.beta_as(lvl, u.dtype)
