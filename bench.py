@@ -93,7 +93,8 @@ def other_configs(mg, W, torch, np):
     """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound), the
     256^3-cell variable-coefficient case (FP64 and mixed to 1e-10, and FP64
     with zero-flux walls), W- and
-    F-cycle solves of the 513^3 Poisson problem, conjugate gradients with the
+    F-cycle solves of the 513^3 Poisson problem, damped-Jacobi cycles with
+    rediscretised and Galerkin coarse operators, conjugate gradients with the
     V-cycle as preconditioner on it, and full multigrid on a 513^3 problem
     with a closed-form discrete solution."""
     res = {}
@@ -197,6 +198,25 @@ def other_configs(mg, W, torch, np):
         dt = min(times)
         res[f"poisson3d_513_{name}cycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
                                                  "status": code_, "ms_per_cycle": round(1e3 * dt / cyc, 3)}
+        s.close()
+    # damped-Jacobi V(2,2) cycles with rediscretised and with Galerkin coarse operators
+    for cop, name in ((mg.MG_COARSE_REDISCRETISE, "rediscretised"), (mg.MG_COARSE_GALERKIN, "galerkin")):
+        s = mg.Solver(3, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2, coarse_op=cop)
+        s.set_rhs(f3)
+        s.set_initial(None)
+        s.solve(1e-10)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            s.set_initial(None)
+            t = time.perf_counter()
+            code_, cyc, rel = s.solve(1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        dt = min(times)
+        res[f"poisson3d_513_jacobi_{name}_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc,
+                                                     "relres": rel, "status": code_,
+                                                     "ms_per_cycle": round(1e3 * dt / cyc, 3)}
         s.close()
     # conjugate gradients preconditioned by the symmetric V(3,3)-cycle
     s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, krylov=1)

@@ -105,7 +105,13 @@ typedef struct mg_bc {
  * V-cycle, on each coarser level); a level directly above the coarsest is
  * visited once (Trottenberg, Oosterlee, Schueller, Multigrid, Sec. 2.4).
  * The solve server runs V-cycles only.  krylov = 1 reserves the vectors of
- * mg_pcg (five FP64 fields of the finest level; FP64 contexts). */
+ * mg_pcg (five FP64 fields of the finest level; FP64 contexts).  coarse_op:
+ * MG_COARSE_REDISCRETISE (every level the 5/7-point stencil with its own
+ * mesh width) or MG_COARSE_GALERKIN (every coarser level the Galerkin
+ * operator R A P of the next finer one, a constant 9/27-point stencil;
+ * node grids, damped Jacobi, FP64). */
+enum { MG_COARSE_REDISCRETISE = 0, MG_COARSE_GALERKIN = 1 };
+
 typedef struct mg_opts {
     int smoother;
     double omega;
@@ -115,6 +121,7 @@ typedef struct mg_opts {
     int post_order;
     int cycle;
     int krylov;
+    int coarse_op;
 } mg_opts;
 
 typedef struct mg_ctx mg_ctx;

@@ -16,7 +16,8 @@ READINGS = {
     "R1": "'coarsest 3x3' / '3^3 coarse solve' = 3^d interior unknowns, i.e. 5^d nodes "
           "(513 -> ... -> 5 is 8 grids, matching the stated 8 levels).",
     "R2": "Full weighting sums to 1 and linear interpolation is P = 2^d R^T.",
-    "R3": "Coarse operators are rediscretised (same stencil, coarse 1/H^2), not Galerkin RAP.",
+    "R3": "Coarse operators are rediscretised (same stencil, coarse 1/H^2) by default; the Galerkin "
+          "option uses R A P on every coarser level and keeps the finest 5/7-point stencil.",
     "R4": "Boundary nodes are not unknowns and hold 0 on every level for u, r and e.",
     "R5": "Red = even index sum (boundary index 0), updated first in pre- and post-smoothing.",
     "R6": "Initial guess 0 where unstated; the 2-D case uses U[-1,1] on interior nodes.",

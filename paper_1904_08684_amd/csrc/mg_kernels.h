@@ -58,6 +58,20 @@ hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const 
 
 // Deterministic reduction of `count` (sum, max) pairs to out[0..1];
 // scratch holds at least 2 * ceil(count / 4096) doubles.
+// Constant 3^d-point node stencil (a Galerkin coarse operator R A P):
+// weights by offset, z offset slowest and x fastest (2-D: the first 9).
+struct Stencil27 {
+    double w[27];
+};
+
+// FP64 node grids with a 3^d-point stencil W: damped Jacobi out of place
+// (out = u + (omega r) / W_centre; zero: u is zero) and r = f - A u (with
+// `norm`, per-block (sum r^2, max |r|) pairs as launch_residual).
+hipError_t launch_jacobi27(const Geom& g, bool zero, const void* u, const void* f, void* out, const Stencil27& W,
+                           double omega, hipStream_t st);
+hipError_t launch_residual27(const Geom& g, const void* u, const void* f, void* r, const Stencil27& W, bool norm,
+                             bool store, double* partials, long long* nblocks, hipStream_t st);
+
 // Cell grids: a -= (sum of a over all cells) / (number of cells), the sum
 // through per-block partials and launch_reduce into out[0].
 hipError_t launch_project(const Geom& g, double* a, double* partials, double* scratch, double* out,

@@ -1436,6 +1436,66 @@ __global__ __launch_bounds__(256) void k_pcg_dir(long long n2, double* __restric
     reinterpret_cast<double2*>(p)[i] = pv;
 }
 
+// ------------------------------------ 3^d-point node stencils (Galerkin)
+// Sum of W[o] u[x + o] over the 3^d offsets, z offset slowest, x fastest; the
+// neighbour (X, Y, Z) is colour (X + Y + Z) & 1 at X >> 1 (boundary nodes hold
+// zero, and an interior node's neighbours are inside the array).
+template <int D>
+__device__ __forceinline__ double stencil27_sum(const Geom& g, const double* __restrict__ u, int x, int y, int z,
+                                                const Stencil27& W) {
+    double acc = 0.0;
+#pragma unroll
+    for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); ++oz)
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int k = (D == 3 ? 9 * (oz + 1) : 0) + 3 * (oy + 1) + (ox + 1);
+                const int X = x + ox, Y = y + oy, Z = z + oz;
+                const double t = W.w[k] * u[(long long)((X + Y + Z) & 1) * g.cs + row_off(g, Y, Z) + (X >> 1)];
+                acc = k == 0 ? t : acc + t;
+            }
+    return acc;
+}
+
+template <int D, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_node27_residual(Geom g, Space sp, const double* __restrict__ u,
+                                                         const double* __restrict__ f, double* __restrict__ r,
+                                                         Stencil27 W, double* __restrict__ part) {
+    const Ex ex = solo_ex();
+    double sq = 0.0, mx = 0.0;
+    Pt p;
+    if (map_point(ex, sp, p)) {
+        const int x = 2 * p.xs + ((p.y + p.z + p.c) & 1);
+        if (x >= 1 && x <= g.n - 2) {
+            const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
+            const double v = f[me] - stencil27_sum<D>(g, u, x, p.y, p.z, W);
+            if (STORE) r[me] = v;
+            sq = v * v;
+            mx = fabs(v);
+        }
+    }
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
+template <int D, bool ZERO>
+__global__ __launch_bounds__(256) void k_node27_jacobi(Geom g, Space sp, const double* __restrict__ u,
+                                                       const double* __restrict__ f, double* __restrict__ out,
+                                                       Stencil27 W, double omega) {
+    Pt p;
+    if (!map_point(solo_ex(), sp, p)) return;
+    const int x = 2 * p.xs + ((p.y + p.z + p.c) & 1);
+    if (x < 1 || x > g.n - 2) return;
+    const long long me = (long long)p.c * g.cs + row_off(g, p.y, p.z) + p.xs;
+    const double wc = W.w[D == 3 ? 13 : 4];
+    if (ZERO) {
+        out[me] = 0.0 + (omega * f[me]) / wc;     // r = f when u = 0
+    } else {
+        const double r = f[me] - stencil27_sum<D>(g, u, x, p.y, p.z, W);
+        out[me] = u[me] + (omega * r) / wc;
+    }
+}
+
 // ------------------------------------------- zero-mean projection (Neumann)
 // Sum over all cells of a cell-grid FP64 field into per-block partials
 // (fixed assignment of cells to threads: deterministic), then a -= sum / count.
@@ -1991,6 +2051,35 @@ long long reduce_scratch_pairs(long long count) {
         total += count;
     }
     return total + 1;
+}
+
+hipError_t launch_jacobi27(const Geom& g, bool zero, const void* u, const void* f, void* out, const Stencil27& W,
+                           double omega, hipStream_t st) {
+    if (g.cell) return hipErrorInvalidValue;
+    const Space sp = space_of(g, 2, 0);
+    MG_DISPATCH_DIM(g, if (zero) k_node27_jacobi<D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                           g, sp, cp<double>(u), cp<double>(f), mp<double>(out), W, omega);
+                       else k_node27_jacobi<D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
+                           g, sp, cp<double>(u), cp<double>(f), mp<double>(out), W, omega));
+    return hipGetLastError();
+}
+
+hipError_t launch_residual27(const Geom& g, const void* u, const void* f, void* r, const Stencil27& W, bool norm,
+                             bool store, double* partials, long long* nblocks, hipStream_t st) {
+    if (g.cell) return hipErrorInvalidValue;
+    const Space sp = space_of(g, 2, 0);
+    if (nblocks) *nblocks = sp.blocks();
+    if (norm && store) {
+        MG_DISPATCH_DIM(g, k_node27_residual<D, true, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<double>(u), cp<double>(f), mp<double>(r), W, partials));
+    } else if (norm) {
+        MG_DISPATCH_DIM(g, k_node27_residual<D, true, false><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<double>(u), cp<double>(f), mp<double>(r), W, partials));
+    } else {
+        MG_DISPATCH_DIM(g, k_node27_residual<D, false, true><<<grid_of(sp), block_of(sp), 0, st>>>(
+                               g, sp, cp<double>(u), cp<double>(f), mp<double>(r), W, partials));
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_project(const Geom& g, double* a, double* partials, double* scratch, double* out,

@@ -52,6 +52,8 @@ struct Level {
     void* utmp[2] = {nullptr, nullptr};
     void* beta[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     size_t field_bytes[2] = {0, 0};
+    bool gal = false;             // Galerkin stencil W instead of the 5/7-point operator
+    Stencil27 W{};
 };
 
 struct Rec {

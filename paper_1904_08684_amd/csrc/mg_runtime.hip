@@ -91,6 +91,11 @@ int validate(const mg_grid* g, const mg_stencil* st, const mg_opts* o, std::stri
     if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) return bad("unknown cycle type");
     if (o->krylov != 0 && o->krylov != 1) return bad("krylov must be 0 or 1");
     if (o->krylov && o->precision != MG_FP64) return bad("krylov vectors need an FP64 context");
+    if (o->coarse_op != MG_COARSE_REDISCRETISE && o->coarse_op != MG_COARSE_GALERKIN)
+        return bad("unknown coarse operator");
+    if (o->coarse_op == MG_COARSE_GALERKIN &&
+        (g->centering != MG_NODE || o->smoother != MG_JACOBI || o->precision != MG_FP64))
+        return bad("Galerkin coarse operators need a node grid, damped Jacobi and FP64");
     return MG_OK;
 }
 
@@ -269,10 +274,63 @@ void coarsen_faces(const Geom& gf, const std::vector<double> bf[3], const Geom& 
 }
 
 // Dense FP64 matrix of the coarsest level over its unknowns in C order.
+// Stencil index of the offset (oz, oy, ox), z slowest (2-D: oz = 0, 9 entries).
+int st_index(int d, int oz, int oy, int ox) { return (d == 3 ? 9 * (oz + 1) : 0) + 3 * (oy + 1) + (ox + 1); }
+
+// The 5/7-point Laplacian of a node level as a 3^d stencil: 2d s at the
+// centre, -s at the axis neighbours, s = (n - 1)^2.
+Stencil27 laplacian27(const Geom& g) {
+    Stencil27 W{};
+    const int d = g.dim;
+    const double s = (double)(g.n - 1) * (g.n - 1);
+    W.w[st_index(d, 0, 0, 0)] = 2.0 * d * s;
+    W.w[st_index(d, 0, 0, -1)] = -s;
+    W.w[st_index(d, 0, 0, 1)] = -s;
+    W.w[st_index(d, 0, -1, 0)] = -s;
+    W.w[st_index(d, 0, 1, 0)] = -s;
+    if (d == 3) {
+        W.w[st_index(d, -1, 0, 0)] = -s;
+        W.w[st_index(d, 1, 0, 0)] = -s;
+    }
+    return W;
+}
+
+// Galerkin coarse stencil R A P of a constant fine stencil: full weighting
+// R (weights prod (2 - |a_k|) / 4 over offsets a) and linear interpolation P
+// (weight prod phi(v_k), phi(0) = 1, phi(+-1) = 1/2), so that the coarse
+// entry at offset J is sum_a R_a sum_b W_b phi(a + b - 2 J).
+Stencil27 galerkin_coarse(const Stencil27& Wf, int d) {
+    auto phi = [](int v) { return v == 0 ? 1.0 : (v == 1 || v == -1 ? 0.5 : 0.0); };
+    auto rho = [](int a) { return a == 0 ? 0.5 : 0.25; };
+    const int zl = d == 3 ? -1 : 0, zh = d == 3 ? 1 : 0;
+    Stencil27 Wc{};
+    for (int jz = zl; jz <= zh; ++jz)
+        for (int jy = -1; jy <= 1; ++jy)
+            for (int jx = -1; jx <= 1; ++jx) {
+                double acc = 0.0;
+                for (int az = zl; az <= zh; ++az)
+                    for (int ay = -1; ay <= 1; ++ay)
+                        for (int ax = -1; ax <= 1; ++ax) {
+                            double inner = 0.0;
+                            for (int bz = zl; bz <= zh; ++bz)
+                                for (int by = -1; by <= 1; ++by)
+                                    for (int bx = -1; bx <= 1; ++bx) {
+                                        const double ph = phi(ax + bx - 2 * jx) * phi(ay + by - 2 * jy) *
+                                                          (d == 3 ? phi(az + bz - 2 * jz) : 1.0);
+                                        inner += Wf.w[st_index(d, bz, by, bx)] * ph;
+                                    }
+                            acc += rho(ax) * rho(ay) * (d == 3 ? rho(az) : 1.0) * inner;
+                        }
+                Wc.w[st_index(d, jz, jy, jx)] = acc;
+            }
+    return Wc;
+}
+
 // With Neumann walls the matrix is singular (constants); a 1 1^T with a the
 // mean diagonal over m is added, which makes it SPD and leaves the solution
-// for a zero-mean right-hand side that of A itself with zero mean.
-std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta) {
+// for a zero-mean right-hand side that of A itself with zero mean.  With a
+// Galerkin stencil W the node-grid matrix is assembled from W.
+std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta, const Stencil27* W) {
     const int d = g.dim;
     const int side = g.cell ? g.n : g.n - 2, off = g.cell ? 0 : 1;
     const int m = side * side * (d == 3 ? side : 1);
@@ -284,7 +342,16 @@ std::vector<double> coarse_matrix(const Geom& g, const std::vector<double>* beta
         for (int y = off; y < off + side; ++y)
             for (int x = off; x < off + side; ++x) {
                 const int i = idx(x, y, z);
-                if (!g.cell) {
+                if (!g.cell && W) {
+                    for (int oz = (d == 3 ? -1 : 0); oz <= (d == 3 ? 1 : 0); ++oz)
+                        for (int oy = -1; oy <= 1; ++oy)
+                            for (int ox = -1; ox <= 1; ++ox) {
+                                const int X = x + ox, Y = y + oy, Z = z + oz;
+                                if (X < 1 || X > g.n - 2 || Y < 1 || Y > g.n - 2) continue;
+                                if (d == 3 && (Z < 1 || Z > g.n - 2)) continue;
+                                A[(size_t)i * m + idx(X, Y, Z)] = W->w[st_index(d, oz, oy, ox)];
+                            }
+                } else if (!g.cell) {
                     A[(size_t)i * m + i] = (double)(2 * d) * s;
                     const int nbx[6] = {x - 1, x + 1, x, x, x, x}, nby[6] = {y, y, y - 1, y + 1, y, y},
                               nbz[6] = {z, z, z, z, z - 1, z + 1};
@@ -475,8 +542,9 @@ int Ctx::jacobi(int l, int pr, bool zero) {
     }
     hipEvent_t e0 = begin();
     int rc = record(MG_K_SMOOTH, l,
-                    launch_jacobi(L.g, pr, zero, L.u[pr], L.f[pr], L.utmp[pr], faces(l, pr), scale(l), opts.omega,
-                                  stream),
+                    L.gal ? launch_jacobi27(L.g, zero, L.u[pr], L.f[pr], L.utmp[pr], L.W, opts.omega, stream)
+                          : launch_jacobi(L.g, pr, zero, L.u[pr], L.f[pr], L.utmp[pr], faces(l, pr), scale(l),
+                                          opts.omega, stream),
                     e0, "jacobi");
     if (rc) return rc;
     std::swap(L.u[pr], L.utmp[pr]);
@@ -565,8 +633,9 @@ int Ctx::residual(int l, int pr, bool norm, bool store) {
     long long nb = 0;
     hipEvent_t e0 = begin();
     int rc = record(MG_K_RESIDUAL, l,
-                    launch_residual(L.g, pr, L.u[pr], L.f[pr], L.r[pr], faces(l, pr), scale(l), norm, store,
-                                    partials, &nb, stream),
+                    L.gal ? launch_residual27(L.g, L.u[pr], L.f[pr], L.r[pr], L.W, norm, store, partials, &nb, stream)
+                          : launch_residual(L.g, pr, L.u[pr], L.f[pr], L.r[pr], faces(l, pr), scale(l), norm, store,
+                                            partials, &nb, stream),
                     e0, "residual");
     if (rc || !norm) return rc;
     e0 = begin();
@@ -654,7 +723,7 @@ int Ctx::fmg(int cpl) {
 int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
     int rc = smooth(l, pr, opts.nu1, from_zero, 0);
-    if (!rc && !rec && grid.centering == MG_NODE && fused_transfers(lv[l].g)) {
+    if (!rc && !rec && grid.centering == MG_NODE && !lv[l].gal && fused_transfers(lv[l].g)) {
         // fine residual and full weighting in one pass; r is not written
         hipEvent_t e0 = begin();
         rc = record(MG_K_RESTRICT, l,
@@ -1110,10 +1179,20 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
         }
         if (!rc) c->coarse_beta_host.assign(bf, bf + 3);
     }
+    // Galerkin stencils of the coarser levels
+    if (!rc && o->coarse_op == MG_COARSE_GALERKIN) {
+        Stencil27 W = laplacian27(c->lv[0].g);
+        for (int l = 1; l < c->L; ++l) {
+            W = galerkin_coarse(W, c->lv[l].g.dim);
+            c->lv[l].gal = true;
+            c->lv[l].W = W;
+        }
+    }
     // coarsest matrix, Cholesky factor
     if (!rc) {
-        std::vector<double> A = coarse_matrix(c->lv.back().g, c->coarse_beta_host.empty() ? nullptr
-                                                                                         : c->coarse_beta_host.data());
+        std::vector<double> A = coarse_matrix(c->lv.back().g,
+                                              c->coarse_beta_host.empty() ? nullptr : c->coarse_beta_host.data(),
+                                              c->lv.back().gal ? &c->lv.back().W : nullptr);
         if (!cholesky(A, c->m)) rc = c->fail(MG_EINVAL, "coarsest matrix is not SPD");
         if (!rc)
             rc = c->dev(hipMemcpyAsync(c->chol, A.data(), A.size() * 8, hipMemcpyHostToDevice, c->stream),
@@ -1150,6 +1229,7 @@ void mg_default_opts(mg_opts* o) {
     o->post_order = 0;
     o->cycle = MG_CYCLE_V;
     o->krylov = 0;
+    o->coarse_op = MG_COARSE_REDISCRETISE;
 }
 
 int mg_workspace_bytes(const mg_grid* g, const mg_stencil* st, const mg_opts* o, size_t* bytes) {

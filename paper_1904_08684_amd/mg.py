@@ -27,6 +27,7 @@ MG_ENOTCONV, MG_ENONFINITE, MG_EDIVERGED, MG_EBUSY = -4, -5, -6, -7
 MG_NODE, MG_CELL = 0, 1
 MG_LAPLACE, MG_VARCOEF = 0, 1
 MG_DIRICHLET0, MG_NEUMANN0 = 0, 1
+MG_COARSE_REDISCRETISE, MG_COARSE_GALERKIN = 0, 1
 MG_JACOBI, MG_RBGS = 0, 1
 MG_FP64, MG_MIXED = 0, 1
 MG_CYCLE_V, MG_CYCLE_W, MG_CYCLE_F = 0, 1, 2
@@ -54,7 +55,7 @@ class mg_bc(C.Structure):
 class mg_opts(C.Structure):
     _fields_ = [("smoother", C.c_int), ("omega", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("precision", C.c_int), ("max_cycles", C.c_int), ("post_order", C.c_int), ("cycle", C.c_int),
-                ("krylov", C.c_int)]
+                ("krylov", C.c_int), ("coarse_op", C.c_int)]
 
 
 _P = C.c_void_p
@@ -119,10 +120,11 @@ def make_grid(dim: int, n: int, centering: int = MG_NODE, coarsest: int | None =
 
 
 def make_opts(smoother=MG_RBGS, omega=0.8, nu1=2, nu2=2, precision=MG_FP64, max_cycles=100,
-              post_order=0, cycle=0, krylov=0) -> mg_opts:
+              post_order=0, cycle=0, krylov=0, coarse_op=0) -> mg_opts:
     o = mg_opts()
     o.smoother, o.omega, o.nu1, o.nu2 = smoother, omega, nu1, nu2
     o.precision, o.max_cycles, o.post_order, o.cycle, o.krylov = precision, max_cycles, post_order, cycle, krylov
+    o.coarse_op = coarse_op
     return o
 
 
@@ -153,12 +155,13 @@ class Solver:
     def __init__(self, dim: int, n: int, centering: int = MG_NODE, coarsest: int | None = None,
                  smoother: int = MG_RBGS, omega: float = 0.8, nu1: int = 2, nu2: int = 2,
                  precision: int = MG_FP64, max_cycles: int = 100, post_order: int = 0, cycle: int = 0,
-                 krylov: int = 0, bc: int = 0,
+                 krylov: int = 0, bc: int = 0, coarse_op: int = 0,
                  k=None, stream=None, device: str = "cuda"):
         import torch
         self.dim, self.n, self.centering = dim, n, centering
         self.grid = make_grid(dim, n, centering, coarsest)
-        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order, cycle, krylov)
+        self.opts = make_opts(smoother, omega, nu1, nu2, precision, max_cycles, post_order, cycle, krylov,
+                              coarse_op)
         self.stencil = mg_stencil()
         self._k = None
         if k is not None:

@@ -148,3 +148,16 @@ def test_neumann_combinations_rejected_before_any_device_work(mg):
         rc = mg.mg_setup(C.byref(g), None, C.byref(bc), C.byref(o), C.c_void_p(256), 1 << 30, None, C.byref(h))
         assert rc == mg.MG_EINVAL
         assert mg.mg_last_error(None)
+
+
+def test_galerkin_option_validation(mg):
+    """Galerkin coarse operators: node grids, damped Jacobi, FP64 only."""
+    b = C.c_size_t()
+    ok = mg.make_opts(smoother=mg.MG_JACOBI, coarse_op=mg.MG_COARSE_GALERKIN)
+    assert mg.mg_workspace_bytes(C.byref(mg.make_grid(3, 65)), None, C.byref(ok), C.byref(b)) == mg.MG_OK
+    for g, kw in ((mg.make_grid(3, 65), {"smoother": mg.MG_RBGS}),
+                  (mg.make_grid(3, 65), {"smoother": mg.MG_JACOBI, "precision": mg.MG_MIXED}),
+                  (mg.make_grid(3, 64, mg.MG_CELL), {"smoother": mg.MG_JACOBI}),
+                  (mg.make_grid(3, 65), {"smoother": mg.MG_JACOBI, "coarse_op": 2})):
+        o = mg.make_opts(**{"coarse_op": mg.MG_COARSE_GALERKIN, **kw})
+        assert mg.mg_workspace_bytes(C.byref(g), None, C.byref(o), C.byref(b)) == mg.MG_EINVAL, kw

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import scipy.fft
 
-from oracle import cell, cycle, node
+from oracle import cell, cycle, galerkin, node
 from paper_1904_08684_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -596,3 +596,64 @@ def test_neumann_256_converges_with_zero_mean(mg):
           flush=True)
     assert code == mg.MG_OK and cyc <= 12 and rel_cpu <= 1.5e-10
     assert abs(np.mean(u)) <= 1e-13 * np.max(np.abs(u))
+
+
+# ---------------------------------------------- Galerkin coarse operators
+@pytest.mark.parametrize("dim,n", [(2, 65), (3, 33)])
+def test_galerkin_stencil_ops_at_level_1(mg, dim, n):
+    """The 9/27-point residual and Jacobi kernels of level 1 against the
+    oracle's stencil operators (the host's R A P and the oracle's differ only
+    by rounding)."""
+    s = mg.Solver(dim, n, smoother=mg.MG_JACOBI, omega=0.8, coarse_op=mg.MG_COARSE_GALERKIN)
+    nc = s.level_size(1)
+    u = W.interior_uniform(nc, dim, 41)
+    f = W.interior_uniform(nc, dim, 42) * (nc - 1) ** 2
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=dim, n=n, smoother="jacobi", omega=0.8,
+                                           coarse_op="galerkin"))
+    s.level_set(1, mg.MG_FIELD_U, u)
+    s.level_set(1, mg.MG_FIELD_F, f)
+    s.apply(mg.MG_OP_RESIDUAL, 1)
+    r = s.level_get(1, mg.MG_FIELD_R)
+    s.apply(mg.MG_OP_JACOBI, 1)
+    uj = s.level_get(1, mg.MG_FIELD_U)
+    s.close()
+    r_ref = galerkin.residual(u, f, h.W[1])
+    uj_ref = galerkin.jacobi(u, f, h.W[1], 0.8)
+    er, ej = rel_max(r, r_ref), rel_max(uj, uj_ref)
+    print(f"Galerkin level-1 ops {dim}d n={n}: residual {er:.2e}, Jacobi {ej:.2e}", flush=True)
+    assert er <= 1e-13 and ej <= 1e-14
+
+
+@pytest.mark.parametrize("dim,n,nu,cycles", [(2, 129, 2, 3), (3, 65, 2, 3), (3, 257, 3, 2)])
+def test_galerkin_per_iterate(mg, dim, n, nu, cycles):
+    f = W.interior_uniform(n, dim, W.SEED_F_3D)
+    u0 = W.interior_uniform(n, dim, W.SEED_U0_2D)
+    s = mg.Solver(dim, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=nu, nu2=nu, coarse_op=mg.MG_COARSE_GALERKIN)
+    s.set_rhs(f)
+    s.set_initial(u0)
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=dim, n=n, smoother="jacobi", omega=0.8, nu1=nu,
+                                           nu2=nu, coarse_op="galerkin"))
+    ref = cycle.cycles(h, f, u0, cycles)
+    for j in range(cycles):
+        s.vcycle(1)
+        err = rel_max(s.solution(), ref[j])
+        print(f"Galerkin {dim}d n={n} V({nu},{nu}) cycle {j + 1}: max rel diff {err:.3e}", flush=True)
+        assert err <= TOL_ITERATE
+    s.close()
+
+
+def test_galerkin_solve_matches_oracle(mg):
+    n = 129
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    s = mg.Solver(3, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2, coarse_op=mg.MG_COARSE_GALERKIN)
+    s.set_rhs(f)
+    s.set_initial(None)
+    code, cyc, rel = s.solve(1e-10)
+    u = s.solution()
+    s.close()
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="jacobi", omega=0.8, nu1=2,
+                                           nu2=2, coarse_op="galerkin"))
+    u_ref, hist, _ = cycle.solve(h, f, tol=1e-10)
+    print(f"Galerkin 129^3 solve: {cyc} cycles (oracle {len(hist) - 1}), relres {rel:.3e}, "
+          f"vs oracle {rel_max(u, u_ref):.2e}", flush=True)
+    assert code == mg.MG_OK and abs(cyc - (len(hist) - 1)) <= 1 and rel_max(u, u_ref) <= 1e-9
