@@ -1,0 +1,61 @@
+/* Volume terms of the quadrature-free discontinuous Galerkin discretisation
+ * of the shallow water equations on triangles (the paper's Sec. 3 on the
+ * discretisation, equations mass_basis and momentum_basis_u): for every
+ * element e and test function p,
+ *
+ *   E[j][p][e] = (A~(c, u), grad(phi_ep e_j))_{Omega_e},  j = 0, 1, 2,
+ *
+ * with the flux tensor rows (U, V), (U u + g xi (H + h_b) / 2, U v),
+ * (V u, V v + g xi (H + h_b) / 2), H = xi + h_b, evaluated algebraically:
+ * products of element coefficients with integrals of products of the
+ * reference basis and its gradients, scaled by the element's affine map.
+ *
+ * Reference triangle (0,0), (1,0), (0,1); F_e(x^) = B_e x^ + a_e1 with
+ * B_e = [a_e2 - a_e1, a_e3 - a_e1]; the element basis is
+ * phi_ep = |det B_e|^(-1/2) phi^_p o F_e^-1 with the paper's ten orthonormal
+ * polynomials phi^_1 .. phi^_10 (K(k) = 1, 3, 6, 10 of them for order
+ * k = 0..3), so that the paper's factors 1/|det B_e| and 1/|det B_e|^(3/2)
+ * appear (written with det B_e itself, which keeps the sign right for
+ * elements of either orientation).  h_b is constant on each element.
+ *
+ * Status codes are those of mg.h. */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Doubles in the reference table of order k: 2 K^2 + 2 K^3, or 0 for k
+ * outside 0..3. */
+long long dg_reference_size(int k);
+
+/* Host: the exact reference integrals of order k into ref (caller-owned,
+ * dg_reference_size(k) doubles): G[l][p][i] = int d_l phi^_p phi^_i, then
+ * H[l][p][i][m] = int d_l phi^_p phi^_i phi^_m over the reference triangle,
+ * l = 0, 1 (d/dx^1, d/dx^2), row-major.  Computed from the monomial
+ * integrals a! b! / (a + b + 2)!.  MG_EINVAL for a bad k or NULL ref. */
+int dg_reference_integrals(int k, double* ref);
+
+/* Device: the volume terms of ne elements of order k, all arrays in device
+ * memory, element index fastest (structure of arrays):
+ *   c[(j K + i) ne + e]    coefficients of xi, U, V (j = 0, 1, 2)
+ *   u[(j K + i) ne + e]    coefficients of u, v (j = 0, 1)
+ *   B[q ne + e]            B_e entries B11, B12, B21, B22 (q = 0..3)
+ *   hb[e]                  bathymetry on the element
+ *   ref                    the table of dg_reference_integrals, on the device
+ *   out[(j K + p) ne + e]  E[j][p][e]
+ * Enqueued on `stream` (a hipStream_t, NULL = the default stream); returns
+ * once launched.  MG_EINVAL for a bad k, ne < 0 or a NULL array (ne = 0 is a
+ * no-op), MG_EDEVICE for a launch failure.  Elements with det B_e = 0 give
+ * non-finite values. */
+int dg_volume_integrals(int k, long long ne, const double* c, const double* u, const double* B,
+                        const double* hb, double g, const double* ref, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

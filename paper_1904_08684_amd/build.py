@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmg.so")
 
-SOURCES = ["mg_kernels.hip", "mg_runtime.hip", "mg_server.hip"]
+SOURCES = ["mg_kernels.hip", "mg_runtime.hip", "mg_server.hip", "mg_dg.hip"]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -425,3 +425,52 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------- DG volume terms (include/dg.h)
+_dsigs = {
+    "dg_reference_size": (C.c_longlong, [C.c_int]),
+    "dg_reference_integrals": (C.c_int, [C.c_int, _D]),
+    "dg_volume_integrals": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, C.c_double, _P, _P, _P]),
+}
+for _name, (_res, _args) in _dsigs.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+DG_K = {0: 1, 1: 3, 2: 6, 3: 10}
+
+
+def dg_reference(k: int) -> np.ndarray:
+    """The exact reference integrals of order k (host): G (2, K, K), H (2, K, K, K)."""
+    K = DG_K[k]
+    ref = np.empty(int(dg_reference_size(k)), dtype=np.float64)
+    _check(dg_reference_integrals(k, ref.ctypes.data_as(_D)))
+    return ref[:2 * K * K].reshape(2, K, K), ref[2 * K * K:].reshape(2, K, K, K)
+
+
+class DGVolume:
+    """Volume terms of order k on the GPU; the reference table lives on the device."""
+
+    def __init__(self, k: int, device: str = "cuda"):
+        import torch
+        self.k, self.K = k, DG_K[k]
+        G, H = dg_reference(k)
+        self.ref = torch.from_numpy(np.concatenate([G.ravel(), H.ravel()])).to(device)
+
+    def __call__(self, c, u, B, hb, g: float, out, stream=None):
+        """c (3K, ne), u (2K, ne), B (4, ne), hb (ne,), out (3K, ne): contiguous
+        FP64 device tensors, element index fastest."""
+        import torch
+        ne = hb.shape[0]
+        for t, rows in ((c, 3 * self.K), (u, 2 * self.K), (B, 4), (out, 3 * self.K)):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (rows, ne):
+                raise ValueError("expected contiguous FP64 device tensors of shape (rows, ne)")
+        if hb.dtype != torch.float64 or not hb.is_cuda or not hb.is_contiguous():
+            raise ValueError("hb must be a contiguous FP64 device tensor")
+        st = stream if stream is not None else torch.cuda.current_stream(hb.device)
+        _check(dg_volume_integrals(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(u.data_ptr()),
+                                   C.c_void_p(B.data_ptr()), C.c_void_p(hb.data_ptr()), g,
+                                   C.c_void_p(self.ref.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   C.c_void_p(st.cuda_stream)))

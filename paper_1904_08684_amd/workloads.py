@@ -135,3 +135,46 @@ def cell_uniform(N: int, dim: int, seed: int, lo=-1.0, hi=1.0) -> np.ndarray:
     """U[lo, hi] samples on N^dim cells."""
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=(N,) * dim)
+
+
+# ------------------------------------------------ DG element workloads
+SEED_DG_MESH = 20
+SEED_DG_FIELDS = 21
+
+
+def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.25) -> np.ndarray:
+    """Affine maps of a split-quad triangulation of the unit square: nx x ny
+    squares, each cut along one diagonal into two counter-clockwise
+    triangles, interior vertices moved by up to `jitter` of a cell width so
+    that every element has its own map.  Returns B (4, 2 nx ny) with rows
+    B11, B12, B21, B22 of B_e = [a_e2 - a_e1, a_e3 - a_e1]."""
+    rng = np.random.default_rng(seed)
+    xs = np.linspace(0.0, 1.0, nx + 1)
+    ys = np.linspace(0.0, 1.0, ny + 1)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    d = jitter * min(1.0 / nx, 1.0 / ny)
+    X[1:-1, 1:-1] += rng.uniform(-d, d, (nx - 1, ny - 1))
+    Y[1:-1, 1:-1] += rng.uniform(-d, d, (nx - 1, ny - 1))
+    p00 = np.stack([X[:-1, :-1], Y[:-1, :-1]], -1).reshape(-1, 2)
+    p10 = np.stack([X[1:, :-1], Y[1:, :-1]], -1).reshape(-1, 2)
+    p01 = np.stack([X[:-1, 1:], Y[:-1, 1:]], -1).reshape(-1, 2)
+    p11 = np.stack([X[1:, 1:], Y[1:, 1:]], -1).reshape(-1, 2)
+    # lower-right (p00, p10, p11) and upper-left (p00, p11, p01) triangles
+    a1 = np.concatenate([p00, p00])
+    a2 = np.concatenate([p10, p11])
+    a3 = np.concatenate([p11, p01])
+    e2, e3 = a2 - a1, a3 - a1
+    return np.ascontiguousarray(np.stack([e2[:, 0], e3[:, 0], e2[:, 1], e3[:, 1]]))
+
+
+def dg_fields(K: int, ne: int, seed: int = SEED_DG_FIELDS):
+    """Coefficients of (xi, U, V) and (u, v), (3K, ne) and (2K, ne), and a
+    per-element bathymetry in [1, 5]: N(0, 1) for the constant mode, N(0,
+    0.1) for the others."""
+    rng = np.random.default_rng(seed)
+    scale = np.full((K, 1), 0.1)
+    scale[0] = 1.0
+    c = rng.normal(0.0, 1.0, (3, K, ne)) * scale
+    u = rng.normal(0.0, 1.0, (2, K, ne)) * scale
+    hb = rng.uniform(1.0, 5.0, ne)
+    return np.ascontiguousarray(c.reshape(3 * K, ne)), np.ascontiguousarray(u.reshape(2 * K, ne)), hb

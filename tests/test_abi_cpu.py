@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI: the library loads, exports every function
-include/mg.h declares, and its host logic (validation, workspace plan, error
+include/*.h declares, and its host logic (validation, workspace plan, error
 strings, device detection) behaves without a GPU."""
 import ctypes as C
 import os
@@ -17,7 +17,7 @@ def declared_functions():
             continue
         text = open(os.path.join(ROOT, "include", fn)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(mg_\w+)\s*\(", text, flags=re.M):
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b((?:mg|dg)_\w+)\s*\(", text, flags=re.M):
             names.add(m.group(1))
     return sorted(names)
 
@@ -32,6 +32,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("mg_setup", "mg_vcycle", "mg_solve", "mg_workspace_bytes", "mg_destroy",
                  "mg_set_rhs", "mg_get_solution", "mg_strerror", "mg_last_error"):
+        assert want in names
+    for want in ("dg_reference_size", "dg_reference_integrals", "dg_volume_integrals"):
         assert want in names
 
 
