@@ -86,8 +86,11 @@ int k_of(int k) { return k == 0 ? 1 : k == 1 ? 3 : k == 2 ? 6 : k == 3 ? 10 : 0;
 
 // One thread per element: for every test function p the two-function terms
 // (mass flux and bathymetry) and, per i, the sums over m of the
-// three-function integrals times u, v and xi, contracted with the element's
-// map and the coefficients of i.
+// three-function integrals, contracted with the coefficients of i.  The
+// velocity enters the advective terms only through
+// u d/dx1 + v d/dx2 = (1/det) [(B22 u - B12 v) d/dx^1 + (B11 v - B21 u) d/dx^2],
+// so the element's map is folded into two combined velocity vectors first
+// and each (p, i) costs four multiply-adds per m.
 template <int K>
 __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* __restrict__ c,
                                                    const double* __restrict__ u, const double* __restrict__ B,
@@ -95,16 +98,17 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
                                                    const double* __restrict__ ref, double* __restrict__ out) {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= ne) return;
-    double xi[K], U[K], V[K], uu[K], vv[K];
+    const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
+    double xi[K], U[K], V[K], wa[K], wb[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         xi[i] = c[(long long)i * ne + e];
         U[i] = c[(long long)(K + i) * ne + e];
         V[i] = c[(long long)(2 * K + i) * ne + e];
-        uu[i] = u[(long long)i * ne + e];
-        vv[i] = u[(long long)(K + i) * ne + e];
+        const double uu = u[(long long)i * ne + e], vv = u[(long long)(K + i) * ne + e];
+        wa[i] = b22 * uu - b12 * vv;
+        wb[i] = b11 * vv - b21 * uu;
     }
-    const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
     const double det = b11 * b22 - b12 * b21;
     const double s2 = 1.0 / det;                         // two-function integrals
     const double s3 = s2 / std::sqrt(std::fabs(det));    // three-function integrals
@@ -123,19 +127,15 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
             e1 += U[i] * d1 + V[i] * d2;
             l2 += xi[i] * d1;
             l3 += xi[i] * d2;
-            double h0u = 0.0, h0v = 0.0, h0x = 0.0, h1u = 0.0, h1v = 0.0, h1x = 0.0;
+            double t = 0.0, h0x = 0.0, h1x = 0.0;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 const double h0 = H0[(p * K + i) * K + m], h1 = H1[(p * K + i) * K + m];
-                h0u += h0 * uu[m];
-                h0v += h0 * vv[m];
+                t += h0 * wa[m] + h1 * wb[m];
                 h0x += h0 * xi[m];
-                h1u += h1 * uu[m];
-                h1v += h1 * vv[m];
                 h1x += h1 * xi[m];
             }
-            // sum over m of u_m dx1(.) + v_m dx2(.), and of xi_m dx1(.), xi_m dx2(.)
-            const double t = (b22 * h0u - b21 * h1u) + (b11 * h1v - b12 * h0v);
+            // sums over m of xi_m dx1(.) and xi_m dx2(.) (times det)
             const double px = b22 * h0x - b21 * h1x, py = b11 * h1x - b12 * h0x;
             e2 += U[i] * t + 0.5 * g * xi[i] * px;
             e3 += V[i] * t + 0.5 * g * xi[i] * py;
