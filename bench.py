@@ -95,8 +95,8 @@ def other_configs(mg, W, torch, np):
     with zero-flux walls), W- and
     F-cycle solves of the 513^3 Poisson problem, damped-Jacobi cycles with
     rediscretised and Galerkin coarse operators, conjugate gradients with the
-    V-cycle as preconditioner on it, and full multigrid on a 513^3 problem
-    with a closed-form discrete solution."""
+    V-cycle as preconditioner on it, full multigrid on a 513^3 problem
+    with a closed-form discrete solution, and the DG volume terms."""
     res = {}
     n = 129
     s = mg.Solver(2, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2)
@@ -257,6 +257,16 @@ def other_configs(mg, W, torch, np):
                                 "algebraic_over_discretisation_error": float((u - ch * ue).abs().max()) / abs(ch - 1.0),
                                 "relres": s.residual_norm() / float(torch.linalg.vector_norm(fs[1:-1, 1:-1, 1:-1]))}
     s.close()
+    u = ue = fs = None
+    # volume terms of the quadrature-free DG shallow-water scheme, 2 x 1024^2
+    # jittered split-quad triangles, orders 1-3 (one launch each, HIP events)
+    from paper_1904_08684_amd import dgbench
+    for k in (1, 2, 3):
+        r = dgbench.run(1024, k, 20)
+        res[f"dg_volume_terms_k{k}_2M_elements"] = {
+            "ms": round(r["ms"], 4), "elements": r["elements"], "gflops": round(r["gflops"], 1),
+            "GBps": round(r["GBps"], 1), "frac_fp64_vector_peak": round(r["frac_fp64_vector"], 3),
+            "frac_hbm_peak": round(r["frac_hbm"], 3)}
     return res
 
 

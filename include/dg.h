@@ -1,6 +1,6 @@
 /* Volume terms of the quadrature-free discontinuous Galerkin discretisation
- * of the shallow water equations on triangles (the paper's Sec. 3 on the
- * discretisation, equations mass_basis and momentum_basis_u): for every
+ * of the shallow water equations on triangles (the paper's Sec. 2.2,
+ * equations mass_basis and momentum_basis_u): for every
  * element e and test function p,
  *
  *   E[j][p][e] = (A~(c, u), grad(phi_ep e_j))_{Omega_e},  j = 0, 1, 2,

@@ -1,5 +1,5 @@
 """Element integrals of the quadrature-free DG discretisation of the shallow
-water equations (the paper's Sec. 3 on the discretisation: the volume terms
+water equations (the paper's Sec. 2.2: the volume terms
 (A~(c, u), grad(phi e_j)) over one triangle, equations mass_basis and
 momentum_basis_u), evaluated here by their plain definition: numerical
 quadrature on the physical triangle of the pointwise flux tensor times the
@@ -12,7 +12,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Conventions (readings):
 * Reference triangle {(0,0), (1,0), (0,1)}; F_e(x^) = B_e x^ + a_e1 with
-  B_e = [a_e2 - a_e1, a_e3 - a_e1] (columns), det B_e > 0.
+  B_e = [a_e2 - a_e1, a_e3 - a_e1] (columns), det B_e != 0 (either
+  orientation; the physical integrals are taken as they are).
 * The element basis is phi_ei = |det B_e|^(-1/2) phi^_i o F_e^-1, orthonormal
   on the element: the factors 1/|det B_e| and 1/|det B_e|^(3/2) of the
   paper's algebraic forms imply this scaling.
@@ -50,7 +51,7 @@ def basis(x, y):
     ]
 
 
-def basis_grad(x, y, h=None):
+def basis_grad(x, y):
     """Reference gradients (d/dx^1, d/dx^2) of the ten polynomials, written
     out by differentiating each term."""
     s = math.sqrt

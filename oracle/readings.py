@@ -41,4 +41,11 @@ READINGS = {
     "R17": "Neumann walls (cell grids): f is projected to zero mean at the start and after every "
            "restriction, the finest iterate after every cycle; the coarsest solve returns the "
            "zero-mean (minimum-norm) solution.",
+    "R18": "DG volume terms: the element basis is |det B_e|^(-1/2) phi^_i o F_e^-1 (orthonormal on the "
+           "element); the paper's algebraic forms carry 1/|det B_e| and 1/|det B_e|^(3/2), which this "
+           "scaling produces, while its definition line omits the factor.",
+    "R19": "The y-momentum volume term (the paper's 'similar expression') uses the third flux row "
+           "(V u, V v + g xi (H + h_b)/2): V in place of U and d/dx2 for the pressure terms.",
+    "R20": "The bathymetry h_b is constant on each element (the algebraic form takes it outside the "
+           "integral); det B_e keeps its sign (|det B_e| for counter-clockwise elements).",
 }
