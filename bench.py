@@ -363,7 +363,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": (traf["hbm_bytes_per_launch"] if traf else None),
-                "kernel": "finest-level fused pass of three red-black GS sweeps (k_node_gs_tb<double, 6, 3, 12, 6, true>)",
+                "kernel": "finest-level fused pass of three red-black GS sweeps (k_node_gs_tb<double, 6, 3, 12, 6, true, true>)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": c0,
                 "timing": "HIP events, profiled repetition of the timed solves",
                 "algorithmic_bytes_per_launch": bytes_per_launch,
