@@ -180,7 +180,7 @@ int dg_reference_integrals(int k, double* ref) {
 int dg_volume_integrals(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
                         double g, const double* ref, double* out, void* stream) {
     const int K = k_of(k);
-    if (!K || ne < 0) return MG_EINVAL;
+    if (!K || ne < 0 || ne > 256LL * 0x7fffffffLL) return MG_EINVAL;
     if (ne == 0) return MG_OK;
     if (!c || !u || !B || !hb || !ref || !out) return MG_EINVAL;
     const hipStream_t st = static_cast<hipStream_t>(stream);

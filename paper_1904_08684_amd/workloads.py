@@ -142,11 +142,13 @@ SEED_DG_MESH = 20
 SEED_DG_FIELDS = 21
 
 
-def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.25) -> np.ndarray:
+def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2) -> np.ndarray:
     """Affine maps of a split-quad triangulation of the unit square: nx x ny
     squares, each cut along one diagonal into two counter-clockwise
-    triangles, interior vertices moved by up to `jitter` of a cell width so
-    that every element has its own map.  Returns B (4, 2 nx ny) with rows
+    triangles, interior vertices moved by up to `jitter` of a cell width (the
+    randomly perturbed regular mesh of the paper's convergence test moves
+    them by up to 20 % of the edge length), so that every element has its
+    own map.  Returns B (4, 2 nx ny) with rows
     B11, B12, B21, B22 of B_e = [a_e2 - a_e1, a_e3 - a_e1]."""
     rng = np.random.default_rng(seed)
     xs = np.linspace(0.0, 1.0, nx + 1)
