@@ -270,6 +270,37 @@ def test_full_size_513_properties(mg, precision):
     s.close()
 
 
+def test_full_size_varcoef_256_properties(mg):
+    """The 256^3-cell variable-coefficient configuration at full size, FP64
+    and mixed, RB-GS V(3,3) to 1e-10: each residual recomputed on the CPU with
+    the oracle's operator meets the tolerance, the convergence factor stays
+    below 0.12, and the two solutions agree to within kappa * tol."""
+    N = 256
+    k = W.varcoef_k(N, 3)
+    f = W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)
+    beta = cell.harmonic_faces(k)
+    sols = {}
+    for prec in (mg.MG_FP64, mg.MG_MIXED):
+        s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, precision=prec)
+        s.set_rhs(f)
+        s.set_initial(None)
+        code, cyc, rel = s.solve(1e-10)
+        u = s.solution()
+        hist = s.history()
+        s.close()
+        rel_cpu = float(np.linalg.norm(cell.residual(u, f, beta)) / np.linalg.norm(f))
+        rates = [hist[i + 1] / hist[i] for i in range(1, len(hist) - 1)]
+        print(f"256^3 cells prec={prec}: {cyc} steps, relres {rel:.3e}, CPU recomputed {rel_cpu:.3e}, "
+              f"worst factor {max(rates) if rates else 0:.3f}", flush=True)
+        assert code == mg.MG_OK and rel <= 1e-10 and rel_cpu <= 1.05e-10
+        if prec == mg.MG_FP64:
+            assert max(rates) < 0.12
+        sols[prec] = u
+    d = rel_max(sols[mg.MG_MIXED], sols[mg.MG_FP64])
+    print(f"  mixed vs FP64 solution: {d:.2e}", flush=True)
+    assert d <= 1e-6
+
+
 @pytest.mark.parametrize("dim,n,sm,nu1,nu2,precision", [
     (3, 65, "rbgs", 3, 3, "fp64"),
     (3, 65, "rbgs", 3, 3, "mixed"),
