@@ -123,3 +123,20 @@ def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: fl
     for j in range(3):
         E[j] = (dx1 * (w * A[j][0])).sum(axis=1) + (dx2 * (w * A[j][1])).sum(axis=1)
     return E
+
+
+def velocity_projection(k: int, c: np.ndarray, B: np.ndarray, hb: float) -> np.ndarray:
+    """The velocity u = (u, v) of one element from (u H, psi) = (q, psi) for
+    every test function psi of the element (the paper's variational_disc_2),
+    H = xi + h_b, q = (U, V): assemble the H-weighted mass matrix and the
+    right-hand sides by quadrature on the physical element and solve.
+    Returns the coefficients (2, K)."""
+    K = K_OF[k]
+    X, Y, Wt = triangle_rule()
+    det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
+    ph = abs(det) ** -0.5 * np.array(basis(X, Y))[:K]
+    w = Wt * abs(det)
+    H = c[0] @ ph + hb
+    M = (ph * (w * H)) @ ph.T
+    rhs = np.stack([(ph * (w * (c[j] @ ph))).sum(axis=1) for j in (1, 2)], axis=1)
+    return np.linalg.solve(M, rhs).T

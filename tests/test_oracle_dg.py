@@ -86,3 +86,39 @@ def test_constant_fields_reduce_to_boundary_integrals(k):
         want = edge_integrals(k, B, a1, Ac)
         assert np.max(np.abs(E - want)) <= 1e-12 * (1 + np.max(np.abs(want)))
         assert np.max(np.abs(E[:, 0])) <= 1e-13 * (1 + np.max(np.abs(E)))   # constant test function
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_projection_of_constant_depth_divides(k):
+    """With xi = 0 the depth is the constant h_b, the weighted mass matrix is
+    h_b times the identity (orthonormal basis) and u = q / h_b."""
+    rng = np.random.default_rng(20 + k)
+    K = dg.K_OF[k]
+    B = np.array([[0.7, 0.2], [-0.1, 0.8]])
+    c = np.zeros((3, K))
+    c[1:] = rng.normal(size=(2, K))
+    u = dg.velocity_projection(k, c, B, 2.5)
+    assert np.max(np.abs(u - c[1:] / 2.5)) <= 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_projection_recovers_a_constant_velocity(k):
+    """q = H u0 with a linear depth H and a constant velocity u0 lies in P^k,
+    so the projection returns exactly u0 (only the constant mode)."""
+    rng = np.random.default_rng(30 + k)
+    K = dg.K_OF[k]
+    B = np.array([[0.9, 0.3], [0.2, 1.1]])
+    det = np.linalg.det(B)
+    hb = 3.0
+    c = np.zeros((3, K))
+    c[0, :3] = rng.normal(0.0, 0.2, 3)                  # linear surface elevation
+    u0 = np.array([0.7, -0.4])
+    unit = math.sqrt(abs(det)) / math.sqrt(2.0)         # coefficient of the constant 1
+    H = c[0].copy()
+    H[0] += hb * unit
+    c[1] = u0[0] * H                                    # U = u0 H, V = v0 H: in P^1
+    c[2] = u0[1] * H
+    u = dg.velocity_projection(k, c, B, hb)
+    want = np.zeros((2, K))
+    want[:, 0] = u0 * unit
+    assert np.max(np.abs(u - want)) <= 1e-12
