@@ -114,7 +114,7 @@ def other_configs(mg, W, torch, np):
     solves of the 513^3 Poisson problem, damped-Jacobi cycles with
     rediscretised and Galerkin coarse operators, CG with the V-cycle as
     preconditioner, full multigrid on a 513^3 problem with a closed-form
-    discrete solution, and the DG volume terms."""
+    discrete solution, and the DG volume terms and velocity projection."""
     res = {}
 
     def solve_entry(s, rhs, tol=1e-10):
@@ -215,12 +215,13 @@ def other_configs(mg, W, torch, np):
     # volume terms of the quadrature-free DG shallow-water scheme, 2 x 1024^2
     # perturbed split-quad triangles, orders 1-3 (one launch each, HIP events)
     from paper_1904_08684_amd import dgbench
-    for kk in (1, 2, 3):
-        r = dgbench.run(1024, kk, 20)
-        res[f"dg_volume_terms_k{kk}_2M_elements"] = {
-            "ms": round(r["ms"], 4), "elements": r["elements"], "gflops": round(r["gflops"], 1),
-            "GBps": round(r["GBps"], 1), "frac_fp64_vector_peak": round(r["frac_fp64_vector"], 3),
-            "frac_hbm_peak": round(r["frac_hbm"], 3)}
+    for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection")):
+        for kk in (1, 2, 3):
+            r = dgbench.run(1024, kk, 20, op)
+            res[f"{name}_k{kk}_2M_elements"] = {
+                "ms": round(r["ms"], 4), "elements": r["elements"], "gflops": round(r["gflops"], 1),
+                "GBps": round(r["GBps"], 1), "frac_fp64_vector_peak": round(r["frac_fp64_vector"], 3),
+                "frac_hbm_peak": round(r["frac_hbm"], 3)}
     return res
 
 

@@ -54,6 +54,26 @@ int dg_reference_integrals(int k, double* ref);
 int dg_volume_integrals(int k, long long ne, const double* c, const double* u, const double* B,
                         const double* hb, double g, const double* ref, double* out, void* stream);
 
+/* Doubles in the product table of order k: K^3, or 0 for k outside 0..3. */
+long long dg_product_size(int k);
+
+/* Host: T[p][i][m] = int phi^_p phi^_i phi^_m over the reference triangle,
+ * row-major, exact like dg_reference_integrals.  MG_EINVAL for a bad k or
+ * NULL T. */
+int dg_product_integrals(int k, double* T);
+
+/* Device: the velocity of every element from the paper's second discrete
+ * equation (variational_disc_2), (u H, psi) = (q, psi) for all psi in P^k
+ * of the element, H = xi + h_b, q = (U, V): per element the H-weighted mass
+ * matrix M[p][m] = |det B_e|^(-1/2) sum_i H_i T[p][i][m] (the constant h_b
+ * enters the coefficient of phi_e1), a Cholesky factorisation and two
+ * solves.  Arrays as for dg_volume_integrals: c (3K x ne), B (4 x ne),
+ * hb (ne), T the table of dg_product_integrals on the device, u (2K x ne)
+ * the result.  MG_EINVAL / MG_EDEVICE as dg_volume_integrals; a depth that
+ * is not positive on the element leaves non-finite values there. */
+int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
+                           const double* T, double* u, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

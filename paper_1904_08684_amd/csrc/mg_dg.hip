@@ -146,6 +146,73 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
     }
 }
 
+// Velocity projection: one thread per element assembles the lower triangle
+// of the H-weighted mass matrix, factors it (Cholesky, in registers) and
+// solves for both velocity components.
+template <int K>
+__global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* __restrict__ c,
+                                                    const double* __restrict__ B, const double* __restrict__ hb,
+                                                    const double* __restrict__ T, double* __restrict__ u) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
+    const double ad = std::fabs(b11 * b22 - b12 * b21);
+    const double sd = 1.0 / std::sqrt(ad);
+    constexpr int NL = K * (K + 1) / 2;
+    double L[NL];                                           // row-major lower triangle
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] = 0.0;
+    // one coefficient of H at a time (a rolled loop keeps the table's scalar
+    // operands of one step live, not all K^3 of them)
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+        double h = c[(long long)i * ne + e];
+        if (i == 0) h += hb[e] * std::sqrt(ad) * 0.70710678118654752440;   // h_b = (h_b sqrt|det| / sqrt 2) phi_e1
+        const double* Ti = T + i * K;
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+#pragma unroll
+            for (int m = 0; m <= p; ++m) L[p * (p + 1) / 2 + m] += h * Ti[p * K * K + m];
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] *= sd;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double d = L[j * (j + 1) / 2 + j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) d -= L[j * (j + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+        const double ljj = std::sqrt(d);
+        L[j * (j + 1) / 2 + j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            double v = L[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) v -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+            L[i * (i + 1) / 2 + j] = v / ljj;
+        }
+    }
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        double y[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            double v = c[(long long)((1 + comp) * K + i) * ne + e];
+#pragma unroll
+            for (int q = 0; q < i; ++q) v -= L[i * (i + 1) / 2 + q] * y[q];
+            y[i] = v / L[i * (i + 1) / 2 + i];
+        }
+#pragma unroll
+        for (int i = K - 1; i >= 0; --i) {
+            double v = y[i];
+#pragma unroll
+            for (int q = i + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + i] * y[q];
+            y[i] = v / L[i * (i + 1) / 2 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) u[(long long)(comp * K + i) * ne + e] = y[i];
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -175,6 +242,42 @@ int dg_reference_integrals(int k, double* ref) {
                         integrate(mul(dp_i, phi[m]), sc[p] * sc[i] * sc[m]);
             }
     return MG_OK;
+}
+
+long long dg_product_size(int k) {
+    const long long K = k_of(k);
+    return K * K * K;
+}
+
+int dg_product_integrals(int k, double* T) {
+    const int K = k_of(k);
+    if (!K || !T) return MG_EINVAL;
+    Poly phi[kMaxK];
+    for (int p = 0; p < K; ++p) phi[p] = basis_poly(p);
+    for (int p = 0; p < K; ++p)
+        for (int i = 0; i < K; ++i) {
+            const Poly pi = mul(phi[p], phi[i]);
+            for (int m = 0; m < K; ++m)
+                T[(p * K + i) * K + m] = integrate(mul(pi, phi[m]), kScale[p] * kScale[i] * kScale[m]);
+        }
+    return MG_OK;
+}
+
+int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
+                           const double* T, double* u, void* stream) {
+    const int K = k_of(k);
+    if (!K || ne < 0 || ne > 256LL * 0x7fffffffLL) return MG_EINVAL;
+    if (ne == 0) return MG_OK;
+    if (!c || !B || !hb || !T || !u) return MG_EINVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const unsigned nb = (unsigned)((ne + 255) / 256);
+    switch (K) {
+        case 1: k_dg_project<1><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+        case 3: k_dg_project<3><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+        case 6: k_dg_project<6><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+        default: k_dg_project<10><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+    }
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_EDEVICE;
 }
 
 int dg_volume_integrals(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,

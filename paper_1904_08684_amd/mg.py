@@ -432,6 +432,9 @@ _dsigs = {
     "dg_reference_size": (C.c_longlong, [C.c_int]),
     "dg_reference_integrals": (C.c_int, [C.c_int, _D]),
     "dg_volume_integrals": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, C.c_double, _P, _P, _P]),
+    "dg_product_size": (C.c_longlong, [C.c_int]),
+    "dg_product_integrals": (C.c_int, [C.c_int, _D]),
+    "dg_velocity_projection": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _dsigs.items():
     _fn = getattr(lib, _name)
@@ -450,6 +453,41 @@ def dg_reference(k: int) -> np.ndarray:
     return ref[:2 * K * K].reshape(2, K, K), ref[2 * K * K:].reshape(2, K, K, K)
 
 
+def dg_products(k: int) -> np.ndarray:
+    """The exact triple-product integrals of order k (host): T (K, K, K)."""
+    K = DG_K[k]
+    T = np.empty(int(dg_product_size(k)), dtype=np.float64)
+    _check(dg_product_integrals(k, T.ctypes.data_as(_D)))
+    return T.reshape(K, K, K)
+
+
+def _dg_check(tensors, ne):
+    import torch
+    for t, rows in tensors:
+        shape = (rows, ne) if rows else (ne,)
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError("expected contiguous FP64 device tensors of shape (rows, ne) / (ne,)")
+
+
+class DGProjection:
+    """Velocity projection of order k on the GPU; the product table lives on the device."""
+
+    def __init__(self, k: int, device: str = "cuda"):
+        import torch
+        self.k, self.K = k, DG_K[k]
+        self.T = torch.from_numpy(dg_products(k).ravel().copy()).to(device)
+
+    def __call__(self, c, B, hb, u, stream=None):
+        """c (3K, ne), B (4, ne), hb (ne,) in; u (2K, ne) out."""
+        import torch
+        ne = hb.shape[0]
+        _dg_check(((c, 3 * self.K), (B, 4), (hb, 0), (u, 2 * self.K)), ne)
+        st = stream if stream is not None else torch.cuda.current_stream(hb.device)
+        _check(dg_velocity_projection(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(B.data_ptr()),
+                                      C.c_void_p(hb.data_ptr()), C.c_void_p(self.T.data_ptr()),
+                                      C.c_void_p(u.data_ptr()), C.c_void_p(st.cuda_stream)))
+
+
 class DGVolume:
     """Volume terms of order k on the GPU; the reference table lives on the device."""
 
@@ -464,11 +502,7 @@ class DGVolume:
         FP64 device tensors, element index fastest."""
         import torch
         ne = hb.shape[0]
-        for t, rows in ((c, 3 * self.K), (u, 2 * self.K), (B, 4), (out, 3 * self.K)):
-            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (rows, ne):
-                raise ValueError("expected contiguous FP64 device tensors of shape (rows, ne)")
-        if hb.dtype != torch.float64 or not hb.is_cuda or not hb.is_contiguous():
-            raise ValueError("hb must be a contiguous FP64 device tensor")
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, 0), (out, 3 * self.K)), ne)
         st = stream if stream is not None else torch.cuda.current_stream(hb.device)
         _check(dg_volume_integrals(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(u.data_ptr()),
                                    C.c_void_p(B.data_ptr()), C.c_void_p(hb.data_ptr()), g,

@@ -169,14 +169,20 @@ def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2) -> 
     return np.ascontiguousarray(np.stack([e2[:, 0], e3[:, 0], e2[:, 1], e3[:, 1]]))
 
 
-def dg_fields(K: int, ne: int, seed: int = SEED_DG_FIELDS):
+def dg_fields(K: int, B: np.ndarray, seed: int = SEED_DG_FIELDS):
     """Coefficients of (xi, U, V) and (u, v), (3K, ne) and (2K, ne), and a
-    per-element bathymetry in [1, 5]: N(0, 1) for the constant mode, N(0,
-    0.1) for the others."""
+    per-element bathymetry h_b in [1, 5], for the elements with maps B
+    (4, ne).  Physical values: xi ~ N(0, 0.1) (so that the depth xi + h_b
+    stays positive), U, V, u, v ~ N(0, 1) for the element mean, a tenth of
+    that for each higher mode; a coefficient is the physical amplitude times
+    sqrt(|det B_e| / 2), the factor of the orthonormal element basis."""
     rng = np.random.default_rng(seed)
+    ne = B.shape[1]
+    unit = np.sqrt(np.abs(B[0] * B[3] - B[1] * B[2]) / 2.0)
     scale = np.full((K, 1), 0.1)
     scale[0] = 1.0
-    c = rng.normal(0.0, 1.0, (3, K, ne)) * scale
-    u = rng.normal(0.0, 1.0, (2, K, ne)) * scale
+    amp = np.array([0.1, 1.0, 1.0])[:, None, None]
+    c = rng.normal(0.0, 1.0, (3, K, ne)) * scale * amp * unit
+    u = rng.normal(0.0, 1.0, (2, K, ne)) * scale * unit
     hb = rng.uniform(1.0, 5.0, ne)
     return np.ascontiguousarray(c.reshape(3 * K, ne)), np.ascontiguousarray(u.reshape(2 * K, ne)), hb

@@ -33,7 +33,8 @@ def test_header_declares_the_boundary():
     for want in ("mg_setup", "mg_vcycle", "mg_solve", "mg_workspace_bytes", "mg_destroy",
                  "mg_set_rhs", "mg_get_solution", "mg_strerror", "mg_last_error"):
         assert want in names
-    for want in ("dg_reference_size", "dg_reference_integrals", "dg_volume_integrals"):
+    for want in ("dg_reference_size", "dg_reference_integrals", "dg_volume_integrals", "dg_product_size",
+                 "dg_product_integrals", "dg_velocity_projection"):
         assert want in names
 
 

@@ -34,3 +34,15 @@ def test_reference_sizes_and_bad_orders(mg):
     assert mg.dg_volume_integrals(5, 10, None, None, None, None, 9.81, None, None, None) == mg.MG_EINVAL
     assert mg.dg_volume_integrals(3, -1, None, None, None, None, 9.81, None, None, None) == mg.MG_EINVAL
     assert mg.dg_volume_integrals(3, 0, None, None, None, None, 9.81, None, None, None) == mg.MG_OK
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_product_integrals_match_quadrature(mg, k):
+    T = mg.dg_products(k)
+    K = dg.K_OF[k]
+    X, Y, Wt = dg.triangle_rule()
+    phi = np.array(dg.basis(X, Y))[:K]
+    Tq = np.einsum("pq,iq,mq->pim", phi * Wt, phi, phi)
+    assert np.max(np.abs(T - Tq)) <= 1e-12
+    assert mg.dg_product_size(k) == K ** 3
+    assert mg.dg_velocity_projection(k, -1, None, None, None, None, None, None) == mg.MG_EINVAL

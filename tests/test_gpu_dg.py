@@ -19,7 +19,7 @@ def run(mg, k, nx, ny):
     K = dg.K_OF[k]
     B = W.dg_mesh(nx, ny)
     ne = B.shape[1]
-    c, u, hb = W.dg_fields(K, ne)
+    c, u, hb = W.dg_fields(K, B)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     out = torch.full((3 * K, ne), float("nan"), dtype=torch.float64, device="cuda")
     mg.DGVolume(k)(dev(c), dev(u), dev(B), dev(hb), G_GRAV, out)
@@ -57,3 +57,33 @@ def test_full_size_sampled(mg):
     worst = check(k, B, c, u, hb, out, elems)
     print(f"DG k=3 {ne} elements: {len(elems)} sampled, worst relative difference {worst:.2e}", flush=True)
     assert np.all(np.isfinite(out)) and worst <= TOL
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_velocity_projection(mg, k):
+    """The per-element solve of (u H, psi) = (q, psi) against the oracle's
+    quadrature-assembled system, every element of a small mesh and sampled
+    elements of a 2M-element mesh (ragged last block)."""
+    import torch
+    K = dg.K_OF[k]
+    for nx, sample in ((8, None), (1000, 300)):
+        B = W.dg_mesh(nx, nx)
+        ne = B.shape[1]
+        c, _, hb = W.dg_fields(K, B)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        u = torch.full((2 * K, ne), float("nan"), dtype=torch.float64, device="cuda")
+        mg.DGProjection(k)(dev(c), dev(B), dev(hb), u)
+        torch.cuda.synchronize()
+        got = u.cpu().numpy()
+        if sample is None:
+            elems = range(ne)
+        else:
+            rng = np.random.default_rng(6)
+            elems = np.concatenate([rng.integers(0, ne, sample), np.arange(ne - 64, ne)])
+        worst = 0.0
+        for e in elems:
+            Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
+            ref = dg.velocity_projection(k, c[:, e].reshape(3, K), Be, hb[e])
+            worst = max(worst, float(np.max(np.abs(got[:, e].reshape(2, K) - ref)) / np.max(np.abs(ref))))
+        print(f"DG projection k={k} {ne} elements: worst relative difference {worst:.2e}", flush=True)
+        assert np.all(np.isfinite(got)) and worst <= TOL
