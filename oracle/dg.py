@@ -140,3 +140,74 @@ def velocity_projection(k: int, c: np.ndarray, B: np.ndarray, hb: float) -> np.n
     M = (ph * (w * H)) @ ph.T
     rhs = np.stack([(ph * (w * (c[j] @ ph))).sum(axis=1) for j in (1, 2)], axis=1)
     return np.linalg.solve(M, rhs).T
+
+
+# ------------------------------------------------------------ edge terms
+# Local edges of the reference triangle, counter-clockwise: q0 (0,0)->(1,0),
+# q1 (1,0)->(0,1), q2 (0,1)->(0,0).
+REF_VERTS = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+
+
+def element_vertices(B: np.ndarray, a1: np.ndarray):
+    return [a1, a1 + B[:, 0], a1 + B[:, 1]]
+
+
+def eval_fields(k: int, coef: np.ndarray, B: np.ndarray, a1: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """Values at physical points pts (P, 2) of the fields with coefficients
+    coef (nf, K) on the element (B, a1)."""
+    K = K_OF[k]
+    det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
+    ref = np.linalg.solve(B, (pts - a1).T)
+    ph = abs(det) ** -0.5 * np.array(basis(ref[0], ref[1]))[:K]
+    return coef @ ph
+
+
+def mean_state(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: float):
+    """Element means of the velocity and of the depth: the constant mode's
+    coefficient times the value of phi_e1, sqrt(2 / |det B_e|)."""
+    det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
+    v1 = math.sqrt(2.0 / abs(det))
+    return u[:, 0] * v1, c[0, 0] * v1 + hb
+
+
+def flux_tensor(xi, U, V, uu, vv, hb, g):
+    pres = 0.5 * g * xi * ((xi + hb) + hb)
+    return [(U, V), (U * uu + pres, U * vv), (V * uu, V * vv + pres)]
+
+
+def edge_integrals_lf(k, own, nbrs, g):
+    """Interior-edge terms of one element: for every local edge q with a
+    neighbour, int_E F_j phi_ep ds with the Lax-Friedrichs flux
+    F = (A(c-, u-) n + A(c+, u+) n) / 2 + lambda_E (c- - c+) / 2, lambda_E
+    = max over both sides of |u_mean . n| + sqrt(g H_mean) (constant on the
+    edge), n the unit outward normal.  own = (c, u, B, a1, hb); nbrs[q] =
+    the neighbour's (c, u, B, a1, hb) or None on the boundary.  Gauss rule
+    on the physical edge.  Returns (3, K)."""
+    K = K_OF[k]
+    c, u, B, a1, hb = own
+    V = element_vertices(B, a1)
+    t, w = np.polynomial.legendre.leggauss(8)
+    s = (t + 1.0) / 2.0
+    out = np.zeros((3, K))
+    for q in range(3):
+        if nbrs[q] is None:
+            continue
+        cn, un, Bn, a1n, hbn = nbrs[q]
+        p0, p1 = V[q], V[(q + 1) % 3]
+        d = p1 - p0
+        L = math.hypot(d[0], d[1])
+        n = np.array([d[1], -d[0]]) / L
+        pts = p0[None, :] + s[:, None] * d[None, :]
+        fm = eval_fields(k, np.vstack([c, u]), B, a1, pts)
+        fp = eval_fields(k, np.vstack([cn, un]), Bn, a1n, pts)
+        um, Hm = mean_state(k, c, u, B, hb)
+        up, Hp = mean_state(k, cn, un, Bn, hbn)
+        lam = max(abs(um @ n) + math.sqrt(g * Hm), abs(up @ n) + math.sqrt(g * Hp))
+        Am = flux_tensor(fm[0], fm[1], fm[2], fm[3], fm[4], hb, g)
+        Ap = flux_tensor(fp[0], fp[1], fp[2], fp[3], fp[4], hbn, g)
+        ph = eval_fields(k, np.eye(K), B, a1, pts)          # the element's basis at the points
+        for j in range(3):
+            F = 0.5 * ((Am[j][0] * n[0] + Am[j][1] * n[1]) + (Ap[j][0] * n[0] + Ap[j][1] * n[1])) \
+                + 0.5 * lam * (fm[j] - fp[j])
+            out[j] += (ph * (F * w / 2.0 * L)).sum(axis=1)
+    return out

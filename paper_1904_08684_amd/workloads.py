@@ -142,14 +142,16 @@ SEED_DG_MESH = 20
 SEED_DG_FIELDS = 21
 
 
-def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2) -> np.ndarray:
+def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, with_origin: bool = False):
     """Affine maps of a split-quad triangulation of the unit square: nx x ny
     squares, each cut along one diagonal into two counter-clockwise
     triangles, interior vertices moved by up to `jitter` of a cell width (the
     randomly perturbed regular mesh of the paper's convergence test moves
     them by up to 20 % of the edge length), so that every element has its
-    own map.  Returns B (4, 2 nx ny) with rows
-    B11, B12, B21, B22 of B_e = [a_e2 - a_e1, a_e3 - a_e1]."""
+    own map.  Returns B (4, 2 nx ny) with rows B11, B12, B21, B22 of
+    B_e = [a_e2 - a_e1, a_e3 - a_e1] (and a_e1 (2, 2 nx ny) with_origin).
+    Elements: the lower-right triangles (p00, p10, p11) of squares (i, j) at
+    i ny + j, then the upper-left ones (p00, p11, p01)."""
     rng = np.random.default_rng(seed)
     xs = np.linspace(0.0, 1.0, nx + 1)
     ys = np.linspace(0.0, 1.0, ny + 1)
@@ -166,7 +168,43 @@ def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2) -> 
     a2 = np.concatenate([p10, p11])
     a3 = np.concatenate([p11, p01])
     e2, e3 = a2 - a1, a3 - a1
-    return np.ascontiguousarray(np.stack([e2[:, 0], e3[:, 0], e2[:, 1], e3[:, 1]]))
+    B = np.ascontiguousarray(np.stack([e2[:, 0], e3[:, 0], e2[:, 1], e3[:, 1]]))
+    return (B, np.ascontiguousarray(a1.T)) if with_origin else B
+
+
+def dg_mesh_neighbours(nx: int, ny: int):
+    """Edge neighbours of the elements of dg_mesh(nx, ny): nbr[q][e] is the
+    element across local edge q of e (q0: a1->a2, q1: a2->a3, q2: a3->a1),
+    -1 on the domain boundary, and nq[q][e] that element's local index of the
+    shared edge (int32 arrays (3, 2 nx ny))."""
+    half = nx * ny
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    lr = i * ny + j                     # lower-right of square (i, j)
+    ul = half + lr                      # upper-left of square (i, j)
+    nbr = np.full((3, 2 * half), -1, dtype=np.int32)
+    nq = np.full((3, 2 * half), -1, dtype=np.int32)
+    # lower-right: q0 bottom -> upper-left of (i, j-1) edge q1; q1 right ->
+    # upper-left of (i+1, j) edge q2; q2 diagonal -> upper-left of (i, j) edge q0
+    m = j > 0
+    nbr[0, lr[m]] = half + i[m] * ny + (j[m] - 1)
+    nq[0, lr[m]] = 1
+    m = i < nx - 1
+    nbr[1, lr[m]] = half + (i[m] + 1) * ny + j[m]
+    nq[1, lr[m]] = 2
+    nbr[2, lr] = ul
+    nq[2, lr] = 0
+    # upper-left: q0 diagonal -> lower-right of (i, j) edge q2; q1 top ->
+    # lower-right of (i, j+1) edge q0; q2 left -> lower-right of (i-1, j) edge q1
+    nbr[0, ul] = lr
+    nq[0, ul] = 2
+    m = j < ny - 1
+    nbr[1, ul[m]] = i[m] * ny + (j[m] + 1)
+    nq[1, ul[m]] = 0
+    m = i > 0
+    nbr[2, ul[m]] = (i[m] - 1) * ny + j[m]
+    nq[2, ul[m]] = 1
+    return nbr, nq
 
 
 def dg_fields(K: int, B: np.ndarray, seed: int = SEED_DG_FIELDS):

@@ -122,3 +122,98 @@ def test_projection_recovers_a_constant_velocity(k):
     want = np.zeros((2, K))
     want[:, 0] = u0 * unit
     assert np.max(np.abs(u - want)) <= 1e-12
+
+
+def _mesh_element(B, a1, e):
+    return np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]]), a1[:, e]
+
+
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_edge_terms_of_a_constant_state_equal_the_volume_terms(k):
+    """A constant state on every element has no jumps, so the flux is A n on
+    every edge; for an element whose three edges are interior the edge terms
+    are the boundary integral that the divergence theorem equates with the
+    volume terms."""
+    from paper_1904_08684_amd import workloads as W
+    K = dg.K_OF[k]
+    g = 9.81
+    B, a1 = W.dg_mesh(3, 3, with_origin=True)
+    nbr, _ = W.dg_mesh_neighbours(3, 3)
+    xi, U, V, u0, v0, hb = 0.05, 0.8, -0.3, 0.4, 0.2, 2.0
+    def state(e):
+        Be, a = _mesh_element(B, a1, e)
+        unit = math.sqrt(abs(np.linalg.det(Be)) / 2.0)
+        c = np.zeros((3, K))
+        u = np.zeros((2, K))
+        c[:, 0] = np.array([xi, U, V]) * unit
+        u[:, 0] = np.array([u0, v0]) * unit
+        return c, u, Be, a, hb
+    e = int(np.flatnonzero((nbr >= 0).all(axis=0))[0])
+    own = state(e)
+    S = dg.edge_integrals_lf(k, own, [state(int(nbr[q, e])) for q in range(3)], g)
+    E = dg.volume_integrals(k, own[0], own[1], own[2], hb, g)
+    assert np.max(np.abs(S - E)) <= 1e-12 * (1 + np.max(np.abs(E)))
+
+
+@pytest.mark.parametrize("k", [0, 2, 3])
+def test_edge_flux_is_conservative(k):
+    """The Lax-Friedrichs flux is odd under the exchange of the two sides (n
+    -> -n), so on a shared edge the mean-mode terms of the two elements,
+    each scaled back by its phi_e1 value, cancel."""
+    from paper_1904_08684_amd import workloads as W
+    K = dg.K_OF[k]
+    g = 9.81
+    B, a1 = W.dg_mesh(2, 2, with_origin=True)
+    nbr, nq = W.dg_mesh_neighbours(2, 2)
+    c, u, hb = W.dg_fields(K, B, seed=4)
+    def state(e):
+        Be, a = _mesh_element(B, a1, e)
+        return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a, hb[e]
+    for e in range(B.shape[1]):
+        for q in range(3):
+            f = int(nbr[q, e])
+            if f < 0:
+                continue
+            only = [None, None, None]
+            only[q] = state(f)
+            Se = dg.edge_integrals_lf(k, state(e), only, g)
+            only = [None, None, None]
+            only[int(nq[q, e])] = state(e)
+            Sf = dg.edge_integrals_lf(k, state(f), only, g)
+            de = abs(np.linalg.det(state(e)[2]))
+            df = abs(np.linalg.det(state(f)[2]))
+            total = Se[:, 0] * math.sqrt(de / 2.0) + Sf[:, 0] * math.sqrt(df / 2.0)
+            assert np.max(np.abs(total)) <= 1e-13 * (1 + np.max(np.abs(Se[:, 0] * math.sqrt(de / 2.0))))
+
+
+def test_edge_flux_jump_term_closed_form():
+    """With u = v = 0 and xi = 0 the momentum flux across an edge is only
+    the Lax-Friedrichs jump term: lambda_E = sqrt(g max(h_b-, h_b+)), and the
+    mean-mode term of constant momenta is lambda_E (U- - U+) / 2 times the
+    edge length times phi_e1 = sqrt(2 / |det B_e|)."""
+    from paper_1904_08684_amd import workloads as W
+    g = 9.81
+    B, a1 = W.dg_mesh(2, 2, with_origin=True)
+    nbr, _ = W.dg_mesh_neighbours(2, 2)
+    e, q = 0, 2
+    f = int(nbr[q, e])
+    def state(idx, U, V, hb):
+        Be, a = _mesh_element(B, a1, idx)
+        unit = math.sqrt(abs(np.linalg.det(Be)) / 2.0)
+        c = np.zeros((3, 1))
+        c[1, 0], c[2, 0] = U * unit, V * unit
+        return c, np.zeros((2, 1)), Be, a, hb
+    own, other = state(e, 0.7, -0.2, 1.5), state(f, -0.4, 0.9, 3.0)
+    only = [None, None, None]
+    only[q] = other
+    S = dg.edge_integrals_lf(0, own, only, g)
+    V = dg.element_vertices(own[2], own[3])
+    L = float(np.hypot(*(V[(q + 1) % 3] - V[q])))
+    lam = math.sqrt(g * 3.0)
+    phi1 = math.sqrt(2.0 / abs(np.linalg.det(own[2])))
+    assert abs(S[1, 0] - 0.5 * lam * (0.7 - (-0.4)) * L * phi1) <= 1e-13 * abs(S[1, 0])
+    assert abs(S[2, 0] - 0.5 * lam * (-0.2 - 0.9) * L * phi1) <= 1e-13 * abs(S[2, 0])
+    # the mass flux is the mean of (U, V) . n (no jump in xi)
+    d = V[(q + 1) % 3] - V[q]
+    n = np.array([d[1], -d[0]]) / L
+    assert abs(S[0, 0] - 0.5 * ((0.7 - 0.4) * n[0] + (-0.2 + 0.9) * n[1]) * L * phi1) <= 1e-13
