@@ -74,6 +74,37 @@ int dg_product_integrals(int k, double* T);
 int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
                            const double* T, double* u, void* stream);
 
+/* Doubles in the edge table of order k: 12 K^2 + 12 K^3, or 0 for a bad k. */
+long long dg_edge_table_size(int k);
+
+/* Host: the exact edge integrals of order k, with the local edges of the
+ * reference triangle q0 (0,0)->(1,0), q1 (1,0)->(0,1), q2 (0,1)->(0,0)
+ * parametrised by s in [0, 1], and a neighbour's edge q' traversed backwards
+ * (its parameter 1 - s), row-major in this order:
+ *   O2[q][p][i]      = int phi^_p phi^_i            along q
+ *   O3[q][p][i][m]   = int phi^_p phi^_i phi^_m     along q
+ *   N2[q][q'][p][i]  = int phi^_p(q, s) phi^_i(q', 1 - s)
+ *   N3[q][q'][p][i][m] = int phi^_p(q, s) phi^_i(q', 1 - s) phi^_m(q', 1 - s)
+ * MG_EINVAL for a bad k or NULL table. */
+int dg_edge_integrals(int k, double* table);
+
+/* Device: the interior-edge terms of every element,
+ *   S[j][p][e] = sum over the local edges q of e that have a neighbour of
+ *                int_E F_j phi_ep ds,
+ * with the Lax-Friedrichs flux F = (A(c-, u-) n + A(c+, u+) n) / 2
+ * + lambda_E (c- - c+) / 2 (the paper cites Lax-Friedrichs without fixing
+ * the wave speed; here lambda_E = max over both sides of |u_mean . n| +
+ * sqrt(g H_mean), element means, constant on the edge), n the unit outward
+ * normal, the flux tensor and basis of dg_volume_integrals, evaluated
+ * algebraically with the table of dg_edge_integrals (on the device).
+ * nbr[q ne + e] is the element across local edge q (-1: domain boundary,
+ * skipped), nq[q ne + e] its local index of that edge; both int32 device
+ * arrays (an index outside [0, ne) or 0..2 is taken as boundary).  Other arrays as dg_volume_integrals; out (3K x ne).  Elements must
+ * be counter-clockwise (det B_e > 0) and the mesh conforming.  Status codes
+ * as dg_volume_integrals. */
+int dg_edge_terms(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
+                  const int* nbr, const int* nq, double g, const double* table, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -152,12 +152,13 @@ def element_vertices(B: np.ndarray, a1: np.ndarray):
     return [a1, a1 + B[:, 0], a1 + B[:, 1]]
 
 
-def eval_fields(k: int, coef: np.ndarray, B: np.ndarray, a1: np.ndarray, pts: np.ndarray) -> np.ndarray:
-    """Values at physical points pts (P, 2) of the fields with coefficients
-    coef (nf, K) on the element (B, a1)."""
+def eval_fields(k: int, coef: np.ndarray, B: np.ndarray, rel: np.ndarray) -> np.ndarray:
+    """Values of the fields with coefficients coef (nf, K) on the element
+    with map B at the points rel (P, 2), given relative to the element's
+    first vertex (relative coordinates keep small elements accurate)."""
     K = K_OF[k]
     det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
-    ref = np.linalg.solve(B, (pts - a1).T)
+    ref = np.linalg.solve(B, rel.T)
     ph = abs(det) ** -0.5 * np.array(basis(ref[0], ref[1]))[:K]
     return coef @ ph
 
@@ -185,7 +186,7 @@ def edge_integrals_lf(k, own, nbrs, g):
     on the physical edge.  Returns (3, K)."""
     K = K_OF[k]
     c, u, B, a1, hb = own
-    V = element_vertices(B, a1)
+    V = element_vertices(B, np.zeros(2))            # relative to a1
     t, w = np.polynomial.legendre.leggauss(8)
     s = (t + 1.0) / 2.0
     out = np.zeros((3, K))
@@ -198,14 +199,14 @@ def edge_integrals_lf(k, own, nbrs, g):
         L = math.hypot(d[0], d[1])
         n = np.array([d[1], -d[0]]) / L
         pts = p0[None, :] + s[:, None] * d[None, :]
-        fm = eval_fields(k, np.vstack([c, u]), B, a1, pts)
-        fp = eval_fields(k, np.vstack([cn, un]), Bn, a1n, pts)
+        fm = eval_fields(k, np.vstack([c, u]), B, pts)
+        fp = eval_fields(k, np.vstack([cn, un]), Bn, (a1 - a1n)[None, :] + pts)
         um, Hm = mean_state(k, c, u, B, hb)
         up, Hp = mean_state(k, cn, un, Bn, hbn)
         lam = max(abs(um @ n) + math.sqrt(g * Hm), abs(up @ n) + math.sqrt(g * Hp))
         Am = flux_tensor(fm[0], fm[1], fm[2], fm[3], fm[4], hb, g)
         Ap = flux_tensor(fp[0], fp[1], fp[2], fp[3], fp[4], hbn, g)
-        ph = eval_fields(k, np.eye(K), B, a1, pts)          # the element's basis at the points
+        ph = eval_fields(k, np.eye(K), B, pts)              # the element's basis at the points
         for j in range(3):
             F = 0.5 * ((Am[j][0] * n[0] + Am[j][1] * n[1]) + (Ap[j][0] * n[0] + Ap[j][1] * n[1])) \
                 + 0.5 * lam * (fm[j] - fp[j])

@@ -435,6 +435,9 @@ _dsigs = {
     "dg_product_size": (C.c_longlong, [C.c_int]),
     "dg_product_integrals": (C.c_int, [C.c_int, _D]),
     "dg_velocity_projection": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P]),
+    "dg_edge_table_size": (C.c_longlong, [C.c_int]),
+    "dg_edge_integrals": (C.c_int, [C.c_int, _D]),
+    "dg_edge_terms": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, C.c_double, _P, _P, _P]),
 }
 for _name, (_res, _args) in _dsigs.items():
     _fn = getattr(lib, _name)
@@ -486,6 +489,42 @@ class DGProjection:
         _check(dg_velocity_projection(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(B.data_ptr()),
                                       C.c_void_p(hb.data_ptr()), C.c_void_p(self.T.data_ptr()),
                                       C.c_void_p(u.data_ptr()), C.c_void_p(st.cuda_stream)))
+
+
+def dg_edge_table(k: int) -> dict:
+    """The exact edge integrals of order k (host), as arrays O2 (3, K, K),
+    O3 (3, K, K, K), N2 (3, 3, K, K), N3 (3, 3, K, K, K)."""
+    K = DG_K[k]
+    t = np.empty(int(dg_edge_table_size(k)), dtype=np.float64)
+    _check(dg_edge_integrals(k, t.ctypes.data_as(_D)))
+    o = [0, 3 * K * K, 3 * K ** 3, 9 * K * K, 9 * K ** 3]
+    o = np.cumsum(o)
+    return {"raw": t, "O2": t[o[0]:o[1]].reshape(3, K, K), "O3": t[o[1]:o[2]].reshape(3, K, K, K),
+            "N2": t[o[2]:o[3]].reshape(3, 3, K, K), "N3": t[o[3]:o[4]].reshape(3, 3, K, K, K)}
+
+
+class DGEdges:
+    """Interior-edge (Lax-Friedrichs) terms of order k on the GPU."""
+
+    def __init__(self, k: int, device: str = "cuda"):
+        import torch
+        self.k, self.K = k, DG_K[k]
+        self.tab = torch.from_numpy(dg_edge_table(k)["raw"].copy()).to(device)
+
+    def __call__(self, c, u, B, hb, nbr, nq, g: float, out, stream=None):
+        """c (3K, ne), u (2K, ne), B (4, ne), hb (ne,) FP64; nbr, nq (3, ne)
+        int32; out (3K, ne): contiguous device tensors."""
+        import torch
+        ne = hb.shape[0]
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, 0), (out, 3 * self.K)), ne)
+        for t in (nbr, nq):
+            if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (3, ne):
+                raise ValueError("nbr and nq must be contiguous int32 device tensors of shape (3, ne)")
+        st = stream if stream is not None else torch.cuda.current_stream(hb.device)
+        _check(dg_edge_terms(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(u.data_ptr()),
+                             C.c_void_p(B.data_ptr()), C.c_void_p(hb.data_ptr()), C.c_void_p(nbr.data_ptr()),
+                             C.c_void_p(nq.data_ptr()), g, C.c_void_p(self.tab.data_ptr()),
+                             C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
 
 
 class DGVolume:

@@ -34,7 +34,8 @@ def test_header_declares_the_boundary():
                  "mg_set_rhs", "mg_get_solution", "mg_strerror", "mg_last_error"):
         assert want in names
     for want in ("dg_reference_size", "dg_reference_integrals", "dg_volume_integrals", "dg_product_size",
-                 "dg_product_integrals", "dg_velocity_projection"):
+                 "dg_product_integrals", "dg_velocity_projection", "dg_edge_table_size",
+                 "dg_edge_integrals", "dg_edge_terms"):
         assert want in names
 
 

@@ -46,3 +46,29 @@ def test_product_integrals_match_quadrature(mg, k):
     assert np.max(np.abs(T - Tq)) <= 1e-12
     assert mg.dg_product_size(k) == K ** 3
     assert mg.dg_velocity_projection(k, -1, None, None, None, None, None, None) == mg.MG_EINVAL
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_edge_tables_match_quadrature(mg, k):
+    """The exact edge integrals (own edge, and the neighbour's edge traversed
+    backwards) against Gauss quadrature of the oracle's basis."""
+    K = dg.K_OF[k]
+    T = mg.dg_edge_table(k)
+    t, w = np.polynomial.legendre.leggauss(8)
+    s = (t + 1.0) / 2.0
+    w = w / 2.0
+    lin = {0: (0, 1, 0, 0), 1: (1, -1, 0, 1), 2: (0, 0, 1, -1)}
+
+    def at(q, back):
+        x0, xs, y0, ys = lin[q]
+        ss = 1.0 - s if back else s
+        return np.array(dg.basis(x0 + xs * ss, y0 + ys * ss))[:K]
+    for q in range(3):
+        ph = at(q, False)
+        assert np.max(np.abs(T["O2"][q] - (ph * w) @ ph.T)) <= 1e-12
+        assert np.max(np.abs(T["O3"][q] - np.einsum("pq,iq,mq->pim", ph * w, ph, ph))) <= 1e-12
+        for r in range(3):
+            pb = at(r, True)
+            assert np.max(np.abs(T["N2"][q, r] - (ph * w) @ pb.T)) <= 1e-12
+            assert np.max(np.abs(T["N3"][q, r] - np.einsum("pq,iq,mq->pim", ph * w, pb, pb))) <= 1e-12
+    assert mg.dg_edge_table_size(k) == 12 * K * K + 12 * K ** 3

@@ -87,3 +87,42 @@ def test_velocity_projection(mg, k):
             worst = max(worst, float(np.max(np.abs(got[:, e].reshape(2, K) - ref)) / np.max(np.abs(ref))))
         print(f"DG projection k={k} {ne} elements: worst relative difference {worst:.2e}", flush=True)
         assert np.all(np.isfinite(got)) and worst <= TOL
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_edge_terms(mg, k):
+    """Interior-edge Lax-Friedrichs terms against the oracle's edge
+    quadrature: every element of an 8 x 8 split-quad mesh (boundary edges
+    skipped), sampled elements of a 2M-element mesh."""
+    import torch
+    K = dg.K_OF[k]
+    for nx, sample in ((8, None), (1000, 200)):
+        B, a1 = W.dg_mesh(nx, nx, with_origin=True)
+        nbr, nq = W.dg_mesh_neighbours(nx, nx)
+        ne = B.shape[1]
+        c, u, hb = W.dg_fields(K, B)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        out = torch.full((3 * K, ne), float("nan"), dtype=torch.float64, device="cuda")
+        mg.DGEdges(k)(dev(c), dev(u), dev(B), dev(hb), dev(nbr), dev(nq), G_GRAV, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.all(np.isfinite(got))
+
+        def state(e):
+            Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
+            return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a1[:, e], hb[e]
+        if sample is None:
+            elems = range(ne)
+        else:
+            rng = np.random.default_rng(7)
+            elems = np.concatenate([rng.integers(0, ne, sample), np.arange(ne - 32, ne)])
+        worst = 0.0
+        for e in elems:
+            nbrs = [state(int(nbr[q, e])) if nbr[q, e] >= 0 else None for q in range(3)]
+            ref = dg.edge_integrals_lf(k, state(e), nbrs, G_GRAV)
+            got_e = got[:, e].reshape(3, K)
+            # relative to the element's largest term: the three rows differ in
+            # size (the pressure terms g h_b xi dominate the momentum rows)
+            worst = max(worst, float(np.max(np.abs(got_e - ref)) / max(np.max(np.abs(ref)), 1e-300)))
+        print(f"DG edge terms k={k} {ne} elements: worst relative difference {worst:.2e}", flush=True)
+        assert worst <= TOL
