@@ -114,7 +114,8 @@ def other_configs(mg, W, torch, np):
     solves of the 513^3 Poisson problem, damped-Jacobi cycles with
     rediscretised and Galerkin coarse operators, CG with the V-cycle as
     preconditioner, full multigrid on a 513^3 problem with a closed-form
-    discrete solution, and the DG volume terms and velocity projection."""
+    discrete solution, and the DG volume terms, velocity projection and
+    interior-edge terms."""
     res = {}
 
     def solve_entry(s, rhs, tol=1e-10):
@@ -215,7 +216,8 @@ def other_configs(mg, W, torch, np):
     # volume terms of the quadrature-free DG shallow-water scheme, 2 x 1024^2
     # perturbed split-quad triangles, orders 1-3 (one launch each, HIP events)
     from paper_1904_08684_amd import dgbench
-    for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection")):
+    for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection"),
+                     ("edges", "dg_edge_terms")):
         for kk in (1, 2, 3):
             r = dgbench.run(1024, kk, 20, op)
             res[f"{name}_k{kk}_2M_elements"] = {

@@ -1,8 +1,8 @@
 """DG element-kernel benchmark: one launch of the quadrature-free volume
-terms, or of the velocity projection, over a perturbed split-quad mesh,
-timed with HIP events.
+terms, of the velocity projection or of the interior-edge terms over a
+perturbed split-quad mesh, timed with HIP events.
 
-    python -m paper_1904_08684_amd.dgbench --nx 1024 --k 3 --reps 20 [--op projection]
+    python -m paper_1904_08684_amd.dgbench --nx 1024 --k 3 --reps 20 [--op projection|edges]
 
 Prints one JSON line.  Bytes count the compulsory traffic.  Volume terms:
 five fields, the map and the bathymetry in, three fields out, (5K + 5 + 3K)
@@ -10,7 +10,12 @@ x 8 B per element; flops of the evaluated form, 8 K^3 + 30 K^2 + 15 K per
 element (four multiply-adds per (p, i, m), the two-function terms and the
 set-up).  Projection: three fields, the map and the bathymetry in, two out,
 (3K + 5 + 2K) x 8 B; flops K^2 (K + 1) for the weighted mass matrix,
-K^3 / 3 for its factorisation and 4 K^2 for the two solves.
+K^3 / 3 for its factorisation and 4 K^2 for the two solves.  Edge terms:
+the element's and its three neighbours' fields, maps and bathymetry, the
+neighbour indices in, three fields out ((5K + 5) x 8 + 24 + 3K x 8 B
+compulsory per element, neighbours' data counted once as it is every
+element's own); flops 3 x (8 K^3 + 26 K^2) per element (three edges, four
+multiply-adds per (p, i, m) on each side).
 """
 from __future__ import annotations
 
@@ -34,6 +39,14 @@ def projection_bytes(K: int) -> int:
     return (3 * K + 5 + 2 * K) * 8
 
 
+def edge_flops(K: int) -> int:
+    return 3 * (8 * K ** 3 + 26 * K * K)
+
+
+def edge_bytes(K: int) -> int:
+    return (5 * K + 5) * 8 + 24 + 3 * K * 8
+
+
 def run(nx: int, k: int, reps: int, op: str = "volume"):
     import numpy as np
     import torch
@@ -52,10 +65,17 @@ def run(nx: int, k: int, reps: int, op: str = "volume"):
         kern = mg.DGVolume(k)
         call = lambda: kern(c, u, B, hb, 9.81, out)
         fl, by = flops_per_element(K) * ne, bytes_per_element(K) * ne
-    else:
+    elif op == "projection":
         kern = mg.DGProjection(k)
         call = lambda: kern(c, B, hb, u)
         fl, by = projection_flops(K) * ne, projection_bytes(K) * ne
+    else:
+        nbr, nq = W.dg_mesh_neighbours(nx, nx)
+        nbr, nq = torch.from_numpy(nbr).cuda(), torch.from_numpy(nq).cuda()
+        out = torch.empty((3 * K, ne), dtype=torch.float64, device="cuda")
+        kern = mg.DGEdges(k)
+        call = lambda: kern(c, u, B, hb, nbr, nq, 9.81, out)
+        fl, by = edge_flops(K) * ne, edge_bytes(K) * ne
     call()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -76,7 +96,7 @@ def main(argv=None):
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--op", default="volume", choices=("volume", "projection"))
+    ap.add_argument("--op", default="volume", choices=("volume", "projection", "edges"))
     a = ap.parse_args(argv)
     print(json.dumps(run(a.nx, a.k, a.reps, a.op)), flush=True)
 
