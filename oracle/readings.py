@@ -48,4 +48,6 @@ READINGS = {
            "(V u, V v + g xi (H + h_b)/2): V in place of U and d/dx2 for the pressure terms.",
     "R20": "The bathymetry h_b is constant on each element (the algebraic form takes it outside the "
            "integral); det B_e keeps its sign (|det B_e| for counter-clockwise elements).",
+    "R21": "DG edge terms: the Lax-Friedrichs wave speed is one value per edge, the larger of "
+           "|u_mean . n| + sqrt(g H_mean) over the two elements (element means).",
 }
