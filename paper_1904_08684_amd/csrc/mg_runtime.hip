@@ -1414,8 +1414,10 @@ int mg_apply(mg_ctx* h, int op, int level, int prec) {
         return c->fail(MG_EINVAL, "no such level in this precision");
     const bool has_next = level + 1 < c->L && c->lv[level + 1].has[prec];
     switch (op) {
-        case MG_OP_GS_RED: return c->gs(level, prec, 0, false);
-        case MG_OP_GS_BLACK: return c->gs(level, prec, 1, false);
+        case MG_OP_GS_RED:
+        case MG_OP_GS_BLACK:
+            if (c->lv[level].gal) return c->fail(MG_EINVAL, "Galerkin levels have no red-black sweep");
+            return c->gs(level, prec, op == MG_OP_GS_RED ? 0 : 1, false);
         case MG_OP_JACOBI:
             if (!c->lv[level].utmp[prec]) return c->fail(MG_EINVAL, "Jacobi needs a Jacobi context");
             return c->jacobi(level, prec, false);
@@ -1431,7 +1433,7 @@ int mg_apply(mg_ctx* h, int op, int level, int prec) {
             return c->coarse(prec);
         case MG_OP_RESIDUAL_RESTRICT: {
             if (!has_next) return c->fail(MG_EINVAL, "no coarser level");
-            if (c->grid.centering == MG_NODE && mg::fused_transfers(c->lv[level].g)) {
+            if (c->grid.centering == MG_NODE && !c->lv[level].gal && mg::fused_transfers(c->lv[level].g)) {
                 hipEvent_t e0 = c->begin();
                 return c->record(MG_K_RESTRICT, level,
                                  mg::launch_residual_restrict(c->lv[level].g, c->lv[level + 1].g, prec,

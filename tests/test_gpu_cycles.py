@@ -630,7 +630,7 @@ def test_neumann_256_converges_with_zero_mean(mg):
 
 
 # ---------------------------------------------- Galerkin coarse operators
-@pytest.mark.parametrize("dim,n", [(2, 65), (3, 33)])
+@pytest.mark.parametrize("dim,n", [(2, 65), (3, 33), (3, 257)])   # 257: level 1 would take the fused transfer
 def test_galerkin_stencil_ops_at_level_1(mg, dim, n):
     """The 9/27-point residual and Jacobi kernels of level 1 against the
     oracle's stencil operators (the host's R A P and the oracle's differ only
@@ -647,12 +647,20 @@ def test_galerkin_stencil_ops_at_level_1(mg, dim, n):
     r = s.level_get(1, mg.MG_FIELD_R)
     s.apply(mg.MG_OP_JACOBI, 1)
     uj = s.level_get(1, mg.MG_FIELD_U)
+    # residual + restriction of level 1 into level 2 uses the Galerkin residual
+    s.level_set(1, mg.MG_FIELD_U, u)
+    s.apply(mg.MG_OP_RESIDUAL_RESTRICT, 1)
+    f2 = s.level_get(2, mg.MG_FIELD_F)
+    with pytest.raises(mg.MGError):
+        s.apply(mg.MG_OP_GS_RED, 1)
     s.close()
     r_ref = galerkin.residual(u, f, h.W[1])
     uj_ref = galerkin.jacobi(u, f, h.W[1], 0.8)
-    er, ej = rel_max(r, r_ref), rel_max(uj, uj_ref)
-    print(f"Galerkin level-1 ops {dim}d n={n}: residual {er:.2e}, Jacobi {ej:.2e}", flush=True)
-    assert er <= 1e-13 and ej <= 1e-14
+    f2_ref = node.restrict_fw(r_ref)
+    er, ej, ef = rel_max(r, r_ref), rel_max(uj, uj_ref), rel_max(f2, f2_ref)
+    print(f"Galerkin level-1 ops {dim}d n={n}: residual {er:.2e}, Jacobi {ej:.2e}, residual+restrict {ef:.2e}",
+          flush=True)
+    assert er <= 1e-13 and ej <= 1e-14 and ef <= 1e-13
 
 
 @pytest.mark.parametrize("dim,n,nu,cycles", [(2, 129, 2, 3), (3, 65, 2, 3), (3, 257, 3, 2)])
