@@ -17,10 +17,21 @@ Conventions (readings):
 * The element basis is phi_ei = |det B_e|^(-1/2) phi^_i o F_e^-1, orthonormal
   on the element: the factors 1/|det B_e| and 1/|det B_e|^(3/2) of the
   paper's algebraic forms imply this scaling.
-* Flux tensor rows (with H = xi + h_b, h_b constant on the element):
+* Flux tensor rows (with H = xi + h_b):
   (U, V), (U u + g xi (H + h_b) / 2, U v), (V u, V v + g xi (H + h_b) / 2);
-  c = (xi, U, V) and u = (u, v) are DG fields with K(k) coefficients each.
+  c = (xi, U, V) and u = (u, v) are DG fields with K(k) coefficients each,
+  and so is the bathymetry h_b (a P^k field on every element: the paper's
+  algebraic form, which takes h_b out of the integral, is the case of a
+  field with only the constant mode; a linear h_b, as in the convergence
+  test of Sec. 3.1, is represented exactly for k >= 1).
 * Output E[j, p] = (A~, grad(phi_ep e_j))_{Omega_e}, j = 1, 2, 3.
+* The semi-discrete system (the paper's variational_disc_1 with the source
+  r(c) of eq:def_r and a body force): with the orthonormal element basis the
+  mass matrix is the identity and
+      dc/dt = E - S + R + F,
+  S the edge terms, R = (r(c), phi_ep e_j).  Time stepping: the three-stage
+  strong-stability-preserving Runge-Kutta method of Shu and Osher (the
+  paper names no integrator).
 """
 from __future__ import annotations
 
@@ -99,9 +110,19 @@ def triangle_rule(n: int = 7):
     return np.array(X), np.array(Y), np.array(Wt)
 
 
-def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: float, g: float) -> np.ndarray:
+def constant_field(k: int, value: float, B: np.ndarray) -> np.ndarray:
+    """Coefficients (K,) of the constant `value` on the element with map B:
+    value / phi_e1 = value sqrt(|det B| / 2) on the constant mode."""
+    det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
+    out = np.zeros(K_OF[k])
+    out[0] = value * math.sqrt(abs(det) / 2.0)
+    return out
+
+
+def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: np.ndarray, g: float) -> np.ndarray:
     """E[j, p] for one element: c (3, K) and u (2, K) coefficients, B (2, 2),
-    bathymetry hb, gravity g.  Quadrature on the physical element."""
+    bathymetry coefficients hb (K,), gravity g.  Quadrature on the physical
+    element."""
     K = K_OF[k]
     X, Y, Wt = triangle_rule()
     phi = np.array(basis(X, Y))[:K]                  # (K, Q)
@@ -116,7 +137,8 @@ def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: fl
     ph = sc * phi
     xi, U, V = (c[j] @ ph for j in range(3))         # field values at the points
     uu, vv = (u[j] @ ph for j in range(2))
-    pres = 0.5 * g * xi * ((xi + hb) + hb)
+    hbv = hb @ ph
+    pres = 0.5 * g * xi * ((xi + hbv) + hbv)
     A = [(U, V), (U * uu + pres, U * vv), (V * uu, V * vv + pres)]
     w = Wt * abs(det)
     E = np.zeros((3, K))
@@ -125,7 +147,7 @@ def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: fl
     return E
 
 
-def velocity_projection(k: int, c: np.ndarray, B: np.ndarray, hb: float) -> np.ndarray:
+def velocity_projection(k: int, c: np.ndarray, B: np.ndarray, hb: np.ndarray) -> np.ndarray:
     """The velocity u = (u, v) of one element from (u H, psi) = (q, psi) for
     every test function psi of the element (the paper's variational_disc_2),
     H = xi + h_b, q = (U, V): assemble the H-weighted mass matrix and the
@@ -136,7 +158,7 @@ def velocity_projection(k: int, c: np.ndarray, B: np.ndarray, hb: float) -> np.n
     det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
     ph = abs(det) ** -0.5 * np.array(basis(X, Y))[:K]
     w = Wt * abs(det)
-    H = c[0] @ ph + hb
+    H = c[0] @ ph + hb @ ph
     M = (ph * (w * H)) @ ph.T
     rhs = np.stack([(ph * (w * (c[j] @ ph))).sum(axis=1) for j in (1, 2)], axis=1)
     return np.linalg.solve(M, rhs).T
@@ -163,17 +185,28 @@ def eval_fields(k: int, coef: np.ndarray, B: np.ndarray, rel: np.ndarray) -> np.
     return coef @ ph
 
 
-def mean_state(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: float):
+def mean_state(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: np.ndarray):
     """Element means of the velocity and of the depth: the constant mode's
     coefficient times the value of phi_e1, sqrt(2 / |det B_e|)."""
     det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
     v1 = math.sqrt(2.0 / abs(det))
-    return u[:, 0] * v1, c[0, 0] * v1 + hb
+    return u[:, 0] * v1, (c[0, 0] + hb[0]) * v1
 
 
-def flux_tensor(xi, U, V, uu, vv, hb, g):
-    pres = 0.5 * g * xi * ((xi + hb) + hb)
+def flux_tensor(xi, U, V, uu, vv, hbv, g):
+    """Rows of the flux tensor from point values (hbv: the bathymetry)."""
+    pres = 0.5 * g * xi * ((xi + hbv) + hbv)
     return [(U, V), (U * uu + pres, U * vv), (V * uu, V * vv + pres)]
+
+
+class Ghost:
+    """A prescribed exterior state on a domain-boundary edge (Dirichlet
+    data): coefficients cb (3, K) and ub (2, K) of polynomials in the basis
+    of the element that owns the edge, whose traces on the edge are the
+    exterior values; the exterior bathymetry is the element's own."""
+
+    def __init__(self, cb: np.ndarray, ub: np.ndarray):
+        self.cb, self.ub = cb, ub
 
 
 def edge_integrals_lf(k, own, nbrs, g):
@@ -182,8 +215,9 @@ def edge_integrals_lf(k, own, nbrs, g):
     F = (A(c-, u-) n + A(c+, u+) n) / 2 + lambda_E (c- - c+) / 2, lambda_E
     = max over both sides of |u_mean . n| + sqrt(g H_mean) (constant on the
     edge), n the unit outward normal.  own = (c, u, B, a1, hb); nbrs[q] =
-    the neighbour's (c, u, B, a1, hb) or None on the boundary.  Gauss rule
-    on the physical edge.  Returns (3, K)."""
+    the neighbour's (c, u, B, a1, hb), a Ghost (prescribed exterior state;
+    its mean state enters lambda_E like a neighbour's), or None (no term).
+    Gauss rule on the physical edge.  Returns (3, K)."""
     K = K_OF[k]
     c, u, B, a1, hb = own
     V = element_vertices(B, np.zeros(2))            # relative to a1
@@ -193,22 +227,117 @@ def edge_integrals_lf(k, own, nbrs, g):
     for q in range(3):
         if nbrs[q] is None:
             continue
-        cn, un, Bn, a1n, hbn = nbrs[q]
+        if isinstance(nbrs[q], Ghost):      # exterior polynomials on this element
+            cn, un, Bn, a1n, hbn = nbrs[q].cb, nbrs[q].ub, B, a1, hb
+        else:
+            cn, un, Bn, a1n, hbn = nbrs[q]
         p0, p1 = V[q], V[(q + 1) % 3]
         d = p1 - p0
         L = math.hypot(d[0], d[1])
         n = np.array([d[1], -d[0]]) / L
         pts = p0[None, :] + s[:, None] * d[None, :]
-        fm = eval_fields(k, np.vstack([c, u]), B, pts)
-        fp = eval_fields(k, np.vstack([cn, un]), Bn, (a1 - a1n)[None, :] + pts)
+        fm = eval_fields(k, np.vstack([c, u, hb[None, :]]), B, pts)
+        fp = eval_fields(k, np.vstack([cn, un, hbn[None, :]]), Bn, (a1 - a1n)[None, :] + pts)
         um, Hm = mean_state(k, c, u, B, hb)
         up, Hp = mean_state(k, cn, un, Bn, hbn)
         lam = max(abs(um @ n) + math.sqrt(g * Hm), abs(up @ n) + math.sqrt(g * Hp))
-        Am = flux_tensor(fm[0], fm[1], fm[2], fm[3], fm[4], hb, g)
-        Ap = flux_tensor(fp[0], fp[1], fp[2], fp[3], fp[4], hbn, g)
+        Am = flux_tensor(fm[0], fm[1], fm[2], fm[3], fm[4], fm[5], g)
+        Ap = flux_tensor(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], g)
         ph = eval_fields(k, np.eye(K), B, pts)              # the element's basis at the points
         for j in range(3):
             F = 0.5 * ((Am[j][0] * n[0] + Am[j][1] * n[1]) + (Ap[j][0] * n[0] + Ap[j][1] * n[1])) \
                 + 0.5 * lam * (fm[j] - fp[j])
             out[j] += (ph * (F * w / 2.0 * L)).sum(axis=1)
     return out
+
+
+# ------------------------------------------------ source terms, the system
+def source_integrals(k: int, c: np.ndarray, B: np.ndarray, hb: np.ndarray, g: float, tau: float,
+                     fc: float) -> np.ndarray:
+    """R[j, p] = (r(c), phi_ep e_j) for one element with the paper's source
+    (eq:def_r without the body force): r = (0, -tau U + fc V + g xi dh_b/dx,
+    -tau V - fc U + g xi dh_b/dy), tau and fc constants.  Quadrature on the
+    physical element; returns (3, K)."""
+    K = K_OF[k]
+    X, Y, Wt = triangle_rule()
+    det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
+    sc = abs(det) ** -0.5
+    ph = sc * np.array(basis(X, Y))[:K]
+    gx, gy = basis_grad(X, Y)
+    Binv = np.linalg.inv(B)
+    dx1 = sc * (Binv[0, 0] * np.array(gx)[:K] + Binv[1, 0] * np.array(gy)[:K])
+    dx2 = sc * (Binv[0, 1] * np.array(gx)[:K] + Binv[1, 1] * np.array(gy)[:K])
+    xi, U, V = (c[j] @ ph for j in range(3))
+    hx, hy = hb @ dx1, hb @ dx2
+    r = [0.0 * xi, -tau * U + fc * V + g * xi * hx, -tau * V - fc * U + g * xi * hy]
+    w = Wt * abs(det)
+    return np.array([(ph * (w * r[j])).sum(axis=1) for j in range(3)])
+
+
+def mesh_rhs(k: int, B: np.ndarray, a1: np.ndarray, nbr: np.ndarray, c: np.ndarray, u: np.ndarray,
+             hb: np.ndarray, g: float, tau: float = 0.0, fc: float = 0.0, F=None, cb=None, ub=None) -> np.ndarray:
+    """dc/dt = E - S + R + F of the semi-discrete system on a mesh: B (4, ne)
+    rows B11, B12, B21, B22; a1 (2, ne) first vertices; nbr (3, ne) the
+    element across each local edge, -1 for no term and -2 - b for the
+    prescribed exterior state b (cb (3K, nb), ub (2K, nb)); c (3K, ne), u
+    (2K, ne), hb (K, ne) coefficients; F (3K, ne) or None.  Returns (3K, ne)."""
+    K = K_OF[k]
+    ne = B.shape[1]
+
+    def state(e):
+        Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
+        return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a1[:, e], hb[:, e]
+
+    out = np.zeros((3 * K, ne))
+    for e in range(ne):
+        own = state(e)
+        nbrs = []
+        for q in range(3):
+            f = int(nbr[q, e])
+            if f >= 0:
+                nbrs.append(state(f))
+            elif f <= -2:
+                b = -2 - f
+                nbrs.append(Ghost(cb[:, b].reshape(3, K), ub[:, b].reshape(2, K)))
+            else:
+                nbrs.append(None)
+        E = volume_integrals(k, own[0], own[1], own[2], own[4], g)
+        S = edge_integrals_lf(k, own, nbrs, g)
+        R = source_integrals(k, own[0], own[2], own[4], g, tau, fc)
+        out[:, e] = (E - S + R).reshape(-1)
+    if F is not None:
+        out += F
+    return out
+
+
+def mesh_velocity(k: int, B: np.ndarray, c: np.ndarray, hb: np.ndarray) -> np.ndarray:
+    """The velocity projection on every element, (2K, ne)."""
+    K = K_OF[k]
+    out = np.zeros((2 * K, B.shape[1]))
+    for e in range(B.shape[1]):
+        Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
+        out[:, e] = velocity_projection(k, c[:, e].reshape(3, K), Be, hb[:, e]).reshape(-1)
+    return out
+
+
+# stage times (fractions of dt) and the convex weights of the three stages
+SSP3_TIMES = (0.0, 1.0, 0.5)
+
+
+def ssp_rk3_step(k: int, B, a1, nbr, c, hb, dt: float, g: float, tau: float = 0.0, fc: float = 0.0,
+                 F3=None, cb3=None, ub3=None):
+    """One step of the three-stage SSP Runge-Kutta method (Shu and Osher):
+        c1 = c + dt L(c),  c2 = 3/4 c + 1/4 (c1 + dt L(c1)),
+        c3 = 1/3 c + 2/3 (c2 + dt L(c2)),
+    L the semi-discrete right-hand side with the velocity projected from the
+    stage state first; F3[s], cb3[s], ub3[s] the body force and exterior
+    states at the stage times t + SSP3_TIMES[s] dt (None: none)."""
+    pick = lambda a, s: None if a is None else a[s]
+    weights = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
+    y = c
+    for s_ in range(3):
+        u = mesh_velocity(k, B, y, hb)
+        L = mesh_rhs(k, B, a1, nbr, y, u, hb, g, tau, fc, pick(F3, s_), pick(cb3, s_), pick(ub3, s_))
+        a, b = weights[s_]
+        y = a * c + b * (y + dt * L)
+    return y

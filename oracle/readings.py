@@ -46,8 +46,18 @@ READINGS = {
            "scaling produces, while its definition line omits the factor.",
     "R19": "The y-momentum volume term (the paper's 'similar expression') uses the third flux row "
            "(V u, V v + g xi (H + h_b)/2): V in place of U and d/dx2 for the pressure terms.",
-    "R20": "The bathymetry h_b is constant on each element (the algebraic form takes it outside the "
-           "integral); det B_e keeps its sign (|det B_e| for counter-clockwise elements).",
+    "R20": "The bathymetry h_b is a P^k field on every element, like xi; the algebraic form, which "
+           "takes h_b outside the integral, is the case of a field with only the constant mode, and "
+           "the linear h_b of the convergence test is exact for k >= 1.  det B_e keeps its sign "
+           "(|det B_e| for counter-clockwise elements).",
     "R21": "DG edge terms: the Lax-Friedrichs wave speed is one value per edge, the larger of "
            "|u_mean . n| + sqrt(g H_mean) over the two elements (element means).",
+    "R22": "Dirichlet boundaries: the exterior state of a boundary edge is a prescribed polynomial "
+           "in the owning element's basis (in the convergence test the L2 projection of the exact "
+           "xi, U, V and of u = U/H, v = V/H onto that element), entering the Lax-Friedrichs flux "
+           "like a neighbour with the element's own bathymetry.",
+    "R23": "Source and time stepping: tau_bf and f_c are constants (zero in the convergence test, "
+           "which states neither); the body force enters as the coefficients of its L2 projection; "
+           "the integrator is the three-stage SSP Runge-Kutta method of Shu and Osher with the "
+           "velocity projected from every stage state.",
 }

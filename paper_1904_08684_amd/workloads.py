@@ -142,8 +142,10 @@ SEED_DG_MESH = 20
 SEED_DG_FIELDS = 21
 
 
-def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, with_origin: bool = False):
-    """Affine maps of a split-quad triangulation of the unit square: nx x ny
+def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, with_origin: bool = False,
+            length: float = 1.0):
+    """Affine maps of a split-quad triangulation of the square [0, length]^2
+    (the convergence test's domain is [0, 1000]^2): nx x ny
     squares, each cut along one diagonal into two counter-clockwise
     triangles, interior vertices moved by up to `jitter` of a cell width (the
     randomly perturbed regular mesh of the paper's convergence test moves
@@ -153,10 +155,10 @@ def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, wit
     Elements: the lower-right triangles (p00, p10, p11) of squares (i, j) at
     i ny + j, then the upper-left ones (p00, p11, p01)."""
     rng = np.random.default_rng(seed)
-    xs = np.linspace(0.0, 1.0, nx + 1)
-    ys = np.linspace(0.0, 1.0, ny + 1)
+    xs = np.linspace(0.0, length, nx + 1)
+    ys = np.linspace(0.0, length, ny + 1)
     X, Y = np.meshgrid(xs, ys, indexing="ij")
-    d = jitter * min(1.0 / nx, 1.0 / ny)
+    d = jitter * min(length / nx, length / ny)
     X[1:-1, 1:-1] += rng.uniform(-d, d, (nx - 1, ny - 1))
     Y[1:-1, 1:-1] += rng.uniform(-d, d, (nx - 1, ny - 1))
     p00 = np.stack([X[:-1, :-1], Y[:-1, :-1]], -1).reshape(-1, 2)
@@ -208,12 +210,13 @@ def dg_mesh_neighbours(nx: int, ny: int):
 
 
 def dg_fields(K: int, B: np.ndarray, seed: int = SEED_DG_FIELDS):
-    """Coefficients of (xi, U, V) and (u, v), (3K, ne) and (2K, ne), and a
-    per-element bathymetry h_b in [1, 5], for the elements with maps B
-    (4, ne).  Physical values: xi ~ N(0, 0.1) (so that the depth xi + h_b
-    stays positive), U, V, u, v ~ N(0, 1) for the element mean, a tenth of
-    that for each higher mode; a coefficient is the physical amplitude times
-    sqrt(|det B_e| / 2), the factor of the orthonormal element basis."""
+    """Coefficients of (xi, U, V), (u, v) and the bathymetry h_b, (3K, ne),
+    (2K, ne) and (K, ne), for the elements with maps B (4, ne).  Physical
+    values: xi ~ N(0, 0.1) (so that the depth xi + h_b stays positive), U,
+    V, u, v ~ N(0, 1) for the element mean, a tenth of that for each higher
+    mode; h_b with a mean U[1, 5] and higher modes N(0, 0.02); a coefficient
+    is the physical amplitude times sqrt(|det B_e| / 2), the factor of the
+    orthonormal element basis."""
     rng = np.random.default_rng(seed)
     ne = B.shape[1]
     unit = np.sqrt(np.abs(B[0] * B[3] - B[1] * B[2]) / 2.0)
@@ -222,5 +225,21 @@ def dg_fields(K: int, B: np.ndarray, seed: int = SEED_DG_FIELDS):
     amp = np.array([0.1, 1.0, 1.0])[:, None, None]
     c = rng.normal(0.0, 1.0, (3, K, ne)) * scale * amp * unit
     u = rng.normal(0.0, 1.0, (2, K, ne)) * scale * unit
-    hb = rng.uniform(1.0, 5.0, ne)
-    return np.ascontiguousarray(c.reshape(3 * K, ne)), np.ascontiguousarray(u.reshape(2 * K, ne)), hb
+    hb = np.empty((K, ne))
+    hb[0] = rng.uniform(1.0, 5.0, ne)
+    hb[1:] = rng.normal(0.0, 0.02, (K - 1, ne))
+    hb *= unit
+    return (np.ascontiguousarray(c.reshape(3 * K, ne)), np.ascontiguousarray(u.reshape(2 * K, ne)),
+            np.ascontiguousarray(hb))
+
+
+def dg_boundary_ghosts(nbr: np.ndarray):
+    """Number the domain-boundary edges of a neighbour table (entries -1):
+    returns a copy of nbr with -2 - b at boundary edge b, and the element
+    and local edge of every boundary edge (be, bq int32 (nb,)), in the order
+    of the element index, then the local edge."""
+    nbr = np.array(nbr, dtype=np.int32, copy=True)
+    q, e = np.nonzero(nbr.T == -1)[1], np.nonzero(nbr.T == -1)[0]
+    b = np.arange(e.size, dtype=np.int32)
+    nbr[q, e] = -2 - b
+    return nbr, e.astype(np.int32), q.astype(np.int32)

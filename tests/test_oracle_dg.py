@@ -2,7 +2,12 @@
 closed-form monomial integrals of the reference triangle, orthonormality of
 the paper's basis, the hand-written gradients against finite differences,
 and the volume integrals of constant fields against the boundary integrals
-the divergence theorem turns them into (1-D Gauss rule on the three edges)."""
+the divergence theorem turns them into (1-D Gauss rule on the three edges);
+then the semi-discrete system: a uniform flow over a sloping bottom is
+steady (source against flux), the source in closed form, the manufactured
+solution's force against finite differences, the consistency order of the
+operator on the manufactured solution, and the Runge-Kutta step's
+stage times and weights (Simpson's rule on a uniform state)."""
 import math
 
 import numpy as np
@@ -80,7 +85,7 @@ def test_constant_fields_reduce_to_boundary_integrals(k):
         unit = math.sqrt(abs(det)) / math.sqrt(2.0)    # coefficient of the constant 1
         c[:, 0] = np.array([xi, U, V]) * unit
         u[:, 0] = np.array([u0, v0]) * unit
-        E = dg.volume_integrals(k, c, u, B, hb, g)
+        E = dg.volume_integrals(k, c, u, B, dg.constant_field(k, hb, B), g)
         pres = 0.5 * g * xi * ((xi + hb) + hb)
         Ac = np.array([[U, V], [U * u0 + pres, U * v0], [V * u0, V * v0 + pres]])
         want = edge_integrals(k, B, a1, Ac)
@@ -97,7 +102,7 @@ def test_projection_of_constant_depth_divides(k):
     B = np.array([[0.7, 0.2], [-0.1, 0.8]])
     c = np.zeros((3, K))
     c[1:] = rng.normal(size=(2, K))
-    u = dg.velocity_projection(k, c, B, 2.5)
+    u = dg.velocity_projection(k, c, B, dg.constant_field(k, 2.5, B))
     assert np.max(np.abs(u - c[1:] / 2.5)) <= 1e-13
 
 
@@ -118,7 +123,7 @@ def test_projection_recovers_a_constant_velocity(k):
     H[0] += hb * unit
     c[1] = u0[0] * H                                    # U = u0 H, V = v0 H: in P^1
     c[2] = u0[1] * H
-    u = dg.velocity_projection(k, c, B, hb)
+    u = dg.velocity_projection(k, c, B, dg.constant_field(k, hb, B))
     want = np.zeros((2, K))
     want[:, 0] = u0 * unit
     assert np.max(np.abs(u - want)) <= 1e-12
@@ -147,11 +152,11 @@ def test_edge_terms_of_a_constant_state_equal_the_volume_terms(k):
         u = np.zeros((2, K))
         c[:, 0] = np.array([xi, U, V]) * unit
         u[:, 0] = np.array([u0, v0]) * unit
-        return c, u, Be, a, hb
+        return c, u, Be, a, dg.constant_field(k, hb, Be)
     e = int(np.flatnonzero((nbr >= 0).all(axis=0))[0])
     own = state(e)
     S = dg.edge_integrals_lf(k, own, [state(int(nbr[q, e])) for q in range(3)], g)
-    E = dg.volume_integrals(k, own[0], own[1], own[2], hb, g)
+    E = dg.volume_integrals(k, own[0], own[1], own[2], own[4], g)
     assert np.max(np.abs(S - E)) <= 1e-12 * (1 + np.max(np.abs(E)))
 
 
@@ -168,7 +173,7 @@ def test_edge_flux_is_conservative(k):
     c, u, hb = W.dg_fields(K, B, seed=4)
     def state(e):
         Be, a = _mesh_element(B, a1, e)
-        return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a, hb[e]
+        return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a, hb[:, e]
     for e in range(B.shape[1]):
         for q in range(3):
             f = int(nbr[q, e])
@@ -202,7 +207,7 @@ def test_edge_flux_jump_term_closed_form():
         unit = math.sqrt(abs(np.linalg.det(Be)) / 2.0)
         c = np.zeros((3, 1))
         c[1, 0], c[2, 0] = U * unit, V * unit
-        return c, np.zeros((2, 1)), Be, a, hb
+        return c, np.zeros((2, 1)), Be, a, dg.constant_field(0, hb, Be)
     own, other = state(e, 0.7, -0.2, 1.5), state(f, -0.4, 0.9, 3.0)
     only = [None, None, None]
     only[q] = other
@@ -217,3 +222,153 @@ def test_edge_flux_jump_term_closed_form():
     d = V[(q + 1) % 3] - V[q]
     n = np.array([d[1], -d[0]]) / L
     assert abs(S[0, 0] - 0.5 * ((0.7 - 0.4) * n[0] + (-0.2 + 0.9) * n[1]) * L * phi1) <= 1e-13
+
+
+# ------------------------------------------------ the semi-discrete system
+def _mesh(nx, length=1.0, jitter=0.2):
+    from paper_1904_08684_amd import workloads as W
+    B, a1 = W.dg_mesh(nx, nx, with_origin=True, length=length, jitter=jitter)
+    nbr, _ = W.dg_mesh_neighbours(nx, nx)
+    nbr, be, bq = W.dg_boundary_ghosts(nbr)
+    return B, a1, nbr, be, bq
+
+
+def _uniform(k, B, vals):
+    """Coefficients (len(vals) K, ne) of constant fields."""
+    K = dg.K_OF[k]
+    unit = np.sqrt(np.abs(B[0] * B[3] - B[1] * B[2]) / 2.0)
+    out = np.zeros((len(vals) * K, B.shape[1]))
+    for j, v in enumerate(vals):
+        out[j * K] = v * unit
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_uniform_flow_over_a_sloping_bottom_is_steady(k):
+    """Constant xi, U, V, u, v over a linear bathymetry, with the exterior
+    states equal to the interior ones: the flux divergence is
+    g xi grad h_b, which the source cancels, so dc/dt = 0 on every element
+    (boundary elements included).  A wrong sign or factor in the source, the
+    bathymetry terms or the ghost edges leaves O(1) residuals."""
+    from oracle import manufactured as M
+    B, a1, nbr, be, bq = _mesh(3)
+    K = dg.K_OF[k]
+    g = 9.81
+    c = _uniform(k, B, (0.3, 0.8, -0.5))
+    u = _uniform(k, B, (0.25, -0.1))
+    hb = M.project(k, B, a1, lambda x, y: (2.0 + 0.7 * x - 0.4 * y,))
+    cb, ub = c[:, be], u[:, be]
+    L = dg.mesh_rhs(k, B, a1, nbr, c, u, hb, g, 0.0, 0.0, None, cb, ub)
+    scale = np.max(np.abs(dg.mesh_rhs(k, B, a1, np.full_like(nbr, -1), c, u, hb, g)))
+    assert scale > 0.1
+    assert np.max(np.abs(L)) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("k", [0, 2])
+def test_source_terms_closed_form(k):
+    """Constant xi, U, V and a linear h_b: r is constant on the element, and
+    its integral against phi_ep is r |Omega_e| phi_e1 for p = 1, else 0."""
+    from oracle import manufactured as M
+    B, a1, _, _, _ = _mesh(2)
+    K = dg.K_OF[k]
+    g, tau, fc = 9.81, 0.03, 1.1e-4
+    xi, U, V, hx, hy = 0.4, 0.9, -0.6, 0.7, -0.4
+    for e in range(B.shape[1]):
+        Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
+        det = np.linalg.det(Be)
+        c = np.zeros((3, K))
+        c[:, 0] = np.array([xi, U, V]) * math.sqrt(abs(det) / 2.0)
+        # h_b's projection on this element (P^0 keeps only its mean, and
+        # then the source sees no slope)
+        hb = M.project(k, B[:, e:e + 1], a1[:, e:e + 1], lambda x, y: (1.0 + hx * x + hy * y,))[:, 0]
+        R = dg.source_integrals(k, c, Be, hb, g, tau, fc)
+        sx, sy = (hx, hy) if k > 0 else (0.0, 0.0)
+        want = np.zeros((3, K))
+        want[1, 0] = (-tau * U + fc * V + g * xi * sx) * math.sqrt(abs(det) / 2.0)
+        want[2, 0] = (-tau * V - fc * U + g * xi * sy) * math.sqrt(abs(det) / 2.0)
+        assert np.max(np.abs(R - want)) <= 1e-13 * (1.0 + np.max(np.abs(want)))
+
+
+def test_manufactured_force_matches_finite_differences():
+    """The hand-derived body force against central differences of the exact
+    fields through the momentum equations, and the mass equation without a
+    force."""
+    from oracle import manufactured as M
+    rng = np.random.default_rng(5)
+    x, y, t = rng.uniform(0, 1000, 50), rng.uniform(0, 1000, 50), rng.uniform(0, 1500, 50)
+    h = 1e-3
+    def q_over(x, y, t):
+        xi, U, V = M.exact(x, y, t)
+        H = M.bathymetry(x, y) + xi
+        return U * U / H, U * V / H, V * V / H
+    d = lambda f, i, dx, dy, dt: (f(x + dx, y + dy, t + dt)[i] - f(x - dx, y - dy, t - dt)[i]) / (2 * h)
+    xi, U, V = M.exact(x, y, t)
+    H = M.bathymetry(x, y) + xi
+    FU = d(M.exact, 1, 0, 0, h) + d(q_over, 0, h, 0, 0) + d(q_over, 1, 0, h, 0) + M.G * H * d(M.exact, 0, h, 0, 0)
+    FV = d(M.exact, 2, 0, 0, h) + d(q_over, 1, h, 0, 0) + d(q_over, 2, 0, h, 0) + M.G * H * d(M.exact, 0, 0, h, 0)
+    fu, fv = M.forcing(x, y, t)
+    assert np.max(np.abs(fu - FU)) <= 1e-7 and np.max(np.abs(fv - FV)) <= 1e-7
+    assert np.max(np.abs(fu)) > 1e-3
+    mass = d(M.exact, 0, 0, 0, h) + d(M.exact, 1, h, 0, 0) + d(M.exact, 2, 0, h, 0)
+    assert np.max(np.abs(mass)) <= 1e-9
+
+
+@pytest.mark.parametrize("k,sizes,rate", [(1, (8, 16), 0.75), (2, (4, 8), 1.8)])
+def test_operator_is_consistent_on_the_manufactured_solution(k, sizes, rate):
+    """dc/dt of the projected exact solution (its velocity projected, the
+    exact force and exterior states) against the projected exact time
+    derivative: the residual falls like h^k (k = 1: rate -> 1, k = 2: 2), and
+    a dropped or wrong term leaves it O(1)."""
+    from oracle import manufactured as M
+    K = dg.K_OF[k]
+    t = 300.0
+    errs = []
+    for nx in sizes:
+        B, a1, nbr, be, bq = _mesh(nx, length=1000.0)
+        c = M.project(k, B, a1, lambda x, y: M.exact(x, y, t))
+        hb = M.project(k, B, a1, lambda x, y: (M.bathymetry(x, y),))
+        F, cb, ub = M.stage_data(k, B, a1, be, t)
+        u = dg.mesh_velocity(k, B, c, hb)
+        L = dg.mesh_rhs(k, B, a1, nbr, c, u, hb, M.G, 0.0, 0.0, F, cb, ub)
+        h = 1e-3
+        dc = (M.project(k, B, a1, lambda x, y: M.exact(x, y, t + h))
+              - M.project(k, B, a1, lambda x, y: M.exact(x, y, t - h))) / (2 * h)
+        errs.append(np.sqrt(np.sum((L - dc) ** 2)))
+    assert math.log2(errs[0] / errs[1]) >= rate, errs
+
+
+def _periodic_neighbours(nx):
+    """Edge neighbours of dg_mesh(nx, nx) with the square's opposite sides
+    identified (an unperturbed mesh is then a periodic one)."""
+    half = nx * nx
+    nbr = np.zeros((3, 2 * half), dtype=np.int32)
+    for i in range(nx):
+        for j in range(nx):
+            lr, ul = i * nx + j, half + i * nx + j
+            nbr[:, lr] = [half + i * nx + (j - 1) % nx, half + ((i + 1) % nx) * nx + j, ul]
+            nbr[:, ul] = [lr, i * nx + (j + 1) % nx, ((i - 1) % nx) * nx + j]
+    return nbr
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_ssp_rk3_step_is_simpson_on_a_uniform_state(k):
+    """On a periodic mesh a uniform state stays uniform, its flux divergence
+    is zero, and dc/dt is the force alone.  The three stages at t, t + dt,
+    t + dt / 2 with the weights 1/6, 1/6, 2/3 of the combined step integrate
+    a cubic force in time exactly (Simpson's rule)."""
+    from paper_1904_08684_amd import workloads as W
+    nx = 3
+    B, a1 = W.dg_mesh(nx, nx, with_origin=True, jitter=0.0)
+    nbr = _periodic_neighbours(nx)
+    K = dg.K_OF[k]
+    hb = _uniform(k, B, (2.0,))
+    c = _uniform(k, B, (0.1, 0.3, -0.2))
+    t0, dt = 0.7, 0.4
+    f = lambda t: 0.5 - t + 2.0 * t ** 2 + 0.8 * t ** 3          # force on U
+    Fint = lambda t: 0.5 * t - 0.5 * t ** 2 + 2.0 * t ** 3 / 3.0 + 0.2 * t ** 4
+    F3 = np.stack([_uniform(k, B, (0.0, f(t0 + s * dt), 0.0)) for s in dg.SSP3_TIMES])
+    out = dg.ssp_rk3_step(k, B, a1, nbr, c, hb, dt, 9.81, F3=F3)
+    want = _uniform(k, B, (0.1, 0.3 + Fint(t0 + dt) - Fint(t0), -0.2))
+    # higher modes: the flux terms of a uniform state cancel to rounding
+    # (O(1) terms); a wrong stage time or weight is off by about 1e-3
+    assert np.max(np.abs(out - want)) <= 1e-11
