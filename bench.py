@@ -217,7 +217,7 @@ def other_configs(mg, W, torch, np):
     # perturbed split-quad triangles, orders 1-3 (one launch each, HIP events)
     from paper_1904_08684_amd import dgbench
     for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection"),
-                     ("edges", "dg_edge_terms")):
+                     ("edges", "dg_edge_terms"), ("rhs", "dg_rhs"), ("step", "dg_ssp_rk3_step")):
         for kk in (1, 2, 3):
             r = dgbench.run(1024, kk, 20, op)
             res[f"{name}_k{kk}_2M_elements"] = {

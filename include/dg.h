@@ -16,7 +16,17 @@
  * polynomials phi^_1 .. phi^_10 (K(k) = 1, 3, 6, 10 of them for order
  * k = 0..3), so that the paper's factors 1/|det B_e| and 1/|det B_e|^(3/2)
  * appear (written with det B_e itself, which keeps the sign right for
- * elements of either orientation).  h_b is constant on each element.
+ * elements of either orientation).  The bathymetry h_b is a field of order
+ * max(k, 1), KB = 3, 3, 6, 10 coefficients per element for k = 0..3; the
+ * paper's algebraic form, with h_b outside the integral, is the case of a
+ * field with only the constant mode (coefficient h_b sqrt(|det B_e| / 2)),
+ * and a linear h_b (the convergence test of Sec. 3.1) is exact at every
+ * order.  (At k = 0 a piecewise-constant h_b would make the scheme
+ * inconsistent where xi != 0: the pressure flux jumps with h_b across the
+ * edges while g xi grad h_b vanishes inside the elements.)  The reference
+ * and edge tables therefore cover the first KB basis functions.  The element
+ * basis is orthonormal, so the mass matrix of the semi-discrete system is the
+ * identity.
  *
  * Status codes are those of mg.h. */
 #ifndef DG_H
@@ -28,14 +38,24 @@
 extern "C" {
 #endif
 
-/* Doubles in the reference table of order k: 2 K^2 + 2 K^3, or 0 for k
+/* Host: the reason of this thread's last MG_EDEVICE from a dg_ entry point
+ * (the step and the HIP error name), or "" (library-owned string, valid
+ * until the thread's next dg_ call). */
+const char* dg_last_error(void);
+
+/* Host: the values of the K(k) reference basis polynomials at npts points
+ * (x[q], y[q]) of the reference plane: out[p npts + q] = phi^_(p+1)(x_q, y_q)
+ * (caller-owned arrays).  MG_EINVAL for a bad k, npts < 0 or a NULL array. */
+int dg_basis_values(int k, long long npts, const double* x, const double* y, double* out);
+
+/* Doubles in the reference table for order k: 2 KB^2 + 2 KB^3, or 0 for k
  * outside 0..3. */
 long long dg_reference_size(int k);
 
-/* Host: the exact reference integrals of order k into ref (caller-owned,
+/* Host: the exact reference integrals for order k into ref (caller-owned,
  * dg_reference_size(k) doubles): G[l][p][i] = int d_l phi^_p phi^_i, then
  * H[l][p][i][m] = int d_l phi^_p phi^_i phi^_m over the reference triangle,
- * l = 0, 1 (d/dx^1, d/dx^2), row-major.  Computed from the monomial
+ * l = 0, 1 (d/dx^1, d/dx^2), all indices below KB, row-major.  Computed from the monomial
  * integrals a! b! / (a + b + 2)!.  MG_EINVAL for a bad k or NULL ref. */
 int dg_reference_integrals(int k, double* ref);
 
@@ -44,7 +64,7 @@ int dg_reference_integrals(int k, double* ref);
  *   c[(j K + i) ne + e]    coefficients of xi, U, V (j = 0, 1, 2)
  *   u[(j K + i) ne + e]    coefficients of u, v (j = 0, 1)
  *   B[q ne + e]            B_e entries B11, B12, B21, B22 (q = 0..3)
- *   hb[e]                  bathymetry on the element
+ *   hb[i ne + e]           coefficients of the bathymetry (i < KB)
  *   ref                    the table of dg_reference_integrals, on the device
  *   out[(j K + p) ne + e]  E[j][p][e]
  * Enqueued on `stream` (a hipStream_t, NULL = the default stream); returns
@@ -65,20 +85,23 @@ int dg_product_integrals(int k, double* T);
 /* Device: the velocity of every element from the paper's second discrete
  * equation (variational_disc_2), (u H, psi) = (q, psi) for all psi in P^k
  * of the element, H = xi + h_b, q = (U, V): per element the H-weighted mass
- * matrix M[p][m] = |det B_e|^(-1/2) sum_i H_i T[p][i][m] (the constant h_b
- * enters the coefficient of phi_e1), a Cholesky factorisation and two
- * solves.  Arrays as for dg_volume_integrals: c (3K x ne), B (4 x ne),
- * hb (ne), T the table of dg_product_integrals on the device, u (2K x ne)
+ * matrix M[p][m] = |det B_e|^(-1/2) sum_i H_i T[p][i][m], a Cholesky
+ * factorisation and two solves.  Arrays as for dg_volume_integrals: c
+ * (3K x ne), B (4 x ne), hb (KB x ne; its modes from K on are orthogonal to
+ * every product of two test functions and do not enter), T the table of
+ * dg_product_integrals
+ * on the device, u (2K x ne)
  * the result.  MG_EINVAL / MG_EDEVICE as dg_volume_integrals; a depth that
  * is not positive on the element leaves non-finite values there. */
 int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
                            const double* T, double* u, void* stream);
 
-/* Doubles in the edge table of order k: 12 K^2 + 12 K^3, or 0 for a bad k. */
+/* Doubles in the edge table for order k: 12 KB^2 + 12 KB^3, or 0 for a bad k. */
 long long dg_edge_table_size(int k);
 
-/* Host: the exact edge integrals of order k, with the local edges of the
- * reference triangle q0 (0,0)->(1,0), q1 (1,0)->(0,1), q2 (0,1)->(0,0)
+/* Host: the exact edge integrals for order k (indices below KB), with the
+ * local edges of the reference triangle q0 (0,0)->(1,0), q1 (1,0)->(0,1),
+ * q2 (0,1)->(0,0)
  * parametrised by s in [0, 1], and a neighbour's edge q' traversed backwards
  * (its parameter 1 - s), row-major in this order:
  *   O2[q][p][i]      = int phi^_p phi^_i            along q
@@ -88,22 +111,66 @@ long long dg_edge_table_size(int k);
  * MG_EINVAL for a bad k or NULL table. */
 int dg_edge_integrals(int k, double* table);
 
-/* Device: the interior-edge terms of every element,
- *   S[j][p][e] = sum over the local edges q of e that have a neighbour of
- *                int_E F_j phi_ep ds,
+/* Device: the edge terms of every element,
+ *   S[j][p][e] = sum over the local edges q of e that have an exterior
+ *                state of int_E F_j phi_ep ds,
  * with the Lax-Friedrichs flux F = (A(c-, u-) n + A(c+, u+) n) / 2
  * + lambda_E (c- - c+) / 2 (the paper cites Lax-Friedrichs without fixing
  * the wave speed; here lambda_E = max over both sides of |u_mean . n| +
  * sqrt(g H_mean), element means, constant on the edge), n the unit outward
  * normal, the flux tensor and basis of dg_volume_integrals, evaluated
  * algebraically with the table of dg_edge_integrals (on the device).
- * nbr[q ne + e] is the element across local edge q (-1: domain boundary,
- * skipped), nq[q ne + e] its local index of that edge; both int32 device
- * arrays (an index outside [0, ne) or 0..2 is taken as boundary).  Other arrays as dg_volume_integrals; out (3K x ne).  Elements must
- * be counter-clockwise (det B_e > 0) and the mesh conforming.  Status codes
- * as dg_volume_integrals. */
+ * nbr[q ne + e] names the exterior side of local edge q (int32, device):
+ *   f in [0, ne)   the element across the edge, nq[q ne + e] its local
+ *                  index of that edge (0..2);
+ *   -2 - b         a prescribed (Dirichlet) state, b in [0, nb): the
+ *                  polynomials cb[(j K + i) nb + b] (xi, U, V) and
+ *                  ub[(j K + i) nb + b] (u, v) in the basis of element e,
+ *                  whose traces on the edge are the exterior values; the
+ *                  exterior bathymetry is e's own;
+ *   anything else  no term (e.g. -1 on a boundary left open).
+ * Other arrays as dg_volume_integrals; out (3K x ne).  nb = 0 allows NULL
+ * cb and ub.  Elements must be counter-clockwise (det B_e > 0) and the mesh
+ * conforming.  Status codes as dg_volume_integrals (MG_EINVAL also for
+ * nb < 0, nb above 2^31 - 1, or nb > 0 with a NULL cb or ub). */
 int dg_edge_terms(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
-                  const int* nbr, const int* nq, double g, const double* table, double* out, void* stream);
+                  const int* nbr, const int* nq, long long nb, const double* cb, const double* ub, double g,
+                  const double* table, double* out, void* stream);
+
+/* Device: the right-hand side of the semi-discrete system (the paper's
+ * variational_disc_1 with the source r(c) of eq:def_r and a body force;
+ * with the orthonormal basis the mass matrix is the identity):
+ *   out = dc/dt = E - S + R + F,
+ * E as dg_volume_integrals, S as dg_edge_terms (same nbr, nq, nb, cb, ub),
+ * R[j][p][e] = (r(c), phi_ep e_j) with r = (0, -tau U + fc V + g xi dh_b/dx1,
+ * -tau V - fc U + g xi dh_b/dx2) (tau_bf and f_c constants), and F
+ * (3K x ne, the coefficients of the body force's L2 projection; NULL for
+ * none).  ref is the table of dg_reference_integrals (its three-function
+ * part also gives the bathymetry source), table that of dg_edge_integrals,
+ * both on the device.  out must not alias an input.  Status codes as
+ * dg_edge_terms. */
+int dg_rhs(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
+           const int* nbr, const int* nq, long long nb, const double* cb, const double* ub, double g, double tau,
+           double fc, const double* F, const double* ref, const double* table, double* out, void* stream);
+
+/* Device: one step of length dt of the three-stage strong-stability-
+ * preserving Runge-Kutta method of Shu and Osher (the paper names no
+ * integrator):
+ *   c1 = c + dt L(c),  c2 = 3/4 c + 1/4 (c1 + dt L(c1)),
+ *   c3 = 1/3 c + 2/3 (c2 + dt L(c2)),
+ * L the right-hand side of dg_rhs, the velocity u first projected from each
+ * stage state (dg_velocity_projection).  Stage s = 0, 1, 2 is at time
+ * t + (0, 1, 1/2)[s] dt; its body force is F3 + s 3K ne (F3 NULL: none) and
+ * its prescribed states cb3 + s 3K nb and ub3 + s 2K nb.  c (3K x ne) is
+ * advanced in place; u (2K x ne) is left holding the velocity of the last
+ * stage's state; work is caller-owned device scratch of 6K ne doubles.
+ * Needs the tables of dg_reference_integrals (ref), dg_product_integrals
+ * (T) and dg_edge_integrals (table) on the device.  Enqueued on stream;
+ * status codes as dg_rhs (MG_EINVAL also for a non-finite dt). */
+int dg_ssp_rk3_step(int k, long long ne, double* c, double* u, double* work, const double* B, const double* hb,
+                    const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3, double g,
+                    double tau, double fc, const double* F3, const double* ref, const double* T,
+                    const double* table, double dt, void* stream);
 
 #ifdef __cplusplus
 }

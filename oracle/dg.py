@@ -20,10 +20,13 @@ Conventions (readings):
 * Flux tensor rows (with H = xi + h_b):
   (U, V), (U u + g xi (H + h_b) / 2, U v), (V u, V v + g xi (H + h_b) / 2);
   c = (xi, U, V) and u = (u, v) are DG fields with K(k) coefficients each,
-  and so is the bathymetry h_b (a P^k field on every element: the paper's
-  algebraic form, which takes h_b out of the integral, is the case of a
-  field with only the constant mode; a linear h_b, as in the convergence
-  test of Sec. 3.1, is represented exactly for k >= 1).
+  and the bathymetry h_b is one of order max(k, 1) (KB(k) = 3, 3, 6, 10
+  coefficients): the paper's algebraic form, which takes h_b out of the
+  integral, is the case of a field with only the constant mode, and a
+  linear h_b (the convergence test of Sec. 3.1) is exact for every k.  At
+  k = 0 a piecewise-constant h_b would not do: the pressure flux jumps with
+  h_b across the edges while g xi grad h_b vanishes inside the elements, an
+  O(1) force wherever xi != 0.
 * Output E[j, p] = (A~, grad(phi_ep e_j))_{Omega_e}, j = 1, 2, 3.
 * The semi-discrete system (the paper's variational_disc_1 with the source
   r(c) of eq:def_r and a body force): with the orthonormal element basis the
@@ -40,6 +43,7 @@ import math
 import numpy as np
 
 K_OF = {0: 1, 1: 3, 2: 6, 3: 10}
+KB_OF = {0: 3, 1: 3, 2: 6, 3: 10}     # coefficients of the bathymetry
 
 
 def basis(x, y):
@@ -121,8 +125,8 @@ def constant_field(k: int, value: float, B: np.ndarray) -> np.ndarray:
 
 def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: np.ndarray, g: float) -> np.ndarray:
     """E[j, p] for one element: c (3, K) and u (2, K) coefficients, B (2, 2),
-    bathymetry coefficients hb (K,), gravity g.  Quadrature on the physical
-    element."""
+    bathymetry coefficients hb (any number of them, up to 10), gravity g.
+    Quadrature on the physical element."""
     K = K_OF[k]
     X, Y, Wt = triangle_rule()
     phi = np.array(basis(X, Y))[:K]                  # (K, Q)
@@ -137,7 +141,7 @@ def volume_integrals(k: int, c: np.ndarray, u: np.ndarray, B: np.ndarray, hb: np
     ph = sc * phi
     xi, U, V = (c[j] @ ph for j in range(3))         # field values at the points
     uu, vv = (u[j] @ ph for j in range(2))
-    hbv = hb @ ph
+    hbv = hb @ (sc * np.array(basis(X, Y))[:len(hb)])
     pres = 0.5 * g * xi * ((xi + hbv) + hbv)
     A = [(U, V), (U * uu + pres, U * vv), (V * uu, V * vv + pres)]
     w = Wt * abs(det)
@@ -158,7 +162,7 @@ def velocity_projection(k: int, c: np.ndarray, B: np.ndarray, hb: np.ndarray) ->
     det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
     ph = abs(det) ** -0.5 * np.array(basis(X, Y))[:K]
     w = Wt * abs(det)
-    H = c[0] @ ph + hb @ ph
+    H = c[0] @ ph + hb @ (abs(det) ** -0.5 * np.array(basis(X, Y))[:len(hb)])
     M = (ph * (w * H)) @ ph.T
     rhs = np.stack([(ph * (w * (c[j] @ ph))).sum(axis=1) for j in (1, 2)], axis=1)
     return np.linalg.solve(M, rhs).T
@@ -178,7 +182,7 @@ def eval_fields(k: int, coef: np.ndarray, B: np.ndarray, rel: np.ndarray) -> np.
     """Values of the fields with coefficients coef (nf, K) on the element
     with map B at the points rel (P, 2), given relative to the element's
     first vertex (relative coordinates keep small elements accurate)."""
-    K = K_OF[k]
+    K = coef.shape[1]              # the fields' own number of coefficients
     det = B[0, 0] * B[1, 1] - B[0, 1] * B[1, 0]
     ref = np.linalg.solve(B, rel.T)
     ph = abs(det) ** -0.5 * np.array(basis(ref[0], ref[1]))[:K]
@@ -236,8 +240,9 @@ def edge_integrals_lf(k, own, nbrs, g):
         L = math.hypot(d[0], d[1])
         n = np.array([d[1], -d[0]]) / L
         pts = p0[None, :] + s[:, None] * d[None, :]
-        fm = eval_fields(k, np.vstack([c, u, hb[None, :]]), B, pts)
-        fp = eval_fields(k, np.vstack([cn, un, hbn[None, :]]), Bn, (a1 - a1n)[None, :] + pts)
+        fm = np.vstack([eval_fields(k, np.vstack([c, u]), B, pts), eval_fields(k, hb[None, :], B, pts)])
+        fp = np.vstack([eval_fields(k, np.vstack([cn, un]), Bn, (a1 - a1n)[None, :] + pts),
+                        eval_fields(k, hbn[None, :], Bn, (a1 - a1n)[None, :] + pts)])
         um, Hm = mean_state(k, c, u, B, hb)
         up, Hp = mean_state(k, cn, un, Bn, hbn)
         lam = max(abs(um @ n) + math.sqrt(g * Hm), abs(up @ n) + math.sqrt(g * Hp))
@@ -268,7 +273,10 @@ def source_integrals(k: int, c: np.ndarray, B: np.ndarray, hb: np.ndarray, g: fl
     dx1 = sc * (Binv[0, 0] * np.array(gx)[:K] + Binv[1, 0] * np.array(gy)[:K])
     dx2 = sc * (Binv[0, 1] * np.array(gx)[:K] + Binv[1, 1] * np.array(gy)[:K])
     xi, U, V = (c[j] @ ph for j in range(3))
-    hx, hy = hb @ dx1, hb @ dx2
+    nb_ = len(hb)
+    bx = sc * (Binv[0, 0] * np.array(gx)[:nb_] + Binv[1, 0] * np.array(gy)[:nb_])
+    by = sc * (Binv[0, 1] * np.array(gx)[:nb_] + Binv[1, 1] * np.array(gy)[:nb_])
+    hx, hy = hb @ bx, hb @ by
     r = [0.0 * xi, -tau * U + fc * V + g * xi * hx, -tau * V - fc * U + g * xi * hy]
     w = Wt * abs(det)
     return np.array([(ph * (w * r[j])).sum(axis=1) for j in range(3)])
@@ -280,7 +288,7 @@ def mesh_rhs(k: int, B: np.ndarray, a1: np.ndarray, nbr: np.ndarray, c: np.ndarr
     rows B11, B12, B21, B22; a1 (2, ne) first vertices; nbr (3, ne) the
     element across each local edge, -1 for no term and -2 - b for the
     prescribed exterior state b (cb (3K, nb), ub (2K, nb)); c (3K, ne), u
-    (2K, ne), hb (K, ne) coefficients; F (3K, ne) or None.  Returns (3K, ne)."""
+    (2K, ne), hb (KB, ne) coefficients; F (3K, ne) or None.  Returns (3K, ne)."""
     K = K_OF[k]
     ne = B.shape[1]
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "dg.h"
@@ -84,6 +85,13 @@ double integrate(const Poly& a, long long scale) {
 
 int k_of(int k) { return k == 0 ? 1 : k == 1 ? 3 : k == 2 ? 6 : k == 3 ? 10 : 0; }
 
+// Coefficients of the bathymetry, and the order of the reference and edge
+// tables: max(k, 1), so that a linear h_b is exact at every order.
+int kb_of(int k) { return k == 0 ? 3 : k_of(k); }
+
+template <int K>
+constexpr int kb_const() { return K == 1 ? 3 : K; }
+
 // ------------------------------------------------------------ edge tables
 // Polynomials in the edge parameter s with integer coefficients.
 constexpr int kDeg1 = 10;
@@ -139,22 +147,28 @@ double integrate1(const Poly1& a, long long scale) {
     return (double)num / 2520.0 * std::sqrt((double)scale);
 }
 
-// One thread per element: for every test function p the two-function terms
-// (mass flux and bathymetry) and, per i, the sums over m of the
-// three-function integrals, contracted with the coefficients of i.  The
-// velocity enters the advective terms only through
+// One thread per element: for every test function p the mass flux and, per
+// i, the sums over m of the three-function integrals, contracted with the
+// coefficients of i.  The velocity enters the advective terms only through
 // u d/dx1 + v d/dx2 = (1/det) [(B22 u - B12 v) d/dx^1 + (B11 v - B21 u) d/dx^2],
 // so the element's map is folded into two combined velocity vectors first
-// and each (p, i) costs four multiply-adds per m.
-template <int K>
+// and each (p, i) costs four multiply-adds per m.  The pressure term
+// g xi (H + h_b) / 2 = g xi (xi + 2 h_b) / 2 is one product of two P^k
+// fields.  With RHS the source (g xi grad h_b, friction, Coriolis) and the
+// body force are added: out = E + R + F.
+template <int K, bool RHS>
 __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* __restrict__ c,
                                                    const double* __restrict__ u, const double* __restrict__ B,
                                                    const double* __restrict__ hb, double g,
-                                                   const double* __restrict__ ref, double* __restrict__ out) {
+                                                   const double* __restrict__ ref, double* __restrict__ out,
+                                                   double tau, double fc, const double* __restrict__ F) {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= ne) return;
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
-    double xi[K], U[K], V[K], wa[K], wb[K];
+    constexpr int KT = kb_const<K>();                    // table order and bathymetry coefficients
+    double xi[K], U[K], V[K], wa[K], wb[K], w[K], hv[KT];
+#pragma unroll
+    for (int i = 0; i < KT; ++i) hv[i] = hb[(long long)i * ne + e];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         xi[i] = c[(long long)i * ne + e];
@@ -163,41 +177,66 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
         const double uu = u[(long long)i * ne + e], vv = u[(long long)(K + i) * ne + e];
         wa[i] = b22 * uu - b12 * vv;
         wb[i] = b11 * vv - b21 * uu;
+        w[i] = xi[i] + 2.0 * hv[i];
     }
     const double det = b11 * b22 - b12 * b21;
     const double s2 = 1.0 / det;                         // two-function integrals
     const double s3 = s2 / std::sqrt(std::fabs(det));    // three-function integrals
-    const double gh = g * hb[e];
+    // (for k = 0 the gradient of the one test function vanishes and only
+    // the source remains; the h_b products there need the order-1 table)
     const double* G0 = ref;
-    const double* G1 = ref + K * K;
-    const double* H0 = ref + 2 * K * K;
-    const double* H1 = H0 + K * K * K;
+    const double* G1 = ref + KT * KT;
+    const double* H0 = ref + 2 * KT * KT;
+    const double* H1 = H0 + KT * KT * KT;
     for (int p = 0; p < K; ++p) {
-        double e1 = 0.0, l2 = 0.0, l3 = 0.0, e2 = 0.0, e3 = 0.0;
+        double e1 = 0.0, e2 = 0.0, e3 = 0.0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const double gx = G0[p * K + i], gy = G1[p * K + i];
+            const double gx = G0[p * KT + i], gy = G1[p * KT + i];
             const double d1 = b22 * gx - b21 * gy;       // x1-derivative direction
             const double d2 = b11 * gy - b12 * gx;       // x2-derivative direction
             e1 += U[i] * d1 + V[i] * d2;
-            l2 += xi[i] * d1;
-            l3 += xi[i] * d2;
             double t = 0.0, h0x = 0.0, h1x = 0.0;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const double h0 = H0[(p * K + i) * K + m], h1 = H1[(p * K + i) * K + m];
+                const double h0 = H0[(p * KT + i) * KT + m], h1 = H1[(p * KT + i) * KT + m];
                 t += h0 * wa[m] + h1 * wb[m];
-                h0x += h0 * xi[m];
-                h1x += h1 * xi[m];
+                h0x += h0 * w[m];
+                h1x += h1 * w[m];
             }
-            // sums over m of xi_m dx1(.) and xi_m dx2(.) (times det)
+            // sums over m of w_m dx1(.) and w_m dx2(.) (times det)
             const double px = b22 * h0x - b21 * h1x, py = b11 * h1x - b12 * h0x;
             e2 += U[i] * t + 0.5 * g * xi[i] * px;
             e3 += V[i] * t + 0.5 * g * xi[i] * py;
         }
-        out[(long long)p * ne + e] = e1 * s2;
-        out[(long long)(K + p) * ne + e] = e2 * s3 + gh * l2 * s2;
-        out[(long long)(2 * K + p) * ne + e] = e3 * s3 + gh * l3 * s2;
+        double o1 = e1 * s2, o2 = e2 * s3, o3 = e3 * s3;
+        if constexpr (RHS) {
+            // (g xi dh_b/dx_l, phi_p): the three-function integrals with the
+            // derivative on h_b's function m
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int m = 0; m < KT; ++m) {
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    a0 += xi[i] * H0[(m * KT + p) * KT + i];
+                    a1 += xi[i] * H1[(m * KT + p) * KT + i];
+                }
+                sx += hv[m] * a0;
+                sy += hv[m] * a1;
+            }
+            const double Up = c[(long long)(K + p) * ne + e], Vp = c[(long long)(2 * K + p) * ne + e];
+            o2 += g * s3 * (b22 * sx - b21 * sy) + (fc * Vp - tau * Up);
+            o3 += g * s3 * (b11 * sy - b12 * sx) - (fc * Up + tau * Vp);
+            if (F) {
+                o1 += F[(long long)p * ne + e];
+                o2 += F[(long long)(K + p) * ne + e];
+                o3 += F[(long long)(2 * K + p) * ne + e];
+            }
+        }
+        out[(long long)p * ne + e] = o1;
+        out[(long long)(K + p) * ne + e] = o2;
+        out[(long long)(2 * K + p) * ne + e] = o3;
     }
 }
 
@@ -217,12 +256,11 @@ __global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* 
     double L[NL];                                           // row-major lower triangle
 #pragma unroll
     for (int q = 0; q < NL; ++q) L[q] = 0.0;
-    // one coefficient of H at a time (a rolled loop keeps the table's scalar
-    // operands of one step live, not all K^3 of them)
+    // one coefficient of H = xi + h_b at a time (a rolled loop keeps the
+    // table's scalar operands of one step live, not all K^3 of them)
 #pragma unroll 1
     for (int i = 0; i < K; ++i) {
-        double h = c[(long long)i * ne + e];
-        if (i == 0) h += hb[e] * std::sqrt(ad) * 0.70710678118654752440;   // h_b = (h_b sqrt|det| / sqrt 2) phi_e1
+        const double h = c[(long long)i * ne + e] + hb[(long long)i * ne + e];
         const double* Ti = T + i * K;
 #pragma unroll
         for (int p = 0; p < K; ++p)
@@ -268,85 +306,110 @@ __global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* 
     }
 }
 
-// Interior-edge terms: one thread per element, edges in turn; for each edge
-// the neighbour's coefficients are gathered and both sides' contributions to
-// every test function p are added to out.  The table offsets depend on the
-// neighbour's local edge index q'; lanes of a wavefront are served one q'
-// value at a time so that the table is always read at a wave-uniform address.
-template <int K>
+// Edge terms: one thread per element, edges in turn; for each edge the
+// exterior state (a neighbour's coefficients, or a prescribed polynomial in
+// the element's own basis on a Dirichlet edge) is gathered and both sides'
+// contributions to every test function p are added to out (SUB: subtracted
+// from what out holds).  The table offsets depend on the kind of the
+// exterior side (the neighbour's local edge index q', or 3 for a prescribed
+// state, which uses the element's own edge tables); lanes of a wavefront are
+// served one kind at a time so that the table is always read at a
+// wave-uniform address.
+template <int K, bool SUB>
 __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __restrict__ c,
                                                   const double* __restrict__ u, const double* __restrict__ B,
                                                   const double* __restrict__ hb, const int* __restrict__ nbr,
-                                                  const int* __restrict__ nq, double g,
-                                                  const double* __restrict__ tab, double* __restrict__ out) {
+                                                  const int* __restrict__ nq, long long nb,
+                                                  const double* __restrict__ cb, const double* __restrict__ ub,
+                                                  double g, const double* __restrict__ tab,
+                                                  double* __restrict__ out) {
     const long long e0 = (long long)blockIdx.x * 256 + threadIdx.x;
     const bool live = e0 < ne;
     const long long e = live ? e0 : 0;     // lanes past the end compute nothing but join the ballots
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
     const double adet = std::fabs(b11 * b22 - b12 * b21);
     const double a = 1.0 / std::sqrt(adet);
-    const double hm = hb[e];
-    double xi[K], U[K], V[K];
+    constexpr int KT = kb_const<K>();                    // table order and bathymetry coefficients
+    double xi[K], U[K], V[K], w[KT];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         xi[i] = c[(long long)i * ne + e];
         U[i] = c[(long long)(K + i) * ne + e];
         V[i] = c[(long long)(2 * K + i) * ne + e];
     }
+    // xi + 2 h_b, the second factor of the pressure term
+#pragma unroll
+    for (int i = 0; i < KT; ++i) w[i] = (i < K ? xi[i] : 0.0) + 2.0 * hb[(long long)i * ne + e];
     const double v1 = std::sqrt(2.0 / adet);                       // value of phi_e1
-    const double umx = u[e] * v1, umy = u[(long long)K * ne + e] * v1, Hm = xi[0] * v1 + hm;
-    if (live)
+    const double umx = u[e] * v1, umy = u[(long long)K * ne + e] * v1, Hm = (xi[0] + hb[e]) * v1;
+    if (!SUB && live)
         for (int t = 0; t < 3 * K; ++t) out[(long long)t * ne + e] = 0.0;
+    const double sg = SUB ? -1.0 : 1.0;
     const double* O2 = tab;
-    const double* O3 = tab + 3 * K * K;
-    const double* N2 = tab + 3 * K * K + 3 * K * K * K;
-    const double* N3 = tab + 12 * K * K + 3 * K * K * K;
+    const double* O3 = tab + 3 * KT * KT;
+    const double* N2 = tab + 3 * KT * KT + 3 * KT * KT * KT;
+    const double* N3 = tab + 12 * KT * KT + 3 * KT * KT * KT;
     for (int q = 0; q < 3; ++q) {
         const double dx = q == 0 ? b11 : (q == 1 ? b12 - b11 : -b12);
         const double dy = q == 0 ? b21 : (q == 1 ? b22 - b21 : -b22);
         const double L = std::sqrt(dx * dx + dy * dy);
         const double n1 = dy / L, n2 = -dx / L;
-        // an index outside [0, ne) or a local edge outside 0..2 counts as boundary
+        // kind 0..2: a neighbour, across its local edge kind; 3: a prescribed
+        // state; anything out of range: no term
         const int fr = live ? nbr[(long long)q * ne + e] : -1;
-        const int qr = fr >= 0 ? nq[(long long)q * ne + e] : -1;
-        const bool ok = fr >= 0 && (long long)fr < ne && qr >= 0 && qr <= 2;
-        const int f = ok ? fr : 0, qp = ok ? qr : -1;
-        bool todo = ok;
+        int kind = -1;
+        long long f = 0;
+        if (fr >= 0) {
+            const int qr = nq[(long long)q * ne + e];
+            if ((long long)fr < ne && qr >= 0 && qr <= 2) {
+                kind = qr;
+                f = fr;
+            }
+        } else if (fr <= -2 && cb && ub && (long long)(-2 - (long long)fr) < nb) {
+            kind = 3;
+            f = -2 - (long long)fr;
+        }
+        bool todo = kind >= 0;
         for (;;) {
             const unsigned long long mask = __ballot(todo);
             if (mask == 0) break;
-            const int qs = __builtin_amdgcn_readfirstlane(__shfl(qp, __ffsll((long long)mask) - 1));
-            if (!(todo && qp == qs)) continue;
+            const int ks = __builtin_amdgcn_readfirstlane(__shfl(kind, __ffsll((long long)mask) - 1));
+            if (!(todo && kind == ks)) continue;
             todo = false;
-            // the neighbour
-            const double c11 = B[f], c12 = B[ne + f], c21 = B[2 * ne + f], c22 = B[3 * ne + f];
+            const bool ghost = ks == 3;                  // wave-uniform
+            const double* cs = ghost ? cb : c;
+            const double* us = ghost ? ub : u;
+            const long long st = ghost ? nb : ne;
+            const long long fg = ghost ? e : f;          // geometry and bathymetry of the exterior side
+            const double c11 = B[fg], c12 = B[ne + fg], c21 = B[2 * ne + fg], c22 = B[3 * ne + fg];
             const double fdet = std::fabs(c11 * c22 - c12 * c21);
             const double bsc = 1.0 / std::sqrt(fdet);
             const double w1 = std::sqrt(2.0 / fdet);
-            double xo[K], Uo[K], Vo[K], wn[K], wo[K];
+            double xo[K], Uo[K], Vo[K], wx[KT], wn[K], wo[K];
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                xo[i] = c[(long long)i * ne + f];
-                Uo[i] = c[(long long)(K + i) * ne + f];
-                Vo[i] = c[(long long)(2 * K + i) * ne + f];
-                wo[i] = u[(long long)i * ne + f] * n1 + u[(long long)(K + i) * ne + f] * n2;
+                xo[i] = cs[(long long)i * st + f];
+                Uo[i] = cs[(long long)(K + i) * st + f];
+                Vo[i] = cs[(long long)(2 * K + i) * st + f];
+                wo[i] = us[(long long)i * st + f] * n1 + us[(long long)(K + i) * st + f] * n2;
                 wn[i] = u[(long long)i * ne + e] * n1 + u[(long long)(K + i) * ne + e] * n2;
             }
-            const double hp = hb[f];
-            const double Hp = xo[0] * w1 + hp;
+#pragma unroll
+            for (int i = 0; i < KT; ++i) wx[i] = (i < K ? xo[i] : 0.0) + 2.0 * hb[(long long)i * ne + fg];
+            const double Hp = (xo[0] + hb[fg]) * w1;
             const double lam = fmax(std::fabs(umx * n1 + umy * n2) + std::sqrt(g * Hm),
-                                    std::fabs((u[f] * n1 + u[(long long)K * ne + f] * n2) * w1) + std::sqrt(g * Hp));
-            const double* o2 = O2 + q * K * K;
-            const double* o3 = O3 + q * K * K * K;
-            const double* m2 = N2 + (q * 3 + qs) * K * K;
-            const double* m3 = N3 + (q * 3 + qs) * K * K * K;
+                                    std::fabs((us[f] * n1 + us[(long long)K * st + f] * n2) * w1) + std::sqrt(g * Hp));
+            const double* o2 = O2 + q * KT * KT;
+            const double* o3 = O3 + q * KT * KT * KT;
+            const double* m2 = ghost ? o2 : N2 + (q * 3 + ks) * KT * KT;
+            const double* m3 = ghost ? o3 : N3 + (q * 3 + ks) * KT * KT * KT;
             const double aa = a * a, aaa = aa * a, ab = a * bsc, abb = ab * bsc;
             for (int p = 0; p < K; ++p) {
                 double jX = 0.0, jU = 0.0, jV = 0.0, kX = 0.0, kU = 0.0, kV = 0.0;
                 double r2o = 0.0, r3o = 0.0, r2n = 0.0, r3n = 0.0;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
-                    const double t2 = o2[p * K + i], s2 = m2[p * K + i];
+                    const double t2 = o2[p * KT + i], s2 = m2[p * KT + i];
                     jX += xi[i] * t2;
                     jU += U[i] * t2;
                     jV += V[i] * t2;
@@ -355,12 +418,14 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
                     kV += Vo[i] * s2;
                     double sw = 0.0, sx = 0.0, tw = 0.0, tx = 0.0;
 #pragma unroll
-                    for (int m = 0; m < K; ++m) {
-                        const double t3 = o3[(p * K + i) * K + m], s3 = m3[(p * K + i) * K + m];
-                        sw += t3 * wn[m];
-                        sx += t3 * xi[m];
-                        tw += s3 * wo[m];
-                        tx += s3 * xo[m];
+                    for (int m = 0; m < KT; ++m) {
+                        const double t3 = o3[(p * KT + i) * KT + m], s3 = m3[(p * KT + i) * KT + m];
+                        if (m < K) {
+                            sw += t3 * wn[m];
+                            tw += s3 * wo[m];
+                        }
+                        sx += t3 * w[m];
+                        tx += s3 * wx[m];
                     }
                     r2o += U[i] * sw + 0.5 * g * n1 * xi[i] * sx;
                     r3o += V[i] * sw + 0.5 * g * n2 * xi[i] * sx;
@@ -368,33 +433,141 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
                     r3n += Vo[i] * tw + 0.5 * g * n2 * xo[i] * tx;
                 }
                 const double own1 = aa * (n1 * jU + n2 * jV);
-                const double own2 = aaa * r2o + aa * g * hm * n1 * jX;
-                const double own3 = aaa * r3o + aa * g * hm * n2 * jX;
+                const double own2 = aaa * r2o;
+                const double own3 = aaa * r3o;
                 const double nb1 = ab * (n1 * kU + n2 * kV);
-                const double nb2 = abb * r2n + ab * g * hp * n1 * kX;
-                const double nb3 = abb * r3n + ab * g * hp * n2 * kX;
+                const double nb2 = abb * r2n;
+                const double nb3 = abb * r3n;
                 const double s1v = L * (0.5 * (own1 + nb1) + 0.5 * lam * (aa * jX - ab * kX));
                 const double s2v = L * (0.5 * (own2 + nb2) + 0.5 * lam * (aa * jU - ab * kU));
                 const double s3v = L * (0.5 * (own3 + nb3) + 0.5 * lam * (aa * jV - ab * kV));
-                out[(long long)p * ne + e] += s1v;
-                out[(long long)(K + p) * ne + e] += s2v;
-                out[(long long)(2 * K + p) * ne + e] += s3v;
+                out[(long long)p * ne + e] += sg * s1v;
+                out[(long long)(K + p) * ne + e] += sg * s2v;
+                out[(long long)(2 * K + p) * ne + e] += sg * s3v;
             }
         }
     }
+}
+
+// One stage of the Runge-Kutta combination: y = a x + b (y + dt r).
+__global__ __launch_bounds__(256) void k_dg_stage(long long n, double a, const double* __restrict__ x, double b,
+                                                  double* __restrict__ y, double dt, const double* __restrict__ r) {
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        y[i] = a * x[i] + b * (y[i] + dt * r[i]);
+}
+
+bool dg_size_ok(long long ne) { return ne >= 0 && ne <= 256LL * 0x7fffffffLL; }
+
+// The reason of the last MG_EDEVICE of this thread (dg_last_error).
+thread_local char g_dg_error[160] = "";
+
+int dg_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return MG_OK;
+    snprintf(g_dg_error, sizeof g_dg_error, "%s: %s", what, hipGetErrorName(e));
+    return MG_EDEVICE;
+}
+
+// A device entry point starts from a clear error status: hipGetLastError
+// also reports what an earlier call of another library left pending, which
+// must not be taken for a failure of this entry point's launches.
+void dg_begin() {
+    (void)hipGetLastError();
+    g_dg_error[0] = 0;
+}
+
+int launch_volume(int K, bool rhs, long long ne, const double* c, const double* u, const double* B, const double* hb,
+                  double g, const double* ref, double* out, double tau, double fc, const double* F, hipStream_t st) {
+    const unsigned nbk = (unsigned)((ne + 255) / 256);
+#define DG_VOL(KK)                                                                                         \
+    if (rhs)                                                                                               \
+        k_dg_volume<KK, true><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F);             \
+    else                                                                                                   \
+        k_dg_volume<KK, false><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F);
+    switch (K) {
+        case 1: DG_VOL(1) break;
+        case 3: DG_VOL(3) break;
+        case 6: DG_VOL(6) break;
+        default: DG_VOL(10) break;
+    }
+#undef DG_VOL
+    return dg_status(hipGetLastError(), "volume kernel launch");
+}
+
+int launch_edges(int K, bool sub, long long ne, const double* c, const double* u, const double* B, const double* hb,
+                 const int* nbr, const int* nq, long long nb, const double* cb, const double* ub, double g,
+                 const double* table, double* out, hipStream_t st) {
+    const unsigned nbk = (unsigned)((ne + 255) / 256);
+#define DG_EDGE(KK)                                                                                          \
+    if (sub)                                                                                                 \
+        k_dg_edges<KK, true><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, nbr, nq, nb, cb, ub, g, table, out);    \
+    else                                                                                                     \
+        k_dg_edges<KK, false><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, nbr, nq, nb, cb, ub, g, table, out);
+    switch (K) {
+        case 1: DG_EDGE(1) break;
+        case 3: DG_EDGE(3) break;
+        case 6: DG_EDGE(6) break;
+        default: DG_EDGE(10) break;
+    }
+#undef DG_EDGE
+    return dg_status(hipGetLastError(), "edge kernel launch");
+}
+
+int launch_project(int K, long long ne, const double* c, const double* B, const double* hb, const double* T,
+                   double* u, hipStream_t st) {
+    const unsigned nbk = (unsigned)((ne + 255) / 256);
+    switch (K) {
+        case 1: k_dg_project<1><<<nbk, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+        case 3: k_dg_project<3><<<nbk, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+        case 6: k_dg_project<6><<<nbk, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+        default: k_dg_project<10><<<nbk, 256, 0, st>>>(ne, c, B, hb, T, u); break;
+    }
+    return dg_status(hipGetLastError(), "projection kernel launch");
+}
+
+int launch_stage(long long n, double a, const double* x, double b, double* y, double dt, const double* r,
+                 hipStream_t st) {
+    const long long want = (n + 255) / 256;
+    const unsigned nbk = (unsigned)(want < 65536 ? want : 65536);
+    k_dg_stage<<<nbk, 256, 0, st>>>(n, a, x, b, y, dt, r);
+    return dg_status(hipGetLastError(), "stage kernel launch");
+}
+
+// the edge arguments: a prescribed-state count needs both state arrays
+bool ghosts_ok(long long nb, const double* cb, const double* ub) {
+    return nb >= 0 && nb <= 0x7fffffffLL && (nb == 0 || (cb && ub));
 }
 
 }  // namespace
 
 extern "C" {
 
+const char* dg_last_error(void) { return g_dg_error; }
+
+int dg_basis_values(int k, long long npts, const double* x, const double* y, double* out) {
+    const int K = k_of(k);
+    if (!K || npts < 0 || (npts > 0 && (!x || !y || !out))) return MG_EINVAL;
+    for (int p = 0; p < K; ++p) {
+        const double sc = std::sqrt((double)kScale[p]);
+        for (long long q = 0; q < npts; ++q) {
+            double v = 0.0;
+            for (int t = 0; t < 10; ++t) {
+                if (kCoef[p][t] == 0.0) continue;
+                v += kCoef[p][t] * std::pow(x[q], kMono[t][0]) * std::pow(y[q], kMono[t][1]);
+            }
+            out[(long long)p * npts + q] = sc * v;
+        }
+    }
+    return MG_OK;
+}
+
 long long dg_reference_size(int k) {
-    const long long K = k_of(k);
+    const long long K = k_of(k) ? kb_of(k) : 0;
     return K ? 2 * K * K + 2 * K * K * K : 0;
 }
 
 int dg_reference_integrals(int k, double* ref) {
-    const int K = k_of(k);
+    const int K = k_of(k) ? kb_of(k) : 0;
     if (!K || !ref) return MG_EINVAL;
     Poly phi[kMaxK], dphi[2][kMaxK];
     for (int p = 0; p < K; ++p) {
@@ -437,27 +610,20 @@ int dg_product_integrals(int k, double* T) {
 int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
                            const double* T, double* u, void* stream) {
     const int K = k_of(k);
-    if (!K || ne < 0 || ne > 256LL * 0x7fffffffLL) return MG_EINVAL;
+    if (!K || !dg_size_ok(ne)) return MG_EINVAL;
     if (ne == 0) return MG_OK;
     if (!c || !B || !hb || !T || !u) return MG_EINVAL;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    const unsigned nb = (unsigned)((ne + 255) / 256);
-    switch (K) {
-        case 1: k_dg_project<1><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
-        case 3: k_dg_project<3><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
-        case 6: k_dg_project<6><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
-        default: k_dg_project<10><<<nb, 256, 0, st>>>(ne, c, B, hb, T, u); break;
-    }
-    return hipGetLastError() == hipSuccess ? MG_OK : MG_EDEVICE;
+    dg_begin();
+    return launch_project(K, ne, c, B, hb, T, u, static_cast<hipStream_t>(stream));
 }
 
 long long dg_edge_table_size(int k) {
-    const long long K = k_of(k);
+    const long long K = k_of(k) ? kb_of(k) : 0;
     return 12 * K * K + 12 * K * K * K;
 }
 
 int dg_edge_integrals(int k, double* table) {
-    const int K = k_of(k);
+    const int K = k_of(k) ? kb_of(k) : 0;
     if (!K || !table) return MG_EINVAL;
     Poly1 own[3][kMaxK], back[3][kMaxK];
     for (int q = 0; q < 3; ++q)
@@ -492,37 +658,70 @@ int dg_edge_integrals(int k, double* table) {
 }
 
 int dg_edge_terms(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
-                  const int* nbr, const int* nq, double g, const double* table, double* out, void* stream) {
+                  const int* nbr, const int* nq, long long nb, const double* cb, const double* ub, double g,
+                  const double* table, double* out, void* stream) {
     const int K = k_of(k);
-    if (!K || ne < 0 || ne > 256LL * 0x7fffffffLL) return MG_EINVAL;
+    if (!K || !dg_size_ok(ne) || !ghosts_ok(nb, cb, ub)) return MG_EINVAL;
     if (ne == 0) return MG_OK;
     if (!c || !u || !B || !hb || !nbr || !nq || !table || !out) return MG_EINVAL;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    const unsigned nb = (unsigned)((ne + 255) / 256);
-    switch (K) {
-        case 1: k_dg_edges<1><<<nb, 256, 0, st>>>(ne, c, u, B, hb, nbr, nq, g, table, out); break;
-        case 3: k_dg_edges<3><<<nb, 256, 0, st>>>(ne, c, u, B, hb, nbr, nq, g, table, out); break;
-        case 6: k_dg_edges<6><<<nb, 256, 0, st>>>(ne, c, u, B, hb, nbr, nq, g, table, out); break;
-        default: k_dg_edges<10><<<nb, 256, 0, st>>>(ne, c, u, B, hb, nbr, nq, g, table, out); break;
-    }
-    return hipGetLastError() == hipSuccess ? MG_OK : MG_EDEVICE;
+    dg_begin();
+    return launch_edges(K, false, ne, c, u, B, hb, nbr, nq, nb, cb, ub, g, table, out,
+                        static_cast<hipStream_t>(stream));
 }
 
 int dg_volume_integrals(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
                         double g, const double* ref, double* out, void* stream) {
     const int K = k_of(k);
-    if (!K || ne < 0 || ne > 256LL * 0x7fffffffLL) return MG_EINVAL;
+    if (!K || !dg_size_ok(ne)) return MG_EINVAL;
     if (ne == 0) return MG_OK;
     if (!c || !u || !B || !hb || !ref || !out) return MG_EINVAL;
+    dg_begin();
+    return launch_volume(K, false, ne, c, u, B, hb, g, ref, out, 0.0, 0.0, nullptr,
+                         static_cast<hipStream_t>(stream));
+}
+
+int dg_rhs(int k, long long ne, const double* c, const double* u, const double* B, const double* hb,
+           const int* nbr, const int* nq, long long nb, const double* cb, const double* ub, double g, double tau,
+           double fc, const double* F, const double* ref, const double* table, double* out, void* stream) {
+    const int K = k_of(k);
+    if (!K || !dg_size_ok(ne) || !ghosts_ok(nb, cb, ub)) return MG_EINVAL;
+    if (ne == 0) return MG_OK;
+    if (!c || !u || !B || !hb || !nbr || !nq || !ref || !table || !out) return MG_EINVAL;
+    dg_begin();
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    const unsigned nb = (unsigned)((ne + 255) / 256);
-    switch (K) {
-        case 1: k_dg_volume<1><<<nb, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out); break;
-        case 3: k_dg_volume<3><<<nb, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out); break;
-        case 6: k_dg_volume<6><<<nb, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out); break;
-        default: k_dg_volume<10><<<nb, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out); break;
+    const int rc = launch_volume(K, true, ne, c, u, B, hb, g, ref, out, tau, fc, F, st);
+    if (rc != MG_OK) return rc;
+    return launch_edges(K, true, ne, c, u, B, hb, nbr, nq, nb, cb, ub, g, table, out, st);
+}
+
+int dg_ssp_rk3_step(int k, long long ne, double* c, double* u, double* work, const double* B, const double* hb,
+                    const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3, double g,
+                    double tau, double fc, const double* F3, const double* ref, const double* T,
+                    const double* table, double dt, void* stream) {
+    const int K = k_of(k);
+    if (!K || !dg_size_ok(ne) || !ghosts_ok(nb, cb3, ub3) || !std::isfinite(dt)) return MG_EINVAL;
+    if (ne == 0) return MG_OK;
+    if (!c || !u || !work || !B || !hb || !nbr || !nq || !ref || !T || !table) return MG_EINVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long n = 3LL * K * ne;
+    double* c0 = work;
+    double* r = work + n;
+    dg_begin();
+    const int cp = dg_status(hipMemcpyAsync(c0, c, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st),
+                             "copy of the state");
+    if (cp != MG_OK) return cp;
+    const double wa[3] = {0.0, 0.75, 1.0 / 3.0}, wb[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int s = 0; s < 3; ++s) {
+        int rc = launch_project(K, ne, c, B, hb, T, u, st);
+        if (rc == MG_OK)
+            rc = launch_volume(K, true, ne, c, u, B, hb, g, ref, r, tau, fc, F3 ? F3 + s * n : nullptr, st);
+        if (rc == MG_OK)
+            rc = launch_edges(K, true, ne, c, u, B, hb, nbr, nq, nb, nb ? cb3 + s * 3LL * K * nb : nullptr,
+                              nb ? ub3 + s * 2LL * K * nb : nullptr, g, table, r, st);
+        if (rc == MG_OK) rc = launch_stage(n, wa[s], c0, wb[s], c, dt, r, st);
+        if (rc != MG_OK) return rc;
     }
-    return hipGetLastError() == hipSuccess ? MG_OK : MG_EDEVICE;
+    return MG_OK;
 }
 
 }  // extern "C"

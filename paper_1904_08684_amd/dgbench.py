@@ -1,21 +1,25 @@
-"""DG element-kernel benchmark: one launch of the quadrature-free volume
-terms, of the velocity projection or of the interior-edge terms over a
-perturbed split-quad mesh, timed with HIP events.
+"""DG benchmark: one launch of the quadrature-free volume terms, of the
+velocity projection or of the edge terms, one evaluation of the whole
+right-hand side, or one SSP-RK3 step, over a perturbed split-quad mesh
+(boundary edges with prescribed exterior states), timed with HIP events.
 
-    python -m paper_1904_08684_amd.dgbench --nx 1024 --k 3 --reps 20 [--op projection|edges]
+    python -m paper_1904_08684_amd.dgbench --nx 1024 --k 3 --reps 20 [--op projection|edges|rhs|step]
 
-Prints one JSON line.  Bytes count the compulsory traffic.  Volume terms:
-five fields, the map and the bathymetry in, three fields out, (5K + 5 + 3K)
-x 8 B per element; flops of the evaluated form, 8 K^3 + 30 K^2 + 15 K per
-element (four multiply-adds per (p, i, m), the two-function terms and the
-set-up).  Projection: three fields, the map and the bathymetry in, two out,
-(3K + 5 + 2K) x 8 B; flops K^2 (K + 1) for the weighted mass matrix,
-K^3 / 3 for its factorisation and 4 K^2 for the two solves.  Edge terms:
-the element's and its three neighbours' fields, maps and bathymetry, the
-neighbour indices in, three fields out ((5K + 5) x 8 + 24 + 3K x 8 B
-compulsory per element, neighbours' data counted once as it is every
-element's own); flops 3 x (8 K^3 + 26 K^2) per element (three edges, four
-multiply-adds per (p, i, m) on each side).
+Prints one JSON line.  Bytes count the compulsory traffic per element (8 B
+a double).  Volume terms: five fields, the map and the bathymetry in, three
+fields out, 5K + 4 + K + 3K doubles; flops of the evaluated form,
+8 K^3 + 30 K^2 + 15 K (four multiply-adds per (p, i, m), the two-function
+terms and the set-up).  Projection: three fields, the map and the
+bathymetry in, two out, 3K + 4 + K + 2K doubles; flops K^2 (K + 1) for the
+weighted mass matrix, K^3 / 3 for its factorisation and 4 K^2 for the two
+solves.  Edge terms: the element's fields, map and bathymetry, the
+neighbour indices (24 B), three fields out (neighbours' data counted once,
+as it is every element's own); flops 3 (8 K^3 + 26 K^2) (three edges, four
+multiply-adds per (p, i, m) on each side).  Right-hand side: both, with the
+edge pass reading back what the volume pass wrote, and the bathymetry
+source (4 K^3 more flops).  Step: three projections and right-hand sides,
+the copy of the state (2 x 3K doubles) and three stage combinations (4 x 3K
+doubles each).
 """
 from __future__ import annotations
 
@@ -28,7 +32,7 @@ def flops_per_element(K: int) -> int:
 
 
 def bytes_per_element(K: int) -> int:
-    return (5 * K + 5 + 3 * K) * 8
+    return (5 * K + 4 + K + 3 * K) * 8
 
 
 def projection_flops(K: int) -> int:
@@ -36,7 +40,7 @@ def projection_flops(K: int) -> int:
 
 
 def projection_bytes(K: int) -> int:
-    return (3 * K + 5 + 2 * K) * 8
+    return (3 * K + 4 + K + 2 * K) * 8
 
 
 def edge_flops(K: int) -> int:
@@ -44,7 +48,23 @@ def edge_flops(K: int) -> int:
 
 
 def edge_bytes(K: int) -> int:
-    return (5 * K + 5) * 8 + 24 + 3 * K * 8
+    return (5 * K + 4 + K) * 8 + 24 + 3 * K * 8
+
+
+def rhs_flops(K: int) -> int:
+    return flops_per_element(K) + 4 * K ** 3 + edge_flops(K)
+
+
+def rhs_bytes(K: int) -> int:
+    return bytes_per_element(K) + edge_bytes(K) + 3 * K * 8
+
+
+def step_flops(K: int) -> int:
+    return 3 * (projection_flops(K) + rhs_flops(K) + 3 * 3 * K)
+
+
+def step_bytes(K: int) -> int:
+    return 3 * (projection_bytes(K) + rhs_bytes(K) + 4 * 3 * K * 8) + 2 * 3 * K * 8
 
 
 def run(nx: int, k: int, reps: int, op: str = "volume"):
@@ -58,8 +78,11 @@ def run(nx: int, k: int, reps: int, op: str = "volume"):
     B = W.dg_mesh(nx, nx)
     ne = B.shape[1]
     c, u, hb = W.dg_fields(K, B)
+    nbr, nq = W.dg_mesh_neighbours(nx, nx)
+    nbr, be, _ = W.dg_boundary_ghosts(nbr)
+    cb, ub, _ = W.dg_fields(K, B[:, be], seed=W.SEED_DG_FIELDS + 1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    c, u, B, hb = dev(c), dev(u), dev(B), dev(hb)
+    c, u, B, hb, nbr, nq, cb, ub = (dev(a) for a in (c, u, B, hb, nbr, nq, cb, ub))
     if op == "volume":
         out = torch.empty((3 * K, ne), dtype=torch.float64, device="cuda")
         kern = mg.DGVolume(k)
@@ -69,13 +92,22 @@ def run(nx: int, k: int, reps: int, op: str = "volume"):
         kern = mg.DGProjection(k)
         call = lambda: kern(c, B, hb, u)
         fl, by = projection_flops(K) * ne, projection_bytes(K) * ne
-    else:
-        nbr, nq = W.dg_mesh_neighbours(nx, nx)
-        nbr, nq = torch.from_numpy(nbr).cuda(), torch.from_numpy(nq).cuda()
+    elif op == "edges":
         out = torch.empty((3 * K, ne), dtype=torch.float64, device="cuda")
         kern = mg.DGEdges(k)
-        call = lambda: kern(c, u, B, hb, nbr, nq, 9.81, out)
+        call = lambda: kern(c, u, B, hb, nbr, nq, 9.81, out, cb, ub)
         fl, by = edge_flops(K) * ne, edge_bytes(K) * ne
+    elif op == "rhs":
+        out = torch.empty((3 * K, ne), dtype=torch.float64, device="cuda")
+        system = mg.DGSystem(k, B, hb, nbr, nq, nb=be.size)
+        call = lambda: system.rhs(c, u, out, cb, ub)
+        fl, by = rhs_flops(K) * ne, rhs_bytes(K) * ne
+    else:
+        # a step of dt small enough for the random fields to stay physical
+        system = mg.DGSystem(k, B, hb, nbr, nq, nb=be.size)
+        cb3, ub3 = cb.expand(3, -1, -1).contiguous(), ub.expand(3, -1, -1).contiguous()
+        call = lambda: system.step(c, u, 1e-6, cb3, ub3)
+        fl, by = step_flops(K) * ne, step_bytes(K) * ne
     call()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -96,7 +128,7 @@ def main(argv=None):
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--op", default="volume", choices=("volume", "projection", "edges"))
+    ap.add_argument("--op", default="volume", choices=("volume", "projection", "edges", "rhs", "step"))
     a = ap.parse_args(argv)
     print(json.dumps(run(a.nx, a.k, a.reps, a.op)), flush=True)
 

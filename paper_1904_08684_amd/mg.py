@@ -19,6 +19,15 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmg.so")
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_1904_08684_amd.build` "
                       "or __graft_entry__.build()")
+# torch's HIP libraries name the runtime libamdhip64.so, this library
+# libamdhip64.so.7: loaded first, this library would pull in the system's
+# runtime and torch then a second copy of its own, whose late start finds no
+# device.  With torch loaded first the dynamic linker resolves this
+# library's dependency to torch's runtime, one runtime for both.
+try:
+    import torch  # noqa: F401
+except ImportError:          # the C-ABI alone, without torch
+    pass
 lib = C.CDLL(_LIB_PATH)
 
 # ------------------------------------------------------------------ constants
@@ -429,6 +438,8 @@ class Server:
 
 # ------------------------------------------- DG volume terms (include/dg.h)
 _dsigs = {
+    "dg_last_error": (C.c_char_p, []),
+    "dg_basis_values": (C.c_int, [C.c_int, C.c_longlong, _D, _D, _D]),
     "dg_reference_size": (C.c_longlong, [C.c_int]),
     "dg_reference_integrals": (C.c_int, [C.c_int, _D]),
     "dg_volume_integrals": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, C.c_double, _P, _P, _P]),
@@ -437,7 +448,12 @@ _dsigs = {
     "dg_velocity_projection": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P]),
     "dg_edge_table_size": (C.c_longlong, [C.c_int]),
     "dg_edge_integrals": (C.c_int, [C.c_int, _D]),
-    "dg_edge_terms": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, C.c_double, _P, _P, _P]),
+    "dg_edge_terms": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, C.c_longlong, _P, _P,
+                                C.c_double, _P, _P, _P]),
+    "dg_rhs": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, C.c_longlong, _P, _P, C.c_double,
+                         C.c_double, C.c_double, _P, _P, _P, _P, _P]),
+    "dg_ssp_rk3_step": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, _P, C.c_longlong, _P, _P,
+                                  C.c_double, C.c_double, C.c_double, _P, _P, _P, _P, C.c_double, _P]),
 }
 for _name, (_res, _args) in _dsigs.items():
     _fn = getattr(lib, _name)
@@ -446,13 +462,32 @@ for _name, (_res, _args) in _dsigs.items():
     globals()[_name] = _fn
 
 DG_K = {0: 1, 1: 3, 2: 6, 3: 10}
+DG_KB = {0: 3, 1: 3, 2: 6, 3: 10}     # bathymetry coefficients; table order max(k, 1)
+
+
+def _dgc(code: int):
+    """Raise MGError for a failed dg_ entry point, with the library's reason."""
+    if code != MG_OK:
+        raise MGError(code, dg_last_error().decode())
+
+
+def dg_basis(k: int, x, y) -> np.ndarray:
+    """Values (K, n) of the reference basis of order k at the points (x, y) (host)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    y = np.ascontiguousarray(y, dtype=np.float64).ravel()
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same size")
+    out = np.empty((DG_K[k], x.size), dtype=np.float64)
+    _dgc(dg_basis_values(k, x.size, x.ctypes.data_as(_D), y.ctypes.data_as(_D), out.ctypes.data_as(_D)))
+    return out
 
 
 def dg_reference(k: int) -> np.ndarray:
-    """The exact reference integrals of order k (host): G (2, K, K), H (2, K, K, K)."""
-    K = DG_K[k]
+    """The exact reference integrals for order k (host), over the first
+    KB = DG_KB[k] basis functions: G (2, KB, KB), H (2, KB, KB, KB)."""
+    K = DG_KB[k]
     ref = np.empty(int(dg_reference_size(k)), dtype=np.float64)
-    _check(dg_reference_integrals(k, ref.ctypes.data_as(_D)))
+    _dgc(dg_reference_integrals(k, ref.ctypes.data_as(_D)))
     return ref[:2 * K * K].reshape(2, K, K), ref[2 * K * K:].reshape(2, K, K, K)
 
 
@@ -460,16 +495,43 @@ def dg_products(k: int) -> np.ndarray:
     """The exact triple-product integrals of order k (host): T (K, K, K)."""
     K = DG_K[k]
     T = np.empty(int(dg_product_size(k)), dtype=np.float64)
-    _check(dg_product_integrals(k, T.ctypes.data_as(_D)))
+    _dgc(dg_product_integrals(k, T.ctypes.data_as(_D)))
     return T.reshape(K, K, K)
 
 
 def _dg_check(tensors, ne):
     import torch
     for t, rows in tensors:
-        shape = (rows, ne) if rows else (ne,)
-        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
-            raise ValueError("expected contiguous FP64 device tensors of shape (rows, ne) / (ne,)")
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (rows, ne):
+            raise ValueError("expected contiguous FP64 device tensors of shape (rows, ne)")
+
+
+def _dg_index(ne, *tensors):
+    import torch
+    for t in tensors:
+        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (3, ne):
+            raise ValueError("nbr and nq must be contiguous int32 device tensors of shape (3, ne)")
+
+
+def _dg_ghosts(K, nb, cb, ub, stages=1):
+    """Pointers of the prescribed exterior states (NULL when nb = 0)."""
+    import torch
+    if nb == 0:
+        return C.c_void_p(None), C.c_void_p(None)
+    want = ((stages, 3 * K, nb), (stages, 2 * K, nb)) if stages > 1 else ((3 * K, nb), (2 * K, nb))
+    for t, shape in zip((cb, ub), want):
+        if t is None or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"expected contiguous FP64 device tensors of shapes {want}")
+    return C.c_void_p(cb.data_ptr()), C.c_void_p(ub.data_ptr())
+
+
+def _ptr(t):
+    return C.c_void_p(None if t is None else t.data_ptr())
+
+
+def _stream(st, dev):
+    import torch
+    return C.c_void_p((st if st is not None else torch.cuda.current_stream(dev)).cuda_stream)
 
 
 class DGProjection:
@@ -477,26 +539,24 @@ class DGProjection:
 
     def __init__(self, k: int, device: str = "cuda"):
         import torch
-        self.k, self.K = k, DG_K[k]
+        self.k, self.K, self.KB = k, DG_K[k], DG_KB[k]
         self.T = torch.from_numpy(dg_products(k).ravel().copy()).to(device)
 
     def __call__(self, c, B, hb, u, stream=None):
-        """c (3K, ne), B (4, ne), hb (ne,) in; u (2K, ne) out."""
-        import torch
-        ne = hb.shape[0]
-        _dg_check(((c, 3 * self.K), (B, 4), (hb, 0), (u, 2 * self.K)), ne)
-        st = stream if stream is not None else torch.cuda.current_stream(hb.device)
-        _check(dg_velocity_projection(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(B.data_ptr()),
-                                      C.c_void_p(hb.data_ptr()), C.c_void_p(self.T.data_ptr()),
-                                      C.c_void_p(u.data_ptr()), C.c_void_p(st.cuda_stream)))
+        """c (3K, ne), B (4, ne), hb (KB, ne) in; u (2K, ne) out."""
+        ne = B.shape[1]
+        _dg_check(((c, 3 * self.K), (B, 4), (hb, self.KB), (u, 2 * self.K)), ne)
+        _dgc(dg_velocity_projection(self.k, ne, _ptr(c), _ptr(B), _ptr(hb), _ptr(self.T), _ptr(u),
+                                      _stream(stream, B.device)))
 
 
 def dg_edge_table(k: int) -> dict:
-    """The exact edge integrals of order k (host), as arrays O2 (3, K, K),
-    O3 (3, K, K, K), N2 (3, 3, K, K), N3 (3, 3, K, K, K)."""
-    K = DG_K[k]
+    """The exact edge integrals for order k (host), over the first KB =
+    DG_KB[k] basis functions, as arrays O2 (3, KB, KB), O3 (3, KB, KB, KB),
+    N2 (3, 3, KB, KB), N3 (3, 3, KB, KB, KB)."""
+    K = DG_KB[k]
     t = np.empty(int(dg_edge_table_size(k)), dtype=np.float64)
-    _check(dg_edge_integrals(k, t.ctypes.data_as(_D)))
+    _dgc(dg_edge_integrals(k, t.ctypes.data_as(_D)))
     o = [0, 3 * K * K, 3 * K ** 3, 9 * K * K, 9 * K ** 3]
     o = np.cumsum(o)
     return {"raw": t, "O2": t[o[0]:o[1]].reshape(3, K, K), "O3": t[o[1]:o[2]].reshape(3, K, K, K),
@@ -504,27 +564,25 @@ def dg_edge_table(k: int) -> dict:
 
 
 class DGEdges:
-    """Interior-edge (Lax-Friedrichs) terms of order k on the GPU."""
+    """Edge (Lax-Friedrichs) terms of order k on the GPU: interior edges and
+    edges with a prescribed exterior state (nbr = -2 - b)."""
 
     def __init__(self, k: int, device: str = "cuda"):
         import torch
-        self.k, self.K = k, DG_K[k]
+        self.k, self.K, self.KB = k, DG_K[k], DG_KB[k]
         self.tab = torch.from_numpy(dg_edge_table(k)["raw"].copy()).to(device)
 
-    def __call__(self, c, u, B, hb, nbr, nq, g: float, out, stream=None):
-        """c (3K, ne), u (2K, ne), B (4, ne), hb (ne,) FP64; nbr, nq (3, ne)
-        int32; out (3K, ne): contiguous device tensors."""
-        import torch
-        ne = hb.shape[0]
-        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, 0), (out, 3 * self.K)), ne)
-        for t in (nbr, nq):
-            if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (3, ne):
-                raise ValueError("nbr and nq must be contiguous int32 device tensors of shape (3, ne)")
-        st = stream if stream is not None else torch.cuda.current_stream(hb.device)
-        _check(dg_edge_terms(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(u.data_ptr()),
-                             C.c_void_p(B.data_ptr()), C.c_void_p(hb.data_ptr()), C.c_void_p(nbr.data_ptr()),
-                             C.c_void_p(nq.data_ptr()), g, C.c_void_p(self.tab.data_ptr()),
-                             C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    def __call__(self, c, u, B, hb, nbr, nq, g: float, out, cb=None, ub=None, stream=None):
+        """c (3K, ne), u (2K, ne), B (4, ne), hb (KB, ne) FP64; nbr, nq (3, ne)
+        int32; out (3K, ne); cb (3K, nb), ub (2K, nb) the prescribed states
+        (None: nb = 0): contiguous device tensors."""
+        ne = B.shape[1]
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, self.KB), (out, 3 * self.K)), ne)
+        _dg_index(ne, nbr, nq)
+        nb = 0 if cb is None else cb.shape[1]
+        pcb, pub = _dg_ghosts(self.K, nb, cb, ub)
+        _dgc(dg_edge_terms(self.k, ne, _ptr(c), _ptr(u), _ptr(B), _ptr(hb), _ptr(nbr), _ptr(nq), nb, pcb, pub,
+                             g, _ptr(self.tab), _ptr(out), _stream(stream, B.device)))
 
 
 class DGVolume:
@@ -532,18 +590,68 @@ class DGVolume:
 
     def __init__(self, k: int, device: str = "cuda"):
         import torch
-        self.k, self.K = k, DG_K[k]
+        self.k, self.K, self.KB = k, DG_K[k], DG_KB[k]
         G, H = dg_reference(k)
         self.ref = torch.from_numpy(np.concatenate([G.ravel(), H.ravel()])).to(device)
 
     def __call__(self, c, u, B, hb, g: float, out, stream=None):
-        """c (3K, ne), u (2K, ne), B (4, ne), hb (ne,), out (3K, ne): contiguous
+        """c (3K, ne), u (2K, ne), B (4, ne), hb (KB, ne), out (3K, ne): contiguous
         FP64 device tensors, element index fastest."""
+        ne = B.shape[1]
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, self.KB), (out, 3 * self.K)), ne)
+        _dgc(dg_volume_integrals(self.k, ne, _ptr(c), _ptr(u), _ptr(B), _ptr(hb), g, _ptr(self.ref), _ptr(out),
+                                   _stream(stream, B.device)))
+
+
+class DGSystem:
+    """The semi-discrete shallow-water system of order k on a fixed mesh, on
+    the GPU: dc/dt = E - S + R + F (dg_rhs) and the SSP-RK3 step
+    (dg_ssp_rk3_step).  B (4, ne), hb (KB, ne) FP64 and nbr, nq (3, ne) int32
+    device tensors; nb prescribed exterior states (nbr = -2 - b)."""
+
+    def __init__(self, k: int, B, hb, nbr, nq, nb: int = 0, g: float = 9.81, tau: float = 0.0,
+                 fc: float = 0.0):
         import torch
-        ne = hb.shape[0]
-        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, 0), (out, 3 * self.K)), ne)
-        st = stream if stream is not None else torch.cuda.current_stream(hb.device)
-        _check(dg_volume_integrals(self.k, ne, C.c_void_p(c.data_ptr()), C.c_void_p(u.data_ptr()),
-                                   C.c_void_p(B.data_ptr()), C.c_void_p(hb.data_ptr()), g,
-                                   C.c_void_p(self.ref.data_ptr()), C.c_void_p(out.data_ptr()),
-                                   C.c_void_p(st.cuda_stream)))
+        self.k, self.K, self.KB = k, DG_K[k], DG_KB[k]
+        self.ne, self.nb = B.shape[1], nb
+        _dg_check(((B, 4), (hb, self.KB)), self.ne)
+        _dg_index(self.ne, nbr, nq)
+        self.B, self.hb, self.nbr, self.nq = B, hb, nbr, nq
+        self.g, self.tau, self.fc = g, tau, fc
+        dev = B.device
+        G, H = dg_reference(k)
+        self.ref = torch.from_numpy(np.concatenate([G.ravel(), H.ravel()])).to(dev)
+        self.T = torch.from_numpy(dg_products(k).ravel().copy()).to(dev)
+        self.tab = torch.from_numpy(dg_edge_table(k)["raw"].copy()).to(dev)
+        self.work = torch.empty(6 * self.K * self.ne, dtype=torch.float64, device=dev)
+
+    def project(self, c, u, stream=None):
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K)), self.ne)
+        _dgc(dg_velocity_projection(self.k, self.ne, _ptr(c), _ptr(self.B), _ptr(self.hb), _ptr(self.T), _ptr(u),
+                                      _stream(stream, c.device)))
+
+    def rhs(self, c, u, out, cb=None, ub=None, F=None, stream=None):
+        """out = dc/dt for the state c with velocity u; cb (3K, nb), ub (2K, nb)
+        the prescribed states, F (3K, ne) the body force (None: none)."""
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K), (out, 3 * self.K)), self.ne)
+        if F is not None:
+            _dg_check(((F, 3 * self.K),), self.ne)
+        pcb, pub = _dg_ghosts(self.K, self.nb, cb, ub)
+        _dgc(dg_rhs(self.k, self.ne, _ptr(c), _ptr(u), _ptr(self.B), _ptr(self.hb), _ptr(self.nbr), _ptr(self.nq),
+                      self.nb, pcb, pub, self.g, self.tau, self.fc, _ptr(F), _ptr(self.ref), _ptr(self.tab), _ptr(out),
+                      _stream(stream, c.device)))
+
+    def step(self, c, u, dt: float, cb3=None, ub3=None, F3=None, stream=None):
+        """Advance c (3K, ne) in place by one SSP-RK3 step; u (2K, ne) is
+        scratch for the stage velocities; cb3 (3, 3K, nb), ub3 (3, 2K, nb),
+        F3 (3, 3K, ne) the data of the stages at t, t + dt, t + dt / 2."""
+        import torch
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K)), self.ne)
+        if F3 is not None:
+            if (F3.dtype != torch.float64 or not F3.is_cuda or not F3.is_contiguous()
+                    or tuple(F3.shape) != (3, 3 * self.K, self.ne)):
+                raise ValueError("F3 must be a contiguous FP64 device tensor (3, 3K, ne)")
+        pcb, pub = _dg_ghosts(self.K, self.nb, cb3, ub3, stages=3)
+        _dgc(dg_ssp_rk3_step(self.k, self.ne, _ptr(c), _ptr(u), _ptr(self.work), _ptr(self.B), _ptr(self.hb),
+                               _ptr(self.nbr), _ptr(self.nq), self.nb, pcb, pub, self.g, self.tau, self.fc, _ptr(F3),
+                               _ptr(self.ref), _ptr(self.T), _ptr(self.tab), dt, _stream(stream, c.device)))

@@ -211,7 +211,8 @@ def dg_mesh_neighbours(nx: int, ny: int):
 
 def dg_fields(K: int, B: np.ndarray, seed: int = SEED_DG_FIELDS):
     """Coefficients of (xi, U, V), (u, v) and the bathymetry h_b, (3K, ne),
-    (2K, ne) and (K, ne), for the elements with maps B (4, ne).  Physical
+    (2K, ne) and (KB, ne) (KB = max(K, 3): the bathymetry is at least
+    linear), for the elements with maps B (4, ne).  Physical
     values: xi ~ N(0, 0.1) (so that the depth xi + h_b stays positive), U,
     V, u, v ~ N(0, 1) for the element mean, a tenth of that for each higher
     mode; h_b with a mean U[1, 5] and higher modes N(0, 0.02); a coefficient
@@ -225,9 +226,10 @@ def dg_fields(K: int, B: np.ndarray, seed: int = SEED_DG_FIELDS):
     amp = np.array([0.1, 1.0, 1.0])[:, None, None]
     c = rng.normal(0.0, 1.0, (3, K, ne)) * scale * amp * unit
     u = rng.normal(0.0, 1.0, (2, K, ne)) * scale * unit
-    hb = np.empty((K, ne))
+    KB = max(K, 3)
+    hb = np.empty((KB, ne))
     hb[0] = rng.uniform(1.0, 5.0, ne)
-    hb[1:] = rng.normal(0.0, 0.02, (K - 1, ne))
+    hb[1:] = rng.normal(0.0, 0.02, (KB - 1, ne))
     hb *= unit
     return (np.ascontiguousarray(c.reshape(3 * K, ne)), np.ascontiguousarray(u.reshape(2 * K, ne)),
             np.ascontiguousarray(hb))

@@ -35,7 +35,8 @@ def test_header_declares_the_boundary():
         assert want in names
     for want in ("dg_reference_size", "dg_reference_integrals", "dg_volume_integrals", "dg_product_size",
                  "dg_product_integrals", "dg_velocity_projection", "dg_edge_table_size",
-                 "dg_edge_integrals", "dg_edge_terms"):
+                 "dg_edge_integrals", "dg_edge_terms", "dg_rhs", "dg_ssp_rk3_step", "dg_basis_values",
+                 "dg_last_error"):
         assert want in names
 
 

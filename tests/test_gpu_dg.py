@@ -1,7 +1,10 @@
-"""GPU parity of the DG volume terms (quadrature-free algebraic form, one
-thread per element) with the oracle's quadrature on the physical element:
-every element of small meshes for orders 0-3, and sampled elements of a
-2 x 1000 x 1000 mesh (a ragged last block)."""
+"""GPU parity of the DG terms (quadrature-free algebraic form, one thread
+per element) with the oracle's quadrature on the physical element: volume
+terms, velocity projection and edge terms (interior and prescribed exterior
+states) on every element of small meshes for orders 0-3 and sampled
+elements of a 2 x 1000 x 1000 mesh (a ragged last block); the full
+right-hand side and SSP-RK3 steps on the manufactured solution of the
+convergence test; and the convergence orders of that test on the GPU."""
 import numpy as np
 import pytest
 
@@ -32,7 +35,7 @@ def check(k, B, c, u, hb, out, elems):
     worst = 0.0
     for e in elems:
         Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
-        ref = dg.volume_integrals(k, c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, hb[e], G_GRAV)
+        ref = dg.volume_integrals(k, c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, hb[:, e], G_GRAV)
         got = out[:, e].reshape(3, K)
         for j in range(3):
             scale = max(np.max(np.abs(ref[j])), 1e-300)
@@ -83,46 +86,191 @@ def test_velocity_projection(mg, k):
         worst = 0.0
         for e in elems:
             Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
-            ref = dg.velocity_projection(k, c[:, e].reshape(3, K), Be, hb[e])
+            ref = dg.velocity_projection(k, c[:, e].reshape(3, K), Be, hb[:, e])
             worst = max(worst, float(np.max(np.abs(got[:, e].reshape(2, K) - ref)) / np.max(np.abs(ref))))
         print(f"DG projection k={k} {ne} elements: worst relative difference {worst:.2e}", flush=True)
         assert np.all(np.isfinite(got)) and worst <= TOL
 
 
+def ghosts_for(K, B, nbr):
+    """Boundary edges numbered as prescribed states, with random states in
+    the owning elements' bases (seeded like the fields)."""
+    nbr_g, be, _ = W.dg_boundary_ghosts(nbr)
+    cb, ub, _ = W.dg_fields(K, B[:, be], seed=W.SEED_DG_FIELDS + 1)
+    return nbr_g, cb, ub
+
+
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_edge_terms(mg, k):
-    """Interior-edge Lax-Friedrichs terms against the oracle's edge
-    quadrature: every element of an 8 x 8 split-quad mesh (boundary edges
-    skipped), sampled elements of a 2M-element mesh."""
+    """Lax-Friedrichs edge terms against the oracle's edge quadrature: every
+    element of an 8 x 8 split-quad mesh with the boundary edges left open
+    (no term) and with prescribed exterior states, sampled elements of a
+    2M-element mesh with prescribed states."""
     import torch
     K = dg.K_OF[k]
-    for nx, sample in ((8, None), (1000, 200)):
+    for nx, sample, with_ghosts in ((8, None, False), (8, None, True), (1000, 200, True)):
         B, a1 = W.dg_mesh(nx, nx, with_origin=True)
         nbr, nq = W.dg_mesh_neighbours(nx, nx)
         ne = B.shape[1]
         c, u, hb = W.dg_fields(K, B)
+        cb = ub = None
+        if with_ghosts:
+            nbr, cb, ub = ghosts_for(K, B, nbr)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         out = torch.full((3 * K, ne), float("nan"), dtype=torch.float64, device="cuda")
-        mg.DGEdges(k)(dev(c), dev(u), dev(B), dev(hb), dev(nbr), dev(nq), G_GRAV, out)
+        mg.DGEdges(k)(dev(c), dev(u), dev(B), dev(hb), dev(nbr), dev(nq), G_GRAV, out,
+                      *((dev(cb), dev(ub)) if with_ghosts else ()))
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         assert np.all(np.isfinite(got))
 
         def state(e):
             Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
-            return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a1[:, e], hb[e]
+            return c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a1[:, e], hb[:, e]
+
+        def side(f):
+            if f >= 0:
+                return state(f)
+            if f <= -2:
+                b = -2 - f
+                return dg.Ghost(cb[:, b].reshape(3, K), ub[:, b].reshape(2, K))
+            return None
         if sample is None:
             elems = range(ne)
         else:
             rng = np.random.default_rng(7)
-            elems = np.concatenate([rng.integers(0, ne, sample), np.arange(ne - 32, ne)])
+            elems = np.concatenate([rng.integers(0, ne, sample), np.arange(ne - 32, ne),
+                                    np.flatnonzero((nbr <= -2).any(axis=0))[:64]])
         worst = 0.0
         for e in elems:
-            nbrs = [state(int(nbr[q, e])) if nbr[q, e] >= 0 else None for q in range(3)]
-            ref = dg.edge_integrals_lf(k, state(e), nbrs, G_GRAV)
+            ref = dg.edge_integrals_lf(k, state(e), [side(int(nbr[q, e])) for q in range(3)], G_GRAV)
             got_e = got[:, e].reshape(3, K)
             # relative to the element's largest term: the three rows differ in
             # size (the pressure terms g h_b xi dominate the momentum rows)
             worst = max(worst, float(np.max(np.abs(got_e - ref)) / max(np.max(np.abs(ref)), 1e-300)))
-        print(f"DG edge terms k={k} {ne} elements: worst relative difference {worst:.2e}", flush=True)
+        print(f"DG edge terms k={k} {ne} elements ghosts={with_ghosts}: worst relative difference {worst:.2e}",
+              flush=True)
         assert worst <= TOL
+
+
+def _element_scale(k, B, a1, nbr, c, u, hb, cb, ub):
+    """Per element, the largest |term| of the volume and edge terms: the
+    right-hand side is their difference and may be much smaller."""
+    K = dg.K_OF[k]
+    ne = B.shape[1]
+    out = np.zeros(ne)
+    for e in range(ne):
+        Be = np.array([[B[0, e], B[1, e]], [B[2, e], B[3, e]]])
+        own = (c[:, e].reshape(3, K), u[:, e].reshape(2, K), Be, a1[:, e], hb[:, e])
+        sides = []
+        for q in range(3):
+            f = int(nbr[q, e])
+            if f >= 0:
+                Bf = np.array([[B[0, f], B[1, f]], [B[2, f], B[3, f]]])
+                sides.append((c[:, f].reshape(3, K), u[:, f].reshape(2, K), Bf, a1[:, f], hb[:, f]))
+            elif f <= -2:
+                sides.append(dg.Ghost(cb[:, -2 - f].reshape(3, K), ub[:, -2 - f].reshape(2, K)))
+            else:
+                sides.append(None)
+        E = dg.volume_integrals(k, own[0], own[1], Be, own[4], G_GRAV)
+        S = dg.edge_integrals_lf(k, own, sides, G_GRAV)
+        out[e] = max(np.max(np.abs(E)), np.max(np.abs(S)))
+    return out
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_rhs(mg, k):
+    """dc/dt = E - S + R + F with prescribed boundary states, friction,
+    Coriolis and a body force, against the oracle on every element of a
+    7 x 7 split-quad mesh."""
+    import torch
+    K = dg.K_OF[k]
+    nx = 7
+    B, a1 = W.dg_mesh(nx, nx, with_origin=True)
+    nbr, nq = W.dg_mesh_neighbours(nx, nx)
+    nbr, cb, ub = ghosts_for(K, B, nbr)
+    c, u, hb = W.dg_fields(K, B)
+    F = W.dg_fields(K, B, seed=W.SEED_DG_FIELDS + 2)[0]
+    tau, fc = 0.02, 1.2e-4
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    system = mg.DGSystem(k, dev(B), dev(hb), dev(nbr), dev(nq), nb=cb.shape[1], g=G_GRAV, tau=tau, fc=fc)
+    out = torch.full((3 * K, B.shape[1]), float("nan"), dtype=torch.float64, device="cuda")
+    system.rhs(dev(c), dev(u), out, dev(cb), dev(ub), dev(F))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = dg.mesh_rhs(k, B, a1, nbr, c, u, hb, G_GRAV, tau, fc, F, cb, ub)
+    scale = _element_scale(k, B, a1, nbr, c, u, hb, cb, ub)
+    worst = float(np.max(np.max(np.abs(got - ref), axis=0) / scale))
+    print(f"DG rhs k={k} {B.shape[1]} elements: worst difference / element scale {worst:.2e}", flush=True)
+    assert np.all(np.isfinite(got)) and worst <= TOL
+
+
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_ssp_rk3_steps_on_the_manufactured_solution(mg, k):
+    """Two SSP-RK3 steps of the convergence test (force and exterior states
+    of the exact solution at the stage times) on a 6 x 6 mesh of
+    [0, 1000]^2 against the oracle's steps from the same data."""
+    import torch
+    from oracle import manufactured as M
+    K = dg.K_OF[k]
+    nx, dt = 6, 2.0
+    B, a1 = W.dg_mesh(nx, nx, with_origin=True, length=1000.0)
+    nbr, nq = W.dg_mesh_neighbours(nx, nx)
+    nbr, be, _ = W.dg_boundary_ghosts(nbr)
+    c = M.project(k, B, a1, lambda x, y: M.exact(x, y, 0.0))
+    hb = M.project(max(k, 1), B, a1, lambda x, y: (M.bathymetry(x, y),))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    system = mg.DGSystem(k, dev(B), dev(hb), dev(nbr), dev(nq), nb=be.size, g=M.G)
+    cg = dev(c)
+    ug = torch.empty(2 * K, B.shape[1], dtype=torch.float64, device="cuda")
+    ref = c
+    for n in range(2):
+        t = n * dt
+        data = [M.stage_data(k, B, a1, be, t + s * dt) for s in dg.SSP3_TIMES]
+        F3, cb3, ub3 = (np.stack([d[i] for d in data]) for i in range(3))
+        ref = dg.ssp_rk3_step(k, B, a1, nbr, ref, hb, dt, M.G, F3=F3, cb3=cb3, ub3=ub3)
+        system.step(cg, ug, dt, dev(cb3), dev(ub3), dev(F3))
+    torch.cuda.synchronize()
+    got = cg.cpu().numpy()
+    # the state is O(1) (xi about 2.3, U about 0.6 times sqrt(|det| / 2))
+    worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"DG SSP-RK3 k={k} {B.shape[1]} elements, 2 steps: worst relative difference {worst:.2e}", flush=True)
+    assert worst <= TOL
+
+
+@pytest.mark.parametrize("k,levels,rate", [(0, (32, 64), 0.9), (1, (4, 8, 16), 1.7), (2, (4, 8, 16), 2.6),
+                                          (3, (4, 8, 16), 3.6)])
+def test_convergence_orders(mg, k, levels, rate):
+    """The paper's convergence test (Sec. 3.1, t in (0, 1500), dt = 0.5 or
+    the explicit scheme's stable step where that is smaller) run by the
+    library's SSP-RK3 step: the L2 errors of xi, U and V fall with the
+    experimental order about k + 1 (the paper's table at these meshes:
+    k = 0: 0.92-1.00, k = 1: 1.7-2.3, k = 2: 3.0-3.4, k = 3: 3.7-4.1)."""
+    from paper_1904_08684_amd import convergence
+    rows = []
+    for nx in levels:
+        pr = convergence.Problem(k, nx)
+        c, _ = pr.run(1500.0, convergence.stable_dt(k, nx, 1500.0)[0])
+        rows.append((pr.ne, *pr.errors(c, 1500.0)))
+        print(f"convergence k={k} {rows[-1][0]} elements: errors xi, U, V = "
+              f"{rows[-1][1]:.4g}, {rows[-1][2]:.4g}, {rows[-1][3]:.4g}", flush=True)
+    for j in (1, 2, 3):
+        eoc = np.log2(rows[-2][j] / rows[-1][j])
+        assert np.isfinite(eoc) and eoc >= rate, (j, rows)
+
+
+def test_library_imported_before_torch(mg):
+    """A process that imports the binding before torch (as the convergence
+    CLI does) must still run the library on torch's HIP runtime: a second
+    runtime, loaded under another file name, finds no device."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_1904_08684_amd import convergence\n"
+        "pr = convergence.Problem(0, 2)\n"
+        "c, n = pr.run(2.0, 0.5)\n"
+        "print('steps', n, 'errors', pr.errors(c, 2.0))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240,
+                       cwd=__import__("os").path.dirname(__import__("os").path.dirname(__file__)))
+    print(r.stdout[-400:], r.stderr[-400:], flush=True)
+    assert r.returncode == 0 and "steps 4" in r.stdout

@@ -243,7 +243,7 @@ def _uniform(k, B, vals):
     return out
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_uniform_flow_over_a_sloping_bottom_is_steady(k):
     """Constant xi, U, V, u, v over a linear bathymetry, with the exterior
     states equal to the interior ones: the flux divergence is
@@ -256,7 +256,7 @@ def test_uniform_flow_over_a_sloping_bottom_is_steady(k):
     g = 9.81
     c = _uniform(k, B, (0.3, 0.8, -0.5))
     u = _uniform(k, B, (0.25, -0.1))
-    hb = M.project(k, B, a1, lambda x, y: (2.0 + 0.7 * x - 0.4 * y,))
+    hb = M.project(max(k, 1), B, a1, lambda x, y: (2.0 + 0.7 * x - 0.4 * y,))
     cb, ub = c[:, be], u[:, be]
     L = dg.mesh_rhs(k, B, a1, nbr, c, u, hb, g, 0.0, 0.0, None, cb, ub)
     scale = np.max(np.abs(dg.mesh_rhs(k, B, a1, np.full_like(nbr, -1), c, u, hb, g)))
@@ -278,14 +278,12 @@ def test_source_terms_closed_form(k):
         det = np.linalg.det(Be)
         c = np.zeros((3, K))
         c[:, 0] = np.array([xi, U, V]) * math.sqrt(abs(det) / 2.0)
-        # h_b's projection on this element (P^0 keeps only its mean, and
-        # then the source sees no slope)
-        hb = M.project(k, B[:, e:e + 1], a1[:, e:e + 1], lambda x, y: (1.0 + hx * x + hy * y,))[:, 0]
+        # h_b's projection on this element (order max(k, 1): exact)
+        hb = M.project(max(k, 1), B[:, e:e + 1], a1[:, e:e + 1], lambda x, y: (1.0 + hx * x + hy * y,))[:, 0]
         R = dg.source_integrals(k, c, Be, hb, g, tau, fc)
-        sx, sy = (hx, hy) if k > 0 else (0.0, 0.0)
         want = np.zeros((3, K))
-        want[1, 0] = (-tau * U + fc * V + g * xi * sx) * math.sqrt(abs(det) / 2.0)
-        want[2, 0] = (-tau * V - fc * U + g * xi * sy) * math.sqrt(abs(det) / 2.0)
+        want[1, 0] = (-tau * U + fc * V + g * xi * hx) * math.sqrt(abs(det) / 2.0)
+        want[2, 0] = (-tau * V - fc * U + g * xi * hy) * math.sqrt(abs(det) / 2.0)
         assert np.max(np.abs(R - want)) <= 1e-13 * (1.0 + np.max(np.abs(want)))
 
 
@@ -326,7 +324,7 @@ def test_operator_is_consistent_on_the_manufactured_solution(k, sizes, rate):
     for nx in sizes:
         B, a1, nbr, be, bq = _mesh(nx, length=1000.0)
         c = M.project(k, B, a1, lambda x, y: M.exact(x, y, t))
-        hb = M.project(k, B, a1, lambda x, y: (M.bathymetry(x, y),))
+        hb = M.project(max(k, 1), B, a1, lambda x, y: (M.bathymetry(x, y),))
         F, cb, ub = M.stage_data(k, B, a1, be, t)
         u = dg.mesh_velocity(k, B, c, hb)
         L = dg.mesh_rhs(k, B, a1, nbr, c, u, hb, M.G, 0.0, 0.0, F, cb, ub)
