@@ -9,6 +9,7 @@
 #include "dg.h"
 #include "mg.h"
 
+
 namespace {
 
 constexpr int kMaxK = 10;
@@ -162,6 +163,11 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
                                                    const double* __restrict__ hb, double g,
                                                    const double* __restrict__ ref, double* __restrict__ out,
                                                    double tau, double fc, const double* __restrict__ F) {
+    // The library is built with contraction off so that the multigrid
+    // kernels round every multiply and add as written (bitwise parity with
+    // the oracle); the DG terms are checked to a tolerance and cost FP64
+    // issue, so here a * b + c is one fused multiply-add.
+#pragma clang fp contract(fast)
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= ne) return;
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
@@ -247,6 +253,7 @@ template <int K>
 __global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* __restrict__ c,
                                                     const double* __restrict__ B, const double* __restrict__ hb,
                                                     const double* __restrict__ T, double* __restrict__ u) {
+#pragma clang fp contract(fast)   // fused multiply-adds, as in k_dg_volume
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= ne) return;
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
@@ -304,6 +311,17 @@ __global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* 
 #pragma unroll
         for (int i = 0; i < K; ++i) u[(long long)(comp * K + i) * ne + e] = y[i];
     }
+}
+
+// a * b + c, fused (one rounding) with F: the edge terms' K^3 inner loop
+// at orders 2 and 3, where FP64 issue is the cost (at lower orders the
+// fused form scheduled worse).
+template <bool F>
+__device__ __forceinline__ double madd(double a, double b, double c) {
+    if constexpr (F)
+        return std::fma(a, b, c);
+    else
+        return a * b + c;
 }
 
 // Edge terms: one thread per element, edges in turn; for each edge the
@@ -421,11 +439,11 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
                     for (int m = 0; m < KT; ++m) {
                         const double t3 = o3[(p * KT + i) * KT + m], s3 = m3[(p * KT + i) * KT + m];
                         if (m < K) {
-                            sw += t3 * wn[m];
-                            tw += s3 * wo[m];
+                            sw = madd<(K >= 6)>(t3, wn[m], sw);
+                            tw = madd<(K >= 6)>(s3, wo[m], tw);
                         }
-                        sx += t3 * w[m];
-                        tx += s3 * wx[m];
+                        sx = madd<(K >= 6)>(t3, w[m], sx);
+                        tx = madd<(K >= 6)>(s3, wx[m], tx);
                     }
                     r2o += U[i] * sw + 0.5 * g * n1 * xi[i] * sx;
                     r3o += V[i] * sw + 0.5 * g * n2 * xi[i] * sx;

@@ -525,7 +525,7 @@ def _dg_ghosts(K, nb, cb, ub, stages=1):
     return C.c_void_p(cb.data_ptr()), C.c_void_p(ub.data_ptr())
 
 
-def _ptr(t):
+def _dptr(t):
     return C.c_void_p(None if t is None else t.data_ptr())
 
 
@@ -546,7 +546,7 @@ class DGProjection:
         """c (3K, ne), B (4, ne), hb (KB, ne) in; u (2K, ne) out."""
         ne = B.shape[1]
         _dg_check(((c, 3 * self.K), (B, 4), (hb, self.KB), (u, 2 * self.K)), ne)
-        _dgc(dg_velocity_projection(self.k, ne, _ptr(c), _ptr(B), _ptr(hb), _ptr(self.T), _ptr(u),
+        _dgc(dg_velocity_projection(self.k, ne, _dptr(c), _dptr(B), _dptr(hb), _dptr(self.T), _dptr(u),
                                       _stream(stream, B.device)))
 
 
@@ -581,8 +581,8 @@ class DGEdges:
         _dg_index(ne, nbr, nq)
         nb = 0 if cb is None else cb.shape[1]
         pcb, pub = _dg_ghosts(self.K, nb, cb, ub)
-        _dgc(dg_edge_terms(self.k, ne, _ptr(c), _ptr(u), _ptr(B), _ptr(hb), _ptr(nbr), _ptr(nq), nb, pcb, pub,
-                             g, _ptr(self.tab), _ptr(out), _stream(stream, B.device)))
+        _dgc(dg_edge_terms(self.k, ne, _dptr(c), _dptr(u), _dptr(B), _dptr(hb), _dptr(nbr), _dptr(nq), nb, pcb, pub,
+                             g, _dptr(self.tab), _dptr(out), _stream(stream, B.device)))
 
 
 class DGVolume:
@@ -599,7 +599,7 @@ class DGVolume:
         FP64 device tensors, element index fastest."""
         ne = B.shape[1]
         _dg_check(((c, 3 * self.K), (u, 2 * self.K), (B, 4), (hb, self.KB), (out, 3 * self.K)), ne)
-        _dgc(dg_volume_integrals(self.k, ne, _ptr(c), _ptr(u), _ptr(B), _ptr(hb), g, _ptr(self.ref), _ptr(out),
+        _dgc(dg_volume_integrals(self.k, ne, _dptr(c), _dptr(u), _dptr(B), _dptr(hb), g, _dptr(self.ref), _dptr(out),
                                    _stream(stream, B.device)))
 
 
@@ -627,7 +627,7 @@ class DGSystem:
 
     def project(self, c, u, stream=None):
         _dg_check(((c, 3 * self.K), (u, 2 * self.K)), self.ne)
-        _dgc(dg_velocity_projection(self.k, self.ne, _ptr(c), _ptr(self.B), _ptr(self.hb), _ptr(self.T), _ptr(u),
+        _dgc(dg_velocity_projection(self.k, self.ne, _dptr(c), _dptr(self.B), _dptr(self.hb), _dptr(self.T), _dptr(u),
                                       _stream(stream, c.device)))
 
     def rhs(self, c, u, out, cb=None, ub=None, F=None, stream=None):
@@ -637,8 +637,8 @@ class DGSystem:
         if F is not None:
             _dg_check(((F, 3 * self.K),), self.ne)
         pcb, pub = _dg_ghosts(self.K, self.nb, cb, ub)
-        _dgc(dg_rhs(self.k, self.ne, _ptr(c), _ptr(u), _ptr(self.B), _ptr(self.hb), _ptr(self.nbr), _ptr(self.nq),
-                      self.nb, pcb, pub, self.g, self.tau, self.fc, _ptr(F), _ptr(self.ref), _ptr(self.tab), _ptr(out),
+        _dgc(dg_rhs(self.k, self.ne, _dptr(c), _dptr(u), _dptr(self.B), _dptr(self.hb), _dptr(self.nbr), _dptr(self.nq),
+                      self.nb, pcb, pub, self.g, self.tau, self.fc, _dptr(F), _dptr(self.ref), _dptr(self.tab), _dptr(out),
                       _stream(stream, c.device)))
 
     def step(self, c, u, dt: float, cb3=None, ub3=None, F3=None, stream=None):
@@ -652,6 +652,6 @@ class DGSystem:
                     or tuple(F3.shape) != (3, 3 * self.K, self.ne)):
                 raise ValueError("F3 must be a contiguous FP64 device tensor (3, 3K, ne)")
         pcb, pub = _dg_ghosts(self.K, self.nb, cb3, ub3, stages=3)
-        _dgc(dg_ssp_rk3_step(self.k, self.ne, _ptr(c), _ptr(u), _ptr(self.work), _ptr(self.B), _ptr(self.hb),
-                               _ptr(self.nbr), _ptr(self.nq), self.nb, pcb, pub, self.g, self.tau, self.fc, _ptr(F3),
-                               _ptr(self.ref), _ptr(self.T), _ptr(self.tab), dt, _stream(stream, c.device)))
+        _dgc(dg_ssp_rk3_step(self.k, self.ne, _dptr(c), _dptr(u), _dptr(self.work), _dptr(self.B), _dptr(self.hb),
+                               _dptr(self.nbr), _dptr(self.nq), self.nb, pcb, pub, self.g, self.tau, self.fc, _dptr(F3),
+                               _dptr(self.ref), _dptr(self.T), _dptr(self.tab), dt, _stream(stream, c.device)))
