@@ -96,19 +96,21 @@ int dg_product_integrals(int k, double* T);
 int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
                            const double* T, double* u, void* stream);
 
-/* Doubles in the edge table for order k: 12 KB^2 + 12 KB^3, or 0 for a bad k. */
+/* Doubles in the edge table for order k: 3 KB NB with NB = max(k, 1) + 1
+ * (2, 2, 3, 4), or 0 for a bad k. */
 long long dg_edge_table_size(int k);
 
-/* Host: the exact edge integrals for order k (indices below KB), with the
- * local edges of the reference triangle q0 (0,0)->(1,0), q1 (1,0)->(0,1),
- * q2 (0,1)->(0,0)
- * parametrised by s in [0, 1], and a neighbour's edge q' traversed backwards
- * (its parameter 1 - s), row-major in this order:
- *   O2[q][p][i]      = int phi^_p phi^_i            along q
- *   O3[q][p][i][m]   = int phi^_p phi^_i phi^_m     along q
- *   N2[q][q'][p][i]  = int phi^_p(q, s) phi^_i(q', 1 - s)
- *   N3[q][q'][p][i][m] = int phi^_p(q, s) phi^_i(q', 1 - s) phi^_m(q', 1 - s)
- * MG_EINVAL for a bad k or NULL table. */
+/* Host: the exact edge-trace table for order k: with the local edges of the
+ * reference triangle q0 (0,0)->(1,0), q1 (1,0)->(0,1), q2 (0,1)->(0,0)
+ * parametrised by s in [0, 1], every basis function restricted to an edge
+ * is a polynomial of degree max(k, 1) in s, expanded here in the shifted
+ * Legendre polynomials P_0 = 1, P_1 = 2s - 1, P_2, P_3 on [0, 1]:
+ *   C[q][i][a] = (2a + 1) int_0^1 phi^_i(edge q at s) P_a(s) ds,
+ * i < KB, a < NB, row-major.  A neighbour traverses the shared edge the
+ * other way (s -> 1 - s), which negates its odd coefficients.  The edge
+ * kernel multiplies traces with the exact integrals int P_a P_b P_c (built
+ * into the kernel), so the products of three basis functions along an edge
+ * never need a table of their own.  MG_EINVAL for a bad k or NULL table. */
 int dg_edge_integrals(int k, double* table);
 
 /* Device: the edge terms of every element,
@@ -119,7 +121,7 @@ int dg_edge_integrals(int k, double* table);
  * the wave speed; here lambda_E = max over both sides of |u_mean . n| +
  * sqrt(g H_mean), element means, constant on the edge), n the unit outward
  * normal, the flux tensor and basis of dg_volume_integrals, evaluated
- * algebraically with the table of dg_edge_integrals (on the device).
+ * algebraically with the trace table of dg_edge_integrals (on the device).
  * nbr[q ne + e] names the exterior side of local edge q (int32, device):
  *   f in [0, ne)   the element across the edge, nq[q ne + e] its local
  *                  index of that edge (0..2);

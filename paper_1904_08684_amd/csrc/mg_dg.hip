@@ -90,8 +90,51 @@ int k_of(int k) { return k == 0 ? 1 : k == 1 ? 3 : k == 2 ? 6 : k == 3 ? 10 : 0;
 // tables: max(k, 1), so that a linear h_b is exact at every order.
 int kb_of(int k) { return k == 0 ? 3 : k_of(k); }
 
+// Coefficients of a trace on an edge (degree max(k, 1) in the edge
+// parameter): the length of the edge table's Legendre expansions.
+int nb_of(int k) { return k == 0 ? 2 : k + 1; }
+
 template <int K>
 constexpr int kb_const() { return K == 1 ? 3 : K; }
+
+template <int K>
+constexpr int nt_const() { return K == 1 ? 1 : K == 3 ? 2 : K == 6 ? 3 : 4; }   // k + 1
+
+template <int K>
+constexpr int nb_const() { return K == 1 ? 2 : nt_const<K>(); }                // max(k, 1) + 1
+
+// int_0^1 P_a P_b P_c ds for the shifted Legendre polynomials, a, b, c <= 3:
+// the square of the Wigner 3j symbol (a b c; 0 0 0), zero unless a + b + c
+// is even and a, b, c satisfy the triangle inequality, else
+// [(2s-2a)! (2s-2b)! (2s-2c)! / (2s+1)!] [s! / ((s-a)! (s-b)! (s-c)!)]^2
+// with 2s = a + b + c.  Exact in double (factorials up to 13!).
+struct Legendre3 {
+    double v[4][4][4];
+};
+
+constexpr double factorial(int n) {
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+constexpr Legendre3 legendre3() {
+    Legendre3 t{};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c) {
+                const int S = a + b + c;
+                if (S % 2 || a > b + c || b > a + c || c > a + b) {
+                    t.v[a][b][c] = 0.0;
+                    continue;
+                }
+                const int s = S / 2;
+                const double r = factorial(s) / (factorial(s - a) * factorial(s - b) * factorial(s - c));
+                t.v[a][b][c] =
+                    factorial(2 * s - 2 * a) * factorial(2 * s - 2 * b) * factorial(2 * s - 2 * c) / factorial(2 * s + 1) * r * r;
+            }
+    return t;
+}
 
 // ------------------------------------------------------------ edge tables
 // Polynomials in the edge parameter s with integer coefficients.
@@ -313,26 +356,20 @@ __global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* 
     }
 }
 
-// a * b + c, fused (one rounding) with F: the edge terms' K^3 inner loop
-// at orders 2 and 3, where FP64 issue is the cost (at lower orders the
-// fused form scheduled worse).
-template <bool F>
-__device__ __forceinline__ double madd(double a, double b, double c) {
-    if constexpr (F)
-        return std::fma(a, b, c);
-    else
-        return a * b + c;
-}
-
-// Edge terms: one thread per element, edges in turn; for each edge the
-// exterior state (a neighbour's coefficients, or a prescribed polynomial in
-// the element's own basis on a Dirichlet edge) is gathered and both sides'
-// contributions to every test function p are added to out (SUB: subtracted
-// from what out holds).  The table offsets depend on the kind of the
-// exterior side (the neighbour's local edge index q', or 3 for a prescribed
-// state, which uses the element's own edge tables); lanes of a wavefront are
-// served one kind at a time so that the table is always read at a
-// wave-uniform address.
+// Edge terms: one thread per element, edges in turn.  Every basis
+// function restricted to an edge is a polynomial of degree max(k, 1) in the
+// edge parameter s, so each field's trace is expanded in shifted Legendre
+// polynomials P_a(s) on [0, 1] (coefficients C[q][i][a] of the table), the
+// flux's products of two traces are integrated against P_a with the exact
+// table L3[a][b][c] = int P_a P_b P_c, and the result is taken back to the
+// test functions with C again: exact integrals as with full triple-product
+// tables, at K (k + 1) instead of K^2 operations per field and edge side.
+// A neighbour's edge runs the other way (s -> 1 - s), which flips the sign
+// of its odd Legendre coefficients; a prescribed exterior state is a
+// polynomial in the element's own basis on the same edge.  The neighbour's
+// local edge index selects its rows of C; lanes of a wavefront are served
+// one such kind at a time so that the table is read at wave-uniform
+// addresses.  The result is added to out (SUB: subtracted).
 template <int K, bool SUB>
 __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __restrict__ c,
                                                   const double* __restrict__ u, const double* __restrict__ B,
@@ -341,37 +378,68 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
                                                   const double* __restrict__ cb, const double* __restrict__ ub,
                                                   double g, const double* __restrict__ tab,
                                                   double* __restrict__ out) {
+#pragma clang fp contract(fast)   // fused multiply-adds, as in k_dg_volume
+    constexpr int KT = kb_const<K>();    // bathymetry coefficients (and rows of C)
+    constexpr int NT = nt_const<K>();    // Legendre coefficients of a state trace
+    constexpr int NB = nb_const<K>();    // ... of the bathymetry's trace (table stride)
+    // the coefficient gathers: unrolled at orders 0 and 1; at orders 2 and 3
+    // rolled, or every load would be hoisted and the registers would spill
+    constexpr int UR = K <= 3 ? KT : 1;
     const long long e0 = (long long)blockIdx.x * 256 + threadIdx.x;
     const bool live = e0 < ne;
     const long long e = live ? e0 : 0;     // lanes past the end compute nothing but join the ballots
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
     const double adet = std::fabs(b11 * b22 - b12 * b21);
     const double a = 1.0 / std::sqrt(adet);
-    constexpr int KT = kb_const<K>();                    // table order and bathymetry coefficients
-    double xi[K], U[K], V[K], w[KT];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        xi[i] = c[(long long)i * ne + e];
-        U[i] = c[(long long)(K + i) * ne + e];
-        V[i] = c[(long long)(2 * K + i) * ne + e];
-    }
-    // xi + 2 h_b, the second factor of the pressure term
-#pragma unroll
-    for (int i = 0; i < KT; ++i) w[i] = (i < K ? xi[i] : 0.0) + 2.0 * hb[(long long)i * ne + e];
     const double v1 = std::sqrt(2.0 / adet);                       // value of phi_e1
-    const double umx = u[e] * v1, umy = u[(long long)K * ne + e] * v1, Hm = (xi[0] + hb[e]) * v1;
+    const double umx = u[e] * v1, umy = u[(long long)K * ne + e] * v1, Hm = (c[e] + hb[e]) * v1;
     if (!SUB && live)
         for (int t = 0; t < 3 * K; ++t) out[(long long)t * ne + e] = 0.0;
     const double sg = SUB ? -1.0 : 1.0;
-    const double* O2 = tab;
-    const double* O3 = tab + 3 * KT * KT;
-    const double* N2 = tab + 3 * KT * KT + 3 * KT * KT * KT;
-    const double* N3 = tab + 12 * KT * KT + 3 * KT * KT * KT;
+    const double* Ctr = tab;
+    constexpr Legendre3 L3 = legendre3();   // compile-time constants: the zeros fold away
+#pragma unroll 1
     for (int q = 0; q < 3; ++q) {
         const double dx = q == 0 ? b11 : (q == 1 ? b12 - b11 : -b12);
         const double dy = q == 0 ? b21 : (q == 1 ? b22 - b21 : -b22);
         const double L = std::sqrt(dx * dx + dy * dy);
         const double n1 = dy / L, n2 = -dx / L;
+        const double* Cq = Ctr + q * KT * NB;
+        // the element's traces (physical values): xi, U, V, u . n, xi + 2 h_b
+        double Xm[NT], Um[NT], Vm[NT], Nm[NT], Wm[NB];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Xm[t] = Um[t] = Vm[t] = Nm[t] = 0.0;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) Wm[t] = 0.0;
+#pragma unroll UR
+        for (int i = 0; i < KT; ++i) {
+            double w = 2.0 * hb[(long long)i * ne + e];
+            if (i < K) {
+                const double x = c[(long long)i * ne + e];
+                const double U = c[(long long)(K + i) * ne + e], V = c[(long long)(2 * K + i) * ne + e];
+                const double un = u[(long long)i * ne + e] * n1 + u[(long long)(K + i) * ne + e] * n2;
+                w += x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double ct = Cq[i * NB + t];
+                    Xm[t] += x * ct;
+                    Um[t] += U * ct;
+                    Vm[t] += V * ct;
+                    Nm[t] += un * ct;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t) Wm[t] += w * Cq[i * NB + t];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            Xm[t] *= a;
+            Um[t] *= a;
+            Vm[t] *= a;
+            Nm[t] *= a;
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) Wm[t] *= a;
         // kind 0..2: a neighbour, across its local edge kind; 3: a prescribed
         // state; anything out of range: no term
         const int fr = live ? nbr[(long long)q * ne + e] : -1;
@@ -403,65 +471,83 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
             const double fdet = std::fabs(c11 * c22 - c12 * c21);
             const double bsc = 1.0 / std::sqrt(fdet);
             const double w1 = std::sqrt(2.0 / fdet);
-            double xo[K], Uo[K], Vo[K], wx[KT], wn[K], wo[K];
+            const double* Cn = ghost ? Cq : Ctr + ks * KT * NB;
+            double Xp[NT], Up[NT], Vp[NT], Np[NT], Wp[NB];
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                xo[i] = cs[(long long)i * st + f];
-                Uo[i] = cs[(long long)(K + i) * st + f];
-                Vo[i] = cs[(long long)(2 * K + i) * st + f];
-                wo[i] = us[(long long)i * st + f] * n1 + us[(long long)(K + i) * st + f] * n2;
-                wn[i] = u[(long long)i * ne + e] * n1 + u[(long long)(K + i) * ne + e] * n2;
+            for (int t = 0; t < NT; ++t) Xp[t] = Up[t] = Vp[t] = Np[t] = 0.0;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) Wp[t] = 0.0;
+#pragma unroll UR
+            for (int i = 0; i < KT; ++i) {
+                double w = 2.0 * hb[(long long)i * ne + fg];
+                if (i < K) {
+                    const double x = cs[(long long)i * st + f];
+                    const double U = cs[(long long)(K + i) * st + f], V = cs[(long long)(2 * K + i) * st + f];
+                    const double un = us[(long long)i * st + f] * n1 + us[(long long)(K + i) * st + f] * n2;
+                    w += x;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const double ct = Cn[i * NB + t];
+                        Xp[t] += x * ct;
+                        Up[t] += U * ct;
+                        Vp[t] += V * ct;
+                        Np[t] += un * ct;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < NB; ++t) Wp[t] += w * Cn[i * NB + t];
             }
+            // scale, and for a neighbour flip the odd coefficients (s -> 1 - s)
 #pragma unroll
-            for (int i = 0; i < KT; ++i) wx[i] = (i < K ? xo[i] : 0.0) + 2.0 * hb[(long long)i * ne + fg];
-            const double Hp = (xo[0] + hb[fg]) * w1;
+            for (int t = 0; t < NB; ++t) {
+                const double sc = (!ghost && (t & 1)) ? -bsc : bsc;
+                if (t < NT) {
+                    Xp[t] *= sc;
+                    Up[t] *= sc;
+                    Vp[t] *= sc;
+                    Np[t] *= sc;
+                }
+                Wp[t] *= sc;
+            }
+            const double Hp = (cs[f] + hb[fg]) * w1;
             const double lam = fmax(std::fabs(umx * n1 + umy * n2) + std::sqrt(g * Hm),
                                     std::fabs((us[f] * n1 + us[(long long)K * st + f] * n2) * w1) + std::sqrt(g * Hp));
-            const double* o2 = O2 + q * KT * KT;
-            const double* o3 = O3 + q * KT * KT * KT;
-            const double* m2 = ghost ? o2 : N2 + (q * 3 + ks) * KT * KT;
-            const double* m3 = ghost ? o3 : N3 + (q * 3 + ks) * KT * KT * KT;
-            const double aa = a * a, aaa = aa * a, ab = a * bsc, abb = ab * bsc;
-            for (int p = 0; p < K; ++p) {
-                double jX = 0.0, jU = 0.0, jV = 0.0, kX = 0.0, kU = 0.0, kV = 0.0;
-                double r2o = 0.0, r3o = 0.0, r2n = 0.0, r3n = 0.0;
+            // int P_t F ds for the three flux rows, t < NT
+            double G1[NT], G2[NT], G3[NT];
 #pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    const double t2 = o2[p * KT + i], s2 = m2[p * KT + i];
-                    jX += xi[i] * t2;
-                    jU += U[i] * t2;
-                    jV += V[i] * t2;
-                    kX += xo[i] * s2;
-                    kU += Uo[i] * s2;
-                    kV += Vo[i] * s2;
-                    double sw = 0.0, sx = 0.0, tw = 0.0, tx = 0.0;
+            for (int t = 0; t < NT; ++t) {
+                double qun = 0.0, qvn = 0.0, qxw = 0.0;
 #pragma unroll
-                    for (int m = 0; m < KT; ++m) {
-                        const double t3 = o3[(p * KT + i) * KT + m], s3 = m3[(p * KT + i) * KT + m];
-                        if (m < K) {
-                            sw = madd<(K >= 6)>(t3, wn[m], sw);
-                            tw = madd<(K >= 6)>(s3, wo[m], tw);
-                        }
-                        sx = madd<(K >= 6)>(t3, w[m], sx);
-                        tx = madd<(K >= 6)>(s3, wx[m], tx);
+                for (int b2 = 0; b2 < NT; ++b2) {
+#pragma unroll
+                    for (int c2 = 0; c2 < NT; ++c2) {
+                        const double l = L3.v[t][b2][c2];
+                        qun += l * (Um[b2] * Nm[c2] + Up[b2] * Np[c2]);
+                        qvn += l * (Vm[b2] * Nm[c2] + Vp[b2] * Np[c2]);
                     }
-                    r2o += U[i] * sw + 0.5 * g * n1 * xi[i] * sx;
-                    r3o += V[i] * sw + 0.5 * g * n2 * xi[i] * sx;
-                    r2n += Uo[i] * tw + 0.5 * g * n1 * xo[i] * tx;
-                    r3n += Vo[i] * tw + 0.5 * g * n2 * xo[i] * tx;
+#pragma unroll
+                    for (int c2 = 0; c2 < NB; ++c2)
+                        qxw += L3.v[t][b2][c2] * (Xm[b2] * Wm[c2] + Xp[b2] * Wp[c2]);
                 }
-                const double own1 = aa * (n1 * jU + n2 * jV);
-                const double own2 = aaa * r2o;
-                const double own3 = aaa * r3o;
-                const double nb1 = ab * (n1 * kU + n2 * kV);
-                const double nb2 = abb * r2n;
-                const double nb3 = abb * r3n;
-                const double s1v = L * (0.5 * (own1 + nb1) + 0.5 * lam * (aa * jX - ab * kX));
-                const double s2v = L * (0.5 * (own2 + nb2) + 0.5 * lam * (aa * jU - ab * kU));
-                const double s3v = L * (0.5 * (own3 + nb3) + 0.5 * lam * (aa * jV - ab * kV));
-                out[(long long)p * ne + e] += sg * s1v;
-                out[(long long)(K + p) * ne + e] += sg * s2v;
-                out[(long long)(2 * K + p) * ne + e] += sg * s3v;
+                const double inv = 1.0 / (2 * t + 1);    // int P_t^2
+                G1[t] = inv * (0.5 * (n1 * (Um[t] + Up[t]) + n2 * (Vm[t] + Vp[t])) + 0.5 * lam * (Xm[t] - Xp[t]));
+                G2[t] = 0.5 * qun + 0.25 * g * n1 * qxw + 0.5 * lam * inv * (Um[t] - Up[t]);
+                G3[t] = 0.5 * qvn + 0.25 * g * n2 * qxw + 0.5 * lam * inv * (Vm[t] - Vp[t]);
+            }
+            const double fac = sg * L * a;
+#pragma unroll 1
+            for (int p = 0; p < K; ++p) {
+                double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double ct = Cq[p * NB + t];
+                    s1 += ct * G1[t];
+                    s2 += ct * G2[t];
+                    s3 += ct * G3[t];
+                }
+                out[(long long)p * ne + e] += fac * s1;
+                out[(long long)(K + p) * ne + e] += fac * s2;
+                out[(long long)(2 * K + p) * ne + e] += fac * s3;
             }
         }
     }
@@ -636,42 +722,26 @@ int dg_velocity_projection(int k, long long ne, const double* c, const double* B
 }
 
 long long dg_edge_table_size(int k) {
-    const long long K = k_of(k) ? kb_of(k) : 0;
-    return 12 * K * K + 12 * K * K * K;
+    if (!k_of(k)) return 0;
+    return 3LL * kb_of(k) * nb_of(k);
 }
 
 int dg_edge_integrals(int k, double* table) {
-    const int K = k_of(k) ? kb_of(k) : 0;
-    if (!K || !table) return MG_EINVAL;
-    Poly1 own[3][kMaxK], back[3][kMaxK];
+    if (!k_of(k) || !table) return MG_EINVAL;
+    const int KT = kb_of(k), NB = nb_of(k);
+    // shifted Legendre polynomials on [0, 1]: 1, 2s - 1, 6s^2 - 6s + 1,
+    // 20s^3 - 30s^2 + 12s - 1
+    static const long long leg[4][4] = {{1, 0, 0, 0}, {-1, 2, 0, 0}, {1, -6, 6, 0}, {-1, 12, -30, 20}};
     for (int q = 0; q < 3; ++q)
-        for (int p = 0; p < K; ++p) {
-            own[q][p] = basis_on_edge(p, q, false);
-            back[q][p] = basis_on_edge(p, q, true);
-        }
-    double* O2 = table;
-    double* O3 = O2 + 3 * K * K;
-    double* N2 = O3 + 3 * K * K * K;
-    double* N3 = N2 + 9 * K * K;
-    for (int q = 0; q < 3; ++q)
-        for (int p = 0; p < K; ++p)
-            for (int i = 0; i < K; ++i) {
-                const Poly1 pi = mul1(own[q][p], own[q][i]);
-                O2[(q * K + p) * K + i] = integrate1(pi, kScale[p] * kScale[i]);
-                for (int m = 0; m < K; ++m)
-                    O3[((q * K + p) * K + i) * K + m] =
-                        integrate1(mul1(pi, own[q][m]), kScale[p] * kScale[i] * kScale[m]);
+        for (int i = 0; i < KT; ++i) {
+            const Poly1 tr = basis_on_edge(i, q, false);
+            for (int a = 0; a < NB; ++a) {
+                Poly1 P;
+                std::memset(&P, 0, sizeof(P));
+                for (int j = 0; j < 4; ++j) P.c[j] = leg[a][j] * (2 * a + 1);   // exact before the one division
+                table[(q * KT + i) * NB + a] = integrate1(mul1(tr, P), kScale[i]);
             }
-    for (int q = 0; q < 3; ++q)
-        for (int r = 0; r < 3; ++r)
-            for (int p = 0; p < K; ++p)
-                for (int i = 0; i < K; ++i) {
-                    const Poly1 pi = mul1(own[q][p], back[r][i]);
-                    N2[((q * 3 + r) * K + p) * K + i] = integrate1(pi, kScale[p] * kScale[i]);
-                    for (int m = 0; m < K; ++m)
-                        N3[(((q * 3 + r) * K + p) * K + i) * K + m] =
-                            integrate1(mul1(pi, back[r][m]), kScale[p] * kScale[i] * kScale[m]);
-                }
+        }
     return MG_OK;
 }
 

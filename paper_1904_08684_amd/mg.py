@@ -550,17 +550,17 @@ class DGProjection:
                                       _stream(stream, B.device)))
 
 
+DG_NB = {0: 2, 1: 2, 2: 3, 3: 4}     # Legendre coefficients of an edge trace, max(k, 1) + 1
+
+
 def dg_edge_table(k: int) -> dict:
-    """The exact edge integrals for order k (host), over the first KB =
-    DG_KB[k] basis functions, as arrays O2 (3, KB, KB), O3 (3, KB, KB, KB),
-    N2 (3, 3, KB, KB), N3 (3, 3, KB, KB, KB)."""
-    K = DG_KB[k]
+    """The exact edge-trace table for order k (host): C (3, KB, NB), the
+    coefficients of the first KB = DG_KB[k] reference basis functions on
+    each local edge in the shifted Legendre polynomials P_0 .. P_(NB-1) of
+    the edge parameter."""
     t = np.empty(int(dg_edge_table_size(k)), dtype=np.float64)
     _dgc(dg_edge_integrals(k, t.ctypes.data_as(_D)))
-    o = [0, 3 * K * K, 3 * K ** 3, 9 * K * K, 9 * K ** 3]
-    o = np.cumsum(o)
-    return {"raw": t, "O2": t[o[0]:o[1]].reshape(3, K, K), "O3": t[o[1]:o[2]].reshape(3, K, K, K),
-            "N2": t[o[2]:o[3]].reshape(3, 3, K, K), "N3": t[o[3]:o[4]].reshape(3, 3, K, K, K)}
+    return {"raw": t, "C": t.reshape(3, DG_KB[k], DG_NB[k])}
 
 
 class DGEdges:

@@ -49,31 +49,60 @@ def test_product_integrals_match_quadrature(mg, k):
     assert mg.dg_velocity_projection(k, -1, None, None, None, None, None, None) == mg.MG_EINVAL
 
 
+def _shifted_legendre(n, s):
+    return [np.ones_like(s), 2 * s - 1, 6 * s * s - 6 * s + 1, 20 * s ** 3 - 30 * s * s + 12 * s - 1][:n]
+
+
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
-def test_edge_tables_match_quadrature(mg, k):
-    """The exact edge integrals (own edge, and the neighbour's edge traversed
-    backwards) against Gauss quadrature of the oracle's basis; tables of
-    order max(k, 1)."""
-    K = dg.KB_OF[k]
-    T = mg.dg_edge_table(k)
+def test_edge_trace_table_matches_quadrature(mg, k):
+    """C[q][i][a] = (2a + 1) int_0^1 phi^_i(edge q at s) P_a(s) ds against
+    Gauss quadrature of the oracle's basis, and the expansion reproduces
+    the traces (they have degree max(k, 1))."""
+    KB, NB = dg.KB_OF[k], mg.DG_NB[k]
+    C = mg.dg_edge_table(k)["C"]
     t, w = np.polynomial.legendre.leggauss(8)
     s = (t + 1.0) / 2.0
     w = w / 2.0
     lin = {0: (0, 1, 0, 0), 1: (1, -1, 0, 1), 2: (0, 0, 1, -1)}
+    P = np.array(_shifted_legendre(NB, s))
+    for q in range(3):
+        x0, xs, y0, ys = lin[q]
+        tr = np.array(dg.basis(x0 + xs * s, y0 + ys * s))[:KB]
+        want = (tr * w) @ P.T * (2 * np.arange(NB) + 1)
+        assert np.max(np.abs(C[q] - want)) <= 1e-12
+        assert np.max(np.abs(C[q] @ P - tr)) <= 1e-12
+    assert mg.dg_edge_table_size(k) == 3 * KB * NB
 
-    def at(q, back):
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_edge_trace_factorisation_gives_the_triple_product_integrals(mg, k):
+    """The edge kernel's factorised form: int phi^_p(q, s) phi^_i(q', s')
+    phi^_m(q', s') ds with s' = s (own edge) or 1 - s (a neighbour's edge,
+    odd Legendre coefficients negated) equals
+    sum_abc C[q][p][a] C'[i][b] C'[m][c] int P_a P_b P_c, the last by
+    Gauss quadrature here."""
+    K, NB = dg.K_OF[k], mg.DG_NB[k]
+    C = mg.dg_edge_table(k)["C"]
+    t, w = np.polynomial.legendre.leggauss(10)
+    s = (t + 1.0) / 2.0
+    w = w / 2.0
+    P = np.array(_shifted_legendre(NB, s))
+    L3 = np.einsum("aq,bq,cq->abc", P * w, P, P)
+    lin = {0: (0, 1, 0, 0), 1: (1, -1, 0, 1), 2: (0, 0, 1, -1)}
+    flip = (-1.0) ** np.arange(NB)
+
+    def trace(q, back):
         x0, xs, y0, ys = lin[q]
         ss = 1.0 - s if back else s
         return np.array(dg.basis(x0 + xs * ss, y0 + ys * ss))[:K]
     for q in range(3):
-        ph = at(q, False)
-        assert np.max(np.abs(T["O2"][q] - (ph * w) @ ph.T)) <= 1e-12
-        assert np.max(np.abs(T["O3"][q] - np.einsum("pq,iq,mq->pim", ph * w, ph, ph))) <= 1e-12
-        for r in range(3):
-            pb = at(r, True)
-            assert np.max(np.abs(T["N2"][q, r] - (ph * w) @ pb.T)) <= 1e-12
-            assert np.max(np.abs(T["N3"][q, r] - np.einsum("pq,iq,mq->pim", ph * w, pb, pb))) <= 1e-12
-    assert mg.dg_edge_table_size(k) == 12 * K * K + 12 * K ** 3
+        own = trace(q, False)
+        for r in (None, 0, 1, 2):
+            other = own if r is None else trace(r, True)
+            want = np.einsum("pq,iq,mq->pim", own * w, other, other)
+            Co = C[q, :K] if r is None else C[r, :K] * flip
+            got = np.einsum("pa,ib,mc,abc->pim", C[q, :K], Co, Co, L3)
+            assert np.max(np.abs(got - want)) <= 1e-11
 
 
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
