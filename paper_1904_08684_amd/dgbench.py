@@ -14,8 +14,10 @@ bathymetry in, two out, 3K + 4 + K + 2K doubles; flops K^2 (K + 1) for the
 weighted mass matrix, K^3 / 3 for its factorisation and 4 K^2 for the two
 solves.  Edge terms: the element's fields, map and bathymetry, the
 neighbour indices (24 B), three fields out (neighbours' data counted once,
-as it is every element's own); flops 3 (8 K^3 + 26 K^2) (three edges, four
-multiply-adds per (p, i, m) on each side).  Right-hand side: both, with the
+as it is every element's own); flops of the Legendre-trace form,
+6 (8 K NT + 2 KB NB + 9 NT^2 NB + 3 K NT) with NT = k + 1 and
+NB = max(k, 1) + 1 (three edges; traces of both sides, trace products,
+the map back to the test functions; a multiply-add counts two).  Right-hand side: both, with the
 edge pass reading back what the volume pass wrote, and the bathymetry
 source (4 K^3 more flops).  Step: three projections and right-hand sides,
 the copy of the state (2 x 3K doubles) and three stage combinations (4 x 3K
@@ -44,7 +46,13 @@ def projection_bytes(K: int) -> int:
 
 
 def edge_flops(K: int) -> int:
-    return 3 * (8 * K ** 3 + 26 * K * K)
+    # per edge: the Legendre traces of both sides (four fields of K and the
+    # bathymetry's KB coefficients), the three trace products against the
+    # dense (NT, NT, NB) integrals, and the map back to the K test functions
+    NT = {1: 1, 3: 2, 6: 3, 10: 4}[K]
+    NB = max(NT, 2)
+    KB = max(K, 3)
+    return 3 * 2 * (8 * K * NT + 2 * KB * NB + 9 * NT * NT * NB + 3 * K * NT)
 
 
 def edge_bytes(K: int) -> int:

@@ -138,3 +138,27 @@ def test_system_entry_points_reject_bad_arguments(mg):
     assert step(3, 0, 0, 0.5) == mg.MG_OK
     assert step(3, 5, 0, 0.5) == E
     assert mg.dg_basis_values(9, 3, n, n, n) == E
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 4), (5, 5)])
+def test_mesh_neighbours_match_the_geometry(nx, ny):
+    """The split-quad mesh's neighbour table: every element is
+    counter-clockwise, edge q of e (vertex q to q + 1) is edge nq of its
+    neighbour traversed backwards, the relation is symmetric, and the
+    2 (nx + ny) boundary edges are the ones without a neighbour."""
+    from paper_1904_08684_amd import workloads as W
+    B, a1 = W.dg_mesh(nx, ny, with_origin=True)
+    nbr, nq = W.dg_mesh_neighbours(nx, ny)
+    assert np.all(B[0] * B[3] - B[1] * B[2] > 0)
+
+    def verts(e):
+        return [a1[:, e], a1[:, e] + B[[0, 2], e], a1[:, e] + B[[1, 3], e]]
+    for e in range(B.shape[1]):
+        for q in range(3):
+            f, r = int(nbr[q, e]), int(nq[q, e])
+            if f < 0:
+                continue
+            P, Q = verts(e), verts(f)
+            assert np.allclose(P[q], Q[(r + 1) % 3]) and np.allclose(P[(q + 1) % 3], Q[r])
+            assert nbr[r, f] == e and nq[r, f] == q
+    assert int((nbr < 0).sum()) == 2 * (nx + ny)
