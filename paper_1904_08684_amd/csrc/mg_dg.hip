@@ -356,6 +356,23 @@ __global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* 
     }
 }
 
+// Block order of the edge pass.  The hardware deals consecutive blocks to
+// the eight XCDs in turn, each with its own L2.  Here every XCD runs a
+// contiguous range of a sequence that pairs block l with block l + H (H half
+// the blocks, rounded up): on the split-quad numbering the second half of
+// the elements holds the first half's edge neighbours, so an element's
+// coefficients are still in its XCD's L2 when the neighbouring waves gather
+// them.  Any other numbering only loses that benefit: the map is a
+// bijection of the block indices.
+__device__ __forceinline__ long long edge_block(long long b, long long nb) {
+    const long long per = nb >> 3, rem = nb & 7;
+    const long long x = b & 7, r = b >> 3;
+    const long long lam = (x < rem) ? x * (per + 1) + r : rem * (per + 1) + (x - rem) * per + r;
+    const long long H = (nb + 1) >> 1, pairs = nb - H;
+    if (lam < 2 * pairs) return (lam & 1) ? H + (lam >> 1) : (lam >> 1);
+    return lam - pairs;      // the unpaired middle block of an odd count
+}
+
 // Edge terms: one thread per element, edges in turn.  Every basis
 // function restricted to an edge is a polynomial of degree max(k, 1) in the
 // edge parameter s, so each field's trace is expanded in shifted Legendre
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
     // the coefficient gathers: unrolled at orders 0 and 1; at orders 2 and 3
     // rolled, or every load would be hoisted and the registers would spill
     constexpr int UR = K <= 3 ? KT : 1;
-    const long long e0 = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long e0 = edge_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     const bool live = e0 < ne;
     const long long e = live ? e0 : 0;     // lanes past the end compute nothing but join the ballots
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
