@@ -529,27 +529,41 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
             const double Hp = (cs[f] + hb[fg]) * w1;
             const double lam = fmax(std::fabs(umx * n1 + umy * n2) + std::sqrt(g * Hm),
                                     std::fabs((us[f] * n1 + us[(long long)K * st + f] * n2) * w1) + std::sqrt(g * Hp));
-            // int P_t F ds for the three flux rows, t < NT
+            // int P_t F ds for the three flux rows, t < NT: each product of two
+            // traces is formed once and scattered into the t accumulators (the
+            // zero integrals fold away), which keeps few values live
+            double qun[NT], qvn[NT], qxw[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) qun[t] = qvn[t] = qxw[t] = 0.0;
+#pragma unroll
+            for (int b2 = 0; b2 < NT; ++b2) {
+#pragma unroll
+                for (int c2 = 0; c2 < NB; ++c2) {
+                    const double px = Xm[b2] * Wm[c2] + Xp[b2] * Wp[c2];
+                    double pu = 0.0, pv = 0.0;
+                    if (c2 < NT) {
+                        pu = Um[b2] * Nm[c2] + Up[b2] * Np[c2];
+                        pv = Vm[b2] * Nm[c2] + Vp[b2] * Np[c2];
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const double l = L3.v[t][b2][c2];
+                        if (l == 0.0) continue;
+                        if (c2 < NT) {
+                            qun[t] += l * pu;
+                            qvn[t] += l * pv;
+                        }
+                        qxw[t] += l * px;
+                    }
+                }
+            }
             double G1[NT], G2[NT], G3[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                double qun = 0.0, qvn = 0.0, qxw = 0.0;
-#pragma unroll
-                for (int b2 = 0; b2 < NT; ++b2) {
-#pragma unroll
-                    for (int c2 = 0; c2 < NT; ++c2) {
-                        const double l = L3.v[t][b2][c2];
-                        qun += l * (Um[b2] * Nm[c2] + Up[b2] * Np[c2]);
-                        qvn += l * (Vm[b2] * Nm[c2] + Vp[b2] * Np[c2]);
-                    }
-#pragma unroll
-                    for (int c2 = 0; c2 < NB; ++c2)
-                        qxw += L3.v[t][b2][c2] * (Xm[b2] * Wm[c2] + Xp[b2] * Wp[c2]);
-                }
                 const double inv = 1.0 / (2 * t + 1);    // int P_t^2
                 G1[t] = inv * (0.5 * (n1 * (Um[t] + Up[t]) + n2 * (Vm[t] + Vp[t])) + 0.5 * lam * (Xm[t] - Xp[t]));
-                G2[t] = 0.5 * qun + 0.25 * g * n1 * qxw + 0.5 * lam * inv * (Um[t] - Up[t]);
-                G3[t] = 0.5 * qvn + 0.25 * g * n2 * qxw + 0.5 * lam * inv * (Vm[t] - Vp[t]);
+                G2[t] = 0.5 * qun[t] + 0.25 * g * n1 * qxw[t] + 0.5 * lam * inv * (Um[t] - Up[t]);
+                G3[t] = 0.5 * qvn[t] + 0.25 * g * n2 * qxw[t] + 0.5 * lam * inv * (Vm[t] - Vp[t]);
             }
             const double fac = sg * L * a;
 #pragma unroll 1
