@@ -386,7 +386,7 @@ __device__ __forceinline__ long long edge_block(long long b, long long nb) {
 // polynomial in the element's own basis on the same edge.  The neighbour's
 // local edge index selects its rows of C; lanes of a wavefront are served
 // one such kind at a time so that the table is read at wave-uniform
-// addresses.  The result is added to out (SUB: subtracted).
+// addresses.  The result is written to out once (SUB: subtracted from it).
 template <int K, bool SUB>
 __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __restrict__ c,
                                                   const double* __restrict__ u, const double* __restrict__ B,
@@ -410,9 +410,11 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
     const double a = 1.0 / std::sqrt(adet);
     const double v1 = std::sqrt(2.0 / adet);                       // value of phi_e1
     const double umx = u[e] * v1, umy = u[(long long)K * ne + e] * v1, Hm = (c[e] + hb[e]) * v1;
-    if (!SUB && live)
-        for (int t = 0; t < 3 * K; ++t) out[(long long)t * ne + e] = 0.0;
-    const double sg = SUB ? -1.0 : 1.0;
+    // every edge's integrals against P_t (scaled), one private LDS column per
+    // thread (structure of arrays: no bank conflicts, no barriers); the map to
+    // the test functions and the one write of out come after the last edge
+    __shared__ double sG[3 * 3 * NT][256];
+    const int tid = threadIdx.x;
     const double* Ctr = tab;
     constexpr Legendre3 L3 = legendre3();   // compile-time constants: the zeros fold away
 #pragma unroll 1
@@ -472,6 +474,8 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
             kind = 3;
             f = -2 - (long long)fr;
         }
+#pragma unroll
+        for (int t = 0; t < 3 * NT; ++t) sG[q * 3 * NT + t][tid] = 0.0;
         bool todo = kind >= 0;
         for (;;) {
             const unsigned long long mask = __ballot(todo);
@@ -565,21 +569,38 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
                 G2[t] = 0.5 * qun[t] + 0.25 * g * n1 * qxw[t] + 0.5 * lam * inv * (Um[t] - Up[t]);
                 G3[t] = 0.5 * qvn[t] + 0.25 * g * n2 * qxw[t] + 0.5 * lam * inv * (Vm[t] - Vp[t]);
             }
-            const double fac = sg * L * a;
-#pragma unroll 1
-            for (int p = 0; p < K; ++p) {
-                double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            const double fac = L * a;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const double ct = Cq[p * NB + t];
-                    s1 += ct * G1[t];
-                    s2 += ct * G2[t];
-                    s3 += ct * G3[t];
-                }
-                out[(long long)p * ne + e] += fac * s1;
-                out[(long long)(K + p) * ne + e] += fac * s2;
-                out[(long long)(2 * K + p) * ne + e] += fac * s3;
+            for (int t = 0; t < NT; ++t) {
+                sG[(q * 3 + 0) * NT + t][tid] = fac * G1[t];
+                sG[(q * 3 + 1) * NT + t][tid] = fac * G2[t];
+                sG[(q * 3 + 2) * NT + t][tid] = fac * G3[t];
             }
+        }
+    }
+    if (!live) return;
+#pragma unroll 1
+    for (int p = 0; p < K; ++p) {
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double ct = Ctr[(q * KT + p) * NB + t];
+                s1 += ct * sG[(q * 3 + 0) * NT + t][tid];
+                s2 += ct * sG[(q * 3 + 1) * NT + t][tid];
+                s3 += ct * sG[(q * 3 + 2) * NT + t][tid];
+            }
+        double* o = out + (long long)p * ne + e;
+        const long long kn = (long long)K * ne;
+        if (SUB) {
+            o[0] -= s1;
+            o[kn] -= s2;
+            o[2 * kn] -= s3;
+        } else {
+            o[0] = s1;
+            o[kn] = s2;
+            o[2 * kn] = s3;
         }
     }
 }
