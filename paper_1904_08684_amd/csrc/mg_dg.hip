@@ -384,9 +384,12 @@ __device__ __forceinline__ long long edge_block(long long b, long long nb) {
 // A neighbour's edge runs the other way (s -> 1 - s), which flips the sign
 // of its odd Legendre coefficients; a prescribed exterior state is a
 // polynomial in the element's own basis on the same edge.  The neighbour's
-// local edge index selects its rows of C; lanes of a wavefront are served
-// one such kind at a time so that the table is read at wave-uniform
-// addresses.  The result is written to out once (SUB: subtracted from it).
+// local edge index selects its rows of C, which every lane reads from a
+// copy of the (small) table in LDS: serving the lanes of a wavefront one
+// neighbour kind at a time, so as to read the table at wave-uniform
+// addresses, held every value live across that loop and cost a quarter of
+// the occupancy.  The result is written to out once (SUB: subtracted from
+// it).
 template <int K, bool SUB>
 __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __restrict__ c,
                                                   const double* __restrict__ u, const double* __restrict__ B,
@@ -404,17 +407,21 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
     constexpr int UR = K <= 3 ? KT : 1;
     const long long e0 = edge_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     const bool live = e0 < ne;
-    const long long e = live ? e0 : 0;     // lanes past the end compute nothing but join the ballots
+    const long long e = live ? e0 : 0;     // lanes past the end read element 0 and write nothing
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
     const double adet = std::fabs(b11 * b22 - b12 * b21);
     const double a = 1.0 / std::sqrt(adet);
     const double v1 = std::sqrt(2.0 / adet);                       // value of phi_e1
     const double umx = u[e] * v1, umy = u[(long long)K * ne + e] * v1, Hm = (c[e] + hb[e]) * v1;
     // every edge's integrals against P_t (scaled), one private LDS column per
-    // thread (structure of arrays: no bank conflicts, no barriers); the map to
-    // the test functions and the one write of out come after the last edge
+    // thread (structure of arrays: no bank conflicts, and no thread reads
+    // another's column); the map to the test functions and the one write of
+    // out come after the last edge
     __shared__ double sG[3 * 3 * NT][256];
+    __shared__ double sC[3 * KT * NB];
     const int tid = threadIdx.x;
+    for (int j = tid; j < 3 * KT * NB; j += 256) sC[j] = tab[j];
+    __syncthreads();                     // every thread reaches it: no return above
     const double* Ctr = tab;
     constexpr Legendre3 L3 = legendre3();   // compile-time constants: the zeros fold away
 #pragma unroll 1
@@ -476,14 +483,9 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
         }
 #pragma unroll
         for (int t = 0; t < 3 * NT; ++t) sG[q * 3 * NT + t][tid] = 0.0;
-        bool todo = kind >= 0;
-        for (;;) {
-            const unsigned long long mask = __ballot(todo);
-            if (mask == 0) break;
-            const int ks = __builtin_amdgcn_readfirstlane(__shfl(kind, __ffsll((long long)mask) - 1));
-            if (!(todo && kind == ks)) continue;
-            todo = false;
-            const bool ghost = ks == 3;                  // wave-uniform
+        if (kind >= 0) {
+            const int ks = kind;
+            const bool ghost = ks == 3;
             const double* cs = ghost ? cb : c;
             const double* us = ghost ? ub : u;
             const long long st = ghost ? nb : ne;
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(256) void k_dg_edges(long long ne, const double* __
             const double fdet = std::fabs(c11 * c22 - c12 * c21);
             const double bsc = 1.0 / std::sqrt(fdet);
             const double w1 = std::sqrt(2.0 / fdet);
-            const double* Cn = ghost ? Cq : Ctr + ks * KT * NB;
+            const double* Cn = sC + (ghost ? q : ks) * KT * NB;
             double Xp[NT], Up[NT], Vp[NT], Np[NT], Wp[NB];
 #pragma unroll
             for (int t = 0; t < NT; ++t) Xp[t] = Up[t] = Vp[t] = Np[t] = 0.0;
