@@ -274,3 +274,59 @@ def test_library_imported_before_torch(mg):
                        cwd=__import__("os").path.dirname(__import__("os").path.dirname(__file__)))
     print(r.stdout[-400:], r.stderr[-400:], flush=True)
     assert r.returncode == 0 and "steps 4" in r.stdout
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_edge_terms_do_not_depend_on_the_numbering(mg, k):
+    """A random relabelling of the elements (neighbour tables remapped) gives
+    the same edge terms, bitwise: each thread does the same arithmetic in
+    the same order whatever the numbering, and neighbours of different local
+    edges now share every wavefront (the table rows are read per lane)."""
+    import torch
+    K = dg.K_OF[k]
+    nx = 24
+    B = W.dg_mesh(nx, nx)
+    nbr, nq = W.dg_mesh_neighbours(nx, nx)
+    nbr, cb, ub = ghosts_for(K, B, nbr)
+    c, u, hb = W.dg_fields(K, B)
+    ne = B.shape[1]
+    perm = np.random.default_rng(9).permutation(ne)          # new index -> old index
+    inv = np.empty(ne, dtype=np.int64)
+    inv[perm] = np.arange(ne)
+    nbr_p = nbr[:, perm].copy()
+    inner = nbr_p >= 0
+    nbr_p[inner] = inv[nbr_p[inner]]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    edges = mg.DGEdges(k)
+    out = torch.empty((3 * K, ne), dtype=torch.float64, device="cuda")
+    out_p = torch.empty_like(out)
+    edges(dev(c), dev(u), dev(B), dev(hb), dev(nbr), dev(nq), G_GRAV, out, dev(cb), dev(ub))
+    edges(dev(c[:, perm]), dev(u[:, perm]), dev(B[:, perm]), dev(hb[:, perm]), dev(nbr_p.astype(np.int32)),
+          dev(nq[:, perm]), G_GRAV, out_p, dev(cb), dev(ub))
+    torch.cuda.synchronize()
+    a, b = out.cpu().numpy(), out_p.cpu().numpy()
+    print(f"DG edges k={k} relabelled {ne} elements: max difference {np.max(np.abs(a[:, perm] - b)):.1e}", flush=True)
+    assert np.array_equal(a[:, perm], b)
+
+
+@pytest.mark.parametrize("k", [0, 3])
+def test_rhs_on_one_square(mg, k):
+    """The smallest mesh: two triangles, every boundary edge with a
+    prescribed state (a block with 254 idle lanes)."""
+    import torch
+    K = dg.K_OF[k]
+    B, a1 = W.dg_mesh(1, 1, with_origin=True)
+    nbr, nq = W.dg_mesh_neighbours(1, 1)
+    nbr, cb, ub = ghosts_for(K, B, nbr)
+    c, u, hb = W.dg_fields(K, B)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    system = mg.DGSystem(k, dev(B), dev(hb), dev(nbr), dev(nq), nb=cb.shape[1], g=G_GRAV, tau=0.01, fc=1e-4)
+    out = torch.full((3 * K, 2), float("nan"), dtype=torch.float64, device="cuda")
+    system.rhs(dev(c), dev(u), out, dev(cb), dev(ub))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = dg.mesh_rhs(k, B, a1, nbr, c, u, hb, G_GRAV, 0.01, 1e-4, None, cb, ub)
+    scale = _element_scale(k, B, a1, nbr, c, u, hb, cb, ub)
+    worst = float(np.max(np.max(np.abs(got - ref), axis=0) / scale))
+    print(f"DG rhs k={k} one square: worst difference / element scale {worst:.2e}", flush=True)
+    assert np.all(np.isfinite(got)) and worst <= TOL
