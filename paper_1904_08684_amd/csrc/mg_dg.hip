@@ -191,6 +191,87 @@ double integrate1(const Poly1& a, long long scale) {
     return (double)num / 2520.0 * std::sqrt((double)scale);
 }
 
+// Velocity projection: one thread per element assembles the lower triangle
+// of the H-weighted mass matrix, factors it (Cholesky, in registers) and
+// solves for both velocity components (project_element; k_dg_project
+// stores them, and the volume pass of a Runge-Kutta step computes them in
+// place of reading them).
+template <int K>
+__device__ __forceinline__ void project_element(long long ne, long long e, const double* __restrict__ c,
+                                                const double* __restrict__ B, const double* __restrict__ hb,
+                                                const double* __restrict__ T, double (&uo)[2][K]) {
+#pragma clang fp contract(fast)   // fused multiply-adds, as in k_dg_volume
+    const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
+    const double ad = std::fabs(b11 * b22 - b12 * b21);
+    const double sd = 1.0 / std::sqrt(ad);
+    constexpr int NL = K * (K + 1) / 2;
+    double L[NL];                                           // row-major lower triangle
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] = 0.0;
+    // one coefficient of H = xi + h_b at a time (a rolled loop keeps the
+    // table's scalar operands of one step live, not all K^3 of them)
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+        const double h = c[(long long)i * ne + e] + hb[(long long)i * ne + e];
+        const double* Ti = T + i * K;
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+#pragma unroll
+            for (int m = 0; m <= p; ++m) L[p * (p + 1) / 2 + m] += h * Ti[p * K * K + m];
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] *= sd;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double d = L[j * (j + 1) / 2 + j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) d -= L[j * (j + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+        const double ljj = std::sqrt(d);
+        L[j * (j + 1) / 2 + j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < K; ++i) {
+            double v = L[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) v -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+            L[i * (i + 1) / 2 + j] = v / ljj;
+        }
+    }
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        double y[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            double v = c[(long long)((1 + comp) * K + i) * ne + e];
+#pragma unroll
+            for (int q = 0; q < i; ++q) v -= L[i * (i + 1) / 2 + q] * y[q];
+            y[i] = v / L[i * (i + 1) / 2 + i];
+        }
+#pragma unroll
+        for (int i = K - 1; i >= 0; --i) {
+            double v = y[i];
+#pragma unroll
+            for (int q = i + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + i] * y[q];
+            y[i] = v / L[i * (i + 1) / 2 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) uo[comp][i] = y[i];
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* __restrict__ c,
+                                                    const double* __restrict__ B, const double* __restrict__ hb,
+                                                    const double* __restrict__ T, double* __restrict__ u) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    double uo[2][K];
+    project_element<K>(ne, e, c, B, hb, T, uo);
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp)
+#pragma unroll
+        for (int i = 0; i < K; ++i) u[(long long)(comp * K + i) * ne + e] = uo[comp][i];
+}
+
 // One thread per element: for every test function p the mass flux and, per
 // i, the sums over m of the three-function integrals, contracted with the
 // coefficients of i.  The velocity enters the advective terms only through
@@ -200,12 +281,13 @@ double integrate1(const Poly1& a, long long scale) {
 // g xi (H + h_b) / 2 = g xi (xi + 2 h_b) / 2 is one product of two P^k
 // fields.  With RHS the source (g xi grad h_b, friction, Coriolis) and the
 // body force are added: out = E + R + F.
-template <int K, bool RHS>
+template <int K, bool RHS, bool PROJ = false>
 __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* __restrict__ c,
                                                    const double* __restrict__ u, const double* __restrict__ B,
                                                    const double* __restrict__ hb, double g,
                                                    const double* __restrict__ ref, double* __restrict__ out,
-                                                   double tau, double fc, const double* __restrict__ F) {
+                                                   double tau, double fc, const double* __restrict__ F,
+                                                   const double* __restrict__ T, double* __restrict__ uout) {
     // The library is built with contraction off so that the multigrid
     // kernels round every multiply and add as written (bitwise parity with
     // the oracle); the DG terms are checked to a tolerance and cost FP64
@@ -215,6 +297,16 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
     if (e >= ne) return;
     const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
     constexpr int KT = kb_const<K>();                    // table order and bathymetry coefficients
+    // PROJ: the element's velocity from its own state (the projection of a
+    // Runge-Kutta stage), stored for the edge pass and used from registers
+    double uo[2][K];
+    if constexpr (PROJ) {
+        project_element<K>(ne, e, c, B, hb, T, uo);
+#pragma unroll
+        for (int comp = 0; comp < 2; ++comp)
+#pragma unroll
+            for (int i = 0; i < K; ++i) uout[(long long)(comp * K + i) * ne + e] = uo[comp][i];
+    }
     double xi[K], U[K], V[K], wa[K], wb[K], w[K], hv[KT];
 #pragma unroll
     for (int i = 0; i < KT; ++i) hv[i] = hb[(long long)i * ne + e];
@@ -223,7 +315,8 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
         xi[i] = c[(long long)i * ne + e];
         U[i] = c[(long long)(K + i) * ne + e];
         V[i] = c[(long long)(2 * K + i) * ne + e];
-        const double uu = u[(long long)i * ne + e], vv = u[(long long)(K + i) * ne + e];
+        const double uu = PROJ ? uo[0][i] : u[(long long)i * ne + e];
+        const double vv = PROJ ? uo[1][i] : u[(long long)(K + i) * ne + e];
         wa[i] = b22 * uu - b12 * vv;
         wb[i] = b11 * vv - b21 * uu;
         w[i] = xi[i] + 2.0 * hv[i];
@@ -286,73 +379,6 @@ __global__ __launch_bounds__(256) void k_dg_volume(long long ne, const double* _
         out[(long long)p * ne + e] = o1;
         out[(long long)(K + p) * ne + e] = o2;
         out[(long long)(2 * K + p) * ne + e] = o3;
-    }
-}
-
-// Velocity projection: one thread per element assembles the lower triangle
-// of the H-weighted mass matrix, factors it (Cholesky, in registers) and
-// solves for both velocity components.
-template <int K>
-__global__ __launch_bounds__(256) void k_dg_project(long long ne, const double* __restrict__ c,
-                                                    const double* __restrict__ B, const double* __restrict__ hb,
-                                                    const double* __restrict__ T, double* __restrict__ u) {
-#pragma clang fp contract(fast)   // fused multiply-adds, as in k_dg_volume
-    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= ne) return;
-    const double b11 = B[e], b12 = B[ne + e], b21 = B[2 * ne + e], b22 = B[3 * ne + e];
-    const double ad = std::fabs(b11 * b22 - b12 * b21);
-    const double sd = 1.0 / std::sqrt(ad);
-    constexpr int NL = K * (K + 1) / 2;
-    double L[NL];                                           // row-major lower triangle
-#pragma unroll
-    for (int q = 0; q < NL; ++q) L[q] = 0.0;
-    // one coefficient of H = xi + h_b at a time (a rolled loop keeps the
-    // table's scalar operands of one step live, not all K^3 of them)
-#pragma unroll 1
-    for (int i = 0; i < K; ++i) {
-        const double h = c[(long long)i * ne + e] + hb[(long long)i * ne + e];
-        const double* Ti = T + i * K;
-#pragma unroll
-        for (int p = 0; p < K; ++p)
-#pragma unroll
-            for (int m = 0; m <= p; ++m) L[p * (p + 1) / 2 + m] += h * Ti[p * K * K + m];
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) L[q] *= sd;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        double d = L[j * (j + 1) / 2 + j];
-#pragma unroll
-        for (int q = 0; q < j; ++q) d -= L[j * (j + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
-        const double ljj = std::sqrt(d);
-        L[j * (j + 1) / 2 + j] = ljj;
-#pragma unroll
-        for (int i = j + 1; i < K; ++i) {
-            double v = L[i * (i + 1) / 2 + j];
-#pragma unroll
-            for (int q = 0; q < j; ++q) v -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
-            L[i * (i + 1) / 2 + j] = v / ljj;
-        }
-    }
-#pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-        double y[K];
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            double v = c[(long long)((1 + comp) * K + i) * ne + e];
-#pragma unroll
-            for (int q = 0; q < i; ++q) v -= L[i * (i + 1) / 2 + q] * y[q];
-            y[i] = v / L[i * (i + 1) / 2 + i];
-        }
-#pragma unroll
-        for (int i = K - 1; i >= 0; --i) {
-            double v = y[i];
-#pragma unroll
-            for (int q = i + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + i] * y[q];
-            y[i] = v / L[i * (i + 1) / 2 + i];
-        }
-#pragma unroll
-        for (int i = 0; i < K; ++i) u[(long long)(comp * K + i) * ne + e] = y[i];
     }
 }
 
@@ -634,14 +660,19 @@ void dg_begin() {
     g_dg_error[0] = 0;
 }
 
+// proj (with rhs): the velocity is computed from c with the product table T
+// and stored to uout instead of read from u
 int launch_volume(int K, bool rhs, long long ne, const double* c, const double* u, const double* B, const double* hb,
-                  double g, const double* ref, double* out, double tau, double fc, const double* F, hipStream_t st) {
+                  double g, const double* ref, double* out, double tau, double fc, const double* F, hipStream_t st,
+                  bool proj = false, const double* T = nullptr, double* uout = nullptr) {
     const unsigned nbk = (unsigned)((ne + 255) / 256);
 #define DG_VOL(KK)                                                                                         \
-    if (rhs)                                                                                               \
-        k_dg_volume<KK, true><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F);             \
+    if (proj)                                                                                              \
+        k_dg_volume<KK, true, true><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F, T, uout); \
+    else if (rhs)                                                                                          \
+        k_dg_volume<KK, true><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F, T, uout);    \
     else                                                                                                   \
-        k_dg_volume<KK, false><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F);
+        k_dg_volume<KK, false><<<nbk, 256, 0, st>>>(ne, c, u, B, hb, g, ref, out, tau, fc, F, T, uout);
     switch (K) {
         case 1: DG_VOL(1) break;
         case 3: DG_VOL(3) break;
@@ -854,9 +885,15 @@ int dg_ssp_rk3_step(int k, long long ne, double* c, double* u, double* work, con
     if (cp != MG_OK) return cp;
     const double wa[3] = {0.0, 0.75, 1.0 / 3.0}, wb[3] = {1.0, 0.25, 2.0 / 3.0};
     for (int s = 0; s < 3; ++s) {
-        int rc = launch_project(K, ne, c, B, hb, T, u, st);
+        // the stage's velocity: projected inside the volume pass up to order
+        // 2; at order 3 the projection's serial Cholesky chain runs faster
+        // on its own (three wavefronts per SIMD against two in the fused
+        // pass) than the saved traffic is worth
+        const bool fuse = K <= 6;
+        int rc = fuse ? MG_OK : launch_project(K, ne, c, B, hb, T, u, st);
         if (rc == MG_OK)
-            rc = launch_volume(K, true, ne, c, u, B, hb, g, ref, r, tau, fc, F3 ? F3 + s * n : nullptr, st);
+            rc = launch_volume(K, true, ne, c, u, B, hb, g, ref, r, tau, fc, F3 ? F3 + s * n : nullptr, st, fuse,
+                               T, u);
         if (rc == MG_OK)
             rc = launch_edges(K, true, ne, c, u, B, hb, nbr, nq, nb, nb ? cb3 + s * 3LL * K * nb : nullptr,
                               nb ? ub3 + s * 2LL * K * nb : nullptr, g, table, r, st);
