@@ -1,7 +1,9 @@
-/* Volume terms of the quadrature-free discontinuous Galerkin discretisation
- * of the shallow water equations on triangles (the paper's Sec. 2.2,
- * equations mass_basis and momentum_basis_u): for every
- * element e and test function p,
+/* The quadrature-free discontinuous Galerkin discretisation of the shallow
+ * water equations on triangles (the paper's Sec. 2.2): volume terms,
+ * velocity projection, Lax-Friedrichs edge terms, the source, the whole
+ * right-hand side of the semi-discrete system and one SSP-RK3 time step.
+ * The volume terms (equations mass_basis and momentum_basis_u) are, for
+ * every element e and test function p,
  *
  *   E[j][p][e] = (A~(c, u), grad(phi_ep e_j))_{Omega_e},  j = 0, 1, 2,
  *
@@ -55,8 +57,9 @@ long long dg_reference_size(int k);
 /* Host: the exact reference integrals for order k into ref (caller-owned,
  * dg_reference_size(k) doubles): G[l][p][i] = int d_l phi^_p phi^_i, then
  * H[l][p][i][m] = int d_l phi^_p phi^_i phi^_m over the reference triangle,
- * l = 0, 1 (d/dx^1, d/dx^2), all indices below KB, row-major.  Computed from the monomial
- * integrals a! b! / (a + b + 2)!.  MG_EINVAL for a bad k or NULL ref. */
+ * l = 0, 1 (d/dx^1, d/dx^2), all indices below KB, row-major.  Computed
+ * from the monomial integrals a! b! / (a + b + 2)!.  MG_EINVAL for a bad k
+ * or NULL ref. */
 int dg_reference_integrals(int k, double* ref);
 
 /* Device: the volume terms of ne elements of order k, all arrays in device
@@ -89,10 +92,9 @@ int dg_product_integrals(int k, double* T);
  * factorisation and two solves.  Arrays as for dg_volume_integrals: c
  * (3K x ne), B (4 x ne), hb (KB x ne; its modes from K on are orthogonal to
  * every product of two test functions and do not enter), T the table of
- * dg_product_integrals
- * on the device, u (2K x ne)
- * the result.  MG_EINVAL / MG_EDEVICE as dg_volume_integrals; a depth that
- * is not positive on the element leaves non-finite values there. */
+ * dg_product_integrals on the device, u (2K x ne) the result.  MG_EINVAL /
+ * MG_EDEVICE as dg_volume_integrals; a depth that is not positive on the
+ * element leaves non-finite values there. */
 int dg_velocity_projection(int k, long long ne, const double* c, const double* B, const double* hb,
                            const double* T, double* u, void* stream);
 
