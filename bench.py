@@ -114,8 +114,8 @@ def other_configs(mg, W, torch, np):
     solves of the 513^3 Poisson problem, damped-Jacobi cycles with
     rediscretised and Galerkin coarse operators, CG with the V-cycle as
     preconditioner, full multigrid on a 513^3 problem with a closed-form
-    discrete solution, and the DG volume terms, velocity projection and
-    interior-edge terms."""
+    discrete solution, and the DG scheme's volume terms, velocity
+    projection, edge terms, whole right-hand side and SSP-RK3 step."""
     res = {}
 
     def solve_entry(s, rhs, tol=1e-10):
@@ -213,8 +213,9 @@ def other_configs(mg, W, torch, np):
     s.close()
     u = ue = fs = None
 
-    # volume terms of the quadrature-free DG shallow-water scheme, 2 x 1024^2
-    # perturbed split-quad triangles, orders 1-3 (one launch each, HIP events)
+    # the quadrature-free DG shallow-water scheme on 2 x 1024^2 perturbed
+    # split-quad triangles, orders 1-3: each term, the right-hand side and an
+    # SSP-RK3 step (HIP events)
     from paper_1904_08684_amd import dgbench
     for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection"),
                      ("edges", "dg_edge_terms"), ("rhs", "dg_rhs"), ("step", "dg_ssp_rk3_step")):
