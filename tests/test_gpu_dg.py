@@ -205,11 +205,12 @@ def test_rhs(mg, k):
     assert np.all(np.isfinite(got)) and worst <= TOL
 
 
-@pytest.mark.parametrize("k", [0, 1, 3])
-def test_ssp_rk3_steps_on_the_manufactured_solution(mg, k):
+@pytest.mark.parametrize("k,tau,fc", [(0, 0.0, 0.0), (1, 0.0, 0.0), (3, 0.0, 0.0), (1, 2e-3, 1e-4)])
+def test_ssp_rk3_steps_on_the_manufactured_solution(mg, k, tau, fc):
     """Two SSP-RK3 steps of the convergence test (force and exterior states
     of the exact solution at the stage times) on a 6 x 6 mesh of
-    [0, 1000]^2 against the oracle's steps from the same data."""
+    [0, 1000]^2 against the oracle's steps from the same data; also with
+    bottom friction and Coriolis switched on."""
     import torch
     from oracle import manufactured as M
     K = dg.K_OF[k]
@@ -220,7 +221,7 @@ def test_ssp_rk3_steps_on_the_manufactured_solution(mg, k):
     c = M.project(k, B, a1, lambda x, y: M.exact(x, y, 0.0))
     hb = M.project(max(k, 1), B, a1, lambda x, y: (M.bathymetry(x, y),))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    system = mg.DGSystem(k, dev(B), dev(hb), dev(nbr), dev(nq), nb=be.size, g=M.G)
+    system = mg.DGSystem(k, dev(B), dev(hb), dev(nbr), dev(nq), nb=be.size, g=M.G, tau=tau, fc=fc)
     cg = dev(c)
     ug = torch.empty(2 * K, B.shape[1], dtype=torch.float64, device="cuda")
     ref = c
@@ -228,7 +229,7 @@ def test_ssp_rk3_steps_on_the_manufactured_solution(mg, k):
         t = n * dt
         data = [M.stage_data(k, B, a1, be, t + s * dt) for s in dg.SSP3_TIMES]
         F3, cb3, ub3 = (np.stack([d[i] for d in data]) for i in range(3))
-        ref = dg.ssp_rk3_step(k, B, a1, nbr, ref, hb, dt, M.G, F3=F3, cb3=cb3, ub3=ub3)
+        ref = dg.ssp_rk3_step(k, B, a1, nbr, ref, hb, dt, M.G, tau, fc, F3=F3, cb3=cb3, ub3=ub3)
         system.step(cg, ug, dt, dev(cb3), dev(ub3), dev(F3))
     torch.cuda.synchronize()
     got = cg.cpu().numpy()
