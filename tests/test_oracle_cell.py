@@ -368,3 +368,73 @@ def test_neumann_rhs_is_projected():
     assert np.max(np.abs(u1 - u2)) <= 1e-10 * np.max(np.abs(u1))
     with pytest.raises(ValueError):
         cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=17, bc="neumann"))
+
+
+# ---------------------------------------------------------------- Jacobi
+def wall_faces(N, d):
+    """Number of wall faces of every cell (0 inside, up to d at a corner),
+    counted cell by cell."""
+    out = np.zeros((N,) * d, dtype=np.int64)
+    for p in itertools.product(range(N), repeat=d):
+        out[p] = sum((c == 0) + (c == N - 1) for c in p)
+    return out
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+@pytest.mark.parametrize("omega", [0.5, 0.8])
+@pytest.mark.parametrize("d,N,ks,kval", [(2, 16, (1, 1), 1.0), (2, 16, (3, 8), 4.0), (3, 8, (1, 2, 3), 1.0),
+                                         (3, 8, (5, 1, 2), 0.25)])
+def test_jacobi_amplification_of_eigenmodes(bc, omega, d, N, ks, kval):
+    """For a constant coefficient k the sine (Dirichlet) or cosine (Neumann)
+    mode v at the cell centres satisfies A v = k lam v with lam =
+    (4/h^2) sum sin^2(k_a pi h / 2); the Jacobi diagonal of a cell is
+    k s (2d + w) with w its wall faces (Dirichlet mirror ghosts) or
+    k s (2d - w) (zero-flux walls).  So one sweep with f = 0 multiplies the
+    mode at cell i by exactly 1 - omega lam / (s (2d +- w_i)): a dropped
+    omega, a wrong diagonal scale or a wrong wall weight changes it."""
+    h = 1.0 / N
+    x = W.cell_coords(N)
+    fn = np.sin if bc == "dirichlet" else np.cos
+    v = np.ones((N,) * d)
+    for ax in range(d):
+        shape = [1] * d
+        shape[ax] = N
+        v = v * fn(ks[ax] * np.pi * x).reshape(shape)
+    lam = 4 / h ** 2 * sum(np.sin(k * np.pi * h / 2) ** 2 for k in ks)
+    beta = cell.harmonic_faces(np.full((N,) * d, kval))
+    out = cell.jacobi(v, np.zeros_like(v), beta, omega, bc)
+    w = wall_faces(N, d)
+    diag = 2 * d + (w if bc == "dirichlet" else -w)
+    g = 1.0 - omega * lam / (N * N * diag)
+    assert np.max(np.abs(out - g * v)) <= 1e-13 * max(1.0, np.max(np.abs(g)))
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+@pytest.mark.parametrize("omega", [0.5, 0.8])
+@pytest.mark.parametrize("d,N", [(2, 8), (3, 4)])
+def test_jacobi_scalar_loop(bc, omega, d, N):
+    """Damped Jacobi with a random coefficient against a cell-by-cell loop
+    that forms the diagonal and the residual from the harmonic means of k
+    directly (the diagonal is the sum of the cell's face weights, walls
+    counted twice for Dirichlet and not at all for Neumann)."""
+    rng = np.random.default_rng(11)
+    k = np.exp(rng.uniform(-1, 1, size=(N,) * d))
+    u = rng.uniform(-1, 1, size=(N,) * d)
+    f = rng.uniform(-1, 1, size=(N,) * d) * N * N
+    got = cell.jacobi(u, f, cell.harmonic_faces(k), omega, bc)
+    s = N * N
+    for p in itertools.product(range(N), repeat=d):
+        diag, au = 0.0, 0.0
+        for ax in range(d):
+            for side in (-1, 1):
+                q = list(p)
+                q[ax] += side
+                if 0 <= q[ax] < N:
+                    kb = 2 * k[p] * k[tuple(q)] / (k[p] + k[tuple(q)])
+                    diag += kb
+                    au += kb * (u[p] - u[tuple(q)])
+                elif bc == "dirichlet":
+                    diag += 2 * k[p]
+                    au += 2 * k[p] * u[p]
+        want = u[p] + omega * (f[p] - s * au) / (s * diag)
+        assert abs(got[p] - want) <= 1e-13 * max(1.0, abs(want)), p

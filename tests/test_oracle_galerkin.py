@@ -113,3 +113,58 @@ def test_galerkin_needs_node_grids_and_jacobi():
                {"centering": "node", "n": 17, "smoother": "rbgs"}):
         with pytest.raises(ValueError):
             cycle.build_hierarchy(cycle.Params(dim=2, coarse_op="galerkin", **kw))
+
+
+def galerkin_symbol(T, M, thetas):
+    """Eigenvalue of the tensor-product stencil sum_a T_a (x) M_b (x) ... on the
+    sine mode with angles thetas (one per axis): a symmetric 3-point 1-D
+    stencil S acts on sin(j theta) as S[1] + 2 S[0] cos(theta)."""
+    t = [float(T[1]) + 2 * float(T[0]) * np.cos(th) for th in thetas]
+    m = [float(M[1]) + 2 * float(M[0]) * np.cos(th) for th in thetas]
+    lam = 0.0
+    for a in range(len(thetas)):
+        term = t[a]
+        for b in range(len(thetas)):
+            if b != a:
+                term *= m[b]
+        lam += term
+    return lam
+
+
+@pytest.mark.parametrize("omega", [0.5, 0.8])
+@pytest.mark.parametrize("d,n,level,ks", [(2, 33, 1, (1, 1)), (2, 33, 1, (5, 12)), (2, 65, 2, (3, 14)),
+                                          (3, 17, 1, (1, 2, 3)), (3, 33, 2, (7, 1, 4))])
+def test_galerkin_jacobi_fourier_amplification(omega, d, n, level, ks):
+    """On a Galerkin level the stencil is a constant tensor product
+    s sum_a T_a (x) M_b (x) ... (T, M the exact 1-D Galerkin products of
+    [-1 2 -1] and [0 1 0]), so the sine modes of that level are eigenvectors
+    and one damped-Jacobi sweep with f = 0 multiplies them by exactly
+    1 - omega lam / W_centre, lam the stencil's symbol.  The stencil fed to
+    the sweep is the closed form built here, not the oracle's R A P."""
+    s = Fraction((n - 1) ** 2)
+    T = [-s, 2 * s, -s]
+    M = [Fraction(0), Fraction(1), Fraction(0)]
+    for _ in range(level):
+        T, M = galerkin_1d(T), galerkin_1d(M)
+    Wl = np.zeros((3,) * d)
+    for o in itertools.product(range(3), repeat=d):
+        acc = Fraction(0)
+        for a in range(d):
+            t = T[o[a]]
+            for b in range(d):
+                if b != a:
+                    t = t * M[o[b]]
+            acc += t
+        Wl[o] = float(acc)
+    nl = (n - 1) // 2 ** level + 1
+    H = 1.0 / (nl - 1)
+    v = W.sine_mode(nl, d, ks)
+    out = galerkin.jacobi(v, np.zeros_like(v), Wl, omega)
+    lam = galerkin_symbol(T, M, [k * np.pi * H for k in ks])
+    centre = float(d * T[1] * M[1] ** (d - 1))
+    g = 1 - omega * lam / centre
+    assert np.max(np.abs(out - g * v)) <= 1e-13
+    if d == 2 and level == 1:
+        # the textbook nine-point stencil: symbol (3 - c_k - c_l - c_k c_l) / H^2, centre 3 / H^2
+        ck, cl = np.cos(ks[0] * np.pi * H), np.cos(ks[1] * np.pi * H)
+        assert abs(g - (1 - omega * (3 - ck - cl - ck * cl) / 3)) <= 1e-14
