@@ -71,7 +71,8 @@ int dg_reference_integrals(int k, double* ref);
  *   ref                    the table of dg_reference_integrals, on the device
  *   out[(j K + p) ne + e]  E[j][p][e]
  * Enqueued on `stream` (a hipStream_t, NULL = the default stream); returns
- * once launched.  MG_EINVAL for a bad k, ne < 0, ne above 256 (2^31 - 1) or
+ * once launched.  MG_EINVAL for a bad k, ne < 0, ne above 2^32 - 256 (one
+ * thread per element, at most 2^32 - 1 work-items per launch) or
  * a NULL array (ne = 0 is a no-op), MG_EDEVICE for a launch failure.
  * Elements with det B_e = 0 give non-finite values. */
 int dg_volume_integrals(int k, long long ne, const double* c, const double* u, const double* B,

@@ -641,7 +641,9 @@ __global__ __launch_bounds__(256) void k_dg_stage(long long n, double a, const d
         y[i] = a * x[i] + b * (y[i] + dt * r[i]);
 }
 
-bool dg_size_ok(long long ne) { return ne >= 0 && ne <= 256LL * 0x7fffffffLL; }
+// One thread per element in blocks of 256: a launch holds at most 2^32 - 1
+// work-items, so ne is capped at the largest multiple of 256 below 2^32.
+bool dg_size_ok(long long ne) { return ne >= 0 && ne <= (1LL << 32) - 256; }
 
 // The reason of the last MG_EDEVICE of this thread (dg_last_error).
 thread_local char g_dg_error[160] = "";

@@ -83,6 +83,29 @@ def test_3d_rbgs_per_iterate(mg, n, cycles):
     s.close()
 
 
+@pytest.mark.timeout(900)
+def test_513_cycle_per_iterate(mg):
+    """The headline configuration, 513^3 nodes and 8 levels: one FP64 V(3,3)
+    red-black GS cycle from zero (fused three-sweep passes on 513^3 and
+    257^3, fused residual + restriction, column-marching kernels below)
+    against the oracle's cycle, 1e-12 relative in the max norm."""
+    n = 513
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
+    assert s.levels() == 8
+    s.set_rhs(f)
+    s.set_initial(None)
+    s.vcycle(1)
+    got = s.solution()
+    s.close()
+    t0 = time.time()
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3))
+    ref = cycle.cycles(h, f, np.zeros_like(f), 1)[0]
+    err = rel_max(got, ref)
+    print(f"513^3 cycle 1: max rel diff {err:.3e} (oracle {time.time() - t0:.0f} s)", flush=True)
+    assert err <= TOL_ITERATE
+
+
 @pytest.mark.parametrize("n", [33, 65])
 def test_3d_solve_history_and_count(mg, n):
     f = W.interior_uniform(n, 3, W.SEED_F_3D)
@@ -306,7 +329,7 @@ def test_full_size_varcoef_256_properties(mg):
     (3, 65, "rbgs", 3, 3, "mixed"),
     (2, 129, "jacobi", 1, 2, "fp64"),     # three buffer swaps per level: two graphs alternate
     (3, 257, "rbgs", 3, 3, "fp64"),      # fused sweeps run out of place
-    (3, 129, "rbgs", 3, 3, "mixed"),     # mg_solve fuses the update with the next residual; mg_vcycle does not
+    (3, 129, "rbgs", 3, 3, "mixed"),
 ])
 def test_graph_replay_equals_eager(mg, dim, n, sm, nu1, nu2, precision):
     """mg_solve and mg_vcycle replay each iteration from a captured HIP graph;
@@ -702,8 +725,10 @@ def test_max_size_1025_fmg_and_solve(mg):
     """1025^3 nodes (fields of 8.6 GB, beyond the 2 GiB range of the buffer
     loads; 9 levels): FMG reaches the discretisation accuracy of the sine
     problem's closed-form discrete solution, and V(3,3) cycles from zero reach
-    1e-10 with a mean convergence factor below 0.1 per cycle (h-independent,
-    as at 513^3) and an algebraic error far below the discretisation error."""
+    1e-10 with a mean convergence factor below 0.1 per cycle and an algebraic
+    error far below the discretisation error.  (The factor measured here is
+    about 0.09 for this smooth right-hand side, against 0.05 for the random
+    one at 513^3; the test bounds it, it does not claim h-independence.)"""
     import torch
     n = 1025
     ue = torch.from_numpy(W.sine_mode(n, 3)).cuda()

@@ -205,12 +205,14 @@ def test_rhs(mg, k):
     assert np.all(np.isfinite(got)) and worst <= TOL
 
 
-@pytest.mark.parametrize("k,tau,fc", [(0, 0.0, 0.0), (1, 0.0, 0.0), (3, 0.0, 0.0), (1, 2e-3, 1e-4)])
+@pytest.mark.parametrize("k,tau,fc", [(0, 0.0, 0.0), (1, 0.0, 0.0), (2, 0.0, 0.0), (3, 0.0, 0.0), (1, 2e-3, 1e-4),
+                                      (2, 2e-3, 1e-4)])
 def test_ssp_rk3_steps_on_the_manufactured_solution(mg, k, tau, fc):
     """Two SSP-RK3 steps of the convergence test (force and exterior states
     of the exact solution at the stage times) on a 6 x 6 mesh of
     [0, 1000]^2 against the oracle's steps from the same data; also with
-    bottom friction and Coriolis switched on."""
+    bottom friction and Coriolis switched on.  Orders up to 2 project the
+    stage's velocity inside the volume pass, order 3 in its own kernel."""
     import torch
     from oracle import manufactured as M
     K = dg.K_OF[k]

@@ -158,7 +158,7 @@ def test_repeat_is_bitwise_deterministic(mg):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("n", [33, 129, 257])
+@pytest.mark.parametrize("n", [33, 129, 257, 513])
 def test_fused_residual_restriction(mg, n, prec):
     """f_coarse = R (f - A u) in one pass (fused on 3-D levels with n >= 129)
     equals restriction of the oracle's residual."""
@@ -210,7 +210,8 @@ def test_fused_sweeps_equal_half_sweeps(mg, prec, nu, post):
 def test_fused_sweeps_513(mg, prec, nu):
     """The fused passes at the full 513^3 size (five regions across x, the
     last one partly outside the grid; two z chunks): bitwise equal to the
-    separate half-sweeps."""
+    separate half-sweeps, and the FP64 three-sweep pass equal to the
+    oracle's sweeps to the op bar."""
     n = 513
     s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=nu, nu2=nu, precision=mg.MG_MIXED if prec else mg.MG_FP64)
     dt = np.float64 if prec == 0 else np.float32
@@ -228,6 +229,12 @@ def test_fused_sweeps_513(mg, prec, nu):
     s.close()
     print(f"513^3 fused nu={nu} prec={prec}: bitwise {np.array_equal(fused, halves)}", flush=True)
     assert np.array_equal(fused, halves)
+    if prec == 0 and nu == 3:
+        ref = u.copy()
+        for _ in range(nu):
+            node.gs_colour(ref, f, 0)
+            node.gs_colour(ref, f, 1)
+        close(fused, ref, prec, f"fused {nu} sweeps 3d n={n} against the oracle")
 
 
 @pytest.mark.parametrize("prec", [0, 1])

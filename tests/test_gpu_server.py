@@ -12,6 +12,10 @@ pytestmark = pytest.mark.gpu
 
 # (dim, n): 2-D requests use damped Jacobi V(2,2), 3-D requests red-black GS V(3,3)
 MIX = [(2, 65), (3, 33), (2, 129), (3, 65), (2, 257), (3, 17), (2, 33), (3, 33)]
+# the largest served classes: 3-D 129^3 runs the column-marching batched
+# smoother and residuals, 2-D 1025^2 the row-marching ones on every level
+# from 1025^2 down to 129^2
+LARGE = [(3, 129), (2, 1025), (3, 65), (2, 513), (3, 129), (2, 257)]
 
 
 def method(dim):
@@ -50,6 +54,25 @@ def run(mg, torch, reqs, order, arena=1 << 30, slots=64, stagger=False, tol=1e-8
     return results, sols, st
 
 
+def oracle_check(mg, res, sols, reqs, rids):
+    for rid in rids:
+        d, n = reqs[rid]
+        f = W.interior_uniform(n, d, W.SEED_REQUEST_BASE + rid)
+        sm = "jacobi" if d == 2 else "rbgs"
+        nu = 2 if d == 2 else 3
+        h = cycle.build_hierarchy(cycle.Params(centering="node", dim=d, n=n, smoother=sm, nu1=nu, nu2=nu))
+        u = sols[rid]
+        rel = cycle.residual_norm(h, u, f) / cycle.residual_norm(h, np.zeros_like(f), f)
+        u_ref, hist = cycle.mixed_solve(h, f, tol=1e-8)
+        diff = np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))
+        print(f"request {rid} {d}d n={n}: steps {res[rid]['steps']} (oracle {len(hist) - 1}) "
+              f"relres {res[rid]['relres']:.3e} cpu {rel:.3e} vs oracle {diff:.2e}", flush=True)
+        assert res[rid]["status"] == mg.MG_OK and rel <= 1e-8
+        assert abs(rel - res[rid]["relres"]) <= 1e-6 * rel
+        assert res[rid]["steps"] == len(hist) - 1
+        assert diff <= 1e-9
+
+
 def test_alone_equals_in_mix_bitwise(mg):
     import torch
     reqs = MIX
@@ -72,21 +95,7 @@ def test_results_meet_tolerance_and_match_oracle(mg):
     import torch
     reqs = MIX[:6]
     res, sols, _ = run(mg, torch, reqs, list(range(len(reqs))))
-    for rid, (d, n) in enumerate(reqs):
-        f = W.interior_uniform(n, d, W.SEED_REQUEST_BASE + rid)
-        sm = "jacobi" if d == 2 else "rbgs"
-        nu = 2 if d == 2 else 3
-        h = cycle.build_hierarchy(cycle.Params(centering="node", dim=d, n=n, smoother=sm, nu1=nu, nu2=nu))
-        u = sols[rid]
-        rel = cycle.residual_norm(h, u, f) / cycle.residual_norm(h, np.zeros_like(f), f)
-        u_ref, hist = cycle.mixed_solve(h, f, tol=1e-8)
-        diff = np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))
-        print(f"request {rid} {d}d n={n}: steps {res[rid]['steps']} (oracle {len(hist) - 1}) "
-              f"relres {res[rid]['relres']:.3e} cpu {rel:.3e} vs oracle {diff:.2e}", flush=True)
-        assert res[rid]["status"] == mg.MG_OK and rel <= 1e-8
-        assert abs(rel - res[rid]["relres"]) <= 1e-6 * rel
-        assert res[rid]["steps"] == len(hist) - 1
-        assert diff <= 1e-9
+    oracle_check(mg, res, sols, reqs, range(len(reqs)))
 
 
 def test_small_budget_admits_within_footprint(mg):
@@ -139,3 +148,26 @@ def test_queue_limit_and_invalid_requests(mg):
     torch.cuda.synchronize()
     assert out[0]["status"] == mg.MG_OK and float(u.abs().max()) == 0.0
     srv.close()
+
+
+def test_largest_classes_alone_equal_mix_and_match_oracle(mg):
+    """3-D 129^3 and 2-D 1025^2 / 513^2 requests (the marching batched ops)
+    beside smaller ones: each result bitwise the same alone and in a
+    staggered mix, within 1e-9 of the oracle's mixed-precision solve with
+    the same step count, and its residual recomputed by the oracle."""
+    import torch
+    reqs = LARGE
+    alone_res, alone_sol = {}, {}
+    for rid in range(len(reqs)):
+        print(f"alone: request {rid} {reqs[rid]}", flush=True)
+        r, s, _ = run(mg, torch, reqs, [rid])
+        alone_res.update(r)
+        alone_sol.update(s)
+    mix_res, mix_sol, st = run(mg, torch, reqs, [1, 0, 3, 2, 5, 4], stagger=True)
+    for rid in range(len(reqs)):
+        assert alone_res[rid]["status"] == mg.MG_OK
+        assert mix_res[rid]["steps"] == alone_res[rid]["steps"]
+        assert np.array_equal(mix_sol[rid], alone_sol[rid]), rid
+        assert mix_res[rid]["relres"] == alone_res[rid]["relres"]
+    print("mix stats", st, flush=True)
+    oracle_check(mg, mix_res, mix_sol, reqs, [0, 1, 3, 4])
