@@ -41,7 +41,8 @@ extern "C" {
 #endif
 
 /* Host: the reason of this thread's last MG_EDEVICE from a dg_ entry point
- * (the step and the HIP error name), or "" (library-owned string, valid
+ * (the step and the HIP error name; also the size limit behind an MG_EINVAL
+ * of dg_ssp_rk3_step_noalloc), or "" (library-owned string, valid
  * until the thread's next dg_ call). */
 const char* dg_last_error(void);
 
@@ -176,6 +177,22 @@ int dg_ssp_rk3_step(int k, long long ne, double* c, double* u, double* work, con
                     const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3, double g,
                     double tau, double fc, const double* F3, const double* ref, const double* T,
                     const double* table, double dt, void* stream);
+
+/* Device, for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): dg_ssp_rk3_step without
+ * the work argument.  The saved state and the right-hand side live in a
+ * fixed 64 MiB device array of the library (2^23 doubles, held on every
+ * device the library runs on until the process ends), so 6 K ne must not
+ * exceed 2^23 (e.g. ne <= 139810 at k = 3, 466033 at k = 1); larger meshes
+ * get MG_EINVAL with the reason in dg_last_error.  The call allocates
+ * nothing.  Every call on a device shares that device's array, so calls
+ * that overlap on one device (two streams, two threads) race and must be
+ * ordered by the caller.  Other arguments, results and status codes as
+ * dg_ssp_rk3_step. */
+int dg_ssp_rk3_step_noalloc(int k, long long ne, double* c, double* u, const double* B, const double* hb,
+                            const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3,
+                            double g, double tau, double fc, const double* F3, const double* ref, const double* T,
+                            const double* table, double dt, void* stream);
 
 #ifdef __cplusplus
 }

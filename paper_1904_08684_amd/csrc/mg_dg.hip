@@ -5,10 +5,20 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "dg.h"
 #include "mg.h"
 
+
+// The allocation-free RK step (dg_ssp_rk3_step_noalloc) keeps the saved
+// state and the right-hand side (6 K ne doubles) in this fixed device array
+// instead of caller scratch: 64 MiB, held on every device the library runs
+// on until the process ends.  In host code the name stands for a host-side
+// shadow: only the address from hipGetSymbolAddress (one per device) may be
+// passed to kernels or copies.
+constexpr long long kDgScratchDoubles = 1LL << 23;
+static __device__ __align__(256) double scratch[kDgScratchDoubles];
 
 namespace {
 
@@ -729,6 +739,68 @@ bool ghosts_ok(long long nb, const double* cb, const double* ub) {
     return nb >= 0 && nb <= 0x7fffffffLL && (nb == 0 || (cb && ub));
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call on that device (with it current) and kept.
+int scratch_address(double** out) {
+    int dev = -1;
+    if (int rc = dg_status(hipGetDevice(&dev), "current device")) return rc;
+    if (dev < 0 || dev >= kMaxDevices) {
+        snprintf(g_dg_error, sizeof g_dg_error, "device %d beyond the scratch table", dev);
+        return MG_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (int rc = dg_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address")) return rc;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MG_OK;
+}
+
+// One SSP-RK3 step with the saved state and the right-hand side in work
+// (6 K ne doubles): the body of both RK entry points.
+int rk3_step(int k, long long ne, double* c, double* u, double* work, const double* B, const double* hb,
+             const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3, double g, double tau,
+             double fc, const double* F3, const double* ref, const double* T, const double* table, double dt,
+             void* stream) {
+    const int K = k_of(k);
+    if (!K || !dg_size_ok(ne) || !ghosts_ok(nb, cb3, ub3) || !std::isfinite(dt)) return MG_EINVAL;
+    if (ne == 0) return MG_OK;
+    if (!c || !u || !work || !B || !hb || !nbr || !nq || !ref || !T || !table) return MG_EINVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long n = 3LL * K * ne;
+    double* c0 = work;
+    double* r = work + n;
+    dg_begin();
+    const int cp = dg_status(hipMemcpyAsync(c0, c, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st),
+                             "copy of the state");
+    if (cp != MG_OK) return cp;
+    const double wa[3] = {0.0, 0.75, 1.0 / 3.0}, wb[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int s = 0; s < 3; ++s) {
+        // the stage's velocity: projected inside the volume pass up to order
+        // 2; at order 3 the projection's serial Cholesky chain runs faster
+        // on its own (three wavefronts per SIMD against two in the fused
+        // pass) than the saved traffic is worth
+        const bool fuse = K <= 6;
+        int rc = fuse ? MG_OK : launch_project(K, ne, c, B, hb, T, u, st);
+        if (rc == MG_OK)
+            rc = launch_volume(K, true, ne, c, u, B, hb, g, ref, r, tau, fc, F3 ? F3 + s * n : nullptr, st, fuse,
+                               T, u);
+        if (rc == MG_OK)
+            rc = launch_edges(K, true, ne, c, u, B, hb, nbr, nq, nb, nb ? cb3 + s * 3LL * K * nb : nullptr,
+                              nb ? ub3 + s * 2LL * K * nb : nullptr, g, table, r, st);
+        if (rc == MG_OK) rc = launch_stage(n, wa[s], c0, wb[s], c, dt, r, st);
+        if (rc != MG_OK) return rc;
+    }
+    return MG_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -873,36 +945,29 @@ int dg_ssp_rk3_step(int k, long long ne, double* c, double* u, double* work, con
                     const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3, double g,
                     double tau, double fc, const double* F3, const double* ref, const double* T,
                     const double* table, double dt, void* stream) {
+    if (ne > 0 && !work) return MG_EINVAL;
+    return rk3_step(k, ne, c, u, work, B, hb, nbr, nq, nb, cb3, ub3, g, tau, fc, F3, ref, T, table, dt, stream);
+}
+
+int dg_ssp_rk3_step_noalloc(int k, long long ne, double* c, double* u, const double* B, const double* hb,
+                            const int* nbr, const int* nq, long long nb, const double* cb3, const double* ub3,
+                            double g, double tau, double fc, const double* F3, const double* ref, const double* T,
+                            const double* table, double dt, void* stream) {
+    g_dg_error[0] = 0;
     const int K = k_of(k);
-    if (!K || !dg_size_ok(ne) || !ghosts_ok(nb, cb3, ub3) || !std::isfinite(dt)) return MG_EINVAL;
-    if (ne == 0) return MG_OK;
-    if (!c || !u || !work || !B || !hb || !nbr || !nq || !ref || !T || !table) return MG_EINVAL;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    const long long n = 3LL * K * ne;
-    double* c0 = work;
-    double* r = work + n;
-    dg_begin();
-    const int cp = dg_status(hipMemcpyAsync(c0, c, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st),
-                             "copy of the state");
-    if (cp != MG_OK) return cp;
-    const double wa[3] = {0.0, 0.75, 1.0 / 3.0}, wb[3] = {1.0, 0.25, 2.0 / 3.0};
-    for (int s = 0; s < 3; ++s) {
-        // the stage's velocity: projected inside the volume pass up to order
-        // 2; at order 3 the projection's serial Cholesky chain runs faster
-        // on its own (three wavefronts per SIMD against two in the fused
-        // pass) than the saved traffic is worth
-        const bool fuse = K <= 6;
-        int rc = fuse ? MG_OK : launch_project(K, ne, c, B, hb, T, u, st);
-        if (rc == MG_OK)
-            rc = launch_volume(K, true, ne, c, u, B, hb, g, ref, r, tau, fc, F3 ? F3 + s * n : nullptr, st, fuse,
-                               T, u);
-        if (rc == MG_OK)
-            rc = launch_edges(K, true, ne, c, u, B, hb, nbr, nq, nb, nb ? cb3 + s * 3LL * K * nb : nullptr,
-                              nb ? ub3 + s * 2LL * K * nb : nullptr, g, table, r, st);
-        if (rc == MG_OK) rc = launch_stage(n, wa[s], c0, wb[s], c, dt, r, st);
-        if (rc != MG_OK) return rc;
+    if (!K || ne < 0) return MG_EINVAL;
+    if (6LL * K * ne > kDgScratchDoubles) {
+        snprintf(g_dg_error, sizeof g_dg_error, "6 K ne = %lld doubles exceed the fixed scratch of %lld", 6LL * K * ne,
+                 kDgScratchDoubles);
+        return MG_EINVAL;
     }
-    return MG_OK;
+    if (ne == 0) return rk3_step(k, ne, c, u, nullptr, B, hb, nbr, nq, nb, cb3, ub3, g, tau, fc, F3, ref, T, table, dt,
+                                 stream);
+    if (!c || !u || !B || !hb || !nbr || !nq || !ref || !T || !table) return MG_EINVAL;
+    dg_begin();
+    double* w = nullptr;
+    if (int rc = scratch_address(&w)) return rc;
+    return rk3_step(k, ne, c, u, w, B, hb, nbr, nq, nb, cb3, ub3, g, tau, fc, F3, ref, T, table, dt, stream);
 }
 
 }  // extern "C"

@@ -454,6 +454,8 @@ _dsigs = {
                          C.c_double, C.c_double, _P, _P, _P, _P, _P]),
     "dg_ssp_rk3_step": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, _P, C.c_longlong, _P, _P,
                                   C.c_double, C.c_double, C.c_double, _P, _P, _P, _P, C.c_double, _P]),
+    "dg_ssp_rk3_step_noalloc": (C.c_int, [C.c_int, C.c_longlong, _P, _P, _P, _P, _P, _P, C.c_longlong, _P, _P,
+                                          C.c_double, C.c_double, C.c_double, _P, _P, _P, _P, C.c_double, _P]),
 }
 for _name, (_res, _args) in _dsigs.items():
     _fn = getattr(lib, _name)
@@ -655,3 +657,19 @@ class DGSystem:
         _dgc(dg_ssp_rk3_step(self.k, self.ne, _dptr(c), _dptr(u), _dptr(self.work), _dptr(self.B), _dptr(self.hb),
                                _dptr(self.nbr), _dptr(self.nq), self.nb, pcb, pub, self.g, self.tau, self.fc, _dptr(F3),
                                _dptr(self.ref), _dptr(self.T), _dptr(self.tab), dt, _stream(stream, c.device)))
+
+    def step_noalloc(self, c, u, dt: float, cb3=None, ub3=None, F3=None, stream=None):
+        """As step, through dg_ssp_rk3_step_noalloc: the stage scratch is the
+        library's fixed device array (6 K ne <= 2^23 doubles) instead of
+        self.work."""
+        import torch
+        _dg_check(((c, 3 * self.K), (u, 2 * self.K)), self.ne)
+        if F3 is not None:
+            if (F3.dtype != torch.float64 or not F3.is_cuda or not F3.is_contiguous()
+                    or tuple(F3.shape) != (3, 3 * self.K, self.ne)):
+                raise ValueError("F3 must be a contiguous FP64 device tensor (3, 3K, ne)")
+        pcb, pub = _dg_ghosts(self.K, self.nb, cb3, ub3, stages=3)
+        _dgc(dg_ssp_rk3_step_noalloc(self.k, self.ne, _dptr(c), _dptr(u), _dptr(self.B), _dptr(self.hb),
+                                       _dptr(self.nbr), _dptr(self.nq), self.nb, pcb, pub, self.g, self.tau, self.fc,
+                                       _dptr(F3), _dptr(self.ref), _dptr(self.T), _dptr(self.tab), dt,
+                                       _stream(stream, c.device)))

@@ -166,3 +166,17 @@ def test_galerkin_option_validation(mg):
                   (mg.make_grid(3, 65), {"smoother": mg.MG_JACOBI, "coarse_op": 2})):
         o = mg.make_opts(**{"coarse_op": mg.MG_COARSE_GALERKIN, **kw})
         assert mg.mg_workspace_bytes(C.byref(g), None, C.byref(o), C.byref(b)) == mg.MG_EINVAL, kw
+
+
+def test_noalloc_rk_step_refuses_sizes_beyond_its_array(mg):
+    """dg_ssp_rk3_step_noalloc checks 6 K ne against its fixed 2^23-double
+    device array before touching any argument or the device."""
+    for k, K in ((0, 1), (1, 3), (3, 10)):
+        ne = (1 << 23) // (6 * K) + 1
+        code = mg.dg_ssp_rk3_step_noalloc(k, ne, None, None, None, None, None, None, 0, None, None, 9.81, 0.0, 0.0,
+                                          None, None, None, None, 1.0, None)
+        assert code == mg.MG_EINVAL
+        assert b"exceed the fixed scratch" in mg.dg_last_error()
+    code = mg.dg_ssp_rk3_step_noalloc(3, 1000, None, None, None, None, None, None, 0, None, None, 9.81, 0.0, 0.0,
+                                      None, None, None, None, 1.0, None)
+    assert code == mg.MG_EINVAL and mg.dg_last_error() == b""
