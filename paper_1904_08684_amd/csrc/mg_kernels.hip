@@ -13,6 +13,9 @@
 // operation rounds exactly as the written formula does.
 
 #include <cmath>
+#include <type_traits>
+#include <utility>
+
 #include <hip/hip_runtime.h>
 
 #include "mg_kernels.h"
@@ -557,6 +560,16 @@ __device__ __forceinline__ float div6(float a) {
 // result is bitwise that of S separate half-sweeps.  The output goes to a
 // second buffer (a neighbouring block may still read the iterate); both
 // colours of every interior node are written, boundary nodes stay zero.
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full __syncthreads waits for every
+// outstanding load, which would expose the latency the one-step-ahead loads
+// are meant to hide).  Only LDS carries data between the block's waves here.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t rsc, unsigned voff, int soff) {
     if constexpr (sizeof(T) == 8)
@@ -565,11 +578,6 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t rsc, unsigned voff,
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsc, voff, soff, 0));
 }
 
-// BUF: fields below 2 GiB are read through buffer resources, the lane's byte
-// offset in a vector register and the row's in a scalar one (no per-load
-// 64-bit address arithmetic).  Offsets stay inside the field (planes are
-// clamped as in the plain path), so the range check never clips a value
-// that is used.
 template <typename T, int S, int R, int NW, int PF, bool P2, bool BUF>
 __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, const T* __restrict__ uin,
                                                         const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
@@ -706,6 +714,208 @@ __global__ __launch_bounds__(64 * NW) void k_node_gs_tb(Geom g, TbSpace ts, cons
         }
         __syncthreads();
     }
+}
+
+// Calls f(integral_constant<int, I>) for I = B .. E - 1 (compile-time indices
+// for register arrays in unrolled bodies).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <int X>
+constexpr int md2() { return ((X % 2) + 2) % 2; }
+
+// The same fused pass as k_node_gs_tb (same regions, halos, chunks, operand
+// order and output), written for fewer instructions per point update.
+// BUF: fields below 2 GiB are read through buffer resources, the lane's byte
+// offset in a vector register and the plane's in a scalar one (no per-load
+// 64-bit address arithmetic).  Offsets stay inside the field (planes are
+// clamped at the ends of the grid), so the range check never clips a value
+// that is used.  Barriers order LDS only (lds_barrier), so the loads issued
+// one step ahead stay in flight across them.
+//
+// Instruction economy.  The x parity of the point a thread updates is the
+// same for every stage of a step and alternates with the row and the step,
+// and stage k keeps its planes p - 1 and p in two register slots chosen by
+// the plane's parity: the march is unrolled two steps at a time (relative to
+// the chunk's first step) so that every slot index, x-neighbour offset and
+// lane mask is fixed at compile time.  Pairs of steps whose planes all lie
+// inside the grid and whose final stages all store run without clamps or
+// plane tests; the lead-in and lead-out pairs test each step.
+template <typename T, int S, int R, int NW, int PF, bool P2, bool BUF>
+__global__ __launch_bounds__(64 * NW) void k_node_gs_tbu(Geom g, TbSpace ts, const T* __restrict__ uin,
+                                                        const T* __restrict__ f, T* __restrict__ uout, T s, T rs,
+                                                        int c1, int zero) {
+    constexpr int W = kTbLanes, RY = NW * R, LP = W + 2, LR = RY + 2, H = (S + 1) / 2;
+    __shared__ T lds[S][LR][LP];
+    {
+        T* lf = &lds[0][0][0];
+        for (int i = (int)threadIdx.x; i < S * LR * LP; i += (int)blockDim.x) lf[i] = T(0);
+    }
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tx = b % ts.ntx, ty = (b / ts.ntx) % ts.nty, tz = b / (ts.ntx * ts.nty);
+    const int lane = (int)threadIdx.x & 63;
+    // rows belong to whole wavefronts: everything that depends on y or z only
+    // is wavefront-uniform and lives in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int n = g.n;
+    const int xg = tx * (W - 2 * H) - H + lane;
+    const int Z0 = 1 + tz * ts.zc, Z1 = min(Z0 + ts.zc, n - 1);
+    const int c0 = 1 - c1;
+    const long long cs = g.cs, pl = g.plane;
+    // lane offset of every access: x >> 1 clamped into the row (values of
+    // positions outside the grid are masked, never their addresses)
+    const int xo = min(max(xg, 0), g.half - 1);
+    const bool xreg = xg >= 0 && xg < g.half;
+    const bool xin0 = xreg && xg >= 1 && 2 * xg <= n - 2;   // x = 2 (x >> 1) is an unknown column
+    const bool xin1 = xreg && 2 * xg + 1 <= n - 2;           // x = 2 (x >> 1) + 1 is
+    const bool xout = xreg && lane >= H && lane < W - H;
+    const int ly0 = 1 + wv * R;                               // the wavefront's first LDS row
+    const int t0 = Z0 - S;
+    // The point of row r updated at step t has x parity (y + t + c1 + 1) & 1
+    // in every stage; rows being consecutive, that is pw ^ ((r + rel) & 1)
+    // with rel = t - t0.  Per parity class q: the x-neighbour's LDS offset,
+    // the unknown mask and the store mask.
+    const int yw = ty * (RY - 2 * S) - S + wv * R;             // the wavefront's first row
+    const int pw = (yw + t0 + c1 + 1) & 1;
+    int dx[2];
+    bool m[2][R], sm[2][R];
+    unsigned vo[R];                                            // byte offset of the lane in row r
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const bool odd = (pw ^ q) != 0;
+        dx[q] = odd ? 1 : -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yw + r;
+            const bool yin = y >= 1 && y <= n - 2;
+            const bool yout = wv * R + r >= S && wv * R + r < RY - S && y <= n - 2;
+            m[q][r] = yin && (odd ? xin1 : xin0);
+            sm[q][r] = yout && xout && (odd ? xin1 : xin0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        vo[r] = (unsigned)(((long long)min(max(yw + r, 0), n - 1) * g.pitch + xo) * (long long)sizeof(T));
+    // (unused without BUF; the byte count is only meaningful below 2 GiB)
+    const int fbytes = BUF ? (int)(2 * cs * (long long)sizeof(T)) : 0;
+    const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(uin), 0, fbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f), 0, fbytes, 0x00020000);
+    // element offset of (colour c, plane p), p clamped into the grid where
+    // it may leave it
+    auto poff = [&](auto gc, int c, int p) -> long long {
+        if constexpr (decltype(gc)::value) p = min(max(p, 0), n - 1);
+        return c * cs + (long long)p * pl;
+    };
+    auto ld = [&](const T* base, __amdgpu_buffer_rsrc_t rsc, long long e, int r) -> T {
+        if constexpr (BUF) return buf_load<T>(rsc, vo[r], (int)(e * (long long)sizeof(T)));
+        else return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + e) + vo[r]);
+    };
+    auto pin = [&](int p) { return p >= 1 && p <= n - 2; };
+    // A[k][i][r]: stage k's value in row r on the plane p with p - t0 = i
+    // mod 2 (stage 0 is the iterate), the two planes behind stage k's
+    // newest; nw[r]: the newest value of the stage just computed.
+    // Right-hand-side and iterate loads run one step ahead: qu = iterate on
+    // plane t, qf[k - 1] = right-hand side of stage k <= PF on plane t - k
+    // (later stages re-read it from L2).
+    T A[S][2][R], nw[R], qu[R], qf[PF > 0 ? PF : 1][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        qu[r] = zero ? T(0) : ld(uin, ru, poff(std::true_type{}, c0, t0), r);
+#pragma unroll
+        for (int k = 1; k <= PF; ++k) qf[k - 1][r] = ld(f, rf, poff(std::true_type{}, (c1 + k - 1) & 1, t0 - k), r);
+        nw[r] = T(0);
+#pragma unroll
+        for (int k = 0; k < S; ++k) A[k][0][r] = A[k][1][r] = T(0);
+    }
+    __syncthreads();
+    // one step of the march: J = (t - t0) mod 2; GEN: planes and stores tested
+    auto step = [&](auto jc, auto gc, const int t) {
+        constexpr int J = decltype(jc)::value;
+        constexpr bool GEN = decltype(gc)::value;
+        // stage k's plane t - 1 - k becomes visible to stage k + 1
+        static_for<0, S>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[k][ly0 + r][1 + lane] = A[k][md2<J - 1 - k>()][r];
+        });
+        lds_barrier();
+        {
+            const bool p0 = !GEN || pin(t);
+            const long long e = poff(gc, c0, t + 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                nw[r] = (p0 && m[(r + J) & 1][r]) ? qu[r] : T(0);
+                if (!zero) qu[r] = ld(uin, ru, e, r);
+            }
+        }
+        static_for<1, S + 1>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            // keep each stage's LDS reads and loads in its own stretch of code
+            // (hoisting them all to the top of the step runs out of registers)
+            __builtin_amdgcn_sched_barrier(0);
+            const int p = t - k, ck = (c1 + k - 1) & 1;
+            const bool pk = !GEN || pin(p);
+            const bool st = k >= S - 1 && (!GEN || (p >= Z0 && p < Z1));
+            const long long ef = poff(gc, ck, k <= PF ? p + 1 : p);
+            T* const dstp = uout + (ck * cs + (long long)p * pl);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r > 0) __builtin_amdgcn_sched_barrier(0);
+                const int q = (r + J) & 1;
+                const T* lrow = &lds[k - 1][ly0 + r][1 + lane];
+                // x neighbours (own position and the lane beside it), y - 1,
+                // y + 1, z - 1, z + 1: the half-sweep's order
+                T nb = A[k - 1][md2<J - k>()][r];
+                nb = nb + lrow[dx[q]];
+                nb = nb + lrow[-LP];
+                nb = nb + lrow[LP];
+                nb = nb + A[k - 1][md2<J - k - 1>()][r];
+                nb = nb + nw[r];
+                T fv;
+                if constexpr (k <= PF) {
+                    fv = qf[k - 1][r];
+                    qf[k - 1][r] = ld(f, rf, ef, r);
+                } else {
+                    fv = ld(f, rf, ef, r);
+                }
+                // s is a power of two when P2: f * (1 / s) rounds exactly as f / s
+                T v = div6((P2 ? fv * rs : fv / s) + nb);
+                v = (pk && m[q][r]) ? v : T(0);
+                if (st && pk && sm[q][r]) {
+                    // FP64 output streams past the L2 (less eviction of the halo
+                    // and right-hand-side planes later stages re-read)
+                    T* dst = reinterpret_cast<T*>(reinterpret_cast<char*>(dstp) + vo[r]);
+                    if constexpr (sizeof(T) == 8) __builtin_nontemporal_store(v, dst);
+                    else *dst = v;
+                }
+                // stage k - 1's plane p + 1 takes the slot of its plane p - 1
+                A[k - 1][md2<J - k - 1>()][r] = nw[r];
+                nw[r] = v;
+            }
+        });
+        lds_barrier();
+    };
+    // Steps t0 .. Z1 + S - 1 in pairs: lead-in pairs, the pairs whose planes
+    // all lie inside the grid (t >= Z0 + S) and whose final stages all store
+    // (t + 2 - S < Z1, t + 2 <= n - 2), then the rest.  Three separate loops:
+    // one loop with both bodies behind a branch makes the register allocator
+    // spill.
+    const int N = Z1 - Z0 + 2 * S;
+    auto gen = [&](int rel) {
+        static_for<0, 2>([&](auto jc) {
+            if (rel + decltype(jc)::value < N) step(jc, std::true_type{}, t0 + rel + decltype(jc)::value);
+        });
+    };
+    int rel = 0;
+    for (; rel < 2 * S && rel < N; rel += 2) gen(rel);
+    for (; rel + 2 < N && t0 + rel + 2 <= n - 2; rel += 2)
+        static_for<0, 2>([&](auto jc) { step(jc, std::false_type{}, t0 + rel + decltype(jc)::value); });
+    for (; rel < N; rel += 2) gen(rel);
 }
 
 // ------------------------------------ 3-D node grids, fused transfer kernels
@@ -1799,6 +2009,10 @@ hipError_t launch_gs(const Geom& g, int prec, int colour, bool zero, void* u, co
                 : gs_t<double>(g, colour, zero, u, f, fc, s, st);
 }
 
+// FP64 levels run the rolled march (k_node_gs_tb), FP32 levels the
+// pair-unrolled one (k_node_gs_tbu): with FP64 values the unrolled march
+// needs more registers than three wavefronts per SIMD leave and measured
+// slower, while on FP32 fields it is 20 % (513^3) to 40 % (257^3) faster.
 template <typename T, int S, int R, int NW, int PF>
 static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void* f, void* out, double s,
                          hipStream_t st) {
@@ -1806,35 +2020,42 @@ static void gs_tb_launch(const Geom& g, int c1, int z, const void* u, const void
     const dim3 grid((unsigned)ts.blocks()), block(64 * NW);
     int e;
     const bool p2 = s > 0.0 && std::frexp(s, &e) == 0.5;   // s = 2^(e - 1)
-    // buffer loads measured 2.6 % faster for FP64 and 19 % slower for FP32
-    const bool buf = sizeof(T) == 8 && 2 * g.cs * (long long)sizeof(T) < (1LL << 31);
+    const bool buf = 2 * g.cs * (long long)sizeof(T) < (1LL << 31);
     const T rs = (T)(1.0 / s);
-    if (p2 && buf)
-        k_node_gs_tb<T, S, R, NW, PF, true, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
-                                                                          (T)s, rs, c1, z);
-    else if (p2)
-        k_node_gs_tb<T, S, R, NW, PF, true, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
-                                                                           (T)s, rs, c1, z);
-    else if (buf)
-        k_node_gs_tb<T, S, R, NW, PF, false, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
-                                                                           (T)s, rs, c1, z);
-    else
-        k_node_gs_tb<T, S, R, NW, PF, false, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),
-                                                                            (T)s, rs, c1, z);
+#define MG_TB(KERNEL)                                                                                        \
+    if (p2 && buf)                                                                                           \
+        KERNEL<T, S, R, NW, PF, true, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, \
+                                                                    rs, c1, z);                             \
+    else if (p2)                                                                                             \
+        KERNEL<T, S, R, NW, PF, true, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),    \
+                                                                     (T)s, rs, c1, z);                      \
+    else if (buf)                                                                                            \
+        KERNEL<T, S, R, NW, PF, false, true><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),    \
+                                                                     (T)s, rs, c1, z);                      \
+    else                                                                                                     \
+        KERNEL<T, S, R, NW, PF, false, false><<<grid, block, 0, st>>>(g, ts, cp<T>(u), cp<T>(f), mp<T>(out),   \
+                                                                      (T)s, rs, c1, z);
+    if constexpr (sizeof(T) == 8) {
+        MG_TB(k_node_gs_tb)
+    } else {
+        MG_TB(k_node_gs_tbu)
+    }
+#undef MG_TB
 }
 
 template <typename T>
 static hipError_t gs_tb_t(const Geom& g, int sweeps, int c1, bool zero, const void* u, const void* f, void* out,
                           double s, hipStream_t st) {
-    // rows per thread: registers (two planes of every stage per row, plus the
-    // operands in flight) and LDS (one plane of every stage) grow with S x R;
-    // these are the largest that stay within 128 VGPRs and 160 KB
+    // rows per thread and wavefronts per block: registers (two planes of
+    // every stage per row, plus the operands in flight) and LDS (one plane of
+    // every stage) grow with S x R; these shapes measured fastest among those
+    // that do not spill
     constexpr bool dp = sizeof(T) == 8;
     const int z = zero ? 1 : 0;
     switch (sweeps) {
         case 1: gs_tb_launch<T, 2, 3, 16, 2>(g, c1, z, u, f, out, s, st); break;
         case 2: gs_tb_launch<T, 4, dp ? 3 : 4, 16, 4>(g, c1, z, u, f, out, s, st); break;
-        case 3: gs_tb_launch<T, 6, dp ? 3 : 4, dp ? 12 : 16, 6>(g, c1, z, u, f, out, s, st); break;
+        case 3: gs_tb_launch<T, 6, 3, dp ? 12 : 16, 6>(g, c1, z, u, f, out, s, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
