@@ -33,9 +33,16 @@ even ghosts, and the finest iterate is projected to zero mean after every
 cycle, which fixes the constant the operator cannot see.
 
 ``mixed_solve`` is FP64 iterative refinement around single-precision
-V-cycles: r = f - A u in FP64, sigma = 2^floor(log2 max|r|), c = V32(0,
-fl32(r / sigma)), u <- u + sigma * fl64(c).  The power-of-two scale adds no
-rounding.
+V-cycles: r_k = f - A u_k in FP64, c = V32(0, fl32(r_k / sigma_k)),
+u_{k+1} = u_k + sigma_k * fl64(c), with the power-of-two scale
+sigma_k = 2^floor(log2 m_k), m_k the largest |r| of the previous step's
+residual r_{k-1} (of r_0 itself in the first step).  A power-of-two scale
+adds no rounding, and every operation of the single-precision cycle commutes
+with it, so away from FP32 underflow and overflow the iterates do not depend
+on which power of two is taken; the scale only keeps the single-precision
+values in range when the residual is tiny or huge.  Taking the previous
+residual's maximum lets an implementation scale the residual while it is
+formed.
 """
 from __future__ import annotations
 
@@ -339,24 +346,29 @@ def pow2_scale(maxabs: float) -> float:
     return float(np.ldexp(1.0, int(e) - 1))
 
 
-def mixed_solve(h: Hierarchy, f, tol=1e-10, max_outer=100, inner=np.float32):
+def mixed_solve(h: Hierarchy, f, tol=1e-10, max_outer=100, inner=np.float32, scale="previous"):
     """FP64 iterative refinement with single-precision V-cycles, from u = 0.
+    scale: "previous" (sigma_k from the previous step's residual, the first
+    step's from its own) or "current" (sigma_k from r_k itself).
     Returns (u, relres history ||r_k|| / ||f||)."""
     if neumann(h):
         raise ValueError("mixed-precision refinement is for Dirichlet problems")
     u = np.zeros_like(f, dtype=np.float64)
     hist = []
     r0 = None
+    m_prev = None
     for _ in range(max_outer + 1):
         r = residual(h, 0, u, f)
         ru = np.asarray(unknowns(h, r))
         nrm = float(np.sqrt(np.sum(ru * ru)))
+        m_cur = float(np.max(np.abs(ru)))
         if r0 is None:
             r0 = nrm
         hist.append(nrm / r0 if r0 else 0.0)
         if r0 == 0.0 or hist[-1] <= tol or len(hist) > max_outer:
             break
-        sigma = pow2_scale(float(np.max(np.abs(ru))))
+        sigma = pow2_scale(m_cur if (scale == "current" or m_prev is None) else m_prev)
+        m_prev = m_cur
         r32 = (r / sigma).astype(inner)
         c = vcycle(h, np.zeros_like(r32), r32)
         u = u + sigma * c.astype(np.float64)

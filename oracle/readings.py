@@ -25,7 +25,8 @@ READINGS = {
     "R8": "'257^3 cells' is read as 256^3 cells (257 vertices per axis).",
     "R9": "Coarse face coefficient = mean of the fine faces that tile the coarse face.",
     "R10": "Mixed precision: one single-precision V-cycle per FP64 refinement step, "
-           "scale 2^floor(log2 max|r|).",
+           "scale 2^floor(log2 m), m = max|r| of the previous step's residual (the first "
+           "step's own); any power of two gives the same iterates away from FP32 under/overflow.",
     "R11": "Norm = unweighted 2-norm over the unknowns; relative to the initial residual.",
     "R12": "Stopping counts may differ by one cycle when ||r|| crosses tol within rounding; "
            "parity is judged on iterates at equal cycle counts.",

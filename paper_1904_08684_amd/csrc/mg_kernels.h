@@ -77,18 +77,28 @@ hipError_t launch_residual27(const Geom& g, const void* u, const void* f, void* 
 hipError_t launch_project(const Geom& g, double* a, double* partials, double* scratch, double* out,
                           hipStream_t st);
 
+// Fixed-order reduction of (sum, max) partial pairs into out[0..1]; with
+// mx_copy the maximum is also stored there.
 hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
-                         hipStream_t st);
+                         hipStream_t st, double* mx_copy = nullptr);
 long long reduce_scratch_pairs(long long count);
 
 // natural FP64 array <-> colour-split level field (node grids: interior only).
 hipError_t launch_pack(const Geom& g, int prec, const double* nat, void* split, hipStream_t st);
 hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat, hipStream_t st);
 
-// Mixed precision: sigma = 2^floor(log2 red[1]) (red[1] = max|r|), stored to
-// *sigma; f32 = fl32(r64 / sigma).  And u64 += sigma * c32.
-hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* red, double* sigma,
+// Mixed precision: sigma = 2^floor(log2 *basis) (basis: the largest |r| of
+// the refinement's previous residual), stored to *sigma; f32 = fl32(r64 /
+// sigma).  And u64 += sigma * c32.
+hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* basis, double* sigma,
                        hipStream_t st);
+// r = f - A u on a 3-D node level where use_zmarch holds (FP64), written as
+// f32 = fl32(r / sigma) with sigma = 2^floor(log2 *basis) stored to *sigma,
+// and per-block (sum r^2, max |r|) partials: the residual and the cast of a
+// refinement step in one pass.  *nblocks is set as by launch_residual.
+hipError_t launch_residual_cast(const Geom& g, const void* u, const void* f, float* f32, double s,
+                                const double* basis, double* sigma, double* partials, long long* nblocks,
+                                hipStream_t st);
 hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
                          hipStream_t st);
 // Groups of four elements in one level field (both colours, padding included).

@@ -82,7 +82,7 @@ __device__ __forceinline__ long long row_off(const Geom& g, int y, int z) {
 // Fixed-order block reduction of (sum, max) over all threads of the block
 // (a power of two, at most 1024): a shuffle tree inside each wavefront, then
 // thread 0 adds the wavefront results in order.  Deterministic.
-__device__ void block_sum_max(double sq, double mx, double* out2) {
+__device__ void block_sum_max(double sq, double mx, double* out2, double* mx_copy = nullptr) {
     __shared__ double s_sq[16];
     __shared__ double s_mx[16];
     const int nt = (int)(blockDim.x * blockDim.y * blockDim.z);
@@ -105,6 +105,7 @@ __device__ void block_sum_max(double sq, double mx, double* out2) {
         }
         out2[0] = a;
         out2[1] = b;
+        if (mx_copy) *mx_copy = b;
     }
 }
 
@@ -301,10 +302,12 @@ __global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __res
 
 // r = f - A u at both colours of the thread's column; both colours' z-1, z,
 // z+1 values stay in registers, U planes per step.
-template <typename T, int U, bool NT, bool NORM, bool STORE>
+// CAST (FP64): the residual is stored as r32 = fl32(r / sigma) instead of r.
+template <typename T, int U, bool NT, bool NORM, bool STORE, bool CAST = false>
 __device__ __forceinline__ void d_node_res_zm(const Ex& ex, Geom g, ZSpace zs, const T* __restrict__ u,
                                                       const T* __restrict__ f, T* __restrict__ r, T s,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, float* __restrict__ r32 = nullptr,
+                                                      double sigma = 1.0) {
     double sq = 0.0, mx = 0.0;
     int tx, ty, tz;
     zm_tile(zs, ex.b, tx, ty, tz);
@@ -331,7 +334,8 @@ __device__ __forceinline__ void d_node_res_zm(const Ex& ex, Geom g, ZSpace zs, c
             nb = nb + zm;
             nb = nb + zp;
             const T v = fv - (T(6) * uc - nb) * s;
-            if (STORE) st_stream<NT>(r + at, v);
+            if constexpr (CAST) st_stream<NT>(r32 + at, (float)((double)v / sigma));
+            else if (STORE) st_stream<NT>(r + at, v);
             const double dv = (double)v;
             sq = sq + dv * dv;
             mx = fmax(mx, fabs(dv));
@@ -1472,7 +1476,7 @@ __global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, 
 }
 
 __device__ __forceinline__ void d_reduce(const Ex& ex, const double* __restrict__ in, long long count,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, double* mx_copy = nullptr) {
     const long long i0 = (long long)ex.b * kReduceChunk;
     const long long i1 = i0 + kReduceChunk < count ? i0 + kReduceChunk : count;
     double sq = 0.0, mx = 0.0;
@@ -1480,12 +1484,12 @@ __device__ __forceinline__ void d_reduce(const Ex& ex, const double* __restrict_
         sq = sq + in[2 * i];
         mx = fmax(mx, in[2 * i + 1]);
     }
-    block_sum_max(sq, mx, out + 2 * (long long)ex.b);
+    block_sum_max(sq, mx, out + 2 * (long long)ex.b, mx_copy);
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, long long count,
-                                                double* __restrict__ out) {
-    d_reduce(solo_ex(), in, count, out);
+                                                double* __restrict__ out, double* mx_copy) {
+    d_reduce(solo_ex(), in, count, out, mx_copy);
 }
 
 // ------------------------------------------------------ layout conversion
@@ -1560,13 +1564,27 @@ __device__ __forceinline__ void d_cast(const Ex& ex, long long n4, const double*
     reinterpret_cast<float4*>(f32)[i] = o;
 }
 
+// The residual and the cast of a refinement step in one pass: sigma comes
+// from the previous residual's maximum (*basis), so it is known before r is.
+template <int U, bool NT>
+__global__ __launch_bounds__(1024) void k_node_res_cast_zm(Geom g, ZSpace zs, const double* __restrict__ u,
+                                                           const double* __restrict__ f, float* __restrict__ r32,
+                                                           double s, const double* __restrict__ basis,
+                                                           double* __restrict__ sigma_out,
+                                                           double* __restrict__ part) {
+    const double sigma = pow2_floor(basis[0]);
+    const Ex ex = solo_ex();
+    if (ex.b == 0 && ex.t == 0) *sigma_out = sigma;
+    d_node_res_zm<double, U, NT, true, true, true>(ex, g, zs, u, f, nullptr, s, part, r32, sigma);
+}
+
 __global__ __launch_bounds__(256) void k_cast(long long n4, const double* __restrict__ r, float* __restrict__ f32,
-                                              const double* __restrict__ red, double* __restrict__ sigma_out) {
+                                              const double* __restrict__ basis, double* __restrict__ sigma_out) {
     Ex ex;
     ex.b = (int)blockIdx.x;
     ex.t = (int)threadIdx.x;
     ex.nt = (int)blockDim.x;
-    d_cast(ex, n4, r, f32, red, sigma_out);
+    d_cast(ex, n4, r, f32, basis, sigma_out);
 }
 
 __device__ __forceinline__ void d_update(const Ex& ex, long long n4, double* __restrict__ u,
@@ -1781,7 +1799,8 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
                 sq = sq + it.part[2 * i];
                 mx = fmax(mx, it.part[2 * i + 1]);
             }
-            block_sum_max(sq, mx, it.red);
+            // m: the maximum also becomes the scale basis of the next cast
+            block_sum_max(sq, mx, it.red, it.m ? it.red + 3 : nullptr);
             if (ex.t == 0 && it.res) {
                 it.res[0] = it.red[0];
                 it.res[1] = it.red[1];
@@ -1789,7 +1808,7 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
             break;
         }
         case BOP_CAST:
-            d_cast(ex, it.n, static_cast<const double*>(it.a), static_cast<float*>(it.b), it.red, it.red + 2);
+            d_cast(ex, it.n, static_cast<const double*>(it.a), static_cast<float*>(it.b), it.red + 3, it.red + 2);
             break;
         case BOP_GS:
         case BOP_GS_ZERO: {
@@ -2315,20 +2334,20 @@ hipError_t launch_project(const Geom& g, double* a, double* partials, double* sc
 }
 
 hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
-                         hipStream_t st) {
+                         hipStream_t st, double* mx_copy) {
     const double* in = partials;
     double* buf = scratch;
     if (count < 1) return hipErrorInvalidValue;
     while (count > 1) {
         const long long nb = (count + kReduceChunk - 1) / kReduceChunk;
         double* dst = (nb == 1) ? out : buf;
-        k_reduce<<<(unsigned)nb, 256, 0, st>>>(in, count, dst);
+        k_reduce<<<(unsigned)nb, 256, 0, st>>>(in, count, dst, nb == 1 ? mx_copy : nullptr);
         in = dst;
         buf += 2 * nb;
         count = nb;
     }
     if (in != out) {   // a single partial pair: copy it through the reduce kernel
-        k_reduce<<<1, 256, 0, st>>>(in, 1, out);
+        k_reduce<<<1, 256, 0, st>>>(in, 1, out, mx_copy);
     }
     return hipGetLastError();
 }
@@ -2355,10 +2374,26 @@ hipError_t launch_unpack(const Geom& g, int prec, const void* split, double* nat
 
 long long field_quads(const Geom& g) { return g.cs / 2; }   // 2 cs elements, 4 per thread
 
-hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* red, double* sigma,
+hipError_t launch_cast(const Geom& g, const double* r64, float* f32, const double* basis, double* sigma,
                        hipStream_t st) {
     const long long n4 = field_quads(g);
-    k_cast<<<(unsigned)((n4 + 255) / 256), 256, 0, st>>>(n4, r64, f32, red, sigma);
+    k_cast<<<(unsigned)((n4 + 255) / 256), 256, 0, st>>>(n4, r64, f32, basis, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_cast(const Geom& g, const void* u, const void* f, float* f32, double s,
+                                const double* basis, double* sigma, double* partials, long long* nblocks,
+                                hipStream_t st) {
+    if (!use_zmarch(g)) return hipErrorInvalidValue;
+    const ZSpace zs = make_zspace(g);
+    if (nblocks) *nblocks = zs.blocks();
+    const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+    if (streams_from_hbm(g, sizeof(double)))
+        k_node_res_cast_zm<2, true><<<grid, block, 0, st>>>(g, zs, cp<double>(u), cp<double>(f), f32, s, basis,
+                                                           sigma, partials);
+    else
+        k_node_res_cast_zm<2, false><<<grid, block, 0, st>>>(g, zs, cp<double>(u), cp<double>(f), f32, s, basis,
+                                                            sigma, partials);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ struct Ctx {
     long long partial_pairs = 0;
     double* partials = nullptr;
     double* reduce_scratch = nullptr;
-    double* red = nullptr;        // [sum r^2, max |r|, sigma, -, projection sum, -]
+    double* red = nullptr;        // [sum r^2, max |r|, sigma, scale basis, projection sum, -]
     double* chol = nullptr;
     double* staging = nullptr;
     // preconditioned CG (krylov = 1): finest-level FP64 vectors and scalars
@@ -95,6 +95,11 @@ struct Ctx {
     // recording mode (batched execution): ops append descriptors here
     std::vector<BItem>* rec = nullptr;
     double* rec_res = nullptr;    // extra destination of recorded norm reductions
+    long long last_partials = 0;  // norm partial pairs of the last residual
+    // mixed precision: red[3] holds the largest |r| of the latest finest
+    // residual, the scale basis of the next refinement step's cast; false
+    // after a new right-hand side, iterate or level write
+    bool scale_known = false;
     BItem item(int op, int l) const;
     int push(BItem it);
     int rec_check(int pr, bool want_fp32);
@@ -111,7 +116,9 @@ struct Ctx {
     int gs(int l, int pr, int colour, bool zero);
     int jacobi(int l, int pr, bool zero);
     int smooth(int l, int pr, int sweeps, bool from_zero, int first_colour);
-    int residual(int l, int pr, bool norm, bool store);
+    int residual(int l, int pr, bool norm, bool store, bool reduce = true);
+    int reduce_norm(int l);
+    int residual_cast(bool first);
     int restrict_to(int l, int pr);
     int prolong(int l, int pr, int mask);
     int coarse(int pr);

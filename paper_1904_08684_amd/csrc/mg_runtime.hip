@@ -595,7 +595,7 @@ int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
     return MG_OK;
 }
 
-int Ctx::residual(int l, int pr, bool norm, bool store) {
+int Ctx::residual(int l, int pr, bool norm, bool store, bool reduce) {
     Level& L = lv[l];
     if (rec) {
         if (pr == 0 && !(norm && store)) return fail(MG_EINVAL, "batched FP64 residual carries its norm");
@@ -620,15 +620,8 @@ int Ctx::residual(int l, int pr, bool norm, bool store) {
         it.c = L.r[pr];
         it.part = partials;
         push(it);
-        if (pr == 0) {
-            BItem rd = item(BOP_REDUCE, l);
-            rd.part = partials;
-            rd.n = it.tiles;
-            rd.res = rec_res;
-            rd.tiles = 1;
-            push(rd);
-        }
-        return MG_OK;
+        last_partials = it.tiles;
+        return pr == 0 && reduce ? reduce_norm(l) : MG_OK;
     }
     long long nb = 0;
     hipEvent_t e0 = begin();
@@ -637,9 +630,75 @@ int Ctx::residual(int l, int pr, bool norm, bool store) {
                           : launch_residual(L.g, pr, L.u[pr], L.f[pr], L.r[pr], faces(l, pr), scale(l), norm, store,
                                             partials, &nb, stream),
                     e0, "residual");
-    if (rc || !norm) return rc;
-    e0 = begin();
-    return record(MG_K_REDUCE, l, launch_reduce(partials, nb, reduce_scratch, red, stream), e0, "reduce");
+    last_partials = nb;
+    if (rc || !norm || !reduce) return rc;
+    return reduce_norm(l);
+}
+
+// (sum r^2, max |r|) of the last residual's partials into red[0..1]; for the
+// finest FP64 residual of a mixed-precision context the maximum is also
+// kept in red[3] as the scale basis of the next refinement step's cast.
+int Ctx::reduce_norm(int l) {
+    const bool basis = opts.precision == MG_MIXED && l == 0;
+    if (rec) {
+        BItem rd = item(BOP_REDUCE, l);
+        rd.part = partials;
+        rd.n = last_partials;
+        rd.res = rec_res;
+        rd.tiles = 1;
+        rd.m = basis ? 1 : 0;
+        return push(rd);
+    }
+    hipEvent_t e0 = begin();
+    int rc = record(MG_K_REDUCE, l,
+                    launch_reduce(partials, last_partials, reduce_scratch, red, stream, basis ? red + 3 : nullptr), e0,
+                    "reduce");
+    if (!rc && basis) scale_known = true;
+    return rc;
+}
+
+// The FP64 residual of a refinement step and its cast to the right-hand
+// side of the single-precision cycle, fl32(r / sigma), sigma the power of
+// two of the previous residual's maximum (red[3]; stored to red[2] for the
+// update); the norms go to red[0..1] and the maximum to red[3].  Without a
+// previous residual (first: a new right-hand side or iterate) the step's own
+// maximum is reduced first and taken.  On 3-D node levels
+// that march columns the residual is cast as it is formed (no FP64 residual
+// is stored); elsewhere r64 is stored, cast, and reduced.
+int Ctx::residual_cast(bool first) {
+    Level& L0 = lv[0];
+    if (!rec && grid.centering == MG_NODE && !L0.gal && use_zmarch(L0.g)) {
+        if (first) {
+            if (int rc = residual(0, 0, true, false)) return rc;
+        }
+        long long nb = 0;
+        hipEvent_t e0 = begin();
+        int rc = record(MG_K_RESIDUAL, 0,
+                        launch_residual_cast(L0.g, L0.u[0], L0.f[0], static_cast<float*>(L0.f[1]), scale(0), red + 3,
+                                             red + 2, partials, &nb, stream),
+                        e0, "residual+cast");
+        last_partials = nb;
+        return rc ? rc : reduce_norm(0);
+    }
+    int rc = residual(0, 0, true, true, false);
+    if (!rc && first) rc = reduce_norm(0);
+    if (rc) return rc;
+    if (rec) {
+        BItem ca = item(BOP_CAST, 0);
+        ca.n = field_quads(L0.g);
+        ca.tiles = (ca.n + 255) / 256;
+        ca.a = L0.r[0];
+        ca.b = L0.f[1];
+        push(ca);
+    } else {
+        hipEvent_t e0 = begin();
+        rc = record(MG_K_CAST, 0,
+                    launch_cast(L0.g, static_cast<const double*>(L0.r[0]), static_cast<float*>(L0.f[1]), red + 3,
+                                red + 2, stream),
+                    e0, "cast");
+    }
+    if (!rc && !first) rc = reduce_norm(0);
+    return rc;
 }
 
 int Ctx::restrict_to(int l, int pr) {
@@ -758,19 +817,12 @@ int Ctx::project(int l, void* a) {
                   "project");
 }
 
-// One FP64 refinement step around a single-precision V-cycle.  Expects
-// r64 and (sum r^2, max |r|) of the current iterate in place (residual()
-// with norm and store); leaves u64 updated.
+// One FP64 refinement step around a single-precision V-cycle from zero,
+// whose right-hand side residual_cast prepared: u64 += sigma fl64(c).
 int Ctx::refine_step() {
     Level& L0 = lv[0];
+    if (int rc = vcycle(0, 1, true)) return rc;
     if (rec) {
-        BItem ca = item(BOP_CAST, 0);
-        ca.n = field_quads(L0.g);
-        ca.tiles = (ca.n + 255) / 256;
-        ca.a = L0.r[0];
-        ca.b = L0.f[1];
-        push(ca);
-        if (int rc = vcycle(0, 1, true)) return rc;
         BItem up = item(BOP_UPDATE, 0);
         up.n = field_quads(L0.g);
         up.tiles = (up.n + 255) / 256;
@@ -779,13 +831,6 @@ int Ctx::refine_step() {
         return push(up);
     }
     hipEvent_t e0 = begin();
-    int rc = record(MG_K_CAST, 0,
-                    launch_cast(L0.g, static_cast<const double*>(L0.r[0]), static_cast<float*>(L0.f[1]), red,
-                                red + 2, stream),
-                    e0, "cast");
-    if (!rc) rc = vcycle(0, 1, true);
-    if (rc) return rc;
-    e0 = begin();
     return record(MG_K_UPDATE, 0,
                   launch_update(L0.g, static_cast<double*>(L0.u[0]), static_cast<const float*>(L0.u[1]), red + 2,
                                 stream),
@@ -803,7 +848,7 @@ int Ctx::read_red(double* sq, double* mx) {
 }
 
 int Ctx::norm(double* out) {
-    int rc = residual(0, 0, true, opts.precision == MG_MIXED);
+    int rc = residual(0, 0, true, false);
     double sq, mx;
     if (!rc) rc = read_red(&sq, &mx);
     if (rc) return rc;
@@ -854,12 +899,13 @@ const Ctx::Graph* Ctx::capture(int kind) {
     hipStream_t user = stream;
     stream = cap_stream;
     int rc;
+    // (mixed: the scale basis of the previous residual is known here)
     if (kind == 0) {
         rc = mixed ? refine_step() : vcycle(0, 0, false);
-        if (!rc) rc = residual(0, 0, true, mixed);
+        if (!rc) rc = mixed ? residual_cast(false) : residual(0, 0, true, false);
         if (!rc) rc = dev(hipMemcpyAsync(h_red, red, 16, hipMemcpyDeviceToHost, stream), "norm copy");
     } else {
-        rc = mixed ? residual(0, 0, true, true) : MG_OK;
+        rc = mixed ? residual_cast(false) : MG_OK;
         if (!rc) rc = mixed ? refine_step() : vcycle(0, 0, false);
     }
     stream = user;
@@ -907,6 +953,10 @@ const Ctx::Graph* Ctx::replayable(int kind) {
 }
 
 int Ctx::step_once() {
+    if (opts.precision == MG_MIXED && !scale_known) {
+        // a new right-hand side or iterate: the first step scales by its own residual
+        if (int rc = residual(0, 0, true, false)) return rc;
+    }
     if (const Graph* gr = replayable(1)) {
         int rc = dev(hipGraphLaunch(gr->exec, stream), "graph launch");
         if (rc) return rc;
@@ -915,7 +965,7 @@ int Ctx::step_once() {
         return MG_OK;
     }
     if (opts.precision == MG_MIXED) {
-        int rc = residual(0, 0, true, true);
+        int rc = residual_cast(false);
         return rc ? rc : refine_step();
     }
     return vcycle(0, 0, false);
@@ -934,7 +984,15 @@ int Ctx::iterate(double* nr) {
             return MG_OK;
         }
     }
-    int rc = opts.precision == MG_MIXED ? refine_step() : vcycle(0, 0, false);
+    if (opts.precision == MG_MIXED) {
+        int rc = refine_step();
+        if (!rc) rc = residual_cast(false);
+        double sq, mx;
+        if (!rc) rc = read_red(&sq, &mx);
+        if (!rc) *nr = std::sqrt(sq);
+        return rc;
+    }
+    int rc = vcycle(0, 0, false);
     if (!rc) rc = norm(nr);
     return rc;
 }
@@ -1031,7 +1089,9 @@ int Ctx::pcg(double tol, int max_it, int* its_out, double* relres_out) {
 int Ctx::solve(double tol, int* cycles_out, double* relres_out) {
     hist.clear();
     double r0;
-    int rc = norm(&r0);   // in mixed mode this also leaves r64 and max|r| for the first step
+    int rc = norm(&r0);   // in mixed mode this also leaves max|r| as the first step's scale basis
+    // mixed: the first step's single-precision right-hand side
+    if (!rc && opts.precision == MG_MIXED && r0 > 0.0 && std::isfinite(r0)) rc = residual_cast(false);
     if (rc) return rc;
     if (!std::isfinite(r0)) return fail(MG_ENONFINITE, "initial residual is not finite");
     hist.push_back(1.0);
@@ -1301,6 +1361,7 @@ static int copy_out(Ctx* c, const mg::Geom& g, int pr, const void* field, double
 int mg_set_rhs(mg_ctx* h, const double* f, int on_device) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     if (!c || !f) return MG_EINVAL;
+    c->scale_known = false;   // the next refinement step scales by its own residual
     int rc = copy_in(c, c->lv[0].g, 0, c->lv[0].f[0], f, on_device);
     if (!rc && c->neu) rc = c->project(0, c->lv[0].f[0]);
     return rc;
@@ -1309,6 +1370,7 @@ int mg_set_rhs(mg_ctx* h, const double* f, int on_device) {
 int mg_set_initial(mg_ctx* h, const double* u0, int on_device) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     if (!c) return MG_EINVAL;
+    c->scale_known = false;   // the next refinement step scales by its own residual
     if (!u0) {
         hipEvent_t e0 = c->begin();
         return c->record(MG_K_COPY, 0, mg::launch_zero(c->lv[0].u[0], c->lv[0].field_bytes[0], c->stream), e0,
@@ -1394,6 +1456,7 @@ static void* field_ptr(Ctx* c, int level, int field, int pr) {
 int mg_level_set(mg_ctx* h, int level, int field, int prec, const double* a, int on_device) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     if (!c || !a) return MG_EINVAL;
+    c->scale_known = false;   // the next refinement step scales by its own residual
     void* p = field_ptr(c, level, field, prec);
     if (!p) return c->fail(MG_EINVAL, "no such level field");
     return copy_in(c, c->lv[level].g, prec, p, a, on_device);
@@ -1410,6 +1473,7 @@ int mg_level_get(mg_ctx* h, int level, int field, int prec, double* a, int on_de
 int mg_apply(mg_ctx* h, int op, int level, int prec) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     if (!c) return MG_EINVAL;
+    c->scale_known = false;   // the next refinement step scales by its own residual
     if (level < 0 || level >= c->L || prec < 0 || prec > 1 || !c->lv[level].has[prec])
         return c->fail(MG_EINVAL, "no such level in this precision");
     const bool has_next = level + 1 < c->L && c->lv[level + 1].has[prec];

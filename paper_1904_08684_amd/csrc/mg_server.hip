@@ -290,7 +290,7 @@ struct Server {
         c->rec = &items;
         c->rec_res = res;
         const size_t init_begin = items.size();
-        int rc = c->residual(0, 0, true, true);
+        int rc = c->residual_cast(true);
         const size_t init_end = items.size();
         // refinement steps, norms -> res[2..3]; record two so that Jacobi
         // double buffers return to their starting state after the pair
@@ -299,7 +299,7 @@ struct Server {
         for (int p = 0; p < 2 && !rc; ++p) {
             sb[p] = items.size();
             rc = c->refine_step();
-            if (!rc) rc = c->residual(0, 0, true, true);
+            if (!rc) rc = c->residual_cast(false);
         }
         sb[2] = items.size();
         c->rec = nullptr;

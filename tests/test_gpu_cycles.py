@@ -193,6 +193,33 @@ def test_mixed_precision_matches_oracle(mg, dim, n, cent):
     s.close()
 
 
+@pytest.mark.parametrize("n", [129, 257])
+def test_mixed_solve_with_residual_cast_pass_is_bitwise_the_oracles(mg, n):
+    """On 3-D node levels that march columns the refinement step's residual
+    is cast to single precision as it is formed, scaled by the power of two
+    of the previous residual's maximum.  The solution equals, bit for bit,
+    the oracle's refinement with that scale and with the scale of the current
+    residual (the separate residual + cast sequence): power-of-two scaling
+    commutes with every single-precision operation in range."""
+    f = W.interior_uniform(n, 3, W.SEED_F_3D)
+    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, precision=mg.MG_MIXED)
+    s.set_rhs(f)
+    s.set_initial(None)
+    code, steps, rel = s.solve(1e-10)
+    u = s.solution()
+    hist_gpu = s.history()
+    s.close()
+    h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3))
+    u_prev, hist_prev = cycle.mixed_solve(h, f, tol=1e-10, scale="previous")
+    u_cur, hist_cur = cycle.mixed_solve(h, f, tol=1e-10, scale="current")
+    print(f"mixed n={n}: {steps} steps (oracle {len(hist_prev) - 1}), relres {rel:.3e}; "
+          f"max |u - u_oracle| {np.max(np.abs(u - u_prev)):.3e}, bitwise {np.array_equal(u, u_prev)}", flush=True)
+    assert code == mg.MG_OK and steps == len(hist_prev) - 1
+    assert np.array_equal(u_prev, u_cur)
+    assert np.array_equal(u, u_prev)
+    assert np.allclose(hist_gpu, hist_prev, rtol=1e-9, atol=0)
+
+
 def test_mixed_step_257_matches_oracle(mg):
     """One refinement step at 257^3 (the single-precision V-cycle smooths the
     finest level with fused passes, the first from a zero iterate) against

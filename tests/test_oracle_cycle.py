@@ -173,6 +173,29 @@ def test_float32_cycle_stays_in_float32_and_tracks_fp64():
     assert np.max(np.abs(c32 - c64)) <= 1e-5 * np.max(np.abs(c64))
 
 
+def test_refinement_scale_is_immaterial_in_range_and_keeps_tiny_residuals():
+    """Every operation of the single-precision cycle commutes with a power of
+    two, so the refinement iterates are bitwise the same whether the scale
+    comes from the previous or the current residual; and scaling f by 2^-140
+    (its residuals lie below FP32's smallest normal, about 1.2e-38, so an
+    unscaled float32 cycle would flush them) scales the solution by exactly
+    2^-140, which holds only if the scale is applied."""
+    n = 17
+    p = cycle.Params(centering="node", dim=3, n=n, smoother="rbgs", nu1=3, nu2=3)
+    h = cycle.build_hierarchy(p)
+    f = W.interior_uniform(n, 3, 1)
+    u_prev, hist_prev = cycle.mixed_solve(h, f, tol=1e-10, scale="previous")
+    u_cur, hist_cur = cycle.mixed_solve(h, f, tol=1e-10, scale="current")
+    assert np.array_equal(u_prev, u_cur) and hist_prev == hist_cur
+    tiny = 2.0 ** -140
+    u_tiny, hist_tiny = cycle.mixed_solve(h, f * tiny, tol=1e-10)
+    assert np.array_equal(u_tiny, u_prev * tiny)
+    assert np.allclose(hist_tiny, hist_prev, rtol=0, atol=0)
+    # without the scale the same steps lose the residual to underflow
+    r32 = (node.residual(np.zeros_like(f), f * tiny)).astype(np.float32)
+    assert np.count_nonzero(r32) < np.count_nonzero(f)
+
+
 def test_pow2_scale():
     for v in (1.0, 0.75, 3.0, 1e-300, 5e300, 2.0 ** -20):
         s = cycle.pow2_scale(v)
