@@ -115,6 +115,23 @@ static inline ZSpace make_zspace(const Geom& g) {
     return z;
 }
 
+// Column-marching tiling of a 3-D cell level (all cells are unknowns):
+// (x >> 1, y) columns over chunks of kZChunk planes, blocks of 64 x kZRows.
+static inline bool use_cell_zm(const Geom& g) {
+    return g.dim == 3 && g.cell && g.n / 2 >= 64;
+}
+
+static inline ZSpace make_czspace(const Geom& g) {
+    ZSpace z;
+    z.xr = g.n / 2;
+    z.rows = kZRows;
+    z.zc = kZChunk < g.n ? kZChunk : g.n;
+    z.ntx = (z.xr + 63) / 64;
+    z.nty = (g.n + z.rows - 1) / z.rows;
+    z.ntz = (g.n + z.zc - 1) / z.zc;
+    return z;
+}
+
 // Row-marching tiling of a 2-D node level: 256-thread blocks of 64 lanes
 // over x >> 1 times `rows` row chunks; each thread walks `yc` consecutive rows
 // of its column and keeps rows y-1, y, y+1 of both colours in registers.

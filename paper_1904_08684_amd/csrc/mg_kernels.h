@@ -11,6 +11,9 @@ namespace mg {
 // Faces of a cell level: x-, y- and z-face coefficient arrays (null for node grids).
 struct Faces {
     const void* b[3];
+    // FP64 cell values k in colour-split layout (finest 3-D cell level, or
+    // null): column-marching kernels form the faces from them
+    const void* k = nullptr;
 };
 
 // One Gauss-Seidel half-sweep over colour `colour` (0 red, 1 black):

@@ -1355,6 +1355,190 @@ __global__ __launch_bounds__(256) void k_cell_residual(Geom g, Space sp, const T
     d_cell_residual<T, D, NORM, STORE>(solo_ex(), g, sp, u, f, r, bx, by, bz, s, part);
 }
 
+// ------------------------------- 3-D cell grids, coefficients from k on the fly
+// On the finest cell level of a variable-coefficient problem every face
+// coefficient is the harmonic mean of the two cells' k, ((2 ka) kb) / (ka + kb)
+// with ka the lower-index cell (a wall face: the inner cell's k), the very
+// operations that form the face arrays on the host, so a face formed here is
+// bitwise the stored one.  Reading k of both colours (16 B per updated cell)
+// replaces three face arrays read at stride two.  Threads march (x >> 1, y)
+// columns of the updated colour over a chunk of planes and keep the other
+// colour's u and k on planes z - 1, z, z + 1 in registers; x and y neighbours
+// come from the L1 / L2.  The diagonal and off-diagonal sums take the faces
+// in the order x-, x+, y-, y+, z-, z+, as cell_sums does.
+__device__ __forceinline__ double harm(double ka, double kb) { return ((2.0 * ka) * kb) / (ka + kb); }
+
+// dg, off of the cell with own k `kc` and u/k of its six neighbours (values
+// at walls unused); ww: weight of a wall face (2 Dirichlet, 0 Neumann).
+template <bool ZERO>
+__device__ __forceinline__ void cell_sums_k(double kc, const double (&kn)[6], const double (&un)[6],
+                                            const bool (&wall)[6], double ww, double& dg, double& off) {
+    double b[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        b[i] = wall[i] ? kc : ((i & 1) ? harm(kc, kn[i]) : harm(kn[i], kc));   // odd i: the + face
+    dg = wall[0] ? ww * b[0] : b[0];
+#pragma unroll
+    for (int i = 1; i < 6; ++i) dg = dg + (wall[i] ? ww * b[i] : b[i]);
+    if (ZERO) {
+        off = 0.0;
+        return;
+    }
+    off = wall[0] ? 0.0 : b[0] * un[0];
+#pragma unroll
+    for (int i = 1; i < 6; ++i) off = off + (wall[i] ? 0.0 : b[i] * un[i]);
+}
+
+// Red-black half-sweep of colour `colour` (me/other: the two colour planes of
+// u; km/ko: of k).
+template <bool NT, bool ZERO>
+__global__ __launch_bounds__(256) void k_cell_gs_zmk(Geom g, ZSpace zs, double* __restrict__ me,
+                                                     const double* __restrict__ other,
+                                                     const double* __restrict__ f,
+                                                     const double* __restrict__ km,
+                                                     const double* __restrict__ ko, double s, int colour) {
+    const Ex ex = solo_ex();
+    int tx, ty, tz;
+    zm_tile(zs, ex.b, tx, ty, tz);
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y = ty * zs.rows + (ex.t >> 6);
+    const int N = g.n;
+    if (xs >= zs.xr || y >= N) return;
+    const int z0 = tz * zs.zc, z1 = min(z0 + zs.zc, N);
+    const long long pl = g.plane, pt = g.pitch;
+    const double ww = g.neu ? 0.0 : 2.0;
+    const bool wym = y == 0, wyp = y == N - 1;
+    // neighbour offsets clamped to the cell itself at walls (values unused)
+    const long long oym = wym ? 0 : -pt, oyp = wyp ? 0 : pt;
+    long long ro = row_off(g, y, z0) + xs;
+    // z ring of the other colour: planes z - 1, z, z + 1 at the own position
+    double um = 0.0, uc = 0.0, kmz = 0.0, kcz = 0.0;
+    if (!ZERO) uc = other[ro];
+    kcz = ko[ro];
+    if (z0 > 0) {
+        if (!ZERO) um = other[ro - pl];
+        kmz = ko[ro - pl];
+    }
+    for (int z = z0; z < z1; ++z, ro += pl) {
+        const bool wzm = z == 0, wzp = z == N - 1;
+        const long long ozp = wzp ? 0 : pl;
+        const double up = ZERO ? 0.0 : other[ro + ozp];
+        const double kp = ko[ro + ozp];
+        const int par = (y + z + colour) & 1;          // x = 2 xs + par
+        const bool wxm = !par && xs == 0, wxp = par && xs == zs.xr - 1;
+        // the x neighbour that is not at the own position: x >> 1 - 1 (par 0) or + 1 (par 1)
+        const long long ox = par ? (wxp ? 0 : 1) : (wxm ? 0 : -1);
+        double kn[6], un[6];
+        const double kx = ko[ro + ox];
+        kn[0] = par ? kcz : kx;
+        kn[1] = par ? kx : kcz;
+        kn[2] = ko[ro + oym];
+        kn[3] = ko[ro + oyp];
+        kn[4] = kmz;
+        kn[5] = kp;
+        if (!ZERO) {
+            const double ux = other[ro + ox];
+            un[0] = par ? uc : ux;
+            un[1] = par ? ux : uc;
+            un[2] = other[ro + oym];
+            un[3] = other[ro + oyp];
+            un[4] = um;
+            un[5] = up;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) un[i] = 0.0;
+        }
+        const bool wall[6] = {wxm, wxp, wym, wyp, wzm, wzp};
+        double dg, off;
+        cell_sums_k<ZERO>(km[ro], kn, un, wall, ww, dg, off);
+        st_stream<NT>(me + ro, (ld_stream<NT>(f + ro) / s + off) / dg);
+        um = uc;
+        uc = up;
+        kmz = kcz;
+        kcz = kp;
+    }
+}
+
+// r = f - (dg u - off) s at both colours of the thread's column (u, k and f
+// in colour-split layout, both colours); NORM: per-block (sum r^2, max |r|).
+template <bool NT, bool NORM, bool STORE>
+__global__ __launch_bounds__(256) void k_cell_res_zmk(Geom g, ZSpace zs, const double* __restrict__ u,
+                                                      const double* __restrict__ f, double* __restrict__ r,
+                                                      const double* __restrict__ k, double s,
+                                                      double* __restrict__ part) {
+    const Ex ex = solo_ex();
+    double sq = 0.0, mx = 0.0;
+    int tx, ty, tz;
+    zm_tile(zs, ex.b, tx, ty, tz);
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y = ty * zs.rows + (ex.t >> 6);
+    const int N = g.n;
+    if (xs < zs.xr && y < N) {
+        const int z0 = tz * zs.zc, z1 = min(z0 + zs.zc, N);
+        const long long pl = g.plane, pt = g.pitch, cs = g.cs;
+        const double ww = g.neu ? 0.0 : 2.0;
+        const bool wym = y == 0, wyp = y == N - 1;
+        const long long oym = wym ? 0 : -pt, oyp = wyp ? 0 : pt;
+        long long ro = row_off(g, y, z0) + xs;
+        // z rings of both colours (c = 0, 1): u and k on planes z - 1, z
+        double um[2], uc[2], kmz[2], kcz[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            uc[c] = u[c * cs + ro];
+            kcz[c] = k[c * cs + ro];
+            um[c] = z0 > 0 ? u[c * cs + ro - pl] : 0.0;
+            kmz[c] = z0 > 0 ? k[c * cs + ro - pl] : 0.0;
+        }
+        for (int z = z0; z < z1; ++z, ro += pl) {
+            const bool wzm = z == 0, wzp = z == N - 1;
+            const long long ozp = wzp ? 0 : pl;
+            double up[2], kp[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                up[c] = u[c * cs + ro + ozp];
+                kp[c] = k[c * cs + ro + ozp];
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {       // the cell of colour c; its neighbours are colour 1 - c
+                const int o = 1 - c;
+                const long long oc = o * cs + ro;
+                const int par = (y + z + c) & 1;
+                const bool wxm = !par && xs == 0, wxp = par && xs == zs.xr - 1;
+                const long long ox = par ? (wxp ? 0 : 1) : (wxm ? 0 : -1);
+                double kn[6], un[6];
+                const double kx = k[oc + ox], ux = u[oc + ox];
+                kn[0] = par ? kcz[o] : kx;
+                kn[1] = par ? kx : kcz[o];
+                kn[2] = k[oc + oym];
+                kn[3] = k[oc + oyp];
+                kn[4] = kmz[o];
+                kn[5] = kp[o];
+                un[0] = par ? uc[o] : ux;
+                un[1] = par ? ux : uc[o];
+                un[2] = u[oc + oym];
+                un[3] = u[oc + oyp];
+                un[4] = um[o];
+                un[5] = up[o];
+                const bool wall[6] = {wxm, wxp, wym, wyp, wzm, wzp};
+                double dg, off;
+                cell_sums_k<false>(kcz[c], kn, un, wall, ww, dg, off);
+                const double rv = ld_stream<NT>(f + c * cs + ro) - (dg * uc[c] - off) * s;
+                if (STORE) st_stream<NT>(r + c * cs + ro, rv);
+                sq = sq + rv * rv;
+                mx = fmax(mx, fabs(rv));
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                um[c] = uc[c];
+                uc[c] = up[c];
+                kmz[c] = kcz[c];
+                kcz[c] = kp[c];
+            }
+        }
+    }
+    if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
 // Mean of the 2^d children, summed with the z offset slowest, then scaled.
 template <typename T, int D>
 __device__ __forceinline__ void d_cell_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
@@ -1999,7 +2183,20 @@ static hipError_t gs_t(const Geom& g, int colour, bool zero, void* u, const void
     T* me = mp<T>(u) + (long long)colour * g.cs;
     const T* other = cp<T>(u) + (long long)(1 - colour) * g.cs;
     const T* fm = cp<T>(f) + (long long)colour * g.cs;
-    if (g.cell) {
+    if (sizeof(T) == 8 && g.cell && fc.k && use_cell_zm(g)) {
+        const ZSpace zs = make_czspace(g);
+        const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+        const double* km = cp<double>(fc.k) + (long long)colour * g.cs;
+        const double* ko = cp<double>(fc.k) + (long long)(1 - colour) * g.cs;
+        double* m64 = reinterpret_cast<double*>(me);
+        const double* o64 = reinterpret_cast<const double*>(other);
+        const double* f64 = reinterpret_cast<const double*>(fm);
+        const bool nt = streams_from_hbm(g, 8);
+        if (zero && nt) k_cell_gs_zmk<true, true><<<grid, block, 0, st>>>(g, zs, m64, o64, f64, km, ko, s, colour);
+        else if (zero) k_cell_gs_zmk<false, true><<<grid, block, 0, st>>>(g, zs, m64, o64, f64, km, ko, s, colour);
+        else if (nt) k_cell_gs_zmk<true, false><<<grid, block, 0, st>>>(g, zs, m64, o64, f64, km, ko, s, colour);
+        else k_cell_gs_zmk<false, false><<<grid, block, 0, st>>>(g, zs, m64, o64, f64, km, ko, s, colour);
+    } else if (g.cell) {
         MG_DISPATCH_DIM(g, if (zero) k_cell_gs<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
                                g, sp, me, other, fm, cp<T>(fc.b[0]), cp<T>(fc.b[1]), cp<T>(fc.b[2]), (T)s);
                            else k_cell_gs<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
@@ -2125,7 +2322,10 @@ hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, cons
 
 long long residual_blocks(const Geom& g) {
     // the stand-alone path may march columns or rows; the batched path may use one point per thread
-    const long long a = use_zmarch(g) ? make_zspace(g).blocks() : (use_ymarch(g) ? make_yspace(g).blocks() : 0);
+    const long long a = use_zmarch(g)    ? make_zspace(g).blocks()
+                        : use_ymarch(g)  ? make_yspace(g).blocks()
+                        : use_cell_zm(g) ? make_czspace(g).blocks()
+                                         : 0;
     const long long b = space_of(g, 2, 0).blocks();
     return a > b ? a : b;
 }
@@ -2147,6 +2347,29 @@ template <typename T>
 static hipError_t residual_t(const Geom& g, const void* u, const void* f, void* r, const Faces& fc,
                              double s, bool norm, bool store, double* part, long long* nb,
                              hipStream_t st) {
+    if (sizeof(T) == 8 && g.cell && fc.k && use_cell_zm(g)) {
+        const ZSpace zs = make_czspace(g);
+        if (nb) *nb = zs.blocks();
+        const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+        const double* u64 = cp<double>(u);
+        const double* f64 = cp<double>(f);
+        double* r64 = reinterpret_cast<double*>(r);
+        const double* kk = cp<double>(fc.k);
+#define MG_CRES(NT)                                                                                         \
+    if (norm && store)                                                                                      \
+        k_cell_res_zmk<NT, true, true><<<grid, block, 0, st>>>(g, zs, u64, f64, r64, kk, s, part);          \
+    else if (norm)                                                                                          \
+        k_cell_res_zmk<NT, true, false><<<grid, block, 0, st>>>(g, zs, u64, f64, r64, kk, s, part);         \
+    else                                                                                                    \
+        k_cell_res_zmk<NT, false, true><<<grid, block, 0, st>>>(g, zs, u64, f64, r64, kk, s, part);
+        if (streams_from_hbm(g, 8)) {
+            MG_CRES(true)
+        } else {
+            MG_CRES(false)
+        }
+#undef MG_CRES
+        return hipGetLastError();
+    }
     if (use_ymarch(g)) {
         const YSpace ys = make_yspace(g);
         if (nb) *nb = ys.blocks();

@@ -24,6 +24,7 @@ struct LevelPlan {
     size_t u[2] = {SIZE_MAX, SIZE_MAX}, f[2] = {SIZE_MAX, SIZE_MAX}, r[2] = {SIZE_MAX, SIZE_MAX};
     size_t utmp[2] = {SIZE_MAX, SIZE_MAX};
     size_t beta[2][3] = {{SIZE_MAX, SIZE_MAX, SIZE_MAX}, {SIZE_MAX, SIZE_MAX, SIZE_MAX}};
+    size_t k = SIZE_MAX;          // FP64 cell values, colour-split (finest 3-D cell level)
 };
 
 struct Plan {
@@ -51,6 +52,7 @@ struct Level {
     void* r[2] = {nullptr, nullptr};
     void* utmp[2] = {nullptr, nullptr};
     void* beta[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    void* k = nullptr;            // FP64 cell values, colour-split (finest 3-D cell level)
     size_t field_bytes[2] = {0, 0};
     bool gal = false;             // Galerkin stencil W instead of the 5/7-point operator
     Stencil27 W{};

@@ -149,6 +149,8 @@ size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, 
             for (int a = 0; a < 3; ++a)
                 lp.beta[pr][a] = (varcoef && a < g->dim) ? take((size_t)lp.g.fsize * es) : SIZE_MAX;
         }
+        // the finest 3-D cell level's kernels form its faces from k
+        if (l == 0 && cell && lp.has[0] && use_cell_zm(lp.g)) lp.k = take((size_t)(2 * lp.g.cs) * 8);
         p.lv.push_back(lp);
     }
     const Geom& g0 = p.lv[0].g;
@@ -434,6 +436,7 @@ void* Ctx::at(size_t off) const { return off == SIZE_MAX ? nullptr : static_cast
 Faces Ctx::faces(int l, int pr) const {
     Faces f;
     for (int a = 0; a < 3; ++a) f.b[a] = lv[l].beta[pr][a];
+    f.k = pr == 0 ? lv[l].k : nullptr;
     return f;
 }
 
@@ -1194,6 +1197,7 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
             lvv.field_bytes[pr] = (size_t)(2 * lp.g.cs) * (pr == 0 ? 8 : 4);
             for (int a = 0; a < 3; ++a) lvv.beta[pr][a] = c->at(lp.beta[pr][a]);
         }
+        lvv.k = c->at(lp.k);
         c->lv.push_back(lvv);
     }
     // zero every field (boundary nodes and padding stay zero for good)
@@ -1215,6 +1219,19 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
         }
         std::vector<double> bf[3], bc2[3];
         if (!rc) harmonic_faces(g0, k.data(), bf);
+        if (!rc && c->lv[0].k) {
+            // k in colour-split layout for the column-marching finest-level kernels
+            std::vector<double> ks((size_t)(2 * g0.cs), 0.0);
+            const int N = g0.n;
+            for (int z = 0; z < N; ++z)
+                for (int y = 0; y < N; ++y)
+                    for (int x = 0; x < N; ++x)
+                        ks[(size_t)(((x + y + z) & 1) * g0.cs + (long long)z * g0.plane + (long long)y * g0.pitch +
+                                    (x >> 1))] = k[((size_t)z * N + y) * N + x];
+            rc = c->dev(hipMemcpyAsync(c->lv[0].k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, c->stream),
+                        "upload k");
+            if (!rc) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
+        }
         std::vector<float> tmp32;
         for (int l = 0; !rc && l < c->L; ++l) {
             const Geom& gl = c->lv[l].g;

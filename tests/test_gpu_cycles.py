@@ -142,7 +142,7 @@ def test_post_order_variants(mg, order):
     s.close()
 
 
-@pytest.mark.parametrize("N,smoother", [(32, "rbgs"), (64, "rbgs"), (32, "jacobi")])
+@pytest.mark.parametrize("N,smoother", [(32, "rbgs"), (64, "rbgs"), (128, "rbgs"), (32, "jacobi")])
 def test_varcoef_cell_per_iterate(mg, N, smoother):
     k = W.varcoef_k(N, 3)
     f = W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)
@@ -603,8 +603,8 @@ def test_pcg_513_converges_faster_than_cycles(mg):
 
 
 # ------------------------------------------------------ Neumann walls (cells)
-@pytest.mark.parametrize("dim,N,sm,nu,cycles", [(3, 32, "rbgs", 2, 3), (3, 64, "rbgs", 3, 2), (3, 32, "jacobi", 2, 3),
-                                                (2, 64, "rbgs", 2, 3)])
+@pytest.mark.parametrize("dim,N,sm,nu,cycles", [(3, 32, "rbgs", 2, 3), (3, 64, "rbgs", 3, 2), (3, 128, "rbgs", 3, 2),
+                                                (3, 32, "jacobi", 2, 3), (2, 64, "rbgs", 2, 3)])
 def test_neumann_per_iterate(mg, dim, N, sm, nu, cycles):
     """Zero-flux walls: f projected at set-up, coarse right-hand sides
     projected, zero-mean coarsest solve, even-ghost interpolation, finest

@@ -88,6 +88,36 @@ def test_smoothers_and_residual(mg, dim, n, cent, prec):
     s.close()
 
 
+@pytest.mark.parametrize("n,bc", [(128, "dirichlet"), (256, "dirichlet"), (128, "neumann")])
+def test_cell_faces_from_k_bitwise(mg, n, bc):
+    """On the finest 3-D cell level with n >= 128 the FP64 half-sweeps and
+    the residual form each face coefficient from k as they go (column
+    marching): every value bit for bit the oracle's, which reads harmonic
+    means stored per face."""
+    k = W.varcoef_k(n, 3)
+    s = mg.Solver(3, n, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=1, nu2=1, k=k,
+                  bc=mg.MG_NEUMANN0 if bc == "neumann" else mg.MG_DIRICHLET0)
+    beta = cell.harmonic_faces(k)
+    u = rand(n, 3, 1, 300 + n, np.float64)
+    f = rand(n, 3, 1, 400 + n, np.float64) * float(n * n)
+    for colour, op in ((0, mg.MG_OP_GS_RED), (1, mg.MG_OP_GS_BLACK)):
+        s.level_set(0, mg.MG_FIELD_U, u, 0)
+        s.level_set(0, mg.MG_FIELD_F, f, 0)
+        s.apply(op, 0, 0)
+        got = s.level_get(0, mg.MG_FIELD_U, 0)
+        ref = u.copy()
+        cell.gs_colour(ref, f, beta, colour, bc)
+        print(f"k-path gs colour {colour} n={n} {bc}: bitwise {np.array_equal(got, ref)}", flush=True)
+        assert np.array_equal(got, ref)
+    s.level_set(0, mg.MG_FIELD_U, u, 0)
+    s.apply(mg.MG_OP_RESIDUAL, 0, 0)
+    got = s.level_get(0, mg.MG_FIELD_R, 0)
+    ref = cell.residual(u, f, beta, bc)
+    print(f"k-path residual n={n} {bc}: bitwise {np.array_equal(got, ref)}", flush=True)
+    assert np.array_equal(got, ref)
+    s.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("dim,n,cent", [c for c in cases() if c[1] > (4 if c[2] else 5)])
 def test_transfers(mg, dim, n, cent, prec):
