@@ -280,6 +280,7 @@ typedef struct mg_request {
 
 typedef struct mg_result {
     uint64_t id;
+    uint64_t ticket;        /* the ticket mg_server_submit returned           */
     int status;             /* MG_OK, MG_ENOTCONV, MG_ENONFINITE              */
     int steps;              /* refinement steps (single-precision V-cycles)   */
     double relres;          /* ||f - A u|| / ||f|| of the returned solution   */
@@ -297,10 +298,14 @@ int mg_server_footprint(const mg_grid* g, const mg_opts* o, size_t* bytes);
 int mg_server_create(const mg_server_opts* o, mg_server** out);
 void mg_server_destroy(mg_server* s);                  /* NULL-safe */
 double mg_server_clock(const mg_server* s);           /* seconds since create */
-/* Queue a request (copies the descriptor, not the arrays).  MG_EBUSY when the
- * queue is full, MG_EINVAL for unsupported grids/options, MG_ENOMEM when the
- * request alone cannot fit the arena. */
-int mg_server_submit(mg_server* s, const mg_request* r);
+/* Queue a request (copies the descriptor, not the arrays).  *ticket (if not
+ * NULL) receives the server's sequence number of the request, 0, 1, 2, ...
+ * in submission order, unique for the server's lifetime and echoed in its
+ * result.  MG_EBUSY when the queue is full, MG_EINVAL for unsupported
+ * grids/options, MG_ENOMEM when the request alone cannot fit the arena (no
+ * ticket is issued then).  The server does no work between calls: rounds
+ * run in mg_server_step, on the caller's thread. */
+int mg_server_submit(mg_server* s, const mg_request* r, uint64_t* ticket);
 /* Run one round; *in_flight receives the requests still in flight and
  * *queued those waiting.  Synchronous. */
 int mg_server_step(mg_server* s, int* in_flight, int* queued);

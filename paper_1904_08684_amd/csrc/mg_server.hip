@@ -117,6 +117,7 @@ struct Hier {
 
 struct Req {
     mg_request r;
+    uint64_t ticket = 0;
     double t_admit = 0.0;
     int steps = 0;
     bool fresh = true;
@@ -164,6 +165,7 @@ struct Server {
     BEntry* h_entries = nullptr;
     std::vector<int> free_slots;
     std::deque<Req> queue;
+    uint64_t next_ticket = 0;     // sequence number of the next submitted request
     std::vector<Req> active;
     std::vector<Hier*> hiers;
     std::vector<mg_result> done;
@@ -346,6 +348,7 @@ struct Server {
                 if (rc) {   // cannot ever be admitted: report it as finished with the error
                     mg_result res{};
                     res.id = q.r.id;
+                    res.ticket = q.ticket;
                     res.status = rc;
                     res.t_arrive = q.r.t_arrive;
                     res.t_admit = res.t_done = now();
@@ -459,6 +462,7 @@ struct Server {
                 for (size_t i = 0; i < fin.size(); ++i) {
                     mg_result res;
                     res.id = fin[i].r.id;
+                    res.ticket = fin[i].ticket;
                     res.status = status[i];
                     res.steps = fin[i].steps;
                     res.relres = fin[i].rel;
@@ -555,7 +559,7 @@ double mg_server_clock(const mg_server* h) {
     return s ? s->now() : 0.0;
 }
 
-int mg_server_submit(mg_server* h, const mg_request* r) {
+int mg_server_submit(mg_server* h, const mg_request* r, uint64_t* ticket) {
     Server* s = reinterpret_cast<Server*>(h);
     if (!s || !r) return MG_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
@@ -572,7 +576,9 @@ int mg_server_submit(mg_server* h, const mg_request* r) {
     mg::Req q;
     q.r = *r;
     q.r.opts.precision = MG_MIXED;
+    q.ticket = s->next_ticket++;
     s->queue.push_back(q);
+    if (ticket) *ticket = q.ticket;
     return MG_OK;
 }
 

@@ -318,8 +318,8 @@ class mg_request(C.Structure):
 
 
 class mg_result(C.Structure):
-    _fields_ = [("id", C.c_uint64), ("status", C.c_int), ("steps", C.c_int), ("relres", C.c_double),
-                ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+    _fields_ = [("id", C.c_uint64), ("ticket", C.c_uint64), ("status", C.c_int), ("steps", C.c_int),
+                ("relres", C.c_double), ("t_arrive", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
 class mg_server_stats(C.Structure):
@@ -334,7 +334,7 @@ _ssigs = {
     "mg_server_create": (C.c_int, [C.POINTER(mg_server_opts), C.POINTER(_P)]),
     "mg_server_destroy": (None, [_P]),
     "mg_server_clock": (C.c_double, [_P]),
-    "mg_server_submit": (C.c_int, [_P, C.POINTER(mg_request)]),
+    "mg_server_submit": (C.c_int, [_P, C.POINTER(mg_request), C.POINTER(C.c_uint64)]),
     "mg_server_step": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "mg_server_poll": (C.c_int, [_P, C.POINTER(mg_result), C.c_int, C.POINTER(C.c_int)]),
     "mg_server_get_stats": (C.c_int, [_P, C.POINTER(mg_server_stats)]),
@@ -394,9 +394,11 @@ class Server:
         r.f = f.data_ptr()
         r.u_out = u_out.data_ptr()
         r.t_arrive = self.clock() if t_arrive is None else t_arrive
-        code = mg_server_submit(self.h, C.byref(r))
+        t = C.c_uint64()
+        code = mg_server_submit(self.h, C.byref(r), C.byref(t))
         if code == MG_OK:
             self._keep[rid] = (f, u_out)
+            self.last_ticket = t.value
         return code
 
     def step(self):
@@ -414,7 +416,7 @@ class Server:
         out = []
         for i in range(n.value):
             r = buf[i]
-            out.append({"id": r.id, "status": r.status, "steps": r.steps, "relres": r.relres,
+            out.append({"id": r.id, "ticket": r.ticket, "status": r.status, "steps": r.steps, "relres": r.relres,
                         "t_arrive": r.t_arrive, "t_admit": r.t_admit, "t_done": r.t_done})
             self._keep.pop(r.id, None)
         return out

@@ -80,8 +80,9 @@ def run_server(mg, srv, reqs, fs, us, tol, arrivals):
 
 
 def run_fifo_fp64(mg, reqs, fs, us, tol, arrivals, limit, torch):
-    """The plain FP64 path, one request at a time in arrival order, one
-    resident context per size class."""
+    """The plain FP64 path, one request at a time in arrival order (the same
+    arrival trace as the open-loop server run), one resident context per
+    size class."""
     idx = sorted(range(len(reqs)), key=lambda i: arrivals[i])[:limit]
     solvers = {}
     for i in idx:
@@ -121,7 +122,8 @@ def main(argv=None, emit=True):
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=512)
     ap.add_argument("--arena-gb", type=float, default=48.0)
-    ap.add_argument("--fifo-count", type=int, default=256)
+    ap.add_argument("--fifo-count", type=int, default=0,
+                    help="requests of the trace the FIFO baseline serves (0: all, the same trace)")
     ap.add_argument("--sweep", default="", help="comma list of further loads (x saturation) to run open loop")
     a = ap.parse_args(argv)
 
@@ -156,7 +158,7 @@ def main(argv=None, emit=True):
     st = srv.stats()
     srv.close()
     print("# serve: FIFO FP64 baseline", file=sys.stderr, flush=True)
-    fifo = run_fifo_fp64(mg, reqs, fs, us, a.tol, arrivals, a.fifo_count, torch)
+    fifo = run_fifo_fp64(mg, reqs, fs, us, a.tol, arrivals, a.fifo_count or a.count, torch)
     out = {"workload": f"{a.count} Poisson solve requests, 2-D 65^2..1025^2 and 3-D 33^3..129^3 nodes, "
                        f"mixed precision to relres {a.tol:g}",
            "cold_start": warm, "saturation": sat, "rate_per_s": rate, "load": a.load, "open_loop": opn,

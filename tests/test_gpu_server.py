@@ -128,7 +128,7 @@ def test_queue_limit_and_invalid_requests(mg):
     r.id, r.grid, r.tol = 11, mg.make_grid(3, 17), 1e-8
     r.opts = mg.make_opts(mg.MG_RBGS, 0.8, 3, 3, mg.MG_MIXED, 50, 0, mg.MG_CYCLE_W)
     r.f, r.u_out = f.data_ptr(), u.data_ptr()
-    assert mg.mg_server_submit(srv.h, mg.C.byref(r)) == mg.MG_EINVAL
+    assert mg.mg_server_submit(srv.h, mg.C.byref(r), None) == mg.MG_EINVAL
     big = mg.server_footprint(3, 257, mg.MG_RBGS, 3, 3)
     assert big > (256 << 20)
     fb = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
@@ -148,6 +148,41 @@ def test_queue_limit_and_invalid_requests(mg):
     torch.cuda.synchronize()
     assert out[0]["status"] == mg.MG_OK and float(u.abs().max()) == 0.0
     srv.close()
+
+
+def test_tickets_and_latency_accounting_on_the_supplied_clock(mg):
+    """Tickets are issued 0, 1, 2, ... in submission order and come back in
+    the results; a result keeps the arrival time the caller supplied (here
+    0.25 s before submission, and one at submission), is admitted no
+    earlier than it was submitted and finishes after admission, so
+    t_done - t_arrive counts the time before submission too."""
+    import torch
+    srv = mg.Server(512 << 20, max_slots=4)
+    reqs = [(3, 33), (2, 65), (3, 17), (2, 129), (3, 33)]
+    fs, us = make_inputs(torch, reqs)
+    tickets, submitted, arrive = {}, {}, {}
+    for rid, (d, n) in enumerate(reqs):
+        sm, nu1, nu2 = method(d)
+        now = srv.clock()
+        arrive[rid] = now - 0.25 if rid % 2 == 0 else now
+        submitted[rid] = now
+        assert srv.submit(rid, d, n, fs[rid], us[rid], 1e-8, sm, nu1, nu2, t_arrive=arrive[rid]) == mg.MG_OK
+        tickets[rid] = srv.last_ticket
+    assert [tickets[i] for i in range(len(reqs))] == list(range(len(reqs)))
+    done = {}
+    while len(done) < len(reqs):
+        srv.step()
+        for r in srv.poll():
+            done[r["id"]] = r
+    srv.close()
+    for rid, r in done.items():
+        assert r["status"] == mg.MG_OK and r["ticket"] == tickets[rid]
+        assert r["t_arrive"] == arrive[rid]
+        assert submitted[rid] <= r["t_admit"] <= r["t_done"]
+        lat = r["t_done"] - r["t_arrive"]
+        assert lat >= (0.25 if rid % 2 == 0 else 0.0)
+        print(f"request {rid} ticket {r['ticket']}: latency {1e3 * lat:.2f} ms, queued "
+              f"{1e3 * (r['t_admit'] - r['t_arrive']):.2f} ms", flush=True)
 
 
 def test_largest_classes_alone_equal_mix_and_match_oracle(mg):
