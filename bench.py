@@ -101,19 +101,48 @@ def cpu_model() -> str:
 
 
 def cpu_baseline(n_sample: int = 257):
-    """The oracle (plain NumPy FP64, one core) timed on one V(3,3)-cycle of the
-    same problem at a bounded size."""
+    """The oracle (plain NumPy FP64, one core) timed on bounded samples of the
+    workloads: one V(3,3)-cycle of the 3-D Poisson problem at n_sample^3 (the
+    reported value), and beside it the 2-D 129^2 case's ten Jacobi V(2,2)
+    cycles, one single-precision refinement step of the mixed solve
+    (float32-emulating cycle) at n_sample^3, and one V(3,3)-cycle of the
+    variable-coefficient cell problem at 128^3 cells (about 15 s in all)."""
     import numpy as np
     from oracle import cycle
     from paper_1904_08684_amd import workloads as W
+    host = f"NumPy single thread on {cpu_model()}, {os.cpu_count()} host CPUs"
+
+    def timed(fn):
+        t = time.perf_counter()
+        fn()
+        return time.perf_counter() - t
+
     f = W.interior_uniform(n_sample, 3, W.SEED_F_3D)
     h = cycle.build_hierarchy(cycle.Params(centering="node", dim=3, n=n_sample, smoother="rbgs", nu1=3, nu2=3))
-    t = time.perf_counter()
-    cycle.vcycle(h, np.zeros_like(f), f)
-    dt = time.perf_counter() - t
-    return {"value": (n_sample - 2) ** 3 / dt / 1e6, "unit": "MLUpS", "cores": 1, "kind": "oracle",
-            "sample": f"one V(3,3) RB-GS cycle of the 3-D Poisson problem at {n_sample}^3 nodes "
-                      f"({dt:.1f} s, NumPy single thread on {cpu_model()}, {os.cpu_count()} host CPUs)"}
+    dt = timed(lambda: cycle.vcycle(h, np.zeros_like(f), f))
+    dt_mx = timed(lambda: cycle.mixed_solve(h, f, tol=0.0, max_outer=1))
+    n2 = 129
+    f2 = W.sine_rhs_2d(n2)
+    u2 = W.interior_uniform(n2, 2, W.SEED_U0_2D)
+    h2 = cycle.build_hierarchy(cycle.Params(centering="node", dim=2, n=n2, smoother="jacobi", omega=0.8,
+                                            nu1=2, nu2=2))
+    dt2 = timed(lambda: cycle.cycles(h2, f2, u2, 10))
+    nc = 128
+    kc = W.varcoef_k(nc, 3)
+    fc = W.normal_zero_mean(nc, 3, W.SEED_F_VARCOEF)
+    hc = cycle.build_hierarchy(cycle.Params(centering="cell", dim=3, n=nc, coarsest=4, smoother="rbgs",
+                                            nu1=3, nu2=3, k=kc))
+    dtc = timed(lambda: cycle.vcycle(hc, np.zeros_like(fc), fc))
+    m = (n_sample - 2) ** 3
+    return {"value": m / dt / 1e6, "unit": "MLUpS", "cores": 1, "kind": "oracle",
+            "sample": f"one V(3,3) RB-GS cycle of the 3-D Poisson problem at {n_sample}^3 nodes ({dt:.1f} s, {host})",
+            "others": {
+                "poisson2d_129_jacobi_10cycles": {"ms_per_cycle": round(1e2 * dt2, 2),
+                                                  "mlups": round(127 ** 2 * 10 / dt2 / 1e6, 2)},
+                f"mixed_refinement_step_{n_sample}": {"s": round(dt_mx, 2), "mlups": round(m / dt_mx / 1e6, 2),
+                                                      "note": "FP64 residual + float32-emulating V(3,3) cycle"},
+                "varcoef_cell_128_cycle": {"s": round(dtc, 2), "mlups": round(nc ** 3 / dtc / 1e6, 2)},
+                "full_513_solve_estimate_s": round(8 * 511 ** 3 / (m / dt), 1)}}
 
 
 def best_of(torch, run, reset=None, reps: int = 3):
@@ -134,7 +163,10 @@ def best_of(torch, run, reset=None, reps: int = 3):
     return best, out
 
 
-def other_configs(mg, W, torch, np):
+CONFIG_GROUPS = ("poisson2d", "varcoef", "cycles", "fmg", "dg")
+
+
+def other_configs(mg, W, torch, np, groups=CONFIG_GROUPS):
     """The 2-D 129^2 Jacobi case (10 V(2,2) cycles, latency bound), the
     256^3-cell variable-coefficient case (FP64 and mixed to 1e-10, FP64 with
     zero-flux walls, and CG preconditioned by the cycle), W- and F-cycle
@@ -155,103 +187,108 @@ def other_configs(mg, W, torch, np):
         dt, (code, its, rel) = best_of(torch, lambda: s.pcg(tol, 40), lambda: s.set_initial(None))
         return dt, code, its, rel
 
-    # 2-D 129^2, ten damped-Jacobi V(2,2) cycles from the seeded start
-    n = 129
-    s = mg.Solver(2, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2)
-    s.set_rhs(W.sine_rhs_2d(n))
-    u0 = W.interior_uniform(n, 2, W.SEED_U0_2D)
-    dt, _ = best_of(torch, lambda: s.vcycle(10), lambda: s.set_initial(u0), reps=20)
-    res["poisson2d_129_jacobi_10cycles"] = {"ms_per_10_cycles": round(1e3 * dt, 3),
-                                            "us_per_cycle": round(1e5 * dt, 2),
-                                            "mlups": round(127 ** 2 * 10 / dt / 1e6, 1)}
-    s.close()
+    if "poisson2d" in groups:
+        # 2-D 129^2, ten damped-Jacobi V(2,2) cycles from the seeded start
+        n = 129
+        s = mg.Solver(2, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2)
+        s.set_rhs(W.sine_rhs_2d(n))
+        u0 = W.interior_uniform(n, 2, W.SEED_U0_2D)
+        dt, _ = best_of(torch, lambda: s.vcycle(10), lambda: s.set_initial(u0), reps=20)
+        res["poisson2d_129_jacobi_10cycles"] = {"ms_per_10_cycles": round(1e3 * dt, 3),
+                                                "us_per_cycle": round(1e5 * dt, 2),
+                                                "mlups": round(127 ** 2 * 10 / dt / 1e6, 1)}
+        s.close()
 
-    # 256^3 cells, variable coefficient
-    N = 256
-    k = torch.from_numpy(W.varcoef_k(N, 3)).cuda()
-    f = torch.from_numpy(W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)).cuda()
-    sols = {}
-    for prec, name in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
-        s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, precision=prec)
+    if "varcoef" in groups:
+        # 256^3 cells, variable coefficient
+        N = 256
+        k = torch.from_numpy(W.varcoef_k(N, 3)).cuda()
+        f = torch.from_numpy(W.normal_zero_mean(N, 3, W.SEED_F_VARCOEF)).cuda()
+        sols = {}
+        for prec, name in ((mg.MG_FP64, "fp64"), (mg.MG_MIXED, "mixed")):
+            s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, precision=prec)
+            dt, code, cyc, rel = solve_entry(s, f)
+            res[f"varcoef_cell_256_{name}"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
+                                               "status": code, "mlups": round(N ** 3 * cyc / dt / 1e6, 1)}
+            sols[name] = torch.empty((N, N, N), dtype=torch.float64, device="cuda")
+            s.solution(sols[name])
+            s.close()
+        res["varcoef_cell_256_mixed"]["max_rel_diff_vs_fp64_solution"] = float(
+            (sols["mixed"] - sols["fp64"]).abs().max() / sols["fp64"].abs().max())
+        # the same problem with zero-flux walls (projected right-hand side, zero-mean solution)
+        s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, bc=mg.MG_NEUMANN0)
         dt, code, cyc, rel = solve_entry(s, f)
-        res[f"varcoef_cell_256_{name}"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
-                                           "status": code, "mlups": round(N ** 3 * cyc / dt / 1e6, 1)}
-        sols[name] = torch.empty((N, N, N), dtype=torch.float64, device="cuda")
-        s.solution(sols[name])
+        res["varcoef_cell_256_neumann_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
+                                                "status": code, "mlups": round(N ** 3 * cyc / dt / 1e6, 1)}
         s.close()
-    res["varcoef_cell_256_mixed"]["max_rel_diff_vs_fp64_solution"] = float(
-        (sols["mixed"] - sols["fp64"]).abs().max() / sols["fp64"].abs().max())
-    # the same problem with zero-flux walls (projected right-hand side, zero-mean solution)
-    s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k, bc=mg.MG_NEUMANN0)
-    dt, code, cyc, rel = solve_entry(s, f)
-    res["varcoef_cell_256_neumann_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
-                                            "status": code, "mlups": round(N ** 3 * cyc / dt / 1e6, 1)}
-    s.close()
-    # the same problem by CG preconditioned with the symmetric V(3,3)-cycle
-    s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, k=k, krylov=1)
-    dt, code, its, rel = pcg_entry(s, f)
-    u = torch.empty((N, N, N), dtype=torch.float64, device="cuda")
-    s.solution(u)
-    res["varcoef_cell_256_pcg_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "iterations": its,
-                                        "relres": rel, "status": code,
-                                        "max_rel_diff_vs_fp64_solution": float(
-                                            (u - sols["fp64"]).abs().max() / sols["fp64"].abs().max())}
-    s.close()
-    sols = u = k = f = None
+        # the same problem by CG preconditioned with the symmetric V(3,3)-cycle
+        s = mg.Solver(3, N, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, k=k, krylov=1)
+        dt, code, its, rel = pcg_entry(s, f)
+        u = torch.empty((N, N, N), dtype=torch.float64, device="cuda")
+        s.solution(u)
+        res["varcoef_cell_256_pcg_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "iterations": its,
+                                            "relres": rel, "status": code,
+                                            "max_rel_diff_vs_fp64_solution": float(
+                                                (u - sols["fp64"]).abs().max() / sols["fp64"].abs().max())}
+        s.close()
+        sols = u = k = f = None
 
-    # 513^3 Poisson: W- and F-cycles, damped-Jacobi cycles with both coarse
-    # operators, and CG preconditioned by the symmetric V(3,3)-cycle
-    n = 513
-    f3 = torch.from_numpy(W.interior_uniform(n, 3, W.SEED_F_3D)).cuda()
-    for code_c, name in ((mg.MG_CYCLE_W, "W"), (mg.MG_CYCLE_F, "F")):
-        s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, cycle=code_c)
-        dt, code, cyc, rel = solve_entry(s, f3)
-        res[f"poisson3d_513_{name}cycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
-                                                 "status": code, "ms_per_cycle": round(1e3 * dt / cyc, 3)}
+    if "cycles" in groups:
+        # 513^3 Poisson: W- and F-cycles, damped-Jacobi cycles with both coarse
+        # operators, and CG preconditioned by the symmetric V(3,3)-cycle
+        n = 513
+        f3 = torch.from_numpy(W.interior_uniform(n, 3, W.SEED_F_3D)).cuda()
+        for code_c, name in ((mg.MG_CYCLE_W, "W"), (mg.MG_CYCLE_F, "F")):
+            s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, cycle=code_c)
+            dt, code, cyc, rel = solve_entry(s, f3)
+            res[f"poisson3d_513_{name}cycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc, "relres": rel,
+                                                     "status": code, "ms_per_cycle": round(1e3 * dt / cyc, 3)}
+            s.close()
+        for cop, name in ((mg.MG_COARSE_REDISCRETISE, "rediscretised"), (mg.MG_COARSE_GALERKIN, "galerkin")):
+            s = mg.Solver(3, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2, coarse_op=cop)
+            dt, code, cyc, rel = solve_entry(s, f3)
+            res[f"poisson3d_513_jacobi_{name}_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc,
+                                                         "relres": rel, "status": code,
+                                                         "ms_per_cycle": round(1e3 * dt / cyc, 3)}
+            s.close()
+        s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, krylov=1)
+        dt, code, its, rel = pcg_entry(s, f3)
+        res["poisson3d_513_pcg_vcycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "iterations": its, "relres": rel,
+                                                "status": code, "ms_per_iteration": round(1e3 * dt / its, 3)}
         s.close()
-    for cop, name in ((mg.MG_COARSE_REDISCRETISE, "rediscretised"), (mg.MG_COARSE_GALERKIN, "galerkin")):
-        s = mg.Solver(3, n, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2, coarse_op=cop)
-        dt, code, cyc, rel = solve_entry(s, f3)
-        res[f"poisson3d_513_jacobi_{name}_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "cycles": cyc,
-                                                     "relres": rel, "status": code,
-                                                     "ms_per_cycle": round(1e3 * dt / cyc, 3)}
-        s.close()
-    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3, post_order=1, krylov=1)
-    dt, code, its, rel = pcg_entry(s, f3)
-    res["poisson3d_513_pcg_vcycle_fp64"] = {"ms_to_1e-10": round(1e3 * dt, 3), "iterations": its, "relres": rel,
-                                            "status": code, "ms_per_iteration": round(1e3 * dt / its, 3)}
-    s.close()
-    f3 = None
+        f3 = None
 
-    # full multigrid on the sine problem, whose discrete solution is known in
-    # closed form: one pass with two V(3,3)-cycles per level
-    ue = torch.from_numpy(W.sine_mode(n, 3)).cuda()
-    fs = 3 * np.pi ** 2 * ue
-    s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
-    s.set_rhs(fs)
-    dt, _ = best_of(torch, lambda: s.fmg(2))
-    u = torch.empty_like(fs)
-    s.solution(u)
-    hh = 1.0 / (n - 1)
-    ch = (np.pi * hh / 2) ** 2 / np.sin(np.pi * hh / 2) ** 2
-    res["fmg_513_sine_fp64"] = {"ms": round(1e3 * dt, 3), "cycles_per_level": 2,
-                                "algebraic_over_discretisation_error": float((u - ch * ue).abs().max()) / abs(ch - 1.0),
-                                "relres": s.residual_norm() / float(torch.linalg.vector_norm(fs[1:-1, 1:-1, 1:-1]))}
-    s.close()
-    u = ue = fs = None
+    if "fmg" in groups:
+        # full multigrid on the sine problem, whose discrete solution is known in
+        # closed form: one pass with two V(3,3)-cycles per level
+        ue = torch.from_numpy(W.sine_mode(n, 3)).cuda()
+        fs = 3 * np.pi ** 2 * ue
+        s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
+        s.set_rhs(fs)
+        dt, _ = best_of(torch, lambda: s.fmg(2))
+        u = torch.empty_like(fs)
+        s.solution(u)
+        hh = 1.0 / (n - 1)
+        ch = (np.pi * hh / 2) ** 2 / np.sin(np.pi * hh / 2) ** 2
+        res["fmg_513_sine_fp64"] = {"ms": round(1e3 * dt, 3), "cycles_per_level": 2,
+                                    "algebraic_over_discretisation_error": float((u - ch * ue).abs().max()) / abs(ch - 1.0),
+                                    "relres": s.residual_norm() / float(torch.linalg.vector_norm(fs[1:-1, 1:-1, 1:-1]))}
+        s.close()
+        u = ue = fs = None
 
     # the quadrature-free DG shallow-water scheme on 2 x 1024^2 perturbed
     # split-quad triangles, orders 1-3: each term, the right-hand side and an
     # SSP-RK3 step (HIP events)
-    from paper_1904_08684_amd import dgbench
-    for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection"),
-                     ("edges", "dg_edge_terms"), ("rhs", "dg_rhs"), ("step", "dg_ssp_rk3_step")):
-        for kk in (1, 2, 3):
-            r = dgbench.run(1024, kk, 20, op)
-            res[f"{name}_k{kk}_2M_elements"] = {
-                "ms": round(r["ms"], 4), "elements": r["elements"], "gflops": round(r["gflops"], 1),
-                "GBps": round(r["GBps"], 1), "frac_fp64_vector_peak": round(r["frac_fp64_vector"], 3),
-                "frac_hbm_peak": round(r["frac_hbm"], 3)}
+    if "dg" in groups:
+        from paper_1904_08684_amd import dgbench
+        for op, name in (("volume", "dg_volume_terms"), ("projection", "dg_velocity_projection"),
+                         ("edges", "dg_edge_terms"), ("rhs", "dg_rhs"), ("step", "dg_ssp_rk3_step")):
+            for kk in (1, 2, 3):
+                r = dgbench.run(1024, kk, 20, op)
+                res[f"{name}_k{kk}_2M_elements"] = {
+                    "ms": round(r["ms"], 4), "elements": r["elements"], "gflops": round(r["gflops"], 1),
+                    "GBps": round(r["GBps"], 1), "frac_fp64_vector_peak": round(r["frac_fp64_vector"], 3),
+                    "frac_hbm_peak": round(r["frac_hbm"], 3)}
     return res
 
 
@@ -266,6 +303,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--configs", default=",".join(CONFIG_GROUPS),
+                    help="comma list of the other configurations to run: " + ", ".join(CONFIG_GROUPS))
     ap.add_argument("--serve-count", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -410,7 +449,7 @@ def main():
     r64 = rmx = None
     torch.cuda.empty_cache()
     if not args.no_configs:
-        out["other_configs"] = other_configs(mg, W, torch, np)
+        out["other_configs"] = other_configs(mg, W, torch, np, tuple(args.configs.split(",")))
     if not args.no_serve:
         print("# bench: served stream", file=sys.stderr, flush=True)
         from paper_1904_08684_amd import serve_bench
