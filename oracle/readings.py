@@ -61,4 +61,10 @@ READINGS = {
            "which states neither); the body force enters as the coefficients of its L2 projection; "
            "the integrator is the three-stage SSP Runge-Kutta method of Shu and Osher with the "
            "velocity projected from every stage state.",
+    "R24": "Gravity in the convergence test: the paper states no value of g.  With g = 9.81 the "
+           "momentum errors are 4-7 times the table's and a step of 0.5 is unstable on the finest "
+           "meshes; one column (k = 1, every mesh, step 0.5) run once with g = 1 is stable and gives "
+           "xi errors within 11 % and U, V errors within 0.9-2.1 times the table's, so the table "
+           "is read as computed with g = 1 (a nondimensional gravity); the library takes g as an "
+           "argument and nothing in it depends on this reading.",
 }

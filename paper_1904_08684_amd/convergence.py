@@ -47,9 +47,9 @@ class Problem:
     """The test on an nx x nx split-quad mesh (2 nx^2 elements) at order k."""
 
     def __init__(self, k: int, nx: int, device: str = "cuda", seed: int = W.SEED_DG_MESH, quad: int = 8,
-                 with_system: bool = True):
+                 with_system: bool = True, g: float = GRAV):
         import torch
-        self.k, self.K, self.nx = k, mg.DG_K[k], nx
+        self.k, self.K, self.nx, self.g = k, mg.DG_K[k], nx, g
         B, a1 = W.dg_mesh(nx, nx, seed=seed, with_origin=True, length=LENGTH)
         nbr, nq = W.dg_mesh_neighbours(nx, nx)
         nbr, be, _ = W.dg_boundary_ghosts(nbr)
@@ -72,7 +72,7 @@ class Problem:
         self.hb = hb
         self.system = None if not with_system else mg.DGSystem(k, Bt.contiguous(), hb.contiguous(),
                                   torch.tensor(nbr, dtype=torch.int32, device=dev),
-                                  torch.tensor(nq, dtype=torch.int32, device=dev), nb=self.nb, g=GRAV)
+                                  torch.tensor(nq, dtype=torch.int32, device=dev), nb=self.nb, g=g)
 
     # -------------------------------------------------- the test problem's data
     def project(self, vals):
@@ -102,8 +102,8 @@ class Problem:
         dqt = C_A * C_T * C_T * d            # dU/dt = dV/dt
         Hx, Hy = 1.0 / 1000.0 + dxi, 2.0 / 1000.0 + dxi
         H2 = H * H
-        FU = dqt + (2.0 * U * dq * H - U * U * Hx) / H2 + ((dq * V + U * dq) * H - U * V * Hy) / H2 + GRAV * H * dxi
-        FV = dqt + ((dq * V + U * dq) * H - U * V * Hx) / H2 + (2.0 * V * dq * H - V * V * Hy) / H2 + GRAV * H * dxi
+        FU = dqt + (2.0 * U * dq * H - U * U * Hx) / H2 + ((dq * V + U * dq) * H - U * V * Hy) / H2 + self.g * H * dxi
+        FV = dqt + ((dq * V + U * dq) * H - U * V * Hx) / H2 + (2.0 * V * dq * H - V * V * Hy) / H2 + self.g * H * dxi
         return FU, FV
 
     def state(self, t: float):
@@ -169,12 +169,14 @@ class Problem:
 WAVE_SPEED = 8.5
 
 
-def stable_dt(k: int, nx: int, t_end: float, dt_max: float = 0.5, cfl: float = 0.25):
+def stable_dt(k: int, nx: int, t_end: float, dt_max: float = 0.5, cfl: float = 0.25, g: float = GRAV):
     """The paper's step (0.5), or less where the explicit scheme needs it:
     lambda dt (2k + 1) / h <= cfl with h the square's side (runs at 0.4 and
-    above blew up); returns (dt, steps) with steps dt = t_end."""
+    above blew up); returns (dt, steps) with steps dt = t_end.  For another
+    g the wave speed bound is 0.25 + sqrt(6.7 g) (H <= 6.7)."""
     h = LENGTH / nx
-    dt = min(dt_max, cfl * h / (WAVE_SPEED * (2 * k + 1)))
+    speed = WAVE_SPEED if g == GRAV else 0.25 + math.sqrt(6.7 * g)
+    dt = min(dt_max, cfl * h / (speed * (2 * k + 1)))
     steps = int(math.ceil(t_end / dt - 1e-9))
     return t_end / steps, steps
 
@@ -209,6 +211,8 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=1500.0)
     ap.add_argument("--dt", type=float, default=0.5)
     ap.add_argument("--max-nx", type=int, default=128)
+    ap.add_argument("--g", type=float, default=GRAV, help="gravitational acceleration (the paper states none)")
+    ap.add_argument("--exact-dt", action="store_true", help="step with --dt on every mesh, no stability cap")
     a = ap.parse_args(argv)
     levels = {0: [4, 8, 16, 32, 64, 128], 1: [4, 8, 16, 32, 64], 2: [4, 8, 16, 32], 3: [4, 8, 16, 32]}
     for k in a.orders:
@@ -216,14 +220,15 @@ def main(argv=None):
         for nx in levels[k]:
             if nx > a.max_nx:
                 break
-            dt, steps = stable_dt(k, nx, a.t_end, a.dt)
-            print(f"# k={k} nx={nx}: {2 * nx * nx} elements, {steps} steps of {dt:.4g}", flush=True)
+            dt, steps = (a.dt, int(round(a.t_end / a.dt))) if a.exact_dt else stable_dt(k, nx, a.t_end, a.dt, g=a.g)
+            print(f"# k={k} nx={nx}: {2 * nx * nx} elements, {steps} steps of {dt:.4g}, g = {a.g:g}", flush=True)
             t0 = time.perf_counter()
-            pr = Problem(k, nx)
+            pr = Problem(k, nx, g=a.g)
             c, steps = pr.run(a.t_end, dt)
             err = pr.errors(c, a.t_end)
             eoc = None if prev is None else [round(math.log2(p / e), 2) for p, e in zip(prev, err)]
-            print(json.dumps({"k": k, "elements": pr.ne, "steps": steps, "dt": dt, "err_xi": err[0], "err_U": err[1],
+            print(json.dumps({"k": k, "g": a.g, "elements": pr.ne, "steps": steps, "dt": dt, "err_xi": err[0],
+                              "err_U": err[1],
                               "err_V": err[2], "eoc": eoc, "seconds": round(time.perf_counter() - t0, 2)}),
                   flush=True)
             prev = err

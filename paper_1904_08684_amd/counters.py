@@ -49,8 +49,8 @@ def read(path: str, counter: str):
 
 def short(name: str) -> str:
     """Kernel name without namespaces and argument list."""
-    base = name.split("(")[0]
-    for pre in ("void ", "mg::(anonymous namespace)::"):
+    base = name.replace("(anonymous namespace)::", "").split("(")[0]
+    for pre in ("void ", "mg::"):
         base = base.replace(pre, "")
     return base.strip()
 
