@@ -261,6 +261,7 @@ def other_configs(mg, W, torch, np, groups=CONFIG_GROUPS):
     if "fmg" in groups:
         # full multigrid on the sine problem, whose discrete solution is known in
         # closed form: one pass with two V(3,3)-cycles per level
+        n = 513
         ue = torch.from_numpy(W.sine_mode(n, 3)).cuda()
         fs = 3 * np.pi ** 2 * ue
         s = mg.Solver(3, n, smoother=mg.MG_RBGS, nu1=3, nu2=3)
@@ -462,6 +463,12 @@ def main():
                         "saturation_solves_per_s": round(sv["saturation"]["solves_per_s"], 1),
                         "fifo_fp64_one_at_a_time": {k: round(v, 3) for k, v in sv["fifo_fp64_one_at_a_time"].items()},
                         "speedup_solves_per_s": round(sv["speedup_solves_per_s"], 2), "server": sv["server"],
+                        "batched_bytes": {"saturation_mb_per_round": round(sv["saturation"]["algorithmic_mb_per_round"], 2),
+                                          "saturation_GBps_over_makespan":
+                                              round(sv["saturation"]["algorithmic_GBps_over_makespan"], 1),
+                                          "open_loop_GBps_over_makespan":
+                                              round(sv["open_loop"]["algorithmic_GBps_over_makespan"], 1),
+                                          "peak_GBps": HBM_PEAK_GBS},
                         "load_sweep": [{k: round(v, 3) for k, v in row.items()} for row in sv["load_sweep"]]}
     if not args.no_cpu_baseline:
         print("# bench: CPU oracle baseline", file=sys.stderr, flush=True)

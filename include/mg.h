@@ -291,6 +291,10 @@ typedef struct mg_server_stats {
     long long rounds, launches, admitted, completed, hierarchies_built, evictions;
     size_t arena_peak_bytes, arena_used_bytes;
     int in_flight, queued, resident;
+    /* algorithmic device-memory bytes of the batched launches so far: each
+     * op's compulsory reads and writes (e.g. 12 B per point of an FP32
+     * Jacobi sweep, 24 B of an FP64 residual), summed over every op run */
+    double algorithmic_bytes;
 } mg_server_stats;
 
 /* Device bytes one resident hierarchy of this grid and options occupies. */

@@ -204,4 +204,42 @@ static inline TbSpace make_tbspace(const Geom& g, int S, int rows) {
     return t;
 }
 
+// The lower part of a V-cycle in one workgroup: every level from
+// lg[0] down to the coarsest keeps its iterate, a second buffer (Jacobi's
+// output and the residual) and its right-hand side in LDS, in colour-split
+// layout with rows of exactly `half` entries.  Offsets are in elements of
+// the hierarchy's precision; the spaces are those of the per-level launches
+// (one colour each, both colours, and the prolongation's colour mask).  The
+// coarsest level's Cholesky factor follows the fields in LDS.
+constexpr int kTailMax = 6;
+constexpr int kTailThreads = 1024;
+constexpr int kTailLdsBytes = 156 * 1024;
+
+struct TailPlan {
+    int nl;                       // levels, the last one the coarsest
+    int rbgs;                     // 1 red-black Gauss-Seidel, 0 damped Jacobi
+    int nu1, nu2, post_order;
+    int from_zero;                // the top level starts from a zero iterate
+    int m;                        // coarsest unknowns
+    int elems;                    // LDS elements in use
+    double omega;
+    const double* chol;           // Cholesky factor of the coarsest matrix
+    const void* beta[kTailMax][3];  // face coefficients (cell grids), device memory
+    Geom g0;                      // the top level in device memory
+    Geom lg[kTailMax];            // every level in LDS
+    Space one[kTailMax][2], all[kTailMax], pro[kTailMax];
+    int oa[kTailMax], ob[kTailMax], of[kTailMax];
+    double s[kTailMax];
+};
+
+// LDS geometry of a level: rows of exactly `half` entries (face arrays keep
+// their device-memory layout).
+static inline Geom tail_geom(const Geom& g) {
+    Geom l = g;
+    l.pitch = g.half;
+    l.plane = (long long)g.ny * g.half;
+    l.cs = (long long)g.nz * l.plane;
+    return l;
+}
+
 }  // namespace mg

@@ -59,6 +59,11 @@ hipError_t launch_prolong(const Geom& gf, const Geom& gc, int prec, void* u, con
 hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const double* L, int m,
                          hipStream_t st);
 
+// One V-cycle from the top level of P (right-hand side f, iterate u in
+// device memory; u read unless P.from_zero) down to the coarsest and back,
+// in one workgroup with every level's fields in LDS; u receives the result.
+hipError_t launch_tail(const TailPlan& P, int prec, const void* f, void* u, hipStream_t st);
+
 // Deterministic reduction of `count` (sum, max) pairs to out[0..1];
 // scratch holds at least 2 * ceil(count / 4096) doubles.
 // Constant 3^d-point node stencil (a Galerkin coarse operator R A P):
@@ -135,7 +140,7 @@ enum BOp : int {
     BOP_ZERO,          // n 16-byte words at a
     BOP_RES64,         // r64 = f64 - A u64, per-tile (sum r^2, max |r|) to part
     BOP_REDUCE,        // part[0..n) -> red[0..1] and res[0..1]
-    BOP_CAST,          // f32 = fl32(r64 / sigma), sigma = 2^floor(log2 red[1]) -> red[2]
+    BOP_CAST,          // f32 = fl32(r64 / sigma), sigma = 2^floor(log2 red[3]) -> red[2]
     BOP_GS,            // FP32 GS half-sweep (colour-offset pointers)
     BOP_GS_ZERO,       // FP32 GS half-sweep from a zero iterate
     BOP_JAC,           // FP32 damped Jacobi, out of place

@@ -126,17 +126,24 @@ __device__ __forceinline__ T node_nb(const T* __restrict__ o, long long ro, int 
 }
 
 template <typename T, int D, bool ZERO>
-__device__ __forceinline__ void d_node_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
+__device__ __forceinline__ void pt_node_gs(const Pt& p, Geom g, Space sp, T* __restrict__ me,
                                                  const T* __restrict__ other, const T* __restrict__ f,
                                                  T s) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > g.n - 2) return;
     const long long ro = row_off(g, p.y, p.z) + p.xs;
     const T nb = ZERO ? T(0) : node_nb<T, D>(other, ro, par, g);
     me[ro] = (f[ro] / s + nb) / T(2 * D);
+}
+
+template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void d_node_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 T s) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_node_gs<T, D, ZERO>(p, g, sp, me, other, f, s);
 }
 
 template <typename T, int D, bool ZERO>
@@ -147,11 +154,9 @@ __global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict
 }
 
 template <typename T, int D, bool ZERO>
-__device__ __forceinline__ void d_node_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
+__device__ __forceinline__ void pt_node_jacobi(const Pt& p, Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
                                                      T s, T omega) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > g.n - 2) return;
@@ -164,10 +169,33 @@ __device__ __forceinline__ void d_node_jacobi(const Ex& ex, Geom g, Space sp, co
 }
 
 template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void d_node_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out,
+                                                     T s, T omega) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_node_jacobi<T, D, ZERO>(p, g, sp, u, f, out, s, omega);
+}
+
+template <typename T, int D, bool ZERO>
 __global__ __launch_bounds__(256) void k_node_jacobi(Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
                                                      T s, T omega) {
     d_node_jacobi<T, D, ZERO>(solo_ex(), g, sp, u, f, out, s, omega);
+}
+
+// Residual at point p (false outside the unknowns): its index and value.
+template <typename T, int D>
+__device__ __forceinline__ bool pt_node_residual(const Pt& p, const Geom& g, const T* __restrict__ u,
+                                                 const T* __restrict__ f, T s, long long& me, T& rv) {
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (x < 1 || x > g.n - 2) return false;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    me = (long long)p.c * g.cs + ro;
+    const T nb = node_nb<T, D>(u + (long long)(1 - p.c) * g.cs, ro, par, g);
+    rv = f[me] - (T(2 * D) * u[me] - nb) * s;
+    return true;
 }
 
 template <typename T, int D, bool NORM, bool STORE>
@@ -176,19 +204,13 @@ __device__ __forceinline__ void d_node_residual(const Ex& ex, Geom g, Space sp, 
                                                        T s, double* __restrict__ part) {
     double sq = 0.0, mx = 0.0;
     Pt p;
-    if (map_point(ex, sp, p)) {
-        const int par = (p.y + p.z + p.c) & 1;
-        const int x = 2 * p.xs + par;
-        if (x >= 1 && x <= g.n - 2) {
-            const long long ro = row_off(g, p.y, p.z) + p.xs;
-            const long long me = (long long)p.c * g.cs + ro;
-            const T nb = node_nb<T, D>(u + (long long)(1 - p.c) * g.cs, ro, par, g);
-            const T rv = f[me] - (T(2 * D) * u[me] - nb) * s;
-            if (STORE) r[me] = rv;
-            const double dv = (double)rv;
-            sq = dv * dv;
-            mx = fabs(dv);
-        }
+    long long me;
+    T rv;
+    if (map_point(ex, sp, p) && pt_node_residual<T, D>(p, g, u, f, s, me, rv)) {
+        if (STORE) r[me] = rv;
+        const double dv = (double)rv;
+        sq = dv * dv;
+        mx = fabs(dv);
     }
     if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
 }
@@ -1147,11 +1169,9 @@ __global__ __launch_bounds__(256) void k_node_prolong_zm(Geom gf, Geom gc, ZSpac
 // Full weighting: f_c[X] = sum_{o in {-1,0,1}^d} prod_a (2 - |o_a|) / 4^d r[2X + o],
 // summed with the z offset slowest and the x offset fastest.
 template <typename T, int D>
-__device__ __forceinline__ void d_node_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
+__device__ __forceinline__ void pt_node_restrict(const Pt& p, Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ fcoarse) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int X = 2 * p.xs + par;
     if (X < 1 || X > gc.n - 2) return;
@@ -1179,6 +1199,15 @@ __device__ __forceinline__ void d_node_restrict(const Ex& ex, Geom gf, Geom gc, 
 }
 
 template <typename T, int D>
+__device__ __forceinline__ void d_node_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_node_restrict<T, D>(p, gf, gc, sp, r, fcoarse);
+}
+
+template <typename T, int D>
 __global__ __launch_bounds__(256) void k_node_restrict(Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ fcoarse) {
@@ -1189,10 +1218,8 @@ __global__ __launch_bounds__(256) void k_node_restrict(Geom gf, Geom gc, Space s
 // node: coarse value; odd: half the sum of the two coarse neighbours),
 // along x first, then y, then z; then u += P e.
 template <typename T, int D>
-__device__ __forceinline__ void d_node_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
+__device__ __forceinline__ void pt_node_prolong(const Pt& p, Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > gf.n - 2) return;
@@ -1214,6 +1241,14 @@ __device__ __forceinline__ void d_node_prolong(const Ex& ex, Geom gf, Geom gc, S
         e = iy(0);
     const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
     u[me] = u[me] + e;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void d_node_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
+                                                      const T* __restrict__ ec) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_node_prolong<T, D>(p, gf, gc, sp, u, ec);
 }
 
 template <typename T, int D>
@@ -1273,18 +1308,26 @@ __device__ __forceinline__ void cell_sums(const Geom& g, const T* __restrict__ o
 }
 
 template <typename T, int D, bool ZERO>
-__device__ __forceinline__ void d_cell_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
+__device__ __forceinline__ void pt_cell_gs(const Pt& p, Geom g, Space sp, T* __restrict__ me,
                                                  const T* __restrict__ other, const T* __restrict__ f,
                                                  const T* __restrict__ bx, const T* __restrict__ by,
                                                  const T* __restrict__ bz, T s) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     const long long ro = row_off(g, p.y, p.z) + p.xs;
     T dg, off;
     cell_sums<T, D, ZERO>(g, other, ro, par, x, p.y, p.z, bx, by, bz, dg, off);
     me[ro] = (f[ro] / s + off) / dg;
+}
+
+template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void d_cell_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 const T* __restrict__ bx, const T* __restrict__ by,
+                                                 const T* __restrict__ bz, T s) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_cell_gs<T, D, ZERO>(p, g, sp, me, other, f, bx, by, bz, s);
 }
 
 template <typename T, int D, bool ZERO>
@@ -1296,12 +1339,10 @@ __global__ __launch_bounds__(256) void k_cell_gs(Geom g, Space sp, T* __restrict
 }
 
 template <typename T, int D, bool ZERO>
-__device__ __forceinline__ void d_cell_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
+__device__ __forceinline__ void pt_cell_jacobi(const Pt& p, Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
                                                      const T* __restrict__ bx, const T* __restrict__ by,
                                                      const T* __restrict__ bz, T s, T omega) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     const long long ro = row_off(g, p.y, p.z) + p.xs;
@@ -1314,11 +1355,35 @@ __device__ __forceinline__ void d_cell_jacobi(const Ex& ex, Geom g, Space sp, co
 }
 
 template <typename T, int D, bool ZERO>
+__device__ __forceinline__ void d_cell_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
+                                                     const T* __restrict__ f, T* __restrict__ out,
+                                                     const T* __restrict__ bx, const T* __restrict__ by,
+                                                     const T* __restrict__ bz, T s, T omega) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_cell_jacobi<T, D, ZERO>(p, g, sp, u, f, out, bx, by, bz, s, omega);
+}
+
+template <typename T, int D, bool ZERO>
 __global__ __launch_bounds__(256) void k_cell_jacobi(Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
                                                      const T* __restrict__ bx, const T* __restrict__ by,
                                                      const T* __restrict__ bz, T s, T omega) {
     d_cell_jacobi<T, D, ZERO>(solo_ex(), g, sp, u, f, out, bx, by, bz, s, omega);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T pt_cell_residual(const Pt& p, const Geom& g, const T* __restrict__ u,
+                                              const T* __restrict__ f, const T* __restrict__ bx,
+                                              const T* __restrict__ by, const T* __restrict__ bz, T s,
+                                              long long& me) {
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    me = (long long)p.c * g.cs + ro;
+    T dg, off;
+    cell_sums<T, D, false>(g, u + (long long)(1 - p.c) * g.cs, ro, par, x, p.y, p.z, bx, by, bz, dg, off);
+    return f[me] - (dg * u[me] - off) * s;
 }
 
 template <typename T, int D, bool NORM, bool STORE>
@@ -1330,14 +1395,8 @@ __device__ __forceinline__ void d_cell_residual(const Ex& ex, Geom g, Space sp, 
     double sq = 0.0, mx = 0.0;
     Pt p;
     if (map_point(ex, sp, p)) {
-        const int par = (p.y + p.z + p.c) & 1;
-        const int x = 2 * p.xs + par;
-        const long long ro = row_off(g, p.y, p.z) + p.xs;
-        const long long me = (long long)p.c * g.cs + ro;
-        T dg, off;
-        cell_sums<T, D, false>(g, u + (long long)(1 - p.c) * g.cs, ro, par, x, p.y, p.z, bx, by, bz, dg,
-                               off);
-        const T rv = f[me] - (dg * u[me] - off) * s;
+        long long me;
+        const T rv = pt_cell_residual<T, D>(p, g, u, f, bx, by, bz, s, me);
         if (STORE) r[me] = rv;
         const double dv = (double)rv;
         sq = dv * dv;
@@ -1541,11 +1600,9 @@ __global__ __launch_bounds__(256) void k_cell_res_zmk(Geom g, ZSpace zs, const d
 
 // Mean of the 2^d children, summed with the z offset slowest, then scaled.
 template <typename T, int D>
-__device__ __forceinline__ void d_cell_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
+__device__ __forceinline__ void pt_cell_restrict(const Pt& p, Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ fcoarse) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int X = 2 * p.xs + par, Y = p.y, Z = p.z;
     T acc = T(0);
@@ -1567,6 +1624,15 @@ __device__ __forceinline__ void d_cell_restrict(const Ex& ex, Geom gf, Geom gc, 
 }
 
 template <typename T, int D>
+__device__ __forceinline__ void d_cell_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_cell_restrict<T, D>(p, gf, gc, sp, r, fcoarse);
+}
+
+template <typename T, int D>
 __global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ fcoarse) {
@@ -1577,10 +1643,8 @@ __global__ __launch_bounds__(256) void k_cell_restrict(Geom gf, Geom gc, Space s
 // fine(2I+1) = 3/4 e[I] + 1/4 e[I+1], ghost -e[I] (Dirichlet) or e[I]
 // (Neumann) beyond a wall; x first, then y, then z; then u += P e.
 template <typename T, int D>
-__device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
+__device__ __forceinline__ void pt_cell_prolong(const Pt& p, Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par, y = p.y, z = p.z;
     const int Nc = gc.n;
@@ -1613,6 +1677,14 @@ __device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, S
     }
     const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
     u[me] = u[me] + e;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
+                                                      const T* __restrict__ ec) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_cell_prolong<T, D>(p, gf, gc, sp, u, ec);
 }
 
 template <typename T, int D>
@@ -1657,6 +1729,204 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, T* __restrict__ u,
                                                const double* __restrict__ L, int m) {
     d_coarse<T>(solo_ex(), g, f, u, L, m);
+}
+
+// ------------------------------------------- coarse levels in one workgroup
+// The V-cycle from level lg[0] down to the coarsest and back, run by one
+// workgroup on LDS copies of the levels' fields: each operation is the
+// per-level kernels' point function, wavefronts taking rows of the level
+// in turn, so every point takes the same operands in the same order as in
+// the separate launches (and in the oracle); a barrier separates operations.
+// Small levels otherwise cost a launch per operation for a few hundred
+// points each.
+// Every point of a space: a wavefront covers 64 >> lx consecutive rows with
+// 1 << lx lanes each (lx = the space's x tiling, log2 of xr rounded up, at
+// most 6), the 16 wavefronts taking such row groups in turn.
+template <typename F>
+__device__ __forceinline__ void tail_points(const Space& sp, F&& fn) {
+    const int lane = (int)threadIdx.x & 63;
+    const int lg = sp.lx, rpw = 64 >> lg;
+    const int nyb = (sp.yr + rpw - 1) / rpw;
+    const int groups = nyb * sp.zr * sp.ncol;
+    for (int b = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); b < groups; b += kTailThreads / 64) {
+        Pt p;
+        const int yb = b % nyb, t = b / nyb;
+        const int y = yb * rpw + (lane >> lg);
+        if (y >= sp.yr) continue;
+        p.y = sp.y0 + y;
+        p.z = sp.z0 + t % sp.zr;
+        p.c = sp.col0 + t / sp.zr;
+        for (p.xs = lane & ((1 << lg) - 1); p.xs < sp.xr; p.xs += 1 << lg) fn(p);
+    }
+}
+
+// Coarsest solve in LDS by the first wavefront: lane t holds b[t] in a
+// register, the factor L (m x m, row major) sits in LDS; forward and
+// backward substitution take the same operations in the same order as
+// d_coarse.
+template <typename T>
+__device__ __forceinline__ void tail_coarse(const Geom& g, const T* __restrict__ f, T* __restrict__ u,
+                                            const double* __restrict__ L, int m) {
+    if (threadIdx.x >= 64) return;
+    const int t = (int)threadIdx.x;
+    const int side = g.cell ? g.n : g.n - 2, off = g.cell ? 0 : 1;
+    long long idx = 0;
+    double bt = 0.0;
+    if (t < m) {
+        const int x = t % side + off, y = (t / side) % side + off;
+        const int z = (g.dim == 3) ? t / (side * side) + off : 0;
+        idx = (long long)((x + y + z) & 1) * g.cs + row_off(g, y, z) + (x >> 1);
+        bt = (double)f[idx];
+    }
+    for (int j = 0; j < m; ++j) {
+        if (t == j) bt = bt / L[j * m + j];
+        const double bj = __shfl(bt, j, 64);
+        if (t > j && t < m) bt = bt - L[t * m + j] * bj;
+    }
+    for (int j = m - 1; j >= 0; --j) {
+        if (t == j) bt = bt / L[j * m + j];
+        const double bj = __shfl(bt, j, 64);
+        if (t < j) bt = bt - L[j * m + t] * bj;
+    }
+    if (t < m) u[idx] = (T)bt;
+}
+
+// Copy a node field between two colour-split layouts of the same level
+// (device memory and LDS rows of `half` entries).
+template <typename T>
+__device__ __forceinline__ void tail_copy(const Geom& gs, const T* __restrict__ src, const Geom& gd,
+                                          T* __restrict__ dst) {
+    const int lane = (int)threadIdx.x & 63;
+    const int rows = 2 * gs.nz * gs.ny;
+    for (int r = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); r < rows; r += kTailThreads / 64) {
+        const int y = r % gs.ny, t = r / gs.ny;
+        const int z = t % gs.nz, c = t / gs.nz;
+        const long long so = (long long)c * gs.cs + (long long)z * gs.plane + (long long)y * gs.pitch;
+        const long long d = (long long)c * gd.cs + (long long)z * gd.plane + (long long)y * gd.pitch;
+        for (int xs = lane; xs < gs.half; xs += 64) dst[d + xs] = src[so + xs];
+    }
+}
+
+template <typename T, int D, bool CELL>
+__device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sweeps, bool zero, int c0) {
+    const Geom g = P.lg[i];
+    const T s = (T)P.s[i];
+    const T* f = A + P.of[i];
+    const T* bx = static_cast<const T*>(P.beta[i][0]);
+    const T* by = static_cast<const T*>(P.beta[i][1]);
+    const T* bz = static_cast<const T*>(P.beta[i][2]);
+    for (int k = 0; k < sweeps; ++k) {
+        const bool z = zero && k == 0;
+        T* u = A + (((sw >> i) & 1u) ? P.ob[i] : P.oa[i]);
+        if (P.rbgs) {
+            for (int h = 0; h < 2; ++h) {
+                const int c = h == 0 ? c0 : 1 - c0;
+                const Space sp = P.one[i][c];
+                T* me = u + (long long)c * g.cs;
+                const T* other = u + (long long)(1 - c) * g.cs;
+                const T* fc = f + (long long)c * g.cs;
+                if constexpr (CELL) {
+                    if (z && h == 0)
+                        tail_points(sp, [&](const Pt& p) {
+                            pt_cell_gs<T, D, true>(p, g, sp, me, other, fc, bx, by, bz, s);
+                        });
+                    else
+                        tail_points(sp, [&](const Pt& p) {
+                            pt_cell_gs<T, D, false>(p, g, sp, me, other, fc, bx, by, bz, s);
+                        });
+                } else {
+                    if (z && h == 0)
+                        tail_points(sp, [&](const Pt& p) { pt_node_gs<T, D, true>(p, g, sp, me, other, fc, s); });
+                    else
+                        tail_points(sp, [&](const Pt& p) { pt_node_gs<T, D, false>(p, g, sp, me, other, fc, s); });
+                }
+                __syncthreads();
+            }
+        } else {
+            T* out = A + (((sw >> i) & 1u) ? P.oa[i] : P.ob[i]);
+            const Space sp = P.all[i];
+            const T om = (T)P.omega;
+            if constexpr (CELL) {
+                if (z)
+                    tail_points(sp, [&](const Pt& p) {
+                        pt_cell_jacobi<T, D, true>(p, g, sp, u, f, out, bx, by, bz, s, om);
+                    });
+                else
+                    tail_points(sp, [&](const Pt& p) {
+                        pt_cell_jacobi<T, D, false>(p, g, sp, u, f, out, bx, by, bz, s, om);
+                    });
+            } else {
+                if (z)
+                    tail_points(sp, [&](const Pt& p) { pt_node_jacobi<T, D, true>(p, g, sp, u, f, out, s, om); });
+                else
+                    tail_points(sp, [&](const Pt& p) { pt_node_jacobi<T, D, false>(p, g, sp, u, f, out, s, om); });
+            }
+            __syncthreads();
+            sw ^= 1u << i;
+        }
+    }
+}
+
+template <typename T, int D, bool CELL>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailPlan P, const T* __restrict__ f0, T* __restrict__ u0) {
+    __shared__ double arena[kTailLdsBytes / 8];
+    T* A = reinterpret_cast<T*>(arena);
+    for (int i = (int)threadIdx.x; i < P.elems; i += kTailThreads) A[i] = T(0);
+    // the coarsest factor after the fields (8-byte aligned)
+    double* Ls = arena + (P.elems * (int)sizeof(T) + 7) / 8;
+    for (int i = (int)threadIdx.x; i < P.m * P.m; i += kTailThreads) Ls[i] = P.chol[i];
+    __syncthreads();
+    tail_copy<T>(P.g0, f0, P.lg[0], A + P.of[0]);
+    if (!P.from_zero) tail_copy<T>(P.g0, u0, P.lg[0], A + P.oa[0]);
+    __syncthreads();
+    unsigned sw = 0;   // bit i set: level i's iterate is in its second buffer
+    const int last = P.nl - 1;
+    for (int i = 0; i < last; ++i) {
+        tail_smooth<T, D, CELL>(P, A, sw, i, P.nu1, i > 0 || P.from_zero, 0);
+        const Geom g = P.lg[i], gc = P.lg[i + 1];
+        const T* u = A + (((sw >> i) & 1u) ? P.ob[i] : P.oa[i]);
+        T* r = A + (((sw >> i) & 1u) ? P.oa[i] : P.ob[i]);
+        const T* f = A + P.of[i];
+        const T s = (T)P.s[i];
+        const Space sa = P.all[i], sc = P.all[i + 1];
+        T* fco = A + P.of[i + 1];
+        if constexpr (CELL) {
+            const T* bx = static_cast<const T*>(P.beta[i][0]);
+            const T* by = static_cast<const T*>(P.beta[i][1]);
+            const T* bz = static_cast<const T*>(P.beta[i][2]);
+            tail_points(sa, [&](const Pt& p) {
+                long long me;
+                const T rv = pt_cell_residual<T, D>(p, g, u, f, bx, by, bz, s, me);
+                r[me] = rv;
+            });
+            __syncthreads();
+            tail_points(sc, [&](const Pt& p) { pt_cell_restrict<T, D>(p, g, gc, sc, r, fco); });
+        } else {
+            tail_points(sa, [&](const Pt& p) {
+                long long me;
+                T rv;
+                if (pt_node_residual<T, D>(p, g, u, f, s, me, rv)) r[me] = rv;
+            });
+            __syncthreads();
+            tail_points(sc, [&](const Pt& p) { pt_node_restrict<T, D>(p, g, gc, sc, r, fco); });
+        }
+        __syncthreads();
+    }
+    tail_coarse<T>(P.lg[last], A + P.of[last], A + P.oa[last], Ls, P.m);
+    __syncthreads();
+    for (int i = last - 1; i >= 0; --i) {
+        const Geom g = P.lg[i], gc = P.lg[i + 1];
+        T* u = A + (((sw >> i) & 1u) ? P.ob[i] : P.oa[i]);
+        const T* e = A + (((sw >> (i + 1)) & 1u) ? P.ob[i + 1] : P.oa[i + 1]);
+        const Space sp = P.pro[i];
+        if constexpr (CELL)
+            tail_points(sp, [&](const Pt& p) { pt_cell_prolong<T, D>(p, g, gc, sp, u, e); });
+        else
+            tail_points(sp, [&](const Pt& p) { pt_node_prolong<T, D>(p, g, gc, sp, u, e); });
+        __syncthreads();
+        tail_smooth<T, D, CELL>(P, A, sw, i, P.nu2, false, P.post_order);
+    }
+    tail_copy<T>(P.lg[0], A + ((sw & 1u) ? P.ob[0] : P.oa[0]), P.g0, u0);
 }
 
 __device__ __forceinline__ void d_reduce(const Ex& ex, const double* __restrict__ in, long long count,
@@ -2504,6 +2774,29 @@ hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const 
         k_coarse<float><<<1, 64, 0, st>>>(g, cp<float>(f), mp<float>(u), L, m);
     else
         k_coarse<double><<<1, 64, 0, st>>>(g, cp<double>(f), mp<double>(u), L, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(const TailPlan& P, int prec, const void* f, void* u, hipStream_t st) {
+    if (P.nl < 2 || P.nl > kTailMax || P.m < 1 || P.m > 64 || P.g0.neu ||
+        ((long long)P.elems * (prec ? 4 : 8) + 7) / 8 * 8 + 8LL * P.m * P.m > kTailLdsBytes)
+        return hipErrorInvalidValue;
+#define MG_TAIL(T, D, C) k_tail<T, D, C><<<1, kTailThreads, 0, st>>>(P, cp<T>(f), mp<T>(u))
+    const bool c = P.g0.cell != 0, d3 = P.g0.dim == 3;
+    if (prec) {
+        if (c) {
+            if (d3) MG_TAIL(float, 3, true); else MG_TAIL(float, 2, true);
+        } else {
+            if (d3) MG_TAIL(float, 3, false); else MG_TAIL(float, 2, false);
+        }
+    } else {
+        if (c) {
+            if (d3) MG_TAIL(double, 3, true); else MG_TAIL(double, 2, true);
+        } else {
+            if (d3) MG_TAIL(double, 3, false); else MG_TAIL(double, 2, false);
+        }
+    }
+#undef MG_TAIL
     return hipGetLastError();
 }
 

@@ -102,6 +102,10 @@ struct Ctx {
     // residual, the scale basis of the next refinement step's cast; false
     // after a new right-hand side, iterate or level write
     bool scale_known = false;
+    // per precision: the level from which a V-cycle runs in one workgroup
+    // with its fields in LDS (-1: none), and that launch's plan
+    int tail_l[2] = {-1, -1};
+    TailPlan tail[2] = {};
     BItem item(int op, int l) const;
     int push(BItem it);
     int rec_check(int pr, bool want_fp32);
@@ -126,6 +130,8 @@ struct Ctx {
     int coarse(int pr);
     int vcycle(int l, int pr, bool from_zero);
     int cycle(int l, int pr, bool from_zero, int kind);
+    void plan_tail();
+    int tail_cycle(int l, int pr, bool from_zero);
     int fmg(int cpl);
     int project(int l, void* a);
     int pcg(double tol, int max_it, int* its_out, double* relres_out);

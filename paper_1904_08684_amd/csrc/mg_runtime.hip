@@ -781,9 +781,74 @@ int Ctx::fmg(int cpl) {
     return rc;
 }
 
+// The levels small enough to keep their fields in one workgroup's LDS run a
+// V-cycle as one launch (k_tail): the largest level from which the iterate,
+// a second buffer and the right-hand side of every level down to the
+// coarsest, and the coarsest factor, fit in kTailLdsBytes (rediscretised
+// operators, Dirichlet walls,
+// Jacobi or red-black smoothing, at most kTailMax levels; cell levels read
+// their face coefficients from device memory).
+void Ctx::plan_tail() {
+    for (int pr = 0; pr < 2; ++pr) {
+        tail_l[pr] = -1;
+        if (neu || m > 64) continue;
+        if (opts.smoother != MG_JACOBI && opts.smoother != MG_RBGS) continue;
+        const long long esz = pr ? 4 : 8;
+        for (int l0 = std::max(0, L - kTailMax); l0 <= L - 2; ++l0) {
+            bool ok = true;
+            long long elems = 0;
+            for (int l = l0; l < L; ++l) {
+                if (lv[l].gal || !lv[l].has[pr]) ok = false;
+                elems += 3 * ((2 * tail_geom(lv[l].g).cs + 3) / 4 * 4);
+            }
+            if (!ok || (elems * esz + 7) / 8 * 8 + 8LL * m * m > kTailLdsBytes) continue;
+            TailPlan& P = tail[pr];
+            P = TailPlan{};
+            P.nl = L - l0;
+            P.rbgs = opts.smoother == MG_RBGS ? 1 : 0;
+            P.nu1 = opts.nu1;
+            P.nu2 = opts.nu2;
+            P.post_order = opts.post_order;
+            P.m = m;
+            P.omega = opts.omega;
+            P.chol = chol;
+            P.g0 = lv[l0].g;
+            int mask = 3;
+            if (opts.smoother == MG_RBGS && opts.nu2 > 0) mask = opts.post_order == 0 ? 2 : 1;
+            int off = 0;
+            for (int i = 0; i < P.nl; ++i) {
+                const Geom lg = tail_geom(lv[l0 + i].g);
+                const int fe = (int)((2 * lg.cs + 3) / 4 * 4);
+                P.lg[i] = lg;
+                P.one[i][0] = level_space(lg, 1, 0);
+                P.one[i][1] = level_space(lg, 1, 1);
+                P.all[i] = level_space(lg, 2, 0);
+                P.pro[i] = level_space(lg, mask == 3 ? 2 : 1, mask == 2 ? 1 : 0);
+                P.oa[i] = off;
+                P.ob[i] = off + fe;
+                P.of[i] = off + 2 * fe;
+                off += 3 * fe;
+                P.s[i] = scale(l0 + i);
+                for (int a = 0; a < 3; ++a) P.beta[i][a] = lv[l0 + i].beta[pr][a];
+            }
+            P.elems = off;
+            tail_l[pr] = l0;
+            break;
+        }
+    }
+}
+
+int Ctx::tail_cycle(int l, int pr, bool from_zero) {
+    TailPlan P = tail[pr];
+    P.from_zero = from_zero ? 1 : 0;
+    hipEvent_t e0 = begin();
+    return record(MG_K_COARSE, l, launch_tail(P, pr, lv[l].f[pr], lv[l].u[pr], stream), e0, "coarse levels");
+}
+
 // One cycle of the given type on level l (see mg_opts).
 int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
+    if (!rec && kind == MG_CYCLE_V && l == tail_l[pr]) return tail_cycle(l, pr, from_zero);
     int rc = smooth(l, pr, opts.nu1, from_zero, 0);
     if (!rc && !rec && grid.centering == MG_NODE && !lv[l].gal && fused_transfers(lv[l].g)) {
         // fine residual and full weighting in one pass; r is not written
@@ -1277,6 +1342,7 @@ int setup_ctx(const mg_grid* g, const mg_stencil* st, const mg_opts* o, void* d_
         if (!rc) rc = c->dev(hipStreamSynchronize(c->stream), "sync");
     }
     c->coarse_beta_host.clear();
+    if (!rc) c->plan_tail();
     if (rc) {
         *errmsg = c->err;
         delete c;

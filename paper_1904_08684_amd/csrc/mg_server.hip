@@ -108,6 +108,7 @@ struct Hier {
     int slot = -1;                    // row of the I/O and result tables
     BItem* d_items = nullptr;
     std::vector<long long> units;     // per item: tiles x work units per tile
+    std::vector<double> ibytes;       // per item: algorithmic bytes (item_bytes)
     std::vector<int> first[2];        // a new request's first round, by step parity
     std::vector<int> step[2];         // one refinement step, by parity (Jacobi buffer swaps)
     int unpack = -1;
@@ -124,6 +125,38 @@ struct Req {
     double r0 = 0.0, rel = 1.0;
     Hier* h = nullptr;
 };
+
+// Compulsory device-memory bytes of one batched op: every operand it must
+// read and every result it must write once (FP32 inner ops 4 B, FP64 outer
+// ops 8 B per value), counted over the points of its space.
+double item_bytes(const BItem& it) {
+    const double pts = (double)it.sp.xr * it.sp.yr * it.sp.zr * it.sp.ncol;
+    const double per = it.dim == 3 ? 8.0 : 4.0;   // fine points per coarse point
+    const double elems4 = 4.0 * (double)it.n;      // cast / update: n groups of four values
+    switch (it.op) {
+        case BOP_PACK:
+        case BOP_UNPACK: return 16.0 * (double)it.n;
+        case BOP_ZERO: return 16.0 * (double)it.n;
+        case BOP_REDUCE: return 16.0 * (double)it.n + 32.0;
+        case BOP_RES64:
+        case BOP_RES64_M: return 24.0 * pts;
+        case BOP_CAST: return 12.0 * elems4;
+        case BOP_UPDATE: return 20.0 * elems4;
+        case BOP_GS:
+        case BOP_GS_M:
+        case BOP_JAC:
+        case BOP_JAC_M:
+        case BOP_RES32:
+        case BOP_RES32_M: return 12.0 * pts;
+        case BOP_GS_ZERO:
+        case BOP_JAC_ZERO:
+        case BOP_JAC_ZERO_M: return 8.0 * pts;
+        case BOP_RESTRICT: return 4.0 * (1.0 + per) * pts;            // sp: coarse points
+        case BOP_PROLONG: return 8.0 * pts + 4.0 * pts * 2.0 / (it.sp.ncol * per);   // sp: corrected points
+        case BOP_COARSE: return 8.0 * it.m + 8.0 * (double)it.m * it.m;
+        default: return 0.0;
+    }
+}
 
 Key key_of(const mg_request& r) {
     return Key{r.grid.dim, r.grid.n[0], r.opts.smoother, r.opts.nu1, r.opts.nu2, r.opts.post_order, r.opts.omega};
@@ -324,9 +357,11 @@ struct Server {
         if (items.size() > items_bound(&c->grid, &c->opts) || h->first[0].size() > (size_t)kMaxProgram)
             return fail(MG_EINVAL, "program larger than its bound");
         h->units.clear();
+        h->ibytes.clear();
         for (BItem& it : items) {
             if (it.w < 1) it.w = 1;
             h->units.push_back(it.tiles * it.w);
+            h->ibytes.push_back(item_bytes(it));
         }
         h->d_items = reinterpret_cast<BItem*>(base + head_bytes + h->off + h->ctx_bytes);
         rc = dev(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, st),
@@ -388,6 +423,7 @@ struct Server {
                 h_entries[ne].item = hs[j]->d_items + idx;
                 h_entries[ne].prefix = l.total;
                 l.total += hs[j]->units[(size_t)idx];
+                stats.algorithmic_bytes += hs[j]->ibytes[(size_t)idx];
                 ++l.count;
                 ++ne;
             }

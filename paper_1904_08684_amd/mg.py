@@ -326,7 +326,8 @@ class mg_server_stats(C.Structure):
     _fields_ = [("rounds", C.c_longlong), ("launches", C.c_longlong), ("admitted", C.c_longlong),
                 ("completed", C.c_longlong), ("hierarchies_built", C.c_longlong), ("evictions", C.c_longlong),
                 ("arena_peak_bytes", C.c_size_t), ("arena_used_bytes", C.c_size_t),
-                ("in_flight", C.c_int), ("queued", C.c_int), ("resident", C.c_int)]
+                ("in_flight", C.c_int), ("queued", C.c_int), ("resident", C.c_int),
+                ("algorithmic_bytes", C.c_double)]
 
 
 _ssigs = {

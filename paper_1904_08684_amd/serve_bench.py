@@ -49,6 +49,7 @@ def run_server(mg, srv, reqs, fs, us, tol, arrivals):
     """Drive the server over a trace; arrivals[i] = offset in seconds (0 = at start)."""
     n = len(reqs)
     order = sorted(range(n), key=lambda i: arrivals[i])
+    st0 = srv.stats()
     t0 = srv.clock()
     nxt = 0
     done = {}
@@ -73,10 +74,18 @@ def run_server(mg, srv, reqs, fs, us, tol, arrivals):
     t_first = min(r["t_arrive"] for r in done.values())
     t_last = max(r["t_done"] for r in done.values())
     bad = [r for r in done.values() if r["status"] != mg.MG_OK]
+    st1 = srv.stats()
+    nbytes = st1["algorithmic_bytes"] - st0["algorithmic_bytes"]
+    rounds = max(1, st1["rounds"] - st0["rounds"])
+    # the batched launches' compulsory bytes (each op's reads and writes once),
+    # per round and as a rate over the pass (a lower bound on k_batch's rate:
+    # the pass also holds the host's round trips and idle gaps)
     return {"requests": n, "solves_per_s": n / (t_last - t_first), "p50_ms": percentile(lat, 50),
             "p99_ms": percentile(lat, 99), "mean_steps": sum(r["steps"] for r in done.values()) / n,
             "max_relres": max(r["relres"] for r in done.values()), "failed": len(bad),
-            "makespan_s": t_last - t_first}
+            "makespan_s": t_last - t_first, "rounds": rounds, "algorithmic_gb": nbytes / 1e9,
+            "algorithmic_mb_per_round": nbytes / rounds / 1e6,
+            "algorithmic_GBps_over_makespan": nbytes / 1e9 / (t_last - t_first)}
 
 
 def run_fifo_fp64(mg, reqs, fs, us, tol, arrivals, limit, torch):
