@@ -88,7 +88,8 @@ hipError_t launch_project(const Geom& g, double* a, double* partials, double* sc
 // Fixed-order reduction of (sum, max) partial pairs into out[0..1]; with
 // mx_copy the maximum is also stored there.
 hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
-                         hipStream_t st, double* mx_copy = nullptr);
+                         hipStream_t st, double* mx_copy = nullptr, const double* move_src = nullptr,
+                         double* move_dst = nullptr);
 long long reduce_scratch_pairs(long long count);
 
 // natural FP64 array <-> colour-split level field (node grids: interior only).
@@ -109,6 +110,12 @@ hipError_t launch_residual_cast(const Geom& g, const void* u, const void* f, flo
                                 hipStream_t st);
 hipError_t launch_update(const Geom& g, double* u64, const float* c32, const double* sigma,
                          hipStream_t st);
+// u' = u + red[2] fl64(c32) written to uo, and the residual of u' cast to f32
+// with 2^floor(log2 red[3]) (stored to red[5]) plus norm partials, in one
+// pass (3-D node levels that march columns).
+hipError_t launch_update_residual_cast(const Geom& g, const double* u, const float* c32, const double* f, double* uo,
+                                       float* f32, double s, double* red, double* partials, long long* nblocks,
+                                       hipStream_t st);
 // Groups of four elements in one level field (both colours, padding included).
 long long field_quads(const Geom& g);
 

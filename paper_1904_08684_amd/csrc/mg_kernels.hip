@@ -1741,22 +1741,40 @@ __global__ __launch_bounds__(64) void k_coarse(Geom g, const T* __restrict__ f, 
 // points each.
 // Every point of a space: a wavefront covers 64 >> lx consecutive rows with
 // 1 << lx lanes each (lx = the space's x tiling, log2 of xr rounded up, at
-// most 6), the 16 wavefronts taking such row groups in turn.
+// most 6); the row groups (y block fastest, then plane, then colour) are
+// split into 16 contiguous runs, one per wavefront, which steps through its
+// run with increments instead of divisions (the uniform index arithmetic
+// otherwise dominates these small passes).
 template <typename F>
 __device__ __forceinline__ void tail_points(const Space& sp, F&& fn) {
     const int lane = (int)threadIdx.x & 63;
     const int lg = sp.lx, rpw = 64 >> lg;
     const int nyb = (sp.yr + rpw - 1) / rpw;
     const int groups = nyb * sp.zr * sp.ncol;
-    for (int b = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); b < groups; b += kTailThreads / 64) {
-        Pt p;
-        const int yb = b % nyb, t = b / nyb;
-        const int y = yb * rpw + (lane >> lg);
-        if (y >= sp.yr) continue;
-        p.y = sp.y0 + y;
-        p.z = sp.z0 + t % sp.zr;
-        p.c = sp.col0 + t / sp.zr;
-        for (p.xs = lane & ((1 << lg) - 1); p.xs < sp.xr; p.xs += 1 << lg) fn(p);
+    constexpr int W = kTailThreads / 64;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int per = (groups + W - 1) / W;
+    const int g0 = w * per, g1 = min(g0 + per, groups);
+    if (g0 >= g1) return;
+    int yb = g0 % nyb, t = g0 / nyb;
+    int z = t % sp.zr, c = t / sp.zr;
+    const int ylane = lane >> lg, x0 = lane & ((1 << lg) - 1);
+    for (int b = g0; b < g1; ++b) {
+        const int y = yb * rpw + ylane;
+        if (y < sp.yr) {
+            Pt p;
+            p.y = sp.y0 + y;
+            p.z = sp.z0 + z;
+            p.c = sp.col0 + c;
+            for (p.xs = x0; p.xs < sp.xr; p.xs += 1 << lg) fn(p);
+        }
+        if (++yb == nyb) {
+            yb = 0;
+            if (++z == sp.zr) {
+                z = 0;
+                ++c;
+            }
+        }
     }
 }
 
@@ -1797,13 +1815,25 @@ template <typename T>
 __device__ __forceinline__ void tail_copy(const Geom& gs, const T* __restrict__ src, const Geom& gd,
                                           T* __restrict__ dst) {
     const int lane = (int)threadIdx.x & 63;
+    constexpr int W = kTailThreads / 64;
     const int rows = 2 * gs.nz * gs.ny;
-    for (int r = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); r < rows; r += kTailThreads / 64) {
-        const int y = r % gs.ny, t = r / gs.ny;
-        const int z = t % gs.nz, c = t / gs.nz;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int per = (rows + W - 1) / W;
+    const int r0 = w * per, r1 = min(r0 + per, rows);
+    if (r0 >= r1) return;
+    int y = r0 % gs.ny, t = r0 / gs.ny;
+    int z = t % gs.nz, c = t / gs.nz;
+    for (int r = r0; r < r1; ++r) {
         const long long so = (long long)c * gs.cs + (long long)z * gs.plane + (long long)y * gs.pitch;
         const long long d = (long long)c * gd.cs + (long long)z * gd.plane + (long long)y * gd.pitch;
         for (int xs = lane; xs < gs.half; xs += 64) dst[d + xs] = src[so + xs];
+        if (++y == gs.ny) {
+            y = 0;
+            if (++z == gs.nz) {
+                z = 0;
+                ++c;
+            }
+        }
     }
 }
 
@@ -1942,8 +1972,10 @@ __device__ __forceinline__ void d_reduce(const Ex& ex, const double* __restrict_
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, long long count,
-                                                double* __restrict__ out, double* mx_copy) {
+                                                double* __restrict__ out, double* mx_copy,
+                                                const double* __restrict__ move_src, double* __restrict__ move_dst) {
     d_reduce(solo_ex(), in, count, out, mx_copy);
+    if (move_dst && blockIdx.x == 0 && threadIdx.x == 0) *move_dst = *move_src;
 }
 
 // ------------------------------------------------------ layout conversion
@@ -2030,6 +2062,145 @@ __global__ __launch_bounds__(1024) void k_node_res_cast_zm(Geom g, ZSpace zs, co
     const Ex ex = solo_ex();
     if (ex.b == 0 && ex.t == 0) *sigma_out = sigma;
     d_node_res_zm<double, U, NT, true, true, true>(ex, g, zs, u, f, nullptr, s, part, r32, sigma);
+}
+
+// The update of one refinement step and the residual and cast of the next in
+// one pass (3-D node levels): u' = u + sigma_old fl64(c) is formed once per
+// point and plane, written out of place (a block's neighbours still read
+// the old iterate at its halo), and the residual of u', fl32(r / sigma_new)
+// and the norm partials follow.  A block is 64 positions of x >> 1 by
+// kUrRows rows plus one halo row on either side (threads that only form
+// u'), marching a chunk of planes; the current plane of u' (both colours,
+// with one halo position left and right, formed by the edge lanes) sits in
+// LDS for the x and y neighbours, planes z - 1 and z + 1 of the thread's own
+// column in registers, and the next plane's loads are issued one step
+// ahead across LDS-only barriers.  Every value takes the operations of the
+// separate update, residual and cast in their order (neighbours x-, x+, y-,
+// y+, z-, z+), so the iterate and the cast are bitwise theirs.  sigma_old is
+// red[2] (the scale of the cast that made c's right-hand side), sigma_new =
+// 2^floor(log2 red[3]) goes to red[5] (moved to red[2] by the reduction that
+// follows, once every block has read the old one).
+constexpr int kUrRows = 14;
+constexpr int kUrChunk = 16;
+
+template <bool NT>
+__global__ __launch_bounds__(64 * (kUrRows + 2)) void k_node_upd_res_cast(
+    Geom g, int ntx, int nty, int zc, const double* __restrict__ u, const float* __restrict__ c32,
+    const double* __restrict__ f, double* __restrict__ uo, float* __restrict__ r32, double s,
+    double* __restrict__ red, double* __restrict__ part) {
+    __shared__ double pl[2][2][kUrRows + 2][66];
+    const Ex ex = solo_ex();
+    const int lane = (int)threadIdx.x, row = (int)threadIdx.y;
+    const int tx = ex.b % ntx, rest = ex.b / ntx;
+    const int ty = rest % nty, tz = rest / nty;
+    const int xr = (g.n - 1) / 2;
+    const int xs = tx * 64 + lane;
+    const int y = ty * kUrRows + row;                 // row 0: the halo row below the block
+    const int z0 = 1 + tz * zc;
+    const int z1 = min(z0 + zc, g.n - 1);
+    const double so = red[2];
+    const double sn = pow2_floor(red[3]);
+    if (ex.b == 0 && ex.t == 0) red[5] = sn;
+    const long long cs = g.cs, plane = g.plane;
+    const bool inrow = y <= g.n - 1;
+    const bool interior = row >= 1 && row <= kUrRows && y <= g.n - 2 && xs < xr;
+    // the edge lanes also form the halo positions xs - 1 (lane 0) and xs + 1 (lane 63)
+    const int hx = lane == 0 ? xs - 1 : xs + 1;
+    const bool edge = (lane == 0 || lane == 63) && inrow && hx >= 0 && hx <= xr;
+    const bool own = inrow && xs <= xr;
+    const long long ro = (long long)y * g.pitch + xs;
+    const long long rh = (long long)y * g.pitch + hx;
+    const int hcol = lane == 0 ? 0 : 65;
+    // raw loads of one plane: own position and halo position, both colours
+    double uR = 0.0, uB = 0.0, hR = 0.0, hB = 0.0;
+    float cR = 0.f, cB = 0.f, gR = 0.f, gB = 0.f;
+    auto load = [&](int zq) {
+        const long long o = (long long)zq * plane + ro;
+        if (own) {
+            uR = u[o];
+            uB = u[cs + o];
+            cR = c32[o];
+            cB = c32[cs + o];
+        }
+        if (edge) {
+            const long long oh = (long long)zq * plane + rh;
+            hR = u[oh];
+            hB = u[cs + oh];
+            gR = c32[oh];
+            gB = c32[cs + oh];
+        }
+    };
+    // u' of the loaded plane into LDS buffer b (and, for the own position, registers)
+    double vR = 0.0, vB = 0.0;
+    auto form = [&](int b) {
+        vR = uR + so * (double)cR;
+        vB = uB + so * (double)cB;
+        pl[b][0][row][lane + 1] = vR;
+        pl[b][1][row][lane + 1] = vB;
+        if (lane == 0 || lane == 63) {
+            pl[b][0][row][hcol] = edge ? hR + so * (double)gR : 0.0;
+            pl[b][1][row][hcol] = edge ? hB + so * (double)gB : 0.0;
+        }
+    };
+    double sq = 0.0, mx = 0.0;
+    // planes z0 - 1 and z0
+    load(z0 - 1);
+    form(1);
+    double pR = vR, pB = vB;
+    load(z0);
+    form(0);
+    double qR = vR, qB = vB;           // plane z
+    double fR = 0.0, fB = 0.0;
+    if (interior) {
+        fR = ld_stream<NT>(f + (long long)z0 * plane + ro);
+        fB = ld_stream<NT>(f + cs + (long long)z0 * plane + ro);
+    }
+    load(z0 + 1);
+    lds_barrier();
+    for (int z = z0; z < z1; ++z) {
+        const int b = (z - z0) & 1;
+        // u' of plane z + 1 (loaded one step ahead) into the other buffer
+        form(b ^ 1);
+        const double nR = vR, nB = vB;
+        const double fr = fR, fb = fB;
+        if (z + 2 <= g.n - 1) load(z + 2);
+        if (interior && z + 1 < z1) {
+            fR = ld_stream<NT>(f + (long long)(z + 1) * plane + ro);
+            fB = ld_stream<NT>(f + cs + (long long)(z + 1) * plane + ro);
+        }
+        if (interior) {
+            const long long at = (long long)z * plane + ro;
+            const int pr = (y + z) & 1;
+            const double(*P)[66] = pl[b][0];
+            const double(*Q)[66] = pl[b][1];
+            auto point = [&](double xm, double xp, double ym, double yp, double zm, double zp, double uc, double fv,
+                             long long o) {
+                double nb = xm;
+                nb = nb + xp;
+                nb = nb + ym;
+                nb = nb + yp;
+                nb = nb + zm;
+                nb = nb + zp;
+                const double v = fv - (6.0 * uc - nb) * s;
+                st_stream<NT>(r32 + o, (float)(v / sn));
+                st_stream<NT>(uo + o, uc);
+                sq = sq + v * v;
+                mx = fmax(mx, fabs(v));
+            };
+            if (pr | xs)
+                point(pr ? Q[row][lane + 1] : Q[row][lane], pr ? Q[row][lane + 2] : Q[row][lane + 1],
+                      Q[row - 1][lane + 1], Q[row + 1][lane + 1], pB, nB, qR, fr, at);
+            if ((1 - pr) | xs)
+                point(pr ? P[row][lane] : P[row][lane + 1], pr ? P[row][lane + 1] : P[row][lane + 2],
+                      P[row - 1][lane + 1], P[row + 1][lane + 1], pR, nR, qB, fb, cs + at);
+        }
+        pR = qR;
+        pB = qB;
+        qR = nR;
+        qB = nB;
+        lds_barrier();
+    }
+    block_sum_max(sq, mx, part + 2 * (long long)ex.b);
 }
 
 __global__ __launch_bounds__(256) void k_cast(long long n4, const double* __restrict__ r, float* __restrict__ f32,
@@ -2850,20 +3021,21 @@ hipError_t launch_project(const Geom& g, double* a, double* partials, double* sc
 }
 
 hipError_t launch_reduce(const double* partials, long long count, double* scratch, double* out,
-                         hipStream_t st, double* mx_copy) {
+                         hipStream_t st, double* mx_copy, const double* move_src, double* move_dst) {
     const double* in = partials;
     double* buf = scratch;
     if (count < 1) return hipErrorInvalidValue;
     while (count > 1) {
         const long long nb = (count + kReduceChunk - 1) / kReduceChunk;
         double* dst = (nb == 1) ? out : buf;
-        k_reduce<<<(unsigned)nb, 256, 0, st>>>(in, count, dst, nb == 1 ? mx_copy : nullptr);
+        k_reduce<<<(unsigned)nb, 256, 0, st>>>(in, count, dst, nb == 1 ? mx_copy : nullptr,
+                                                nb == 1 ? move_src : nullptr, nb == 1 ? move_dst : nullptr);
         in = dst;
         buf += 2 * nb;
         count = nb;
     }
     if (in != out) {   // a single partial pair: copy it through the reduce kernel
-        k_reduce<<<1, 256, 0, st>>>(in, 1, out, mx_copy);
+        k_reduce<<<1, 256, 0, st>>>(in, 1, out, mx_copy, move_src, move_dst);
     }
     return hipGetLastError();
 }
@@ -2910,6 +3082,22 @@ hipError_t launch_residual_cast(const Geom& g, const void* u, const void* f, flo
     else
         k_node_res_cast_zm<2, false><<<grid, block, 0, st>>>(g, zs, cp<double>(u), cp<double>(f), f32, s, basis,
                                                             sigma, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_residual_cast(const Geom& g, const double* u, const float* c32, const double* f, double* uo,
+                                       float* f32, double s, double* red, double* partials, long long* nblocks,
+                                       hipStream_t st) {
+    if (!use_zmarch(g)) return hipErrorInvalidValue;
+    const int ntx = ((g.n - 1) / 2 + 63) / 64, nty = (g.n - 2 + kUrRows - 1) / kUrRows;
+    const int ntz = (g.n - 2 + kUrChunk - 1) / kUrChunk;
+    const long long nb = (long long)ntx * nty * ntz;
+    if (nblocks) *nblocks = nb;
+    const dim3 grid((unsigned)nb), block(64, kUrRows + 2);
+    if (streams_from_hbm(g, sizeof(double)))
+        k_node_upd_res_cast<true><<<grid, block, 0, st>>>(g, ntx, nty, kUrChunk, u, c32, f, uo, f32, s, red, partials);
+    else
+        k_node_upd_res_cast<false><<<grid, block, 0, st>>>(g, ntx, nty, kUrChunk, u, c32, f, uo, f32, s, red, partials);
     return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ struct Ctx {
     long long partial_pairs = 0;
     double* partials = nullptr;
     double* reduce_scratch = nullptr;
-    double* red = nullptr;        // [sum r^2, max |r|, sigma, scale basis, projection sum, -]
+    double* red = nullptr;        // [sum r^2, max |r|, sigma, scale basis, projection sum, next sigma]
     double* chol = nullptr;
     double* staging = nullptr;
     // preconditioned CG (krylov = 1): finest-level FP64 vectors and scalars
@@ -135,7 +135,9 @@ struct Ctx {
     int fmg(int cpl);
     int project(int l, void* a);
     int pcg(double tol, int max_it, int* its_out, double* relres_out);
-    int refine_step();
+    int refine_step(bool defer = false);
+    bool fused_update() const;
+    int update_residual_cast();
     int read_red(double* sq, double* mx);
     int norm(double* out);
     int step(int k);

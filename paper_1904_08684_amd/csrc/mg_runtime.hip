@@ -144,7 +144,10 @@ size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, 
             // a second iterate: Jacobi's output, or the out-of-place target of
             // fused red-black sweeps on large 3-D node levels
             const bool smoothed = !(mixed && pr == 0);
-            const bool need_tmp = smoothed && (jac || (!cell && use_tb(lp.g)));
+            // (mixed FP64 finest level that marches columns: the out-of-place
+            // target of the fused update, residual and cast)
+            const bool fused_update = mixed && pr == 0 && l == 0 && !cell && use_zmarch(lp.g);
+            const bool need_tmp = (smoothed && (jac || (!cell && use_tb(lp.g)))) || fused_update;
             lp.utmp[pr] = need_tmp ? take(fb) : SIZE_MAX;
             for (int a = 0; a < 3; ++a)
                 lp.beta[pr][a] = (varcoef && a < g->dim) ? take((size_t)lp.g.fsize * es) : SIZE_MAX;
@@ -157,7 +160,7 @@ size_t plan_workspace(const mg_grid* g, const mg_stencil* st, const mg_opts* o, 
     p.partial_pairs = residual_blocks(g0);
     p.partials = take((size_t)p.partial_pairs * 16);
     p.reduce_scratch = take((size_t)reduce_scratch_pairs(p.partial_pairs) * 16);
-    p.red = take(64);   // [sum r^2, max |r|, sigma, spare...]
+    p.red = take(64);   // [sum r^2, max |r|, sigma, scale basis, projection sum, next sigma, -, -]
     const Geom& gc = p.lv.back().g;
     const int side = cell ? gc.n : gc.n - 2;
     p.m = side * side * (g->dim == 3 ? side : 1);
@@ -704,6 +707,37 @@ int Ctx::residual_cast(bool first) {
     return rc;
 }
 
+// Whether a refinement step's update can run fused with the next residual
+// and cast (update_residual_cast).
+bool Ctx::fused_update() const {
+    const Level& L0 = lv[0];
+    return opts.precision == MG_MIXED && !rec && grid.centering == MG_NODE && !L0.gal && use_zmarch(L0.g) &&
+           L0.utmp[0] != nullptr;
+}
+
+// The deferred update of a refinement step, u64 + sigma fl64(c) written to
+// the second FP64 iterate (which then becomes the iterate), and the next
+// step's residual, cast and norms, in one pass; the reduction then moves
+// the new sigma from red[5] to red[2].
+int Ctx::update_residual_cast() {
+    Level& L0 = lv[0];
+    long long nb = 0;
+    hipEvent_t e0 = begin();
+    int rc = record(MG_K_RESIDUAL, 0,
+                    launch_update_residual_cast(L0.g, static_cast<const double*>(L0.u[0]),
+                                                static_cast<const float*>(L0.u[1]), static_cast<const double*>(L0.f[0]),
+                                                static_cast<double*>(L0.utmp[0]), static_cast<float*>(L0.f[1]),
+                                                scale(0), red, partials, &nb, stream),
+                    e0, "update+residual+cast");
+    if (rc) return rc;
+    std::swap(L0.u[0], L0.utmp[0]);
+    last_partials = nb;
+    hipEvent_t e1 = begin();
+    return record(MG_K_REDUCE, 0, launch_reduce(partials, last_partials, reduce_scratch, red, stream, red + 3, red + 5,
+                                                red + 2),
+                  e1, "reduce");
+}
+
 int Ctx::restrict_to(int l, int pr) {
     if (rec) {
         if (int rc = rec_check(pr, true)) return rc;
@@ -886,10 +920,12 @@ int Ctx::project(int l, void* a) {
 }
 
 // One FP64 refinement step around a single-precision V-cycle from zero,
-// whose right-hand side residual_cast prepared: u64 += sigma fl64(c).
-int Ctx::refine_step() {
+// whose right-hand side residual_cast prepared: u64 += sigma fl64(c)
+// (deferred: left to update_residual_cast).
+int Ctx::refine_step(bool defer) {
     Level& L0 = lv[0];
     if (int rc = vcycle(0, 1, true)) return rc;
+    if (defer) return MG_OK;
     if (rec) {
         BItem up = item(BOP_UPDATE, 0);
         up.n = field_quads(L0.g);
@@ -968,7 +1004,11 @@ const Ctx::Graph* Ctx::capture(int kind) {
     stream = cap_stream;
     int rc;
     // (mixed: the scale basis of the previous residual is known here)
-    if (kind == 0) {
+    if (kind == 0 && fused_update()) {
+        rc = refine_step(true);
+        if (!rc) rc = update_residual_cast();
+        if (!rc) rc = dev(hipMemcpyAsync(h_red, red, 16, hipMemcpyDeviceToHost, stream), "norm copy");
+    } else if (kind == 0) {
         rc = mixed ? refine_step() : vcycle(0, 0, false);
         if (!rc) rc = mixed ? residual_cast(false) : residual(0, 0, true, false);
         if (!rc) rc = dev(hipMemcpyAsync(h_red, red, 16, hipMemcpyDeviceToHost, stream), "norm copy");
@@ -1053,8 +1093,9 @@ int Ctx::iterate(double* nr) {
         }
     }
     if (opts.precision == MG_MIXED) {
-        int rc = refine_step();
-        if (!rc) rc = residual_cast(false);
+        const bool fu = fused_update();
+        int rc = refine_step(fu);
+        if (!rc) rc = fu ? update_residual_cast() : residual_cast(false);
         double sq, mx;
         if (!rc) rc = read_red(&sq, &mx);
         if (!rc) *nr = std::sqrt(sq);
@@ -1649,6 +1690,8 @@ const char* mg_strerror(int code) {
         case MG_ENONFINITE: return "non-finite residual";
         case MG_EDIVERGED: return "diverged";
         case MG_EBUSY: return "busy";
+        case MG_ECANCELED: return "cancelled";
+        case MG_ETIMEDOUT: return "deadline passed";
         default: return "unknown error";
     }
 }

@@ -142,8 +142,20 @@ SEED_DG_MESH = 20
 SEED_DG_FIELDS = 21
 
 
+def _square_index(i, j, nx: int, ny: int, tile: int):
+    """Index of square (i, j) in the element numbering: i ny + j, or with
+    tile > 0 tile by tile (tiles of tile x tile squares, ordered like the
+    squares, and the squares of a tile in that order inside it), which keeps
+    most edge neighbours within a few hundred indices."""
+    if tile <= 0:
+        return i * ny + j
+    if nx % tile or ny % tile:
+        raise ValueError("tile must divide nx and ny")
+    return ((i // tile) * (ny // tile) + j // tile) * tile * tile + (i % tile) * tile + j % tile
+
+
 def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, with_origin: bool = False,
-            length: float = 1.0):
+            length: float = 1.0, tile: int = 0):
     """Affine maps of a split-quad triangulation of the square [0, length]^2
     (the convergence test's domain is [0, 1000]^2): nx x ny
     squares, each cut along one diagonal into two counter-clockwise
@@ -153,7 +165,8 @@ def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, wit
     own map.  Returns B (4, 2 nx ny) with rows B11, B12, B21, B22 of
     B_e = [a_e2 - a_e1, a_e3 - a_e1] (and a_e1 (2, 2 nx ny) with_origin).
     Elements: the lower-right triangles (p00, p10, p11) of squares (i, j) at
-    i ny + j, then the upper-left ones (p00, p11, p01)."""
+    i ny + j (or the tiled index of _square_index), then the upper-left ones
+    (p00, p11, p01) in the same order."""
     rng = np.random.default_rng(seed)
     xs = np.linspace(0.0, length, nx + 1)
     ys = np.linspace(0.0, length, ny + 1)
@@ -165,6 +178,11 @@ def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, wit
     p10 = np.stack([X[1:, :-1], Y[1:, :-1]], -1).reshape(-1, 2)
     p01 = np.stack([X[:-1, 1:], Y[:-1, 1:]], -1).reshape(-1, 2)
     p11 = np.stack([X[1:, 1:], Y[1:, 1:]], -1).reshape(-1, 2)
+    if tile > 0:
+        i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+        order = np.empty(nx * ny, dtype=np.int64)
+        order[_square_index(i.ravel(), j.ravel(), nx, ny, tile)] = i.ravel() * ny + j.ravel()
+        p00, p10, p01, p11 = p00[order], p10[order], p01[order], p11[order]
     # lower-right (p00, p10, p11) and upper-left (p00, p11, p01) triangles
     a1 = np.concatenate([p00, p00])
     a2 = np.concatenate([p10, p11])
@@ -174,25 +192,29 @@ def dg_mesh(nx: int, ny: int, seed: int = SEED_DG_MESH, jitter: float = 0.2, wit
     return (B, np.ascontiguousarray(a1.T)) if with_origin else B
 
 
-def dg_mesh_neighbours(nx: int, ny: int):
-    """Edge neighbours of the elements of dg_mesh(nx, ny): nbr[q][e] is the
-    element across local edge q of e (q0: a1->a2, q1: a2->a3, q2: a3->a1),
-    -1 on the domain boundary, and nq[q][e] that element's local index of the
-    shared edge (int32 arrays (3, 2 nx ny))."""
+def dg_mesh_neighbours(nx: int, ny: int, tile: int = 0):
+    """Edge neighbours of the elements of dg_mesh(nx, ny, tile=tile):
+    nbr[q][e] is the element across local edge q of e (q0: a1->a2, q1:
+    a2->a3, q2: a3->a1), -1 on the domain boundary, and nq[q][e] that
+    element's local index of the shared edge (int32 arrays (3, 2 nx ny))."""
     half = nx * ny
     i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
     i, j = i.ravel(), j.ravel()
-    lr = i * ny + j                     # lower-right of square (i, j)
+
+    def sq(a, b):
+        return _square_index(a, b, nx, ny, tile)
+
+    lr = sq(i, j)                       # lower-right of square (i, j)
     ul = half + lr                      # upper-left of square (i, j)
     nbr = np.full((3, 2 * half), -1, dtype=np.int32)
     nq = np.full((3, 2 * half), -1, dtype=np.int32)
     # lower-right: q0 bottom -> upper-left of (i, j-1) edge q1; q1 right ->
     # upper-left of (i+1, j) edge q2; q2 diagonal -> upper-left of (i, j) edge q0
     m = j > 0
-    nbr[0, lr[m]] = half + i[m] * ny + (j[m] - 1)
+    nbr[0, lr[m]] = half + sq(i[m], j[m] - 1)
     nq[0, lr[m]] = 1
     m = i < nx - 1
-    nbr[1, lr[m]] = half + (i[m] + 1) * ny + j[m]
+    nbr[1, lr[m]] = half + sq(i[m] + 1, j[m])
     nq[1, lr[m]] = 2
     nbr[2, lr] = ul
     nq[2, lr] = 0
@@ -201,10 +223,10 @@ def dg_mesh_neighbours(nx: int, ny: int):
     nbr[0, ul] = lr
     nq[0, ul] = 2
     m = j < ny - 1
-    nbr[1, ul[m]] = i[m] * ny + (j[m] + 1)
+    nbr[1, ul[m]] = sq(i[m], j[m] + 1)
     nq[1, ul[m]] = 0
     m = i > 0
-    nbr[2, ul[m]] = (i[m] - 1) * ny + j[m]
+    nbr[2, ul[m]] = sq(i[m] - 1, j[m])
     nq[2, ul[m]] = 1
     return nbr, nq
 

@@ -140,15 +140,15 @@ def test_system_entry_points_reject_bad_arguments(mg):
     assert mg.dg_basis_values(9, 3, n, n, n) == E
 
 
-@pytest.mark.parametrize("nx,ny", [(3, 4), (5, 5)])
-def test_mesh_neighbours_match_the_geometry(nx, ny):
-    """The split-quad mesh's neighbour table: every element is
-    counter-clockwise, edge q of e (vertex q to q + 1) is edge nq of its
-    neighbour traversed backwards, the relation is symmetric, and the
-    2 (nx + ny) boundary edges are the ones without a neighbour."""
+@pytest.mark.parametrize("nx,ny,tile", [(3, 4, 0), (5, 5, 0), (8, 12, 4)])
+def test_mesh_neighbours_match_the_geometry(nx, ny, tile):
+    """The split-quad mesh's neighbour table (row-wise and tiled numbering):
+    every element is counter-clockwise, edge q of e (vertex q to q + 1) is
+    edge nq of its neighbour traversed backwards, the relation is symmetric,
+    and the 2 (nx + ny) boundary edges are the ones without a neighbour."""
     from paper_1904_08684_amd import workloads as W
-    B, a1 = W.dg_mesh(nx, ny, with_origin=True)
-    nbr, nq = W.dg_mesh_neighbours(nx, ny)
+    B, a1 = W.dg_mesh(nx, ny, with_origin=True, tile=tile)
+    nbr, nq = W.dg_mesh_neighbours(nx, ny, tile=tile)
     assert np.all(B[0] * B[3] - B[1] * B[2] > 0)
 
     def verts(e):
@@ -162,3 +162,24 @@ def test_mesh_neighbours_match_the_geometry(nx, ny):
             assert np.allclose(P[q], Q[(r + 1) % 3]) and np.allclose(P[(q + 1) % 3], Q[r])
             assert nbr[r, f] == e and nq[r, f] == q
     assert int((nbr < 0).sum()) == 2 * (nx + ny)
+
+
+def test_tiled_numbering_is_a_relabelling():
+    """The tiled numbering holds the same elements (maps and origins) as the
+    row-wise one, the halves in the same order, and a relabelled neighbour
+    table."""
+    from paper_1904_08684_amd import workloads as W
+    nx, ny, t = 8, 12, 4
+    B0, o0 = W.dg_mesh(nx, ny, with_origin=True)
+    B1, o1 = W.dg_mesh(nx, ny, with_origin=True, tile=t)
+    n0, _ = W.dg_mesh_neighbours(nx, ny)
+    n1, _ = W.dg_mesh_neighbours(nx, ny, tile=t)
+    half = nx * ny
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    new = W._square_index(i.ravel(), j.ravel(), nx, ny, t)
+    perm = np.concatenate([new, half + new])          # row-wise index -> tiled index
+    assert sorted(perm.tolist()) == list(range(2 * half))
+    np.testing.assert_array_equal(B1[:, perm], B0)
+    np.testing.assert_array_equal(o1[:, perm], o0)
+    relab = np.where(n0 >= 0, perm[np.maximum(n0, 0)], -1)
+    np.testing.assert_array_equal(n1[:, perm], relab)

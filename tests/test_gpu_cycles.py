@@ -361,7 +361,11 @@ def test_full_size_varcoef_256_properties(mg):
 def test_graph_replay_equals_eager(mg, dim, n, sm, nu1, nu2, precision):
     """mg_solve and mg_vcycle replay each iteration from a captured HIP graph;
     after k iterations the iterate and the residual history equal k cycles
-    issued launch by launch (profiling on) bitwise."""
+    issued launch by launch (profiling on) bitwise.  (A mixed-precision solve
+    on a level that marches columns forms its stopping-test norm inside the
+    fused update, residual and cast pass, summed in another order than the
+    separate residual's: there the history agrees to 1e-12 and the iterate
+    bitwise.)"""
     k = 4
     f = W.interior_uniform(n, dim, W.SEED_F_3D)
     smoother = mg.MG_RBGS if sm == "rbgs" else mg.MG_JACOBI
@@ -406,7 +410,9 @@ def test_graph_replay_equals_eager(mg, dim, n, sm, nu1, nu2, precision):
         print(f"graph {dim}d n={n} {sm} V({nu1},{nu2}) {precision} {mode}: bitwise {np.array_equal(u, u_e)}",
               flush=True)
         assert np.array_equal(u, u_e)
-        if hist is not None:
+        if hist is not None and precision == "mixed" and dim == 3 and n >= 129:
+            np.testing.assert_allclose(hist, hist_e, rtol=1e-12, atol=0.0)
+        elif hist is not None:
             assert hist == hist_e
 
 
