@@ -47,7 +47,9 @@ enum {
     MG_ENOTCONV = -4,    /* max_cycles reached before the tolerance         */
     MG_ENONFINITE = -5,  /* residual norm is NaN or Inf                     */
     MG_EDIVERGED = -6,   /* residual grew in 3 consecutive cycles           */
-    MG_EBUSY = -7        /* server queue full                               */
+    MG_EBUSY = -7,       /* server queue full                               */
+    MG_ECANCELED = -8,   /* server request cancelled by mg_server_cancel    */
+    MG_ETIMEDOUT = -9    /* server request not converged by its deadline    */
 };
 
 enum { MG_NODE = 0, MG_CELL = 1 };              /* field location           */
@@ -267,7 +269,11 @@ typedef struct mg_server_opts {
  * nu2, max_cycles (refinement steps); precision is always MG_MIXED.  f and
  * u_out are device arrays of n^dim doubles (C order, boundary included);
  * the caller keeps them valid until the request's result is polled.
- * t_arrive is the arrival time on the server clock (mg_server_clock). */
+ * t_arrive is the arrival time on the server clock (mg_server_clock).
+ * deadline (server clock, <= 0 = none): a request not converged when a round
+ * ends at or after it is retired with MG_ETIMEDOUT (u_out receives its
+ * iterate so far, relres its residual); one still queued at its deadline is
+ * retired unadmitted (steps 0, u_out untouched). */
 typedef struct mg_request {
     uint64_t id;
     mg_grid grid;
@@ -276,12 +282,14 @@ typedef struct mg_request {
     const double* f;
     double* u_out;
     double t_arrive;
+    double deadline;
 } mg_request;
 
 typedef struct mg_result {
     uint64_t id;
     uint64_t ticket;        /* the ticket mg_server_submit returned           */
-    int status;             /* MG_OK, MG_ENOTCONV, MG_ENONFINITE              */
+    int status;             /* MG_OK, MG_ENOTCONV, MG_ENONFINITE, MG_ECANCELED,
+                               MG_ETIMEDOUT                                   */
     int steps;              /* refinement steps (single-precision V-cycles)   */
     double relres;          /* ||f - A u|| / ||f|| of the returned solution   */
     double t_arrive, t_admit, t_done;   /* server clock, seconds               */
@@ -313,6 +321,11 @@ int mg_server_submit(mg_server* s, const mg_request* r, uint64_t* ticket);
 /* Run one round; *in_flight receives the requests still in flight and
  * *queued those waiting.  Synchronous. */
 int mg_server_step(mg_server* s, int* in_flight, int* queued);
+/* Cancel the request with this ticket: a queued one is retired at once, one
+ * in flight at the start of the next round (its slot freed, no further
+ * work); either way its result carries MG_ECANCELED and u_out is left as
+ * it is.  MG_EINVAL for a ticket that is unknown or already finished. */
+int mg_server_cancel(mg_server* s, uint64_t ticket);
 /* Move up to cap finished results to out; *n receives the count. */
 int mg_server_poll(mg_server* s, mg_result* out, int cap, int* n);
 int mg_server_get_stats(const mg_server* s, mg_server_stats* st);

@@ -146,11 +146,19 @@ struct YSpace {
 constexpr int kYChunk = 16;
 constexpr int kYRows = 4;
 
-// Row marching pays from 513^2 nodes: on smaller 2-D levels a thread per
-// point spreads the work over more workgroups and measured faster (a 129^2
-// Jacobi V(2,2)-cycle 78 us against 120 us, 257^2 94 against 200 us).
+// Stand-alone 2-D levels run a thread per point: it spreads a level over
+// more workgroups and measured faster than row marching at every size (a
+// Jacobi V(2,2)-cycle at 129^2 78 against 120 us, 513^2 114 against 255 us,
+// 1025^2 173 against 372 us).  The batched server keeps the row-marching
+// forms for its large 2-D requests (use_ymarch_batched), where a launch
+// holds many requests and fewer, larger tiles pay.
 static inline bool use_ymarch(const Geom& g) {
-    return g.dim == 2 && !g.cell && (g.n - 1) / 2 >= 256;
+    (void)g;
+    return false;
+}
+
+static inline bool use_ymarch_batched(const Geom& g) {
+    return g.dim == 2 && !g.cell && (g.n - 1) / 2 >= 64;
 }
 
 static inline YSpace make_yspace(const Geom& g) {

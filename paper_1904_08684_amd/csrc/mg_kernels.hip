@@ -2764,7 +2764,7 @@ hipError_t launch_jacobi(const Geom& g, int prec, bool zero, const void* u, cons
 long long residual_blocks(const Geom& g) {
     // the stand-alone path may march columns or rows; the batched path may use one point per thread
     const long long a = use_zmarch(g)    ? make_zspace(g).blocks()
-                        : use_ymarch(g)  ? make_yspace(g).blocks()
+                        : use_ymarch_batched(g) ? make_yspace(g).blocks()
                         : use_cell_zm(g) ? make_czspace(g).blocks()
                                          : 0;
     const long long b = space_of(g, 2, 0).blocks();

@@ -531,7 +531,7 @@ int Ctx::jacobi(int l, int pr, bool zero) {
     Level& L = lv[l];
     if (rec) {
         if (int rc = rec_check(pr, true)) return rc;
-        const bool march = use_ymarch(L.g);
+        const bool march = use_ymarch_batched(L.g);
         BItem it = item(march ? (zero ? BOP_JAC_ZERO_M : BOP_JAC_M) : (zero ? BOP_JAC_ZERO : BOP_JAC), l);
         it.sp = level_space(L.g, 2, 0);
         if (march) {
@@ -607,7 +607,7 @@ int Ctx::residual(int l, int pr, bool norm, bool store, bool reduce) {
         if (pr == 0 && !(norm && store)) return fail(MG_EINVAL, "batched FP64 residual carries its norm");
         if (pr == 1 && norm) return fail(MG_EINVAL, "batched FP32 residual has no norm");
         if (grid.centering != MG_NODE) return fail(MG_EINVAL, "batched execution supports node grids");
-        const bool zm = use_zmarch(L.g) && 64 * kZRows == 256, ym = use_ymarch(L.g);
+        const bool zm = use_zmarch(L.g) && 64 * kZRows == 256, ym = use_ymarch_batched(L.g);
         BItem it = item(zm || ym ? (pr == 0 ? BOP_RES64_M : BOP_RES32_M) : (pr == 0 ? BOP_RES64 : BOP_RES32), l);
         it.sp = level_space(L.g, 2, 0);
         if (zm) {

@@ -122,6 +122,7 @@ struct Req {
     double t_admit = 0.0;
     int steps = 0;
     bool fresh = true;
+    bool cancel = false;          // retire at the start of the next round
     double r0 = 0.0, rel = 1.0;
     Hier* h = nullptr;
 };
@@ -439,7 +440,62 @@ struct Server {
         return rc;
     }
 
+    // Retire without further work: the result of a request that never ran
+    // or stops here (cancelled, or still queued at its deadline).
+    void retire_idle(const Req& q, int status) {
+        mg_result res{};
+        res.id = q.r.id;
+        res.ticket = q.ticket;
+        res.status = status;
+        res.steps = q.steps;
+        res.relres = q.rel;
+        res.t_arrive = q.r.t_arrive;
+        res.t_admit = q.h ? q.t_admit : 0.0;
+        res.t_done = now();
+        done.push_back(res);
+        if (q.h) {
+            q.h->busy = false;
+            q.h->last_used = ++tick;
+        }
+        stats.completed++;
+    }
+
+    // Cancellations in flight, and queued requests past their deadline.
+    void sweep() {
+        std::vector<Req> keep;
+        for (Req& q : active) {
+            if (q.cancel) retire_idle(q, MG_ECANCELED);
+            else keep.push_back(q);
+        }
+        active.swap(keep);
+        const double t = now();
+        for (auto it = queue.begin(); it != queue.end();) {
+            if (it->r.deadline > 0.0 && t >= it->r.deadline) {
+                retire_idle(*it, MG_ETIMEDOUT);
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+
+    int cancel(uint64_t ticket) {
+        for (auto it = queue.begin(); it != queue.end(); ++it)
+            if (it->ticket == ticket) {
+                retire_idle(*it, MG_ECANCELED);
+                queue.erase(it);
+                return MG_OK;
+            }
+        for (Req& q : active)
+            if (q.ticket == ticket && !q.cancel) {
+                q.cancel = true;
+                return MG_OK;
+            }
+        return MG_EINVAL;
+    }
+
     int round(int* in_flight, int* queued) {
+        sweep();
         admit();
         if (!active.empty()) {
             int rc = dev(hipMemcpyAsync(d_io, h_io, (size_t)max_hier * 2 * sizeof(void*), hipMemcpyHostToDevice, st),
@@ -475,6 +531,7 @@ struct Server {
                 if (!std::isfinite(q.r0) || !std::isfinite(q.rel)) stt = MG_ENONFINITE;
                 else if (q.rel <= q.r.tol) stt = MG_OK;
                 else if (q.steps >= q.r.opts.max_cycles) stt = MG_ENOTCONV;
+                else if (q.r.deadline > 0.0 && now() >= q.r.deadline) stt = MG_ETIMEDOUT;
                 if (stt == 1) {
                     keep.push_back(q);
                 } else {
@@ -616,6 +673,14 @@ int mg_server_submit(mg_server* h, const mg_request* r, uint64_t* ticket) {
     s->queue.push_back(q);
     if (ticket) *ticket = q.ticket;
     return MG_OK;
+}
+
+int mg_server_cancel(mg_server* h, uint64_t ticket) {
+    Server* s = reinterpret_cast<Server*>(h);
+    if (!s) return MG_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int rc = s->cancel(ticket);
+    return rc ? s->fail(rc, "no queued or running request with this ticket") : MG_OK;
 }
 
 int mg_server_step(mg_server* h, int* in_flight, int* queued) {

@@ -33,6 +33,7 @@ lib = C.CDLL(_LIB_PATH)
 # ------------------------------------------------------------------ constants
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE = 0, -1, -2, -3
 MG_ENOTCONV, MG_ENONFINITE, MG_EDIVERGED, MG_EBUSY = -4, -5, -6, -7
+MG_ECANCELED, MG_ETIMEDOUT = -8, -9
 MG_NODE, MG_CELL = 0, 1
 MG_LAPLACE, MG_VARCOEF = 0, 1
 MG_DIRICHLET0, MG_NEUMANN0 = 0, 1
@@ -314,7 +315,7 @@ class mg_server_opts(C.Structure):
 
 class mg_request(C.Structure):
     _fields_ = [("id", C.c_uint64), ("grid", mg_grid), ("opts", mg_opts), ("tol", C.c_double),
-                ("f", C.c_void_p), ("u_out", C.c_void_p), ("t_arrive", C.c_double)]
+                ("f", C.c_void_p), ("u_out", C.c_void_p), ("t_arrive", C.c_double), ("deadline", C.c_double)]
 
 
 class mg_result(C.Structure):
@@ -337,6 +338,7 @@ _ssigs = {
     "mg_server_clock": (C.c_double, [_P]),
     "mg_server_submit": (C.c_int, [_P, C.POINTER(mg_request), C.POINTER(C.c_uint64)]),
     "mg_server_step": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "mg_server_cancel": (C.c_int, [_P, C.c_uint64]),
     "mg_server_poll": (C.c_int, [_P, C.POINTER(mg_result), C.c_int, C.POINTER(C.c_int)]),
     "mg_server_get_stats": (C.c_int, [_P, C.POINTER(mg_server_stats)]),
     "mg_server_last_error": (C.c_char_p, [_P]),
@@ -384,9 +386,11 @@ class Server:
         return mg_server_clock(self.h)
 
     def submit(self, rid: int, dim: int, n: int, f, u_out, tol: float, smoother: int = MG_RBGS,
-               nu1: int = 2, nu2: int = 2, omega: float = 0.8, max_steps: int = 50, t_arrive=None) -> int:
+               nu1: int = 2, nu2: int = 2, omega: float = 0.8, max_steps: int = 50, t_arrive=None,
+               deadline: float = 0.0) -> int:
         """f and u_out: contiguous float64 CUDA tensors of shape (n,)*dim, kept
-        alive here until the result is polled.  Returns the status code."""
+        alive here until the result is polled; deadline on the server clock
+        (0: none).  Returns the status code; the ticket is in last_ticket."""
         r = mg_request()
         r.id = rid
         r.grid = make_grid(dim, n)
@@ -395,12 +399,17 @@ class Server:
         r.f = f.data_ptr()
         r.u_out = u_out.data_ptr()
         r.t_arrive = self.clock() if t_arrive is None else t_arrive
+        r.deadline = deadline
         t = C.c_uint64()
         code = mg_server_submit(self.h, C.byref(r), C.byref(t))
         if code == MG_OK:
             self._keep[rid] = (f, u_out)
             self.last_ticket = t.value
         return code
+
+    def cancel(self, ticket: int) -> int:
+        """Cancel a queued or running request; returns the status code."""
+        return mg_server_cancel(self.h, ticket)
 
     def step(self):
         a = C.c_int()

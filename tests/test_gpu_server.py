@@ -185,6 +185,53 @@ def test_tickets_and_latency_accounting_on_the_supplied_clock(mg):
               f"{1e3 * (r['t_admit'] - r['t_arrive']):.2f} ms", flush=True)
 
 
+def test_cancellation_and_deadlines(mg):
+    """A queued request cancelled at once and one in flight cancelled before
+    the next round come back MG_ECANCELED with u_out untouched; a request
+    queued past its deadline is retired unadmitted, and one that cannot
+    reach its tolerance is retired MG_ETIMEDOUT at the first round ending
+    after its deadline, with its iterate so far; the rest converge; unknown
+    and finished tickets are refused."""
+    import torch
+    srv = mg.Server(512 << 20, max_slots=2)
+    reqs = [(3, 33)] * 5
+    fs, us = make_inputs(torch, reqs)
+    sm, nu1, nu2 = method(3)
+    now = srv.clock()
+    dl = {2: now + 0.2, 3: 1e-9}          # request 3: a deadline already past
+    tickets = []
+    for rid in range(5):
+        tol, steps = (1e-30, 100000) if rid == 2 else (1e-8, 50)
+        assert srv.submit(rid, 3, 33, fs[rid], us[rid], tol, sm, nu1, nu2, max_steps=steps,
+                          deadline=dl.get(rid, 0.0)) == mg.MG_OK
+        tickets.append(srv.last_ticket)
+    assert srv.cancel(tickets[4]) == mg.MG_OK              # still queued
+    done = {r["id"]: r for r in srv.poll()}
+    assert done[4]["status"] == mg.MG_ECANCELED and done[4]["steps"] == 0
+    srv.step()                                               # requests 0 and 1 run one round
+    assert srv.cancel(tickets[1]) == mg.MG_OK              # in flight
+    assert srv.cancel(99) != mg.MG_OK
+    while len(done) < 5:
+        srv.step()
+        for r in srv.poll():
+            done[r["id"]] = r
+    assert srv.cancel(tickets[0]) != mg.MG_OK              # finished
+    srv.close()
+    torch.cuda.synchronize()
+    assert done[0]["status"] == mg.MG_OK and done[0]["relres"] <= 1e-8
+    assert done[1]["status"] == mg.MG_ECANCELED and done[1]["steps"] == 1
+    assert done[3]["status"] == mg.MG_ETIMEDOUT and done[3]["steps"] == 0
+    assert done[2]["status"] == mg.MG_ETIMEDOUT and done[2]["steps"] >= 1 and 0.0 < done[2]["relres"] < 1e-6
+    assert done[2]["t_done"] >= dl[2]
+    for rid in (1, 3, 4):
+        assert float(us[rid].abs().max()) == 0.0
+    assert float(us[2].abs().max()) > 0.0 and float(us[0].abs().max()) > 0.0
+    for rid in range(5):
+        assert done[rid]["ticket"] == tickets[rid]
+        print(f"request {rid}: status {done[rid]['status']} steps {done[rid]['steps']} "
+              f"relres {done[rid]['relres']:.3e}", flush=True)
+
+
 def test_largest_classes_alone_equal_mix_and_match_oracle(mg):
     """3-D 129^3 and 2-D 1025^2 / 513^2 requests (the marching batched ops)
     beside smaller ones: each result bitwise the same alone and in a
