@@ -1010,49 +1010,114 @@ __global__ __launch_bounds__(64 * NW, 4) void k_node_res_restrict_zm(Geom gf, Ge
         const bool zin = z >= 1 && z <= n - 2;
         const long long zo = (long long)z * gf.plane;
         T frn[R], fbn[R];
+        if constexpr (sizeof(T) == 4) {
+            // FP32: this plane's x neighbours and the y neighbours beyond the
+            // thread's rows first, then the next plane's loads, which stay in
+            // flight across the LDS-only barrier (FP64 measured faster with
+            // the loads in the order below: the hoisted values cost registers)
+            bool rin[R], bin[R];
+            T bx[R], rx[R], byl = T(0), ryl = T(0), byh = T(0), ryh = T(0);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const long long a = ro[r] + zo + gf.plane;
-            const bool ld = rowin[r] && z + 1 <= n - 1;
-            rn[r] = ld ? RD[a] : T(0);
-            bn[r] = ld ? BK[a] : T(0);
-            frn[r] = ld ? f[a] : T(0);
-            fbn[r] = ld ? f[gf.cs + a] : T(0);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int y = yg[r];
-            const int pr = (y + z) & 1;   // x parity of the red point
-            const bool yin = rowin[r] && y >= 1 && y <= n - 2 && zin;
-            const int xr = 2 * xs + pr, xb = 2 * xs + 1 - pr;
-            const bool rin = yin && xr >= 1 && xr <= n - 2, bin = yin && xb >= 1 && xb <= n - 2;
-            const long long a = ro[r] + zo;
-            T vr = T(0), vb = T(0);
-            if (rin) {
+            for (int r = 0; r < R; ++r) {
+                const int y = yg[r];
+                const int pr = (y + z) & 1;   // x parity of the red point
+                const bool yin = rowin[r] && y >= 1 && y <= n - 2 && zin;
+                const int xr = 2 * xs + pr, xb = 2 * xs + 1 - pr;
+                rin[r] = yin && xr >= 1 && xr <= n - 2;
+                bin[r] = yin && xb >= 1 && xb <= n - 2;
+                const long long a = ro[r] + zo;
                 // black neighbours of the red point: x - 1, x + 1 at x >> 1 - 1 + pr, x >> 1 + pr
-                const T bx = BK[a + (pr ? 1 : -1)];
-                T nb = pr ? bc[r] : bx;
-                nb = nb + (pr ? bx : bc[r]);
-                nb = nb + (r > 0 ? bc[r - 1] : BK[a - gf.pitch]);
-                nb = nb + (r < R - 1 ? bc[r + 1] : BK[a + gf.pitch]);
-                nb = nb + bm[r];
-                nb = nb + bn[r];
-                vr = fr[r] - (T(6) * rc[r] - nb) * s;
+                bx[r] = rin[r] ? BK[a + (pr ? 1 : -1)] : T(0);
+                rx[r] = bin[r] ? RD[a + (pr ? -1 : 1)] : T(0);
+                if (r == 0) {
+                    byl = rin[r] ? BK[a - gf.pitch] : T(0);
+                    ryl = bin[r] ? RD[a - gf.pitch] : T(0);
+                }
+                if (r == R - 1) {
+                    byh = rin[r] ? BK[a + gf.pitch] : T(0);
+                    ryh = bin[r] ? RD[a + gf.pitch] : T(0);
+                }
             }
-            if (bin) {
-                const T rx = RD[a + (pr ? -1 : 1)];
-                T nb = pr ? rx : rc[r];
-                nb = nb + (pr ? rc[r] : rx);
-                nb = nb + (r > 0 ? rc[r - 1] : RD[a - gf.pitch]);
-                nb = nb + (r < R - 1 ? rc[r + 1] : RD[a + gf.pitch]);
-                nb = nb + rm[r];
-                nb = nb + rn[r];
-                vb = fb[r] - (T(6) * bc[r] - nb) * s;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long long a = ro[r] + zo + gf.plane;
+                const bool ld = rowin[r] && z + 1 <= n - 1;
+                rn[r] = ld ? RD[a] : T(0);
+                bn[r] = ld ? BK[a] : T(0);
+                frn[r] = ld ? f[a] : T(0);
+                fbn[r] = ld ? f[gf.cs + a] : T(0);
             }
-            rp[wv * R + r][2 * lane + pr] = vr;
-            rp[wv * R + r][2 * lane + 1 - pr] = vb;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int pr = (yg[r] + z) & 1;
+                T vr = T(0), vb = T(0);
+                if (rin[r]) {
+                    T nb = pr ? bc[r] : bx[r];
+                    nb = nb + (pr ? bx[r] : bc[r]);
+                    nb = nb + (r > 0 ? bc[r - 1] : byl);
+                    nb = nb + (r < R - 1 ? bc[r + 1] : byh);
+                    nb = nb + bm[r];
+                    nb = nb + bn[r];
+                    vr = fr[r] - (T(6) * rc[r] - nb) * s;
+                }
+                if (bin[r]) {
+                    T nb = pr ? rx[r] : rc[r];
+                    nb = nb + (pr ? rc[r] : rx[r]);
+                    nb = nb + (r > 0 ? rc[r - 1] : ryl);
+                    nb = nb + (r < R - 1 ? rc[r + 1] : ryh);
+                    nb = nb + rm[r];
+                    nb = nb + rn[r];
+                    vb = fb[r] - (T(6) * bc[r] - nb) * s;
+                }
+                rp[wv * R + r][2 * lane + pr] = vr;
+                rp[wv * R + r][2 * lane + 1 - pr] = vb;
+            }
+            lds_barrier();
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long long a = ro[r] + zo + gf.plane;
+                const bool ld = rowin[r] && z + 1 <= n - 1;
+                rn[r] = ld ? RD[a] : T(0);
+                bn[r] = ld ? BK[a] : T(0);
+                frn[r] = ld ? f[a] : T(0);
+                fbn[r] = ld ? f[gf.cs + a] : T(0);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int y = yg[r];
+                const int pr = (y + z) & 1;   // x parity of the red point
+                const bool yin = rowin[r] && y >= 1 && y <= n - 2 && zin;
+                const int xr = 2 * xs + pr, xb = 2 * xs + 1 - pr;
+                const bool rin = yin && xr >= 1 && xr <= n - 2, bin = yin && xb >= 1 && xb <= n - 2;
+                const long long a = ro[r] + zo;
+                T vr = T(0), vb = T(0);
+                if (rin) {
+                    // black neighbours of the red point: x - 1, x + 1 at x >> 1 - 1 + pr, x >> 1 + pr
+                    const T bx = BK[a + (pr ? 1 : -1)];
+                    T nb = pr ? bc[r] : bx;
+                    nb = nb + (pr ? bx : bc[r]);
+                    nb = nb + (r > 0 ? bc[r - 1] : BK[a - gf.pitch]);
+                    nb = nb + (r < R - 1 ? bc[r + 1] : BK[a + gf.pitch]);
+                    nb = nb + bm[r];
+                    nb = nb + bn[r];
+                    vr = fr[r] - (T(6) * rc[r] - nb) * s;
+                }
+                if (bin) {
+                    const T rx = RD[a + (pr ? -1 : 1)];
+                    T nb = pr ? rx : rc[r];
+                    nb = nb + (pr ? rc[r] : rx);
+                    nb = nb + (r > 0 ? rc[r - 1] : RD[a - gf.pitch]);
+                    nb = nb + (r < R - 1 ? rc[r + 1] : RD[a + gf.pitch]);
+                    nb = nb + rm[r];
+                    nb = nb + rn[r];
+                    vb = fb[r] - (T(6) * bc[r] - nb) * s;
+                }
+                rp[wv * R + r][2 * lane + pr] = vr;
+                rp[wv * R + r][2 * lane + 1 - pr] = vb;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // fine plane z is offset -1 of coarse plane (z + 1) / 2 and +1 of
         // (z - 1) / 2 when odd, offset 0 of z / 2 when even
         const bool odd = z & 1;
@@ -1167,14 +1232,14 @@ __global__ __launch_bounds__(256) void k_node_prolong_zm(Geom gf, Geom gc, ZSpac
 }
 
 // Full weighting: f_c[X] = sum_{o in {-1,0,1}^d} prod_a (2 - |o_a|) / 4^d r[2X + o],
-// summed with the z offset slowest and the x offset fastest.
-template <typename T, int D>
-__device__ __forceinline__ void pt_node_restrict(const Pt& p, Geom gf, Geom gc, Space sp,
-                                                       const T* __restrict__ r,
-                                                       T* __restrict__ fcoarse) {
+// summed with the z offset slowest and the x offset fastest, at coarse point
+// p of the fine values rf(colour, x >> 1, y, z) (a stored residual, or one
+// formed on the fly); false outside the unknowns.
+template <typename T, int D, typename RF>
+__device__ __forceinline__ bool pt_node_restrict_by(const Pt& p, const Geom& gc, RF&& rf, T* __restrict__ fcoarse) {
     const int par = (p.y + p.z + p.c) & 1;
     const int X = 2 * p.xs + par;
-    if (X < 1 || X > gc.n - 2) return;
+    if (X < 1 || X > gc.n - 2) return false;
     const int Y = p.y, Z = p.z;
     T acc = T(0);
     bool first = true;
@@ -1188,14 +1253,23 @@ __device__ __forceinline__ void pt_node_restrict(const Pt& p, Geom gf, Geom gc, 
                 const int wgt = (2 - (ox < 0 ? -ox : ox)) * (2 - (oy < 0 ? -oy : oy)) *
                                 (D == 3 ? (2 - (oz < 0 ? -oz : oz)) : 1);
                 const T w = T(wgt) / T(D == 3 ? 64 : 16);
-                const int cf = (fx + fy + fz) & 1;
-                const T term = w * r[(long long)cf * gf.cs + row_off(gf, fy, fz) + (fx >> 1)];
+                const T term = w * rf((fx + fy + fz) & 1, fx >> 1, fy, fz);
                 acc = first ? term : acc + term;
                 first = false;
             }
         }
     }
     fcoarse[(long long)p.c * gc.cs + row_off(gc, Y, Z) + p.xs] = acc;
+    return true;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void pt_node_restrict(const Pt& p, Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    pt_node_restrict_by<T, D>(p, gc, [&](int c, int xs, int y, int z) -> T {
+        return r[(long long)c * gf.cs + row_off(gf, y, z) + xs];
+    }, fcoarse);
 }
 
 template <typename T, int D>
@@ -1598,11 +1672,10 @@ __global__ __launch_bounds__(256) void k_cell_res_zmk(Geom g, ZSpace zs, const d
     if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
 }
 
-// Mean of the 2^d children, summed with the z offset slowest, then scaled.
-template <typename T, int D>
-__device__ __forceinline__ void pt_cell_restrict(const Pt& p, Geom gf, Geom gc, Space sp,
-                                                       const T* __restrict__ r,
-                                                       T* __restrict__ fcoarse) {
+// Mean of the 2^d children, summed with the z offset slowest, then scaled, at
+// coarse cell p of the fine values rf(colour, x >> 1, y, z).
+template <typename T, int D, typename RF>
+__device__ __forceinline__ bool pt_cell_restrict_by(const Pt& p, const Geom& gc, RF&& rf, T* __restrict__ fcoarse) {
     const int par = (p.y + p.z + p.c) & 1;
     const int X = 2 * p.xs + par, Y = p.y, Z = p.z;
     T acc = T(0);
@@ -1614,13 +1687,23 @@ __device__ __forceinline__ void pt_cell_restrict(const Pt& p, Geom gf, Geom gc, 
 #pragma unroll
             for (int ox = 0; ox <= 1; ++ox) {
                 const int fx = 2 * X + ox, fy = 2 * Y + oy, fz = (D == 3) ? 2 * Z + oz : 0;
-                const T v = r[(long long)((fx + fy + fz) & 1) * gf.cs + row_off(gf, fy, fz) + (fx >> 1)];
+                const T v = rf((fx + fy + fz) & 1, fx >> 1, fy, fz);
                 acc = first ? v : acc + v;
                 first = false;
             }
         }
     }
     fcoarse[(long long)p.c * gc.cs + row_off(gc, Y, Z) + p.xs] = acc * T(D == 3 ? 0.125 : 0.25);
+    return true;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void pt_cell_restrict(const Pt& p, Geom gf, Geom gc, Space sp,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ fcoarse) {
+    pt_cell_restrict_by<T, D>(p, gc, [&](int c, int xs, int y, int z) -> T {
+        return r[(long long)c * gf.cs + row_off(gf, y, z) + xs];
+    }, fcoarse);
 }
 
 template <typename T, int D>
@@ -1838,18 +1921,21 @@ __device__ __forceinline__ void tail_copy(const Geom& gs, const T* __restrict__ 
 }
 
 template <typename T, int D, bool CELL>
-__device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sweeps, bool zero, int c0) {
+__device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sweeps, bool zero, int c0,
+                            bool first_done = false) {
     const Geom g = P.lg[i];
     const T s = (T)P.s[i];
     const T* f = A + P.of[i];
     const T* bx = static_cast<const T*>(P.beta[i][0]);
     const T* by = static_cast<const T*>(P.beta[i][1]);
     const T* bz = static_cast<const T*>(P.beta[i][2]);
-    for (int k = 0; k < sweeps; ++k) {
+    // first_done: the first sweep's first (pointwise, from zero) operation
+    // already ran with the restriction into this level
+    for (int k = (first_done && !P.rbgs) ? 1 : 0; k < sweeps; ++k) {
         const bool z = zero && k == 0;
         T* u = A + (((sw >> i) & 1u) ? P.ob[i] : P.oa[i]);
         if (P.rbgs) {
-            for (int h = 0; h < 2; ++h) {
+            for (int h = (first_done && k == 0) ? 1 : 0; h < 2; ++h) {
                 const int c = h == 0 ? c0 : 1 - c0;
                 const Space sp = P.one[i][c];
                 T* me = u + (long long)c * g.cs;
@@ -1911,36 +1997,92 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailPlan P, const T* __re
     __syncthreads();
     unsigned sw = 0;   // bit i set: level i's iterate is in its second buffer
     const int last = P.nl - 1;
+    bool first_done = false;
     for (int i = 0; i < last; ++i) {
-        tail_smooth<T, D, CELL>(P, A, sw, i, P.nu1, i > 0 || P.from_zero, 0);
+        tail_smooth<T, D, CELL>(P, A, sw, i, P.nu1, i > 0 || P.from_zero, 0, first_done);
+        // the residual of level i restricted to level i + 1 and, when level
+        // i + 1 is smoothed before its own restriction, that smoothing's
+        // first operation, pointwise from zero, at the same coarse point
         const Geom g = P.lg[i], gc = P.lg[i + 1];
         const T* u = A + (((sw >> i) & 1u) ? P.ob[i] : P.oa[i]);
-        T* r = A + (((sw >> i) & 1u) ? P.oa[i] : P.ob[i]);
         const T* f = A + P.of[i];
         const T s = (T)P.s[i];
-        const Space sa = P.all[i], sc = P.all[i + 1];
+        const Space sc = P.all[i + 1];
         T* fco = A + P.of[i + 1];
+        const bool pre = i + 1 < last && P.nu1 > 0;
+        T* uc = A + P.oa[i + 1];           // level i + 1 is untouched: its iterate is in oa
+        T* oc = A + P.ob[i + 1];
+        const T sc1 = (T)P.s[i + 1], om = (T)P.omega;
         if constexpr (CELL) {
             const T* bx = static_cast<const T*>(P.beta[i][0]);
             const T* by = static_cast<const T*>(P.beta[i][1]);
             const T* bz = static_cast<const T*>(P.beta[i][2]);
+            const T* cx = static_cast<const T*>(P.beta[i + 1][0]);
+            const T* cy = static_cast<const T*>(P.beta[i + 1][1]);
+            const T* cz = static_cast<const T*>(P.beta[i + 1][2]);
+            // (cell residuals read six faces from device memory each: stored
+            // once by their own pass rather than formed eight times per
+            // coarse cell)
+            T* r = A + (((sw >> i) & 1u) ? P.oa[i] : P.ob[i]);
+            const Space sa = P.all[i];
             tail_points(sa, [&](const Pt& p) {
                 long long me;
                 const T rv = pt_cell_residual<T, D>(p, g, u, f, bx, by, bz, s, me);
                 r[me] = rv;
             });
             __syncthreads();
-            tail_points(sc, [&](const Pt& p) { pt_cell_restrict<T, D>(p, g, gc, sc, r, fco); });
-        } else {
-            tail_points(sa, [&](const Pt& p) {
-                long long me;
-                T rv;
-                if (pt_node_residual<T, D>(p, g, u, f, s, me, rv)) r[me] = rv;
+            tail_points(sc, [&](const Pt& p) {
+                pt_cell_restrict_by<T, D>(p, gc, [&](int c, int xs, int y, int z) -> T {
+                    return r[(long long)c * g.cs + row_off(g, y, z) + xs];
+                }, fco);
+                if (!pre) return;
+                if (P.rbgs) {
+                    if (p.c == 0) pt_cell_gs<T, D, true>(p, gc, sc, uc, uc + gc.cs, fco, cx, cy, cz, sc1);
+                } else {
+                    pt_cell_jacobi<T, D, true>(p, gc, sc, uc, fco, oc, cx, cy, cz, sc1, om);
+                }
             });
-            __syncthreads();
-            tail_points(sc, [&](const Pt& p) { pt_node_restrict<T, D>(p, g, gc, sc, r, fco); });
+        } else {
+            // 2-D: the residual formed as the restriction needs it (nine
+            // terms per coarse point); 3-D: stored once by its own pass (27
+            // terms per coarse point measured slower than the extra pass)
+            T* r = A + (((sw >> i) & 1u) ? P.oa[i] : P.ob[i]);
+            if constexpr (D == 3) {
+                const Space sa = P.all[i];
+                tail_points(sa, [&](const Pt& p) {
+                    long long me;
+                    T rv;
+                    if (pt_node_residual<T, D>(p, g, u, f, s, me, rv)) r[me] = rv;
+                });
+                __syncthreads();
+            }
+            tail_points(sc, [&](const Pt& p) {
+                const bool in = pt_node_restrict_by<T, D>(p, gc, [&](int c, int xs, int y, int z) -> T {
+                    if constexpr (D == 3) {
+                        return r[(long long)c * g.cs + row_off(g, y, z) + xs];
+                    } else {
+                        Pt q;
+                        q.xs = xs;
+                        q.y = y;
+                        q.z = z;
+                        q.c = c;
+                        long long me;
+                        T rv = T(0);
+                        pt_node_residual<T, D>(q, g, u, f, s, me, rv);
+                        return rv;
+                    }
+                }, fco);
+                if (!in || !pre) return;
+                if (P.rbgs) {
+                    if (p.c == 0) pt_node_gs<T, D, true>(p, gc, sc, uc, uc + gc.cs, fco, sc1);
+                } else {
+                    pt_node_jacobi<T, D, true>(p, gc, sc, uc, fco, oc, sc1, om);
+                }
+            });
         }
         __syncthreads();
+        if (pre && !P.rbgs) sw ^= 1u << (i + 1);
+        first_done = pre;
     }
     tail_coarse<T>(P.lg[last], A + P.of[last], A + P.oa[last], Ls, P.m);
     __syncthreads();

@@ -205,6 +205,39 @@ def test_fused_residual_restriction(mg, n, prec):
     s.close()
 
 
+@pytest.mark.parametrize("n,bc,nu,post", [(128, "dirichlet", 2, 0), (256, "dirichlet", 3, 0),
+                                         (256, "dirichlet", 3, 1), (128, "neumann", 3, 1),
+                                         (256, "neumann", 1, 0)])
+def test_cell_smoothing_step_equals_half_sweeps(mg, n, bc, nu, post):
+    """A smoothing step of the finest 3-D cell level (faces formed from k by
+    the column-marching sweeps) equals the same number of separate red-black
+    half-sweeps bitwise, and the oracle's sweeps bitwise."""
+    k = W.varcoef_k(n, 3)
+    s = mg.Solver(3, n, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=nu, nu2=nu, post_order=post, k=k,
+                  bc=mg.MG_NEUMANN0 if bc == "neumann" else mg.MG_DIRICHLET0)
+    u = rand(n, 3, 1, 500 + n + nu, np.float64)
+    f = rand(n, 3, 1, 600 + n + nu, np.float64) * float(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, 0)
+    s.level_set(0, mg.MG_FIELD_F, f, 0)
+    s.apply(mg.MG_OP_POSTSMOOTH if post else mg.MG_OP_PRESMOOTH, 0, 0)
+    fused = s.level_get(0, mg.MG_FIELD_U, 0)
+    s.level_set(0, mg.MG_FIELD_U, u, 0)
+    first, second = (mg.MG_OP_GS_BLACK, mg.MG_OP_GS_RED) if post else (mg.MG_OP_GS_RED, mg.MG_OP_GS_BLACK)
+    for _ in range(nu):
+        s.apply(first, 0, 0)
+        s.apply(second, 0, 0)
+    halves = s.level_get(0, mg.MG_FIELD_U, 0)
+    s.close()
+    print(f"cell smoothing step n={n} {bc} nu={nu} post={post}: bitwise {np.array_equal(fused, halves)}", flush=True)
+    assert np.array_equal(fused, halves)
+    beta = cell.harmonic_faces(k)
+    ref = u.copy()
+    for _ in range(nu):
+        cell.gs_colour(ref, f, beta, post, bc)
+        cell.gs_colour(ref, f, beta, 1 - post, bc)
+    assert np.array_equal(fused, ref)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("nu,post", [(1, 0), (2, 0), (3, 0), (3, 1), (4, 0), (5, 1)])
 def test_fused_sweeps_equal_half_sweeps(mg, prec, nu, post):
