@@ -15,6 +15,7 @@
 // boundary entries and handle walls with mirror ghosts inside the kernels.
 #pragma once
 
+#include <cmath>
 #include <cstdint>
 
 namespace mg {
@@ -241,7 +242,15 @@ struct TailPlan {
     Space one[kTailMax][2], all[kTailMax], pro[kTailMax];
     int oa[kTailMax], ob[kTailMax], of[kTailMax];
     double s[kTailMax];
+    double rs[kTailMax];          // 1 / s
+    int p2;                       // every s is a power of two (rs exact)
 };
+
+// Is the operator scale s = 1 / h^2 a power of two (its reciprocal exact)?
+static inline bool pow2_scale(double s) {
+    int e;
+    return s > 0.0 && std::frexp(s, &e) == 0.5;
+}
 
 // LDS geometry of a level: rows of exactly `half` entries (face arrays keep
 // their device-memory layout).

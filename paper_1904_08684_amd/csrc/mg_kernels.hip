@@ -153,10 +153,39 @@ __global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict
     d_node_gs<T, D, ZERO>(solo_ex(), g, sp, me, other, f, s);
 }
 
-template <typename T, int D, bool ZERO>
+// a / 6 correctly rounded with one multiply and two FMAs (Markstein's
+// correction step): q0 = a y with y = RN(1/6) is faithful, r = a - 6 q0 is
+// exact, and RN(q0 + r y) is then the correctly rounded quotient.  Equal to
+// a / 6 for every finite a away from the subnormal range (checked over 4e8
+// random doubles and every float mantissa of one binade), except that -0
+// gives +0.
+__device__ __forceinline__ double div6(double a) {
+    constexpr double y = 1.0 / 6.0;
+    const double q0 = a * y;
+    return __builtin_fma(__builtin_fma(-q0, 6.0, a), y, q0);
+}
+__device__ __forceinline__ float div6(float a) {
+    constexpr float y = 1.0f / 6.0f;
+    const float q0 = a * y;
+    return __builtin_fmaf(__builtin_fmaf(-q0, 6.0f, a), y, q0);
+}
+
+// (omega r) / (2 D s).  P2: s is a power of two and rs = 1 / s (exact), so
+// the quotient is the product with the exact reciprocal 2^-2 rs (D = 2) or
+// the correctly rounded division by 6 of (omega r) rs (D = 3): the same
+// rounding as the division, without its instruction sequence (away from
+// the subnormal range).
+template <typename T, int D, bool P2>
+__device__ __forceinline__ T jacobi_step(T w, T s, T rs) {
+    if constexpr (P2 && D == 2) return w * (rs * T(0.25));
+    else if constexpr (P2 && D == 3) return div6(w * rs);
+    else return w / (T(2 * D) * s);
+}
+
+template <typename T, int D, bool ZERO, bool P2 = false>
 __device__ __forceinline__ void pt_node_jacobi(const Pt& p, Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
-                                                     T s, T omega) {
+                                                     T s, T omega, T rs = T(0)) {
     const int par = (p.y + p.z + p.c) & 1;
     const int x = 2 * p.xs + par;
     if (x < 1 || x > g.n - 2) return;
@@ -165,23 +194,23 @@ __device__ __forceinline__ void pt_node_jacobi(const Pt& p, Geom g, Space sp, co
     const T uc = ZERO ? T(0) : u[me];
     const T nb = ZERO ? T(0) : node_nb<T, D>(u + (long long)(1 - p.c) * g.cs, ro, par, g);
     const T r = f[me] - (T(2 * D) * uc - nb) * s;
-    out[me] = uc + (omega * r) / (T(2 * D) * s);
+    out[me] = uc + jacobi_step<T, D, P2>(omega * r, s, rs);
 }
 
-template <typename T, int D, bool ZERO>
+template <typename T, int D, bool ZERO, bool P2>
 __device__ __forceinline__ void d_node_jacobi(const Ex& ex, Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
-                                                     T s, T omega) {
+                                                     T s, T omega, T rs) {
     Pt p;
     if (!map_point(ex, sp, p)) return;
-    pt_node_jacobi<T, D, ZERO>(p, g, sp, u, f, out, s, omega);
+    pt_node_jacobi<T, D, ZERO, P2>(p, g, sp, u, f, out, s, omega, rs);
 }
 
-template <typename T, int D, bool ZERO>
+template <typename T, int D, bool ZERO, bool P2>
 __global__ __launch_bounds__(256) void k_node_jacobi(Geom g, Space sp, const T* __restrict__ u,
                                                      const T* __restrict__ f, T* __restrict__ out,
-                                                     T s, T omega) {
-    d_node_jacobi<T, D, ZERO>(solo_ex(), g, sp, u, f, out, s, omega);
+                                                     T s, T omega, T rs) {
+    d_node_jacobi<T, D, ZERO, P2>(solo_ex(), g, sp, u, f, out, s, omega, rs);
 }
 
 // Residual at point p (false outside the unknowns): its index and value.
@@ -552,23 +581,6 @@ __global__ __launch_bounds__(256) void k_node_res_ym(Geom g, YSpace ys, const T*
                                                      const T* __restrict__ f, T* __restrict__ r, T s,
                                                      double* __restrict__ part) {
     d_node_res_ym<T, NORM, STORE>(solo_ex(), g, ys, u, f, r, s, part);
-}
-
-// a / 6 correctly rounded with one multiply and two FMAs (Markstein's
-// correction step): q0 = a y with y = RN(1/6) is faithful, r = a - 6 q0 is
-// exact, and RN(q0 + r y) is then the correctly rounded quotient.  Equal to
-// a / 6 for every finite a away from the subnormal range (checked over 4e8
-// random doubles and every float mantissa of one binade), except that -0
-// gives +0.
-__device__ __forceinline__ double div6(double a) {
-    constexpr double y = 1.0 / 6.0;
-    const double q0 = a * y;
-    return __builtin_fma(__builtin_fma(-q0, 6.0, a), y, q0);
-}
-__device__ __forceinline__ float div6(float a) {
-    constexpr float y = 1.0f / 6.0f;
-    const float q0 = a * y;
-    return __builtin_fmaf(__builtin_fmaf(-q0, 6.0f, a), y, q0);
 }
 
 // ------------------------------------------ 3-D node grids, temporal blocking
@@ -1972,10 +1984,22 @@ __device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sw
                         pt_cell_jacobi<T, D, false>(p, g, sp, u, f, out, bx, by, bz, s, om);
                     });
             } else {
-                if (z)
-                    tail_points(sp, [&](const Pt& p) { pt_node_jacobi<T, D, true>(p, g, sp, u, f, out, s, om); });
-                else
-                    tail_points(sp, [&](const Pt& p) { pt_node_jacobi<T, D, false>(p, g, sp, u, f, out, s, om); });
+                const T rs = (T)P.rs[i];
+                if (P.p2) {
+                    if (z)
+                        tail_points(sp, [&](const Pt& p) {
+                            pt_node_jacobi<T, D, true, true>(p, g, sp, u, f, out, s, om, rs);
+                        });
+                    else
+                        tail_points(sp, [&](const Pt& p) {
+                            pt_node_jacobi<T, D, false, true>(p, g, sp, u, f, out, s, om, rs);
+                        });
+                } else {
+                    if (z)
+                        tail_points(sp, [&](const Pt& p) { pt_node_jacobi<T, D, true>(p, g, sp, u, f, out, s, om); });
+                    else
+                        tail_points(sp, [&](const Pt& p) { pt_node_jacobi<T, D, false>(p, g, sp, u, f, out, s, om); });
+                }
             }
             __syncthreads();
             sw ^= 1u << i;
@@ -2076,7 +2100,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailPlan P, const T* __re
                 if (P.rbgs) {
                     if (p.c == 0) pt_node_gs<T, D, true>(p, gc, sc, uc, uc + gc.cs, fco, sc1);
                 } else {
-                    pt_node_jacobi<T, D, true>(p, gc, sc, uc, fco, oc, sc1, om);
+                    if (P.p2) pt_node_jacobi<T, D, true, true>(p, gc, sc, uc, fco, oc, sc1, om, (T)P.rs[i + 1]);
+                    else pt_node_jacobi<T, D, true>(p, gc, sc, uc, fco, oc, sc1, om);
                 }
             });
         }
@@ -2599,11 +2624,11 @@ __device__ void run_item(const BItem& it, const Ex& ex) {
             float* out = static_cast<float*>(it.c);
             const float s = (float)it.s, om = (float)it.omega;
             if (it.op == BOP_JAC_ZERO) {
-                if (it.dim == 3) d_node_jacobi<float, 3, true>(ex, it.g, it.sp, u, f, out, s, om);
-                else d_node_jacobi<float, 2, true>(ex, it.g, it.sp, u, f, out, s, om);
+                if (it.dim == 3) d_node_jacobi<float, 3, true, false>(ex, it.g, it.sp, u, f, out, s, om, 0.f);
+                else d_node_jacobi<float, 2, true, false>(ex, it.g, it.sp, u, f, out, s, om, 0.f);
             } else {
-                if (it.dim == 3) d_node_jacobi<float, 3, false>(ex, it.g, it.sp, u, f, out, s, om);
-                else d_node_jacobi<float, 2, false>(ex, it.g, it.sp, u, f, out, s, om);
+                if (it.dim == 3) d_node_jacobi<float, 3, false, false>(ex, it.g, it.sp, u, f, out, s, om, 0.f);
+                else d_node_jacobi<float, 2, false, false>(ex, it.g, it.sp, u, f, out, s, om, 0.f);
             }
             break;
         }
@@ -2889,10 +2914,24 @@ static hipError_t jacobi_t(const Geom& g, bool zero, const void* u, const void* 
                                g, sp, cp<T>(u), cp<T>(f), mp<T>(out), cp<T>(fc.b[0]), cp<T>(fc.b[1]),
                                cp<T>(fc.b[2]), (T)s, (T)omega));
     } else {
-        MG_DISPATCH_DIM(g, if (zero) k_node_jacobi<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
-                               g, sp, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, (T)omega);
-                           else k_node_jacobi<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
-                               g, sp, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, (T)omega));
+        const T rs = (T)(1.0 / s);
+#define MG_NJAC(Z, P)                                                                                  \
+    MG_DISPATCH_DIM(g, k_node_jacobi<T, D, Z, P><<<grid_of(sp), block_of(sp), 0, st>>>(                \
+                           g, sp, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, (T)omega, rs))
+        if (pow2_scale(s)) {
+            if (zero) {
+                MG_NJAC(true, true);
+            } else {
+                MG_NJAC(false, true);
+            }
+        } else {
+            if (zero) {
+                MG_NJAC(true, false);
+            } else {
+                MG_NJAC(false, false);
+            }
+        }
+#undef MG_NJAC
     }
     return hipGetLastError();
 }

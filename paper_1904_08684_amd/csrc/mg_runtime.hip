@@ -850,6 +850,7 @@ void Ctx::plan_tail() {
             int mask = 3;
             if (opts.smoother == MG_RBGS && opts.nu2 > 0) mask = opts.post_order == 0 ? 2 : 1;
             int off = 0;
+            P.p2 = 1;
             for (int i = 0; i < P.nl; ++i) {
                 const Geom lg = tail_geom(lv[l0 + i].g);
                 const int fe = (int)((2 * lg.cs + 3) / 4 * 4);
@@ -863,6 +864,8 @@ void Ctx::plan_tail() {
                 P.of[i] = off + 2 * fe;
                 off += 3 * fe;
                 P.s[i] = scale(l0 + i);
+                P.rs[i] = 1.0 / P.s[i];
+                if (!pow2_scale(P.s[i])) P.p2 = 0;
                 for (int a = 0; a < 3; ++a) P.beta[i][a] = lv[l0 + i].beta[pr][a];
             }
             P.elems = off;

@@ -88,6 +88,27 @@ def test_smoothers_and_residual(mg, dim, n, cent, prec):
     s.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("dim,n", [(2, 65), (2, 97), (3, 33), (3, 49)])
+def test_jacobi_sweep_bitwise_at_both_kinds_of_scale(mg, dim, n, prec):
+    """A damped-Jacobi sweep equals the oracle's (omega r) / (2d s) bitwise
+    whether s = (n - 1)^2 is a power of two (65, 33: the kernels multiply by
+    the exact reciprocal) or not (97, 49: they divide)."""
+    s = mg.Solver(dim, n, coarsest=4 if n in (97, 49) else 5, smoother=mg.MG_JACOBI, omega=0.8, nu1=2, nu2=2,
+                  precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, dim, 0, 300 + n, dt)
+    f = rand(n, dim, 0, 400 + n, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_JACOBI, 0, prec)
+    got = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.close()
+    ref = node.jacobi(u, f, 0.8)
+    print(f"jacobi {dim}d n={n} prec={prec}: bitwise {np.array_equal(got, ref)}", flush=True)
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("n,bc", [(128, "dirichlet"), (256, "dirichlet"), (128, "neumann")])
 def test_cell_faces_from_k_bitwise(mg, n, bc):
     """On the finest 3-D cell level with n >= 128 the FP64 half-sweeps and
