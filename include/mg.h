@@ -308,6 +308,36 @@ typedef struct mg_server_stats {
 /* Device bytes one resident hierarchy of this grid and options occupies. */
 int mg_server_footprint(const mg_grid* g, const mg_opts* o, size_t* bytes);
 int mg_server_create(const mg_server_opts* o, mg_server** out);
+/* A server whose rounds run through host callbacks instead of the batched
+ * device kernels, and which makes no HIP call: the scheduler is the one
+ * above (FIFO queue, tickets, footprint admission against arena_bytes,
+ * resident hierarchies reused by shape and evicted least recently used
+ * first, one step per request per round, deadlines, cancellation, the
+ * clock), so that its logic runs on machines without a GPU.  The library
+ * computes nothing on this path; its own tests drive it with the CPU
+ * reference implementation as the executor.  d_arena and hip_stream are
+ * ignored, and f and u_out are whatever the executor takes them to be.
+ * A callback returning an MG_E* code aborts the round (mg_server_step
+ * returns it). */
+typedef struct mg_server_executor {
+    void* user;
+    /* a hierarchy of r's shape now occupies slot (0 .. 4 max_slots - 1),
+     * which later requests of the same shape reuse; 0 or an MG_E* code */
+    int (*build)(void* user, int slot, const mg_request* r);
+    /* one round: request reqs[i] runs its next refinement step on the
+     * hierarchy in slots[i] (first loading f and forming its initial
+     * residual when first[i] != 0); norms[2 i] receives the sum of squares
+     * of that initial residual (first steps only), norms[2 i + 1] that of
+     * the residual after the step */
+    int (*step)(void* user, int count, const int* slots, const int* first, const mg_request* reqs,
+                double* norms);
+    /* the request in slot retired after at least one step (converged, out
+     * of steps or past its deadline): its iterate goes to r->u_out */
+    int (*finish)(void* user, int slot, const mg_request* r);
+    /* the hierarchy in slot was evicted (NULL: not told) */
+    void (*release)(void* user, int slot);
+} mg_server_executor;
+int mg_server_create_hosted(const mg_server_opts* o, const mg_server_executor* ex, mg_server** out);
 void mg_server_destroy(mg_server* s);                  /* NULL-safe */
 double mg_server_clock(const mg_server* s);           /* seconds since create */
 /* Queue a request (copies the descriptor, not the arrays).  *ticket (if not

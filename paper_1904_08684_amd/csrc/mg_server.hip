@@ -185,6 +185,10 @@ size_t items_bound(const mg_grid* g, const mg_opts* o) {
 
 struct Server {
     mg_server_opts o{};
+    // host executor (mg_server_create_hosted): rounds run through its
+    // callbacks, nothing on a device
+    bool hosted = false;
+    mg_server_executor hx{};
     hipStream_t st = nullptr;
     char* base = nullptr;
     size_t head_bytes = 0;
@@ -240,6 +244,7 @@ struct Server {
     }
 
     void release(Hier* h) {
+        if (hosted && hx.release) hx.release(hx.user, h->slot);
         arena.release(h->off, h->bytes);
         free_slots.push_back(h->slot);
         delete h->ctx;
@@ -280,6 +285,19 @@ struct Server {
         h->ctx_bytes = ctx_bytes;
         h->slot = free_slots.back();
         free_slots.pop_back();
+        if (hosted) {
+            const int rc = hx.build(hx.user, h->slot, &r);
+            if (rc) {
+                arena.release(off, fb);
+                free_slots.push_back(h->slot);
+                delete h;
+                return fail(rc, "host executor: build");
+            }
+            hiers.push_back(h);
+            stats.hierarchies_built++;
+            *out = h;
+            return MG_OK;
+        }
         const mg_opts m = mixed_opts(r.opts);
         std::string why;
         int rc = setup_ctx(&r.grid, nullptr, &m, base + head_bytes + off, ctx_bytes, st, false, &h->ctx, &why);
@@ -397,8 +415,10 @@ struct Server {
             h->last_used = ++tick;
             q.h = h;
             q.t_admit = now();
-            h_io[2 * h->slot] = const_cast<double*>(q.r.f);
-            h_io[2 * h->slot + 1] = q.r.u_out;
+            if (!hosted) {
+                h_io[2 * h->slot] = const_cast<double*>(q.r.f);
+                h_io[2 * h->slot + 1] = q.r.u_out;
+            }
             active.push_back(q);
             queue.pop_front();
             stats.admitted++;
@@ -494,39 +514,68 @@ struct Server {
         return MG_EINVAL;
     }
 
+    // One refinement step of every active request on the device: one
+    // batched launch per op position, then the norms of every slot.
+    int device_round(std::vector<double>& norms) {
+        int rc = dev(hipMemcpyAsync(d_io, h_io, (size_t)max_hier * 2 * sizeof(void*), hipMemcpyHostToDevice, st),
+                     "upload io");
+        if (rc) return rc;
+        std::vector<const std::vector<int>*> progs;
+        std::vector<Hier*> hs;
+        for (Req& q : active) {
+            const int par = q.steps & 1;
+            progs.push_back(q.fresh ? &q.h->first[par] : &q.h->step[par]);
+            hs.push_back(q.h);
+        }
+        rc = launch_round(progs, hs);
+        if (!rc)
+            rc = dev(hipMemcpyAsync(h_results, d_results, (size_t)max_hier * 4 * sizeof(double),
+                                    hipMemcpyDeviceToHost, st),
+                     "read norms");
+        if (!rc) rc = dev(hipStreamSynchronize(st), "sync");
+        if (rc) return rc;
+        for (size_t i = 0; i < active.size(); ++i) {
+            const double* rs = h_results + 4 * active[i].h->slot;
+            norms[2 * i] = rs[0];
+            norms[2 * i + 1] = rs[2];
+        }
+        return MG_OK;
+    }
+
+    // The same step through the host executor.
+    int host_round(std::vector<double>& norms) {
+        std::vector<int> slots, first;
+        std::vector<mg_request> reqs;
+        for (const Req& q : active) {
+            slots.push_back(q.h->slot);
+            first.push_back(q.fresh ? 1 : 0);
+            reqs.push_back(q.r);
+        }
+        const int rc = hx.step(hx.user, (int)active.size(), slots.data(), first.data(), reqs.data(), norms.data());
+        return rc ? fail(rc, "host executor: step") : MG_OK;
+    }
+
     int round(int* in_flight, int* queued) {
         sweep();
         admit();
         if (!active.empty()) {
-            int rc = dev(hipMemcpyAsync(d_io, h_io, (size_t)max_hier * 2 * sizeof(void*), hipMemcpyHostToDevice, st),
-                         "upload io");
-            if (rc) return rc;
-            std::vector<const std::vector<int>*> progs;
-            std::vector<Hier*> hs;
-            for (Req& q : active) {
-                const int par = q.steps & 1;
-                progs.push_back(q.fresh ? &q.h->first[par] : &q.h->step[par]);
-                hs.push_back(q.h);
-            }
-            rc = launch_round(progs, hs);
-            if (!rc)
-                rc = dev(hipMemcpyAsync(h_results, d_results, (size_t)max_hier * 4 * sizeof(double),
-                                        hipMemcpyDeviceToHost, st),
-                         "read norms");
-            if (!rc) rc = dev(hipStreamSynchronize(st), "sync");
+            // norms[2 i], norms[2 i + 1]: sums of squares of active[i]'s
+            // initial residual (first step) and of its residual now
+            std::vector<double> norms(2 * active.size(), 0.0);
+            int rc = hosted ? host_round(norms) : device_round(norms);
             if (rc) return rc;
             stats.rounds++;
             // retire converged requests
             std::vector<Req> keep, fin;
             std::vector<int> status;
-            for (Req& q : active) {
-                const double* rs = h_results + 4 * q.h->slot;
+            for (size_t i = 0; i < active.size(); ++i) {
+                Req& q = active[i];
                 if (q.fresh) {
-                    q.r0 = std::sqrt(rs[0]);
+                    q.r0 = std::sqrt(norms[2 * i]);
                     q.fresh = false;
                 }
                 q.steps++;
-                q.rel = q.r0 > 0.0 ? std::sqrt(rs[2]) / q.r0 : 0.0;
+                q.rel = q.r0 > 0.0 ? std::sqrt(norms[2 * i + 1]) / q.r0 : 0.0;
                 int stt = 1;
                 if (!std::isfinite(q.r0) || !std::isfinite(q.rel)) stt = MG_ENONFINITE;
                 else if (q.rel <= q.r.tol) stt = MG_OK;
@@ -539,7 +588,12 @@ struct Server {
                     status.push_back(stt);
                 }
             }
-            if (!fin.empty()) {
+            if (hosted) {
+                for (size_t i = 0; i < fin.size(); ++i) {
+                    rc = hx.finish(hx.user, fin[i].h->slot, &fin[i].r);
+                    if (rc) return fail(rc, "host executor: finish");
+                }
+            } else if (!fin.empty()) {
                 std::vector<std::vector<int>> one(fin.size());
                 std::vector<const std::vector<int>*> up;
                 std::vector<Hier*> uh;
@@ -551,6 +605,8 @@ struct Server {
                 rc = launch_round(up, uh);
                 if (!rc) rc = dev(hipStreamSynchronize(st), "sync");
                 if (rc) return rc;
+            }
+            if (!fin.empty()) {
                 const double t = now();
                 for (size_t i = 0; i < fin.size(); ++i) {
                     mg_result res;
@@ -640,10 +696,31 @@ int mg_server_create(const mg_server_opts* o, mg_server** out) {
     return MG_OK;
 }
 
+int mg_server_create_hosted(const mg_server_opts* o, const mg_server_executor* ex, mg_server** out) {
+    if (!o || !ex || !out) return MG_EINVAL;
+    *out = nullptr;
+    if (!ex->build || !ex->step || !ex->finish || o->max_slots < 1 || o->max_slots > 4096 || o->max_queue < 1 ||
+        o->arena_bytes < mg::kGranule)
+        return MG_EINVAL;
+    Server* s = new (std::nothrow) Server();
+    if (!s) return MG_ENOMEM;
+    s->o = *o;
+    s->o.d_arena = nullptr;
+    s->o.hip_stream = nullptr;
+    s->hosted = true;
+    s->hx = *ex;
+    s->max_hier = std::min(4 * o->max_slots, 16384);
+    s->arena.init(o->arena_bytes / mg::kGranule * mg::kGranule);
+    for (int i = s->max_hier - 1; i >= 0; --i) s->free_slots.push_back(i);
+    s->t0 = std::chrono::steady_clock::now();
+    *out = reinterpret_cast<mg_server*>(s);
+    return MG_OK;
+}
+
 void mg_server_destroy(mg_server* h) {
     Server* s = reinterpret_cast<Server*>(h);
     if (!s) return;
-    (void)hipStreamSynchronize(s->st);
+    if (!s->hosted) (void)hipStreamSynchronize(s->st);
     delete s;
 }
 

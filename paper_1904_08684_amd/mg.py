@@ -331,9 +331,22 @@ class mg_server_stats(C.Structure):
                 ("algorithmic_bytes", C.c_double)]
 
 
+_EX_BUILD = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(mg_request))
+_EX_STEP = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(mg_request),
+                       C.POINTER(C.c_double))
+_EX_FINISH = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(mg_request))
+_EX_RELEASE = C.CFUNCTYPE(None, C.c_void_p, C.c_int)
+
+
+class mg_server_executor(C.Structure):
+    _fields_ = [("user", C.c_void_p), ("build", _EX_BUILD), ("step", _EX_STEP), ("finish", _EX_FINISH),
+                ("release", _EX_RELEASE)]
+
+
 _ssigs = {
     "mg_server_footprint": (C.c_int, [C.POINTER(mg_grid), C.POINTER(mg_opts), C.POINTER(C.c_size_t)]),
     "mg_server_create": (C.c_int, [C.POINTER(mg_server_opts), C.POINTER(_P)]),
+    "mg_server_create_hosted": (C.c_int, [C.POINTER(mg_server_opts), C.POINTER(mg_server_executor), C.POINTER(_P)]),
     "mg_server_destroy": (None, [_P]),
     "mg_server_clock": (C.c_double, [_P]),
     "mg_server_submit": (C.c_int, [_P, C.POINTER(mg_request), C.POINTER(C.c_uint64)]),
@@ -396,8 +409,8 @@ class Server:
         r.grid = make_grid(dim, n)
         r.opts = make_opts(smoother, omega, nu1, nu2, MG_MIXED, max_steps)
         r.tol = tol
-        r.f = f.data_ptr()
-        r.u_out = u_out.data_ptr()
+        r.f = _address(f)
+        r.u_out = _address(u_out)
         r.t_arrive = self.clock() if t_arrive is None else t_arrive
         r.deadline = deadline
         t = C.c_uint64()
@@ -446,6 +459,72 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _address(a) -> int:
+    """Data address of a torch tensor or a NumPy array."""
+    return a.data_ptr() if hasattr(a, "data_ptr") else a.ctypes.data
+
+
+class HostedServer(Server):
+    """The server's scheduler with its rounds run by a host executor instead
+    of the batched device kernels (mg_server_create_hosted): no device work.
+    The executor object provides build(slot, request),
+    step(slots, first, requests) -> [(initial sum r^2, sum r^2), ...],
+    finish(slot, request) and release(slot); requests are mg_request
+    structures whose f and u_out hold the addresses of the arrays passed to
+    submit.  An exception in a callback aborts the round with MG_EDEVICE."""
+
+    def __init__(self, executor, arena_bytes: int, max_slots: int = 256, max_queue: int = 1 << 20):
+        o = mg_server_opts()
+        o.arena_bytes = arena_bytes
+        o.max_slots = max_slots
+        o.max_queue = max_queue
+        self.executor = executor
+        self.callback_error = None
+
+        def guard(fn):
+            def run(*a):
+                try:
+                    return fn(*a)
+                except Exception as e:   # reported through the round's status
+                    self.callback_error = e
+                    return MG_EDEVICE
+            return run
+
+        @guard
+        def build(_user, slot, req):
+            executor.build(slot, req.contents)
+            return MG_OK
+
+        @guard
+        def step(_user, count, slots, first, reqs, norms):
+            out = executor.step([slots[i] for i in range(count)], [first[i] for i in range(count)],
+                                [reqs[i] for i in range(count)])
+            for i, (a, b) in enumerate(out):
+                norms[2 * i] = a
+                norms[2 * i + 1] = b
+            return MG_OK
+
+        @guard
+        def finish(_user, slot, req):
+            executor.finish(slot, req.contents)
+            return MG_OK
+
+        def release(_user, slot):
+            try:
+                executor.release(slot)
+            except Exception as e:
+                self.callback_error = e
+
+        self._callbacks = (_EX_BUILD(build), _EX_STEP(step), _EX_FINISH(finish), _EX_RELEASE(release))
+        ex = mg_server_executor(None, *self._callbacks)
+        h = C.c_void_p()
+        code = mg_server_create_hosted(C.byref(o), C.byref(ex), C.byref(h))
+        if code != MG_OK:
+            raise MGError(code, "hosted server create")
+        self.h = h
+        self._keep = {}
 
 
 # ------------------------------------------- DG volume terms (include/dg.h)

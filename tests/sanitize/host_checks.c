@@ -2,7 +2,7 @@
  * build (host code instrumented, no GPU needed): the workspace and footprint
  * planners over many grids and options, argument validation of every entry
  * point that rejects before touching a device, the exact DG tables and the
- * basis values.  Exits non-zero on the first unexpected return code; the
+ * basis values, and the server's scheduler driven by a host executor.  Exits non-zero on the first unexpected return code; the
  * sanitizers abort on any memory or undefined-behaviour error. */
 #include <stdio.h>
 #include <stdlib.h>
@@ -110,10 +110,106 @@ static void dg_tables(void) {
            MG_EINVAL, "noalloc step: null arrays");
 }
 
+/* The server's scheduler with a host executor whose requests "converge" by
+ * a factor 10 per step: queue, admission against a budget of two
+ * hierarchies, reuse, eviction, cancellation and deadlines under the
+ * sanitizers. */
+static int steps_of[64];
+static int ex_build(void* user, int slot, const mg_request* r) {
+    (void)user;
+    return (slot < 0 || r->grid.n[0] < 9) ? MG_EINVAL : MG_OK;
+}
+static int ex_step(void* user, int count, const int* slots, const int* first, const mg_request* reqs, double* norms) {
+    (void)user;
+    (void)slots;
+    for (int i = 0; i < count; ++i) {
+        const int id = (int)reqs[i].id;
+        if (first[i]) steps_of[id] = 0;
+        ++steps_of[id];
+        double v = 1.0;
+        for (int k = 0; k < steps_of[id]; ++k) v *= 0.01;
+        norms[2 * i] = first[i] ? 1.0 : 0.0;
+        norms[2 * i + 1] = v;
+    }
+    return MG_OK;
+}
+static int ex_finish(void* user, int slot, const mg_request* r) {
+    (void)user;
+    (void)slot;
+    r->u_out[0] = (double)steps_of[r->id];
+    return MG_OK;
+}
+static void ex_release(void* user, int slot) {
+    (void)user;
+    (void)slot;
+}
+
+static void hosted_server(void) {
+    static const int shapes[4][2] = {{2, 33}, {3, 17}, {2, 65}, {3, 9}};
+    size_t fp[4], big = 0;
+    for (int s = 0; s < 4; ++s) {
+        mg_grid g = {shapes[s][0], {shapes[s][1], shapes[s][1], shapes[s][0] == 3 ? shapes[s][1] : 1}, MG_NODE, 5};
+        mg_opts o;
+        mg_default_opts(&o);
+        o.precision = MG_MIXED;
+        expect(mg_server_footprint(&g, &o, &fp[s]), MG_OK, "server footprint");
+        if (fp[s] > big) big = fp[s];
+    }
+    mg_server_opts so;
+    memset(&so, 0, sizeof(so));
+    so.arena_bytes = 2 * big;
+    so.max_slots = 3;
+    so.max_queue = 64;
+    mg_server_executor ex = {NULL, ex_build, ex_step, ex_finish, ex_release};
+    mg_server* srv = NULL;
+    expect(mg_server_create_hosted(&so, &ex, &srv), MG_OK, "hosted server");
+    if (!srv) return;
+    static double f[64], u[64];
+    uint64_t tk[40];
+    for (int i = 0; i < 40; ++i) {
+        const int s = i % 4;
+        mg_request r;
+        memset(&r, 0, sizeof(r));
+        r.id = (uint64_t)i;
+        r.grid = (mg_grid){shapes[s][0], {shapes[s][1], shapes[s][1], shapes[s][0] == 3 ? shapes[s][1] : 1}, MG_NODE,
+                           5};
+        mg_default_opts(&r.opts);
+        r.opts.precision = MG_MIXED;
+        r.tol = 1e-7;
+        r.f = &f[i];
+        r.u_out = &u[i];
+        r.deadline = (i % 13 == 5) ? 1e-12 : 0.0;   /* past at the first round */
+        expect(mg_server_submit(srv, &r, &tk[i]), MG_OK, "hosted submit");
+    }
+    expect(mg_server_cancel(srv, tk[7]), MG_OK, "hosted cancel");
+    int in_flight = 1, queued = 1, rounds = 0, got = 0, ok = 0;
+    mg_result res[64];
+    while ((in_flight || queued) && rounds < 1000) {
+        expect(mg_server_step(srv, &in_flight, &queued), MG_OK, "hosted step");
+        int n = 0;
+        expect(mg_server_poll(srv, res, 64, &n), MG_OK, "hosted poll");
+        for (int k = 0; k < n; ++k) ok += res[k].status == MG_OK;
+        got += n;
+        ++rounds;
+    }
+    int n = 0;
+    expect(mg_server_poll(srv, res, 64, &n), MG_OK, "hosted poll");
+    got += n;
+    mg_server_stats st;
+    expect(mg_server_get_stats(srv, &st), MG_OK, "hosted stats");
+    expect(got, 40, "hosted: every request retired");
+    expect(ok, 40 - 1 - 3, "hosted: converged requests");
+    expect((int)(st.arena_peak_bytes <= so.arena_bytes), 1, "hosted: budget respected");
+    expect((int)(st.evictions > 0), 1, "hosted: idle hierarchies evicted");
+    mg_server_destroy(srv);
+    expect(mg_server_create_hosted(&so, NULL, &srv), MG_EINVAL, "hosted: no executor");
+}
+
 int main(void) {
     printf("%s\n", mg_version());
     planners();
     dg_tables();
+    hosted_server();
     if (fails) {
         fprintf(stderr, "%d unexpected return codes\n", fails);
         return 1;
