@@ -54,6 +54,15 @@ hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, int prec, co
 // u_fine += P e_coarse on the colours in `colour_mask` (bit 0 red, bit 1 black).
 hipError_t launch_prolong(const Geom& gf, const Geom& gc, int prec, void* u, const void* ec,
                           int colour_mask, hipStream_t st);
+// 2-D node levels running point kernels (fused_point_transfers): residual +
+// full weighting into the coarse f in one launch, and interpolation +
+// correction + the first damped-Jacobi sweep (u, coarse e -> out, out of
+// place) in one launch; both bitwise equal to the separate operations.
+bool fused_point_transfers(const Geom& gf);
+hipError_t launch_residual_restrict_pt(const Geom& gf, const Geom& gc, int prec, const void* u, const void* f,
+                                       void* fcoarse, double s, hipStream_t st);
+hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const void* u, const void* ec,
+                                 const void* f, void* out, double s, double omega, hipStream_t st);
 
 // Coarsest solve u = A^-1 f with the FP64 lower Cholesky factor L (m x m, row major).
 hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const double* L, int m,

@@ -1284,6 +1284,30 @@ __device__ __forceinline__ void pt_node_restrict(const Pt& p, Geom gf, Geom gc, 
     }, fcoarse);
 }
 
+// Residual and full weighting in one launch over the coarse points of a
+// level that runs point kernels: each coarse point forms the residuals of
+// its 3^d fine footprint as it sums them (nothing stored), each with the
+// residual kernel's operands and order, so f_coarse is bitwise that of the
+// residual then the restriction.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_node_res_restrict_pt(Geom gf, Geom gc, Space sp, const T* __restrict__ u,
+                                                              const T* __restrict__ f, T* __restrict__ fcoarse,
+                                                              T s) {
+    Pt p;
+    if (!map_point(solo_ex(), sp, p)) return;
+    pt_node_restrict_by<T, D>(p, gc, [&](int c, int xs, int y, int z) -> T {
+        Pt q;
+        q.xs = xs;
+        q.y = y;
+        q.z = z;
+        q.c = c;
+        long long me;
+        T rv = T(0);
+        pt_node_residual<T, D>(q, gf, u, f, s, me, rv);
+        return rv;
+    }, fcoarse);
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void d_node_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
@@ -1341,6 +1365,59 @@ template <typename T, int D>
 __global__ __launch_bounds__(256) void k_node_prolong(Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
     d_node_prolong<T, D>(solo_ex(), gf, gc, sp, u, ec);
+}
+
+// Iterate after interpolation + correction at fine node (x, y, z): u + P e
+// formed as pt_node_prolong forms it (boundary nodes: u, uncorrected).
+template <typename T, int D>
+__device__ __forceinline__ T node_corrected(const Geom& gf, const Geom& gc, const T* __restrict__ u,
+                                            const T* __restrict__ ec, int x, int y, int z) {
+    const T uv = u[(long long)((x + y + z) & 1) * gf.cs + row_off(gf, y, z) + (x >> 1)];
+    if (x < 1 || x > gf.n - 2 || y < 1 || y > gf.n - 2 || (D == 3 && (z < 1 || z > gf.n - 2))) return uv;
+    const T half = T(0.5);
+    const int X0 = x >> 1, X1 = (x + 1) >> 1, Y0 = y >> 1, Y1 = (y + 1) >> 1;
+    const int Z0 = z >> 1, Z1 = (z + 1) >> 1;
+    auto E = [&](int X, int Y, int Z) -> T {
+        return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
+    };
+    auto ix = [&](int Y, int Z) -> T {
+        return (x & 1) ? half * (E(X0, Y, Z) + E(X1, Y, Z)) : E(X0, Y, Z);
+    };
+    auto iy = [&](int Z) -> T { return (y & 1) ? half * (ix(Y0, Z) + ix(Y1, Z)) : ix(Y0, Z); };
+    T e;
+    if (D == 3)
+        e = (z & 1) ? half * (iy(Z0) + iy(Z1)) : iy(Z0);
+    else
+        e = iy(0);
+    return uv + e;
+}
+
+// Interpolation + correction fused with the first damped-Jacobi sweep that
+// follows it: out = J(u + P e) at every unknown, with the corrected values
+// of the point and its neighbours formed on the fly (never stored) and the
+// operands in the order of the separate kernels, so out is bitwise what
+// prolongation then a sweep give.
+template <typename T, int D, bool P2>
+__global__ __launch_bounds__(256) void k_node_prolong_jacobi(Geom gf, Geom gc, Space sp, const T* __restrict__ u,
+                                                             const T* __restrict__ ec, const T* __restrict__ f,
+                                                             T* __restrict__ out, T s, T omega, T rs) {
+    Pt p;
+    if (!map_point(solo_ex(), sp, p)) return;
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par, y = p.y, z = p.z;
+    if (x < 1 || x > gf.n - 2) return;
+    const long long me = (long long)p.c * gf.cs + row_off(gf, y, z) + p.xs;
+    const T uc = node_corrected<T, D>(gf, gc, u, ec, x, y, z);
+    T nb = node_corrected<T, D>(gf, gc, u, ec, x - 1, y, z);
+    nb = nb + node_corrected<T, D>(gf, gc, u, ec, x + 1, y, z);
+    nb = nb + node_corrected<T, D>(gf, gc, u, ec, x, y - 1, z);
+    nb = nb + node_corrected<T, D>(gf, gc, u, ec, x, y + 1, z);
+    if (D == 3) {
+        nb = nb + node_corrected<T, D>(gf, gc, u, ec, x, y, z - 1);
+        nb = nb + node_corrected<T, D>(gf, gc, u, ec, x, y, z + 1);
+    }
+    const T r = f[me] - (T(2 * D) * uc - nb) * s;
+    out[me] = uc + jacobi_step<T, D, P2>(omega * r, s, rs);
 }
 
 // ------------------------------------------------------------ cell grids
@@ -3081,6 +3158,49 @@ hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, int prec, co
     if (!fused_transfers(gf)) return hipErrorInvalidValue;
     return prec ? res_restrict_t<float>(gf, gc, u, f, fcoarse, s, st)
                 : res_restrict_t<double>(gf, gc, u, f, fcoarse, s, st);
+}
+
+// 2-D node levels that run point kernels: residual + full weighting, and
+// interpolation + correction + the first damped-Jacobi sweep, one launch each.
+bool fused_point_transfers(const Geom& gf) { return gf.dim == 2 && !gf.cell && !use_ymarch(gf); }
+
+template <typename T>
+static hipError_t res_restrict_pt_t(const Geom& gf, const Geom& gc, const void* u, const void* f, void* fco,
+                                    double s, hipStream_t st) {
+    const Space sp = space_of(gc, 2, 0);
+    k_node_res_restrict_pt<T, 2><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, cp<T>(u), cp<T>(f), mp<T>(fco),
+                                                                       (T)s);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_restrict_pt(const Geom& gf, const Geom& gc, int prec, const void* u, const void* f,
+                                       void* fcoarse, double s, hipStream_t st) {
+    if (!fused_point_transfers(gf)) return hipErrorInvalidValue;
+    return prec ? res_restrict_pt_t<float>(gf, gc, u, f, fcoarse, s, st)
+                : res_restrict_pt_t<double>(gf, gc, u, f, fcoarse, s, st);
+}
+
+template <typename T>
+static hipError_t prolong_jacobi_t(const Geom& gf, const Geom& gc, const void* u, const void* ec, const void* f,
+                                   void* out, double s, double omega, hipStream_t st) {
+    const Space sp = space_of(gf, 2, 0);
+    const T rs = (T)(1.0 / s);
+    if (pow2_scale(s))
+        k_node_prolong_jacobi<T, 2, true><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, cp<T>(u), cp<T>(ec),
+                                                                                 cp<T>(f), mp<T>(out), (T)s,
+                                                                                 (T)omega, rs);
+    else
+        k_node_prolong_jacobi<T, 2, false><<<grid_of(sp), block_of(sp), 0, st>>>(gf, gc, sp, cp<T>(u), cp<T>(ec),
+                                                                                  cp<T>(f), mp<T>(out), (T)s,
+                                                                                  (T)omega, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const void* u, const void* ec,
+                                 const void* f, void* out, double s, double omega, hipStream_t st) {
+    if (!fused_point_transfers(gf)) return hipErrorInvalidValue;
+    return prec ? prolong_jacobi_t<float>(gf, gc, u, ec, f, out, s, omega, st)
+                : prolong_jacobi_t<double>(gf, gc, u, ec, f, out, s, omega, st);
 }
 
 hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void* r, void* fcoarse,

@@ -894,6 +894,13 @@ int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
                     launch_residual_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr], lv[l + 1].f[pr],
                                              scale(l), stream),
                     e0, "residual+restrict");
+    } else if (!rc && !rec && grid.centering == MG_NODE && !lv[l].gal && fused_point_transfers(lv[l].g)) {
+        // 2-D point levels: each coarse point forms its fine residuals
+        hipEvent_t e0 = begin();
+        rc = record(MG_K_RESTRICT, l,
+                    launch_residual_restrict_pt(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr],
+                                                lv[l + 1].f[pr], scale(l), stream),
+                    e0, "residual+restrict");
     } else {
         if (!rc) rc = residual(l, pr, false, true);
         if (!rc) rc = restrict_to(l, pr);
@@ -908,8 +915,23 @@ int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     // other colour only.
     int mask = 3;
     if (opts.smoother == MG_RBGS && opts.nu2 > 0) mask = opts.post_order == 0 ? 2 : 1;
-    rc = prolong(l, pr, mask);
-    if (!rc) rc = smooth(l, pr, opts.nu2, false, opts.post_order);
+    Level& F = lv[l];
+    if (!rec && opts.smoother == MG_JACOBI && opts.nu2 > 0 && grid.centering == MG_NODE && !F.gal && F.utmp[pr] &&
+        fused_point_transfers(F.g)) {
+        // 2-D point levels: the first post-smoothing sweep reads the
+        // corrected iterate as the interpolation forms it
+        hipEvent_t e0 = begin();
+        rc = record(MG_K_SMOOTH, l,
+                    launch_prolong_jacobi(F.g, lv[l + 1].g, pr, F.u[pr], lv[l + 1].u[pr], F.f[pr], F.utmp[pr],
+                                          scale(l), opts.omega, stream),
+                    e0, "prolong+jacobi");
+        if (rc) return rc;
+        std::swap(F.u[pr], F.utmp[pr]);
+        rc = smooth(l, pr, opts.nu2 - 1, false, opts.post_order);
+    } else {
+        rc = prolong(l, pr, mask);
+        if (!rc) rc = smooth(l, pr, opts.nu2, false, opts.post_order);
+    }
     if (!rc && neu && l == 0) rc = project(0, lv[0].u[pr]);
     return rc;
 }
