@@ -63,6 +63,12 @@ hipError_t launch_residual_restrict_pt(const Geom& gf, const Geom& gc, int prec,
                                        void* fcoarse, double s, hipStream_t st);
 hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const void* u, const void* ec,
                                  const void* f, void* out, double s, double omega, hipStream_t st);
+// The finest 3-D cell level (FP64, faces from k): residual and the mean of
+// the eight children into the coarse f in one pass, bitwise equal to the
+// residual then the restriction.
+bool cell_res_restrict_fused(const Geom& gf);
+hipError_t launch_cell_res_restrict(const Geom& gf, const Geom& gc, const void* u, const void* f, const void* k,
+                                    void* fco, double s, hipStream_t st);
 
 // Coarsest solve u = A^-1 f with the FP64 lower Cholesky factor L (m x m, row major).
 hipError_t launch_coarse(const Geom& g, int prec, const void* f, void* u, const double* L, int m,

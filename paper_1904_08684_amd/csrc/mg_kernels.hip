@@ -1761,6 +1761,110 @@ __global__ __launch_bounds__(256) void k_cell_res_zmk(Geom g, ZSpace zs, const d
     if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
 }
 
+// Residual and the mean of the eight children in one pass on the finest
+// 3-D cell level (faces formed from k as in k_cell_res_zmk): thread
+// (x >> 1, Y) forms the residuals of fine rows 2Y and 2Y + 1, both colours,
+// plane by plane, and adds them into coarse cell (x >> 1, Y, z >> 1) with
+// the z offset slowest and the x offset fastest, as the restriction sums
+// them.  Each residual takes k_cell_res_zmk's operands in its order, so the
+// coarse right-hand side is bitwise that of the two kernels; the fine
+// residual is never written.  Chunks hold an even number of planes.
+template <bool NT>
+__global__ __launch_bounds__(256) void k_cell_res_restrict_zmk(Geom g, Geom gc, ZSpace zs,
+                                                               const double* __restrict__ u,
+                                                               const double* __restrict__ f,
+                                                               const double* __restrict__ k,
+                                                               double* __restrict__ fco, double s) {
+    const Ex ex = solo_ex();
+    int tx, ty, tz;
+    zm_tile(zs, ex.b, tx, ty, tz);
+    const int xs = tx * 64 + (ex.t & 63);
+    const int Y = ty * zs.rows + (ex.t >> 6);
+    const int N = g.n;
+    if (xs >= zs.xr || 2 * Y >= N) return;
+    const int z0 = tz * zs.zc, z1 = min(z0 + zs.zc, N);
+    const long long pl = g.plane, pt = g.pitch, cs = g.cs;
+    const double ww = g.neu ? 0.0 : 2.0;
+    // per fine row j (y = 2Y + j): wall flags, y offsets, row offset, and
+    // the z rings of both colours (u and k on planes z - 1, z)
+    bool wym[2], wyp[2];
+    long long oym[2], oyp[2], ro[2];
+    double um[2][2], uc[2][2], kmz[2][2], kcz[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int y = 2 * Y + j;
+        wym[j] = y == 0;
+        wyp[j] = y == N - 1;
+        oym[j] = wym[j] ? 0 : -pt;
+        oyp[j] = wyp[j] ? 0 : pt;
+        ro[j] = row_off(g, y, z0) + xs;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            uc[j][c] = u[c * cs + ro[j]];
+            kcz[j][c] = k[c * cs + ro[j]];
+            um[j][c] = z0 > 0 ? u[c * cs + ro[j] - pl] : 0.0;
+            kmz[j][c] = z0 > 0 ? k[c * cs + ro[j] - pl] : 0.0;
+        }
+    }
+    double acc = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        const bool wzm = z == 0, wzp = z == N - 1;
+        const long long ozp = wzp ? 0 : pl;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int y = 2 * Y + j;
+            double up[2], kp[2], rv[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                up[c] = u[c * cs + ro[j] + ozp];
+                kp[c] = k[c * cs + ro[j] + ozp];
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int o = 1 - c;
+                const long long oc = o * cs + ro[j];
+                const int par = (y + z + c) & 1;
+                const bool wxm = !par && xs == 0, wxp = par && xs == zs.xr - 1;
+                const long long ox = par ? (wxp ? 0 : 1) : (wxm ? 0 : -1);
+                double kn[6], un[6];
+                const double kx = k[oc + ox], ux = u[oc + ox];
+                kn[0] = par ? kcz[j][o] : kx;
+                kn[1] = par ? kx : kcz[j][o];
+                kn[2] = k[oc + oym[j]];
+                kn[3] = k[oc + oyp[j]];
+                kn[4] = kmz[j][o];
+                kn[5] = kp[o];
+                un[0] = par ? uc[j][o] : ux;
+                un[1] = par ? ux : uc[j][o];
+                un[2] = u[oc + oym[j]];
+                un[3] = u[oc + oyp[j]];
+                un[4] = um[j][o];
+                un[5] = up[o];
+                const bool wall[6] = {wxm, wxp, wym[j], wyp[j], wzm, wzp};
+                double dg, off;
+                cell_sums_k<false>(kcz[j][c], kn, un, wall, ww, dg, off);
+                rv[c] = ld_stream<NT>(f + c * cs + ro[j]) - (dg * uc[j][c] - off) * s;
+            }
+            // x offset 0 is the colour with (y + z + c) even
+            const int c0 = (y + z) & 1;
+            acc = ((z & 1) == 0 && j == 0) ? rv[c0] : acc + rv[c0];
+            acc = acc + rv[1 - c0];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                um[j][c] = uc[j][c];
+                uc[j][c] = up[c];
+                kmz[j][c] = kcz[j][c];
+                kcz[j][c] = kp[c];
+            }
+            ro[j] += pl;
+        }
+        if (z & 1) {
+            const int Z = z >> 1;
+            fco[(long long)((xs + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (xs >> 1)] = acc * 0.125;
+        }
+    }
+}
+
 // Mean of the 2^d children, summed with the z offset slowest, then scaled, at
 // coarse cell p of the fine values rf(colour, x >> 1, y, z).
 template <typename T, int D, typename RF>
@@ -3201,6 +3305,23 @@ hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const
     if (!fused_point_transfers(gf)) return hipErrorInvalidValue;
     return prec ? prolong_jacobi_t<float>(gf, gc, u, ec, f, out, s, omega, st)
                 : prolong_jacobi_t<double>(gf, gc, u, ec, f, out, s, omega, st);
+}
+
+bool cell_res_restrict_fused(const Geom& gf) { return use_cell_zm(gf) && kZChunk % 2 == 0; }
+
+hipError_t launch_cell_res_restrict(const Geom& gf, const Geom& gc, const void* u, const void* f, const void* k,
+                                    void* fco, double s, hipStream_t st) {
+    if (!cell_res_restrict_fused(gf) || !k) return hipErrorInvalidValue;
+    ZSpace zs = make_czspace(gf);
+    zs.nty = (gf.n / 2 + zs.rows - 1) / zs.rows;   // tiles of coarse rows
+    const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+    if (streams_from_hbm(gf, 8))
+        k_cell_res_restrict_zmk<true><<<grid, block, 0, st>>>(gf, gc, zs, cp<double>(u), cp<double>(f), cp<double>(k),
+                                                              mp<double>(fco), s);
+    else
+        k_cell_res_restrict_zmk<false><<<grid, block, 0, st>>>(gf, gc, zs, cp<double>(u), cp<double>(f),
+                                                               cp<double>(k), mp<double>(fco), s);
+    return hipGetLastError();
 }
 
 hipError_t launch_restrict(const Geom& gf, const Geom& gc, int prec, const void* r, void* fcoarse,

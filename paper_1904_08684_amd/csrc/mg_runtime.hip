@@ -882,29 +882,46 @@ int Ctx::tail_cycle(int l, int pr, bool from_zero) {
     return record(MG_K_COARSE, l, launch_tail(P, pr, lv[l].f[pr], lv[l].u[pr], stream), e0, "coarse levels");
 }
 
+// Residual of level l restricted into level l + 1's right-hand side: one
+// pass where a fused kernel exists (3-D node levels that march columns, 2-D
+// node point levels, the finest cell level with k), else the two operations.
+int Ctx::residual_restrict(int l, int pr) {
+    const Geom& g = lv[l].g;
+    const char* what = "residual+restrict";
+    if (!rec && grid.centering == MG_NODE && !lv[l].gal && fused_transfers(g)) {
+        // fine residual and full weighting in one pass; r is not written
+        hipEvent_t e0 = begin();
+        return record(MG_K_RESTRICT, l,
+                      launch_residual_restrict(g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr], lv[l + 1].f[pr],
+                                               scale(l), stream),
+                      e0, what);
+    }
+    if (!rec && grid.centering == MG_CELL && pr == 0 && faces(l, pr).k && cell_res_restrict_fused(g)) {
+        // the finest cell level: residual and 8-child mean in one pass
+        hipEvent_t e0 = begin();
+        return record(MG_K_RESTRICT, l,
+                      launch_cell_res_restrict(g, lv[l + 1].g, lv[l].u[pr], lv[l].f[pr], faces(l, pr).k,
+                                               lv[l + 1].f[pr], scale(l), stream),
+                      e0, what);
+    }
+    if (!rec && grid.centering == MG_NODE && !lv[l].gal && fused_point_transfers(g)) {
+        // 2-D point levels: each coarse point forms its fine residuals
+        hipEvent_t e0 = begin();
+        return record(MG_K_RESTRICT, l,
+                      launch_residual_restrict_pt(g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr], lv[l + 1].f[pr],
+                                                  scale(l), stream),
+                      e0, what);
+    }
+    int rc = residual(l, pr, false, true);
+    return rc ? rc : restrict_to(l, pr);
+}
+
 // One cycle of the given type on level l (see mg_opts).
 int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
     if (!rec && kind == MG_CYCLE_V && l == tail_l[pr]) return tail_cycle(l, pr, from_zero);
     int rc = smooth(l, pr, opts.nu1, from_zero, 0);
-    if (!rc && !rec && grid.centering == MG_NODE && !lv[l].gal && fused_transfers(lv[l].g)) {
-        // fine residual and full weighting in one pass; r is not written
-        hipEvent_t e0 = begin();
-        rc = record(MG_K_RESTRICT, l,
-                    launch_residual_restrict(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr], lv[l + 1].f[pr],
-                                             scale(l), stream),
-                    e0, "residual+restrict");
-    } else if (!rc && !rec && grid.centering == MG_NODE && !lv[l].gal && fused_point_transfers(lv[l].g)) {
-        // 2-D point levels: each coarse point forms its fine residuals
-        hipEvent_t e0 = begin();
-        rc = record(MG_K_RESTRICT, l,
-                    launch_residual_restrict_pt(lv[l].g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr],
-                                                lv[l + 1].f[pr], scale(l), stream),
-                    e0, "residual+restrict");
-    } else {
-        if (!rc) rc = residual(l, pr, false, true);
-        if (!rc) rc = restrict_to(l, pr);
-    }
+    if (!rc) rc = residual_restrict(l, pr);
     if (!rc && neu) rc = project(l + 1, lv[l + 1].f[pr]);
     if (!rc) rc = cycle(l + 1, pr, true, kind);
     if (!rc && l + 2 < L && kind != MG_CYCLE_V)
@@ -1644,19 +1661,9 @@ int mg_apply(mg_ctx* h, int op, int level, int prec) {
         case MG_OP_COARSE:
             if (level != c->L - 1) return c->fail(MG_EINVAL, "not the coarsest level");
             return c->coarse(prec);
-        case MG_OP_RESIDUAL_RESTRICT: {
+        case MG_OP_RESIDUAL_RESTRICT:
             if (!has_next) return c->fail(MG_EINVAL, "no coarser level");
-            if (c->grid.centering == MG_NODE && !c->lv[level].gal && mg::fused_transfers(c->lv[level].g)) {
-                hipEvent_t e0 = c->begin();
-                return c->record(MG_K_RESTRICT, level,
-                                 mg::launch_residual_restrict(c->lv[level].g, c->lv[level + 1].g, prec,
-                                                              c->lv[level].u[prec], c->lv[level].f[prec],
-                                                              c->lv[level + 1].f[prec], c->scale(level), c->stream),
-                                 e0, "residual+restrict");
-            }
-            int rc = c->residual(level, prec, false, true);
-            return rc ? rc : c->restrict_to(level, prec);
-        }
+            return c->residual_restrict(level, prec);
         case MG_OP_VCYCLE:
             if (level < c->L - 1 && !has_next) return c->fail(MG_EINVAL, "no coarser level");
             return c->vcycle(level, prec, false);

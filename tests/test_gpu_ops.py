@@ -208,6 +208,44 @@ def test_repeat_is_bitwise_deterministic(mg):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("case", [("node", 2, 129, "dirichlet", 0), ("node", 2, 129, "dirichlet", 1),
+                                  ("node", 2, 1025, "dirichlet", 0), ("cell", 3, 128, "dirichlet", 0),
+                                  ("cell", 3, 256, "dirichlet", 0), ("cell", 3, 128, "neumann", 0)])
+def test_one_pass_residual_restriction_equals_the_two_ops(mg, case):
+    """The one-pass residual + restriction of 2-D node levels (each coarse
+    point forms its nine fine residuals) and of the finest 3-D cell level
+    (residuals of both colours and two rows per thread, faces from k, summed
+    into the 8-child mean) equal the residual then the restriction bitwise,
+    and the oracle's restriction of its residual."""
+    kind, dim, n, bc, prec = case
+    cent = mg.MG_CELL if kind == "cell" else mg.MG_NODE
+    k = W.varcoef_k(n, dim) if kind == "cell" else None
+    s = mg.Solver(dim, n, centering=cent, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k,
+                  bc=mg.MG_NEUMANN0 if bc == "neumann" else mg.MG_DIRICHLET0,
+                  precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    cflag = 1 if kind == "cell" else 0
+    u = rand(n, dim, cflag, 700 + n, dt)
+    f = rand(n, dim, cflag, 800 + n, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_RESIDUAL_RESTRICT, 0, prec)
+    fused = s.level_get(1, mg.MG_FIELD_F, prec)
+    s.level_set(1, mg.MG_FIELD_F, np.zeros_like(fused).astype(dt), prec)
+    s.apply(mg.MG_OP_RESIDUAL, 0, prec)
+    s.apply(mg.MG_OP_RESTRICT, 0, prec)
+    two = s.level_get(1, mg.MG_FIELD_F, prec)
+    s.close()
+    print(f"one-pass residual+restriction {case}: bitwise {np.array_equal(fused, two)}", flush=True)
+    assert np.array_equal(fused, two)
+    if kind == "cell":
+        beta = cell.harmonic_faces(k)
+        ref = cell.restrict_mean(cell.residual(u, f, beta, bc))
+    else:
+        ref = node.restrict_fw(node.residual(u, f))
+    close(fused, ref.astype(np.float64), prec, f"one-pass residual+restriction {case} vs oracle")
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("n", [33, 129, 257, 513])
 def test_fused_residual_restriction(mg, n, prec):
