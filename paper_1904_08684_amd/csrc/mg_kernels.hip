@@ -1955,6 +1955,69 @@ __device__ __forceinline__ void pt_cell_prolong(const Pt& p, Geom gf, Geom gc, S
     u[me] = u[me] + e;
 }
 
+// Cell-centred interpolation + correction on large 3-D cell levels, one
+// thread per (x >> 1, y) column of one colour marching a chunk of planes.
+// Along the column the fine x parity alternates with z, so plane 2K uses the
+// coarse planes K and K - 1 at one parity and plane 2K + 1 the planes K and
+// K + 1 at the other: each y-interpolated coarse value serves two fine planes
+// and is formed once (half the coarse loads of the point kernel).  Every fine
+// cell takes pt_cell_prolong's operands in its order (bitwise equal).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cell_prolong_zm(Geom gf, Geom gc, ZSpace zs, int colour,
+                                                         T* __restrict__ u, const T* __restrict__ ec) {
+    int tx, ty, tz;
+    zm_tile(zs, (int)blockIdx.x, tx, ty, tz);
+    const int xs = tx * 64 + (int)threadIdx.x;
+    const int y = ty * zs.rows + (int)threadIdx.y;
+    if (xs >= zs.xr || y >= gf.n) return;
+    const int z0 = tz * zs.zc, z1 = min(z0 + zs.zc, gf.n);
+    const int Nc = gc.n;
+    const T a = T(0.75), b = T(0.25);
+    const T sg = gc.neu ? T(1) : T(-1);
+    const int J = y >> 1, Jn = (y & 1) ? J + 1 : J - 1;
+    const bool wJ = Jn < 0 || Jn >= Nc;
+    const int pe = (y + colour) & 1, po = 1 - pe;   // x parity on even and odd planes
+    auto E = [&](int X, int Y, int Z) -> T {
+        return ec[(long long)((X + Y + Z) & 1) * gc.cs + row_off(gc, Y, Z) + (X >> 1)];
+    };
+    // x- then y-interpolated coarse value of plane Z for x parity p
+    auto iyp = [&](int Z, int p) -> T {
+        const int In = p ? xs + 1 : xs - 1;
+        const bool wI = In < 0 || In >= Nc;
+        auto ix = [&](int Y) -> T {
+            const T c0 = E(xs, Y, Z);
+            const T c1 = wI ? sg * c0 : E(In, Y, Z);
+            return a * c0 + b * c1;
+        };
+        const T c0 = ix(J);
+        const T c1 = wJ ? sg * c0 : ix(Jn);
+        return a * c0 + b * c1;
+    };
+    const long long pl = gf.plane;
+    long long ro = (long long)colour * gf.cs + row_off(gf, y, z0) + xs;
+    int K = z0 >> 1;
+    T ecur = iyp(K, pe);
+    T eprev = K >= 1 ? iyp(K - 1, pe) : T(0);
+    T ocur = iyp(K, po);
+    for (int z = z0; z < z1; z += 2, ro += 2 * pl, ++K) {
+        {   // plane 2K: coarse K and K - 1
+            const T c0 = ecur;
+            const T c1 = K - 1 < 0 ? sg * c0 : eprev;
+            u[ro] = u[ro] + (a * c0 + b * c1);
+        }
+        const bool top = K + 1 >= Nc;
+        const T onext = top ? T(0) : iyp(K + 1, po);
+        {   // plane 2K + 1: coarse K and K + 1
+            const T c0 = ocur;
+            const T c1 = top ? sg * c0 : onext;
+            u[ro + pl] = u[ro + pl] + (a * c0 + b * c1);
+        }
+        eprev = ecur;
+        ecur = top ? T(0) : iyp(K + 1, pe);
+        ocur = onext;
+    }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void d_cell_prolong(const Ex& ex, Geom gf, Geom gc, Space sp, T* __restrict__ u,
                                                       const T* __restrict__ ec) {
@@ -3337,6 +3400,14 @@ static hipError_t prolong_t(const Geom& gf, const Geom& gc, void* u, const void*
         for (int c = 0; c < 2; ++c)
             if (mask & (1 << c))
                 k_node_prolong_zm<T><<<dim3((unsigned)zs.blocks()), dim3(64, zs.rows), 0, st>>>(
+                    gf, gc, zs, c, mp<T>(u), cp<T>(ec));
+        return hipGetLastError();
+    }
+    if (gf.cell && gf.dim == 3 && use_cell_zm(gf) && kZChunk % 2 == 0) {
+        const ZSpace zs = make_czspace(gf);
+        for (int c = 0; c < 2; ++c)
+            if (mask & (1 << c))
+                k_cell_prolong_zm<T><<<dim3((unsigned)zs.blocks()), dim3(64, zs.rows), 0, st>>>(
                     gf, gc, zs, c, mp<T>(u), cp<T>(ec));
         return hipGetLastError();
     }

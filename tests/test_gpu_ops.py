@@ -164,6 +164,28 @@ def test_transfers(mg, dim, n, cent, prec):
     s.close()
 
 
+@pytest.mark.parametrize("n,bc,prec", [(128, "dirichlet", 0), (128, "dirichlet", 1), (256, "dirichlet", 0),
+                                       (256, "dirichlet", 1), (128, "neumann", 0)])
+def test_cell_prolongation_on_column_levels(mg, n, bc, prec):
+    """Large 3-D cell levels interpolate along columns (each coarse value
+    formed once for two fine planes): the correction equals the oracle's
+    cell-centred trilinear interpolation with mirror ghosts (Neumann walls
+    are FP64-only)."""
+    k = W.varcoef_k(n, 3)
+    s = mg.Solver(3, n, centering=mg.MG_CELL, smoother=mg.MG_RBGS, nu1=3, nu2=3, k=k,
+                  bc=mg.MG_NEUMANN0 if bc == "neumann" else mg.MG_DIRICHLET0,
+                  precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 3, 1, 900 + n, dt)
+    e = rand(n // 2, 3, 1, 950 + n, dt)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(1, mg.MG_FIELD_U, e, prec)
+    s.apply(mg.MG_OP_PROLONG, 0, prec)
+    got = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.close()
+    close(got, cell.correct(u, e, bc).astype(np.float64), prec, f"cell prolong n={n} {bc} prec={prec}")
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("dim,cent", [(2, 0), (3, 0), (2, 1), (3, 1)])
 def test_coarsest_solve(mg, dim, cent, prec):
