@@ -2772,6 +2772,29 @@ __global__ __launch_bounds__(256) void k_cell_sum(Geom g, Space sp, const double
     block_sum_max(v, 0.0, part + 2 * (long long)ex.b);
 }
 
+// The same per-block sums on large 3-D cell levels: each thread first adds
+// its (x >> 1, y) column of both colours over a chunk of planes (colour 0,
+// then 1, plane by plane), so a block of 256 threads reduces 16 values per
+// thread instead of one and the partials are 16 times fewer.
+__global__ __launch_bounds__(256) void k_cell_sum_zm(Geom g, ZSpace zs, const double* __restrict__ a,
+                                                     double* __restrict__ part) {
+    const Ex ex = solo_ex();
+    int tx, ty, tz;
+    zm_tile(zs, ex.b, tx, ty, tz);
+    const int xs = tx * 64 + (ex.t & 63);
+    const int y = ty * zs.rows + (ex.t >> 6);
+    double v = 0.0;
+    if (xs < zs.xr && y < g.n) {
+        const int z0 = tz * zs.zc, z1 = min(z0 + zs.zc, g.n);
+        long long ro = row_off(g, y, z0) + xs;
+        for (int z = z0; z < z1; ++z, ro += g.plane) {
+            v = v + a[ro];
+            v = v + a[g.cs + ro];
+        }
+    }
+    block_sum_max(v, 0.0, part + 2 * (long long)ex.b);
+}
+
 __global__ __launch_bounds__(256) void k_cell_shift(Geom g, Space sp, double* __restrict__ a,
                                                     const double* __restrict__ sum, double count) {
     Pt p;
@@ -3506,8 +3529,15 @@ hipError_t launch_project(const Geom& g, double* a, double* partials, double* sc
                           hipStream_t st) {
     if (!g.cell) return hipErrorInvalidValue;
     const Space sp = space_of(g, 2, 0);
-    k_cell_sum<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, a, partials);
-    hipError_t e = launch_reduce(partials, sp.blocks(), scratch, out, st);
+    long long nparts = sp.blocks();
+    if (g.dim == 3 && use_cell_zm(g)) {
+        const ZSpace zs = make_czspace(g);
+        nparts = zs.blocks();
+        k_cell_sum_zm<<<(unsigned)zs.blocks(), dim3(64, zs.rows), 0, st>>>(g, zs, a, partials);
+    } else {
+        k_cell_sum<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, a, partials);
+    }
+    hipError_t e = launch_reduce(partials, nparts, scratch, out, st);
     if (e != hipSuccess) return e;
     k_cell_shift<<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, a, out, (double)nat_count(g));
     return hipGetLastError();
