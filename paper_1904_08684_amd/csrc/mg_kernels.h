@@ -66,6 +66,11 @@ hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const
 // The finest 3-D cell level (FP64, faces from k): residual and the mean of
 // the eight children into the coarse f in one pass, bitwise equal to the
 // residual then the restriction.
+// Cell levels with stored face coefficients (fc.b): residual and the 2^d
+// mean into the coarse f in one launch over the coarse cells, bitwise equal
+// to the two operations.
+hipError_t launch_cell_res_restrict_pt(const Geom& gf, const Geom& gc, int prec, const void* u, const void* f,
+                                       const Faces& fc, void* fco, double s, hipStream_t st);
 bool cell_res_restrict_fused(const Geom& gf);
 hipError_t launch_cell_res_restrict(const Geom& gf, const Geom& gc, const void* u, const void* f, const void* k,
                                     void* fco, double s, hipStream_t st);

@@ -1899,6 +1899,30 @@ __device__ __forceinline__ void pt_cell_restrict(const Pt& p, Geom gf, Geom gc, 
     }, fcoarse);
 }
 
+// Residual and the mean of the 2^d children in one launch over the coarse
+// cells of a level with stored face coefficients: each coarse cell forms
+// the residuals of its own children (each fine cell belongs to exactly one
+// coarse cell: no residual is formed twice), with the residual kernel's
+// operands and order, summed as the restriction sums them (bitwise equal to
+// the two kernels; the fine residual is never written).
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_cell_res_restrict_pt(Geom gf, Geom gc, Space sp, const T* __restrict__ u,
+                                                              const T* __restrict__ f, const T* __restrict__ bx,
+                                                              const T* __restrict__ by, const T* __restrict__ bz,
+                                                              T* __restrict__ fcoarse, T s) {
+    Pt p;
+    if (!map_point(solo_ex(), sp, p)) return;
+    pt_cell_restrict_by<T, D>(p, gc, [&](int c, int xs, int y, int z) -> T {
+        Pt q;
+        q.xs = xs;
+        q.y = y;
+        q.z = z;
+        q.c = c;
+        long long me;
+        return pt_cell_residual<T, D>(q, gf, u, f, bx, by, bz, s, me);
+    }, fcoarse);
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void d_cell_restrict(const Ex& ex, Geom gf, Geom gc, Space sp,
                                                        const T* __restrict__ r,
@@ -3391,6 +3415,23 @@ hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const
     if (!fused_point_transfers(gf)) return hipErrorInvalidValue;
     return prec ? prolong_jacobi_t<float>(gf, gc, u, ec, f, out, s, omega, st)
                 : prolong_jacobi_t<double>(gf, gc, u, ec, f, out, s, omega, st);
+}
+
+template <typename T>
+static hipError_t cell_res_restrict_pt_t(const Geom& gf, const Geom& gc, const void* u, const void* f,
+                                         const Faces& fc, void* fco, double s, hipStream_t st) {
+    const Space sp = space_of(gc, 2, 0);
+    MG_DISPATCH_DIM(gf, k_cell_res_restrict_pt<T, D><<<grid_of(sp), block_of(sp), 0, st>>>(
+                            gf, gc, sp, cp<T>(u), cp<T>(f), cp<T>(fc.b[0]), cp<T>(fc.b[1]), cp<T>(fc.b[2]),
+                            mp<T>(fco), (T)s));
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_res_restrict_pt(const Geom& gf, const Geom& gc, int prec, const void* u, const void* f,
+                                       const Faces& fc, void* fco, double s, hipStream_t st) {
+    if (!gf.cell || !fc.b[0] || !fc.b[1] || (gf.dim == 3 && !fc.b[2])) return hipErrorInvalidValue;
+    return prec ? cell_res_restrict_pt_t<float>(gf, gc, u, f, fc, fco, s, st)
+                : cell_res_restrict_pt_t<double>(gf, gc, u, f, fc, fco, s, st);
 }
 
 bool cell_res_restrict_fused(const Geom& gf) { return use_cell_zm(gf) && kZChunk % 2 == 0; }

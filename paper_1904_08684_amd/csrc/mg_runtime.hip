@@ -904,6 +904,15 @@ int Ctx::residual_restrict(int l, int pr) {
                                                lv[l + 1].f[pr], scale(l), stream),
                       e0, what);
     }
+    if (!rec && grid.centering == MG_CELL && !faces(l, pr).k) {
+        // cell levels with stored faces: each coarse cell forms the
+        // residuals of its children
+        hipEvent_t e0 = begin();
+        return record(MG_K_RESTRICT, l,
+                      launch_cell_res_restrict_pt(g, lv[l + 1].g, pr, lv[l].u[pr], lv[l].f[pr], faces(l, pr),
+                                                  lv[l + 1].f[pr], scale(l), stream),
+                      e0, what);
+    }
     if (!rec && grid.centering == MG_NODE && !lv[l].gal && fused_point_transfers(g)) {
         // 2-D point levels: each coarse point forms its fine residuals
         hipEvent_t e0 = begin();
