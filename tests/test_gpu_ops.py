@@ -234,13 +234,14 @@ def test_repeat_is_bitwise_deterministic(mg):
                                   ("node", 2, 1025, "dirichlet", 0), ("cell", 3, 128, "dirichlet", 0),
                                   ("cell", 3, 256, "dirichlet", 0), ("cell", 3, 128, "neumann", 0),
                                   ("cell", 3, 128, "dirichlet", 1), ("cell", 3, 32, "neumann", 0),
-                                  ("cell", 2, 128, "dirichlet", 0), ("cell", 2, 64, "dirichlet", 1)])
+                                  ("cell", 3, 64, "dirichlet", 1), ("cell", 2, 64, "dirichlet", 0),
+                                  ("cell", 2, 32, "dirichlet", 1)])
 def test_one_pass_residual_restriction_equals_the_two_ops(mg, case):
     """The one-pass residual + restriction of 2-D node levels (each coarse
     point forms its nine fine residuals), of the finest 3-D cell level
     (residuals of both colours and two rows per thread, faces from k, summed
-    into the 8-child mean) and of cell levels with stored faces (FP32, 2-D,
-    small 3-D: each coarse cell forms its children's residuals) equal the
+    into the 8-child mean) and of small cell levels with stored faces
+    (each coarse cell forms its children's residuals) equal the
     residual then the restriction bitwise, and the oracle's restriction of
     its residual."""
     kind, dim, n, bc, prec = case
