@@ -1223,10 +1223,18 @@ __global__ __launch_bounds__(256) void k_node_prolong_zm(Geom gf, Geom gc, ZSpac
     };
     int Zlo = z0 >> 1;
     T lo_e, lo_o, hi_e, hi_o;
+    const long long ro0 = row_off(gf, y, z0) + xs + (long long)colour * gf.cs;
+    // the column's iterate for the whole chunk, loaded before any store
+    // (the loads of later planes would otherwise wait behind earlier stores)
+    T uv[kZChunk];
+#pragma unroll
+    for (int k = 0; k < kZChunk; ++k) uv[k] = z0 + k < z1 ? u[ro0 + k * gf.plane] : T(0);
     plane(Zlo, lo_e, lo_o);
     plane(Zlo + 1, hi_e, hi_o);
-    long long ro = row_off(gf, y, z0) + xs + (long long)colour * gf.cs;
-    for (int z = z0; z < z1; ++z, ro += gf.plane) {
+#pragma unroll
+    for (int k = 0; k < kZChunk; ++k) {
+        const int z = z0 + k;
+        if (z >= z1) break;
         const int Zc = z >> 1;
         if (Zc != Zlo) {   // advance the two-plane window by one coarse plane
             lo_e = hi_e;
@@ -1238,7 +1246,7 @@ __global__ __launch_bounds__(256) void k_node_prolong_zm(Geom gf, Geom gc, ZSpac
         if (par | xs) {
             const T v0 = par ? lo_o : lo_e;
             const T e = (z & 1) ? half * (v0 + (par ? hi_o : hi_e)) : v0;
-            u[ro] = u[ro] + e;
+            u[ro0 + k * gf.plane] = uv[k] + e;
         }
     }
 }
@@ -2018,23 +2026,29 @@ __global__ __launch_bounds__(256) void k_cell_prolong_zm(Geom gf, Geom gc, ZSpac
         return a * c0 + b * c1;
     };
     const long long pl = gf.plane;
-    long long ro = (long long)colour * gf.cs + row_off(gf, y, z0) + xs;
+    const long long ro0 = (long long)colour * gf.cs + row_off(gf, y, z0) + xs;
+    // the column's iterate for the whole chunk, loaded before any store
+    T uv[kZChunk];
+#pragma unroll
+    for (int k = 0; k < kZChunk; ++k) uv[k] = z0 + k < z1 ? u[ro0 + k * pl] : T(0);
     int K = z0 >> 1;
     T ecur = iyp(K, pe);
     T eprev = K >= 1 ? iyp(K - 1, pe) : T(0);
     T ocur = iyp(K, po);
-    for (int z = z0; z < z1; z += 2, ro += 2 * pl, ++K) {
+#pragma unroll
+    for (int k = 0; k < kZChunk; k += 2, ++K) {
+        if (z0 + k >= z1) break;
         {   // plane 2K: coarse K and K - 1
             const T c0 = ecur;
             const T c1 = K - 1 < 0 ? sg * c0 : eprev;
-            u[ro] = u[ro] + (a * c0 + b * c1);
+            u[ro0 + k * pl] = uv[k] + (a * c0 + b * c1);
         }
         const bool top = K + 1 >= Nc;
         const T onext = top ? T(0) : iyp(K + 1, po);
         {   // plane 2K + 1: coarse K and K + 1
             const T c0 = ocur;
             const T c1 = top ? sg * c0 : onext;
-            u[ro + pl] = u[ro + pl] + (a * c0 + b * c1);
+            u[ro0 + (k + 1) * pl] = uv[k + 1] + (a * c0 + b * c1);
         }
         eprev = ecur;
         ecur = top ? T(0) : iyp(K + 1, pe);
