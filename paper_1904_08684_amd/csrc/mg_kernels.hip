@@ -125,34 +125,6 @@ __device__ __forceinline__ T node_nb(const T* __restrict__ o, long long ro, int 
     return nb;
 }
 
-template <typename T, int D, bool ZERO>
-__device__ __forceinline__ void pt_node_gs(const Pt& p, Geom g, Space sp, T* __restrict__ me,
-                                                 const T* __restrict__ other, const T* __restrict__ f,
-                                                 T s) {
-    const int par = (p.y + p.z + p.c) & 1;
-    const int x = 2 * p.xs + par;
-    if (x < 1 || x > g.n - 2) return;
-    const long long ro = row_off(g, p.y, p.z) + p.xs;
-    const T nb = ZERO ? T(0) : node_nb<T, D>(other, ro, par, g);
-    me[ro] = (f[ro] / s + nb) / T(2 * D);
-}
-
-template <typename T, int D, bool ZERO>
-__device__ __forceinline__ void d_node_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
-                                                 const T* __restrict__ other, const T* __restrict__ f,
-                                                 T s) {
-    Pt p;
-    if (!map_point(ex, sp, p)) return;
-    pt_node_gs<T, D, ZERO>(p, g, sp, me, other, f, s);
-}
-
-template <typename T, int D, bool ZERO>
-__global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict__ me,
-                                                 const T* __restrict__ other, const T* __restrict__ f,
-                                                 T s) {
-    d_node_gs<T, D, ZERO>(solo_ex(), g, sp, me, other, f, s);
-}
-
 // a / 6 correctly rounded with one multiply and two FMAs (Markstein's
 // correction step): q0 = a y with y = RN(1/6) is faithful, r = a - 6 q0 is
 // exact, and RN(q0 + r y) is then the correctly rounded quotient.  Equal to
@@ -168,6 +140,45 @@ __device__ __forceinline__ float div6(float a) {
     constexpr float y = 1.0f / 6.0f;
     const float q0 = a * y;
     return __builtin_fmaf(__builtin_fmaf(-q0, 6.0f, a), y, q0);
+}
+
+// (f / s + nb) / (2 D), the Gauss-Seidel update.  P2: s is a power of two
+// and rs = 1 / s, so f / s = f rs exactly and the division by 2D is a
+// multiplication by 1/4 (2-D) or Markstein's division by 6 (3-D): the same
+// rounding without the division sequences (away from the subnormal range).
+template <typename T, int D, bool P2>
+__device__ __forceinline__ T gs_value(T fv, T nb, T s, T rs) {
+    if constexpr (P2 && D == 2) return (fv * rs + nb) * T(0.25);
+    else if constexpr (P2 && D == 3) return div6(fv * rs + nb);
+    else return (fv / s + nb) / T(2 * D);
+}
+
+template <typename T, int D, bool ZERO, bool P2 = false>
+__device__ __forceinline__ void pt_node_gs(const Pt& p, Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 T s, T rs = T(0)) {
+    const int par = (p.y + p.z + p.c) & 1;
+    const int x = 2 * p.xs + par;
+    if (x < 1 || x > g.n - 2) return;
+    const long long ro = row_off(g, p.y, p.z) + p.xs;
+    const T nb = ZERO ? T(0) : node_nb<T, D>(other, ro, par, g);
+    me[ro] = gs_value<T, D, P2>(f[ro], nb, s, rs);
+}
+
+template <typename T, int D, bool ZERO, bool P2 = false>
+__device__ __forceinline__ void d_node_gs(const Ex& ex, Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 T s, T rs = T(0)) {
+    Pt p;
+    if (!map_point(ex, sp, p)) return;
+    pt_node_gs<T, D, ZERO, P2>(p, g, sp, me, other, f, s, rs);
+}
+
+template <typename T, int D, bool ZERO, bool P2>
+__global__ __launch_bounds__(256) void k_node_gs(Geom g, Space sp, T* __restrict__ me,
+                                                 const T* __restrict__ other, const T* __restrict__ f,
+                                                 T s, T rs) {
+    d_node_gs<T, D, ZERO, P2>(solo_ex(), g, sp, me, other, f, s, rs);
 }
 
 // (omega r) / (2 D s).  P2: s is a power of two and rs = 1 / s (exact), so
@@ -277,10 +288,10 @@ __device__ __forceinline__ void st_stream(T* p, T v) {
 // z-1, z, z+1 stays in registers while it walks its planes, U planes at a
 // time so that U planes of loads are in flight per thread.  f and the
 // updated colour are pure streams (NT: non-temporal).
-template <typename T, int U, bool NT>
+template <typename T, int U, bool NT, bool P2 = false>
 __device__ __forceinline__ void d_node_gs_zm(const Ex& ex, Geom g, ZSpace zs, T* __restrict__ me,
                                                      const T* __restrict__ other,
-                                                     const T* __restrict__ f, T s, int colour) {
+                                                     const T* __restrict__ f, T s, int colour, T rs = T(0)) {
     int tx, ty, tz;
     zm_tile(zs, ex.b, tx, ty, tz);
     const int xs = tx * 64 + (ex.t & 63);
@@ -319,7 +330,7 @@ __device__ __forceinline__ void d_node_gs_zm(const Ex& ex, Geom g, ZSpace zs, T*
                 nb = nb + yp[k];
                 nb = nb + zv[k];
                 nb = nb + zv[k + 2];
-                st_stream<NT>(me + ro + k * pl, (fv[k] / s + nb) / T(6));
+                st_stream<NT>(me + ro + k * pl, gs_value<T, 3, P2>(fv[k], nb, s, rs));
             }
         }
     }
@@ -337,18 +348,18 @@ __device__ __forceinline__ void d_node_gs_zm(const Ex& ex, Geom g, ZSpace zs, T*
             nb = nb + yp;
             nb = nb + om;
             nb = nb + op;
-            st_stream<NT>(me + ro, (ld_stream<NT>(f + ro) / s + nb) / T(6));
+            st_stream<NT>(me + ro, gs_value<T, 3, P2>(ld_stream<NT>(f + ro), nb, s, rs));
         }
         om = oc;
         oc = op;
     }
 }
 
-template <typename T, int U, bool NT>
+template <typename T, int U, bool NT, bool P2>
 __global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __restrict__ me,
                                                      const T* __restrict__ other,
-                                                     const T* __restrict__ f, T s, int colour) {
-    d_node_gs_zm<T, U, NT>(solo_ex(), g, zs, me, other, f, s, colour);
+                                                     const T* __restrict__ f, T s, int colour, T rs) {
+    d_node_gs_zm<T, U, NT, P2>(solo_ex(), g, zs, me, other, f, s, colour, rs);
 }
 
 // r = f - A u at both colours of the thread's column; both colours' z-1, z,
@@ -2219,6 +2230,7 @@ __device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sw
                             bool first_done = false) {
     const Geom g = P.lg[i];
     const T s = (T)P.s[i];
+    const T rs = (T)P.rs[i];   // exact when P.p2
     const T* f = A + P.of[i];
     const T* bx = static_cast<const T*>(P.beta[i][0]);
     const T* by = static_cast<const T*>(P.beta[i][1]);
@@ -2246,9 +2258,15 @@ __device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sw
                         });
                 } else {
                     if (z && h == 0)
-                        tail_points(sp, [&](const Pt& p) { pt_node_gs<T, D, true>(p, g, sp, me, other, fc, s); });
+                        tail_points(sp, [&](const Pt& p) {
+                            if (P.p2) pt_node_gs<T, D, true, true>(p, g, sp, me, other, fc, s, rs);
+                            else pt_node_gs<T, D, true>(p, g, sp, me, other, fc, s);
+                        });
                     else
-                        tail_points(sp, [&](const Pt& p) { pt_node_gs<T, D, false>(p, g, sp, me, other, fc, s); });
+                        tail_points(sp, [&](const Pt& p) {
+                            if (P.p2) pt_node_gs<T, D, false, true>(p, g, sp, me, other, fc, s, rs);
+                            else pt_node_gs<T, D, false>(p, g, sp, me, other, fc, s);
+                        });
                 }
                 __syncthreads();
             }
@@ -2266,7 +2284,6 @@ __device__ void tail_smooth(const TailPlan& P, T* A, unsigned& sw, int i, int sw
                         pt_cell_jacobi<T, D, false>(p, g, sp, u, f, out, bx, by, bz, s, om);
                     });
             } else {
-                const T rs = (T)P.rs[i];
                 if (P.p2) {
                     if (z)
                         tail_points(sp, [&](const Pt& p) {
@@ -2380,7 +2397,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailPlan P, const T* __re
                 }, fco);
                 if (!in || !pre) return;
                 if (P.rbgs) {
-                    if (p.c == 0) pt_node_gs<T, D, true>(p, gc, sc, uc, uc + gc.cs, fco, sc1);
+                    if (p.c == 0) {
+                        if (P.p2) pt_node_gs<T, D, true, true>(p, gc, sc, uc, uc + gc.cs, fco, sc1, (T)P.rs[i + 1]);
+                        else pt_node_gs<T, D, true>(p, gc, sc, uc, uc + gc.cs, fco, sc1);
+                    }
                 } else {
                     if (P.p2) pt_node_jacobi<T, D, true, true>(p, gc, sc, uc, fco, oc, sc1, om, (T)P.rs[i + 1]);
                     else pt_node_jacobi<T, D, true>(p, gc, sc, uc, fco, oc, sc1, om);
@@ -3119,15 +3139,31 @@ static hipError_t gs_t(const Geom& g, int colour, bool zero, void* u, const void
         const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
         // planes in flight per thread: 2 x 8 B (FP64) or 4 x 4 B (FP32) columns
         constexpr int U = sizeof(T) == 8 ? 2 : 4;
-        if (streams_from_hbm(g, sizeof(T)))
-            k_node_gs_zm<T, U, true><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour);
-        else
-            k_node_gs_zm<T, U, false><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour);
+        const bool nt = streams_from_hbm(g, sizeof(T)), p2 = pow2_scale(s);
+        const T rs = (T)(1.0 / s);
+        if (nt && p2) k_node_gs_zm<T, U, true, true><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour, rs);
+        else if (nt) k_node_gs_zm<T, U, true, false><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour, rs);
+        else if (p2) k_node_gs_zm<T, U, false, true><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour, rs);
+        else k_node_gs_zm<T, U, false, false><<<grid, block, 0, st>>>(g, zs, me, other, fm, (T)s, colour, rs);
     } else {
-        MG_DISPATCH_DIM(g, if (zero) k_node_gs<T, D, true><<<grid_of(sp), block_of(sp), 0, st>>>(
-                               g, sp, me, other, fm, (T)s);
-                           else k_node_gs<T, D, false><<<grid_of(sp), block_of(sp), 0, st>>>(
-                               g, sp, me, other, fm, (T)s));
+        const T rs = (T)(1.0 / s);
+#define MG_NGS(Z, P)                                                                                   \
+    MG_DISPATCH_DIM(g, k_node_gs<T, D, Z, P><<<grid_of(sp), block_of(sp), 0, st>>>(g, sp, me, other, fm, \
+                                                                                (T)s, rs))
+        if (pow2_scale(s)) {
+            if (zero) {
+                MG_NGS(true, true);
+            } else {
+                MG_NGS(false, true);
+            }
+        } else {
+            if (zero) {
+                MG_NGS(true, false);
+            } else {
+                MG_NGS(false, false);
+            }
+        }
+#undef MG_NGS
     }
     return hipGetLastError();
 }
