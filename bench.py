@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
