@@ -1439,6 +1439,65 @@ __global__ __launch_bounds__(256) void k_node_prolong_jacobi(Geom gf, Geom gc, S
     out[me] = uc + jacobi_step<T, D, P2>(omega * r, s, rs);
 }
 
+// Two damped-Jacobi sweeps of a 2-D node level in one launch.  A block owns
+// a tile of kJ2 x kJ2 nodes: it loads the iterate (natural layout, from
+// zero when ZERO; with PRO the iterate corrected by the interpolated coarse
+// error, formed as the prolongation forms it) and f on the tile with a halo
+// of two into LDS, runs the first sweep on the tile and one ring of halo and
+// the second on the tile, and writes the tile to out.  Every point takes the
+// point kernels' operands in their order, so out is bitwise what the
+// separate launches (prolongation, then two sweeps) give; boundary nodes
+// are neither updated nor written.
+constexpr int kJ2 = 16;
+
+template <typename T, bool P2, bool ZERO, bool PRO>
+__global__ __launch_bounds__(256) void k_node_jacobi2(Geom g, Geom gc, int ntx, const T* __restrict__ u,
+                                                      const T* __restrict__ ec, const T* __restrict__ f,
+                                                      T* __restrict__ out, T s, T omega, T rs) {
+    constexpr int H = 2, L = kJ2 + 2 * H;
+    __shared__ T a[L][L + 1], b[L][L + 1], ff[L][L + 1];
+    const int blk = (int)blockIdx.x;
+    const int x0 = (blk % ntx) * kJ2 - H, y0 = (blk / ntx) * kJ2 - H;
+    const int n = g.n;
+    auto at = [&](int x, int y) -> long long {
+        return (long long)((x + y) & 1) * g.cs + row_off(g, y, 0) + (x >> 1);
+    };
+    auto interior = [&](int x, int y) { return x >= 1 && x <= n - 2 && y >= 1 && y <= n - 2; };
+    for (int i = (int)threadIdx.x; i < L * L; i += 256) {
+        const int ly = i / L, lx = i % L, x = x0 + lx, y = y0 + ly;
+        T uv = T(0), fv = T(0);
+        if (x >= 0 && x < n && y >= 0 && y < n) {
+            if (PRO) uv = node_corrected<T, 2>(g, gc, u, ec, x, y, 0);
+            else if (!ZERO) uv = u[at(x, y)];
+            fv = f[at(x, y)];
+        }
+        a[ly][lx] = uv;
+        ff[ly][lx] = fv;
+    }
+    __syncthreads();
+    // (x - 1, x + 1, y - 1, y + 1: the order of the point kernels)
+    auto sweep = [&](T (*src)[L + 1], int ly, int lx) -> T {
+        T nb = src[ly][lx - 1];
+        nb = nb + src[ly][lx + 1];
+        nb = nb + src[ly - 1][lx];
+        nb = nb + src[ly + 1][lx];
+        const T uc = src[ly][lx];
+        const T r = ff[ly][lx] - (T(4) * uc - nb) * s;
+        return uc + jacobi_step<T, 2, P2>(omega * r, s, rs);
+    };
+    for (int i = (int)threadIdx.x; i < (L - 2) * (L - 2); i += 256) {
+        const int ly = 1 + i / (L - 2), lx = 1 + i % (L - 2);
+        // (off the unknowns the first sweep's output holds zero, as the
+        // second buffer of the separate sweeps does)
+        b[ly][lx] = interior(x0 + lx, y0 + ly) ? sweep(a, ly, lx) : T(0);
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < kJ2 * kJ2; i += 256) {
+        const int ly = H + i / kJ2, lx = H + i % kJ2, x = x0 + lx, y = y0 + ly;
+        if (interior(x, y)) out[at(x, y)] = sweep(b, ly, lx);
+    }
+}
+
 // ------------------------------------------------------------ cell grids
 // Face-coefficient sums of one cell: diag = sum of w_f beta_f (w_f = 2 on
 // walls) and, unless ZERO, off = sum of beta_f u_neighbour over interior
@@ -3465,6 +3524,38 @@ hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const
     if (!fused_point_transfers(gf)) return hipErrorInvalidValue;
     return prec ? prolong_jacobi_t<float>(gf, gc, u, ec, f, out, s, omega, st)
                 : prolong_jacobi_t<double>(gf, gc, u, ec, f, out, s, omega, st);
+}
+
+template <typename T>
+static hipError_t jacobi2_t(const Geom& g, const Geom* gc, bool zero, const void* u, const void* ec, const void* f,
+                            void* out, double s, double omega, hipStream_t st) {
+    const int ntx = (g.n + kJ2 - 1) / kJ2;
+    const unsigned nb = (unsigned)(ntx * ntx);
+    const T rs = (T)(1.0 / s);
+    const Geom gcc = gc ? *gc : g;
+#define MG_J2(P, Z, R)                                                                                     \
+    k_node_jacobi2<T, P, Z, R><<<nb, 256, 0, st>>>(g, gcc, ntx, cp<T>(u), cp<T>(ec), cp<T>(f), mp<T>(out), \
+                                                   (T)s, (T)omega, rs)
+    const bool p2 = pow2_scale(s);
+    if (gc) {
+        if (p2) MG_J2(true, false, true);
+        else MG_J2(false, false, true);
+    } else if (zero) {
+        if (p2) MG_J2(true, true, false);
+        else MG_J2(false, true, false);
+    } else {
+        if (p2) MG_J2(true, false, false);
+        else MG_J2(false, false, false);
+    }
+#undef MG_J2
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi2(const Geom& g, const Geom* gc, int prec, bool zero, const void* u, const void* ec,
+                          const void* f, void* out, double s, double omega, hipStream_t st) {
+    if (!fused_point_transfers(g) || (gc && (zero || !ec))) return hipErrorInvalidValue;
+    return prec ? jacobi2_t<float>(g, gc, zero, u, ec, f, out, s, omega, st)
+                : jacobi2_t<double>(g, gc, zero, u, ec, f, out, s, omega, st);
 }
 
 template <typename T>

@@ -587,6 +587,19 @@ int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
             done += k;
         }
     }
+    if (opts.smoother == MG_JACOBI && !rec && grid.centering == MG_NODE && !L.gal && L.utmp[pr] &&
+        fused_point_transfers(L.g)) {
+        // 2-D point levels: two sweeps per launch (tiles with a halo of two)
+        for (; done + 2 <= sweeps; done += 2) {
+            hipEvent_t e0 = begin();
+            int rc = record(MG_K_SMOOTH, l,
+                            launch_jacobi2(L.g, nullptr, pr, from_zero && done == 0, L.u[pr], nullptr, L.f[pr],
+                                           L.utmp[pr], scale(l), opts.omega, stream),
+                            e0, "jacobi x2");
+            if (rc) return rc;
+            std::swap(L.u[pr], L.utmp[pr]);
+        }
+    }
     for (int k = done; k < sweeps; ++k) {
         const bool z = from_zero && k == 0;
         int rc;
@@ -946,16 +959,19 @@ int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     Level& F = lv[l];
     if (!rec && opts.smoother == MG_JACOBI && opts.nu2 > 0 && grid.centering == MG_NODE && !F.gal && F.utmp[pr] &&
         fused_point_transfers(F.g)) {
-        // 2-D point levels: the first post-smoothing sweep reads the
+        // 2-D point levels: the first post-smoothing sweep (or two) reads the
         // corrected iterate as the interpolation forms it
+        const int k = opts.nu2 >= 2 ? 2 : 1;
         hipEvent_t e0 = begin();
         rc = record(MG_K_SMOOTH, l,
-                    launch_prolong_jacobi(F.g, lv[l + 1].g, pr, F.u[pr], lv[l + 1].u[pr], F.f[pr], F.utmp[pr],
-                                          scale(l), opts.omega, stream),
+                    k == 2 ? launch_jacobi2(F.g, &lv[l + 1].g, pr, false, F.u[pr], lv[l + 1].u[pr], F.f[pr],
+                                            F.utmp[pr], scale(l), opts.omega, stream)
+                           : launch_prolong_jacobi(F.g, lv[l + 1].g, pr, F.u[pr], lv[l + 1].u[pr], F.f[pr],
+                                                   F.utmp[pr], scale(l), opts.omega, stream),
                     e0, "prolong+jacobi");
         if (rc) return rc;
         std::swap(F.u[pr], F.utmp[pr]);
-        rc = smooth(l, pr, opts.nu2 - 1, false, opts.post_order);
+        rc = smooth(l, pr, opts.nu2 - k, false, opts.post_order);
     } else {
         rc = prolong(l, pr, mask);
         if (!rc) rc = smooth(l, pr, opts.nu2, false, opts.post_order);

@@ -89,6 +89,35 @@ def test_smoothers_and_residual(mg, dim, n, cent, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n,nu", [(129, 2), (129, 3), (257, 2), (97, 2), (1025, 4)])
+def test_two_jacobi_sweeps_per_launch_equal_single_sweeps(mg, n, nu, prec):
+    """On 2-D levels a smoothing step runs two damped-Jacobi sweeps per
+    launch (tiles with a halo of two in LDS): bitwise equal to the same
+    number of single sweeps, at power-of-two (129, 257, 1025) and other (97)
+    scales, and to the oracle's sweeps."""
+    s = mg.Solver(2, n, coarsest=4 if n == 97 else 5, smoother=mg.MG_JACOBI, omega=0.8, nu1=nu, nu2=nu,
+                  precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 2, 0, 1300 + n, dt)
+    f = rand(n, 2, 0, 1400 + n, dt) * dt(n * n)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_PRESMOOTH, 0, prec)
+    fused = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    for _ in range(nu):
+        s.apply(mg.MG_OP_JACOBI, 0, prec)
+    single = s.level_get(0, mg.MG_FIELD_U, prec)
+    s.close()
+    print(f"two sweeps per launch n={n} nu={nu} prec={prec}: bitwise {np.array_equal(fused, single)}", flush=True)
+    assert np.array_equal(fused, single)
+    ref = u.copy()
+    for _ in range(nu):
+        ref = node.jacobi(ref, f, 0.8)
+    assert np.array_equal(fused, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("dim,n", [(2, 65), (2, 97), (3, 33), (3, 49)])
 def test_jacobi_sweep_bitwise_at_both_kinds_of_scale(mg, dim, n, prec):
     """A damped-Jacobi sweep equals the oracle's (omega r) / (2d s) bitwise
