@@ -64,11 +64,12 @@ hipError_t launch_residual_restrict_pt(const Geom& gf, const Geom& gc, int prec,
 hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const void* u, const void* ec,
                                  const void* f, void* out, double s, double omega, hipStream_t st);
 // Two damped-Jacobi sweeps of a 2-D point level in one launch (u -> out, out
-// of place; zero: from a zero iterate; gc non-null: the iterate is first
-// corrected by the interpolation of the coarse error ec), bitwise equal to
-// the separate operations.
+// of place; zero: from a zero iterate; ec non-null: the iterate is first
+// corrected by the interpolation of the coarse error ec of level gc; fco
+// non-null: the residual after the sweeps is also restricted into level
+// gc's right-hand side fco), bitwise equal to the separate operations.
 hipError_t launch_jacobi2(const Geom& g, const Geom* gc, int prec, bool zero, const void* u, const void* ec,
-                          const void* f, void* out, double s, double omega, hipStream_t st);
+                          const void* f, void* out, void* fco, double s, double omega, hipStream_t st);
 // The finest 3-D cell level (FP64, faces from k): residual and the mean of
 // the eight children into the coarse f in one pass, bitwise equal to the
 // residual then the restriction.

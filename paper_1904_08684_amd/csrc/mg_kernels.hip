@@ -1444,20 +1444,28 @@ __global__ __launch_bounds__(256) void k_node_prolong_jacobi(Geom gf, Geom gc, S
 // zero when ZERO; with PRO the iterate corrected by the interpolated coarse
 // error, formed as the prolongation forms it) and f on the tile with a halo
 // of two into LDS, runs the first sweep on the tile and one ring of halo and
-// the second on the tile, and writes the tile to out.  Every point takes the
-// point kernels' operands in their order, so out is bitwise what the
-// separate launches (prolongation, then two sweeps) give; boundary nodes
-// are neither updated nor written.
+// the second on the tile, and writes the tile to out.  RR (a halo of four):
+// the sweeps cover three and two rings, the residual is formed on the tile
+// and one ring, and the block's coarse points (the even nodes of its tile)
+// restrict it into fco with the full weighting's order.  Every point takes
+// the point kernels' operands in their order, so out (and fco) are bitwise
+// what the separate launches give; boundary nodes are neither updated nor
+// written.
 constexpr int kJ2 = 16;
 
-template <typename T, bool P2, bool ZERO, bool PRO>
+template <typename T, bool P2, bool ZERO, bool PRO, bool RR>
 __global__ __launch_bounds__(256) void k_node_jacobi2(Geom g, Geom gc, int ntx, const T* __restrict__ u,
                                                       const T* __restrict__ ec, const T* __restrict__ f,
-                                                      T* __restrict__ out, T s, T omega, T rs) {
-    constexpr int H = 2, L = kJ2 + 2 * H;
+                                                      T* __restrict__ out, T* __restrict__ fco, T s, T omega,
+                                                      T rs) {
+    // RR: the restriction reads residuals on one ring around the tile, which
+    // read the second sweep on two rings, which reads the first on three
+    constexpr int H = RR ? 4 : 2, L = kJ2 + 2 * H;
     __shared__ T a[L][L + 1], b[L][L + 1], ff[L][L + 1];
+    __shared__ T rr[RR ? L : 1][RR ? L + 1 : 1];
     const int blk = (int)blockIdx.x;
-    const int x0 = (blk % ntx) * kJ2 - H, y0 = (blk / ntx) * kJ2 - H;
+    const int tx0 = (blk % ntx) * kJ2, ty0 = (blk / ntx) * kJ2;
+    const int x0 = tx0 - H, y0 = ty0 - H;
     const int n = g.n;
     auto at = [&](int x, int y) -> long long {
         return (long long)((x + y) & 1) * g.cs + row_off(g, y, 0) + (x >> 1);
@@ -1475,26 +1483,61 @@ __global__ __launch_bounds__(256) void k_node_jacobi2(Geom g, Geom gc, int ntx, 
         ff[ly][lx] = fv;
     }
     __syncthreads();
-    // (x - 1, x + 1, y - 1, y + 1: the order of the point kernels)
-    auto sweep = [&](T (*src)[L + 1], int ly, int lx) -> T {
+    // the residual at a node from src (x - 1, x + 1, y - 1, y + 1: the order
+    // of the point kernels), and the sweep's value from it
+    auto resid = [&](T (*src)[L + 1], int ly, int lx) -> T {
         T nb = src[ly][lx - 1];
         nb = nb + src[ly][lx + 1];
         nb = nb + src[ly - 1][lx];
         nb = nb + src[ly + 1][lx];
-        const T uc = src[ly][lx];
-        const T r = ff[ly][lx] - (T(4) * uc - nb) * s;
-        return uc + jacobi_step<T, 2, P2>(omega * r, s, rs);
+        return ff[ly][lx] - (T(4) * src[ly][lx] - nb) * s;
     };
+    auto sweep = [&](T (*src)[L + 1], int ly, int lx) -> T {
+        return src[ly][lx] + jacobi_step<T, 2, P2>(omega * resid(src, ly, lx), s, rs);
+    };
+    // first sweep on the tile and H - 1 rings (off the unknowns its output
+    // holds zero, as the second buffer of the separate sweeps does)
     for (int i = (int)threadIdx.x; i < (L - 2) * (L - 2); i += 256) {
         const int ly = 1 + i / (L - 2), lx = 1 + i % (L - 2);
-        // (off the unknowns the first sweep's output holds zero, as the
-        // second buffer of the separate sweeps does)
         b[ly][lx] = interior(x0 + lx, y0 + ly) ? sweep(a, ly, lx) : T(0);
     }
     __syncthreads();
-    for (int i = (int)threadIdx.x; i < kJ2 * kJ2; i += 256) {
-        const int ly = H + i / kJ2, lx = H + i % kJ2, x = x0 + lx, y = y0 + ly;
-        if (interior(x, y)) out[at(x, y)] = sweep(b, ly, lx);
+    if constexpr (!RR) {
+        for (int i = (int)threadIdx.x; i < kJ2 * kJ2; i += 256) {
+            const int ly = H + i / kJ2, lx = H + i % kJ2, x = x0 + lx, y = y0 + ly;
+            if (interior(x, y)) out[at(x, y)] = sweep(b, ly, lx);
+        }
+    } else {
+        // second sweep on the tile and two rings (into a, which is no longer
+        // read), writing the tile
+        for (int i = (int)threadIdx.x; i < (L - 4) * (L - 4); i += 256) {
+            const int ly = 2 + i / (L - 4), lx = 2 + i % (L - 4), x = x0 + lx, y = y0 + ly;
+            const bool in = interior(x, y);
+            const T v = in ? sweep(b, ly, lx) : T(0);
+            a[ly][lx] = v;
+            if (in && ly >= H && ly < H + kJ2 && lx >= H && lx < H + kJ2) out[at(x, y)] = v;
+        }
+        __syncthreads();
+        for (int i = (int)threadIdx.x; i < (L - 6) * (L - 6); i += 256) {
+            const int ly = 3 + i / (L - 6), lx = 3 + i % (L - 6);
+            rr[ly][lx] = interior(x0 + lx, y0 + ly) ? resid(a, ly, lx) : T(0);
+        }
+        __syncthreads();
+        // coarse points X, Y with 2X, 2Y on the tile
+        const int t = (int)threadIdx.x;
+        if (t < (kJ2 / 2) * (kJ2 / 2)) {
+            const int X = tx0 / 2 + t % (kJ2 / 2), Y = ty0 / 2 + t / (kJ2 / 2);
+            Pt p;
+            p.y = Y;
+            p.z = 0;
+            p.c = (X + Y) & 1;
+            p.xs = X >> 1;
+            if (Y >= 1 && Y <= gc.n - 2)
+                pt_node_restrict_by<T, 2>(p, gc, [&](int c, int xs, int y, int z) -> T {
+                    const int x = 2 * xs + ((y + z + c) & 1);
+                    return rr[y - y0][x - x0];
+                }, fco);
+        }
     }
 }
 
@@ -3528,34 +3571,42 @@ hipError_t launch_prolong_jacobi(const Geom& gf, const Geom& gc, int prec, const
 
 template <typename T>
 static hipError_t jacobi2_t(const Geom& g, const Geom* gc, bool zero, const void* u, const void* ec, const void* f,
-                            void* out, double s, double omega, hipStream_t st) {
+                            void* out, void* fco, double s, double omega, hipStream_t st) {
     const int ntx = (g.n + kJ2 - 1) / kJ2;
     const unsigned nb = (unsigned)(ntx * ntx);
     const T rs = (T)(1.0 / s);
     const Geom gcc = gc ? *gc : g;
-#define MG_J2(P, Z, R)                                                                                     \
-    k_node_jacobi2<T, P, Z, R><<<nb, 256, 0, st>>>(g, gcc, ntx, cp<T>(u), cp<T>(ec), cp<T>(f), mp<T>(out), \
-                                                   (T)s, (T)omega, rs)
+#define MG_J2(P, Z, R, Q)                                                                                      \
+    k_node_jacobi2<T, P, Z, R, Q><<<nb, 256, 0, st>>>(g, gcc, ntx, cp<T>(u), cp<T>(ec), cp<T>(f), mp<T>(out), \
+                                                      mp<T>(fco), (T)s, (T)omega, rs)
     const bool p2 = pow2_scale(s);
-    if (gc) {
-        if (p2) MG_J2(true, false, true);
-        else MG_J2(false, false, true);
+    if (fco) {   // sweeps, residual and restriction
+        if (zero) {
+            if (p2) MG_J2(true, true, false, true);
+            else MG_J2(false, true, false, true);
+        } else {
+            if (p2) MG_J2(true, false, false, true);
+            else MG_J2(false, false, false, true);
+        }
+    } else if (ec) {
+        if (p2) MG_J2(true, false, true, false);
+        else MG_J2(false, false, true, false);
     } else if (zero) {
-        if (p2) MG_J2(true, true, false);
-        else MG_J2(false, true, false);
+        if (p2) MG_J2(true, true, false, false);
+        else MG_J2(false, true, false, false);
     } else {
-        if (p2) MG_J2(true, false, false);
-        else MG_J2(false, false, false);
+        if (p2) MG_J2(true, false, false, false);
+        else MG_J2(false, false, false, false);
     }
 #undef MG_J2
     return hipGetLastError();
 }
 
 hipError_t launch_jacobi2(const Geom& g, const Geom* gc, int prec, bool zero, const void* u, const void* ec,
-                          const void* f, void* out, double s, double omega, hipStream_t st) {
-    if (!fused_point_transfers(g) || (gc && (zero || !ec))) return hipErrorInvalidValue;
-    return prec ? jacobi2_t<float>(g, gc, zero, u, ec, f, out, s, omega, st)
-                : jacobi2_t<double>(g, gc, zero, u, ec, f, out, s, omega, st);
+                          const void* f, void* out, void* fco, double s, double omega, hipStream_t st) {
+    if (!fused_point_transfers(g) || (ec && (zero || fco)) || ((ec || fco) && !gc)) return hipErrorInvalidValue;
+    return prec ? jacobi2_t<float>(g, gc, zero, u, ec, f, out, fco, s, omega, st)
+                : jacobi2_t<double>(g, gc, zero, u, ec, f, out, fco, s, omega, st);
 }
 
 template <typename T>

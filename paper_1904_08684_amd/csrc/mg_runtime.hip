@@ -594,7 +594,7 @@ int Ctx::smooth(int l, int pr, int sweeps, bool from_zero, int first_colour) {
             hipEvent_t e0 = begin();
             int rc = record(MG_K_SMOOTH, l,
                             launch_jacobi2(L.g, nullptr, pr, from_zero && done == 0, L.u[pr], nullptr, L.f[pr],
-                                           L.utmp[pr], scale(l), opts.omega, stream),
+                                           L.utmp[pr], nullptr, scale(l), opts.omega, stream),
                             e0, "jacobi x2");
             if (rc) return rc;
             std::swap(L.u[pr], L.utmp[pr]);
@@ -944,8 +944,26 @@ int Ctx::residual_restrict(int l, int pr) {
 int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
     if (!rec && kind == MG_CYCLE_V && l == tail_l[pr]) return tail_cycle(l, pr, from_zero);
-    int rc = smooth(l, pr, opts.nu1, from_zero, 0);
-    if (!rc) rc = residual_restrict(l, pr);
+    int rc;
+    Level& P = lv[l];
+    if (!rec && opts.smoother == MG_JACOBI && opts.nu1 >= 2 && grid.centering == MG_NODE && !P.gal && P.utmp[pr] &&
+        fused_point_transfers(P.g)) {
+        // 2-D point levels: the last two pre-smoothing sweeps, the residual
+        // and its restriction in one launch
+        const int k = opts.nu1 - 2;
+        rc = smooth(l, pr, k, from_zero, 0);
+        if (!rc) {
+            hipEvent_t e0 = begin();
+            rc = record(MG_K_SMOOTH, l,
+                        launch_jacobi2(P.g, &lv[l + 1].g, pr, from_zero && k == 0, P.u[pr], nullptr, P.f[pr],
+                                       P.utmp[pr], lv[l + 1].f[pr], scale(l), opts.omega, stream),
+                        e0, "jacobi x2 + residual + restrict");
+            if (!rc) std::swap(P.u[pr], P.utmp[pr]);
+        }
+    } else {
+        rc = smooth(l, pr, opts.nu1, from_zero, 0);
+        if (!rc) rc = residual_restrict(l, pr);
+    }
     if (!rc && neu) rc = project(l + 1, lv[l + 1].f[pr]);
     if (!rc) rc = cycle(l + 1, pr, true, kind);
     if (!rc && l + 2 < L && kind != MG_CYCLE_V)
@@ -965,7 +983,7 @@ int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
         hipEvent_t e0 = begin();
         rc = record(MG_K_SMOOTH, l,
                     k == 2 ? launch_jacobi2(F.g, &lv[l + 1].g, pr, false, F.u[pr], lv[l + 1].u[pr], F.f[pr],
-                                            F.utmp[pr], scale(l), opts.omega, stream)
+                                            F.utmp[pr], nullptr, scale(l), opts.omega, stream)
                            : launch_prolong_jacobi(F.g, lv[l + 1].g, pr, F.u[pr], lv[l + 1].u[pr], F.f[pr],
                                                    F.utmp[pr], scale(l), opts.omega, stream),
                     e0, "prolong+jacobi");
