@@ -216,12 +216,19 @@ enum {
     MG_OP_COARSE = 6,     /* u <- A^-1 f on the coarsest level (FP64 Cholesky)    */
     MG_OP_VCYCLE = 7,     /* one V-cycle starting at `level` (u, f of that level) */
     MG_OP_RESIDUAL_RESTRICT = 8, /* f(level+1) <- R (f - A u); r is not written where a
-                                    fused kernel exists (3-D node levels with n >= 129) */
+                                    fused kernel exists (3-D node levels with n >= 129,
+                                    2-D node levels, the finest 3-D cell level with k,
+                                    cell levels with n <= 64) */
     MG_OP_PRESMOOTH = 9,  /* u <- nu1 smoothing sweeps, as the V-cycle's pre-smoothing
                              (red-black: red first); on 3-D node levels with
                              n >= 257 up to three red-black sweeps run as one fused
-                             pass, bitwise equal to the separate half-sweeps     */
-    MG_OP_POSTSMOOTH = 10 /* u <- nu2 sweeps, as the post-smoothing (post_order)     */
+                             pass, on 2-D node levels two damped-Jacobi sweeps per
+                             launch, bitwise equal to the separate sweeps        */
+    MG_OP_POSTSMOOTH = 10, /* u <- nu2 sweeps, as the post-smoothing (post_order)    */
+    MG_OP_PRESMOOTH_RESTRICT = 11 /* MG_OP_PRESMOOTH then MG_OP_RESIDUAL_RESTRICT, as the
+                             V-cycle runs them (2-D node levels with damped Jacobi
+                             and nu1 >= 2: the last two sweeps, the residual and the
+                             restriction in one launch, bitwise equal)           */
 };
 int mg_apply(mg_ctx* c, int op, int level, int prec);
 

@@ -127,6 +127,7 @@ struct Ctx {
     int residual_cast(bool first);
     int restrict_to(int l, int pr);
     int residual_restrict(int l, int pr);
+    int presmooth_restrict(int l, int pr, bool from_zero);
     int prolong(int l, int pr, int mask);
     int coarse(int pr);
     int vcycle(int l, int pr, bool from_zero);

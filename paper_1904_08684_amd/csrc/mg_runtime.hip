@@ -940,30 +940,34 @@ int Ctx::residual_restrict(int l, int pr) {
     return rc ? rc : restrict_to(l, pr);
 }
 
+// The first half of a cycle on level l: pre-smoothing, then the residual
+// restricted into level l + 1 (2-D node levels with damped Jacobi and
+// nu1 >= 2: the last two sweeps, the residual and the restriction in one
+// launch).
+int Ctx::presmooth_restrict(int l, int pr, bool from_zero) {
+    Level& P = lv[l];
+    if (!rec && opts.smoother == MG_JACOBI && opts.nu1 >= 2 && grid.centering == MG_NODE && !P.gal && P.utmp[pr] &&
+        fused_point_transfers(P.g)) {
+        const int k = opts.nu1 - 2;
+        int rc = smooth(l, pr, k, from_zero, 0);
+        if (rc) return rc;
+        hipEvent_t e0 = begin();
+        rc = record(MG_K_SMOOTH, l,
+                    launch_jacobi2(P.g, &lv[l + 1].g, pr, from_zero && k == 0, P.u[pr], nullptr, P.f[pr],
+                                   P.utmp[pr], lv[l + 1].f[pr], scale(l), opts.omega, stream),
+                    e0, "jacobi x2 + residual + restrict");
+        if (!rc) std::swap(P.u[pr], P.utmp[pr]);
+        return rc;
+    }
+    int rc = smooth(l, pr, opts.nu1, from_zero, 0);
+    return rc ? rc : residual_restrict(l, pr);
+}
+
 // One cycle of the given type on level l (see mg_opts).
 int Ctx::cycle(int l, int pr, bool from_zero, int kind) {
     if (l == L - 1) return coarse(pr);
     if (!rec && kind == MG_CYCLE_V && l == tail_l[pr]) return tail_cycle(l, pr, from_zero);
-    int rc;
-    Level& P = lv[l];
-    if (!rec && opts.smoother == MG_JACOBI && opts.nu1 >= 2 && grid.centering == MG_NODE && !P.gal && P.utmp[pr] &&
-        fused_point_transfers(P.g)) {
-        // 2-D point levels: the last two pre-smoothing sweeps, the residual
-        // and its restriction in one launch
-        const int k = opts.nu1 - 2;
-        rc = smooth(l, pr, k, from_zero, 0);
-        if (!rc) {
-            hipEvent_t e0 = begin();
-            rc = record(MG_K_SMOOTH, l,
-                        launch_jacobi2(P.g, &lv[l + 1].g, pr, from_zero && k == 0, P.u[pr], nullptr, P.f[pr],
-                                       P.utmp[pr], lv[l + 1].f[pr], scale(l), opts.omega, stream),
-                        e0, "jacobi x2 + residual + restrict");
-            if (!rc) std::swap(P.u[pr], P.utmp[pr]);
-        }
-    } else {
-        rc = smooth(l, pr, opts.nu1, from_zero, 0);
-        if (!rc) rc = residual_restrict(l, pr);
-    }
+    int rc = presmooth_restrict(l, pr, from_zero);
     if (!rc && neu) rc = project(l + 1, lv[l + 1].f[pr]);
     if (!rc) rc = cycle(l + 1, pr, true, kind);
     if (!rc && l + 2 < L && kind != MG_CYCLE_V)
@@ -1714,6 +1718,9 @@ int mg_apply(mg_ctx* h, int op, int level, int prec) {
             return c->vcycle(level, prec, false);
         case MG_OP_PRESMOOTH: return c->smooth(level, prec, c->opts.nu1, false, 0);
         case MG_OP_POSTSMOOTH: return c->smooth(level, prec, c->opts.nu2, false, c->opts.post_order);
+        case MG_OP_PRESMOOTH_RESTRICT:
+            if (!has_next) return c->fail(MG_EINVAL, "no coarser level");
+            return c->presmooth_restrict(level, prec, false);
         default: return c->fail(MG_EINVAL, "unknown op");
     }
 }

@@ -45,7 +45,7 @@ MG_PREC_FP64, MG_PREC_FP32 = 0, 1
 MG_FIELD_U, MG_FIELD_F, MG_FIELD_R = 0, 1, 2
 (MG_OP_GS_RED, MG_OP_GS_BLACK, MG_OP_JACOBI, MG_OP_RESIDUAL, MG_OP_RESTRICT,
  MG_OP_PROLONG, MG_OP_COARSE, MG_OP_VCYCLE, MG_OP_RESIDUAL_RESTRICT, MG_OP_PRESMOOTH,
- MG_OP_POSTSMOOTH) = range(11)
+ MG_OP_POSTSMOOTH, MG_OP_PRESMOOTH_RESTRICT) = range(12)
 (MG_K_SMOOTH, MG_K_RESIDUAL, MG_K_RESTRICT, MG_K_PROLONG, MG_K_COARSE, MG_K_REDUCE,
  MG_K_CAST, MG_K_UPDATE, MG_K_COPY, MG_K_COUNT) = range(10)
 

@@ -89,6 +89,41 @@ def test_smoothers_and_residual(mg, dim, n, cent, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n,nu", [(129, 2), (129, 3), (97, 2), (257, 4), (1025, 2)])
+def test_presmoothing_residual_restriction_in_one_launch(mg, n, nu, prec):
+    """2-D damped Jacobi: the last two pre-smoothing sweeps, the residual and
+    its full weighting in one launch (LDS tiles with a halo of four) give
+    the iterate and the coarse right-hand side of the separate sweeps and
+    residual + restriction bitwise, and the oracle's."""
+    def solver():
+        return mg.Solver(2, n, coarsest=4 if n == 97 else 5, smoother=mg.MG_JACOBI, omega=0.8, nu1=nu, nu2=nu,
+                         precision=mg.MG_MIXED if prec else mg.MG_FP64)
+    dt = np.float64 if prec == 0 else np.float32
+    u = rand(n, 2, 0, 1500 + n, dt)
+    f = rand(n, 2, 0, 1600 + n, dt) * dt(n * n)
+    s = solver()
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    s.level_set(0, mg.MG_FIELD_F, f, prec)
+    s.apply(mg.MG_OP_PRESMOOTH_RESTRICT, 0, prec)
+    uf, ff = s.level_get(0, mg.MG_FIELD_U, prec), s.level_get(1, mg.MG_FIELD_F, prec)
+    s.level_set(0, mg.MG_FIELD_U, u, prec)
+    for _ in range(nu):
+        s.apply(mg.MG_OP_JACOBI, 0, prec)
+    s.apply(mg.MG_OP_RESIDUAL, 0, prec)
+    s.apply(mg.MG_OP_RESTRICT, 0, prec)
+    us, fs = s.level_get(0, mg.MG_FIELD_U, prec), s.level_get(1, mg.MG_FIELD_F, prec)
+    s.close()
+    print(f"presmooth+restrict n={n} nu={nu} prec={prec}: bitwise {np.array_equal(uf, us)} {np.array_equal(ff, fs)}",
+          flush=True)
+    assert np.array_equal(uf, us) and np.array_equal(ff, fs)
+    ref = u.copy()
+    for _ in range(nu):
+        ref = node.jacobi(ref, f, 0.8)
+    assert np.array_equal(uf, ref)
+    close(ff, node.restrict_fw(node.residual(ref, f)).astype(np.float64), prec, f"presmooth+restrict n={n}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("n,nu", [(129, 2), (129, 3), (257, 2), (97, 2), (1025, 4)])
 def test_two_jacobi_sweeps_per_launch_equal_single_sweeps(mg, n, nu, prec):
     """On 2-D levels a smoothing step runs two damped-Jacobi sweeps per
