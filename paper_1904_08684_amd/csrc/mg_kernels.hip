@@ -365,11 +365,13 @@ __global__ __launch_bounds__(1024) void k_node_gs_zm(Geom g, ZSpace zs, T* __res
 // r = f - A u at both colours of the thread's column; both colours' z-1, z,
 // z+1 values stay in registers, U planes per step.
 // CAST (FP64): the residual is stored as r32 = fl32(r / sigma) instead of r.
-template <typename T, int U, bool NT, bool NORM, bool STORE, bool CAST = false>
+// JAC (1, or 2 with s a power of two and rs = 1 / s): a damped-Jacobi sweep,
+// r receiving u + (omega res) / (6 s) as pt_node_jacobi forms it.
+template <typename T, int U, bool NT, bool NORM, bool STORE, bool CAST = false, int JAC = 0>
 __device__ __forceinline__ void d_node_res_zm(const Ex& ex, Geom g, ZSpace zs, const T* __restrict__ u,
                                                       const T* __restrict__ f, T* __restrict__ r, T s,
                                                       double* __restrict__ part, float* __restrict__ r32 = nullptr,
-                                                      double sigma = 1.0) {
+                                                      double sigma = 1.0, T omega = T(0), T rs = T(0)) {
     double sq = 0.0, mx = 0.0;
     int tx, ty, tz;
     zm_tile(zs, ex.b, tx, ty, tz);
@@ -396,7 +398,8 @@ __device__ __forceinline__ void d_node_res_zm(const Ex& ex, Geom g, ZSpace zs, c
             nb = nb + zm;
             nb = nb + zp;
             const T v = fv - (T(6) * uc - nb) * s;
-            if constexpr (CAST) st_stream<NT>(r32 + at, (float)((double)v / sigma));
+            if constexpr (JAC > 0) st_stream<NT>(r + at, uc + jacobi_step<T, 3, JAC == 2>(omega * v, s, rs));
+            else if constexpr (CAST) st_stream<NT>(r32 + at, (float)((double)v / sigma));
             else if (STORE) st_stream<NT>(r + at, v);
             const double dv = (double)v;
             sq = sq + dv * dv;
@@ -456,6 +459,15 @@ __device__ __forceinline__ void d_node_res_zm(const Ex& ex, Geom g, ZSpace zs, c
         }
     }
     if (NORM) block_sum_max(sq, mx, part + 2 * (long long)ex.b);
+}
+
+// Damped-Jacobi sweep of a 3-D node level along columns (u -> out).
+template <typename T, int U, bool NT, bool P2>
+__global__ __launch_bounds__(1024) void k_node_jac_zm(Geom g, ZSpace zs, const T* __restrict__ u,
+                                                      const T* __restrict__ f, T* __restrict__ out, T s, T omega,
+                                                      T rs) {
+    d_node_res_zm<T, U, NT, false, false, false, P2 ? 2 : 1>(solo_ex(), g, zs, u, f, out, s, nullptr, nullptr, 1.0,
+                                                             omega, rs);
 }
 
 template <typename T, int U, bool NT, bool NORM, bool STORE>
@@ -3346,6 +3358,21 @@ static hipError_t jacobi_t(const Geom& g, bool zero, const void* u, const void* 
         else
             k_node_jac_ym<T, false><<<(unsigned)ys.blocks(), 256, 0, st>>>(g, ys, cp<T>(u), cp<T>(f), mp<T>(out),
                                                                           (T)s, (T)omega);
+        return hipGetLastError();
+    }
+    if (!zero && !g.cell && use_zmarch(g)) {
+        const ZSpace zs = make_zspace(g);
+        const dim3 grid((unsigned)zs.blocks()), block(64, zs.rows);
+        constexpr int U = sizeof(T) == 8 ? 2 : 4;
+        const bool nt = streams_from_hbm(g, sizeof(T)), p2 = pow2_scale(s);
+        const T rs = (T)(1.0 / s);
+#define MG_JZ(N, P) \
+    k_node_jac_zm<T, U, N, P><<<grid, block, 0, st>>>(g, zs, cp<T>(u), cp<T>(f), mp<T>(out), (T)s, (T)omega, rs)
+        if (nt && p2) MG_JZ(true, true);
+        else if (nt) MG_JZ(true, false);
+        else if (p2) MG_JZ(false, true);
+        else MG_JZ(false, false);
+#undef MG_JZ
         return hipGetLastError();
     }
     const Space sp = space_of(g, 2, 0);
