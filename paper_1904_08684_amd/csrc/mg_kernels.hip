@@ -3536,9 +3536,12 @@ template <typename T>
 static hipError_t res_restrict_t(const Geom& gf, const Geom& gc, const void* u, const void* f, void* fco,
                                  double s, hipStream_t st) {
     // 256-thread blocks of 3 (FP64) or 4 (FP32) rows per thread measured
-    // fastest among 2-4 rows and 4 or 8 wavefronts
-    constexpr int R = sizeof(T) == 8 ? 3 : 4, NW = 4, CY = (R * NW - 1) / 2, KC = 8;
+    // fastest among 2-4 rows and 4 or 8 wavefronts; chunks of 8 coarse
+    // planes, shorter on small levels so that at least 512 blocks run
+    constexpr int R = sizeof(T) == 8 ? 3 : 4, NW = 4, CY = (R * NW - 1) / 2;
     const int ntx = (gc.n - 2 + kRrCX - 1) / kRrCX, nty = (gc.n - 2 + CY - 1) / CY;
+    int KC = 8;
+    while (KC > 1 && (long long)ntx * nty * ((gc.n - 2 + KC - 1) / KC) < 512) KC /= 2;
     const int ntz = (gc.n - 2 + KC - 1) / KC;
     const unsigned nb = (unsigned)((long long)ntx * nty * ntz);
     k_node_res_restrict_zm<T, R, NW><<<nb, 64 * NW, 0, st>>>(gf, gc, ntx, nty, KC, cp<T>(u), cp<T>(f), mp<T>(fco),
