@@ -224,6 +224,10 @@ static inline TbSpace make_tbspace(const Geom& g, int S, int rows) {
 // (one colour each, both colours, and the prolongation's colour mask).  The
 // coarsest level's Cholesky factor follows the fields in LDS.
 constexpr int kTailMax = 6;
+// Largest 2-D level of a damped-Jacobi tail: a 129^2 Jacobi V(2,2) cycle
+// measured 64.3 us with the tail from 65^2, 54.6 from 33^2, 53.8 from 17^2
+// and 55.9 us from 9^2.
+constexpr int kTail2DJacobiMax = 17;
 constexpr int kTailThreads = 1024;
 constexpr int kTailLdsBytes = 156 * 1024;
 

@@ -849,6 +849,9 @@ void Ctx::plan_tail() {
                 elems += 3 * ((2 * tail_geom(lv[l].g).cs + 3) / 4 * 4);
             }
             if (!ok || (elems * esz + 7) / 8 * 8 + 8LL * m * m > kTailLdsBytes) continue;
+            // 2-D damped Jacobi: levels above 17^2 run faster as the
+            // two-sweep tile launches than inside the one workgroup
+            if (grid.dim == 2 && opts.smoother == MG_JACOBI && lv[l0].g.n > kTail2DJacobiMax) continue;
             TailPlan& P = tail[pr];
             P = TailPlan{};
             P.nl = L - l0;
